@@ -1,0 +1,154 @@
+/*
+ * cinr_oracle.h -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow CPU reference of the cache-accelerated INR volume renderer of
+ * "From Cluster to Desktop: A Cache-Accelerated INR Framework for Interactive
+ * Visualization of Tera-Scale Data" (Zavorotny et al.).  Only the test suite,
+ * the smoke check and the benchmark's CPU-baseline leg may load it; the
+ * product library never does.  It shares no code with the GPU path.
+ *
+ * Two precisions by design:
+ *  - value plane (voxel values, colours): FP64;
+ *  - decision plane (ray setup, sample positions, LoD choice, brick and
+ *    page-table indices): a fixed sequence of correctly rounded binary32
+ *    operations (built with -ffp-contract=off, no fast-math), so that page
+ *    tables, miss lists and eviction logs can be compared bit for bit.
+ */
+#ifndef CINR_ORACLE_H
+#define CINR_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_MAX_LEVELS 32
+#define ORC_MAX_LAYERS 8
+#define ORC_MAX_LODS 16
+
+/* Hash-grid INR (Section 3, Figure 2): n_levels grids, each a table of
+ * T_l = min(2^log2_table, (N_l+1)^3) entries of n_features floats, stored
+ * level-major in `table`; then an MLP without biases, ReLU between layers,
+ * weights per layer [out][in] row-major, concatenated in `weights`.
+ * value = clamp(value_scale * y + value_offset, 0, 1) (Section 4.1). */
+typedef struct {
+    int32_t dims[3];
+    int32_t n_levels, n_features, log2_table;
+    int32_t level_res[ORC_MAX_LEVELS];
+    int32_t n_layers;
+    int32_t widths[ORC_MAX_LAYERS + 1];
+    float value_scale, value_offset;
+    const float* table;
+    const float* weights;
+} orc_inr;
+
+typedef struct {
+    int32_t projection; /* 0 perspective, 1 orthographic */
+    int32_t width, height;
+    float eye[3], forward[3], right[3], up[3];
+    float tan_half_x, tan_half_y, ortho_w, ortho_h;
+} orc_camera;
+
+enum { ORC_CACHED = 0, ORC_UNCACHED_DIRECT = 1, ORC_UNCACHED_LATTICE = 2 };
+
+typedef struct {
+    float step;          /* sample spacing in LoD-0 voxels */
+    float lod_scale;     /* Algorithm 2: LoD distance = |p - eye| * lod_scale */
+    float ert_threshold; /* early ray termination at A >= threshold; > 1 disables */
+    uint32_t seed;       /* per-run seed of the per-frame stochastic-LoD seed */
+    int32_t frame_index;
+    int32_t samples_per_iter; /* samples gathered per wavefront step after a true miss */
+    int32_t mode;
+    int32_t macro_cell;  /* macro-cell side N; 0 = no empty-space skipping */
+    const float* macro_minmax; /* [Mz][My][Mx][2] */
+} orc_params;
+
+typedef struct {
+    int32_t brick;        /* stored brick side B */
+    int32_t n_lods;
+    int32_t pool_bricks;
+    int32_t max_requests;
+    int32_t rank_window;  /* ranking clamp above the timestamp (1000) */
+    int32_t ranking;      /* 0 = key order of this frame's requests, 1 = priority rank */
+    int32_t preload_period; /* frames per LoD step of the coarse-LoD pre-load; 0 = off */
+} orc_cache_desc;
+
+typedef struct {
+    int64_t rays, samples, hits, fallbacks, misses, skipped;
+    int64_t requested, selected, evicted;
+} orc_stats;
+
+typedef struct orc_cache orc_cache;
+
+/* --- random numbers (published generators) --- */
+uint64_t orc_splitmix64(uint64_t state);           /* one output of SplitMix64 from `state` */
+uint32_t orc_xorshift32(uint32_t x);               /* one step of Marsaglia's xorshift (13,17,5) */
+uint32_t orc_frame_seed(uint32_t seed, uint32_t frame);
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* --- INR --- */
+int64_t orc_level_size(const orc_inr* m, int level);
+int64_t orc_table_entries(const orc_inr* m);
+void orc_encode(const orc_inr* m, const double* u, int64_t n, double* feat);
+void orc_mlp(const orc_inr* m, const double* feat, int64_t n, double* y);
+void orc_value(const orc_inr* m, const double* x, int64_t n, double* v);
+
+/* --- LoD lattice and bricks (Section 4.3.2) --- */
+int orc_lod_geometry(const int32_t dims[3], int32_t brick, int32_t n_lods,
+                     int32_t* K /*[n_lods][3]*/, int32_t* nb /*[n_lods][3]*/,
+                     int64_t* key_offset /*[n_lods+1]*/);
+void orc_brick_origin_literal(const int32_t b[3], int32_t lod, int32_t brick, int64_t out[3]);
+int orc_decode_bricks(const orc_inr* m, const int32_t* reqs, int64_t n, int32_t brick,
+                      int32_t n_lods, double* out);
+
+/* --- macro-cells (Section 5.2) --- */
+void orc_macrocells(const orc_inr* m, int32_t cell, float* minmax);
+void orc_macrocell_flags(const float* minmax, int64_t n_cells, const float* tf, uint8_t* flags);
+
+/* --- decision-plane pieces exposed for pinning --- */
+int orc_ray_setup(const orc_camera* c, const int32_t dims[3], int32_t i, int32_t j,
+                  float o[3], float d[3], float* ts, float* te);
+int32_t orc_select_lod(const float p[3], const float eye[3], float lod_scale, uint32_t frame_seed,
+                       int32_t lod_floor, int32_t n_lods);
+int32_t orc_lod_floor(int32_t frame, int32_t period, int32_t n_lods);
+
+/* --- uncached renderers (no cache state) --- */
+int orc_render_uncached(const orc_inr* m, const orc_camera* c, const float* tf,
+                        const orc_params* p, double* rgba, orc_stats* st);
+
+/* --- cached renderer --- */
+orc_cache* orc_cache_create(const orc_inr* m, const orc_cache_desc* d);
+void orc_cache_destroy(orc_cache* c);
+int orc_cache_render(orc_cache* c, const orc_camera* cam, const float* tf, const orc_params* p,
+                     double* rgba, orc_stats* st);
+int orc_cache_prefill(orc_cache* c, const int32_t* keys, int64_t n, int32_t stamp);
+int64_t orc_cache_n_keys(const orc_cache* c);
+int orc_cache_inject_requests(orc_cache* c, const int32_t* keys, const uint32_t* counts, int64_t n);
+int orc_cache_touch(orc_cache* c, int32_t slot, int32_t frame);
+int orc_cache_end_frame(orc_cache* c, int32_t frame, orc_stats* st);
+void orc_cache_page_table(const orc_cache* c, int32_t* out);
+void orc_cache_owner(const orc_cache* c, int32_t* out);
+void orc_cache_last_used(const orc_cache* c, int32_t* out);
+void orc_cache_rank(const orc_cache* c, int64_t* out);
+void orc_cache_req_count(const orc_cache* c, uint32_t* out);
+int64_t orc_cache_request_list(const orc_cache* c, int32_t* out);
+int64_t orc_cache_miss_list(const orc_cache* c, int32_t* pix_k /*[n][2]*/, float* pos /*[n][3]*/, int64_t cap);
+int64_t orc_cache_evict_log(const orc_cache* c, int32_t* out /*[n][4]*/, int64_t cap);
+void orc_cache_pool(const orc_cache* c, double* out);
+void orc_cache_set_miss_logging(orc_cache* c, int on);
+void orc_cache_set_ert_trace(orc_cache* c, int on);
+int64_t orc_cache_ert_trace(const orc_cache* c, int32_t* out, int64_t cap);
+
+/* --- training (the learned part): loss and analytic gradients --- */
+double orc_loss_grad(const orc_inr* m, const double* u, const double* target, int64_t n,
+                     double* g_table, double* g_weights);
+void orc_adam_step(double* p, double* m1, double* m2, const double* g, int64_t n, int64_t step,
+                   double lr, double b1, double b2, double eps);
+
+void orc_set_threads(int n);
+int orc_get_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

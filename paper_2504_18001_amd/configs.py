@@ -1,0 +1,110 @@
+"""Named workloads.
+
+Each workload fixes the INR architecture, the camera path, the transfer
+functions, the marching parameters and the cache shape.  The synthetic INRs
+and fields stand in for the paper's datasets (Table 1), which are not
+available.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, replace
+
+from . import synth
+from .synth import InrArch
+
+# -- INR architectures --------------------------------------------------------
+
+# 64^3 blob-scale volume: 8 levels x 2 features, T = 2^14, N_min 4, growth 1.5,
+# MLP 16 -> 32 -> 32 -> 1.
+ARCH_SMALL = InrArch(dims=(64, 64, 64), n_levels=8, n_features=2, log2_table=14, n_min=4,
+                     growth=1.5, widths=(16, 32, 32, 1))
+
+# 512^3 virtual volume: 16 levels x 2 features, T = 2^19, growth 1.38,
+# MLP 32 -> 64 -> 64 -> 1.
+ARCH_512 = InrArch(dims=(512, 512, 512), n_levels=16, n_features=2, log2_table=19, n_min=4,
+                   growth=1.38, widths=(32, 64, 64, 1))
+
+# Tera-shaped virtual domain with the channel-flow dimensions of Table 1:
+# 16 levels x 4 features, T = 2^22, finest level 10240, MLP 64 -> 64 -> 64 -> 1.
+ARCH_TERA = InrArch(dims=(10240, 7680, 1536), n_levels=16, n_features=4, log2_table=22, n_min=4,
+                    growth=2560.0 ** (1.0 / 15.0), widths=(64, 64, 64, 1))
+
+# Learned part: 1024^3 field, 16 levels x 2 features, T = 2^20, finest level 1024.
+ARCH_LEARN = InrArch(dims=(1024, 1024, 1024), n_levels=16, n_features=2, log2_table=20, n_min=4,
+                     growth=256.0 ** (1.0 / 15.0), widths=(32, 64, 64, 1))
+
+
+@dataclass
+class CacheShape:
+    brick: int            # stored brick side B (samples per axis)
+    n_lods: int
+    pool_bricks: int
+    max_requests: int
+    rank_window: int = 1000
+    ranking: int = 1      # 0 = timestamp/key order, 1 = priority ranking
+    preload_period: int = 0
+    miss_log_capacity: int = 0
+    evict_log_capacity: int = 4096
+
+
+@dataclass
+class Workload:
+    name: str
+    arch: InrArch
+    inr_seed: int
+    width: int
+    height: int
+    projection: int
+    n_frames: int
+    step: float
+    lod_scale: float
+    cache: CacheShape
+    macro_cell: int = 16
+    ert_threshold: float = 0.999
+    samples_per_iter: int = 32
+    seed: int = 1234
+    orbit_radius: float = 0.0
+    orbit_elev_deg: float = 0.0
+    orbit_step_deg: float = 0.0
+    fov_y_deg: float = 45.0
+    ortho_extent: float = 0.0
+    tf_switch_frame: int = -1     # from this frame (mod n_frames) on, a random TF is used
+    tf_seed: int = 77
+
+    def camera(self, frame: int) -> synth.Camera:
+        ang = self.orbit_step_deg * (frame % self.n_frames)
+        return synth.orbit_camera(self.projection, self.arch.dims, self.orbit_radius, ang,
+                                  self.orbit_elev_deg, self.width, self.height, self.fov_y_deg,
+                                  self.ortho_extent, self.ortho_extent)
+
+    def tf(self, frame: int):
+        if self.tf_switch_frame >= 0 and (frame % self.n_frames) >= self.tf_switch_frame:
+            return synth.tf_random(self.tf_seed)
+        return synth.tf_ramp()
+
+
+# 64^3, orthographic 128x128, 4 frames at 5 degree steps, B = 8, 2 LoDs, 96-slot pool.
+SMALL = Workload(
+    name="blob64_ortho128", arch=ARCH_SMALL, inr_seed=0, width=128, height=128,
+    projection=synth.ORTHOGRAPHIC, n_frames=4, step=0.5, lod_scale=1.0 / 96.0,
+    cache=CacheShape(brick=8, n_lods=2, pool_bricks=96, max_requests=16),
+    orbit_radius=96.0, orbit_elev_deg=0.0, orbit_step_deg=5.0, ortho_extent=64.0 * math.sqrt(3.0),
+    samples_per_iter=8,
+)
+
+# 512^3 random INR at 1920x1080 perspective, 60-frame orbit (6 degrees per frame,
+# 20 degree elevation), TF switched at frame 30, B = 16, 4 LoDs, 2 GiB pool.
+HD512 = Workload(
+    name="inr512_persp1080p", arch=ARCH_512, inr_seed=0, width=1920, height=1080,
+    projection=synth.PERSPECTIVE, n_frames=60, step=0.5, lod_scale=1.0 / 800.0,
+    cache=CacheShape(brick=16, n_lods=4, pool_bricks=(2 << 30) // (16 ** 3 * 4), max_requests=40,
+                     preload_period=4),
+    orbit_radius=1159.0, orbit_elev_deg=20.0, orbit_step_deg=6.0, tf_switch_frame=30,
+    samples_per_iter=32,
+)
+
+
+def scaled(w: Workload, width: int, height: int, **kw) -> Workload:
+    """Same workload at another resolution (and optional overrides)."""
+    return replace(w, width=width, height=height, **kw)
