@@ -1,0 +1,276 @@
+#!/usr/bin/env python3
+"""Frame rate of the cached INR renderer at 1080p (BF16 MLP) beside the
+uncached FP32 INR renderer on the same GPU, and brick-decode throughput.
+
+Workload (inr512_persp1080p): a 512^3 virtual volume defined by a seeded
+random-init hash-grid INR (16 levels x 2 features, T = 2^19, growth 1.38,
+MLP 32-64-64-1), rendered at 1920x1080 (perspective, 45 degree vertical FOV)
+along a 60-frame orbit (6 degrees per frame, 20 degree elevation, ramp
+transfer function for frames 0-29 of each loop, a seeded random one for
+30-59); step 0.5 voxel, LoD distance scale 1/800, early ray termination at
+0.999; cache of 16^3-sample bricks, 4 LoDs, 2 GiB FP32 pool (131072 slots),
+40 requests per frame, pre-load of the coarsest LoD (4 frames per LoD),
+macro-cells of side 16 built from the INR on the GPU.
+
+A step is one whole frame of the hot path: ray generation, sampling through
+the page tables, true-miss inference, compositing, the cache manager's
+ranking and request selection, and brick decoding into the pool.  The cache
+state evolves across steps exactly as in interactive use: the warm-up
+frames fill it and the timed frames continue the same orbit.
+
+Prints one JSON line.  Inputs are synthetic and seeded; the paper's datasets
+are not used.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fps at 1080p (cached, BF16 MLP) vs uncached FP32 INR, PSNR≥45 dB; bricks/s"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes of the sampler: a served sample reads its page-table entry
+# and 8 trilinear corners (36 B); a true miss probes the page tables (16 B
+# budget for up to 4 LoDs); each marched ray reads and writes its colour
+# (32 B), its sample index and its live-list entry (8 B)
+BYTES_SERVED, BYTES_MISS, BYTES_RAY = 36, 16, 40
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def load_value_range(key):
+    with open(os.path.join(ROOT, "tests", "golden", "value_ranges.json")) as f:
+        vr = json.load(f)[key]
+    return vr["value_scale"], vr["value_offset"]
+
+
+def make_scene(w, dtype_decode="bf16"):
+    import torch
+    from paper_2504_18001_amd import cinr, synth
+    table, weights = synth.random_inr_params(w.arch, w.inr_seed)
+    s, o = load_value_range(f"inr512/{w.inr_seed}")
+    base = cinr.Volume(w.arch, table, weights, s, o)
+    mm = base.build_macrocells(w.macro_cell, "f32")
+    vol = cinr.Volume(w.arch, base.table, base.weights, s, o, macrocells=mm, macro_cell=w.macro_cell)
+    cams = [w.camera(f) for f in range(w.n_frames)]
+    tfs = [torch.as_tensor(w.tf(f)).cuda() for f in range(w.n_frames)]
+    return vol, cams, tfs
+
+
+def new_cache(vol, w):
+    from paper_2504_18001_amd import cinr
+    cs = w.cache
+    return cinr.Cache(vol, cs.brick, cs.n_lods, cs.pool_bricks, cs.max_requests, rank_window=cs.rank_window,
+                      ranking=cs.ranking, preload_period=cs.preload_period)
+
+
+def run_frames(r, vol, cams, tfs, w, frames, mode, dtype, cache, stats=None, out=None):
+    from paper_2504_18001_amd import cinr
+    img = None
+    for i, f in enumerate(frames):
+        img = r.render(vol, cams[f % w.n_frames], tfs[f % w.n_frames], w.step, w.lod_scale, frame_index=f,
+                       seed=w.seed, ert_threshold=w.ert_threshold, samples_per_iter=w.samples_per_iter, mode=mode,
+                       dtype=dtype, cache=cache, stats=None if stats is None else stats[i], out=out)
+    return img
+
+
+def psnr(a, b):
+    mse = float(((a - b) ** 2).mean())
+    return float("inf") if mse == 0 else 10.0 * math.log10(1.0 / mse)
+
+
+def decode_throughput(vol, w, dtype, n_bricks, reps=5):
+    import numpy as np
+    import torch
+    from paper_2504_18001_amd import synth
+    cs = w.cache
+    nb, _ = vol.geometry(cs.brick, cs.n_lods)
+    reqs = torch.from_numpy(synth.random_requests(nb.tolist(), n_bricks, seed=11)).cuda()
+    out = torch.empty((n_bricks, cs.brick, cs.brick, cs.brick), dtype=torch.float32, device="cuda")
+    vol.decode_bricks(reqs, cs.brick, dtype, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        vol.decode_bricks(reqs, cs.brick, dtype, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return n_bricks / (ms * 1e-3), ms
+
+
+def cpu_baseline(w, budget_s):
+    """The CPU oracle on a bounded sample of the same workload: cached frames
+    from a cold cache at 1/8 x 1/8 of the resolution."""
+    import numpy as np
+    from oracle import oracle as O
+    from paper_2504_18001_amd import synth
+    table, weights = synth.random_inr_params(w.arch, w.inr_seed)
+    s, o = load_value_range(f"inr512/{w.inr_seed}")
+    m = O.OracleInr(w.arch, table, weights, s, o)
+    cs = w.cache
+    oc = O.OracleCache(m, brick=cs.brick, n_lods=cs.n_lods, pool_bricks=cs.pool_bricks, max_requests=cs.max_requests,
+                       rank_window=cs.rank_window, ranking=cs.ranking, preload_period=cs.preload_period)
+    W, H = w.width // 8, w.height // 8
+    times = []
+    t_start = time.perf_counter()
+    f = 0
+    while f < 12 and (time.perf_counter() - t_start) < budget_s:
+        cam = w.camera(f)
+        cam.width, cam.height = W, H
+        p = O.make_params(w.step, w.lod_scale, seed=w.seed, frame_index=f, ert_threshold=w.ert_threshold,
+                          samples_per_iter=w.samples_per_iter)
+        t0 = time.perf_counter()
+        oc.render(cam, w.tf(f), p)
+        times.append(time.perf_counter() - t0)
+        f += 1
+    med = float(np.median(times))
+    return {"value": 1.0 / (64.0 * med), "unit": "frames/s", "cores": O.get_threads(), "kind": "oracle",
+            "sample": f"cached frames 0-{len(times) - 1} from a cold cache at {W}x{H} (1/64 of the pixels, no "
+                      f"macro-cells); value = 1 / (64 x median frame time {med:.3f} s), i.e. the per-pixel work "
+                      f"extrapolated to 1080p"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--warmup", type=int, default=180)
+    ap.add_argument("--dtype", default="bf16")
+    ap.add_argument("--uncached-steps", type=int, default=None)
+    ap.add_argument("--decode-bricks", type=int, default=4096)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32-cached", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); multi-GPU sort-first "
+              f"rendering is not part of it", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2504_18001_amd import cinr, configs
+
+    torch.cuda.set_device(0)
+    w = configs.HD512
+    K, Wm = args.steps, args.warmup
+    log(f"[bench] workload {w.name}: warmup {Wm} frames, timed {K} frames")
+    vol, cams, tfs = make_scene(w)
+    torch.cuda.synchronize()
+
+    # --- cached, reduced-precision MLP: the headline run ---------------------
+    cache = new_cache(vol, w)
+    r = cinr.Renderer()
+    out = torch.empty((w.height, w.width, 4), dtype=torch.float32, device="cuda")
+    run_frames(r, vol, cams, tfs, w, range(Wm), cinr.CACHED, args.dtype, cache, out=out)
+    torch.cuda.synchronize()
+    log("[bench] warm-up done")
+    stats = torch.zeros((K, len(cinr.STAT_FIELDS)), dtype=torch.int64, device="cuda")
+    vol.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_frames(r, vol, cams, tfs, w, range(Wm, Wm + K), cinr.CACHED, args.dtype, cache, stats=stats, out=out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    vol.set_timing(False)
+    stages = vol.collect_timing()
+    cached_img = out.clone()
+    fps = K / (t1 - t0)
+    st = stats.cpu().numpy()
+    tot = {k: int(st[:, i].sum()) for i, k in enumerate(cinr.STAT_FIELDS)}
+    log(f"[bench] cached {args.dtype}: {fps:.1f} fps; stages {stages}; totals {tot}")
+
+    # roofline of the dominant kernel (the sampler)
+    march_ms, march_n = stages["march"]
+    alg_bytes = (BYTES_SERVED * (tot["hits"] + tot["fallbacks"]) + BYTES_MISS * tot["misses"] +
+                 BYTES_RAY * tot["rays"])
+    achieved = alg_bytes / (march_ms * 1e-3) / 1e9 if march_ms > 0 else 0.0
+
+    # --- uncached FP32 INR renderer on the same frames ------------------------
+    KU = args.uncached_steps or K
+    r2 = cinr.Renderer()
+    out2 = torch.empty_like(out)
+    run_frames(r2, vol, cams, tfs, w, range(Wm, Wm + 2), cinr.UNCACHED_DIRECT, "f32", None, out=out2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_frames(r2, vol, cams, tfs, w, range(Wm, Wm + KU), cinr.UNCACHED_DIRECT, "f32", None, out=out2)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fps_unc = KU / (t1 - t0)
+    # same frame as the last cached one
+    run_frames(r2, vol, cams, tfs, w, [Wm + K - 1], cinr.UNCACHED_DIRECT, "f32", None, out=out2)
+    torch.cuda.synchronize()
+    q_unc = psnr(cached_img.cpu().numpy(), out2.cpu().numpy())
+    log(f"[bench] uncached f32: {fps_unc:.1f} fps; PSNR cached vs uncached {q_unc:.2f} dB")
+
+    # --- cached FP32 MLP (same sequence, own cache) ---------------------------
+    fps_c32 = None
+    q_prec = None
+    if not args.no_fp32_cached:
+        cache32 = new_cache(vol, w)
+        r3 = cinr.Renderer()
+        out3 = torch.empty_like(out)
+        run_frames(r3, vol, cams, tfs, w, range(Wm), cinr.CACHED, "f32", cache32, out=out3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run_frames(r3, vol, cams, tfs, w, range(Wm, Wm + K), cinr.CACHED, "f32", cache32, out=out3)
+        torch.cuda.synchronize()
+        fps_c32 = K / (time.perf_counter() - t0)
+        q_prec = psnr(cached_img.cpu().numpy(), out3.cpu().numpy())
+        del cache32
+        log(f"[bench] cached f32: {fps_c32:.1f} fps; PSNR {args.dtype} vs f32 cached {q_prec:.2f} dB")
+
+    # --- brick decoding throughput -------------------------------------------
+    bps = {}
+    for dt in (args.dtype, "f32"):
+        bps[dt], _ = decode_throughput(vol, w, dt, args.decode_bricks)
+    log(f"[bench] decode bricks/s {bps}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, args.cpu_budget)
+        log(f"[bench] cpu baseline {cpu}")
+
+    line = {
+        "metric": METRIC,
+        "value": round(fps, 2),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": round(1000.0 / fps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic (seeded random-init INR; the paper's datasets are not used)",
+        "config": {"workload": w.name, "width": w.width, "height": w.height, "volume": list(w.arch.dims),
+                   "hash_grid": "16 levels x 2 features, T=2^19", "mlp": "32-64-64-1", "brick": w.cache.brick,
+                   "n_lods": w.cache.n_lods, "pool_bricks": w.cache.pool_bricks,
+                   "max_requests": w.cache.max_requests, "step": w.step, "ert": w.ert_threshold,
+                   "orbit_frames": w.n_frames},
+        "uncached_fp32_fps": round(fps_unc, 2),
+        "speedup_vs_uncached_fp32": round(fps / fps_unc, 3),
+        "cached_fp32_fps": None if fps_c32 is None else round(fps_c32, 2),
+        "bricks_per_s": {k: round(v, 1) for k, v in bps.items()},
+        "psnr_cached_vs_uncached_db": round(q_unc, 2),
+        "psnr_reduced_vs_fp32_cached_db": None if q_prec is None else round(q_prec, 2),
+        "stage_ms_per_frame": {k: round(v[0] / K, 4) for k, v in stages.items()},
+        "frame_totals": tot,
+        "roofline": {"kernel": "k_march", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "launches": march_n, "avg_launch_ms": round(march_ms / max(march_n, 1), 5)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,282 @@
+/*
+ * cinr.h -- C ABI of the MI355X (gfx950) cache-accelerated INR volume renderer.
+ *
+ * Implements the per-frame hot path of Zavorotny et al., "From Cluster to
+ * Desktop: A Cache-Accelerated INR Framework for Interactive Visualization of
+ * Tera-Scale Data": a scalar field defined only by a hash-grid INR (Section 3,
+ * Figure 2) is ray marched (Section 5.1) through a multi-resolution brick cache
+ * (Section 4.3): every sample looks up a per-LoD page table, falls back to
+ * coarser LoDs, and interpolates trilinearly inside a brick of the pool; true
+ * misses are inferred directly (Section 4.3.4, Algorithms 1 and 2); requested
+ * bricks are ranked (Section 4.3.3) and decoded from the INR in batches
+ * (Section 4.3.2) into the pool with LRU replacement (Figure 1, step (5)).
+ *
+ * Conventions shared by every entry point:
+ *  - Plain C linkage; no C++ types, exceptions or STL cross this boundary.
+ *  - Pointers prefixed d_ are device pointers (HIP device memory of the
+ *    current device); other pointers are host pointers.
+ *  - The caller owns every device buffer (parameters, pool, workspaces,
+ *    images, statistics).  The library borrows them for the lifetime of the
+ *    object or call and never frees them.  Library-owned memory is limited to
+ *    host structs and one small pinned host buffer per volume.
+ *  - `stream` is a hipStream_t (passed as void*); all work is enqueued on it.
+ *    render_frame blocks the host until the first marching step of the frame
+ *    has finished (it reads back the number of live rays to stop early);
+ *    cinr_cache_dump synchronises the stream.  Nothing else synchronises.
+ *  - Arguments are validated before any launch.  On failure the call returns
+ *    a negative cinr_status and cinr_last_error() describes it (thread-local).
+ *    Faults inside kernels surface at the next synchronising call.
+ *  - Objects are not thread-safe; use one cache per stream.
+ *  - Volume coordinates are LoD-0 voxel units; the volume box is
+ *    [0, V-1]^3 (lattice points at integer coordinates).
+ */
+#ifndef CINR_H
+#define CINR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CINR_OK = 0,
+    CINR_INVALID_ARG = -1,
+    CINR_OUT_OF_MEMORY = -2, /* a caller-provided buffer or workspace is too small */
+    CINR_HIP_ERROR = -3,     /* the message holds the HIP error string */
+    CINR_UNSUPPORTED = -4,   /* architecture, dtype or device not supported */
+    CINR_BAD_STATE = -5
+} cinr_status;
+
+/* Arithmetic of the MLP layers (hash-grid interpolation, compositing and the
+ * brick pool stay FP32); reduced precisions accumulate in FP32 on MFMA. */
+typedef enum { CINR_F32 = 0, CINR_BF16 = 1, CINR_F16 = 2 } cinr_dtype;
+
+typedef enum {
+    CINR_CACHED = 0,         /* sampler of Algorithm 2 behind the brick cache */
+    CINR_UNCACHED_DIRECT = 1 /* every sample inferred from the INR (the uncached baseline) */
+} cinr_mode;
+
+typedef enum {
+    CINR_RANK_TIMESTAMP = 0, /* take this frame's requested bricks in key order (Section 4.3.3, default of Sarton et al.) */
+    CINR_RANK_PRIORITY = 1   /* priority ranking of Section 4.3.3 */
+} cinr_ranking;
+
+typedef enum { CINR_PERSPECTIVE = 0, CINR_ORTHOGRAPHIC = 1 } cinr_projection;
+
+#define CINR_MAX_LEVELS 32
+#define CINR_MAX_LAYERS 8
+#define CINR_MAX_LODS 16
+
+/* A volume defined by a hash-grid INR (Section 3, Figure 2; value range of
+ * Section 4.1; macro-cells of Section 5.2).
+ *  dims          LoD-0 size (Vx, Vy, Vz), each >= 2.
+ *  n_levels      grid levels m (<= 32); n_features entries per table slot
+ *                (n, 1..4); log2_table: log2 of the per-level capacity T.
+ *  level_res     per-level resolution N_l; level l stores
+ *                T_l = min(T, (N_l+1)^3) entries; a level whose full grid fits
+ *                is indexed densely (x + y(N+1) + z(N+1)^2), otherwise by the
+ *                spatial hash (x*1 ^ y*2654435761 ^ z*805459861) mod T.
+ *  n_layers, widths  MLP without biases: widths[0] = n_levels*n_features,
+ *                widths[n_layers] = 1, ReLU between layers.
+ *  value_scale, value_offset  value = clamp(scale*y + offset, 0, 1).
+ *  d_table       f32 [sum_l T_l][n_features], level-major.  Borrowed.
+ *  d_weights     f32, layer k as [widths[k+1]][widths[k]] row-major,
+ *                layers concatenated.  Borrowed.
+ *  d_macrocells  optional f32 [ceil(Vz/N)][ceil(Vy/N)][ceil(Vx/N)][2] of
+ *                (min, max) value per macro-cell of side macrocell_size N;
+ *                NULL (and N = 0) disables empty-space skipping.  Borrowed.
+ * The GPU path has kernels for 3 layers (two equal hidden layers of 32 or 64
+ * neurons) with (n_levels, n_features) in {(8,2), (16,2), (16,4)}; other
+ * shapes return CINR_UNSUPPORTED. */
+typedef struct {
+    int32_t dims[3];
+    int32_t n_levels, n_features, log2_table;
+    int32_t level_res[CINR_MAX_LEVELS];
+    int32_t n_layers;
+    int32_t widths[CINR_MAX_LAYERS + 1];
+    float value_scale, value_offset;
+    const float* d_table;
+    const float* d_weights;
+    const float* d_macrocells;
+    int32_t macrocell_size;
+} cinr_volume_desc;
+
+/* Brick cache (Section 4.3.1).
+ *  brick         stored samples per brick side B (2..64); neighbouring bricks
+ *                share one sample per face, so a LoD-L brick spans
+ *                (B-1)*2^L voxels (Section 4.3.2).
+ *  n_lods        LoDs 0..n_lods-1 (<= 16).
+ *  pool_bricks   brick slots in the pool (f32, B^3 values each).
+ *  max_requests  bricks requested and decoded per frame (maxNumRequests,
+ *                at most 256).
+ *  rank_window   ranks are clamped to timestamp + rank_window (1000).
+ *  ranking       cinr_ranking.
+ *  preload_period  pre-load of Section 4.3.4: the LoD floor starts at
+ *                n_lods-1 and drops by one every preload_period frames
+ *                (0 = off).
+ *  miss_log_capacity   true-miss records kept per frame for dumps (0 = off).
+ *  evict_log_capacity  insertion/eviction records kept for dumps.
+ *  keep_request_counts nonzero: keep each frame's per-brick request counts
+ *                for CINR_DUMP_REQ_COUNT. */
+typedef struct {
+    int32_t brick, n_lods, pool_bricks, max_requests, rank_window;
+    int32_t ranking;
+    int32_t preload_period;
+    int32_t miss_log_capacity;
+    int32_t evict_log_capacity;
+    int32_t keep_request_counts;
+} cinr_cache_desc;
+
+/* Pinhole or orthographic camera.  Basis vectors are unit length; pixel
+ * (i, j) (row j = 0 at the top) maps to screen offsets
+ * sx = ((i+0.5)/W*2-1)*tan_half_x, sy = (1-(j+0.5)/H*2)*tan_half_y
+ * (perspective), or to an origin offset ((i+0.5)/W-0.5)*ortho_w along right
+ * and (0.5-(j+0.5)/H)*ortho_h along up (orthographic).  The LoD distance of
+ * Algorithm 2 is measured from `eye`. */
+typedef struct {
+    int32_t projection, width, height;
+    float eye[3], forward[3], right[3], up[3];
+    float tan_half_x, tan_half_y, ortho_w, ortho_h;
+} cinr_camera;
+
+/* Per-frame parameters.
+ *  step          sample spacing (LoD-0 voxels); opacity is corrected from a
+ *                one-voxel reference: a' = 1 - (1-a)^step.
+ *  lod_scale     LoD distance |p - eye| * lod_scale (Algorithm 2).
+ *  ert_threshold early ray termination at accumulated opacity >= threshold;
+ *                a value > 1 disables it.
+ *  seed, frame_index  the stochastic-LoD seed of frame f is derived from
+ *                (seed, f) (Section 5.3); frame_index is also the cache's
+ *                timestamp and must increase by one per cached frame.
+ *  samples_per_iter  samples gathered per wavefront step after a true miss.
+ *  mode          cinr_mode.
+ *  mlp_dtype     cinr_dtype of brick decoding and true-miss inference. */
+typedef struct {
+    float step, lod_scale, ert_threshold;
+    uint32_t seed;
+    int32_t frame_index;
+    int32_t samples_per_iter;
+    int32_t mode;
+    int32_t mlp_dtype;
+} cinr_render_params;
+
+/* Frame counters written (not accumulated) by cinr_render_frame. */
+typedef struct {
+    uint64_t rays, samples, hits, fallbacks, misses, skipped;
+    uint64_t requested, selected, evicted, iterations;
+} cinr_frame_stats;
+
+typedef enum {
+    CINR_DUMP_PAGE_TABLE = 0,   /* int32 [n_keys]: slot or -1 */
+    CINR_DUMP_SLOT_OWNER = 1,   /* int32 [pool_bricks]: key or -1 */
+    CINR_DUMP_LAST_USED = 2,    /* int32 [pool_bricks]: last frame that read the slot, -1 never */
+    CINR_DUMP_RANK = 3,         /* int64 [n_keys]: rank, -1 undefined */
+    CINR_DUMP_REQ_COUNT = 4,    /* uint32 [n_keys]: requests of the last frame (keep_request_counts) */
+    CINR_DUMP_REQUEST_LIST = 5, /* int32 [n]: keys selected at the end of the last frame, in order */
+    CINR_DUMP_MISS_LIST = 6,    /* {int32 pixel, int32 k, float x, y, z} [n] of the last frame, sorted by (pixel, k) */
+    CINR_DUMP_EVICTION_LOG = 7, /* {int32 stamp, slot, old_key, new_key} [n] since creation */
+    CINR_DUMP_POOL = 8          /* float [pool_bricks][B][B][B] */
+} cinr_dump_kind;
+
+typedef struct cinr_volume_s* cinr_volume;
+typedef struct cinr_cache_s* cinr_cache;
+
+/* Validates the description and binds the borrowed parameter buffers.
+ * Computes the per-level table layout on the host.  No device work. */
+cinr_status cinr_create_volume_inr(const cinr_volume_desc* desc, cinr_volume* out);
+void cinr_destroy_volume(cinr_volume vol);
+
+/* LoD lattice and bricks of Section 4.3.2: at LoD L the lattice step is 2^L,
+ * K_L = ceil((V-1)/2^L) + 1 points per axis, nb_L = ceil((K_L-1)/(B-1))
+ * bricks per axis; keys are numbered LoD by LoD, x fastest.
+ * Writes nb [n_lods][3] and key_offset [n_lods+1] (host arrays, either may be
+ * NULL); key_offset[n_lods] is the number of keys. */
+cinr_status cinr_lod_geometry(cinr_volume vol, int32_t brick, int32_t n_lods, int32_t* nb, int64_t* key_offset);
+
+/* Evaluates the INR (InferINR of Algorithm 1) at n positions d_pos
+ * (f32 [n][3], voxel coordinates, clamped to the box) into d_out (f32 [n]). */
+cinr_status cinr_infer_points(cinr_volume vol, const float* d_pos, int64_t n, float* d_out, int32_t mlp_dtype,
+                              void* stream);
+
+/* Brick decoding of Section 4.3.2 (the request handler's INR integration).
+ * d_reqs int32 [n][4] = (lod, bx, by, bz); d_out f32 [n][B][B][B] in
+ * (z, y, x) order; element (r, k, j, i) is the value at voxel coordinate
+ * clamp((b*(B-1) + (i, j, k)) * 2^lod, 0, V-1).  Requests are checked on the
+ * device: an out-of-range request yields a brick of NaNs. */
+cinr_status cinr_decode_bricks(cinr_volume vol, const int32_t* d_reqs, int32_t n, int32_t brick, float* d_out,
+                               int32_t mlp_dtype, void* stream);
+
+/* Macro-cell table of Section 5.2 built from the INR itself: for each cell of
+ * side `cell`, min and max of the LoD-0 lattice values in its closed region
+ * [cN, min((c+1)N, V-1)]^3, written to d_minmax (layout as d_macrocells). */
+cinr_status cinr_build_macrocells(cinr_volume vol, int32_t cell, float* d_minmax, int32_t mlp_dtype, void* stream);
+
+/* Size of the caller-provided cache workspace (page table, ranks, request
+ * counts, slot owners and stamps, request and log buffers). */
+cinr_status cinr_cache_workspace_size(cinr_volume vol, const cinr_cache_desc* desc, size_t* bytes);
+
+/* Creates a cache over a caller-provided pool (f32, >= pool_bricks*B^3
+ * values) and workspace; initialises the workspace on `stream` (all bricks
+ * unmapped, all slots free). */
+cinr_status cinr_create_cache(cinr_volume vol, const cinr_cache_desc* desc, float* d_pool, size_t pool_bytes,
+                              void* d_workspace, size_t ws_bytes, void* stream, cinr_cache* out);
+void cinr_destroy_cache(cinr_cache cache);
+
+/* Pre-loading: inserts the bricks d_keys [n] (distinct, unmapped keys) into
+ * free slots, in order, as the request handler would at the start of a frame
+ * stamped `stamp`: decoded, mapped and stamped.  Keys beyond the free slots
+ * are not inserted (pre-loading never evicts).  n <= min(pool, n_keys). */
+cinr_status cinr_cache_prefill(cinr_cache cache, const int32_t* d_keys, int32_t n, int32_t stamp, int32_t mlp_dtype,
+                               void* stream);
+
+/* Size of the per-call render workspace (ray lists, sample buffers, miss
+ * records, counters, macro-cell flags) for a width x height image. */
+cinr_status cinr_render_workspace_size(cinr_volume vol, int32_t width, int32_t height, int32_t samples_per_iter,
+                                       size_t* bytes);
+
+/* Renders one frame into d_rgba (f32 [H][W][4], straight colour and
+ * opacity, no background).
+ *  CACHED mode: `cache` must be non-NULL; the frame runs the sampler against
+ *  the cache, then the end-of-frame cache manager (ranking, request list) and
+ *  the request handler (slot choice, brick decoding, mapping), so that the
+ *  next frame starts with the new bricks (latency of one frame).
+ *  UNCACHED_DIRECT mode: `cache` is ignored; every sample is inferred.
+ *  d_tf f32 [256][4] RGBA transfer function (Section 3), linearly
+ *  interpolated at value*255.  d_stats (nullable) receives the counters. */
+cinr_status cinr_render_frame(cinr_cache cache, cinr_volume vol, const cinr_camera* camera, const float* d_tf,
+                              const cinr_render_params* params, float* d_rgba, cinr_frame_stats* d_stats,
+                              void* d_workspace, size_t ws_bytes, void* stream);
+
+/* Optional per-stage GPU timing of cinr_render_frame, for profiling.
+ * While enabled, every stage launch of render_frame is bracketed by HIP
+ * events on the caller's stream (no synchronisation is added);
+ * cinr_collect_timing synchronises on the last event, writes the summed
+ * milliseconds and the number of bracketed launches per stage
+ * (arrays of CINR_STAGE_COUNT) and clears the record. */
+typedef enum {
+    CINR_STAGE_SETUP = 0,   /* frame initialisation, macro-cell flags, ray generation */
+    CINR_STAGE_MARCH = 1,   /* sampler: cache lookups, compositing, miss gathering */
+    CINR_STAGE_INFER = 2,   /* true-miss inference */
+    CINR_STAGE_SHADE = 3,   /* compositing of gathered wavefront steps */
+    CINR_STAGE_CM = 4,      /* ranking, request selection, slot choice, mapping */
+    CINR_STAGE_DECODE = 5,  /* brick decoding into the pool */
+    CINR_STAGE_COUNT = 6
+} cinr_stage;
+cinr_status cinr_set_timing(cinr_volume vol, int32_t enable);
+cinr_status cinr_collect_timing(cinr_volume vol, double* ms, int64_t* launches);
+
+/* Copies one piece of cache state to host memory.  If `bytes` is too small
+ * (or host_dst is NULL) nothing is copied, *needed receives the size and
+ * CINR_OUT_OF_MEMORY is returned.  Synchronises `stream`. */
+cinr_status cinr_cache_dump(cinr_cache cache, int32_t kind, void* host_dst, size_t bytes, size_t* needed,
+                            void* stream);
+
+/* Thread-local description of the last failure. */
+const char* cinr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -405,7 +405,7 @@ int orc_ray_setup(const orc_camera* c, const int32_t dims[3], int32_t i, int32_t
         if (hi_ < thi) thi = hi_;
     }
     float t0 = tlo > 0.0f ? tlo : 0.0f;
-    if (!(thi >= t0)) return 0;
+    if (!(thi >= t0) || !(thi < INFINITY)) return 0; /* degenerate direction: no samples */
     *ts = t0;
     *te = thi;
     return 1;
@@ -671,8 +671,11 @@ static void insert_brick(orc_cache* c, int32_t key, int32_t stamp, uint8_t* fill
     e[3] = key;
 }
 
+/* Pre-loading into free slots only (never evicts). */
 int orc_cache_prefill(orc_cache* c, const int32_t* keys, int64_t n, int32_t stamp) {
-    if (n > c->d.pool_bricks) return -1;
+    int64_t n_free = 0;
+    for (int32_t s = 0; s < c->d.pool_bricks; ++s) n_free += c->owner[s] < 0;
+    if (n > n_free) return -1;
     for (int64_t i = 0; i < n; ++i)
         if (keys[i] < 0 || keys[i] >= c->n_keys || c->pt[keys[i]] >= 0) return -1;
     for (int64_t i = 0; i < n; ++i)

@@ -1,0 +1,51 @@
+"""Builds libcinr.so for gfx950 with hipcc (in-tree, next to this file)."""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
+LIB = os.path.join(HERE, "libcinr.so")
+SOURCES = ["inr.hip", "render.hip", "cache.hip", "api.hip"]
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+# -ffp-contract=off: the sampler's decision plane is a fixed sequence of
+# correctly rounded binary32 operations (value-plane code uses explicit fmaf).
+# -packed-fp32-ops: no packed FP32 instructions.
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-I", INCLUDE, "-I", CSRC]
+
+
+def build(verbose: bool = False, jobs: int = 4) -> str:
+    objs = []
+    procs = []
+    for src in SOURCES:
+        obj = os.path.join(CSRC, src.replace(".hip", ".o"))
+        cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((subprocess.Popen(cmd, stderr=subprocess.PIPE, text=True), src))
+        objs.append(obj)
+    failed = False
+    for p, src in procs:
+        _, err = p.communicate()
+        err = "\n".join(l for l in err.splitlines() if "not a recognized feature" not in l)
+        if p.returncode != 0:
+            failed = True
+            sys.stderr.write(f"--- {src} ---\n{err}\n")
+        elif err.strip() and verbose:
+            sys.stderr.write(err + "\n")
+    if failed:
+        raise RuntimeError("HIP build failed")
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB, *objs]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True, stderr=subprocess.PIPE)
+    for o in objs:
+        os.remove(o)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)

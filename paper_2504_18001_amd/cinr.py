@@ -1,0 +1,304 @@
+"""Thin Python binding of libcinr (include/cinr.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  PyTorch provides device memory and the current stream.  The
+library is loaded from this package directory; importing this module on a
+machine where it is missing raises immediately.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcinr.so")
+
+MAX_LEVELS, MAX_LAYERS, MAX_LODS = 32, 8, 16
+F32, BF16, F16 = 0, 1, 2
+CACHED, UNCACHED_DIRECT = 0, 1
+RANK_TIMESTAMP, RANK_PRIORITY = 0, 1
+PERSPECTIVE, ORTHOGRAPHIC = 0, 1
+DUMP_PAGE_TABLE, DUMP_SLOT_OWNER, DUMP_LAST_USED, DUMP_RANK, DUMP_REQ_COUNT = 0, 1, 2, 3, 4
+DUMP_REQUEST_LIST, DUMP_MISS_LIST, DUMP_EVICTION_LOG, DUMP_POOL = 5, 6, 7, 8
+
+DTYPES = {"f32": F32, "fp32": F32, "bf16": BF16, "f16": F16, "fp16": F16}
+
+
+class CinrError(RuntimeError):
+    pass
+
+
+class VolumeDesc(C.Structure):
+    _fields_ = [("dims", C.c_int32 * 3), ("n_levels", C.c_int32), ("n_features", C.c_int32),
+                ("log2_table", C.c_int32), ("level_res", C.c_int32 * MAX_LEVELS), ("n_layers", C.c_int32),
+                ("widths", C.c_int32 * (MAX_LAYERS + 1)), ("value_scale", C.c_float), ("value_offset", C.c_float),
+                ("d_table", C.c_void_p), ("d_weights", C.c_void_p), ("d_macrocells", C.c_void_p),
+                ("macrocell_size", C.c_int32)]
+
+
+class CacheDesc(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("brick", "n_lods", "pool_bricks", "max_requests", "rank_window", "ranking",
+                                          "preload_period", "miss_log_capacity", "evict_log_capacity",
+                                          "keep_request_counts")]
+
+
+class CameraDesc(C.Structure):
+    _fields_ = [("projection", C.c_int32), ("width", C.c_int32), ("height", C.c_int32), ("eye", C.c_float * 3),
+                ("forward", C.c_float * 3), ("right", C.c_float * 3), ("up", C.c_float * 3),
+                ("tan_half_x", C.c_float), ("tan_half_y", C.c_float), ("ortho_w", C.c_float), ("ortho_h", C.c_float)]
+
+
+class RenderParams(C.Structure):
+    _fields_ = [("step", C.c_float), ("lod_scale", C.c_float), ("ert_threshold", C.c_float), ("seed", C.c_uint32),
+                ("frame_index", C.c_int32), ("samples_per_iter", C.c_int32), ("mode", C.c_int32),
+                ("mlp_dtype", C.c_int32)]
+
+
+STAGES = ("setup", "march", "infer", "shade", "cm", "decode")
+STAT_FIELDS = ("rays", "samples", "hits", "fallbacks", "misses", "skipped", "requested", "selected", "evicted",
+               "iterations")
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise CinrError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        P, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+        sig = {
+            "cinr_create_volume_inr": [P, P],
+            "cinr_destroy_volume": [P],
+            "cinr_lod_geometry": [P, i32, i32, P, P],
+            "cinr_infer_points": [P, P, i64, P, i32, P],
+            "cinr_decode_bricks": [P, P, i32, i32, P, i32, P],
+            "cinr_build_macrocells": [P, i32, P, i32, P],
+            "cinr_cache_workspace_size": [P, P, P],
+            "cinr_create_cache": [P, P, P, sz, P, sz, P, P],
+            "cinr_destroy_cache": [P],
+            "cinr_cache_prefill": [P, P, i32, i32, i32, P],
+            "cinr_render_workspace_size": [P, i32, i32, i32, P],
+            "cinr_render_frame": [P, P, P, P, P, P, P, P, sz, P],
+            "cinr_cache_dump": [P, i32, P, sz, P, P],
+            "cinr_last_error": [],
+            "cinr_set_timing": [P, i32],
+            "cinr_collect_timing": [P, P, P],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.cinr_destroy_volume.restype = None
+        L.cinr_destroy_cache.restype = None
+        L.cinr_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise CinrError(f"libcinr error {rc}: {lib().cinr_last_error().decode()}")
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dtype(d):
+    return DTYPES[d] if isinstance(d, str) else int(d)
+
+
+class Volume:
+    """A volume defined by a hash-grid INR whose parameters live on the GPU."""
+
+    def __init__(self, arch, table, weights, value_scale=1.0, value_offset=0.0, macrocells=None, macro_cell=0,
+                 dims=None, device="cuda"):
+        self.arch = arch
+        self.dims = tuple(int(x) for x in (arch.dims if dims is None else dims))
+        self.table = torch.as_tensor(np.asarray(table, np.float32)).to(device).contiguous() \
+            if not torch.is_tensor(table) else table.to(device=device, dtype=torch.float32).contiguous()
+        self.weights = torch.as_tensor(np.asarray(weights, np.float32)).to(device).contiguous() \
+            if not torch.is_tensor(weights) else weights.to(device=device, dtype=torch.float32).contiguous()
+        self.macrocells = None
+        if macrocells is not None:
+            mc = macrocells if torch.is_tensor(macrocells) else torch.as_tensor(np.asarray(macrocells, np.float32))
+            self.macrocells = mc.to(device=device, dtype=torch.float32).contiguous()
+        d = VolumeDesc()
+        for a in range(3):
+            d.dims[a] = self.dims[a]
+        d.n_levels, d.n_features, d.log2_table = arch.n_levels, arch.n_features, arch.log2_table
+        for l, n in enumerate(arch.level_res):
+            d.level_res[l] = n
+        d.n_layers = len(arch.widths) - 1
+        for i, w in enumerate(arch.widths):
+            d.widths[i] = w
+        d.value_scale, d.value_offset = float(value_scale), float(value_offset)
+        d.d_table = self.table.data_ptr()
+        d.d_weights = self.weights.data_ptr()
+        d.d_macrocells = self.macrocells.data_ptr() if self.macrocells is not None else None
+        d.macrocell_size = int(macro_cell) if self.macrocells is not None else 0
+        self.desc = d
+        h = C.c_void_p()
+        _check(lib().cinr_create_volume_inr(C.byref(d), C.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.cinr_destroy_volume(self.h)
+            self.h = None
+
+    def geometry(self, brick, n_lods):
+        nb = np.zeros((n_lods, 3), np.int32)
+        off = np.zeros(n_lods + 1, np.int64)
+        _check(lib().cinr_lod_geometry(self.h, brick, n_lods, nb.ctypes.data_as(C.c_void_p),
+                                       off.ctypes.data_as(C.c_void_p)))
+        return nb, off
+
+    def infer_points(self, pos, dtype="f32", out=None):
+        pos = pos.contiguous()
+        n = pos.shape[0]
+        out = torch.empty(n, dtype=torch.float32, device=pos.device) if out is None else out
+        _check(lib().cinr_infer_points(self.h, _ptr(pos), n, _ptr(out), _dtype(dtype), _stream()))
+        return out
+
+    def decode_bricks(self, reqs, brick, dtype="f32", out=None):
+        reqs = reqs.to(torch.int32).contiguous()
+        n = reqs.shape[0]
+        out = torch.empty((n, brick, brick, brick), dtype=torch.float32, device=reqs.device) if out is None else out
+        _check(lib().cinr_decode_bricks(self.h, _ptr(reqs), n, brick, _ptr(out), _dtype(dtype), _stream()))
+        return out
+
+    def set_timing(self, on: bool):
+        _check(lib().cinr_set_timing(self.h, 1 if on else 0))
+
+    def collect_timing(self):
+        """{stage: (milliseconds, launches)} since the last collection."""
+        ms = np.zeros(len(STAGES), np.float64)
+        n = np.zeros(len(STAGES), np.int64)
+        _check(lib().cinr_collect_timing(self.h, ms.ctypes.data_as(C.c_void_p), n.ctypes.data_as(C.c_void_p)))
+        return {s: (float(ms[i]), int(n[i])) for i, s in enumerate(STAGES)}
+
+    def build_macrocells(self, cell, dtype="f32"):
+        M = [(d + cell - 1) // cell for d in self.dims]
+        out = torch.empty((M[2], M[1], M[0], 2), dtype=torch.float32, device=self.table.device)
+        _check(lib().cinr_build_macrocells(self.h, cell, _ptr(out), _dtype(dtype), _stream()))
+        return out
+
+
+class Cache:
+    """Multi-resolution brick cache over a torch-allocated pool and workspace."""
+
+    def __init__(self, volume: Volume, brick, n_lods, pool_bricks, max_requests, rank_window=1000,
+                 ranking=RANK_PRIORITY, preload_period=0, miss_log_capacity=0, evict_log_capacity=4096,
+                 keep_request_counts=False):
+        self.volume = volume
+        d = CacheDesc()
+        d.brick, d.n_lods, d.pool_bricks, d.max_requests = brick, n_lods, pool_bricks, max_requests
+        d.rank_window, d.ranking, d.preload_period = rank_window, ranking, preload_period
+        d.miss_log_capacity, d.evict_log_capacity = miss_log_capacity, evict_log_capacity
+        d.keep_request_counts = 1 if keep_request_counts else 0
+        self.desc = d
+        ws = C.c_size_t()
+        _check(lib().cinr_cache_workspace_size(volume.h, C.byref(d), C.byref(ws)))
+        dev = volume.table.device
+        self.pool = torch.empty(max(pool_bricks, 1) * brick ** 3, dtype=torch.float32, device=dev)
+        self.workspace = torch.empty(ws.value, dtype=torch.uint8, device=dev)
+        h = C.c_void_p()
+        _check(lib().cinr_create_cache(volume.h, C.byref(d), _ptr(self.pool), self.pool.numel() * 4,
+                                       _ptr(self.workspace), ws.value, _stream(), C.byref(h)))
+        self.h = h
+        nb, off = volume.geometry(brick, n_lods)
+        self.nb, self.key_offset = nb, off
+        self.n_keys = int(off[-1])
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.cinr_destroy_cache(self.h)
+            self.h = None
+
+    def prefill(self, keys, stamp=0, dtype="f32"):
+        k = keys.to(torch.int32).contiguous()
+        _check(lib().cinr_cache_prefill(self.h, _ptr(k), k.numel(), stamp, _dtype(dtype), _stream()))
+
+    def dump(self, kind):
+        need = C.c_size_t()
+        rc = lib().cinr_cache_dump(self.h, kind, None, 0, C.byref(need), _stream())
+        if rc not in (0, -2):
+            _check(rc)
+        buf = np.empty(max(need.value, 1), np.uint8)
+        _check(lib().cinr_cache_dump(self.h, kind, buf.ctypes.data_as(C.c_void_p), buf.size, C.byref(need),
+                                     _stream()))
+        buf = buf[:need.value]
+        if kind in (DUMP_PAGE_TABLE, DUMP_SLOT_OWNER, DUMP_LAST_USED, DUMP_REQUEST_LIST):
+            return buf.view(np.int32)
+        if kind == DUMP_RANK:
+            return buf.view(np.int64)
+        if kind == DUMP_REQ_COUNT:
+            return buf.view(np.uint32)
+        if kind == DUMP_MISS_LIST:
+            rec = buf.view(np.int32).reshape(-1, 5)
+            return rec[:, :2].copy(), rec[:, 2:].copy().view(np.float32)
+        if kind == DUMP_EVICTION_LOG:
+            return buf.view(np.int32).reshape(-1, 4)
+        if kind == DUMP_POOL:
+            B = self.desc.brick
+            return buf.view(np.float32).reshape(-1, B, B, B)
+        return buf
+
+
+def camera_desc(cam) -> CameraDesc:
+    c = CameraDesc()
+    c.projection, c.width, c.height = int(cam.projection), int(cam.width), int(cam.height)
+    for a in range(3):
+        c.eye[a] = float(cam.eye[a])
+        c.forward[a] = float(cam.forward[a])
+        c.right[a] = float(cam.right[a])
+        c.up[a] = float(cam.up[a])
+    c.tan_half_x, c.tan_half_y = float(cam.tan_half_x), float(cam.tan_half_y)
+    c.ortho_w, c.ortho_h = float(cam.ortho_w), float(cam.ortho_h)
+    return c
+
+
+class Renderer:
+    """Owns the per-call render workspace (grown on demand)."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self.ws = None
+        self.stats = torch.zeros(len(STAT_FIELDS), dtype=torch.int64, device=device)
+
+    def render(self, volume: Volume, cam, tf, step, lod_scale=0.0, frame_index=0, seed=0, ert_threshold=2.0,
+               samples_per_iter=32, mode=CACHED, dtype="f32", cache: Cache = None, out=None, stats=None):
+        need = C.c_size_t()
+        _check(lib().cinr_render_workspace_size(volume.h, cam.width, cam.height, samples_per_iter, C.byref(need)))
+        if self.ws is None or self.ws.numel() < need.value:
+            self.ws = torch.empty(need.value, dtype=torch.uint8, device=self.device)
+        out = torch.empty((cam.height, cam.width, 4), dtype=torch.float32, device=self.device) if out is None else out
+        tf = tf if torch.is_tensor(tf) else torch.as_tensor(np.asarray(tf, np.float32))
+        tf = tf.to(device=self.device, dtype=torch.float32).contiguous()
+        self._tf = tf
+        p = RenderParams()
+        p.step, p.lod_scale, p.ert_threshold = float(step), float(lod_scale), float(ert_threshold)
+        p.seed, p.frame_index, p.samples_per_iter = int(seed) & 0xFFFFFFFF, int(frame_index), int(samples_per_iter)
+        p.mode, p.mlp_dtype = int(mode), _dtype(dtype)
+        cd = camera_desc(cam)
+        st = self.stats if stats is None else stats
+        _check(lib().cinr_render_frame(cache.h if cache is not None else None, volume.h, C.byref(cd), _ptr(tf),
+                                       C.byref(p), _ptr(out), _ptr(st), _ptr(self.ws), self.ws.numel(),
+                                       _stream()))
+        self._last_stats = st
+        return out
+
+    def last_stats(self):
+        v = self._last_stats.cpu().numpy()
+        return {k: int(v[i]) for i, k in enumerate(STAT_FIELDS)}

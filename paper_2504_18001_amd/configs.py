@@ -72,9 +72,9 @@ class Workload:
     tf_switch_frame: int = -1     # from this frame (mod n_frames) on, a random TF is used
     tf_seed: int = 77
 
-    def camera(self, frame: int) -> synth.Camera:
+    def camera(self, frame: int, dims=None) -> synth.Camera:
         ang = self.orbit_step_deg * (frame % self.n_frames)
-        return synth.orbit_camera(self.projection, self.arch.dims, self.orbit_radius, ang,
+        return synth.orbit_camera(self.projection, dims or self.arch.dims, self.orbit_radius, ang,
                                   self.orbit_elev_deg, self.width, self.height, self.fov_y_deg,
                                   self.ortho_extent, self.ortho_extent)
 

@@ -1,0 +1,666 @@
+// C ABI of libcinr: object lifetimes, argument validation, workspace
+// carving and the per-frame launch sequence.  All device work is enqueued on
+// the caller's stream.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "frame.h"
+
+using namespace cinr;
+
+namespace {
+
+thread_local std::string g_err;
+
+cinr_status fail(cinr_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) return fail(CINR_HIP_ERROR, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Sequential carving of a caller workspace.
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(void* b) : base((char*)b) {}
+    template <class T>
+    T* take(size_t n) {
+        T* p = base ? (T*)(base + off) : nullptr;
+        off = align256(off + sizeof(T) * (n ? n : 1));
+        return p;
+    }
+};
+
+bool geometry(const int32_t dims[3], int32_t B, int32_t n_lods, CacheGeom& g) {
+    if (B < 2 || n_lods < 1 || n_lods > kMaxLods) return false;
+    g = CacheGeom{};
+    g.brick = B;
+    g.n_lods = n_lods;
+    int64_t off = 0;
+    for (int L = 0; L < n_lods; ++L) {
+        int64_t cnt = 1;
+        for (int a = 0; a < 3; ++a) {
+            const int64_t span = (int64_t)dims[a] - 1;
+            const int64_t step = (int64_t)1 << L;
+            const int64_t K = (span + step - 1) / step + 1;
+            const int64_t nb = (K - 1 + (B - 1) - 1) / (B - 1);
+            g.lod[L].K[a] = (int32_t)K;
+            g.lod[L].nb[a] = (int32_t)nb;
+            cnt *= nb;
+        }
+        g.lod[L].off = off;
+        off += cnt;
+    }
+    g.n_keys = off;
+    return true;
+}
+
+}  // namespace
+
+// Per-stage event timing (optional).
+struct Timing {
+    bool on = false;
+    std::vector<hipEvent_t> pool;  // free timing events
+    struct Rec {
+        int stage;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        (void)hipEventCreate(&e);
+        return e;
+    }
+};
+
+struct cinr_volume_s {
+    cinr_volume_desc desc;
+    InrDev m;
+    int32_t n_cells = 0;
+    int32_t M[3] = {0, 0, 0};
+    int32_t* pinned = nullptr;  // readback of the live-ray count
+    hipEvent_t ev = nullptr;
+    Timing timing;
+};
+
+namespace {
+// Brackets the launches of one stage with timing events when enabled.
+struct StageTimer {
+    Timing& t;
+    hipStream_t s;
+    int stage;
+    hipEvent_t a = nullptr;
+    StageTimer(Timing& t_, hipStream_t s_, int stage_) : t(t_), s(s_), stage(stage_) {
+        if (t.on) {
+            a = t.get();
+            (void)hipEventRecord(a, s);
+        }
+    }
+    ~StageTimer() {
+        if (t.on) {
+            hipEvent_t b = t.get();
+            (void)hipEventRecord(b, s);
+            t.recs.push_back(Timing::Rec{stage, a, b});
+        }
+    }
+};
+}  // namespace
+
+struct cinr_cache_s {
+    cinr_volume vol;
+    cinr_cache_desc desc;
+    CacheGeom g;
+    CacheDev c;
+    TopkPlan plan_sel, plan_vic;
+    int32_t lim;  // request list length bound: min(max_requests, pool)
+};
+
+// ---------------------------------------------------------------------------
+// Volume
+// ---------------------------------------------------------------------------
+
+extern "C" const char* cinr_last_error(void) { return g_err.c_str(); }
+
+extern "C" cinr_status cinr_create_volume_inr(const cinr_volume_desc* d, cinr_volume* out) {
+    if (!d || !out) return fail(CINR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    for (int a = 0; a < 3; ++a)
+        if (d->dims[a] < 2 || d->dims[a] > (1 << 24)) return fail(CINR_INVALID_ARG, "dims[%d] = %d out of [2, 2^24]", a, d->dims[a]);
+    if (d->n_levels < 1 || d->n_levels > CINR_MAX_LEVELS) return fail(CINR_INVALID_ARG, "n_levels = %d", d->n_levels);
+    if (d->n_features < 1 || d->n_features > 4 || d->n_features == 3)
+        return fail(CINR_INVALID_ARG, "n_features = %d (1, 2 or 4)", d->n_features);
+    if (d->log2_table < 4 || d->log2_table > 30) return fail(CINR_INVALID_ARG, "log2_table = %d", d->log2_table);
+    if (d->n_layers < 1 || d->n_layers > CINR_MAX_LAYERS) return fail(CINR_INVALID_ARG, "n_layers = %d", d->n_layers);
+    if (d->widths[0] != d->n_levels * d->n_features) return fail(CINR_INVALID_ARG, "widths[0] must be n_levels*n_features");
+    if (d->widths[d->n_layers] != 1) return fail(CINR_INVALID_ARG, "the last width must be 1");
+    if (!d->d_table || !d->d_weights) return fail(CINR_INVALID_ARG, "null parameter buffer");
+    if (d->d_macrocells && d->macrocell_size < 1) return fail(CINR_INVALID_ARG, "macrocell_size must be >= 1");
+    cinr_volume v = new cinr_volume_s();
+    v->desc = *d;
+    InrDev& m = v->m;
+    m = InrDev{};
+    const uint64_t T = 1ull << d->log2_table;
+    uint64_t off = 0;
+    for (int a = 0; a < 3; ++a) {
+        m.dims[a] = d->dims[a];
+        m.vm1[a] = (float)(d->dims[a] - 1);
+        m.inv_dims[a] = 1.0 / (double)d->dims[a];
+    }
+    m.n_levels = d->n_levels;
+    m.n_features = d->n_features;
+    for (int l = 0; l < d->n_levels; ++l) {
+        const int64_t N = d->level_res[l];
+        if (N < 1 || N > (1 << 24)) {
+            delete v;
+            return fail(CINR_INVALID_ARG, "level_res[%d] = %lld", l, (long long)N);
+        }
+        const uint64_t side = (uint64_t)N + 1;
+        const uint64_t dense = side * side * side;
+        m.lv[l].res = (double)N;
+        m.lv[l].side = (uint32_t)side;
+        m.lv[l].side2 = (uint32_t)(side * side <= 0xFFFFFFFFull ? side * side : 0);
+        m.lv[l].offset = (uint32_t)off;
+        m.lv[l].mask = dense <= T ? 0u : (uint32_t)(T - 1);
+        off += dense <= T ? dense : T;
+        if (off > 0xFFFFFFFFull) {
+            delete v;
+            return fail(CINR_INVALID_ARG, "hash table too large");
+        }
+    }
+    m.value_scale = d->value_scale;
+    m.value_offset = d->value_offset;
+    m.table = d->d_table;
+    m.weights = d->d_weights;
+    m.in = d->widths[0];
+    m.hidden = d->n_layers == 3 && d->widths[1] == d->widths[2] ? d->widths[1] : -1;
+    if (d->d_macrocells) {
+        for (int a = 0; a < 3; ++a) v->M[a] = (d->dims[a] + d->macrocell_size - 1) / d->macrocell_size;
+        v->n_cells = v->M[0] * v->M[1] * v->M[2];
+    }
+    *out = v;
+    return CINR_OK;
+}
+
+extern "C" void cinr_destroy_volume(cinr_volume v) {
+    if (!v) return;
+    if (v->pinned) (void)hipHostFree(v->pinned);
+    if (v->ev) (void)hipEventDestroy(v->ev);
+    for (auto& r : v->timing.recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : v->timing.pool) (void)hipEventDestroy(e);
+    delete v;
+}
+
+extern "C" cinr_status cinr_set_timing(cinr_volume v, int32_t enable) {
+    if (!v) return fail(CINR_INVALID_ARG, "null volume");
+    v->timing.on = enable != 0;
+    return CINR_OK;
+}
+
+extern "C" cinr_status cinr_collect_timing(cinr_volume v, double* ms, int64_t* launches) {
+    if (!v || !ms || !launches) return fail(CINR_INVALID_ARG, "null argument");
+    for (int i = 0; i < CINR_STAGE_COUNT; ++i) {
+        ms[i] = 0.0;
+        launches[i] = 0;
+    }
+    Timing& t = v->timing;
+    if (!t.recs.empty()) HIP_TRY(hipEventSynchronize(t.recs.back().b));
+    for (auto& r : t.recs) {
+        float e = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&e, r.a, r.b));
+        ms[r.stage] += e;
+        launches[r.stage] += 1;
+        t.pool.push_back(r.a);
+        t.pool.push_back(r.b);
+    }
+    t.recs.clear();
+    return CINR_OK;
+}
+
+extern "C" cinr_status cinr_lod_geometry(cinr_volume v, int32_t brick, int32_t n_lods, int32_t* nb, int64_t* key_offset) {
+    if (!v) return fail(CINR_INVALID_ARG, "null volume");
+    CacheGeom g;
+    if (!geometry(v->desc.dims, brick, n_lods, g)) return fail(CINR_INVALID_ARG, "brick >= 2 and 1 <= n_lods <= 16 required");
+    for (int L = 0; L < n_lods; ++L) {
+        if (nb)
+            for (int a = 0; a < 3; ++a) nb[3 * L + a] = g.lod[L].nb[a];
+        if (key_offset) key_offset[L] = g.lod[L].off;
+    }
+    if (key_offset) key_offset[n_lods] = g.n_keys;
+    return CINR_OK;
+}
+
+static cinr_status check_shape(cinr_volume v, int32_t prec) {
+    if (prec != CINR_F32 && prec != CINR_BF16 && prec != CINR_F16) return fail(CINR_INVALID_ARG, "mlp_dtype = %d", prec);
+    if (v->m.hidden < 0 || !inr_shape_supported(v->m))
+        return fail(CINR_UNSUPPORTED, "no gfx950 kernel for this INR shape (3 layers, levels x features in {8x2, 16x2, 16x4}, hidden 32 or 64)");
+    return CINR_OK;
+}
+
+extern "C" cinr_status cinr_infer_points(cinr_volume v, const float* d_pos, int64_t n, float* d_out, int32_t prec, void* stream) {
+    if (!v || (n > 0 && (!d_pos || !d_out)) || n < 0) return fail(CINR_INVALID_ARG, "invalid arguments");
+    cinr_status st = check_shape(v, prec);
+    if (st) return st;
+    HIP_TRY(inr_infer_points(v->m, d_pos, n, d_out, prec, (hipStream_t)stream));
+    return CINR_OK;
+}
+
+extern "C" cinr_status cinr_decode_bricks(cinr_volume v, const int32_t* d_reqs, int32_t n, int32_t brick, float* d_out,
+                                          int32_t prec, void* stream) {
+    if (!v || n < 0 || (n > 0 && (!d_reqs || !d_out))) return fail(CINR_INVALID_ARG, "invalid arguments");
+    if (brick < 2 || brick > 64) return fail(CINR_INVALID_ARG, "brick = %d out of [2, 64]", brick);
+    cinr_status st = check_shape(v, prec);
+    if (st) return st;
+    CacheGeom g;
+    geometry(v->desc.dims, brick, kMaxLods, g);
+    HIP_TRY(inr_decode_bricks(v->m, g, d_reqs, nullptr, n, nullptr, d_out, prec, (hipStream_t)stream));
+    return CINR_OK;
+}
+
+extern "C" cinr_status cinr_build_macrocells(cinr_volume v, int32_t cell, float* d_minmax, int32_t prec, void* stream) {
+    if (!v || cell < 1 || !d_minmax) return fail(CINR_INVALID_ARG, "invalid arguments");
+    cinr_status st = check_shape(v, prec);
+    if (st) return st;
+    HIP_TRY(inr_macrocells(v->m, cell, d_minmax, prec, (hipStream_t)stream));
+    return CINR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Cache
+// ---------------------------------------------------------------------------
+
+static cinr_status check_cache_desc(cinr_volume v, const cinr_cache_desc* d, CacheGeom& g) {
+    if (!v || !d) return fail(CINR_INVALID_ARG, "null argument");
+    if (d->brick < 2 || d->brick > 64) return fail(CINR_INVALID_ARG, "brick = %d out of [2, 64]", d->brick);
+    if (d->n_lods < 1 || d->n_lods > CINR_MAX_LODS) return fail(CINR_INVALID_ARG, "n_lods = %d", d->n_lods);
+    if (d->pool_bricks < 0 || d->max_requests < 0 || d->max_requests > kMaxRequests)
+        return fail(CINR_INVALID_ARG, "pool_bricks >= 0 and 0 <= max_requests <= %d required", kMaxRequests);
+    if (d->rank_window < 0) return fail(CINR_INVALID_ARG, "rank_window < 0");
+    if (d->miss_log_capacity < 0 || d->evict_log_capacity < 0) return fail(CINR_INVALID_ARG, "negative log capacity");
+    if (!geometry(v->desc.dims, d->brick, d->n_lods, g)) return fail(CINR_INVALID_ARG, "invalid geometry");
+    if (g.n_keys > 0x7FFFFFFF) return fail(CINR_UNSUPPORTED, "more than 2^31 bricks");
+    return CINR_OK;
+}
+
+static size_t cache_layout(const cinr_cache_desc* d, const CacheGeom& g, CacheDev* c, TopkPlan* ps, TopkPlan* pv,
+                           void* base) {
+    const int64_t nk = g.n_keys;
+    const int32_t P = d->pool_bricks;
+    const int32_t lim = std::max(1, std::min(d->max_requests, P));
+    const int32_t ins_cap = std::max(lim, (int32_t)std::min<int64_t>(P, nk));
+    const TopkPlan plan_sel = make_topk_plan(nk, lim);
+    const TopkPlan plan_vic = make_topk_plan(P > 0 ? P : 1, lim);
+    size_t buf = 0;
+    for (const TopkPlan* p : {&plan_sel, &plan_vic})
+        for (int i = 0; i < p->n_pass; ++i) buf = std::max(buf, (size_t)p->blocks[i] * lim);
+    Carver cv(base);
+    CacheDev x{};
+    x.pt = cv.take<int32_t>(nk);
+    x.rank = cv.take<int64_t>(nk);
+    x.req = cv.take<uint32_t>(nk);
+    x.last_req = d->keep_request_counts ? cv.take<uint32_t>(nk) : nullptr;
+    x.touched = cv.take<int32_t>(nk);
+    x.cand = cv.take<uint64_t>(nk);
+    x.owner = cv.take<int32_t>(P);
+    x.last_used = cv.take<int32_t>(P);
+    x.ins_keys = cv.take<int32_t>(ins_cap);
+    x.ins_slots = cv.take<int32_t>(ins_cap);
+    x.ins_reqs = cv.take<int32_t>((size_t)ins_cap * 4);
+    x.topk[0] = cv.take<uint64_t>(buf);
+    x.topk[1] = cv.take<uint64_t>(buf);
+    x.sel = cv.take<uint64_t>(lim);
+    x.vic = cv.take<uint64_t>(lim);
+    x.misslog = cv.take<MissLogRec>(d->miss_log_capacity);
+    x.misslog_cap = d->miss_log_capacity;
+    x.evlog = cv.take<int32_t>((size_t)d->evict_log_capacity * 4);
+    x.evlog_cap = d->evict_log_capacity;
+    x.ctr = cv.take<CacheCtr>(1);
+    x.pool_bricks = P;
+    x.max_requests = d->max_requests;
+    x.rank_window = d->rank_window;
+    x.ranking = d->ranking;
+    x.ins_cap = ins_cap;
+    if (!d->keep_request_counts && base == nullptr) x.last_req = nullptr;
+    if (c) *c = x;
+    if (ps) *ps = plan_sel;
+    if (pv) *pv = plan_vic;
+    return cv.off;
+}
+
+extern "C" cinr_status cinr_cache_workspace_size(cinr_volume v, const cinr_cache_desc* d, size_t* bytes) {
+    CacheGeom g;
+    cinr_status st = check_cache_desc(v, d, g);
+    if (st) return st;
+    if (!bytes) return fail(CINR_INVALID_ARG, "null bytes");
+    *bytes = cache_layout(d, g, nullptr, nullptr, nullptr, nullptr);
+    return CINR_OK;
+}
+
+extern "C" cinr_status cinr_create_cache(cinr_volume v, const cinr_cache_desc* d, float* d_pool, size_t pool_bytes,
+                                         void* d_ws, size_t ws_bytes, void* stream, cinr_cache* out) {
+    if (!out) return fail(CINR_INVALID_ARG, "null out");
+    *out = nullptr;
+    CacheGeom g;
+    cinr_status st = check_cache_desc(v, d, g);
+    if (st) return st;
+    const size_t B3 = (size_t)d->brick * d->brick * d->brick;
+    if (pool_bytes < (size_t)d->pool_bricks * B3 * sizeof(float))
+        return fail(CINR_OUT_OF_MEMORY, "pool of %zu bytes < %zu needed", pool_bytes, (size_t)d->pool_bricks * B3 * 4);
+    if (d->pool_bricks > 0 && !d_pool) return fail(CINR_INVALID_ARG, "null pool");
+    const size_t need = cache_layout(d, g, nullptr, nullptr, nullptr, nullptr);
+    if (!d_ws || ws_bytes < need) return fail(CINR_OUT_OF_MEMORY, "workspace of %zu bytes < %zu needed", ws_bytes, need);
+    cinr_cache c = new cinr_cache_s();
+    c->vol = v;
+    c->desc = *d;
+    c->g = g;
+    cache_layout(d, g, &c->c, &c->plan_sel, &c->plan_vic, d_ws);
+    c->c.pool = d_pool;
+    c->lim = std::max(1, std::min(d->max_requests, d->pool_bricks));
+    hipError_t e = launch_cache_init(c->c, g.n_keys, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(CINR_HIP_ERROR, "cache init: %s", hipGetErrorString(e));
+    }
+    *out = c;
+    return CINR_OK;
+}
+
+extern "C" void cinr_destroy_cache(cinr_cache c) { delete c; }
+
+extern "C" cinr_status cinr_cache_prefill(cinr_cache c, const int32_t* d_keys, int32_t n, int32_t stamp, int32_t prec,
+                                          void* stream) {
+    if (!c || n < 0 || (n > 0 && !d_keys)) return fail(CINR_INVALID_ARG, "invalid arguments");
+    if (n > c->c.ins_cap) return fail(CINR_INVALID_ARG, "prefill of %d bricks exceeds %d", n, c->c.ins_cap);
+    cinr_status st = check_shape(c->vol, prec);
+    if (st) return st;
+    if (n == 0) return CINR_OK;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(launch_prefill_setup(c->c, d_keys, n, s));
+    HIP_TRY(launch_insert(c->c, c->g, stamp, n, s));
+    HIP_TRY(inr_decode_bricks(c->vol->m, c->g, c->c.ins_reqs, &c->c.ctr->n_sel, n, c->c.ins_slots, c->c.pool, prec, s));
+    return CINR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Render
+// ---------------------------------------------------------------------------
+
+struct RenderLayout {
+    int32_t* live0;
+    int32_t* live1;
+    int32_t* k_next;
+    int32_t* pend_pix;
+    int32_t* pend_n;
+    float* vals;
+    float4* miss_rec;
+    IterCtr* ctr;
+    uint8_t* flags;
+    unsigned long long* stats;
+};
+
+static size_t render_layout(int64_t npix, int32_t S, int64_t n_cells, RenderLayout* r, void* base) {
+    Carver cv(base);
+    RenderLayout x;
+    x.live0 = cv.take<int32_t>(npix);
+    x.live1 = cv.take<int32_t>(npix);
+    x.k_next = cv.take<int32_t>(npix);
+    x.pend_pix = cv.take<int32_t>(npix);
+    x.pend_n = cv.take<int32_t>(npix);
+    x.vals = cv.take<float>((size_t)npix * S);
+    x.miss_rec = cv.take<float4>((size_t)npix * S);
+    x.ctr = cv.take<IterCtr>(kMaxIters + 2);
+    x.flags = cv.take<uint8_t>(n_cells);
+    x.stats = cv.take<unsigned long long>(ST_COUNT);
+    if (r) *r = x;
+    return cv.off;
+}
+
+extern "C" cinr_status cinr_render_workspace_size(cinr_volume v, int32_t W, int32_t H, int32_t S, size_t* bytes) {
+    if (!v || !bytes || W < 1 || H < 1 || S < 1) return fail(CINR_INVALID_ARG, "invalid arguments");
+    if ((int64_t)W * H * S > 0xFFFFFFFFll) return fail(CINR_INVALID_ARG, "width*height*samples_per_iter >= 2^32");
+    *bytes = render_layout((int64_t)W * H, S, v->n_cells, nullptr, nullptr);
+    return CINR_OK;
+}
+
+extern "C" cinr_status cinr_render_frame(cinr_cache c, cinr_volume v, const cinr_camera* cam, const float* d_tf,
+                                         const cinr_render_params* rp, float* d_rgba, cinr_frame_stats* d_stats,
+                                         void* d_ws, size_t ws_bytes, void* stream) {
+    if (!v || !cam || !d_tf || !rp || !d_rgba) return fail(CINR_INVALID_ARG, "null argument");
+    if (cam->width < 1 || cam->height < 1) return fail(CINR_INVALID_ARG, "empty image");
+    if (cam->projection != CINR_PERSPECTIVE && cam->projection != CINR_ORTHOGRAPHIC)
+        return fail(CINR_INVALID_ARG, "projection = %d", cam->projection);
+    {
+        const float* vs[4] = {cam->eye, cam->forward, cam->right, cam->up};
+        for (const float* q : vs)
+            for (int a = 0; a < 3; ++a)
+                if (!isfinite(q[a])) return fail(CINR_INVALID_ARG, "non-finite camera vector");
+        const float sc[4] = {cam->tan_half_x, cam->tan_half_y, cam->ortho_w, cam->ortho_h};
+        for (float x : sc)
+            if (!isfinite(x)) return fail(CINR_INVALID_ARG, "non-finite camera extent");
+        if (cam->forward[0] == 0.0f && cam->forward[1] == 0.0f && cam->forward[2] == 0.0f)
+            return fail(CINR_INVALID_ARG, "zero forward vector");
+    }
+    if (rp->mode != CINR_CACHED && rp->mode != CINR_UNCACHED_DIRECT) return fail(CINR_INVALID_ARG, "mode = %d", rp->mode);
+    if (!(rp->step > 0.0f) || !isfinite(rp->step)) return fail(CINR_INVALID_ARG, "step must be > 0");
+    if (!(rp->lod_scale >= 0.0f)) return fail(CINR_INVALID_ARG, "lod_scale must be >= 0");
+    if (rp->samples_per_iter < 1) return fail(CINR_INVALID_ARG, "samples_per_iter must be >= 1");
+    const bool cached = rp->mode == CINR_CACHED;
+    if (cached && !c) return fail(CINR_INVALID_ARG, "the cached mode needs a cache");
+    if (cached && c->vol != v) return fail(CINR_INVALID_ARG, "cache belongs to another volume");
+    if (cached && rp->frame_index < 0) return fail(CINR_INVALID_ARG, "frame_index must be >= 0");
+    cinr_status st = check_shape(v, rp->mlp_dtype);
+    if (st) return st;
+    const int64_t npix = (int64_t)cam->width * cam->height;
+    const int32_t S = rp->samples_per_iter;
+    if (npix * S > 0xFFFFFFFFll) return fail(CINR_INVALID_ARG, "width*height*samples_per_iter >= 2^32");
+    const size_t need = render_layout(npix, S, v->n_cells, nullptr, nullptr);
+    if (!d_ws || ws_bytes < need) return fail(CINR_OUT_OF_MEMORY, "render workspace of %zu bytes < %zu needed", ws_bytes, need);
+    // bound on the wavefront iterations: every iteration advances a live ray by >= S samples
+    double diag = 0.0;
+    for (int a = 0; a < 3; ++a) diag += (double)(v->desc.dims[a] - 1) * (double)(v->desc.dims[a] - 1);
+    const double max_samples = ceil(sqrt(diag) / (double)rp->step) + 2.0;
+    const int64_t max_iters = (int64_t)ceil(max_samples / S) + 2;
+    if (max_iters > kMaxIters) return fail(CINR_INVALID_ARG, "step too small for samples_per_iter (needs %lld iterations)", (long long)max_iters);
+    hipStream_t s = (hipStream_t)stream;
+    if (!v->pinned) {
+        HIP_TRY(hipHostMalloc((void**)&v->pinned, 64, hipHostMallocDefault));
+        HIP_TRY(hipEventCreateWithFlags(&v->ev, hipEventDisableTiming));
+    }
+    RenderLayout L;
+    render_layout(npix, S, v->n_cells, &L, d_ws);
+
+    FrameDev f{};
+    f.cam.proj = cam->projection;
+    f.cam.W = cam->width;
+    f.cam.H = cam->height;
+    for (int a = 0; a < 3; ++a) {
+        f.cam.eye[a] = cam->eye[a];
+        f.cam.fwd[a] = cam->forward[a];
+        f.cam.right[a] = cam->right[a];
+        f.cam.up[a] = cam->up[a];
+        f.dims[a] = v->desc.dims[a];
+        f.vm1[a] = (float)(v->desc.dims[a] - 1);
+        f.M[a] = v->M[a];
+    }
+    f.cam.tanx = cam->tan_half_x;
+    f.cam.tany = cam->tan_half_y;
+    f.cam.ow = cam->ortho_w;
+    f.cam.oh = cam->ortho_h;
+    f.step = rp->step;
+    f.lod_scale = rp->lod_scale;
+    f.ert = rp->ert_threshold;
+    f.ert_on = rp->ert_threshold <= 1.0f;
+    f.frame = rp->frame_index;
+    f.S = S;
+    f.mode = rp->mode;
+    f.mc_N = v->desc.macrocell_size;
+    f.flags = v->n_cells > 0 ? L.flags : nullptr;
+    f.tf = d_tf;
+    f.rgba = reinterpret_cast<float4*>(d_rgba);
+    f.k_next = L.k_next;
+    f.live0 = L.live0;
+    f.live1 = L.live1;
+    f.pend_pix = L.pend_pix;
+    f.pend_n = L.pend_n;
+    f.vals = L.vals;
+    f.miss_rec = L.miss_rec;
+    f.ctr = L.ctr;
+    f.stats = d_stats ? reinterpret_cast<unsigned long long*>(d_stats) : L.stats;
+    CacheCtr* cctr = nullptr;
+    if (cached) {
+        const cinr_cache_desc& cd = c->desc;
+        // per-frame seed of the stochastic LoD: high half of SplitMix64 of (seed << 32 | frame)
+        uint64_t z = (((uint64_t)rp->seed << 32) | (uint64_t)(uint32_t)rp->frame_index) + 0x9e3779b97f4a7c15ull;
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+        z = z ^ (z >> 31);
+        f.frame_seed = (uint32_t)(z >> 32);
+        int32_t floor_ = 0;
+        if (cd.preload_period > 0) {
+            floor_ = cd.n_lods - 1 - rp->frame_index / cd.preload_period;
+            if (floor_ < 0) floor_ = 0;
+        }
+        f.lod_floor = floor_;
+        f.geo = c->g;
+        f.pt = c->c.pt;
+        f.last_used = c->c.last_used;
+        f.req = c->c.req;
+        f.touched = c->c.touched;
+        f.n_touched = &c->c.ctr->n_touched;
+        f.pool = c->c.pool;
+        f.misslog = c->c.misslog;
+        f.n_misslog = &c->c.ctr->n_misslog;
+        f.misslog_cap = c->c.misslog_cap;
+        cctr = c->c.ctr;
+    } else {
+        f.geo.n_lods = 1;
+        f.geo.brick = 2;
+    }
+    const int32_t n_ctr = (int32_t)std::min<int64_t>(max_iters + 2, kMaxIters + 2);
+    Timing& tm = v->timing;
+    {
+        StageTimer st_(tm, s, CINR_STAGE_SETUP);
+        HIP_TRY(launch_frame_begin(f, n_ctr, f.flags, v->desc.d_macrocells, v->n_cells, cctr, s));
+        if (cached && c->c.last_req) HIP_TRY(launch_clear_last_req(c->c, c->g.n_keys, s));
+        HIP_TRY(launch_raygen(f, s));
+    }
+    int n_iters = 0;
+    for (int it = 0; it < max_iters; ++it) {
+        {
+            StageTimer st_(tm, s, CINR_STAGE_MARCH);
+            HIP_TRY(launch_march(f, it, npix, s));
+        }
+        {
+            StageTimer st_(tm, s, CINR_STAGE_INFER);
+            HIP_TRY(inr_infer_misses(v->m, f.miss_rec, &f.ctr[it].misses, npix * S, f.vals, rp->mlp_dtype, s));
+        }
+        {
+            StageTimer st_(tm, s, CINR_STAGE_SHADE);
+            HIP_TRY(launch_shade(f, it, npix, s));
+        }
+        n_iters = it + 1;
+        HIP_TRY(hipMemcpyAsync(v->pinned, &f.ctr[it + 1].live, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipEventRecord(v->ev, s));
+        HIP_TRY(hipEventSynchronize(v->ev));
+        if (*(volatile int32_t*)v->pinned == 0) break;
+    }
+    if (cached) {
+        const CacheDev& cd = c->c;
+        StageTimer st_(tm, s, CINR_STAGE_CM);
+        HIP_TRY(launch_cm_rank(cd, rp->frame_index, c->g.n_keys, s));
+        HIP_TRY(launch_topk(cd.cand, &cd.ctr->n_touched, c->plan_sel, c->lim, cd.topk[0], cd.topk[1], cd.sel, nullptr,
+                            nullptr, s));
+        HIP_TRY(launch_cm_select(cd, s));
+        if (cd.pool_bricks > 0)
+            HIP_TRY(launch_topk(nullptr, &cd.ctr->n_used, c->plan_vic, c->lim, cd.topk[0], cd.topk[1], cd.vic,
+                                &cd.ctr->need_evict, cd.last_used, s));
+        HIP_TRY(launch_insert(cd, c->g, rp->frame_index + 1, c->lim, s));
+    }
+    if (cached) {
+        const CacheDev& cd = c->c;
+        StageTimer st_(tm, s, CINR_STAGE_DECODE);
+        HIP_TRY(inr_decode_bricks(v->m, c->g, cd.ins_reqs, &cd.ctr->n_sel, c->lim, cd.ins_slots, cd.pool,
+                                  rp->mlp_dtype, s));
+    }
+    HIP_TRY(launch_frame_end(f, n_iters, cctr, s));
+    if (cached) HIP_TRY(launch_touched_reset(c->c, s));
+    return CINR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Dumps
+// ---------------------------------------------------------------------------
+
+extern "C" cinr_status cinr_cache_dump(cinr_cache c, int32_t kind, void* dst, size_t bytes, size_t* needed, void* stream) {
+    if (!c || !needed) return fail(CINR_INVALID_ARG, "null argument");
+    hipStream_t s = (hipStream_t)stream;
+    const CacheDev& cd = c->c;
+    CacheCtr h{};
+    HIP_TRY(hipMemcpyAsync(&h, cd.ctr, sizeof h, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const void* src = nullptr;
+    size_t n = 0;
+    const size_t nk = (size_t)c->g.n_keys, P = (size_t)cd.pool_bricks;
+    const size_t B3 = (size_t)c->g.brick * c->g.brick * c->g.brick;
+    switch (kind) {
+        case CINR_DUMP_PAGE_TABLE: src = cd.pt; n = nk * 4; break;
+        case CINR_DUMP_SLOT_OWNER: src = cd.owner; n = P * 4; break;
+        case CINR_DUMP_LAST_USED: src = cd.last_used; n = P * 4; break;
+        case CINR_DUMP_RANK: src = cd.rank; n = nk * 8; break;
+        case CINR_DUMP_REQ_COUNT:
+            if (!cd.last_req) return fail(CINR_BAD_STATE, "request counts are not kept (keep_request_counts = 0)");
+            src = cd.last_req;
+            n = nk * 4;
+            break;
+        case CINR_DUMP_REQUEST_LIST: src = cd.ins_keys; n = (size_t)h.n_sel * 4; break;
+        case CINR_DUMP_MISS_LIST:
+            if ((int64_t)h.n_misslog > cd.misslog_cap) return fail(CINR_BAD_STATE, "miss log overflow: %u records, capacity %d", h.n_misslog, cd.misslog_cap);
+            src = cd.misslog;
+            n = (size_t)h.n_misslog * sizeof(MissLogRec);
+            break;
+        case CINR_DUMP_EVICTION_LOG: {
+            const size_t m = std::min<size_t>(h.n_evlog, (size_t)cd.evlog_cap);
+            src = cd.evlog;
+            n = m * 16;
+            break;
+        }
+        case CINR_DUMP_POOL: src = cd.pool; n = P * B3 * 4; break;
+        default: return fail(CINR_INVALID_ARG, "dump kind %d", kind);
+    }
+    *needed = n;
+    if (!dst || bytes < n) return fail(CINR_OUT_OF_MEMORY, "dump needs %zu bytes", n);
+    if (n == 0) return CINR_OK;
+    HIP_TRY(hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (kind == CINR_DUMP_MISS_LIST) {
+        MissLogRec* r = (MissLogRec*)dst;
+        std::sort(r, r + h.n_misslog, [](const MissLogRec& a, const MissLogRec& b) {
+            return a.pix != b.pix ? a.pix < b.pix : a.k < b.k;
+        });
+    }
+    return CINR_OK;
+}

@@ -1,0 +1,82 @@
+// Internal definitions shared by the HIP sources of libcinr (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cinr.h"
+
+namespace cinr {
+
+constexpr int kMaxLevels = CINR_MAX_LEVELS;
+constexpr int kMaxLods = CINR_MAX_LODS;
+constexpr int kBlock = 256;  // threads per workgroup (4 wave64s)
+
+constexpr uint32_t kPrime1 = 2654435761u;
+constexpr uint32_t kPrime2 = 805459861u;
+
+// One hash-grid level as seen by the kernels.
+struct LevelDev {
+    double res;       // N_l
+    uint32_t side;    // N_l + 1
+    uint32_t side2;   // (N_l + 1)^2
+    uint32_t offset;  // first table entry of the level
+    uint32_t mask;    // T - 1 for a hashed level, 0 for a dense one
+};
+
+// Hash-grid INR as seen by the kernels (passed by value).
+struct InrDev {
+    int32_t dims[3];
+    float vm1[3];          // V - 1
+    double inv_dims[3];    // 1 / V
+    int32_t n_levels, n_features;
+    LevelDev lv[kMaxLevels];
+    float value_scale, value_offset;
+    const float* table;
+    const float* weights;
+    int32_t in, hidden;            // widths[0], hidden width
+};
+
+// LoD lattice / brick geometry (Section 4.3.2).
+struct LodGeom {
+    int32_t K[3];    // lattice points per axis
+    int32_t nb[3];   // bricks per axis
+    int64_t off;     // first key of the LoD
+};
+
+struct CacheGeom {
+    int32_t brick;
+    int32_t n_lods;
+    LodGeom lod[kMaxLods];
+    int64_t n_keys;
+};
+
+// ---------------------------------------------------------------------------
+// Wave-level helpers
+// ---------------------------------------------------------------------------
+
+__device__ inline int lane_id() { return __lane_id(); }
+
+// Wave-aggregated append: returns the index of this lane's element in the
+// destination list, or -1 when `pred` is false.  One atomic per wave.
+__device__ inline int64_t wave_append(bool pred, uint32_t* counter) {
+    const uint64_t mask = __ballot(pred);
+    if (!pred) return -1;
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    const uint32_t rank = __popcll(mask & ((1ull << lane_id()) - 1ull));
+    uint32_t base = 0;
+    if (lane_id() == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
+    base = __shfl(base, leader);
+    return (int64_t)base + rank;
+}
+
+// Wave-aggregated 64-bit counter increment.
+__device__ inline void wave_add_u64(unsigned long long* dst, uint64_t v) {
+    // reduce across the wave with shuffles
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane_id() == 0 && v) atomicAdd(dst, (unsigned long long)v);
+}
+
+inline hipError_t launch_check() { return hipGetLastError(); }
+
+}  // namespace cinr

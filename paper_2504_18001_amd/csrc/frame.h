@@ -1,0 +1,156 @@
+// Device-side state of one frame and of the brick cache, and the host-side
+// launch functions of the render and cache kernels.
+#pragma once
+
+#include "common.h"
+#include "decision.h"
+
+namespace cinr {
+
+constexpr int kMaxIters = 8192;
+
+enum : int32_t { S_HIT = 0, S_FALLBACK = 1, S_MISS = 2, S_SKIP = 3 };
+
+enum StatIdx : int { ST_RAYS = 0, ST_SAMPLES, ST_HITS, ST_FALLBACKS, ST_MISSES, ST_SKIPPED, ST_REQUESTED, ST_SELECTED,
+                     ST_EVICTED, ST_ITERS, ST_COUNT };
+
+// Per wavefront iteration: rays live at its start, rays with a deferred
+// wavefront step, true-miss records.
+struct IterCtr {
+    uint32_t live, pending, misses, pad;
+};
+
+// Cache-manager counters (device).
+struct CacheCtr {
+    uint32_t n_touched;   // bricks requested in the current frame
+    uint32_t n_sel;       // bricks selected / to insert
+    uint32_t n_free;      // free slots before the insertion
+    uint32_t need_evict;  // slots to take from the LRU order
+    uint32_t n_used;      // slots in use (free slots are [n_used, pool))
+    uint32_t n_misslog;
+    uint32_t n_evlog;
+    uint32_t error;
+};
+
+struct MissLogRec {
+    int32_t pix, k;
+    float x, y, z;
+};
+
+struct CacheDev {
+    int32_t* pt;
+    int64_t* rank;
+    uint32_t* req;
+    uint32_t* last_req;   // nullable
+    int32_t* touched;
+    uint64_t* cand;
+    int32_t* owner;
+    int32_t* last_used;
+    float* pool;
+    int32_t* ins_keys;    // [ins_cap]
+    int32_t* ins_slots;   // [ins_cap]
+    int32_t* ins_reqs;    // [ins_cap][4]
+    uint64_t* topk[2];    // ping-pong buffers of the selection passes
+    uint64_t* sel;        // final selection (sorted scores)
+    uint64_t* vic;        // final victim list (sorted scores)
+    MissLogRec* misslog;
+    int32_t misslog_cap;
+    int32_t* evlog;
+    int32_t evlog_cap;
+    CacheCtr* ctr;
+    int32_t pool_bricks, max_requests, rank_window, ranking, ins_cap;
+};
+
+struct FrameDev {
+    CamDev cam;
+    int32_t dims[3];
+    float vm1[3];
+    float step, lod_scale, ert;
+    int32_t ert_on;
+    uint32_t frame_seed;
+    int32_t frame;
+    int32_t lod_floor;
+    int32_t S;
+    int32_t mode;
+    int32_t mc_N;
+    int32_t M[3];
+    const uint8_t* flags;  // nullable
+    CacheGeom geo;
+    // cache (null in the uncached mode)
+    const int32_t* pt;
+    int32_t* last_used;
+    uint32_t* req;
+    int32_t* touched;
+    uint32_t* n_touched;
+    const float* pool;
+    MissLogRec* misslog;
+    uint32_t* n_misslog;
+    int32_t misslog_cap;
+    // shading and ray state
+    const float* tf;
+    float4* rgba;
+    int32_t* k_next;
+    int32_t* live0;
+    int32_t* live1;
+    int32_t* pend_pix;
+    int32_t* pend_n;
+    float* vals;
+    float4* miss_rec;
+    IterCtr* ctr;
+    unsigned long long* stats;
+};
+
+// Plan of the tournament top-k selection (blocks per pass).
+constexpr int kTopkChunk = 2048;
+constexpr int kMaxTopkPasses = 16;
+constexpr int kMaxRequests = 256;  // each pass keeps k of 2048: at least 8:1 reduction
+struct TopkPlan {
+    int n_pass;
+    int blocks[kMaxTopkPasses];
+    uint32_t count[kMaxTopkPasses];  // input elements per pass (capacity)
+};
+
+inline TopkPlan make_topk_plan(int64_t cap, int k) {
+    TopkPlan p{};
+    int64_t c = cap;
+    for (;;) {
+        const int64_t b = (c + kTopkChunk - 1) / kTopkChunk;
+        p.count[p.n_pass] = (uint32_t)c;
+        p.blocks[p.n_pass] = (int)(b < 1 ? 1 : b);
+        ++p.n_pass;
+        if (b <= 1 || p.n_pass == kMaxTopkPasses) break;
+        c = b * k;
+    }
+    return p;
+}
+
+// render.cpp launchers
+hipError_t launch_frame_begin(const FrameDev& f, int32_t n_iter_ctr, const uint8_t* flags_out, const float* minmax,
+                              int64_t n_cells, CacheCtr* cctr, hipStream_t s);
+hipError_t launch_raygen(const FrameDev& f, hipStream_t s);
+hipError_t launch_march(const FrameDev& f, int it, int64_t cap_rays, hipStream_t s);
+hipError_t launch_shade(const FrameDev& f, int it, int64_t cap_rays, hipStream_t s);
+hipError_t launch_frame_end(const FrameDev& f, int n_iters, const CacheCtr* cctr, hipStream_t s);
+
+// cache launchers
+hipError_t launch_cache_init(const CacheDev& c, int64_t n_keys, hipStream_t s);
+hipError_t launch_cm_rank(const CacheDev& c, int32_t frame, int64_t cap, hipStream_t s);
+hipError_t launch_topk(const uint64_t* in, const uint32_t* count_dev, const TopkPlan& plan, int k, uint64_t* buf0,
+                       uint64_t* buf1, uint64_t* final_out, const uint32_t* gate, const int32_t* lru_last_used,
+                       hipStream_t s);
+hipError_t launch_cm_select(const CacheDev& c, hipStream_t s);
+hipError_t launch_prefill_setup(const CacheDev& c, const int32_t* keys, int32_t n, hipStream_t s);
+hipError_t launch_insert(const CacheDev& c, const CacheGeom& g, int32_t stamp, int32_t cap, hipStream_t s);
+hipError_t launch_clear_last_req(const CacheDev& c, int64_t n_keys, hipStream_t s);
+hipError_t launch_touched_reset(const CacheDev& c, hipStream_t s);
+
+// inr.hip launchers
+bool inr_shape_supported(const InrDev& m);
+hipError_t inr_infer_points(const InrDev& m, const float* pos, int64_t n, float* out, int prec, hipStream_t s);
+hipError_t inr_decode_bricks(const InrDev& m, const CacheGeom& g, const int32_t* reqs, const uint32_t* n_dev,
+                             int32_t n_cap, const int32_t* slots, float* out, int prec, hipStream_t s);
+hipError_t inr_macrocells(const InrDev& m, int32_t N, float* minmax, int prec, hipStream_t s);
+hipError_t inr_infer_misses(const InrDev& m, const float4* rec, const uint32_t* n_dev, int64_t cap, float* vals,
+                            int prec, hipStream_t s);
+
+}  // namespace cinr

@@ -1,0 +1,325 @@
+// Hash-grid INR evaluation on gfx950: encoding on the vector ALUs, the MLP on
+// MFMA (Section 3, Figure 2).  Used by brick decoding (Section 4.3.2), true-
+// miss inference (Section 4.3.4, Algorithm 1) and the uncached renderer.
+//
+// Layout of one round (a workgroup of 256 lanes = 4 wave64s, 256 points):
+//  - each lane encodes one point over all levels (level constants are
+//    wave-uniform, so dense/hashed branches never diverge) and writes its
+//    feature row to LDS;
+//  - each wave then runs its 64 points through the MLP as four 16-point MFMA
+//    tiles.  Layers are computed transposed (H^T = W X^T): weights are the
+//    A operand (rows = neurons), points the B operand (columns), so a layer's
+//    accumulator (lane l: neurons 4*(l/16)+r of point l%16) is directly the
+//    next layer's B operand once the K order of the next weight matrix is
+//    permuted to match.  Hidden activations never leave registers.
+//  - the last layer (width 1) is a per-lane dot product in FP32 reduced across
+//    the four 16-lane groups; lane l ends with the output of point l.
+#include "common.h"
+#include "inr_engine.h"
+
+namespace cinr {
+
+// ---------------------------------------------------------------------------
+// Point sources and sinks
+// ---------------------------------------------------------------------------
+
+// Arbitrary positions (voxel coordinates, f32 xyz).
+struct PosSrc {
+    const float* pos;
+    int64_t n;
+    __device__ int64_t count() const { return n; }
+    __device__ void position(int64_t i, double x[3]) const {
+        x[0] = pos[3 * i];
+        x[1] = pos[3 * i + 1];
+        x[2] = pos[3 * i + 2];
+    }
+};
+
+struct LinearDst {
+    float* out;
+    __device__ void store(int64_t i, float v) const { out[i] = v; }
+};
+
+// Brick lattice points: request r = (lod, bx, by, bz), sample i in (z, y, x)
+// order; voxel coordinate clamp((b*(B-1) + i) * 2^lod, 0, V-1).
+struct BrickSrc {
+    const int32_t* reqs;      // [n][4]
+    const uint32_t* n_dev;    // device count of requests (nullable)
+    int32_t n_host;
+    int32_t B;
+    int32_t B3;
+    int32_t n_lods;
+    int32_t nb[kMaxLods][3];
+    int32_t dims[3];
+    __device__ int64_t count() const {
+        const int64_t n = n_dev ? (int64_t)*n_dev : (int64_t)n_host;
+        return n * B3;
+    }
+    // returns false for an invalid request
+    __device__ bool position(int64_t idx, double x[3]) const {
+        const int32_t r = (int32_t)(idx / B3);
+        const int32_t i = (int32_t)(idx - (int64_t)r * B3);
+        const int32_t* q = reqs + 4 * r;
+        const int32_t L = q[0];
+        const int32_t ix = i % B, iy = (i / B) % B, iz = i / (B * B);
+        const int32_t li[3] = {ix, iy, iz};
+        bool ok = L >= 0 && L < n_lods;
+        const int32_t Ls = ok ? L : 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int32_t b = q[1 + a];
+            const bool ba = b >= 0 && b < nb[Ls][a];
+            ok = ok && ba;
+            int64_t xa = ((int64_t)(ba ? b : 0) * (B - 1) + li[a]) << Ls;
+            if (xa > dims[a] - 1) xa = dims[a] - 1;
+            x[a] = (double)xa;
+        }
+        return ok;
+    }
+};
+
+struct BrickDst {
+    float* out;
+    const int32_t* slots;  // nullable: brick r goes to slot slots[r] (skipped if negative), else to r
+    int32_t B3;
+    __device__ void store(int64_t idx, float v) const {
+        const int32_t r = (int32_t)(idx / B3);
+        const int32_t i = (int32_t)(idx - (int64_t)r * B3);
+        const int64_t s = slots ? (int64_t)slots[r] : (int64_t)r;
+        if (s >= 0) out[s * B3 + i] = v;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+
+template <class Cfg, class Src, class Dst>
+__global__ __launch_bounds__(kBlock) void k_inr_points(const InrDev m, const Src src, const Dst dst) {
+    InrEngine<Cfg> eng;
+    eng.load_weights(m);
+    __shared__ typename InrEngine<Cfg>::Lds lds;
+    const int64_t n = src.count();
+    for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n; base += (int64_t)gridDim.x * kBlock) {
+        const int64_t idx = base + threadIdx.x;
+        const bool valid = idx < n;
+        double x[3];
+        src.position(valid ? idx : base, x);
+        const float v = eng.eval(m, x, lds);
+        if (valid) dst.store(idx, v);
+    }
+}
+
+// Brick decoding: like k_inr_points, invalid requests produce NaN bricks.
+template <class Cfg>
+__global__ __launch_bounds__(kBlock) void k_decode(const InrDev m, const BrickSrc src, const BrickDst dst) {
+    InrEngine<Cfg> eng;
+    eng.load_weights(m);
+    __shared__ typename InrEngine<Cfg>::Lds lds;
+    const int64_t n = src.count();
+    for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n; base += (int64_t)gridDim.x * kBlock) {
+        const int64_t idx = base + threadIdx.x;
+        const bool valid = idx < n;
+        double x[3];
+        const bool ok = src.position(valid ? idx : base, x);
+        const float v = eng.eval(m, x, lds);
+        if (valid) dst.store(idx, ok ? v : __builtin_nanf(""));
+    }
+}
+
+// Macro-cells (Section 5.2): one workgroup per cell, min/max of the lattice
+// values in the cell's closed region.
+template <class Cfg>
+__global__ __launch_bounds__(kBlock) void k_macrocells(const InrDev m, int32_t N, int32_t Mx, int32_t My,
+                                                       int32_t Mz, float* minmax) {
+    InrEngine<Cfg> eng;
+    eng.load_weights(m);
+    __shared__ typename InrEngine<Cfg>::Lds lds;
+    __shared__ float red[2][kBlock / 64];
+    const int64_t ncell = (int64_t)Mx * My * Mz;
+    for (int64_t c = blockIdx.x; c < ncell; c += gridDim.x) {
+        const int32_t cx = (int32_t)(c % Mx), cy = (int32_t)((c / Mx) % My), cz = (int32_t)(c / ((int64_t)Mx * My));
+        const int32_t lo[3] = {cx * N, cy * N, cz * N};
+        int32_t ext[3];
+        const int32_t ci[3] = {cx, cy, cz};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            int32_t hi = (ci[a] + 1) * N;
+            if (hi > m.dims[a] - 1) hi = m.dims[a] - 1;
+            ext[a] = hi - lo[a] + 1;
+        }
+        const int32_t npts = ext[0] * ext[1] * ext[2];
+        float vmin = __builtin_inff(), vmax = -__builtin_inff();
+        for (int32_t base = 0; base < npts; base += kBlock) {
+            const int32_t i = base + threadIdx.x;
+            const bool valid = i < npts;
+            const int32_t j = valid ? i : base;
+            double x[3] = {(double)(lo[0] + j % ext[0]), (double)(lo[1] + (j / ext[0]) % ext[1]),
+                           (double)(lo[2] + j / (ext[0] * ext[1]))};
+            const float v = eng.eval(m, x, lds);
+            if (valid) {
+                vmin = fminf(vmin, v);
+                vmax = fmaxf(vmax, v);
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            vmin = fminf(vmin, __shfl_xor(vmin, o));
+            vmax = fmaxf(vmax, __shfl_xor(vmax, o));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            red[0][threadIdx.x >> 6] = vmin;
+            red[1][threadIdx.x >> 6] = vmax;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float a = red[0][0], b = red[1][0];
+            for (int w = 1; w < kBlock / 64; ++w) {
+                a = fminf(a, red[0][w]);
+                b = fmaxf(b, red[1][w]);
+            }
+            minmax[2 * c] = a;
+            minmax[2 * c + 1] = b;
+        }
+        __syncthreads();
+    }
+}
+
+// True misses of the cached renderer: records (x, y, z, destination index).
+struct MissSrc {
+    const float4* rec;
+    const uint32_t* n_dev;
+    __device__ int64_t count() const { return (int64_t)*n_dev; }
+    __device__ void position(int64_t i, double x[3]) const {
+        const float4 r = rec[i];
+        x[0] = r.x;
+        x[1] = r.y;
+        x[2] = r.z;
+    }
+};
+
+struct MissDst {
+    const float4* rec;
+    float* vals;
+    __device__ void store(int64_t i, float v) const { vals[__float_as_uint(rec[i].w)] = v; }
+};
+
+// ---------------------------------------------------------------------------
+// Dispatch
+// ---------------------------------------------------------------------------
+
+static int grid_for(int64_t points, int max_blocks) {
+    int64_t b = (points + kBlock - 1) / kBlock;
+    if (b < 1) b = 1;
+    if (b > max_blocks) b = max_blocks;
+    return (int)b;
+}
+
+constexpr int kMaxInrBlocks = 256 * 8;  // 8 workgroups per CU on 256 CUs
+
+template <class Cfg>
+static hipError_t launch_all(int what, const InrDev& m, const void* a, hipStream_t s) {
+    switch (what) {
+        case 0: {
+            const PosSrc* src = (const PosSrc*)((const void* const*)a)[0];
+            const LinearDst* dst = (const LinearDst*)((const void* const*)a)[1];
+            hipLaunchKernelGGL((k_inr_points<Cfg, PosSrc, LinearDst>), dim3(grid_for(src->n, kMaxInrBlocks)),
+                               dim3(kBlock), 0, s, m, *src, *dst);
+            break;
+        }
+        case 1: {
+            const BrickSrc* src = (const BrickSrc*)((const void* const*)a)[0];
+            const BrickDst* dst = (const BrickDst*)((const void* const*)a)[1];
+            const int64_t cap = (int64_t)src->n_host * src->B3;
+            hipLaunchKernelGGL((k_decode<Cfg>), dim3(grid_for(cap, kMaxInrBlocks)), dim3(kBlock), 0, s, m, *src,
+                               *dst);
+            break;
+        }
+        case 2: {
+            const int32_t* p = (const int32_t*)((const void* const*)a)[0];
+            float* mm = (float*)((const void* const*)a)[1];
+            const int64_t nc = (int64_t)p[1] * p[2] * p[3];
+            hipLaunchKernelGGL((k_macrocells<Cfg>), dim3((int)(nc < kMaxInrBlocks * 4 ? nc : kMaxInrBlocks * 4)),
+                               dim3(kBlock), 0, s, m, p[0], p[1], p[2], p[3], mm);
+            break;
+        }
+        case 3: {
+            const MissSrc* src = (const MissSrc*)((const void* const*)a)[0];
+            const MissDst* dst = (const MissDst*)((const void* const*)a)[1];
+            const int64_t cap = *(const int64_t*)((const void* const*)a)[2];
+            hipLaunchKernelGGL((k_inr_points<Cfg, MissSrc, MissDst>), dim3(grid_for(cap, kMaxInrBlocks)),
+                               dim3(kBlock), 0, s, m, *src, *dst);
+            break;
+        }
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int NL, int F, int H>
+static hipError_t dispatch_prec(int prec, int what, const InrDev& m, const void* a, hipStream_t s) {
+    switch (prec) {
+        case CINR_F32: return launch_all<EngCfg<NL, F, H, CINR_F32>>(what, m, a, s);
+        case CINR_BF16: return launch_all<EngCfg<NL, F, H, CINR_BF16>>(what, m, a, s);
+        case CINR_F16: return launch_all<EngCfg<NL, F, H, CINR_F16>>(what, m, a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+bool inr_shape_supported(const InrDev& m) {
+    const int NL = m.n_levels, F = m.n_features, H = m.hidden;
+    return (NL == 8 && F == 2 && H == 32) || (NL == 16 && F == 2 && H == 64) || (NL == 16 && F == 4 && H == 64) ||
+           (NL == 8 && F == 2 && H == 64) || (NL == 16 && F == 2 && H == 32);
+}
+
+static hipError_t dispatch(int prec, int what, const InrDev& m, const void* a, hipStream_t s) {
+    const int NL = m.n_levels, F = m.n_features, H = m.hidden;
+    if (NL == 8 && F == 2 && H == 32) return dispatch_prec<8, 2, 32>(prec, what, m, a, s);
+    if (NL == 8 && F == 2 && H == 64) return dispatch_prec<8, 2, 64>(prec, what, m, a, s);
+    if (NL == 16 && F == 2 && H == 32) return dispatch_prec<16, 2, 32>(prec, what, m, a, s);
+    if (NL == 16 && F == 2 && H == 64) return dispatch_prec<16, 2, 64>(prec, what, m, a, s);
+    if (NL == 16 && F == 4 && H == 64) return dispatch_prec<16, 4, 64>(prec, what, m, a, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t inr_infer_points(const InrDev& m, const float* pos, int64_t n, float* out, int prec, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    PosSrc src{pos, n};
+    LinearDst dst{out};
+    const void* a[2] = {&src, &dst};
+    return dispatch(prec, 0, m, a, s);
+}
+
+hipError_t inr_decode_bricks(const InrDev& m, const CacheGeom& g, const int32_t* reqs, const uint32_t* n_dev,
+                             int32_t n_cap, const int32_t* slots, float* out, int prec, hipStream_t s) {
+    if (n_cap <= 0) return hipSuccess;
+    BrickSrc src;
+    src.reqs = reqs;
+    src.n_dev = n_dev;
+    src.n_host = n_cap;
+    src.B = g.brick;
+    src.B3 = g.brick * g.brick * g.brick;
+    src.n_lods = g.n_lods;
+    for (int L = 0; L < kMaxLods; ++L)
+        for (int a = 0; a < 3; ++a) src.nb[L][a] = L < g.n_lods ? g.lod[L].nb[a] : 0;
+    for (int a = 0; a < 3; ++a) src.dims[a] = m.dims[a];
+    BrickDst dst{out, slots, src.B3};
+    const void* a[2] = {&src, &dst};
+    return dispatch(prec, 1, m, a, s);
+}
+
+hipError_t inr_macrocells(const InrDev& m, int32_t N, float* minmax, int prec, hipStream_t s) {
+    int32_t p[4] = {N, (m.dims[0] + N - 1) / N, (m.dims[1] + N - 1) / N, (m.dims[2] + N - 1) / N};
+    const void* a[2] = {p, minmax};
+    return dispatch(prec, 2, m, a, s);
+}
+
+hipError_t inr_infer_misses(const InrDev& m, const float4* rec, const uint32_t* n_dev, int64_t cap, float* vals,
+                            int prec, hipStream_t s) {
+    MissSrc src{rec, n_dev};
+    MissDst dst{rec, vals};
+    const void* a[3] = {&src, &dst, &cap};
+    return dispatch(prec, 3, m, a, s);
+}
+
+}  // namespace cinr

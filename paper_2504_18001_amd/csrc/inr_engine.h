@@ -1,0 +1,343 @@
+// INR engine: hash-grid encoding + MLP for one 256-point round of a
+// workgroup.  See inr.hip for the data layout.
+#pragma once
+
+#include "common.h"
+
+namespace cinr {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+template <int NL_, int F_, int H_, int PREC_>
+struct EngCfg {
+    static constexpr int NL = NL_, F = F_, H = H_, PREC = PREC_;
+    static constexpr int IN = NL * F;
+    static constexpr int MT = H / 16;  // 16-neuron tiles per hidden layer
+};
+
+template <int PREC>
+struct Half;
+template <>
+struct Half<CINR_BF16> {
+    typedef __bf16 T;
+    typedef bf16x8 V8;
+};
+template <>
+struct Half<CINR_F16> {
+    typedef _Float16 T;
+    typedef f16x8 V8;
+};
+
+__device__ inline f32x4 mfma_k32(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ inline f32x4 mfma_k32(f16x8 a, f16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+__device__ inline f32x4 mfma_k4(float a, float b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <int F>
+struct Entry;
+template <>
+struct Entry<1> {
+    __device__ static inline void load(const float* p, float* e) { e[0] = p[0]; }
+};
+template <>
+struct Entry<2> {
+    __device__ static inline void load(const float* p, float* e) {
+        const float2 v = *reinterpret_cast<const float2*>(p);
+        e[0] = v.x;
+        e[1] = v.y;
+    }
+};
+template <>
+struct Entry<4> {
+    __device__ static inline void load(const float* p, float* e) {
+        const float4 v = *reinterpret_cast<const float4*>(p);
+        e[0] = v.x;
+        e[1] = v.y;
+        e[2] = v.z;
+        e[3] = v.w;
+    }
+};
+
+// Normalised coordinate u = (clamp(x, 0, V-1) + 0.5) / V in FP64, so that the
+// fine levels' cell fractions keep full FP32 precision.
+__device__ inline void to_unit(const InrDev& m, const double x[3], double u[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double xa = x[a];
+        xa = xa < 0.0 ? 0.0 : xa;
+        xa = xa > (double)m.vm1[a] ? (double)m.vm1[a] : xa;
+        u[a] = (xa + 0.5) * m.inv_dims[a];
+    }
+}
+
+// Multi-resolution hash encoding (Section 3) of one level: trilinear
+// interpolation of the 8 grid corners around u*N_l.  The level index is
+// wave-uniform, so the dense/hashed branch never diverges.
+template <int F>
+__device__ inline void encode_level(const LevelDev& lv, const float* table, const double u[3], float* out) {
+    const double N = lv.res;
+    const double s0 = u[0] * N, s1 = u[1] * N, s2 = u[2] * N;
+    const double f0 = floor(s0), f1 = floor(s1), f2 = floor(s2);
+    const float w0 = (float)(s0 - f0), w1 = (float)(s1 - f1), w2 = (float)(s2 - f2);
+    const uint32_t c0 = (uint32_t)f0, c1 = (uint32_t)f1, c2 = (uint32_t)f2;
+    uint32_t idx[8];
+    if (lv.mask == 0u) {
+        const uint32_t sd = lv.side, sd2 = lv.side2;
+        const uint32_t b = c0 + c1 * sd + c2 * sd2;
+        idx[0] = b;
+        idx[1] = b + 1u;
+        idx[2] = b + sd;
+        idx[3] = b + sd + 1u;
+        idx[4] = b + sd2;
+        idx[5] = b + sd2 + 1u;
+        idx[6] = b + sd2 + sd;
+        idx[7] = b + sd2 + sd + 1u;
+    } else {
+        const uint32_t mk = lv.mask;
+        const uint32_t x0 = c0, x1 = c0 + 1u;
+        const uint32_t y0 = c1 * kPrime1, y1 = y0 + kPrime1;
+        const uint32_t z0 = c2 * kPrime2, z1 = z0 + kPrime2;
+        const uint32_t a00 = y0 ^ z0, a10 = y1 ^ z0, a01 = y0 ^ z1, a11 = y1 ^ z1;
+        idx[0] = (x0 ^ a00) & mk;
+        idx[1] = (x1 ^ a00) & mk;
+        idx[2] = (x0 ^ a10) & mk;
+        idx[3] = (x1 ^ a10) & mk;
+        idx[4] = (x0 ^ a01) & mk;
+        idx[5] = (x1 ^ a01) & mk;
+        idx[6] = (x0 ^ a11) & mk;
+        idx[7] = (x1 ^ a11) & mk;
+    }
+    const float* tb = table + (size_t)lv.offset * F;
+    float e[8][F];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) Entry<F>::load(tb + (size_t)idx[k] * F, e[k]);
+    const float wx0 = 1.0f - w0, wy0 = 1.0f - w1, wz0 = 1.0f - w2;
+    const float wxy[4] = {wx0 * wy0, w0 * wy0, wx0 * w1, w0 * w1};
+#pragma unroll
+    for (int j = 0; j < F; ++j) out[j] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const float wt = wxy[k & 3] * ((k & 4) ? w2 : wz0);
+#pragma unroll
+        for (int j = 0; j < F; ++j) out[j] = __builtin_fmaf(wt, e[k][j], out[j]);
+    }
+}
+
+__device__ inline float finish_value(const InrDev& m, float y) {
+    float v = __builtin_fmaf(m.value_scale, y, m.value_offset);
+    v = v < 0.0f ? 0.0f : v;
+    v = v > 1.0f ? 1.0f : v;
+    return v;
+}
+
+template <class Cfg, bool IS_F32 = (Cfg::PREC == CINR_F32)>
+struct InrEngine;
+
+// ---------------------------------------------------------------------------
+// FP32 MLP on v_mfma_f32_16x16x4_f32.
+// Layer 1, K step (u, r): lane group g supplies feature 16u + 4g + r.
+// Layer 2, K step (m', r): lane group g supplies neuron 16m' + 4g + r, which
+// is where layer 1's accumulator already holds it.
+// ---------------------------------------------------------------------------
+template <class Cfg>
+struct InrEngine<Cfg, true> {
+    static constexpr int NL = Cfg::NL, F = Cfg::F, IN = Cfg::IN, H = Cfg::H, MT = Cfg::MT;
+    static constexpr int KU = IN / 16;
+    static constexpr int ROW = IN + 4;  // padded row in floats (16-byte aligned)
+    static_assert(IN % 16 == 0, "input width must be a multiple of 16");
+    struct Lds {
+        float f[kBlock * ROW];
+    };
+    float w1[MT][KU][4];
+    float w2[MT][MT][4];
+    float w3[MT][4];
+
+    __device__ void load_weights(const InrDev& m) {
+        const int lane = threadIdx.x & 63, row = lane & 15, g = lane >> 4;
+        const float* W1 = m.weights;
+        const float* W2 = W1 + H * IN;
+        const float* W3 = W2 + H * H;
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+#pragma unroll
+            for (int u = 0; u < KU; ++u)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) w1[t][u][r] = W1[(16 * t + row) * IN + 16 * u + 4 * g + r];
+#pragma unroll
+            for (int p = 0; p < MT; ++p)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) w2[t][p][r] = W2[(16 * t + row) * H + 16 * p + 4 * g + r];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) w3[t][r] = W3[16 * t + 4 * g + r];
+        }
+    }
+
+    // All 256 lanes of the workgroup must call eval together.
+    __device__ float eval(const InrDev& m, const double x[3], Lds& lds) {
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, row = lane & 15, g = lane >> 4;
+        double u[3];
+        to_unit(m, x, u);
+        float* my = lds.f + threadIdx.x * ROW;
+#pragma unroll 2
+        for (int l = 0; l < NL; ++l) {
+            float f[F];
+            encode_level<F>(m.lv[l], m.table, u, f);
+#pragma unroll
+            for (int j = 0; j < F; ++j) my[l * F + j] = f[j];
+        }
+        __syncthreads();
+        float my_y = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const float* pr = lds.f + (wave * 64 + 16 * t + row) * ROW;
+            f32x4 h1[MT];
+#pragma unroll
+            for (int i = 0; i < MT; ++i) h1[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int uu = 0; uu < KU; ++uu) {
+                const float4 b = *reinterpret_cast<const float4*>(pr + 16 * uu + 4 * g);
+                const float bb[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int i = 0; i < MT; ++i) h1[i] = mfma_k4(w1[i][uu][r], bb[r], h1[i]);
+            }
+#pragma unroll
+            for (int i = 0; i < MT; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) h1[i][r] = h1[i][r] > 0.0f ? h1[i][r] : 0.0f;
+            f32x4 h2[MT];
+#pragma unroll
+            for (int i = 0; i < MT; ++i) h2[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int p = 0; p < MT; ++p)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int i = 0; i < MT; ++i) h2[i] = mfma_k4(w2[i][p][r], h1[p][r], h2[i]);
+            float part = 0.0f;
+#pragma unroll
+            for (int i = 0; i < MT; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) part = __builtin_fmaf(w3[i][r], h2[i][r] > 0.0f ? h2[i][r] : 0.0f, part);
+            part += __shfl_xor(part, 16);
+            part += __shfl_xor(part, 32);
+            if (g == t) my_y = part;
+        }
+        __syncthreads();
+        return finish_value(m, my_y);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// BF16 / FP16 MLP on v_mfma_f32_16x16x32_{bf16,f16}, FP32 accumulation; the
+// output layer stays FP32.
+// Layer 1, K chunk c: lane group g supplies features 32c + 8g + j (zero past
+// the input width).  Layer 2, K chunk c: element j of lane group g is neuron
+// 32c + 16(j/4) + 4g + j%4, i.e. accumulator tiles 2c and 2c+1.
+// ---------------------------------------------------------------------------
+template <class Cfg>
+struct InrEngine<Cfg, false> {
+    static constexpr int NL = Cfg::NL, F = Cfg::F, IN = Cfg::IN, H = Cfg::H, MT = Cfg::MT;
+    typedef typename Half<Cfg::PREC>::T T;
+    typedef typename Half<Cfg::PREC>::V8 V8;
+    static constexpr int KC = (IN + 31) / 32;
+    static constexpr int KC2 = H / 32;
+    static constexpr int ROW = KC * 32 + 8;  // padded row in 16-bit elements (16-byte aligned)
+    static_assert(H % 32 == 0, "hidden width must be a multiple of 32");
+    struct Lds {
+        T f[kBlock * ROW];
+    };
+    V8 w1[MT][KC];
+    V8 w2[MT][KC2];
+    float w3[MT][4];
+
+    __device__ void load_weights(const InrDev& m) {
+        const int lane = threadIdx.x & 63, row = lane & 15, g = lane >> 4;
+        const float* W1 = m.weights;
+        const float* W2 = W1 + H * IN;
+        const float* W3 = W2 + H * H;
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+#pragma unroll
+            for (int c = 0; c < KC; ++c)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int k = 32 * c + 8 * g + j;
+                    w1[t][c][j] = (T)(k < IN ? W1[(16 * t + row) * IN + k] : 0.0f);
+                }
+#pragma unroll
+            for (int c = 0; c < KC2; ++c)
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    w2[t][c][j] = (T)W2[(16 * t + row) * H + 32 * c + 16 * (j >> 2) + 4 * g + (j & 3)];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) w3[t][r] = W3[16 * t + 4 * g + r];
+        }
+    }
+
+    __device__ float eval(const InrDev& m, const double x[3], Lds& lds) {
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, row = lane & 15, g = lane >> 4;
+        double u[3];
+        to_unit(m, x, u);
+        T* my = lds.f + threadIdx.x * ROW;
+#pragma unroll 2
+        for (int l = 0; l < NL; ++l) {
+            float f[F];
+            encode_level<F>(m.lv[l], m.table, u, f);
+#pragma unroll
+            for (int j = 0; j < F; ++j) my[l * F + j] = (T)f[j];
+        }
+        // zero padding of the K chunk past the input width
+#pragma unroll
+        for (int k = IN; k < KC * 32; ++k) my[k] = (T)0.0f;
+        __syncthreads();
+        float my_y = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const T* pr = lds.f + (wave * 64 + 16 * t + row) * ROW;
+            f32x4 h1[MT];
+#pragma unroll
+            for (int i = 0; i < MT; ++i) h1[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int c = 0; c < KC; ++c) {
+                const V8 b = *reinterpret_cast<const V8*>(pr + 32 * c + 8 * g);
+#pragma unroll
+                for (int i = 0; i < MT; ++i) h1[i] = mfma_k32(w1[i][c], b, h1[i]);
+            }
+            f32x4 h2[MT];
+#pragma unroll
+            for (int i = 0; i < MT; ++i) h2[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int c = 0; c < KC2; ++c) {
+                V8 b;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const float h = h1[2 * c + (j >> 2)][j & 3];
+                    b[j] = (T)(h > 0.0f ? h : 0.0f);
+                }
+#pragma unroll
+                for (int i = 0; i < MT; ++i) h2[i] = mfma_k32(w2[i][c], b, h2[i]);
+            }
+            float part = 0.0f;
+#pragma unroll
+            for (int i = 0; i < MT; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) part = __builtin_fmaf(w3[i][r], h2[i][r] > 0.0f ? h2[i][r] : 0.0f, part);
+            part += __shfl_xor(part, 16);
+            part += __shfl_xor(part, 32);
+            if (g == t) my_y = part;
+        }
+        __syncthreads();
+        return finish_value(m, my_y);
+    }
+};
+
+}  // namespace cinr

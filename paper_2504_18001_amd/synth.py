@@ -99,16 +99,26 @@ def tf_ramp() -> np.ndarray:
     return np.repeat(r[:, None], 4, axis=1).copy()
 
 
-def tf_random(seed: int) -> np.ndarray:
+def tf_random(seed: int, n_ctrl: int = 9) -> np.ndarray:
+    """Random RGBA table, piecewise linear through `n_ctrl` random control
+    rows (U(0,1) per channel).  Its slope is bounded (<= (n_ctrl-1) per unit
+    value), so a value error maps to a colour error of the same order."""
     rng = np.random.default_rng(seed)
-    return rng.uniform(0.0, 1.0, size=(256, 4)).astype(np.float32)
+    ctrl = rng.uniform(0.0, 1.0, size=(n_ctrl, 4))
+    xs = np.linspace(0.0, 255.0, n_ctrl)
+    rows = np.arange(256, dtype=np.float64)
+    out = np.stack([np.interp(rows, xs, ctrl[:, c]) for c in range(4)], axis=1)
+    return out.astype(np.float32)
 
 
-def tf_window(lo: int, hi: int) -> np.ndarray:
-    """Opacity only inside rows [lo, hi]; zero elsewhere (makes macro-cell skipping bite)."""
+def tf_window(lo: int, hi: int, edge: int = 32) -> np.ndarray:
+    """Ramp colours with opacity zero outside rows [lo, hi] and rising over
+    `edge` rows from lo (opacity is exactly zero at and below row lo)."""
     t = tf_ramp()
-    t[:lo, 3] = 0.0
-    t[hi + 1:, 3] = 0.0
+    r = np.arange(256, dtype=np.float64)
+    a = np.clip((r - lo) / edge, 0.0, 1.0) * r / 255.0
+    a[r > hi] = 0.0
+    t[:, 3] = a.astype(np.float32)
     return t
 
 

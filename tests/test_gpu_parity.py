@@ -1,0 +1,192 @@
+"""GPU parity against the CPU oracle (through the C ABI).
+
+Tolerances: value-plane results (INR values, images) within max abs 2e-3 for
+the FP32 MLP and 8e-3 for BF16/FP16 (images: max abs RGBA); decision-plane
+results (page table, slot owners, stamps, ranks, request counts, request
+lists, miss lists, eviction logs) bit-exact.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2504_18001_amd import configs, synth
+from tests.helpers import inr_params, oracle_inr, value_range
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 2e-3, "bf16": 8e-3, "f16": 8e-3}
+# per-value (INR output) tolerances: FP32 only suffers reordering
+VTOL = {"f32": 1e-4, "bf16": 8e-3, "f16": 2e-3}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2504_18001_amd import cinr
+    cinr.lib()  # fails loudly if the library is missing
+
+
+def gpu_volume(arch, seed, dims=None, macrocells=None, macro_cell=0):
+    from paper_2504_18001_amd import cinr
+    t, w = inr_params(arch, seed)
+    s, o = value_range(arch, seed)
+    return cinr.Volume(arch, t, w, s, o, macrocells=macrocells, macro_cell=macro_cell, dims=dims)
+
+
+ARCHS = [("small", configs.ARCH_SMALL), ("inr512", configs.ARCH_512), ("tera", configs.ARCH_TERA)]
+
+
+@pytest.mark.parametrize("name,arch", ARCHS)
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
+def test_infer_points(name, arch, dtype):
+    if name == "tera" and dtype == "f32":
+        dtype = "f32"
+    vol = gpu_volume(arch, 0)
+    m = oracle_inr(arch, 0)
+    rng = np.random.default_rng(7)
+    n = 4099  # several workgroup rounds plus a ragged tail
+    V = np.asarray(arch.dims, np.float64)
+    x = (rng.uniform(-0.5, 1.0, size=(n, 3)) * (V - 1)).astype(np.float32)  # includes positions clamped to the box
+    got = vol.infer_points(torch.from_numpy(x).cuda(), dtype).cpu().numpy()
+    ref = m.value(x.astype(np.float64))
+    err = np.abs(got - ref)
+    print(name, dtype, "max", err.max(), "mean", err.mean())
+    assert err.max() <= VTOL[dtype]
+
+
+@pytest.mark.parametrize("name,arch,B,n_lods", [("small", configs.ARCH_SMALL, 8, 2), ("inr512", configs.ARCH_512, 16, 4)])
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_decode_bricks(name, arch, B, n_lods, dtype):
+    vol = gpu_volume(arch, 1)
+    m = oracle_inr(arch, 1)
+    nb, _ = vol.geometry(B, n_lods)
+    reqs = synth.random_requests(nb.tolist(), 37, seed=3)
+    # include the last brick of every LoD (clamped samples) and the origin brick
+    extra = [[L, *(nb[L] - 1)] for L in range(n_lods)] + [[0, 0, 0, 0]]
+    reqs = np.concatenate([reqs, np.asarray(extra, np.int32)])
+    got = vol.decode_bricks(torch.from_numpy(reqs).cuda(), B, dtype).cpu().numpy()
+    ref = m.decode_bricks(reqs, B, n_lods)
+    err = np.abs(got - ref)
+    print(name, dtype, "max", err.max())
+    assert err.max() <= VTOL[dtype]
+
+
+def test_decode_invalid_request_gives_nan():
+    vol = gpu_volume(configs.ARCH_SMALL, 0)
+    reqs = torch.tensor([[0, 0, 0, 0], [0, 99, 0, 0], [17, 0, 0, 0]], dtype=torch.int32, device="cuda")
+    out = vol.decode_bricks(reqs, 8).cpu().numpy()
+    assert np.isfinite(out[0]).all() and np.isnan(out[1]).all() and np.isnan(out[2]).all()
+
+
+def test_macrocells_match_oracle():
+    vol = gpu_volume(configs.ARCH_SMALL, 0)
+    m = oracle_inr(configs.ARCH_SMALL, 0)
+    got = vol.build_macrocells(16).cpu().numpy()
+    ref = m.macrocells(16)
+    assert np.abs(got - ref).max() <= 1e-4
+
+
+def _render_gpu(vol, cam, tf, w, frame, mode, dtype="f32", cache=None, ert=2.0, S=None, renderer=None):
+    from paper_2504_18001_amd import cinr
+    r = renderer or cinr.Renderer()
+    img = r.render(vol, cam, tf, w.step, w.lod_scale, frame_index=frame, seed=w.seed, ert_threshold=ert,
+                   samples_per_iter=S or w.samples_per_iter, mode=mode, dtype=dtype, cache=cache)
+    return img.cpu().numpy().astype(np.float64), r.last_stats()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_uncached_render_small(dtype):
+    from oracle import oracle as O
+    from paper_2504_18001_amd import cinr
+    w = configs.SMALL
+    vol = gpu_volume(w.arch, 0)
+    m = oracle_inr(w.arch, 0)
+    for frame in (0, 3):
+        cam = w.camera(frame)
+        cam.width, cam.height = 72, 56  # ragged 8x8 tiles
+        tf = w.tf(frame)
+        img, st = _render_gpu(vol, cam, tf, w, frame, cinr.UNCACHED_DIRECT, dtype)
+        p = O.make_params(w.step, w.lod_scale, seed=w.seed, frame_index=frame, samples_per_iter=w.samples_per_iter,
+                          mode=O.UNCACHED_DIRECT)
+        ref, rst = O.render_uncached(m, cam, tf, p)
+        err = np.abs(img - ref).max()
+        print("uncached", dtype, frame, err, st, rst)
+        assert err <= TOL[dtype]
+        assert st["rays"] == rst["rays"] and st["samples"] == rst["samples"] and st["misses"] == rst["misses"]
+
+
+def _compare_state(gc, oc, frame, check_misses=True):
+    from paper_2504_18001_amd import cinr
+    np.testing.assert_array_equal(gc.dump(cinr.DUMP_PAGE_TABLE), oc.page_table(), err_msg=f"page table f{frame}")
+    np.testing.assert_array_equal(gc.dump(cinr.DUMP_SLOT_OWNER), oc.owner(), err_msg=f"owner f{frame}")
+    np.testing.assert_array_equal(gc.dump(cinr.DUMP_LAST_USED), oc.last_used(), err_msg=f"last_used f{frame}")
+    np.testing.assert_array_equal(gc.dump(cinr.DUMP_RANK), oc.rank(), err_msg=f"rank f{frame}")
+    np.testing.assert_array_equal(gc.dump(cinr.DUMP_REQ_COUNT), oc.req_count(), err_msg=f"req f{frame}")
+    np.testing.assert_array_equal(gc.dump(cinr.DUMP_REQUEST_LIST), oc.request_list(), err_msg=f"list f{frame}")
+    np.testing.assert_array_equal(gc.dump(cinr.DUMP_EVICTION_LOG), oc.evict_log(), err_msg=f"evlog f{frame}")
+    if check_misses:
+        gpk, gpos = gc.dump(cinr.DUMP_MISS_LIST)
+        opk, opos = oc.miss_list()
+        np.testing.assert_array_equal(gpk, opk, err_msg=f"miss list f{frame}")
+        np.testing.assert_array_equal(gpos.view(np.uint32), opos.view(np.uint32), err_msg=f"miss pos f{frame}")
+
+
+def run_cached_sequence(w, frames, width, height, dtype="f32", dims=None, pool=None, max_req=None, ranking=1,
+                        preload=None, S=None, macro=False, tf_fn=None, n_lods=None, brick=None):
+    from oracle import oracle as O
+    from paper_2504_18001_amd import cinr
+    arch = w.arch
+    cs = w.cache
+    B = brick or cs.brick
+    nl = n_lods or cs.n_lods
+    pool = pool if pool is not None else cs.pool_bricks
+    max_req = max_req if max_req is not None else cs.max_requests
+    preload = cs.preload_period if preload is None else preload
+    m = oracle_inr(arch, 0, dims=dims)
+    mm = m.macrocells(w.macro_cell) if macro else None
+    vol = gpu_volume(arch, 0, dims=dims, macrocells=mm, macro_cell=w.macro_cell if macro else 0)
+    gc = cinr.Cache(vol, B, nl, pool, max_req, ranking=ranking, preload_period=preload, miss_log_capacity=1 << 22,
+                    evict_log_capacity=1 << 16, keep_request_counts=True)
+    oc = O.OracleCache(m, brick=B, n_lods=nl, pool_bricks=pool, max_requests=max_req, ranking=ranking,
+                       preload_period=preload, log_misses=True)
+    r = cinr.Renderer()
+    worst = 0.0
+    for f in frames:
+        cam = w.camera(f, dims)
+        cam.width, cam.height = width, height
+        tf = tf_fn(f) if tf_fn else w.tf(f)
+        img, st = _render_gpu(vol, cam, tf, w, f, cinr.CACHED, dtype, cache=gc, S=S, renderer=r)
+        p = O.make_params(w.step, w.lod_scale, seed=w.seed, frame_index=f, samples_per_iter=S or w.samples_per_iter,
+                          mode=O.CACHED, macro_cell=w.macro_cell if macro else 0, macro_minmax=mm)
+        ref, rst = oc.render(cam, tf, p)
+        err = np.abs(img - ref).max()
+        worst = max(worst, err)
+        print(f"frame {f}: err {err:.2e} gpu {st} oracle {rst}", flush=True)
+        for k in ("rays", "samples", "hits", "fallbacks", "misses", "skipped", "requested", "selected", "evicted"):
+            assert st[k] == rst[k], (f, k, st[k], rst[k])
+        _compare_state(gc, oc, f)
+        assert err <= TOL[dtype], (f, err)
+    return worst
+
+
+def test_cached_sequence_small_parity():
+    # 64^3, 128x128, B = 8, 2 LoDs, 96-slot pool, 16 requests per frame:
+    # the pool fills after 6 frames and LRU eviction runs from then on.
+    w = configs.SMALL
+    run_cached_sequence(w, range(12), 128, 128)
+
+
+def test_cached_sequence_small_bf16_with_macrocells_and_key_order():
+    w = configs.SMALL
+    run_cached_sequence(w, range(6), 64, 48, dtype="bf16", ranking=0, macro=True,
+                        tf_fn=lambda f: synth.tf_window(60, 255))
+
+
+def test_cached_sequence_512_arch_reduced():
+    # the 512^3 architecture (16 levels x 2, T = 2^19, 32-64-64-1) on a
+    # 120x104x96 virtual volume, 4 LoDs, B = 16, pre-load of the coarsest LoD
+    w = configs.scaled(configs.HD512, 80, 45, orbit_radius=260.0, lod_scale=1.0 / 180.0)
+    run_cached_sequence(w, range(8), 80, 45, dims=(120, 104, 96), pool=300, max_req=12, preload=2)
