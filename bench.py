@@ -142,13 +142,30 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=60)
     ap.add_argument("--warmup", type=int, default=180)
-    ap.add_argument("--dtype", default="bf16")
+    ap.add_argument("--dtype", default="bf16x3",
+                    help="MLP arithmetic of the headline run: bf16x3 (BF16 MFMA with split operands), bf16, f16, f32")
+    ap.add_argument("--precisions", default="f32,bf16,f16",
+                    help="other MLP precisions run on the same cached sequence (own caches) for comparison")
     ap.add_argument("--uncached-steps", type=int, default=None)
     ap.add_argument("--decode-bricks", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp32-cached", action="store_true")
+    ap.add_argument("--no-fp32-cached", action="store_true", help="skip the comparison precisions")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only run a plain elementwise copy of this many MiB (y = x * 1) five times, to scale "
+                         "hardware traffic counters, and exit")
     args = ap.parse_args()
+    if args.calibrate_copy_mib:
+        import torch
+        n = args.calibrate_copy_mib * (1 << 20) // 4
+        x = torch.rand(n, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "elementwise copy", "bytes_read": 4 * n, "bytes_written": 4 * n,
+                          "launches": 5}))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); multi-GPU sort-first "
               f"rendering is not part of it", file=sys.stderr)
@@ -210,26 +227,27 @@ def main():
     q_unc = psnr(cached_img.cpu().numpy(), out2.cpu().numpy())
     log(f"[bench] uncached f32: {fps_unc:.1f} fps; PSNR cached vs uncached {q_unc:.2f} dB")
 
-    # --- cached FP32 MLP (same sequence, own cache) ---------------------------
-    fps_c32 = None
-    q_prec = None
+    # --- the same cached sequence with the other MLP precisions -----------------
+    other = {}
     if not args.no_fp32_cached:
-        cache32 = new_cache(vol, w)
-        r3 = cinr.Renderer()
-        out3 = torch.empty_like(out)
-        run_frames(r3, vol, cams, tfs, w, range(Wm), cinr.CACHED, "f32", cache32, out=out3)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        run_frames(r3, vol, cams, tfs, w, range(Wm, Wm + K), cinr.CACHED, "f32", cache32, out=out3)
-        torch.cuda.synchronize()
-        fps_c32 = K / (time.perf_counter() - t0)
-        q_prec = psnr(cached_img.cpu().numpy(), out3.cpu().numpy())
-        del cache32
-        log(f"[bench] cached f32: {fps_c32:.1f} fps; PSNR {args.dtype} vs f32 cached {q_prec:.2f} dB")
+        ref_img = cached_img.cpu().numpy()
+        for dt in [d for d in args.precisions.split(",") if d and d != args.dtype]:
+            c2 = new_cache(vol, w)
+            r3 = cinr.Renderer()
+            out3 = torch.empty_like(out)
+            run_frames(r3, vol, cams, tfs, w, range(Wm), cinr.CACHED, dt, c2, out=out3)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            run_frames(r3, vol, cams, tfs, w, range(Wm, Wm + K), cinr.CACHED, dt, c2, out=out3)
+            torch.cuda.synchronize()
+            other[dt] = {"fps": round(K / (time.perf_counter() - t0), 2),
+                         "psnr_vs_headline_db": round(psnr(ref_img, out3.cpu().numpy()), 2)}
+            del c2
+            log(f"[bench] cached {dt}: {other[dt]}")
 
     # --- brick decoding throughput -------------------------------------------
     bps = {}
-    for dt in (args.dtype, "f32"):
+    for dt in dict.fromkeys([args.dtype, "bf16", "f16", "f32"]):
         bps[dt], _ = decode_throughput(vol, w, dt, args.decode_bricks)
     log(f"[bench] decode bricks/s {bps}")
 
@@ -249,7 +267,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.dtype,
+        "dtype": "bf16" if args.dtype == "bf16x3" else args.dtype,
         "data": "synthetic (seeded random-init INR; the paper's datasets are not used)",
         "config": {"workload": w.name, "width": w.width, "height": w.height, "volume": list(w.arch.dims),
                    "hash_grid": "16 levels x 2 features, T=2^19", "mlp": "32-64-64-1", "brick": w.cache.brick,
@@ -258,10 +276,12 @@ def main():
                    "orbit_frames": w.n_frames},
         "uncached_fp32_fps": round(fps_unc, 2),
         "speedup_vs_uncached_fp32": round(fps / fps_unc, 3),
-        "cached_fp32_fps": None if fps_c32 is None else round(fps_c32, 2),
+        "mlp_precision": {"bf16x3": "BF16 MFMA, operands split into hi+lo BF16, FP32 accumulation",
+                          "bf16": "BF16 MFMA, FP32 accumulation", "f16": "FP16 MFMA, FP32 accumulation",
+                          "f32": "FP32 MFMA"}.get(args.dtype, args.dtype),
+        "cached_other_precisions": other,
         "bricks_per_s": {k: round(v, 1) for k, v in bps.items()},
         "psnr_cached_vs_uncached_db": round(q_unc, 2),
-        "psnr_reduced_vs_fp32_cached_db": None if q_prec is None else round(q_prec, 2),
         "stage_ms_per_frame": {k: round(v[0] / K, 4) for k, v in stages.items()},
         "frame_totals": tot,
         "roofline": {"kernel": "k_march", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,

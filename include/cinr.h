@@ -50,8 +50,11 @@ typedef enum {
 } cinr_status;
 
 /* Arithmetic of the MLP layers (hash-grid interpolation, compositing and the
- * brick pool stay FP32); reduced precisions accumulate in FP32 on MFMA. */
-typedef enum { CINR_F32 = 0, CINR_BF16 = 1, CINR_F16 = 2 } cinr_dtype;
+ * brick pool stay FP32; the output layer is FP32).  Reduced precisions run on
+ * MFMA with FP32 accumulation.  CINR_BF16X3 splits every operand into two
+ * BF16 terms (x = hi + lo) and accumulates hi*hi + hi*lo + lo*hi: BF16 MFMA
+ * arithmetic with close to FP32 accuracy. */
+typedef enum { CINR_F32 = 0, CINR_BF16 = 1, CINR_F16 = 2, CINR_BF16X3 = 3 } cinr_dtype;
 
 typedef enum {
     CINR_CACHED = 0,         /* sampler of Algorithm 2 behind the brick cache */
@@ -152,7 +155,12 @@ typedef struct {
  *                timestamp and must increase by one per cached frame.
  *  samples_per_iter  samples gathered per wavefront step after a true miss.
  *  mode          cinr_mode.
- *  mlp_dtype     cinr_dtype of brick decoding and true-miss inference. */
+ *  mlp_dtype     cinr_dtype of brick decoding and true-miss inference.
+ *  pipe_depth    tuning: samples each ray decides and fetches ahead while
+ *                marching (1, 2, 4 or 8; 0 = default 2).  Results do not
+ *                depend on it.
+ *  xcd_bands     tuning: image bands per XCD in the sampler's work split
+ *                (0 = default 4).  Results do not depend on it. */
 typedef struct {
     float step, lod_scale, ert_threshold;
     uint32_t seed;
@@ -160,6 +168,8 @@ typedef struct {
     int32_t samples_per_iter;
     int32_t mode;
     int32_t mlp_dtype;
+    int32_t pipe_depth;
+    int32_t xcd_bands;
 } cinr_render_params;
 
 /* Frame counters written (not accumulated) by cinr_render_frame. */

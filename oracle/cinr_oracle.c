@@ -629,7 +629,7 @@ int64_t orc_cache_ert_trace(const orc_cache* c, int32_t* out, int64_t cap) {
  * recently used slot by (last_used, slot) among slots not filled by this
  * batch.  The evicted brick's page-table entry is unmapped and its rank
  * forgotten; the new brick is decoded into the slot, mapped, and stamped. */
-static void insert_brick(orc_cache* c, int32_t key, int32_t stamp, uint8_t* filled) {
+static void insert_brick(orc_cache* c, int32_t key, int32_t stamp, uint8_t* filled, int32_t* slot_out) {
     const int32_t P = c->d.pool_bricks;
     int32_t slot = -1;
     for (int32_t s = 0; s < P; ++s)
@@ -643,19 +643,14 @@ static void insert_brick(orc_cache* c, int32_t key, int32_t stamp, uint8_t* fill
             if (slot < 0 || c->last_used[s] < c->last_used[slot]) slot = s;
         }
     }
+    *slot_out = -1;
     if (slot < 0) return;
     int32_t old = c->owner[slot];
     if (old >= 0) {
         c->pt[old] = -1;
         c->rank[old] = -1;
     }
-    int L = 0;
-    while (L + 1 < c->d.n_lods && key >= c->g[L + 1].off) ++L;
-    int64_t local = key - c->g[L].off;
-    int32_t b[3] = {(int32_t)(local % c->g[L].nb[0]), (int32_t)((local / c->g[L].nb[0]) % c->g[L].nb[1]),
-                    (int32_t)(local / ((int64_t)c->g[L].nb[0] * c->g[L].nb[1]))};
-    const int64_t B3 = (int64_t)c->d.brick * c->d.brick * c->d.brick;
-    decode_brick(&c->inr, L, b, c->d.brick, c->pool + (int64_t)slot * B3);
+    *slot_out = slot;
     c->pt[key] = slot;
     c->owner[slot] = key;
     c->last_used[slot] = stamp;
@@ -672,6 +667,22 @@ static void insert_brick(orc_cache* c, int32_t key, int32_t stamp, uint8_t* fill
 }
 
 /* Pre-loading into free slots only (never evicts). */
+/* Decodes the bricks just inserted (key -> slot) into their pool slots. */
+static void decode_inserted(orc_cache* c, const int32_t* keys, const int32_t* slots, int64_t n) {
+    const int64_t B3 = (int64_t)c->d.brick * c->d.brick * c->d.brick;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < n; ++i) {
+        if (slots[i] < 0) continue;
+        const int32_t key = keys[i];
+        int L = 0;
+        while (L + 1 < c->d.n_lods && key >= c->g[L + 1].off) ++L;
+        const int64_t local = key - c->g[L].off;
+        const int32_t b[3] = {(int32_t)(local % c->g[L].nb[0]), (int32_t)((local / c->g[L].nb[0]) % c->g[L].nb[1]),
+                              (int32_t)(local / ((int64_t)c->g[L].nb[0] * c->g[L].nb[1]))};
+        decode_brick(&c->inr, L, b, c->d.brick, c->pool + (int64_t)slots[i] * B3);
+    }
+}
+
 int orc_cache_prefill(orc_cache* c, const int32_t* keys, int64_t n, int32_t stamp) {
     int64_t n_free = 0;
     for (int32_t s = 0; s < c->d.pool_bricks; ++s) n_free += c->owner[s] < 0;
@@ -682,7 +693,10 @@ int orc_cache_prefill(orc_cache* c, const int32_t* keys, int64_t n, int32_t stam
         for (int64_t j = i + 1; j < n; ++j)
             if (keys[i] == keys[j]) return -1;
     uint8_t* filled = (uint8_t*)calloc(c->d.pool_bricks > 0 ? c->d.pool_bricks : 1, 1);
-    for (int64_t i = 0; i < n; ++i) insert_brick(c, keys[i], stamp, filled);
+    int32_t* slots = (int32_t*)malloc(sizeof(int32_t) * (n ? n : 1));
+    for (int64_t i = 0; i < n; ++i) insert_brick(c, keys[i], stamp, filled, &slots[i]);
+    decode_inserted(c, keys, slots, n);
+    free(slots);
     free(filled);
     return 0;
 }
@@ -696,6 +710,7 @@ enum { S_HIT = 0, S_FALLBACK = 1, S_MISS = 2, S_SKIP = 3 };
 typedef struct {
     const orc_inr* m;
     orc_cache* c;           /* NULL in the uncached modes */
+    int readonly;           /* no request counts, no stamps */
     const orc_camera* cam;
     const orc_params* p;
     const uint8_t* flags;   /* macro-cell flags or NULL */
@@ -801,11 +816,13 @@ static void sample_decide(const frame_ctx* fc, const float o[3], const float d[3
         }
         so->value = trilinear8(corner, f);
         so->status = (Lp == L) ? S_HIT : S_FALLBACK;
+        if (!fc->readonly) {
 #pragma omp atomic write
-        c->last_used[slot] = P->frame_index;
+            c->last_used[slot] = P->frame_index;
+        }
         break;
     }
-    if (so->status != S_HIT) {
+    if (so->status != S_HIT && !fc->readonly) {
 #pragma omp atomic
         c->req[req_key] += 1u;
     }
@@ -1059,7 +1076,10 @@ static void finish_frame(orc_cache* c, int32_t f, orc_stats* st) {
     end_of_frame(c, f, st);
     const int64_t ev0 = c->n_evlog;
     uint8_t* filled = (uint8_t*)calloc(c->d.pool_bricks > 0 ? c->d.pool_bricks : 1, 1);
-    for (int64_t i = 0; i < c->n_req_list; ++i) insert_brick(c, c->req_list[i], f + 1, filled);
+    int32_t* slots = (int32_t*)malloc(sizeof(int32_t) * (size_t)(c->n_req_list > 0 ? c->n_req_list : 1));
+    for (int64_t i = 0; i < c->n_req_list; ++i) insert_brick(c, c->req_list[i], f + 1, filled, &slots[i]);
+    decode_inserted(c, c->req_list, slots, c->n_req_list);
+    free(slots);
     free(filled);
     int64_t ev = 0;
     for (int64_t i = ev0; i < c->n_evlog; ++i)
@@ -1113,6 +1133,46 @@ int orc_cache_render(orc_cache* c, const orc_camera* cam, const float* tf, const
     render_pass(&fc, tf, rgba, st, c->log_misses, trace);
     free((void*)fc.flags);
     finish_frame(c, p->frame_index, st);
+    return 0;
+}
+
+/* Renders only the listed pixels (index j*W + i) of a frame, against the
+ * cache's current residency (c may be NULL for the uncached modes), without
+ * changing any cache state: no request counts, no stamps, no end of frame. */
+int orc_render_pixels(const orc_inr* m, orc_cache* c, const orc_camera* cam, const float* tf, const orc_params* p,
+                      const int32_t* pix, int64_t n, double* rgba) {
+    if ((p->mode == ORC_CACHED) != (c != NULL)) return -1;
+    frame_ctx fc;
+    memset(&fc, 0, sizeof(fc));
+    fc.m = c ? &c->inr : m;
+    fc.c = c;
+    fc.readonly = 1;
+    fc.cam = cam;
+    fc.p = p;
+    for (int a = 0; a < 3; ++a) fc.vm1[a] = (float)(fc.m->dims[a] - 1);
+    fc.flags = make_flags(fc.m, p, tf, fc.M);
+    if (c) {
+        fc.frame_seed = orc_frame_seed(p->seed, (uint32_t)p->frame_index);
+        fc.lod_floor = orc_lod_floor(p->frame_index, c->d.preload_period, c->d.n_lods);
+    }
+    const int nt = orc_get_threads();
+    thread_acc* acc = (thread_acc*)calloc(nt, sizeof(thread_acc));
+#pragma omp parallel
+    {
+#ifdef _OPENMP
+        thread_acc* ta = &acc[omp_get_thread_num()];
+#else
+        thread_acc* ta = &acc[0];
+#endif
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t q = 0; q < n; ++q) {
+            const int32_t i = pix[q] % cam->width, j = pix[q] / cam->width;
+            march(&fc, ta, tf, i, j, rgba + 4 * q, 0);
+        }
+    }
+    for (int t = 0; t < nt; ++t) free(acc[t].misses_buf);
+    free(acc);
+    free((void*)fc.flags);
     return 0;
 }
 

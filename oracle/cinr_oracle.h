@@ -116,6 +116,10 @@ int32_t orc_lod_floor(int32_t frame, int32_t period, int32_t n_lods);
 int orc_render_uncached(const orc_inr* m, const orc_camera* c, const float* tf,
                         const orc_params* p, double* rgba, orc_stats* st);
 
+/* Listed pixels of a frame against the current residency, no state change. */
+int orc_render_pixels(const orc_inr* m, orc_cache* c, const orc_camera* cam, const float* tf, const orc_params* p,
+                      const int32_t* pix, int64_t n, double* rgba);
+
 /* --- cached renderer --- */
 orc_cache* orc_cache_create(const orc_inr* m, const orc_cache_desc* d);
 void orc_cache_destroy(orc_cache* c);

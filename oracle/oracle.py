@@ -85,6 +85,7 @@ def lib():
             "orc_select_lod": (i32, [P, P, C.c_float, u32, i32, i32]),
             "orc_lod_floor": (i32, [i32, i32, i32]),
             "orc_render_uncached": (C.c_int, [P, P, P, P, P, P]),
+            "orc_render_pixels": (C.c_int, [P, P, P, P, P, P, i64, P]),
             "orc_cache_create": (P, [P, P]),
             "orc_cache_destroy": (None, [P]),
             "orc_cache_render": (C.c_int, [P, P, P, P, P, P]),
@@ -290,6 +291,19 @@ def render_uncached(inr: OracleInr, cam, tf, params: Params):
     rc = lib().orc_render_uncached(inr.ref(), C.byref(c), _ptr(t), C.byref(params), _ptr(out), C.byref(st))
     assert rc == 0
     return out, st.as_dict()
+
+
+def render_pixels(inr: OracleInr, cam, tf, params: Params, pixels, cache=None):
+    """Colours of the listed pixels (j*W + i), against `cache`'s residency
+    (None for the uncached modes), leaving all state untouched."""
+    c = camera_struct(cam)
+    t = np.ascontiguousarray(tf, np.float32)
+    px = np.ascontiguousarray(pixels, np.int32)
+    out = np.zeros((px.size, 4), np.float64)
+    rc = lib().orc_render_pixels(inr.ref(), cache.h if cache is not None else None, C.byref(c), _ptr(t),
+                                 C.byref(params), _ptr(px), px.size, _ptr(out))
+    assert rc == 0
+    return out
 
 
 class OracleCache:

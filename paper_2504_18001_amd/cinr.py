@@ -17,14 +17,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcinr.so")
 
 MAX_LEVELS, MAX_LAYERS, MAX_LODS = 32, 8, 16
-F32, BF16, F16 = 0, 1, 2
+F32, BF16, F16, BF16X3 = 0, 1, 2, 3
 CACHED, UNCACHED_DIRECT = 0, 1
 RANK_TIMESTAMP, RANK_PRIORITY = 0, 1
 PERSPECTIVE, ORTHOGRAPHIC = 0, 1
 DUMP_PAGE_TABLE, DUMP_SLOT_OWNER, DUMP_LAST_USED, DUMP_RANK, DUMP_REQ_COUNT = 0, 1, 2, 3, 4
 DUMP_REQUEST_LIST, DUMP_MISS_LIST, DUMP_EVICTION_LOG, DUMP_POOL = 5, 6, 7, 8
 
-DTYPES = {"f32": F32, "fp32": F32, "bf16": BF16, "f16": F16, "fp16": F16}
+DTYPES = {"f32": F32, "fp32": F32, "bf16": BF16, "f16": F16, "fp16": F16, "bf16x3": BF16X3}
 
 
 class CinrError(RuntimeError):
@@ -54,7 +54,7 @@ class CameraDesc(C.Structure):
 class RenderParams(C.Structure):
     _fields_ = [("step", C.c_float), ("lod_scale", C.c_float), ("ert_threshold", C.c_float), ("seed", C.c_uint32),
                 ("frame_index", C.c_int32), ("samples_per_iter", C.c_int32), ("mode", C.c_int32),
-                ("mlp_dtype", C.c_int32)]
+                ("mlp_dtype", C.c_int32), ("pipe_depth", C.c_int32), ("xcd_bands", C.c_int32)]
 
 
 STAGES = ("setup", "march", "infer", "shade", "cm", "decode")
@@ -278,7 +278,8 @@ class Renderer:
         self.stats = torch.zeros(len(STAT_FIELDS), dtype=torch.int64, device=device)
 
     def render(self, volume: Volume, cam, tf, step, lod_scale=0.0, frame_index=0, seed=0, ert_threshold=2.0,
-               samples_per_iter=32, mode=CACHED, dtype="f32", cache: Cache = None, out=None, stats=None):
+               samples_per_iter=32, mode=CACHED, dtype="f32", cache: Cache = None, out=None, stats=None,
+               pipe_depth=0, xcd_bands=0):
         need = C.c_size_t()
         _check(lib().cinr_render_workspace_size(volume.h, cam.width, cam.height, samples_per_iter, C.byref(need)))
         if self.ws is None or self.ws.numel() < need.value:
@@ -291,6 +292,7 @@ class Renderer:
         p.step, p.lod_scale, p.ert_threshold = float(step), float(lod_scale), float(ert_threshold)
         p.seed, p.frame_index, p.samples_per_iter = int(seed) & 0xFFFFFFFF, int(frame_index), int(samples_per_iter)
         p.mode, p.mlp_dtype = int(mode), _dtype(dtype)
+        p.pipe_depth, p.xcd_bands = int(pipe_depth), int(xcd_bands)
         cd = camera_desc(cam)
         st = self.stats if stats is None else stats
         _check(lib().cinr_render_frame(cache.h if cache is not None else None, volume.h, C.byref(cd), _ptr(tf),

@@ -52,6 +52,7 @@ bool geometry(const int32_t dims[3], int32_t B, int32_t n_lods, CacheGeom& g) {
     if (B < 2 || n_lods < 1 || n_lods > kMaxLods) return false;
     g = CacheGeom{};
     g.brick = B;
+    g.div_b1 = make_fastdiv((uint32_t)(B - 1));
     g.n_lods = n_lods;
     int64_t off = 0;
     for (int L = 0; L < n_lods; ++L) {
@@ -134,7 +135,8 @@ struct cinr_cache_s {
     CacheGeom g;
     CacheDev c;
     TopkPlan plan_sel, plan_vic;
-    int32_t lim;  // request list length bound: min(max_requests, pool)
+    int32_t lim;          // request list length bound: min(max_requests, pool)
+    int64_t used_bound;   // host upper bound on occupied slots (no LRU pass needed below the pool size)
 };
 
 // ---------------------------------------------------------------------------
@@ -255,7 +257,8 @@ extern "C" cinr_status cinr_lod_geometry(cinr_volume v, int32_t brick, int32_t n
 }
 
 static cinr_status check_shape(cinr_volume v, int32_t prec) {
-    if (prec != CINR_F32 && prec != CINR_BF16 && prec != CINR_F16) return fail(CINR_INVALID_ARG, "mlp_dtype = %d", prec);
+    if (prec != CINR_F32 && prec != CINR_BF16 && prec != CINR_F16 && prec != CINR_BF16X3)
+        return fail(CINR_INVALID_ARG, "mlp_dtype = %d", prec);
     if (v->m.hidden < 0 || !inr_shape_supported(v->m))
         return fail(CINR_UNSUPPORTED, "no gfx950 kernel for this INR shape (3 layers, levels x features in {8x2, 16x2, 16x4}, hidden 32 or 64)");
     return CINR_OK;
@@ -380,6 +383,7 @@ extern "C" cinr_status cinr_create_cache(cinr_volume v, const cinr_cache_desc* d
     cache_layout(d, g, &c->c, &c->plan_sel, &c->plan_vic, d_ws);
     c->c.pool = d_pool;
     c->lim = std::max(1, std::min(d->max_requests, d->pool_bricks));
+    c->used_bound = 0;
     hipError_t e = launch_cache_init(c->c, g.n_keys, (hipStream_t)stream);
     if (e != hipSuccess) {
         delete c;
@@ -399,6 +403,7 @@ extern "C" cinr_status cinr_cache_prefill(cinr_cache c, const int32_t* d_keys, i
     if (st) return st;
     if (n == 0) return CINR_OK;
     hipStream_t s = (hipStream_t)stream;
+    c->used_bound = std::min<int64_t>(c->used_bound + n, c->c.pool_bricks);
     HIP_TRY(launch_prefill_setup(c->c, d_keys, n, s));
     HIP_TRY(launch_insert(c->c, c->g, stamp, n, s));
     HIP_TRY(inr_decode_bricks(c->vol->m, c->g, c->c.ins_reqs, &c->c.ctr->n_sel, n, c->c.ins_slots, c->c.pool, prec, s));
@@ -440,7 +445,7 @@ static size_t render_layout(int64_t npix, int32_t S, int64_t n_cells, RenderLayo
 }
 
 extern "C" cinr_status cinr_render_workspace_size(cinr_volume v, int32_t W, int32_t H, int32_t S, size_t* bytes) {
-    if (!v || !bytes || W < 1 || H < 1 || S < 1) return fail(CINR_INVALID_ARG, "invalid arguments");
+    if (!v || !bytes || W < 1 || H < 1 || S < 1 || S > 64) return fail(CINR_INVALID_ARG, "invalid arguments");
     if ((int64_t)W * H * S > 0xFFFFFFFFll) return fail(CINR_INVALID_ARG, "width*height*samples_per_iter >= 2^32");
     *bytes = render_layout((int64_t)W * H, S, v->n_cells, nullptr, nullptr);
     return CINR_OK;
@@ -467,7 +472,11 @@ extern "C" cinr_status cinr_render_frame(cinr_cache c, cinr_volume v, const cinr
     if (rp->mode != CINR_CACHED && rp->mode != CINR_UNCACHED_DIRECT) return fail(CINR_INVALID_ARG, "mode = %d", rp->mode);
     if (!(rp->step > 0.0f) || !isfinite(rp->step)) return fail(CINR_INVALID_ARG, "step must be > 0");
     if (!(rp->lod_scale >= 0.0f)) return fail(CINR_INVALID_ARG, "lod_scale must be >= 0");
-    if (rp->samples_per_iter < 1) return fail(CINR_INVALID_ARG, "samples_per_iter must be >= 1");
+    if (rp->pipe_depth != 0 && rp->pipe_depth != 1 && rp->pipe_depth != 2 && rp->pipe_depth != 4 && rp->pipe_depth != 8)
+        return fail(CINR_INVALID_ARG, "pipe_depth must be 0, 1, 2, 4 or 8");
+    if (rp->xcd_bands < 0 || rp->xcd_bands > 64) return fail(CINR_INVALID_ARG, "xcd_bands must be in [0, 64]");
+    if (rp->samples_per_iter < 1 || rp->samples_per_iter > 64)
+        return fail(CINR_INVALID_ARG, "samples_per_iter must be in [1, 64]");
     const bool cached = rp->mode == CINR_CACHED;
     if (cached && !c) return fail(CINR_INVALID_ARG, "the cached mode needs a cache");
     if (cached && c->vol != v) return fail(CINR_INVALID_ARG, "cache belongs to another volume");
@@ -517,7 +526,10 @@ extern "C" cinr_status cinr_render_frame(cinr_cache c, cinr_volume v, const cinr
     f.frame = rp->frame_index;
     f.S = S;
     f.mode = rp->mode;
+    f.xcd_bands = rp->xcd_bands > 0 ? rp->xcd_bands : 4;
+    f.pipe = rp->pipe_depth > 0 ? rp->pipe_depth : 2;
     f.mc_N = v->desc.macrocell_size;
+    f.div_mc = make_fastdiv((uint32_t)(f.mc_N > 0 ? f.mc_N : 1));
     f.flags = v->n_cells > 0 ? L.flags : nullptr;
     f.tf = d_tf;
     f.rgba = reinterpret_cast<float4*>(d_rgba);
@@ -566,14 +578,20 @@ extern "C" cinr_status cinr_render_frame(cinr_cache c, cinr_volume v, const cinr
         StageTimer st_(tm, s, CINR_STAGE_SETUP);
         HIP_TRY(launch_frame_begin(f, n_ctr, f.flags, v->desc.d_macrocells, v->n_cells, cctr, s));
         if (cached && c->c.last_req) HIP_TRY(launch_clear_last_req(c->c, c->g.n_keys, s));
-        HIP_TRY(launch_raygen(f, s));
     }
+    // wavefront iterations: march; stop when no ray gathered a step with a
+    // true miss; otherwise infer the misses and composite the gathered steps
     int n_iters = 0;
     for (int it = 0; it < max_iters; ++it) {
         {
             StageTimer st_(tm, s, CINR_STAGE_MARCH);
             HIP_TRY(launch_march(f, it, npix, s));
         }
+        n_iters = it + 1;
+        HIP_TRY(hipMemcpyAsync(v->pinned, &f.ctr[it].pending, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipEventRecord(v->ev, s));
+        HIP_TRY(hipEventSynchronize(v->ev));
+        if (*(volatile int32_t*)v->pinned == 0) break;
         {
             StageTimer st_(tm, s, CINR_STAGE_INFER);
             HIP_TRY(inr_infer_misses(v->m, f.miss_rec, &f.ctr[it].misses, npix * S, f.vals, rp->mlp_dtype, s));
@@ -582,22 +600,33 @@ extern "C" cinr_status cinr_render_frame(cinr_cache c, cinr_volume v, const cinr
             StageTimer st_(tm, s, CINR_STAGE_SHADE);
             HIP_TRY(launch_shade(f, it, npix, s));
         }
-        n_iters = it + 1;
-        HIP_TRY(hipMemcpyAsync(v->pinned, &f.ctr[it + 1].live, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipEventRecord(v->ev, s));
-        HIP_TRY(hipEventSynchronize(v->ev));
-        if (*(volatile int32_t*)v->pinned == 0) break;
     }
     if (cached) {
         const CacheDev& cd = c->c;
         StageTimer st_(tm, s, CINR_STAGE_CM);
-        HIP_TRY(launch_cm_rank(cd, rp->frame_index, c->g.n_keys, s));
-        HIP_TRY(launch_topk(cd.cand, &cd.ctr->n_touched, c->plan_sel, c->lim, cd.topk[0], cd.topk[1], cd.sel, nullptr,
-                            nullptr, s));
-        HIP_TRY(launch_cm_select(cd, s));
-        if (cd.pool_bricks > 0)
-            HIP_TRY(launch_topk(nullptr, &cd.ctr->n_used, c->plan_vic, c->lim, cd.topk[0], cd.topk[1], cd.vic,
-                                &cd.ctr->need_evict, cd.last_used, s));
+        // ranking of the requested bricks fused into the first selection pass;
+        // the request list is published by the last pass
+        TopkArgs ta{};
+        ta.in = cd.cand;
+        ta.count_dev = &cd.ctr->n_touched;
+        ta.cap0 = (uint64_t)c->g.n_keys;
+        ta.k = c->lim;
+        ta.mode = TOPK_RANK;
+        ta.ra = RankArgs{cd.touched, cd.req, cd.last_req, cd.rank, rp->frame_index, cd.rank_window, cd.ranking};
+        SelectArgs sel{cd.ins_keys, cd.ctr, cd.pool_bricks, c->lim};
+        HIP_TRY(launch_topk(ta, c->plan_sel, cd.topk[0], cd.topk[1], cd.sel, &sel, s));
+        // LRU victims, only when the pool may be full
+        if (cd.pool_bricks > 0 && c->used_bound + c->lim > cd.pool_bricks) {
+            TopkArgs tv{};
+            tv.count_dev = &cd.ctr->n_used;
+            tv.cap0 = (uint64_t)cd.pool_bricks;
+            tv.k = c->lim;
+            tv.gate = &cd.ctr->need_evict;
+            tv.mode = TOPK_LRU;
+            tv.lru_last_used = cd.last_used;
+            HIP_TRY(launch_topk(tv, c->plan_vic, cd.topk[0], cd.topk[1], cd.vic, nullptr, s));
+        }
+        c->used_bound = std::min<int64_t>(c->used_bound + c->lim, cd.pool_bricks);
         HIP_TRY(launch_insert(cd, c->g, rp->frame_index + 1, c->lim, s));
     }
     if (cached) {
@@ -607,7 +636,6 @@ extern "C" cinr_status cinr_render_frame(cinr_cache c, cinr_volume v, const cinr
                                   rp->mlp_dtype, s));
     }
     HIP_TRY(launch_frame_end(f, n_iters, cctr, s));
-    if (cached) HIP_TRY(launch_touched_reset(c->c, s));
     return CINR_OK;
 }
 

@@ -33,92 +33,99 @@ __global__ void k_cache_init(CacheDev c, int64_t n_keys) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *c.ctr = CacheCtr{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
 }
 
-__global__ void k_cm_rank(CacheDev c, int32_t frame) {
-    const uint32_t n = c.ctr->n_touched;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const int32_t key = c.touched[i];
-        const uint32_t cnt = c.req[key];
-        if (c.last_req) c.last_req[key] = cnt;
-        const int64_t old = c.rank[key];
-        int64_t r = old < 0 ? (int64_t)frame + (int64_t)cnt - 1 : old + (int64_t)cnt;
-        const int64_t cap = (int64_t)frame + c.rank_window;
-        if (r > cap) r = cap;
-        c.rank[key] = r;
-        c.req[key] = 0u;
-        const uint64_t low = 0xFFFFFFFFull - (uint64_t)(uint32_t)key;
-        c.cand[i] = c.ranking ? (((uint64_t)r << 32) | low) : low;
-    }
-}
-
 // Clears the request counts kept for dumps (before the frame's sampler).
 __global__ void k_clear_last_req(CacheDev c, int64_t n_keys) {
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_keys; t += (int64_t)gridDim.x * blockDim.x)
         c.last_req[t] = 0u;
 }
 
-// One tournament pass: workgroup b sorts elements [b*2048, (b+1)*2048) of
-// its input (missing elements are 0, which sorts last) in descending order
-// and writes the first k to out[b*k ...].  In LRU mode the input is the slot
-// range [0, count) scored ~(last_used << 32 | slot).
-__global__ __launch_bounds__(256) void k_topk(const uint64_t* in, const uint32_t* count_dev, uint32_t count_cap,
-                                              uint64_t* out, int32_t k, const uint32_t* gate,
-                                              const int32_t* lru_last_used) {
+// Score of touched brick `idx` after its rank update (first selection pass).
+__device__ inline uint64_t rank_score(const RankArgs& ra, uint64_t idx) {
+    const int32_t key = ra.touched[idx];
+    const uint32_t cnt = ra.req[key];
+    if (ra.last_req) ra.last_req[key] = cnt;
+    const int64_t old = ra.rank[key];
+    int64_t r = old < 0 ? (int64_t)ra.frame + (int64_t)cnt - 1 : old + (int64_t)cnt;
+    const int64_t cap = (int64_t)ra.frame + ra.window;
+    if (r > cap) r = cap;
+    ra.rank[key] = r;
+    ra.req[key] = 0u;
+    const uint64_t low = 0xFFFFFFFFull - (uint64_t)(uint32_t)key;
+    return ra.ranking ? (((uint64_t)r << 32) | low) : low;
+}
+
+// One tournament pass: workgroup b sorts its elements [b*2048, (b+1)*2048)
+// of the pass input in descending order and writes the best k to
+// out[b*k ...].  The number of live input elements of pass p follows from
+// the device count of pass 0 (each pass keeps k per 2048), so empty
+// workgroups return at once and partial ones sort only a power of two
+// covering their elements.  Sources of pass 0: a score array, the LRU order
+// of the slots [0, count) scored ~(last_used << 32 | slot), or the touched
+// bricks ranked on the fly.  The final pass may also publish the request
+// list (select epilogue).
+__global__ __launch_bounds__(256) void k_topk(TopkArgs a) {
     __shared__ uint64_t s[kTopkChunk];
-    if (gate && *gate == 0u) return;
-    uint32_t count = count_cap;
-    if (count_dev && *count_dev < count) count = *count_dev;
+    __shared__ uint32_t nsel;
+    if (a.gate && *a.gate == 0u) return;
+    uint64_t c = a.cap0;
+    if (a.count_dev && (uint64_t)*a.count_dev < c) c = *a.count_dev;
+    for (int q = 0; q < a.pass; ++q) c = ((c + kTopkChunk - 1) / kTopkChunk) * (uint64_t)a.k;
     const uint64_t base = (uint64_t)blockIdx.x * kTopkChunk;
-    for (int e = threadIdx.x; e < kTopkChunk; e += 256) {
+    if (base >= c && blockIdx.x > 0) return;
+    const uint32_t have = base >= c ? 0u : (uint32_t)(c - base < kTopkChunk ? c - base : kTopkChunk);
+    uint32_t m = 1;
+    while (m < have) m <<= 1;
+    for (uint32_t e = threadIdx.x; e < m; e += 256) {
         const uint64_t idx = base + e;
         uint64_t v = 0ull;
-        if (idx < count) {
-            if (lru_last_used)
-                v = ~(((uint64_t)(uint32_t)lru_last_used[idx] << 32) | (uint64_t)idx);
+        if (e < have) {
+            if (a.pass == 0 && a.mode == TOPK_LRU)
+                v = ~(((uint64_t)(uint32_t)a.lru_last_used[idx] << 32) | idx);
+            else if (a.pass == 0 && a.mode == TOPK_RANK)
+                v = rank_score(a.ra, idx);
             else
-                v = in[idx];
+                v = a.in[idx];
         }
         s[e] = v;
     }
     __syncthreads();
-    for (int len = 2; len <= kTopkChunk; len <<= 1) {
-        for (int j = len >> 1; j > 0; j >>= 1) {
-            for (int e = threadIdx.x; e < kTopkChunk; e += 256) {
-                const int x = e ^ j;
+    for (uint32_t len = 2; len <= m; len <<= 1) {
+        for (uint32_t j = len >> 1; j > 0; j >>= 1) {
+            for (uint32_t e = threadIdx.x; e < m; e += 256) {
+                const uint32_t x = e ^ j;
                 if (x > e) {
-                    const uint64_t a = s[e], b = s[x];
+                    const uint64_t p = s[e], q = s[x];
                     const bool desc = (e & len) == 0;
-                    if (desc ? (a < b) : (a > b)) {
-                        s[e] = b;
-                        s[x] = a;
+                    if (desc ? (p < q) : (p > q)) {
+                        s[e] = q;
+                        s[x] = p;
                     }
                 }
             }
             __syncthreads();
         }
     }
-    for (int e = threadIdx.x; e < k; e += 256) out[(uint64_t)blockIdx.x * k + e] = s[e];
-}
-
-// Request list from the final selection; free-slot and eviction counts.
-__global__ void k_cm_select(CacheDev c) {
-    const int32_t lim = c.max_requests < c.pool_bricks ? c.max_requests : c.pool_bricks;
-    __shared__ uint32_t nsel;
-    if (threadIdx.x == 0) nsel = 0u;
-    __syncthreads();
-    for (int32_t t = threadIdx.x; t < lim; t += blockDim.x) {
-        const uint64_t v = c.sel[t];
-        if (v != 0ull) {
-            c.ins_keys[t] = (int32_t)(0xFFFFFFFFull - (v & 0xFFFFFFFFull));
-            atomicAdd(&nsel, 1u);
+    for (int32_t e = threadIdx.x; e < a.k; e += 256)
+        a.out[(uint64_t)blockIdx.x * a.k + e] = (uint32_t)e < m ? s[e] : 0ull;
+    if (a.sel.ctr) {
+        // request list: keys of the non-zero scores, best first
+        if (threadIdx.x == 0) nsel = 0u;
+        __syncthreads();
+        for (int32_t t = threadIdx.x; t < a.sel.lim; t += 256) {
+            const uint64_t v = (uint32_t)t < m ? s[t] : 0ull;
+            if (v != 0ull) {
+                a.sel.ins_keys[t] = (int32_t)(0xFFFFFFFFull - (v & 0xFFFFFFFFull));
+                atomicAdd(&nsel, 1u);
+            }
         }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        CacheCtr* ctr = c.ctr;
-        const uint32_t n_free = (uint32_t)c.pool_bricks - ctr->n_used;
-        ctr->n_sel = nsel;
-        ctr->n_free = n_free;
-        ctr->need_evict = nsel > n_free ? nsel - n_free : 0u;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            CacheCtr* ctr = a.sel.ctr;
+            const uint32_t n_free = (uint32_t)a.sel.pool_bricks - ctr->n_used;
+            ctr->n_sel = nsel;
+            ctr->n_free = n_free;
+            ctr->need_evict = nsel > n_free ? nsel - n_free : 0u;
+        }
     }
 }
 
@@ -136,7 +143,7 @@ __global__ void k_prefill_setup(CacheDev c, const int32_t* keys, int32_t n) {
     }
 }
 
-__global__ void k_insert(CacheDev c, CacheGeom g, int32_t stamp) {
+__global__ void k_insert(CacheDev c, CacheGeom g, int32_t stamp, int32_t finish_inline) {
     const CacheCtr ctr = *c.ctr;
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ctr.n_sel; t += gridDim.x * blockDim.x) {
         const int32_t key = c.ins_keys[t];
@@ -177,6 +184,14 @@ __global__ void k_insert(CacheDev c, CacheGeom g, int32_t stamp) {
             r[3] = key;
         }
     }
+    if (finish_inline) {  // single-workgroup launch: update the counters here
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const uint32_t filled = ctr.n_sel < ctr.n_free ? ctr.n_sel : ctr.n_free;
+            c.ctr->n_used = ctr.n_used + filled;
+            c.ctr->n_evlog = ctr.n_evlog + ctr.n_sel;
+        }
+    }
 }
 
 __global__ void k_insert_finish(CacheDev c) {
@@ -186,10 +201,6 @@ __global__ void k_insert_finish(CacheDev c) {
         ctr->n_used += filled;
         ctr->n_evlog += ctr->n_sel;
     }
-}
-
-__global__ void k_touched_reset(CacheDev c) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) c.ctr->n_touched = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -209,28 +220,19 @@ hipError_t launch_clear_last_req(const CacheDev& c, int64_t n_keys, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_cm_rank(const CacheDev& c, int32_t frame, int64_t cap, hipStream_t s) {
-    int64_t b = (cap + 255) / 256;
-    b = b < 1 ? 1 : (b > 1024 ? 1024 : b);
-    hipLaunchKernelGGL(k_cm_rank, dim3((unsigned)b), dim3(256), 0, s, c, frame);
-    return hipGetLastError();
-}
-
-hipError_t launch_topk(const uint64_t* in, const uint32_t* count_dev, const TopkPlan& plan, int k, uint64_t* buf0,
-                       uint64_t* buf1, uint64_t* final_out, const uint32_t* gate, const int32_t* lru_last_used,
-                       hipStream_t s) {
-    const uint64_t* src = in;
+hipError_t launch_topk(const TopkArgs& base, const TopkPlan& plan, uint64_t* buf0, uint64_t* buf1, uint64_t* final_out,
+                       const SelectArgs* epilogue, hipStream_t s) {
+    const uint64_t* src = base.in;
     for (int p = 0; p < plan.n_pass; ++p) {
-        uint64_t* dst = (p + 1 == plan.n_pass) ? final_out : ((p & 1) ? buf1 : buf0);
-        hipLaunchKernelGGL(k_topk, dim3(plan.blocks[p]), dim3(256), 0, s, src, p == 0 ? count_dev : nullptr,
-                           plan.count[p], dst, k, gate, p == 0 ? lru_last_used : nullptr);
-        src = dst;
+        TopkArgs a = base;
+        a.pass = p;
+        a.in = src;
+        const bool last = p + 1 == plan.n_pass;
+        a.out = last ? final_out : ((p & 1) ? buf1 : buf0);
+        a.sel = (last && epilogue) ? *epilogue : SelectArgs{};
+        hipLaunchKernelGGL(k_topk, dim3(plan.blocks[p]), dim3(256), 0, s, a);
+        src = a.out;
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_cm_select(const CacheDev& c, hipStream_t s) {
-    hipLaunchKernelGGL(k_cm_select, dim3(1), dim3(1024), 0, s, c);
     return hipGetLastError();
 }
 
@@ -242,15 +244,14 @@ hipError_t launch_prefill_setup(const CacheDev& c, const int32_t* keys, int32_t 
 }
 
 hipError_t launch_insert(const CacheDev& c, const CacheGeom& g, int32_t stamp, int32_t cap, hipStream_t s) {
+    if (cap <= 256) {
+        hipLaunchKernelGGL(k_insert, dim3(1), dim3(256), 0, s, c, g, stamp, 1);
+        return hipGetLastError();
+    }
     int b = (cap + 255) / 256;
-    b = b < 1 ? 1 : (b > 1024 ? 1024 : b);
-    hipLaunchKernelGGL(k_insert, dim3(b), dim3(256), 0, s, c, g, stamp);
+    b = b > 1024 ? 1024 : b;
+    hipLaunchKernelGGL(k_insert, dim3(b), dim3(256), 0, s, c, g, stamp, 0);
     hipLaunchKernelGGL(k_insert_finish, dim3(1), dim3(64), 0, s, c);
-    return hipGetLastError();
-}
-
-hipError_t launch_touched_reset(const CacheDev& c, hipStream_t s) {
-    hipLaunchKernelGGL(k_touched_reset, dim3(1), dim3(64), 0, s, c);
     return hipGetLastError();
 }
 

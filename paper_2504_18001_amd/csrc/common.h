@@ -37,6 +37,28 @@ struct InrDev {
     int32_t in, hidden;            // widths[0], hidden width
 };
 
+// Exact unsigned division by a frame-invariant divisor d >= 1 for dividends
+// n < 2^31: q = umulhi(n, ceil(2^(32+s)/d)) >> s with 2^s <= d < 2^(s+1)
+// (the rounding error of the multiplier stays below one quotient step for
+// n < 2^31); powers of two use a shift (mul = 0).
+struct FastDiv {
+    uint32_t mul;
+    uint32_t shift;
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+    uint32_t s = 0;
+    while ((2u << s) <= d && s < 31) ++s;  // 2^s <= d < 2^(s+1)
+    if ((d & (d - 1)) == 0) return FastDiv{0u, s};
+    const unsigned __int128 num = (unsigned __int128)1 << (32 + s);
+    const uint64_t m = (uint64_t)((num + d - 1) / d);
+    return FastDiv{(uint32_t)m, s};
+}
+
+__device__ inline uint32_t fast_div(uint32_t n, FastDiv f) {
+    return f.mul ? (__umulhi(n, f.mul) >> f.shift) : (n >> f.shift);
+}
+
 // LoD lattice / brick geometry (Section 4.3.2).
 struct LodGeom {
     int32_t K[3];    // lattice points per axis
@@ -46,6 +68,7 @@ struct LodGeom {
 
 struct CacheGeom {
     int32_t brick;
+    FastDiv div_b1;  // division by brick - 1
     int32_t n_lods;
     LodGeom lod[kMaxLods];
     int64_t n_keys;
@@ -68,6 +91,23 @@ __device__ inline int64_t wave_append(bool pred, uint32_t* counter) {
     if (lane_id() == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
     base = __shfl(base, leader);
     return (int64_t)base + rank;
+}
+
+// Reserves n consecutive entries per lane of a list with one atomic per wave
+// and returns this lane's first index.  All 64 lanes must call it together
+// (lanes with nothing to add pass n = 0).
+__device__ inline uint32_t wave_reserve(uint32_t n, uint32_t* counter) {
+    uint32_t incl = n;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t v = __shfl_up(incl, o);
+        if (lane_id() >= o) incl += v;
+    }
+    const uint32_t total = __shfl(incl, 63);
+    uint32_t base = 0;
+    if (lane_id() == 63 && total) base = atomicAdd(counter, total);
+    base = __shfl(base, 63);
+    return base + incl - n;
 }
 
 // Wave-aggregated 64-bit counter increment.

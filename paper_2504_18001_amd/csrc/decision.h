@@ -151,7 +151,7 @@ __device__ inline BrickAddr brick_addr(const CacheGeom& g, int32_t L, const floa
         const float q = p[a] * sc;
         int32_t j = (int32_t)q;
         if (j > lg.K[a] - 2) j = lg.K[a] - 2;
-        b[a] = j / B1;
+        b[a] = (int32_t)fast_div((uint32_t)j, g.div_b1);
         r.lj[a] = j - b[a] * B1;
         r.frac[a] = q - (float)j;
     }

@@ -72,7 +72,10 @@ struct FrameDev {
     int32_t lod_floor;
     int32_t S;
     int32_t mode;
+    int32_t xcd_bands;  // image bands per XCD in the march kernel's work split
+    int32_t pipe;       // samples fetched ahead per ray in the march kernel
     int32_t mc_N;
+    FastDiv div_mc;  // division by mc_N
     int32_t M[3];
     const uint8_t* flags;  // nullable
     CacheGeom geo;
@@ -124,25 +127,50 @@ inline TopkPlan make_topk_plan(int64_t cap, int k) {
     return p;
 }
 
+enum TopkMode : int32_t { TOPK_SCORES = 0, TOPK_LRU = 1, TOPK_RANK = 2 };
+
+struct RankArgs {
+    const int32_t* touched;
+    uint32_t* req;
+    uint32_t* last_req;  // nullable
+    int64_t* rank;
+    int32_t frame, window, ranking;
+};
+
+struct SelectArgs {
+    int32_t* ins_keys;
+    CacheCtr* ctr;  // null: no epilogue
+    int32_t pool_bricks, lim;
+};
+
+struct TopkArgs {
+    const uint64_t* in;
+    const uint32_t* count_dev;  // live elements of pass 0 (nullable)
+    uint64_t cap0;              // capacity of pass 0
+    int32_t pass;
+    uint64_t* out;
+    int32_t k;
+    const uint32_t* gate;       // nullable: skip when *gate == 0
+    int32_t mode;               // TopkMode of pass 0
+    const int32_t* lru_last_used;
+    RankArgs ra;
+    SelectArgs sel;
+};
+
 // render.cpp launchers
 hipError_t launch_frame_begin(const FrameDev& f, int32_t n_iter_ctr, const uint8_t* flags_out, const float* minmax,
                               int64_t n_cells, CacheCtr* cctr, hipStream_t s);
-hipError_t launch_raygen(const FrameDev& f, hipStream_t s);
 hipError_t launch_march(const FrameDev& f, int it, int64_t cap_rays, hipStream_t s);
 hipError_t launch_shade(const FrameDev& f, int it, int64_t cap_rays, hipStream_t s);
-hipError_t launch_frame_end(const FrameDev& f, int n_iters, const CacheCtr* cctr, hipStream_t s);
+hipError_t launch_frame_end(const FrameDev& f, int n_iters, CacheCtr* cctr, hipStream_t s);
 
 // cache launchers
 hipError_t launch_cache_init(const CacheDev& c, int64_t n_keys, hipStream_t s);
-hipError_t launch_cm_rank(const CacheDev& c, int32_t frame, int64_t cap, hipStream_t s);
-hipError_t launch_topk(const uint64_t* in, const uint32_t* count_dev, const TopkPlan& plan, int k, uint64_t* buf0,
-                       uint64_t* buf1, uint64_t* final_out, const uint32_t* gate, const int32_t* lru_last_used,
-                       hipStream_t s);
-hipError_t launch_cm_select(const CacheDev& c, hipStream_t s);
+hipError_t launch_topk(const TopkArgs& base, const TopkPlan& plan, uint64_t* buf0, uint64_t* buf1, uint64_t* final_out,
+                       const SelectArgs* epilogue, hipStream_t s);
 hipError_t launch_prefill_setup(const CacheDev& c, const int32_t* keys, int32_t n, hipStream_t s);
 hipError_t launch_insert(const CacheDev& c, const CacheGeom& g, int32_t stamp, int32_t cap, hipStream_t s);
 hipError_t launch_clear_last_req(const CacheDev& c, int64_t n_keys, hipStream_t s);
-hipError_t launch_touched_reset(const CacheDev& c, hipStream_t s);
 
 // inr.hip launchers
 bool inr_shape_supported(const InrDev& m);

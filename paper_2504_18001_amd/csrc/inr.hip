@@ -262,6 +262,7 @@ static hipError_t dispatch_prec(int prec, int what, const InrDev& m, const void*
         case CINR_F32: return launch_all<EngCfg<NL, F, H, CINR_F32>>(what, m, a, s);
         case CINR_BF16: return launch_all<EngCfg<NL, F, H, CINR_BF16>>(what, m, a, s);
         case CINR_F16: return launch_all<EngCfg<NL, F, H, CINR_F16>>(what, m, a, s);
+        case CINR_BF16X3: return launch_all<EngCfg<NL, F, H, CINR_BF16X3>>(what, m, a, s);
         default: return hipErrorInvalidValue;
     }
 }

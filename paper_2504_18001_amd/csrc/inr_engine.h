@@ -23,11 +23,21 @@ template <>
 struct Half<CINR_BF16> {
     typedef __bf16 T;
     typedef bf16x8 V8;
+    static constexpr bool kSplit = false;
+};
+// BF16 with split operands: x = hi + lo (both BF16), products hi*hi + hi*lo
+// + lo*hi accumulated in FP32 -- about 16 significant bits per operand.
+template <>
+struct Half<CINR_BF16X3> {
+    typedef __bf16 T;
+    typedef bf16x8 V8;
+    static constexpr bool kSplit = true;
 };
 template <>
 struct Half<CINR_F16> {
     typedef _Float16 T;
     typedef f16x8 V8;
+    static constexpr bool kSplit = false;
 };
 
 __device__ inline f32x4 mfma_k32(bf16x8 a, bf16x8 b, f32x4 c) {
@@ -248,16 +258,22 @@ struct InrEngine<Cfg, false> {
     static constexpr int NL = Cfg::NL, F = Cfg::F, IN = Cfg::IN, H = Cfg::H, MT = Cfg::MT;
     typedef typename Half<Cfg::PREC>::T T;
     typedef typename Half<Cfg::PREC>::V8 V8;
+    static constexpr bool SPLIT = Half<Cfg::PREC>::kSplit;
+    static constexpr int NP = SPLIT ? 2 : 1;  // operand parts (hi, lo)
     static constexpr int KC = (IN + 31) / 32;
     static constexpr int KC2 = H / 32;
     static constexpr int ROW = KC * 32 + 8;  // padded row in 16-bit elements (16-byte aligned)
     static_assert(H % 32 == 0, "hidden width must be a multiple of 32");
     struct Lds {
-        T f[kBlock * ROW];
+        T f[NP][kBlock * ROW];
     };
-    V8 w1[MT][KC];
-    V8 w2[MT][KC2];
+    V8 w1[NP][MT][KC];
+    V8 w2[NP][MT][KC2];
     float w3[MT][4];
+
+    // x = hi + lo with both parts representable in T
+    __device__ static inline T part_hi(float x) { return (T)x; }
+    __device__ static inline T part_lo(float x) { return (T)(x - (float)(T)x); }
 
     __device__ void load_weights(const InrDev& m) {
         const int lane = threadIdx.x & 63, row = lane & 15, g = lane >> 4;
@@ -271,13 +287,18 @@ struct InrEngine<Cfg, false> {
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
                     const int k = 32 * c + 8 * g + j;
-                    w1[t][c][j] = (T)(k < IN ? W1[(16 * t + row) * IN + k] : 0.0f);
+                    const float x = k < IN ? W1[(16 * t + row) * IN + k] : 0.0f;
+                    w1[0][t][c][j] = part_hi(x);
+                    if (SPLIT) w1[NP - 1][t][c][j] = part_lo(x);
                 }
 #pragma unroll
             for (int c = 0; c < KC2; ++c)
 #pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    w2[t][c][j] = (T)W2[(16 * t + row) * H + 32 * c + 16 * (j >> 2) + 4 * g + (j & 3)];
+                for (int j = 0; j < 8; ++j) {
+                    const float x = W2[(16 * t + row) * H + 32 * c + 16 * (j >> 2) + 4 * g + (j & 3)];
+                    w2[0][t][c][j] = part_hi(x);
+                    if (SPLIT) w2[NP - 1][t][c][j] = part_lo(x);
+                }
 #pragma unroll
             for (int r = 0; r < 4; ++r) w3[t][r] = W3[16 * t + 4 * g + r];
         }
@@ -287,44 +308,67 @@ struct InrEngine<Cfg, false> {
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, row = lane & 15, g = lane >> 4;
         double u[3];
         to_unit(m, x, u);
-        T* my = lds.f + threadIdx.x * ROW;
+        T* my = lds.f[0] + threadIdx.x * ROW;
+        T* my_lo = lds.f[NP - 1] + threadIdx.x * ROW;
 #pragma unroll 2
         for (int l = 0; l < NL; ++l) {
             float f[F];
             encode_level<F>(m.lv[l], m.table, u, f);
 #pragma unroll
-            for (int j = 0; j < F; ++j) my[l * F + j] = (T)f[j];
+            for (int j = 0; j < F; ++j) {
+                my[l * F + j] = part_hi(f[j]);
+                if (SPLIT) my_lo[l * F + j] = part_lo(f[j]);
+            }
         }
         // zero padding of the K chunk past the input width
 #pragma unroll
-        for (int k = IN; k < KC * 32; ++k) my[k] = (T)0.0f;
+        for (int k = IN; k < KC * 32; ++k) {
+            my[k] = (T)0.0f;
+            my_lo[k] = (T)0.0f;
+        }
         __syncthreads();
         float my_y = 0.0f;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const T* pr = lds.f + (wave * 64 + 16 * t + row) * ROW;
+            const int pr = (wave * 64 + 16 * t + row) * ROW;
             f32x4 h1[MT];
 #pragma unroll
             for (int i = 0; i < MT; ++i) h1[i] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int c = 0; c < KC; ++c) {
-                const V8 b = *reinterpret_cast<const V8*>(pr + 32 * c + 8 * g);
+                const V8 b = *reinterpret_cast<const V8*>(lds.f[0] + pr + 32 * c + 8 * g);
 #pragma unroll
-                for (int i = 0; i < MT; ++i) h1[i] = mfma_k32(w1[i][c], b, h1[i]);
+                for (int i = 0; i < MT; ++i) h1[i] = mfma_k32(w1[0][i][c], b, h1[i]);
+                if (SPLIT) {
+                    const V8 bl = *reinterpret_cast<const V8*>(lds.f[NP - 1] + pr + 32 * c + 8 * g);
+#pragma unroll
+                    for (int i = 0; i < MT; ++i) {
+                        h1[i] = mfma_k32(w1[0][i][c], bl, h1[i]);
+                        h1[i] = mfma_k32(w1[NP - 1][i][c], b, h1[i]);
+                    }
+                }
             }
             f32x4 h2[MT];
 #pragma unroll
             for (int i = 0; i < MT; ++i) h2[i] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int c = 0; c < KC2; ++c) {
-                V8 b;
+                V8 b, bl = {};
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
-                    const float h = h1[2 * c + (j >> 2)][j & 3];
-                    b[j] = (T)(h > 0.0f ? h : 0.0f);
+                    float h = h1[2 * c + (j >> 2)][j & 3];
+                    h = h > 0.0f ? h : 0.0f;
+                    b[j] = part_hi(h);
+                    if (SPLIT) bl[j] = part_lo(h);
                 }
 #pragma unroll
-                for (int i = 0; i < MT; ++i) h2[i] = mfma_k32(w2[i][c], b, h2[i]);
+                for (int i = 0; i < MT; ++i) {
+                    h2[i] = mfma_k32(w2[0][i][c], b, h2[i]);
+                    if (SPLIT) {
+                        h2[i] = mfma_k32(w2[0][i][c], bl, h2[i]);
+                        h2[i] = mfma_k32(w2[NP - 1][i][c], b, h2[i]);
+                    }
+                }
             }
             float part = 0.0f;
 #pragma unroll

@@ -13,6 +13,7 @@
 
 namespace cinr {
 
+
 struct SampleRes {
     int32_t status;
     int32_t slot;
@@ -20,9 +21,33 @@ struct SampleRes {
     float value;
 };
 
+// The two most recent page-table lookups of a ray.  Residency is constant
+// within a frame, so a repeated key (consecutive samples in the same brick)
+// needs no reload.
+struct SlotCache {
+    int32_t k0 = -1, s0 = -1, k1 = -1, s1 = -1;
+    __device__ int32_t lookup(const int32_t* pt, int32_t key) {
+        if (key == k0) return s0;
+        if (key == k1) {
+            const int32_t tk = k0, ts = s0;
+            k0 = k1;
+            s0 = s1;
+            k1 = tk;
+            s1 = ts;
+            return s0;
+        }
+        const int32_t v = pt[key];
+        k1 = k0;
+        s1 = s0;
+        k0 = key;
+        s0 = v;
+        return v;
+    }
+};
+
 // Sampler of Algorithm 2 for one position: macro-cell skip, stochastic LoD,
 // page-table lookup at that LoD and every coarser one, trilinear fetch.
-__device__ inline SampleRes sample_cache(const FrameDev& f, const float p[3]) {
+__device__ inline SampleRes sample_cache(const FrameDev& f, const float p[3], SlotCache& sc) {
     SampleRes s;
     s.slot = -1;
     s.req_key = -1;
@@ -31,7 +56,7 @@ __device__ inline SampleRes sample_cache(const FrameDev& f, const float p[3]) {
         int32_t ci[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            ci[a] = (int32_t)p[a] / f.mc_N;
+            ci[a] = (int32_t)fast_div((uint32_t)(int32_t)p[a], f.div_mc);
             if (ci[a] > f.M[a] - 1) ci[a] = f.M[a] - 1;
         }
         if (!f.flags[((int64_t)ci[2] * f.M[1] + ci[1]) * f.M[0] + ci[0]]) {
@@ -47,7 +72,7 @@ __device__ inline SampleRes sample_cache(const FrameDev& f, const float p[3]) {
     for (int32_t Lp = L; Lp < nl; ++Lp) {
         const BrickAddr a = brick_addr(f.geo, Lp, p);
         if (Lp == L) s.req_key = a.key;
-        const int32_t slot = f.pt[a.key];
+        const int32_t slot = sc.lookup(f.pt, (int32_t)a.key);
         if (slot < 0) continue;
         const float* br = f.pool + (int64_t)slot * (B * B * B) + ((int64_t)a.lj[2] * B + a.lj[1]) * B + a.lj[0];
         const int32_t B2 = B * B;
@@ -81,7 +106,8 @@ __device__ inline void composite(float4& acc, float v, const float4* tfs, float 
     const float bl = __builtin_fmaf(t, b.z - a.z, a.z);
     float al = __builtin_fmaf(t, b.w - a.w, a.w);
     al = al < 0.0f ? 0.0f : (al > 1.0f ? 1.0f : al);
-    const float ac = 1.0f - exp2f(step * log2f(1.0f - al));
+    // value plane: the hardware exp2/log2 (about 1 ulp) are accurate enough
+    const float ac = 1.0f - __builtin_amdgcn_exp2f(step * __builtin_amdgcn_logf(1.0f - al));
     const float w = (1.0f - acc.w) * ac;
     acc.x = __builtin_fmaf(w, r, acc.x);
     acc.y = __builtin_fmaf(w, g, acc.y);
@@ -113,7 +139,7 @@ __device__ inline void log_miss(const FrameDev& f, int32_t pix, int32_t k, const
 }
 
 struct Tally {
-    uint64_t samples = 0, hits = 0, fallbacks = 0, misses = 0, skipped = 0;
+    uint64_t rays = 0, samples = 0, hits = 0, fallbacks = 0, misses = 0, skipped = 0;
     __device__ void add(int32_t st) {
         ++samples;
         hits += st == S_HIT;
@@ -123,6 +149,7 @@ struct Tally {
     }
     // all 64 lanes of the wave must call this together
     __device__ void commit(unsigned long long* stats) {
+        wave_add_u64(&stats[ST_RAYS], rays);
         wave_add_u64(&stats[ST_SAMPLES], samples);
         wave_add_u64(&stats[ST_HITS], hits);
         wave_add_u64(&stats[ST_FALLBACKS], fallbacks);
@@ -162,6 +189,9 @@ struct RayBook {
 
 __global__ __launch_bounds__(kBlock) void k_frame_begin(FrameDev f, int32_t n_ctr, uint8_t* flags,
                                                         const float* minmax, int64_t n_cells, CacheCtr* cctr) {
+    __shared__ float alpha[256];
+    alpha[threadIdx.x] = f.tf[4 * threadIdx.x + 3];
+    __syncthreads();
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (t < n_ctr) f.ctr[t] = IterCtr{0u, 0u, 0u, 0u};
     if (t < ST_COUNT) f.stats[t] = 0ull;
@@ -175,104 +205,150 @@ __global__ __launch_bounds__(kBlock) void k_frame_begin(FrameDev f, int32_t n_ct
         lo = lo < 0 ? 0 : lo;
         hi = hi > 255 ? 255 : hi;
         float mu = 0.0f;
-        for (int32_t r = lo; r <= hi; ++r) mu = f.tf[4 * r + 3] > mu ? f.tf[4 * r + 3] : mu;
+        for (int32_t r = lo; r <= hi; ++r) mu = alpha[r] > mu ? alpha[r] : mu;
         flags[t] = mu > 0.0f ? 1 : 0;
     }
 }
 
-// One thread per pixel, pixels enumerated in 8x8 tiles so that each wave
-// holds one tile; rays that hit the box are appended to the live list.
-__global__ __launch_bounds__(kBlock) void k_raygen(FrameDev f) {
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int32_t tiles_x = (f.cam.W + 7) / 8, tiles_y = (f.cam.H + 7) / 8;
-    const int64_t tile = t >> 6;
-    const int32_t w = (int32_t)(t & 63);
-    const int32_t tx = (int32_t)(tile % tiles_x), ty = (int32_t)(tile / tiles_x);
-    const int32_t i = tx * 8 + (w & 7), j = ty * 8 + (w >> 3);
-    const bool inside = ty < tiles_y && i < f.cam.W && j < f.cam.H;
-    bool active = false;
-    int32_t pix = 0;
-    if (inside) {
-        pix = j * f.cam.W + i;
-        float o[3], d[3], ts, te;
-        active = ray_setup(f.cam, f.vm1, i, j, o, d, ts, te);
-        f.rgba[pix] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (active) f.k_next[pix] = 0;
-    }
-    const int64_t slot = wave_append(active, &f.ctr[0].live);
-    if (active) f.live0[slot] = pix;
-    wave_add_u64(&f.stats[ST_RAYS], active ? 1ull : 0ull);
-}
-
-__global__ __launch_bounds__(kBlock) void k_march(FrameDev f, int32_t it) {
+// One thread per ray.  Iteration 0 walks all pixels in 8x8 tiles (one tile
+// per wave) and generates the rays itself; later iterations walk the list
+// of rays re-queued by k_shade.  Every lane of a wave runs the same number
+// of loop trips so that list reservations can be made per wave.
+template <int kPipe>
+__global__ __launch_bounds__(kBlock) void k_march(FrameDev f, int32_t it, uint32_t n0) {
     __shared__ float4 tfs[256];
     tfs[threadIdx.x] = reinterpret_cast<const float4*>(f.tf)[threadIdx.x];
     __syncthreads();
-    const uint32_t n = f.ctr[it].live;
+    const uint32_t n = it == 0 ? n0 : f.ctr[it].live;
     const int32_t* cur = (it & 1) ? f.live1 : f.live0;
-    // contiguous chunks of the live list per workgroup; consecutive chunks go
-    // to the same XCD (workgroups are dispatched round-robin over 8 XCDs)
+    // The ray list is cut into 8*bands contiguous bands; XCD x (workgroups are
+    // dispatched round-robin over the 8 XCDs) walks bands x, x+8, ...  Each
+    // band is a compact image region (locality in one XCD's L2) and every XCD
+    // gets bands from all over the image (balance).
     const uint32_t nb = gridDim.x;
-    const uint32_t lb = (blockIdx.x & 7u) * (nb >> 3) + (blockIdx.x >> 3);
+    const uint32_t bands = (uint32_t)f.xcd_bands;
+    const uint32_t bs = nb / (8u * bands);  // workgroups per band
+    const uint32_t x = blockIdx.x & 7u, i8 = blockIdx.x >> 3;
+    const uint32_t lb = (x + 8u * (i8 / bs)) * bs + (i8 % bs);
     const uint32_t per = (n + nb - 1) / nb;
     const uint32_t beg = lb * per;
     const uint32_t end = beg + per < n ? beg + per : n;
+    const int32_t tiles_x = (f.cam.W + 7) / 8;
     Tally tally;
     const int32_t S = f.S;
-    for (uint32_t r = beg + threadIdx.x; r < end; r += kBlock) {
-        const int32_t pix = cur[r];
-        const int32_t i = pix % f.cam.W, j = pix / f.cam.W;
-        float o[3], d[3], ts, te;
-        ray_setup(f.cam, f.vm1, i, j, o, d, ts, te);
-        int32_t k = f.k_next[pix];
-        float4 acc = f.rgba[pix];
-        RayBook book;
-        bool pend = false;
-        float p[3];
-        for (;;) {
-            if (!sample_pos(o, d, ts, te, f.step, k, f.vm1, p)) break;
-            const SampleRes s = sample_cache(f, p);
-            tally.add(s.status);
-            book.note(f, s);
-            if (s.status == S_MISS) {
-                pend = true;
-                break;
+    for (uint32_t r0 = beg; r0 < end; r0 += kBlock) {
+        const uint32_t r = r0 + threadIdx.x;
+        bool has = r < end;
+        int32_t pix = 0;
+        float o[3], d[3], ts = 0.0f, te = -1.0f;
+        if (has) {
+            int32_t i, j;
+            if (it == 0) {
+                const uint32_t tile = r >> 6, w = r & 63u;
+                i = (int32_t)(tile % (uint32_t)tiles_x) * 8 + (int32_t)(w & 7u);
+                j = (int32_t)(tile / (uint32_t)tiles_x) * 8 + (int32_t)(w >> 3);
+                has = i < f.cam.W && j < f.cam.H;
+            } else {
+                pix = cur[r];
+                i = pix % f.cam.W;
+                j = pix / f.cam.W;
             }
-            if (s.status != S_SKIP) composite(acc, s.value, tfs, f.step);
-            ++k;
-            if (f.ert_on && acc.w >= f.ert) break;
+            if (has) {
+                if (it == 0) pix = j * f.cam.W + i;
+                const bool hit = ray_setup(f.cam, f.vm1, i, j, o, d, ts, te);
+                if (it == 0) {
+                    if (!hit) f.rgba[pix] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    tally.rays += hit;
+                }
+                has = hit;
+            }
         }
-        if (pend) {
-            // gather a wavefront step of S samples starting at the miss
-            const int64_t pi = wave_append(true, &f.ctr[it].pending);
-            f.pend_pix[pi] = pix;
-            float* vb = f.vals + pi * S;
-            {
-                const int64_t mi = wave_append(true, &f.ctr[it].misses);
-                f.miss_rec[mi] = make_float4(p[0], p[1], p[2], __uint_as_float((uint32_t)(pi * S)));
-                log_miss(f, pix, k, p);
+        int32_t k = 0;
+        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (has && it > 0) {
+            k = f.k_next[pix];
+            acc = f.rgba[pix];
+        }
+        RayBook book;
+        SlotCache sc;
+        bool pend = false;
+        if (has) {
+            // Fast phase, software-pipelined: decide and fetch a group of
+            // kPipe samples, then commit them in order (bookkeeping,
+            // compositing, early termination).  Samples fetched past an early
+            // termination or a true miss are discarded without side effects.
+            float p[3];
+            bool run = true;
+            while (run) {
+                SampleRes grp[kPipe];
+                int32_t cnt = 0;
+#pragma unroll
+                for (int u = 0; u < kPipe; ++u) {
+                    if (cnt == u && sample_pos(o, d, ts, te, f.step, k + u, f.vm1, p)) {
+                        grp[u] = sample_cache(f, p, sc);
+                        ++cnt;
+                    }
+                }
+                if (cnt < kPipe) run = false;
+#pragma unroll
+                for (int u = 0; u < kPipe; ++u) {
+                    if (u >= cnt) break;
+                    const SampleRes& sr = grp[u];
+                    tally.add(sr.status);
+                    book.note(f, sr);
+                    if (sr.status == S_MISS) {
+                        pend = true;
+                        run = false;
+                        break;
+                    }
+                    if (sr.status != S_SKIP) composite(acc, sr.value, tfs, f.step);
+                    ++k;
+                    if (f.ert_on && acc.w >= f.ert) {
+                        run = false;
+                        break;
+                    }
+                }
             }
-            int32_t nc = 1;
+        }
+        // a wavefront step of S samples starting at the miss
+        const uint32_t pi = wave_reserve(pend ? 1u : 0u, &f.ctr[it].pending);
+        uint64_t mask = 0;
+        int32_t nc = 0;
+        if (pend) {
+            f.pend_pix[pi] = pix;
+            float* vb = f.vals + (int64_t)pi * S;
+            mask = 1;
+            nc = 1;
             while (nc < S) {
                 float q[3];
                 if (!sample_pos(o, d, ts, te, f.step, k + nc, f.vm1, q)) break;
-                const SampleRes s = sample_cache(f, q);
-                tally.add(s.status);
-                book.note(f, s);
-                if (s.status == S_MISS) {
-                    const int64_t mi = wave_append(true, &f.ctr[it].misses);
-                    f.miss_rec[mi] = make_float4(q[0], q[1], q[2], __uint_as_float((uint32_t)(pi * S + nc)));
-                    log_miss(f, pix, k + nc, q);
-                } else {
-                    vb[nc] = s.status == S_SKIP ? -1.0f : s.value;
-                }
+                const SampleRes sr = sample_cache(f, q, sc);
+                tally.add(sr.status);
+                book.note(f, sr);
+                if (sr.status == S_MISS)
+                    mask |= 1ull << nc;
+                else
+                    vb[nc] = sr.status == S_SKIP ? -1.0f : sr.value;
                 ++nc;
             }
             f.pend_n[pi] = nc;
             f.k_next[pix] = k;
         }
-        book.flush(f);
-        f.rgba[pix] = acc;
+        // true-miss records (position, destination slot), reserved per wave
+        uint32_t mb = wave_reserve((uint32_t)__popcll(mask), &f.ctr[it].misses);
+        if (pend) {
+            for (int32_t sidx = 0; sidx < nc; ++sidx) {
+                if (!((mask >> sidx) & 1ull)) continue;
+                float q[3];
+                sample_pos(o, d, ts, te, f.step, k + sidx, f.vm1, q);
+                f.miss_rec[mb++] = make_float4(q[0], q[1], q[2], __uint_as_float(pi * (uint32_t)S + (uint32_t)sidx));
+                log_miss(f, pix, k + sidx, q);
+            }
+        }
+        if (has) {
+            book.flush(f);
+            f.rgba[pix] = acc;
+        }
     }
     tally.commit(f.stats);
 }
@@ -315,13 +391,14 @@ __global__ __launch_bounds__(kBlock) void k_shade(FrameDev f, int32_t it) {
     }
 }
 
-__global__ void k_frame_end(FrameDev f, int32_t n_iters, const CacheCtr* cctr) {
+__global__ void k_frame_end(FrameDev f, int32_t n_iters, CacheCtr* cctr) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         f.stats[ST_ITERS] = (unsigned long long)n_iters;
         if (cctr) {
             f.stats[ST_REQUESTED] = cctr->n_touched;
             f.stats[ST_SELECTED] = cctr->n_sel;
             f.stats[ST_EVICTED] = cctr->need_evict;
+            cctr->n_touched = 0u;  // the next frame's requests start empty
         }
     }
 }
@@ -345,19 +422,22 @@ hipError_t launch_frame_begin(const FrameDev& f, int32_t n_iter_ctr, const uint8
     return hipGetLastError();
 }
 
-hipError_t launch_raygen(const FrameDev& f, hipStream_t s) {
-    const int64_t tiles = (int64_t)((f.cam.W + 7) / 8) * ((f.cam.H + 7) / 8);
-    hipLaunchKernelGGL(k_raygen, dim3((unsigned)((tiles * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, f);
-    return hipGetLastError();
-}
-
 hipError_t launch_march(const FrameDev& f, int it, int64_t cap_rays, hipStream_t s) {
-    // a multiple of 8 workgroups, at most 16 per CU
-    int64_t b = (cap_rays + kBlock - 1) / kBlock;
-    b = b < 8 ? 8 : b;
-    b = b > 4096 ? 4096 : b;
-    b = (b + 7) & ~7LL;
-    hipLaunchKernelGGL(k_march, dim3((unsigned)b), dim3(kBlock), 0, s, f, it);
+    // iteration 0 walks all pixels in 8x8 tiles, one workgroup per 256 pixels
+    const uint32_t n0 = (uint32_t)(((f.cam.W + 7) / 8) * ((f.cam.H + 7) / 8)) * 64u;
+    const int64_t cap = it == 0 ? (int64_t)n0 : cap_rays;
+    // a multiple of 8 * bands workgroups
+    const int64_t q = 8LL * f.xcd_bands;
+    int64_t b = (cap + kBlock - 1) / kBlock;
+    b = b > (1 << 20) ? (1 << 20) : b;
+    b = ((b + q - 1) / q) * q;
+    // kPipe: samples decided and fetched ahead in the fast phase
+    switch (f.pipe) {
+        case 1: hipLaunchKernelGGL(k_march<1>, dim3((unsigned)b), dim3(kBlock), 0, s, f, it, n0); break;
+        case 2: hipLaunchKernelGGL(k_march<2>, dim3((unsigned)b), dim3(kBlock), 0, s, f, it, n0); break;
+        case 8: hipLaunchKernelGGL(k_march<8>, dim3((unsigned)b), dim3(kBlock), 0, s, f, it, n0); break;
+        default: hipLaunchKernelGGL(k_march<4>, dim3((unsigned)b), dim3(kBlock), 0, s, f, it, n0); break;
+    }
     return hipGetLastError();
 }
 
@@ -366,7 +446,7 @@ hipError_t launch_shade(const FrameDev& f, int it, int64_t cap_rays, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_frame_end(const FrameDev& f, int n_iters, const CacheCtr* cctr, hipStream_t s) {
+hipError_t launch_frame_end(const FrameDev& f, int n_iters, CacheCtr* cctr, hipStream_t s) {
     hipLaunchKernelGGL(k_frame_end, dim3(1), dim3(64), 0, s, f, n_iters, cctr);
     return hipGetLastError();
 }

@@ -1,0 +1,186 @@
+"""Full-size parity: the 512^3 INR at 1920x1080, B = 16, 4 LoDs, 2 GiB pool,
+40 requests per frame, in the launch configuration bench.py times (BF16 MLP,
+S = 32, early termination at 0.999, default march tuning).
+
+The oracle cannot replay hundreds of 1080p frames, so these tests use
+properties that hold at any size and outputs it can compute one by one:
+ - frame 0 from an empty cache: every sample is a true miss, so the frame
+   equals the uncached INR rendering (invariant I1); sampled pixels are
+   compared with the oracle's pixel renderer;
+ - a seeded prefilled residency: sampled pixels against the oracle's
+   renderer on the same residency; in parity mode (no early termination,
+   FP32 MLP) the full per-brick request counts, the request list and the
+   page table after the frame are bit-exact against a full oracle frame;
+ - decoded bricks of the prefilled pool against oracle decoding.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2504_18001_amd import configs, synth
+from tests.helpers import inr_params, oracle_inr, value_range
+
+pytestmark = pytest.mark.gpu
+
+W = configs.HD512
+N_PIX = 3000
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2504_18001_amd import cinr
+    cinr.lib()
+
+
+@pytest.fixture(scope="module")
+def scene():
+    from oracle import oracle as O
+    from paper_2504_18001_amd import cinr
+    t, wts = inr_params(W.arch, 0)
+    s, o = value_range(W.arch, 0)
+    # macro-cells: a seeded table in which every cell is visible (the random
+    # INR spans [0, 1] in every cell), so the skip test runs on every sample
+    M = [(d + W.macro_cell - 1) // W.macro_cell for d in W.arch.dims]
+    mm = np.zeros((M[2], M[1], M[0], 2), np.float32)
+    mm[..., 1] = 1.0
+    vol = cinr.Volume(W.arch, t, wts, s, o, macrocells=mm, macro_cell=W.macro_cell)
+    m = O.OracleInr(W.arch, t, wts, s, o)
+    return vol, m, mm
+
+
+def _pixels(seed=0):
+    rng = np.random.default_rng(seed)
+    return rng.choice(W.width * W.height, size=N_PIX, replace=False).astype(np.int32)
+
+
+def _prefill_keys(off, seed=5):
+    rng = np.random.default_rng(seed)
+    keys = [np.arange(off[3], off[4])]
+    for L, frac in ((2, 0.3), (1, 0.03), (0, 0.003)):
+        n = off[L + 1] - off[L]
+        keys.append(off[L] + rng.choice(n, size=int(frac * n), replace=False))
+    return np.sort(np.concatenate(keys)).astype(np.int32)
+
+
+def _gpu_cache(vol, keep=False):
+    from paper_2504_18001_amd import cinr
+    cs = W.cache
+    return cinr.Cache(vol, cs.brick, cs.n_lods, cs.pool_bricks, cs.max_requests, preload_period=cs.preload_period,
+                      keep_request_counts=keep, evict_log_capacity=64)
+
+
+def _oracle_cache(m):
+    from oracle import oracle as O
+    cs = W.cache
+    return O.OracleCache(m, brick=cs.brick, n_lods=cs.n_lods, pool_bricks=cs.pool_bricks, max_requests=cs.max_requests,
+                         preload_period=cs.preload_period)
+
+
+def test_frame0_equals_uncached_inr_on_sampled_pixels(scene):
+    from oracle import oracle as O
+    from paper_2504_18001_amd import cinr
+    vol, m, mm = scene
+    cache = _gpu_cache(vol)
+    r = cinr.Renderer()
+    cam, tf = W.camera(0), W.tf(0)
+    img = r.render(vol, cam, tf, W.step, W.lod_scale, frame_index=0, seed=W.seed, ert_threshold=W.ert_threshold,
+                   samples_per_iter=W.samples_per_iter, mode=cinr.CACHED, dtype="bf16x3", cache=cache)
+    st = r.last_stats()
+    assert st["hits"] == st["fallbacks"] == 0 and st["misses"] > 0
+    px = _pixels(0)
+    got = img.reshape(-1, 4)[torch.from_numpy(px).long().cuda()].cpu().numpy().astype(np.float64)
+    p = O.make_params(W.step, W.lod_scale, seed=W.seed, frame_index=0, ert_threshold=W.ert_threshold,
+                      samples_per_iter=W.samples_per_iter, mode=O.UNCACHED_DIRECT, macro_cell=W.macro_cell,
+                      macro_minmax=mm)
+    ref = O.render_pixels(m, cam, tf, p, px)
+    err = np.abs(got - ref).max()
+    print("frame 0 bf16x3 max abs", err, "mean", np.abs(got - ref).mean())
+    assert err <= 8e-3
+
+
+def test_prefilled_fullsize_parity_mode_bit_exact_requests(scene):
+    from oracle import oracle as O
+    from paper_2504_18001_amd import cinr
+    vol, m, mm = scene
+    off = vol.geometry(W.cache.brick, W.cache.n_lods)[1]
+    keys = _prefill_keys(off)
+    cache = _gpu_cache(vol, keep=True)
+    cache.prefill(torch.from_numpy(keys).cuda(), stamp=0, dtype="f32")
+    oc = _oracle_cache(m)
+    oc.prefill(keys, 0)
+    # decoded pool: prefilled slot i holds key i, equal to the oracle's decoding
+    B = W.cache.brick
+    nb = vol.geometry(B, W.cache.n_lods)[0]
+    sl = np.sort(np.random.default_rng(1).choice(len(keys), size=64, replace=False))
+    reqs = []
+    for k in keys[sl]:
+        L = int(np.searchsorted(off, k, side="right") - 1)
+        loc = int(k - off[L])
+        reqs.append((L, loc % nb[L][0], (loc // nb[L][0]) % nb[L][1], loc // (nb[L][0] * nb[L][1])))
+    got = cache.pool.view(-1, B, B, B)[torch.from_numpy(sl).long().cuda()].cpu().numpy()
+    ref = m.decode_bricks(np.asarray(reqs, np.int32), B, W.cache.n_lods)
+    err = np.abs(got - ref).max()
+    print("pool max abs", err)
+    assert err <= 1e-4
+    np.testing.assert_array_equal(cache.dump(cinr.DUMP_SLOT_OWNER)[:len(keys)], keys)
+    f = 12  # pre-load released down to LoD 0
+    cam, tf = W.camera(f), W.tf(f)
+    r = cinr.Renderer()
+    img = r.render(vol, cam, tf, W.step, W.lod_scale, frame_index=f, seed=W.seed, ert_threshold=2.0,
+                   samples_per_iter=W.samples_per_iter, mode=cinr.CACHED, dtype="f32", cache=cache)
+    st = r.last_stats()
+    px = _pixels(1)
+    got = img.reshape(-1, 4)[torch.from_numpy(px).long().cuda()].cpu().numpy().astype(np.float64)
+    p = O.make_params(W.step, W.lod_scale, seed=W.seed, frame_index=f, ert_threshold=2.0,
+                      samples_per_iter=W.samples_per_iter, mode=O.CACHED, macro_cell=W.macro_cell, macro_minmax=mm)
+    ref = O.render_pixels(m, cam, tf, p, px, cache=oc)
+    err = np.abs(got - ref).max()
+    print("prefilled f32 parity-mode pixels max abs", err)
+    assert err <= 2e-3
+    # the whole frame's decisions: request counts, request list, page table
+    _, ost = oc.render(cam, tf, p)
+    for k in ("rays", "samples", "hits", "fallbacks", "misses", "requested", "selected"):
+        assert st[k] == ost[k], (k, st[k], ost[k])
+    np.testing.assert_array_equal(cache.dump(cinr.DUMP_REQ_COUNT), oc.req_count())
+    np.testing.assert_array_equal(cache.dump(cinr.DUMP_REQUEST_LIST), oc.request_list())
+    np.testing.assert_array_equal(cache.dump(cinr.DUMP_PAGE_TABLE), oc.page_table())
+    np.testing.assert_array_equal(cache.dump(cinr.DUMP_LAST_USED), oc.last_used())
+
+
+# Max abs RGBA bound per MLP precision on a frame of the random transfer
+# function (piecewise linear, slope up to 8 per unit value).  Plain BF16
+# carries 8 significant bits per operand (value errors up to about 6e-3), so
+# this transfer function amplifies them beyond the 8e-3 image bound; its
+# PSNR stays far above 45 dB.  Split BF16 and FP16 meet the bound.
+MAXABS = {"bf16x3": 8e-3, "f16": 8e-3, "bf16": 2.5e-2}
+
+
+@pytest.mark.parametrize("dtype", ["bf16x3", "f16", "bf16"])
+def test_prefilled_fullsize_bench_configuration_pixels(scene, dtype):
+    from oracle import oracle as O
+    from paper_2504_18001_amd import cinr
+    vol, m, mm = scene
+    off = vol.geometry(W.cache.brick, W.cache.n_lods)[1]
+    keys = _prefill_keys(off, seed=9)
+    cache = _gpu_cache(vol)
+    cache.prefill(torch.from_numpy(keys).cuda(), stamp=0, dtype=dtype)
+    oc = _oracle_cache(m)
+    oc.prefill(keys, 0)
+    f = 40  # random transfer function part of the orbit
+    cam, tf = W.camera(f), W.tf(f)
+    r = cinr.Renderer()
+    img = r.render(vol, cam, tf, W.step, W.lod_scale, frame_index=f, seed=W.seed, ert_threshold=W.ert_threshold,
+                   samples_per_iter=W.samples_per_iter, mode=cinr.CACHED, dtype=dtype, cache=cache)
+    px = _pixels(2)
+    got = img.reshape(-1, 4)[torch.from_numpy(px).long().cuda()].cpu().numpy().astype(np.float64)
+    p = O.make_params(W.step, W.lod_scale, seed=W.seed, frame_index=f, ert_threshold=W.ert_threshold,
+                      samples_per_iter=W.samples_per_iter, mode=O.CACHED, macro_cell=W.macro_cell, macro_minmax=mm)
+    ref = O.render_pixels(m, cam, tf, p, px, cache=oc)
+    d = np.abs(got - ref)
+    mse = float((d ** 2).mean())
+    psnr = 10 * np.log10(1.0 / mse) if mse > 0 else float("inf")
+    print(f"prefilled {dtype} bench-configuration pixels: max abs", d.max(), "PSNR", psnr)
+    assert d.max() <= MAXABS[dtype]
+    assert psnr >= 45.0

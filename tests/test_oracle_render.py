@@ -335,3 +335,22 @@ def test_macrocell_skip_is_exact_in_lattice_mode():
     b, sb = O.render_uncached(m, cam, tf, p1)
     assert sb["skipped"] > 0
     np.testing.assert_array_equal(a, b)
+
+
+def test_pixel_renderer_matches_full_frames():
+    m = oracle_inr(configs.ARCH_SMALL, 0)
+    w = configs.SMALL
+    cam = w.camera(1)
+    cam.width = cam.height = 40
+    px = np.arange(0, 1600, 7)
+    p = O.make_params(0.5, w.lod_scale, seed=3, frame_index=2, samples_per_iter=8, mode=O.UNCACHED_DIRECT)
+    full, _ = O.render_uncached(m, cam, w.tf(0), p)
+    np.testing.assert_array_equal(full.reshape(-1, 4)[px], O.render_pixels(m, cam, w.tf(0), p, px))
+    c = O.OracleCache(m, brick=8, n_lods=2, pool_bricks=400, max_requests=16)
+    c.prefill(np.arange(0, 854, 3), 0)
+    p.mode = O.CACHED
+    part = O.render_pixels(m, cam, w.tf(0), p, px, cache=c)
+    before = c.page_table().copy()
+    full, _ = c.render(cam, w.tf(0), p)
+    np.testing.assert_array_equal(full.reshape(-1, 4)[px], part)
+    assert np.array_equal(before[before >= 0], c.page_table()[before >= 0])
