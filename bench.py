@@ -186,8 +186,11 @@ def main():
     cache = new_cache(vol, w)
     r = cinr.Renderer()
     out = torch.empty((w.height, w.width, 4), dtype=torch.float32, device="cuda")
+    vol.set_timing(True)
     run_frames(r, vol, cams, tfs, w, range(Wm), cinr.CACHED, args.dtype, cache, out=out)
     torch.cuda.synchronize()
+    vol.set_timing(False)
+    warm_stages = vol.collect_timing()
     log("[bench] warm-up done")
     stats = torch.zeros((K, len(cinr.STAT_FIELDS)), dtype=torch.int64, device="cuda")
     vol.set_timing(True)
@@ -286,7 +289,8 @@ def main():
         "frame_totals": tot,
         "roofline": {"kernel": "k_march", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "launches": march_n, "avg_launch_ms": round(march_ms / max(march_n, 1), 5)},
+                     "launches": march_n, "avg_launch_ms": round(march_ms / max(march_n, 1), 5),
+                     "launches_before_timed": warm_stages["march"][1]},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

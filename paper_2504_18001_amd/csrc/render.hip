@@ -176,7 +176,9 @@ struct RayBook {
             }
         }
         if (s.slot >= 0 && s.slot != last_slot) {
-            f.last_used[s.slot] = f.frame;
+            // many rays stamp the same slot: store only if not yet stamped in
+            // this frame, so that the L2 does not serialise identical stores
+            if (f.last_used[s.slot] != f.frame) f.last_used[s.slot] = f.frame;
             last_slot = s.slot;
         }
     }
