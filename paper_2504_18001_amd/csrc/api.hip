@@ -423,7 +423,8 @@ struct RenderLayout {
     float* vals;
     float4* miss_rec;
     IterCtr* ctr;
-    uint8_t* flags;
+    uint32_t* claim;
+    uint64_t* flags;
     unsigned long long* stats;
 };
 
@@ -438,7 +439,8 @@ static size_t render_layout(int64_t npix, int32_t S, int64_t n_cells, RenderLayo
     x.vals = cv.take<float>((size_t)npix * S);
     x.miss_rec = cv.take<float4>((size_t)npix * S);
     x.ctr = cv.take<IterCtr>(kMaxIters + 2);
-    x.flags = cv.take<uint8_t>(n_cells);
+    x.claim = cv.take<uint32_t>(16 * kClaimStride);
+    x.flags = cv.take<uint64_t>((size_t)(n_cells + 63) / 64);
     x.stats = cv.take<unsigned long long>(ST_COUNT);
     if (r) *r = x;
     return cv.off;
@@ -531,6 +533,8 @@ extern "C" cinr_status cinr_render_frame(cinr_cache c, cinr_volume v, const cinr
     f.mc_N = v->desc.macrocell_size;
     f.div_mc = make_fastdiv((uint32_t)(f.mc_N > 0 ? f.mc_N : 1));
     f.flags = v->n_cells > 0 ? L.flags : nullptr;
+    f.flag_words = (int32_t)((v->n_cells + 63) / 64);
+    f.claim = L.claim;
     f.tf = d_tf;
     f.rgba = reinterpret_cast<float4*>(d_rgba);
     f.k_next = L.k_next;
@@ -576,22 +580,24 @@ extern "C" cinr_status cinr_render_frame(cinr_cache c, cinr_volume v, const cinr
     Timing& tm = v->timing;
     {
         StageTimer st_(tm, s, CINR_STAGE_SETUP);
-        HIP_TRY(launch_frame_begin(f, n_ctr, f.flags, v->desc.d_macrocells, v->n_cells, cctr, s));
+        HIP_TRY(launch_frame_begin(f, n_ctr, v->desc.d_macrocells, v->n_cells, cctr, s));
         if (cached && c->c.last_req) HIP_TRY(launch_clear_last_req(c->c, c->g.n_keys, s));
     }
     // wavefront iterations: march; stop when no ray gathered a step with a
     // true miss; otherwise infer the misses and composite the gathered steps
     int n_iters = 0;
+    int64_t queued = npix;  // rays iteration `it` may find re-queued (<= the previous iteration's pending steps)
     for (int it = 0; it < max_iters; ++it) {
         {
             StageTimer st_(tm, s, CINR_STAGE_MARCH);
-            HIP_TRY(launch_march(f, it, npix, s));
+            HIP_TRY(launch_march(f, it, queued, s));
         }
         n_iters = it + 1;
         HIP_TRY(hipMemcpyAsync(v->pinned, &f.ctr[it].pending, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipEventRecord(v->ev, s));
         HIP_TRY(hipEventSynchronize(v->ev));
-        if (*(volatile int32_t*)v->pinned == 0) break;
+        queued = *(volatile uint32_t*)v->pinned;
+        if (queued == 0) break;
         {
             StageTimer st_(tm, s, CINR_STAGE_INFER);
             HIP_TRY(inr_infer_misses(v->m, f.miss_rec, &f.ctr[it].misses, npix * S, f.vals, rp->mlp_dtype, s));

@@ -140,18 +140,18 @@ struct BrickAddr {
     float frac[3];
 };
 
-__device__ inline BrickAddr brick_addr(const CacheGeom& g, int32_t L, const float p[3]) {
+// `lg` is the geometry of LoD L, `div_b1` divides by brick - 1.
+__device__ inline BrickAddr brick_addr(const LodGeom& lg, int32_t brick, FastDiv div_b1, int32_t L, const float p[3]) {
     BrickAddr r;
-    const LodGeom& lg = g.lod[L];
     const float sc = __builtin_ldexpf(1.0f, -L);
-    const int32_t B1 = g.brick - 1;
+    const int32_t B1 = brick - 1;
     int32_t b[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const float q = p[a] * sc;
         int32_t j = (int32_t)q;
         if (j > lg.K[a] - 2) j = lg.K[a] - 2;
-        b[a] = (int32_t)fast_div((uint32_t)j, g.div_b1);
+        b[a] = (int32_t)fast_div((uint32_t)j, div_b1);
         r.lj[a] = j - b[a] * B1;
         r.frac[a] = q - (float)j;
     }

@@ -8,6 +8,7 @@
 namespace cinr {
 
 constexpr int kMaxIters = 8192;
+constexpr int kClaimStride = 64;  // words between work-unit counters (separate cache lines)
 
 enum : int32_t { S_HIT = 0, S_FALLBACK = 1, S_MISS = 2, S_SKIP = 3 };
 
@@ -77,7 +78,10 @@ struct FrameDev {
     int32_t mc_N;
     FastDiv div_mc;  // division by mc_N
     int32_t M[3];
-    const uint8_t* flags;  // nullable
+    uint64_t* flags;     // nullable: one bit per macro-cell, set when the cell is visible
+    int32_t flag_words;  // 64-bit words of `flags`
+    uint32_t* claim;     // [2][8] work-unit counters of the march kernel (one set per iteration
+                         // parity), kClaimStride words apart
     CacheGeom geo;
     // cache (null in the uncached mode)
     const int32_t* pt;
@@ -158,9 +162,13 @@ struct TopkArgs {
 };
 
 // render.cpp launchers
-hipError_t launch_frame_begin(const FrameDev& f, int32_t n_iter_ctr, const uint8_t* flags_out, const float* minmax,
-                              int64_t n_cells, CacheCtr* cctr, hipStream_t s);
-hipError_t launch_march(const FrameDev& f, int it, int64_t cap_rays, hipStream_t s);
+// Macro-cell flags are staged in LDS by the march kernel up to this many words
+// (131072 cells); larger grids are read from global memory.
+constexpr int kMaxLdsFlagWords = 2048;
+
+hipError_t launch_frame_begin(const FrameDev& f, int32_t n_iter_ctr, const float* minmax, int64_t n_cells,
+                              CacheCtr* cctr, hipStream_t s);
+hipError_t launch_march(const FrameDev& f, int it, int64_t max_rays, hipStream_t s);
 hipError_t launch_shade(const FrameDev& f, int it, int64_t cap_rays, hipStream_t s);
 hipError_t launch_frame_end(const FrameDev& f, int n_iters, CacheCtr* cctr, hipStream_t s);
 

@@ -1,14 +1,18 @@
 // Wavefront ray marching through the brick cache (Section 5.1 with the
 // sampler of Algorithms 1 and 2 and the fallback of Section 4.3).
 //
-// One frame is: raygen (box test, compaction of hitting rays in 8x8 pixel
-// tiles) -> iterations of { march, infer misses, shade } until no ray is live.
-// `march` runs one thread per ray and composites samples as they are served
-// by the cache; at the first true miss it switches to gathering a wavefront
-// step of S samples (the miss included) into a per-ray buffer, appending
-// true-miss records with one atomic per wave.  The INR then infers all misses
-// in one batch (Algorithm 1), and `shade` composites the gathered samples in
-// order, re-queueing unfinished rays for the next iteration.
+// One frame is: iterations of { march, infer misses, shade } until no ray has
+// a deferred step.  `march` is a persistent kernel: every lane owns one ray at
+// a time and composites samples as the cache serves them; lanes whose ray has
+// ended are refilled from work units (8x8 pixel tiles in the first iteration,
+// runs of 64 re-queued rays later) claimed from per-XCD counters.  At the
+// first true miss a ray gathers a wavefront step of S samples (the miss
+// included) into a per-ray buffer and appends true-miss records, with one
+// atomic per wave for each list.  The INR then infers all misses in one batch
+// (Algorithm 1), and `shade` composites the gathered samples in order,
+// re-queueing unfinished rays for the next iteration.
+#include <type_traits>
+
 #include "frame.h"
 
 namespace cinr {
@@ -45,34 +49,54 @@ struct SlotCache {
     }
 };
 
+// Macro-cell flags, staged in LDS or read from global memory.
+struct LdsFlags {
+    const uint64_t* w;
+    __device__ bool get(uint32_t cell) const { return (w[cell >> 6] >> (cell & 63u)) & 1ull; }
+};
+struct GlobalFlags {
+    const uint64_t* w;
+    __device__ bool get(uint32_t cell) const { return (w[cell >> 6] >> (cell & 63u)) & 1ull; }
+};
+
 // Sampler of Algorithm 2 for one position: macro-cell skip, stochastic LoD,
-// page-table lookup at that LoD and every coarser one, trilinear fetch.
-__device__ inline SampleRes sample_cache(const FrameDev& f, const float p[3], SlotCache& sc) {
+// page-table lookup at that LoD and every coarser one, trilinear fetch.  The
+// flag read and the first page-table read are issued together; a skipped
+// sample discards the lookup.
+template <class Flags>
+__device__ inline SampleRes sample_cache(const FrameDev& f, const LodGeom* lg, const Flags& fl, const float p[3],
+                                         SlotCache& sc) {
     SampleRes s;
     s.slot = -1;
     s.req_key = -1;
     s.value = 0.0f;
+    bool live = true;
     if (f.flags) {
-        int32_t ci[3];
+        uint32_t ci[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            ci[a] = (int32_t)fast_div((uint32_t)(int32_t)p[a], f.div_mc);
-            if (ci[a] > f.M[a] - 1) ci[a] = f.M[a] - 1;
+            ci[a] = fast_div((uint32_t)(int32_t)p[a], f.div_mc);
+            if (ci[a] > (uint32_t)f.M[a] - 1u) ci[a] = (uint32_t)f.M[a] - 1u;
         }
-        if (!f.flags[((int64_t)ci[2] * f.M[1] + ci[1]) * f.M[0] + ci[0]]) {
-            s.status = S_SKIP;
-            return s;
-        }
+        live = fl.get((ci[2] * (uint32_t)f.M[1] + ci[1]) * (uint32_t)f.M[0] + ci[0]);
     }
-    s.status = S_MISS;
-    if (f.mode != CINR_CACHED) return s;
+    if (f.mode != CINR_CACHED) {
+        s.status = live ? S_MISS : S_SKIP;
+        return s;
+    }
     const int32_t nl = f.geo.n_lods;
     const int32_t L = select_lod(p, f.cam.eye, f.lod_scale, f.frame_seed, f.lod_floor, nl);
     const int32_t B = f.geo.brick;
+    s.status = S_MISS;
     for (int32_t Lp = L; Lp < nl; ++Lp) {
-        const BrickAddr a = brick_addr(f.geo, Lp, p);
+        const BrickAddr a = brick_addr(lg[Lp], f.geo.brick, f.geo.div_b1, Lp, p);
         if (Lp == L) s.req_key = a.key;
         const int32_t slot = sc.lookup(f.pt, (int32_t)a.key);
+        if (!live) {
+            s.status = S_SKIP;
+            s.req_key = -1;
+            return s;
+        }
         if (slot < 0) continue;
         const float* br = f.pool + (int64_t)slot * (B * B * B) + ((int64_t)a.lj[2] * B + a.lj[1]) * B + a.lj[0];
         const int32_t B2 = B * B;
@@ -138,8 +162,9 @@ __device__ inline void log_miss(const FrameDev& f, int32_t pix, int32_t k, const
     }
 }
 
+// Per-lane sample counters (32 bits per lane, summed per wave at the end).
 struct Tally {
-    uint64_t rays = 0, samples = 0, hits = 0, fallbacks = 0, misses = 0, skipped = 0;
+    uint32_t rays = 0, samples = 0, hits = 0, fallbacks = 0, misses = 0, skipped = 0;
     __device__ void add(int32_t st) {
         ++samples;
         hits += st == S_HIT;
@@ -189,58 +214,110 @@ struct RayBook {
     }
 };
 
-__global__ __launch_bounds__(kBlock) void k_frame_begin(FrameDev f, int32_t n_ctr, uint8_t* flags,
-                                                        const float* minmax, int64_t n_cells, CacheCtr* cctr) {
+__global__ __launch_bounds__(kBlock) void k_frame_begin(FrameDev f, int32_t n_ctr, const float* minmax,
+                                                        int64_t n_cells, CacheCtr* cctr) {
     __shared__ float alpha[256];
     alpha[threadIdx.x] = f.tf[4 * threadIdx.x + 3];
     __syncthreads();
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (t < n_ctr) f.ctr[t] = IterCtr{0u, 0u, 0u, 0u};
+    if (t < 16) f.claim[t * kClaimStride] = 0u;
     if (t < ST_COUNT) f.stats[t] = 0ull;
     if (t == 0 && cctr) cctr->n_misslog = 0u;
     // macro-cell flags (Section 5.2): maximum opacity over the TF rows a
-    // cell's value range can reach; zero means the cell is skipped
-    if (flags && t < n_cells) {
-        const float a = minmax[2 * t] * 255.0f;
-        const float b = minmax[2 * t + 1] * 255.0f;
-        int32_t lo = (int32_t)__builtin_floorf(a), hi = (int32_t)__builtin_ceilf(b);
-        lo = lo < 0 ? 0 : lo;
-        hi = hi > 255 ? 255 : hi;
-        float mu = 0.0f;
-        for (int32_t r = lo; r <= hi; ++r) mu = alpha[r] > mu ? alpha[r] : mu;
-        flags[t] = mu > 0.0f ? 1 : 0;
+    // cell's value range can reach; zero means the cell is skipped.  One bit
+    // per cell, 64 cells (one wave) per word.
+    if (f.flags && (t >> 6) < f.flag_words) {
+        bool vis = false;
+        if (t < n_cells) {
+            const float a = minmax[2 * t] * 255.0f;
+            const float b = minmax[2 * t + 1] * 255.0f;
+            int32_t lo = (int32_t)__builtin_floorf(a), hi = (int32_t)__builtin_ceilf(b);
+            lo = lo < 0 ? 0 : lo;
+            hi = hi > 255 ? 255 : hi;
+            float mu = 0.0f;
+            for (int32_t r = lo; r <= hi; ++r) mu = alpha[r] > mu ? alpha[r] : mu;
+            vis = mu > 0.0f;
+        }
+        const uint64_t word = __ballot(vis);
+        if (lane_id() == 0) f.flags[t >> 6] = word;
     }
 }
 
-// One thread per ray.  Iteration 0 walks all pixels in 8x8 tiles (one tile
-// per wave) and generates the rays itself; later iterations walk the list
-// of rays re-queued by k_shade.  Every lane of a wave runs the same number
-// of loop trips so that list reservations can be made per wave.
-template <int kPipe>
-__global__ __launch_bounds__(kBlock) void k_march(FrameDev f, int32_t it, uint32_t n0) {
+// Work units of one march launch, claimed by waves.  Units are cut into
+// 8*bands contiguous bands; XCD x (workgroups are dispatched round-robin over
+// the 8 XCDs) claims bands x, x+8, ... in order through its own counter, so
+// that each XCD's L2 sees compact image regions and every XCD gets bands from
+// all over the image.  A wave whose XCD has no unit left claims from the
+// others.
+
+struct UnitQueue {
+    uint32_t* ctr;  // 8 counters, kClaimStride words apart
+    uint32_t n_units, bsz, per_x, home;
+    uint32_t dead = 0;  // counters known to be exhausted (wave-uniform)
+    __device__ UnitQueue(uint32_t* c, uint32_t n, uint32_t bands) : ctr(c), n_units(n) {
+        const uint32_t nb = 8u * bands;
+        bsz = (n + nb - 1u) / nb;
+        per_x = bands * bsz;
+        home = blockIdx.x & 7u;
+    }
+    // Next unit for the whole wave, or -1 when every counter is exhausted.
+    // Each trip either returns, or advances a counter that is bounded by
+    // per_x, or marks one of the 8 counters dead.
+    __device__ int64_t claim() {
+        while (dead != 0xFFu) {
+            uint32_t xo = 0;
+            while ((dead >> xo) & 1u) ++xo;
+            const uint32_t x = (home + xo) & 7u;
+            uint32_t j = 0;
+            if (lane_id() == 0) j = atomicAdd(&ctr[x * kClaimStride], 1u);
+            j = __builtin_amdgcn_readfirstlane(j);
+            if (j >= per_x) {
+                dead |= 1u << xo;
+                continue;
+            }
+            const uint32_t band = x + 8u * (j / bsz);
+            const uint32_t u = band * bsz + j % bsz;
+            if (u < n_units) return (int64_t)u;
+        }
+        return -1;
+    }
+};
+
+// Persistent march: each wave claims work units of 64 rays (one per lane) and
+// marches them in lockstep, so that neighbouring rays read neighbouring brick
+// samples together.  Every lane of a wave runs the same trips of the unit loop
+// so that list reservations can be made per wave.
+// (at least 4 waves per SIMD: the register budget is 128 VGPRs)
+template <int kPipe, bool kLdsFlags>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_march(FrameDev f, int32_t it, uint32_t n0) {
     __shared__ float4 tfs[256];
+    __shared__ LodGeom lgs[kMaxLods];
+    __shared__ uint64_t sflags[kLdsFlags ? kMaxLdsFlagWords : 1];
     tfs[threadIdx.x] = reinterpret_cast<const float4*>(f.tf)[threadIdx.x];
+    if (threadIdx.x < kMaxLods) lgs[threadIdx.x] = f.geo.lod[threadIdx.x];
+    if (kLdsFlags)
+        for (int32_t w = threadIdx.x; w < f.flag_words; w += kBlock) sflags[w] = f.flags[w];
+    // the counters of the next iteration were last used two launches ago
+    if (blockIdx.x == 0 && threadIdx.x < 8) f.claim[(((it + 1) & 1) * 8 + threadIdx.x) * kClaimStride] = 0u;
     __syncthreads();
+    using Flags = typename std::conditional<kLdsFlags, LdsFlags, GlobalFlags>::type;
+    const Flags fl{kLdsFlags ? (const uint64_t*)sflags : (const uint64_t*)f.flags};
+
+    // iteration 0: all pixels in 8x8 tiles (unit = tile); later: the rays
+    // re-queued by k_shade, 64 per unit
     const uint32_t n = it == 0 ? n0 : f.ctr[it].live;
     const int32_t* cur = (it & 1) ? f.live1 : f.live0;
-    // The ray list is cut into 8*bands contiguous bands; XCD x (workgroups are
-    // dispatched round-robin over the 8 XCDs) walks bands x, x+8, ...  Each
-    // band is a compact image region (locality in one XCD's L2) and every XCD
-    // gets bands from all over the image (balance).
-    const uint32_t nb = gridDim.x;
-    const uint32_t bands = (uint32_t)f.xcd_bands;
-    const uint32_t bs = nb / (8u * bands);  // workgroups per band
-    const uint32_t x = blockIdx.x & 7u, i8 = blockIdx.x >> 3;
-    const uint32_t lb = (x + 8u * (i8 / bs)) * bs + (i8 % bs);
-    const uint32_t per = (n + nb - 1) / nb;
-    const uint32_t beg = lb * per;
-    const uint32_t end = beg + per < n ? beg + per : n;
+    UnitQueue q(f.claim + (it & 1) * 8 * kClaimStride, (n + 63u) / 64u, (uint32_t)f.xcd_bands);
     const int32_t tiles_x = (f.cam.W + 7) / 8;
-    Tally tally;
     const int32_t S = f.S;
-    for (uint32_t r0 = beg; r0 < end; r0 += kBlock) {
-        const uint32_t r = r0 + threadIdx.x;
-        bool has = r < end;
+    Tally tally;
+    SlotCache sc;  // residency is constant within a frame: valid across rays
+    for (;;) {
+        const int64_t unit = q.claim();
+        if (unit < 0) break;
+        const uint32_t r = (uint32_t)unit * 64u + (uint32_t)lane_id();
+        bool has = r < n;
         int32_t pix = 0;
         float o[3], d[3], ts = 0.0f, te = -1.0f;
         if (has) {
@@ -265,6 +342,7 @@ __global__ __launch_bounds__(kBlock) void k_march(FrameDev f, int32_t it, uint32
                 has = hit;
             }
         }
+        if (__ballot(has) == 0ull) continue;
         int32_t k = 0;
         float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
         if (has && it > 0) {
@@ -272,7 +350,6 @@ __global__ __launch_bounds__(kBlock) void k_march(FrameDev f, int32_t it, uint32
             acc = f.rgba[pix];
         }
         RayBook book;
-        SlotCache sc;
         bool pend = false;
         if (has) {
             // Fast phase, software-pipelined: decide and fetch a group of
@@ -287,7 +364,7 @@ __global__ __launch_bounds__(kBlock) void k_march(FrameDev f, int32_t it, uint32
 #pragma unroll
                 for (int u = 0; u < kPipe; ++u) {
                     if (cnt == u && sample_pos(o, d, ts, te, f.step, k + u, f.vm1, p)) {
-                        grp[u] = sample_cache(f, p, sc);
+                        grp[u] = sample_cache(f, lgs, fl, p, sc);
                         ++cnt;
                     }
                 }
@@ -313,38 +390,40 @@ __global__ __launch_bounds__(kBlock) void k_march(FrameDev f, int32_t it, uint32
             }
         }
         // a wavefront step of S samples starting at the miss
-        const uint32_t pi = wave_reserve(pend ? 1u : 0u, &f.ctr[it].pending);
-        uint64_t mask = 0;
-        int32_t nc = 0;
-        if (pend) {
-            f.pend_pix[pi] = pix;
-            float* vb = f.vals + (int64_t)pi * S;
-            mask = 1;
-            nc = 1;
-            while (nc < S) {
-                float q[3];
-                if (!sample_pos(o, d, ts, te, f.step, k + nc, f.vm1, q)) break;
-                const SampleRes sr = sample_cache(f, q, sc);
-                tally.add(sr.status);
-                book.note(f, sr);
-                if (sr.status == S_MISS)
-                    mask |= 1ull << nc;
-                else
-                    vb[nc] = sr.status == S_SKIP ? -1.0f : sr.value;
-                ++nc;
+        if (__ballot(pend) != 0ull) {
+            const uint32_t pi = wave_reserve(pend ? 1u : 0u, &f.ctr[it].pending);
+            uint64_t mask = 0;
+            int32_t nc = 0;
+            if (pend) {
+                f.pend_pix[pi] = pix;
+                float* vb = f.vals + (int64_t)pi * S;
+                mask = 1;
+                nc = 1;
+                while (nc < S) {
+                    float qp[3];
+                    if (!sample_pos(o, d, ts, te, f.step, k + nc, f.vm1, qp)) break;
+                    const SampleRes sr = sample_cache(f, lgs, fl, qp, sc);
+                    tally.add(sr.status);
+                    book.note(f, sr);
+                    if (sr.status == S_MISS)
+                        mask |= 1ull << nc;
+                    else
+                        vb[nc] = sr.status == S_SKIP ? -1.0f : sr.value;
+                    ++nc;
+                }
+                f.pend_n[pi] = nc;
+                f.k_next[pix] = k;
             }
-            f.pend_n[pi] = nc;
-            f.k_next[pix] = k;
-        }
-        // true-miss records (position, destination slot), reserved per wave
-        uint32_t mb = wave_reserve((uint32_t)__popcll(mask), &f.ctr[it].misses);
-        if (pend) {
-            for (int32_t sidx = 0; sidx < nc; ++sidx) {
-                if (!((mask >> sidx) & 1ull)) continue;
-                float q[3];
-                sample_pos(o, d, ts, te, f.step, k + sidx, f.vm1, q);
-                f.miss_rec[mb++] = make_float4(q[0], q[1], q[2], __uint_as_float(pi * (uint32_t)S + (uint32_t)sidx));
-                log_miss(f, pix, k + sidx, q);
+            // true-miss records (position, destination slot), reserved per wave
+            uint32_t mb = wave_reserve((uint32_t)__popcll(mask), &f.ctr[it].misses);
+            if (pend) {
+                for (int32_t sidx = 0; sidx < nc; ++sidx) {
+                    if (!((mask >> sidx) & 1ull)) continue;
+                    float qp[3];
+                    sample_pos(o, d, ts, te, f.step, k + sidx, f.vm1, qp);
+                    f.miss_rec[mb++] = make_float4(qp[0], qp[1], qp[2], __uint_as_float(pi * (uint32_t)S + (uint32_t)sidx));
+                    log_miss(f, pix, k + sidx, qp);
+                }
             }
         }
         if (has) {
@@ -414,33 +493,68 @@ static int blocks_for(int64_t n, int64_t cap) {
     return (int)b;
 }
 
-hipError_t launch_frame_begin(const FrameDev& f, int32_t n_iter_ctr, const uint8_t* flags_out, const float* minmax,
-                              int64_t n_cells, CacheCtr* cctr, hipStream_t s) {
+hipError_t launch_frame_begin(const FrameDev& f, int32_t n_iter_ctr, const float* minmax, int64_t n_cells,
+                              CacheCtr* cctr, hipStream_t s) {
     int64_t n = n_iter_ctr;
-    if (flags_out && n_cells > n) n = n_cells;
+    if (f.flags && n_cells > n) n = n_cells;
     if (n < ST_COUNT) n = ST_COUNT;
-    hipLaunchKernelGGL(k_frame_begin, dim3(blocks_for(n, 1 << 20)), dim3(kBlock), 0, s, f, n_iter_ctr,
-                       (uint8_t*)flags_out, minmax, flags_out ? n_cells : 0, cctr);
+    hipLaunchKernelGGL(k_frame_begin, dim3(blocks_for(n, 1 << 20)), dim3(kBlock), 0, s, f, n_iter_ctr, minmax,
+                       f.flags ? n_cells : 0, cctr);
     return hipGetLastError();
 }
 
-hipError_t launch_march(const FrameDev& f, int it, int64_t cap_rays, hipStream_t s) {
-    // iteration 0 walks all pixels in 8x8 tiles, one workgroup per 256 pixels
-    const uint32_t n0 = (uint32_t)(((f.cam.W + 7) / 8) * ((f.cam.H + 7) / 8)) * 64u;
-    const int64_t cap = it == 0 ? (int64_t)n0 : cap_rays;
-    // a multiple of 8 * bands workgroups
-    const int64_t q = 8LL * f.xcd_bands;
-    int64_t b = (cap + kBlock - 1) / kBlock;
-    b = b > (1 << 20) ? (1 << 20) : b;
-    b = ((b + q - 1) / q) * q;
-    // kPipe: samples decided and fetched ahead in the fast phase
-    switch (f.pipe) {
-        case 1: hipLaunchKernelGGL(k_march<1>, dim3((unsigned)b), dim3(kBlock), 0, s, f, it, n0); break;
-        case 2: hipLaunchKernelGGL(k_march<2>, dim3((unsigned)b), dim3(kBlock), 0, s, f, it, n0); break;
-        case 8: hipLaunchKernelGGL(k_march<8>, dim3((unsigned)b), dim3(kBlock), 0, s, f, it, n0); break;
-        default: hipLaunchKernelGGL(k_march<4>, dim3((unsigned)b), dim3(kBlock), 0, s, f, it, n0); break;
+// Workgroups of one k_march instantiation that are resident at once on the
+// current device (the grid of the persistent kernel), cached per device.
+template <int P, bool LDS>
+static hipError_t resident_blocks(int* out) {
+    static int cache[64] = {0};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    if (cache[dev] == 0) {
+        int per_cu = 0, n_cu = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_march<P, LDS>, kBlock, 0);
+        if (e != hipSuccess) return e;
+        e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        cache[dev] = (per_cu > 0 ? per_cu : 1) * (n_cu > 0 ? n_cu : 1);
     }
+    *out = cache[dev];
+    return hipSuccess;
+}
+
+template <int P, bool LDS>
+static hipError_t launch_march_t(const FrameDev& f, int it, int64_t max_rays, uint32_t n0, hipStream_t s) {
+    int cap = 0;
+    hipError_t e = resident_blocks<P, LDS>(&cap);
+    if (e != hipSuccess) return e;
+    // one work unit (64 rays) per wave at least
+    int64_t b = (max_rays + kBlock - 1) / kBlock;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    hipLaunchKernelGGL((k_march<P, LDS>), dim3((unsigned)b), dim3(kBlock), 0, s, f, it, n0);
     return hipGetLastError();
+}
+
+template <int P>
+static hipError_t launch_march_p(const FrameDev& f, int it, int64_t max_rays, uint32_t n0, hipStream_t s) {
+    if (f.flags && f.flag_words <= kMaxLdsFlagWords) return launch_march_t<P, true>(f, it, max_rays, n0, s);
+    return launch_march_t<P, false>(f, it, max_rays, n0, s);
+}
+
+hipError_t launch_march(const FrameDev& f, int it, int64_t max_rays, hipStream_t s) {
+    // iteration 0 walks all pixels in 8x8 tiles; later iterations at most
+    // `max_rays` re-queued rays
+    const uint32_t n0 = (uint32_t)(((f.cam.W + 7) / 8) * ((f.cam.H + 7) / 8)) * 64u;
+    const int64_t n = it == 0 ? (int64_t)n0 : max_rays;
+    // kPipe: samples decided and fetched ahead per ray
+    switch (f.pipe) {
+        case 1: return launch_march_p<1>(f, it, n, n0, s);
+        case 2: return launch_march_p<2>(f, it, n, n0, s);
+        case 8: return launch_march_p<8>(f, it, n, n0, s);
+        default: return launch_march_p<4>(f, it, n, n0, s);
+    }
 }
 
 hipError_t launch_shade(const FrameDev& f, int it, int64_t cap_rays, hipStream_t s) {
