@@ -1,0 +1,169 @@
+"""The C ABI on the CPU: the library loads, exports every function that
+include/cinr.h declares, and its host-side logic (argument validation,
+LoD/brick geometry, workspace sizing) behaves as documented.
+
+No call in this file launches a kernel or touches device memory: volume
+creation only records the parameter pointers, so placeholder addresses are
+passed for them.
+"""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2504_18001_amd import cinr, configs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cinr.h")
+
+OK, INVALID_ARG = 0, -1
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(cinr_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert len(names) >= 16
+    L = cinr.lib()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert missing == []
+    # and the binding declares a signature for each of them
+    for n in names:
+        assert getattr(L, n).argtypes is not None or n == "cinr_last_error", n
+
+
+def fake_volume(arch, macro_cell=0):
+    """Creates a volume with placeholder parameter addresses (never read)."""
+    d = cinr.VolumeDesc()
+    for a in range(3):
+        d.dims[a] = arch.dims[a]
+    d.n_levels, d.n_features, d.log2_table = arch.n_levels, arch.n_features, arch.log2_table
+    for l, n in enumerate(arch.level_res):
+        d.level_res[l] = n
+    d.n_layers = len(arch.widths) - 1
+    for i, w in enumerate(arch.widths):
+        d.widths[i] = w
+    d.value_scale, d.value_offset = 1.0, 0.0
+    d.d_table = C.c_void_p(0x10000)
+    d.d_weights = C.c_void_p(0x20000)
+    if macro_cell:
+        d.d_macrocells = C.c_void_p(0x30000)
+        d.macrocell_size = macro_cell
+    h = C.c_void_p()
+    rc = cinr.lib().cinr_create_volume_inr(C.byref(d), C.byref(h))
+    return rc, h, d
+
+
+def test_null_arguments_are_rejected_with_a_message():
+    L = cinr.lib()
+    h = C.c_void_p()
+    assert L.cinr_create_volume_inr(None, C.byref(h)) == INVALID_ARG
+    assert b"null" in L.cinr_last_error()
+    assert L.cinr_lod_geometry(None, 16, 4, None, None) == INVALID_ARG
+    assert L.cinr_render_frame(None, None, None, None, None, None, None, None, 0, None) == INVALID_ARG
+
+
+@pytest.mark.parametrize("field,value", [("n_levels", 0), ("n_levels", 33), ("n_features", 3), ("log2_table", 3),
+                                         ("n_layers", 0)])
+def test_invalid_volume_descriptors(field, value):
+    rc, h, d = fake_volume(configs.ARCH_SMALL)
+    assert rc == OK
+    cinr.lib().cinr_destroy_volume(h)
+    setattr(d, field, value)
+    h2 = C.c_void_p()
+    assert cinr.lib().cinr_create_volume_inr(C.byref(d), C.byref(h2)) == INVALID_ARG
+    assert len(cinr.lib().cinr_last_error()) > 0
+
+
+def test_first_width_must_match_the_encoding():
+    _, h, d = fake_volume(configs.ARCH_SMALL)
+    cinr.lib().cinr_destroy_volume(h)
+    d.widths[0] = d.widths[0] + 1
+    h2 = C.c_void_p()
+    assert cinr.lib().cinr_create_volume_inr(C.byref(d), C.byref(h2)) == INVALID_ARG
+
+
+@pytest.mark.parametrize("arch,brick,n_lods", [(configs.ARCH_SMALL, 8, 2), (configs.ARCH_512, 16, 4),
+                                               (configs.ARCH_TERA, 16, 6)])
+def test_lod_geometry_matches_the_oracle(arch, brick, n_lods):
+    rc, h, _ = fake_volume(arch)
+    assert rc == OK
+    try:
+        nb = np.zeros((n_lods, 3), np.int32)
+        off = np.zeros(n_lods + 1, np.int64)
+        rc = cinr.lib().cinr_lod_geometry(h, brick, n_lods, nb.ctypes.data_as(C.c_void_p),
+                                          off.ctypes.data_as(C.c_void_p))
+        assert rc == OK
+        _, onb, ooff = O.lod_geometry(arch.dims, brick, n_lods)
+        assert np.array_equal(nb, np.asarray(onb).reshape(n_lods, 3))
+        assert np.array_equal(off, np.asarray(ooff))
+    finally:
+        cinr.lib().cinr_destroy_volume(h)
+
+
+def test_brick_key_counts_of_the_two_small_configurations():
+    # Section 4.3.2 geometry, stride B-1: 9^3 + 5^3 and 35^3 + 18^3 + 9^3 + 5^3 keys
+    for arch, brick, n_lods, keys in ((configs.ARCH_SMALL, 8, 2, 854), (configs.ARCH_512, 16, 4, 49561)):
+        _, h, _ = fake_volume(arch)
+        off = np.zeros(n_lods + 1, np.int64)
+        assert cinr.lib().cinr_lod_geometry(h, brick, n_lods, None, off.ctypes.data_as(C.c_void_p)) == OK
+        assert off[-1] == keys
+        cinr.lib().cinr_destroy_volume(h)
+
+
+def test_invalid_brick_geometry_is_rejected():
+    _, h, _ = fake_volume(configs.ARCH_SMALL)
+    try:
+        for brick, n_lods in ((1, 2), (8, 0), (8, cinr.MAX_LODS + 1)):
+            assert cinr.lib().cinr_lod_geometry(h, brick, n_lods, None, None) == INVALID_ARG
+    finally:
+        cinr.lib().cinr_destroy_volume(h)
+
+
+def cache_desc(brick=8, n_lods=2, pool=96, max_requests=16):
+    d = cinr.CacheDesc()
+    d.brick, d.n_lods, d.pool_bricks, d.max_requests = brick, n_lods, pool, max_requests
+    d.rank_window, d.ranking = 1000, cinr.RANK_PRIORITY
+    return d
+
+
+def test_cache_workspace_grows_with_the_pool_and_rejects_bad_descriptors():
+    _, h, _ = fake_volume(configs.ARCH_SMALL)
+    L = cinr.lib()
+    try:
+        sizes = []
+        for pool in (16, 96, 4096):
+            b = C.c_size_t()
+            assert L.cinr_cache_workspace_size(h, C.byref(cache_desc(pool=pool)), C.byref(b)) == OK
+            sizes.append(b.value)
+        assert sizes[0] < sizes[1] < sizes[2]
+        b = C.c_size_t()
+        # 0 <= max_requests <= 256, pool_bricks >= 0
+        assert L.cinr_cache_workspace_size(h, C.byref(cache_desc(max_requests=0)), C.byref(b)) == OK
+        assert L.cinr_cache_workspace_size(h, C.byref(cache_desc(max_requests=-1)), C.byref(b)) == INVALID_ARG
+        assert L.cinr_cache_workspace_size(h, C.byref(cache_desc(max_requests=257)), C.byref(b)) == INVALID_ARG
+        assert L.cinr_cache_workspace_size(h, C.byref(cache_desc(pool=-1)), C.byref(b)) == INVALID_ARG
+    finally:
+        L.cinr_destroy_volume(h)
+
+
+def test_render_workspace_covers_the_per_ray_buffers():
+    _, h, _ = fake_volume(configs.ARCH_512, macro_cell=16)
+    L = cinr.lib()
+    try:
+        b = C.c_size_t()
+        assert L.cinr_render_workspace_size(h, 1920, 1080, 32, C.byref(b)) == OK
+        npix = 1920 * 1080
+        # per pixel at least: two live lists, k, pending pixel and count, S values, S miss records
+        assert b.value >= npix * (5 * 4 + 32 * 4 + 32 * 16)
+        assert L.cinr_render_workspace_size(h, 1920, 1080, 65, C.byref(b)) == INVALID_ARG
+        assert L.cinr_render_workspace_size(h, 0, 1080, 32, C.byref(b)) == INVALID_ARG
+    finally:
+        L.cinr_destroy_volume(h)
