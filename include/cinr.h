@@ -157,8 +157,8 @@ typedef struct {
  *  mode          cinr_mode.
  *  mlp_dtype     cinr_dtype of brick decoding and true-miss inference.
  *  pipe_depth    tuning: samples each ray decides and fetches ahead while
- *                marching (1, 2, 4 or 8; 0 = default 2).  Results do not
- *                depend on it.
+ *                marching (1, 2 or 4; 8 is accepted and runs as 4; 0 =
+ *                default 2).  Results do not depend on it.
  *  xcd_bands     tuning: image bands per XCD in the sampler's work split
  *                (0 = default 4).  Results do not depend on it. */
 typedef struct {

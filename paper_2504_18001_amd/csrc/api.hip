@@ -568,6 +568,7 @@ extern "C" cinr_status cinr_render_frame(cinr_cache c, cinr_volume v, const cinr
         f.touched = c->c.touched;
         f.n_touched = &c->c.ctr->n_touched;
         f.pool = c->c.pool;
+        f.pool_bricks = c->c.pool_bricks;
         f.misslog = c->c.misslog;
         f.n_misslog = &c->c.ctr->n_misslog;
         f.misslog_cap = c->c.misslog_cap;

@@ -133,29 +133,32 @@ __device__ inline int32_t select_lod(const float p[3], const float eye[3], float
 }
 
 // Brick of LoD L holding sample position p: lattice cell j (clamped so that
-// j+1 exists), brick b = j / (B-1), key, and the cell fraction q - j.
+// j+1 exists), brick b = j / (B-1), key, and the cell fraction q - j.  Keys
+// fit in 31 bits (checked when the cache is created).
 struct BrickAddr {
-    int64_t key;
+    int32_t key;
     int32_t lj[3];   // cell inside the brick (j - b(B-1))
     float frac[3];
 };
 
-// `lg` is the geometry of LoD L, `div_b1` divides by brick - 1.
+// `lg` is the geometry of LoD L; kB is the brick size when it is known at
+// compile time (0: `brick`, with `div_b1` dividing by brick - 1).
+template <int kB>
 __device__ inline BrickAddr brick_addr(const LodGeom& lg, int32_t brick, FastDiv div_b1, int32_t L, const float p[3]) {
     BrickAddr r;
     const float sc = __builtin_ldexpf(1.0f, -L);
-    const int32_t B1 = brick - 1;
+    const int32_t B1 = (kB ? kB : brick) - 1;
     int32_t b[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const float q = p[a] * sc;
         int32_t j = (int32_t)q;
         if (j > lg.K[a] - 2) j = lg.K[a] - 2;
-        b[a] = (int32_t)fast_div((uint32_t)j, div_b1);
+        b[a] = kB ? (int32_t)((uint32_t)j / (uint32_t)(kB - 1)) : (int32_t)fast_div((uint32_t)j, div_b1);
         r.lj[a] = j - b[a] * B1;
         r.frac[a] = q - (float)j;
     }
-    r.key = lg.off + ((int64_t)b[2] * lg.nb[1] + b[1]) * lg.nb[0] + b[0];
+    r.key = (int32_t)lg.off + (b[2] * lg.nb[1] + b[1]) * lg.nb[0] + b[0];
     return r;
 }
 

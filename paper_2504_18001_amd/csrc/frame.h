@@ -90,6 +90,7 @@ struct FrameDev {
     int32_t* touched;
     uint32_t* n_touched;
     const float* pool;
+    int32_t pool_bricks;
     MissLogRec* misslog;
     uint32_t* n_misslog;
     int32_t misslog_cap;

@@ -21,7 +21,7 @@ namespace cinr {
 struct SampleRes {
     int32_t status;
     int32_t slot;
-    int64_t req_key;
+    int32_t req_key;
     float value;
 };
 
@@ -62,10 +62,13 @@ struct GlobalFlags {
 // Sampler of Algorithm 2 for one position: macro-cell skip, stochastic LoD,
 // page-table lookup at that LoD and every coarser one, trilinear fetch.  The
 // flag read and the first page-table read are issued together; a skipped
-// sample discards the lookup.
-template <class Flags>
+// sample discards the lookup.  kFast: bricks of 16^3 in a pool of less than
+// 4 GiB (compile-time brick offsets, 32-bit byte offsets into the pool) and
+// macro-cells of 16^3 voxels.
+template <bool kFast, class Flags>
 __device__ inline SampleRes sample_cache(const FrameDev& f, const LodGeom* lg, const Flags& fl, const float p[3],
                                          SlotCache& sc) {
+    constexpr int kB = kFast ? 16 : 0;
     SampleRes s;
     s.slot = -1;
     s.req_key = -1;
@@ -75,7 +78,7 @@ __device__ inline SampleRes sample_cache(const FrameDev& f, const LodGeom* lg, c
         uint32_t ci[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            ci[a] = fast_div((uint32_t)(int32_t)p[a], f.div_mc);
+            ci[a] = kFast ? (uint32_t)(int32_t)p[a] >> 4 : fast_div((uint32_t)(int32_t)p[a], f.div_mc);
             if (ci[a] > (uint32_t)f.M[a] - 1u) ci[a] = (uint32_t)f.M[a] - 1u;
         }
         live = fl.get((ci[2] * (uint32_t)f.M[1] + ci[1]) * (uint32_t)f.M[0] + ci[0]);
@@ -86,19 +89,26 @@ __device__ inline SampleRes sample_cache(const FrameDev& f, const LodGeom* lg, c
     }
     const int32_t nl = f.geo.n_lods;
     const int32_t L = select_lod(p, f.cam.eye, f.lod_scale, f.frame_seed, f.lod_floor, nl);
-    const int32_t B = f.geo.brick;
+    const int32_t B = kFast ? kB : f.geo.brick;
     s.status = S_MISS;
     for (int32_t Lp = L; Lp < nl; ++Lp) {
-        const BrickAddr a = brick_addr(lg[Lp], f.geo.brick, f.geo.div_b1, Lp, p);
+        const BrickAddr a = brick_addr<kB>(lg[Lp], f.geo.brick, f.geo.div_b1, Lp, p);
         if (Lp == L) s.req_key = a.key;
-        const int32_t slot = sc.lookup(f.pt, (int32_t)a.key);
+        const int32_t slot = sc.lookup(f.pt, a.key);
         if (!live) {
             s.status = S_SKIP;
             s.req_key = -1;
             return s;
         }
         if (slot < 0) continue;
-        const float* br = f.pool + (int64_t)slot * (B * B * B) + ((int64_t)a.lj[2] * B + a.lj[1]) * B + a.lj[0];
+        const float* br;
+        if (kFast) {
+            const uint32_t off = (((uint32_t)slot * (uint32_t)(kB * kB * kB) +
+                                   ((uint32_t)a.lj[2] * kB + (uint32_t)a.lj[1]) * kB + (uint32_t)a.lj[0])) * 4u;
+            br = reinterpret_cast<const float*>(reinterpret_cast<const char*>(f.pool) + off);
+        } else {
+            br = f.pool + (int64_t)slot * (B * B * B) + ((int64_t)a.lj[2] * B + a.lj[1]) * B + a.lj[0];
+        }
         const int32_t B2 = B * B;
         const float c000 = br[0], c100 = br[1], c010 = br[B], c110 = br[B + 1];
         const float c001 = br[B2], c101 = br[B2 + 1], c011 = br[B2 + B], c111 = br[B2 + B + 1];
@@ -139,44 +149,93 @@ __device__ inline void composite(float4& acc, float v, const float4* tfs, float 
     acc.w += w;
 }
 
-__device__ inline void flush_requests(const FrameDev& f, int64_t key, uint32_t cnt) {
+// Values of one march launch that only its cold paths read (ray setup,
+// wavefront steps, request and miss-log appends).  They are staged in LDS and
+// read through a volatile pointer at each use, so that they hold no registers
+// across the sample loop.
+struct MarchCold {
+    CamDev cam;
+    float4* rgba;
+    int32_t* k_next;
+    const int32_t* cur;
+    int32_t* pend_pix;
+    int32_t* pend_n;
+    float* vals;
+    float4* miss_rec;
+    uint32_t* pending;  // counters of this iteration
+    uint32_t* misses;
+    MissLogRec* misslog;
+    uint32_t* n_misslog;
+    int32_t misslog_cap;
+    uint32_t* req;
+    int32_t* touched;
+    uint32_t* n_touched;
+};
+using ColdRef = const volatile MarchCold*;
+
+__device__ inline CamDev load_cam(const volatile CamDev& v) {
+    CamDev c;
+    c.proj = v.proj;
+    c.W = v.W;
+    c.H = v.H;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        c.eye[a] = v.eye[a];
+        c.fwd[a] = v.fwd[a];
+        c.right[a] = v.right[a];
+        c.up[a] = v.up[a];
+    }
+    c.tanx = v.tanx;
+    c.tany = v.tany;
+    c.ow = v.ow;
+    c.oh = v.oh;
+    return c;
+}
+
+__device__ inline void flush_requests(ColdRef c, int32_t key, uint32_t cnt) {
     if (key < 0 || cnt == 0) return;
-    const uint32_t old = atomicAdd(&f.req[key], cnt);
+    uint32_t* req = c->req;
+    const uint32_t old = atomicAdd(&req[key], cnt);
     if (old == 0u) {
-        const uint32_t i = atomicAdd(f.n_touched, 1u);
-        f.touched[i] = (int32_t)key;
+        const uint32_t i = atomicAdd(c->n_touched, 1u);
+        int32_t* touched = c->touched;
+        touched[i] = key;
     }
 }
 
-__device__ inline void log_miss(const FrameDev& f, int32_t pix, int32_t k, const float p[3]) {
-    if (f.misslog_cap <= 0) return;
-    const uint32_t i = atomicAdd(f.n_misslog, 1u);
-    if ((int32_t)i < f.misslog_cap) {
+__device__ inline void log_miss(ColdRef c, int32_t pix, int32_t k, const float p[3]) {
+    const int32_t cap = c->misslog_cap;
+    if (cap <= 0) return;
+    const uint32_t i = atomicAdd(c->n_misslog, 1u);
+    if ((int32_t)i < cap) {
         MissLogRec r;
         r.pix = pix;
         r.k = k;
         r.x = p[0];
         r.y = p[1];
         r.z = p[2];
-        f.misslog[i] = r;
+        MissLogRec* log = c->misslog;
+        log[i] = r;
     }
 }
 
-// Per-lane sample counters (32 bits per lane, summed per wave at the end).
+// Per-lane sample counters (32 bits per lane, summed per wave at the end);
+// hits are the samples that are none of the other kinds.
 struct Tally {
-    uint32_t rays = 0, samples = 0, hits = 0, fallbacks = 0, misses = 0, skipped = 0;
+    uint32_t rays = 0, samples = 0, fallbacks = 0, misses = 0, skipped = 0;
     __device__ void add(int32_t st) {
         ++samples;
-        hits += st == S_HIT;
-        fallbacks += st == S_FALLBACK;
-        misses += st == S_MISS;
-        skipped += st == S_SKIP;
+        if (st != S_HIT) {
+            fallbacks += st == S_FALLBACK;
+            misses += st == S_MISS;
+            skipped += st == S_SKIP;
+        }
     }
     // all 64 lanes of the wave must call this together
     __device__ void commit(unsigned long long* stats) {
         wave_add_u64(&stats[ST_RAYS], rays);
         wave_add_u64(&stats[ST_SAMPLES], samples);
-        wave_add_u64(&stats[ST_HITS], hits);
+        wave_add_u64(&stats[ST_HITS], samples - fallbacks - misses - skipped);
         wave_add_u64(&stats[ST_FALLBACKS], fallbacks);
         wave_add_u64(&stats[ST_MISSES], misses);
         wave_add_u64(&stats[ST_SKIPPED], skipped);
@@ -185,30 +244,32 @@ struct Tally {
 
 // Per-ray bookkeeping of one decided sample: request run-length aggregation
 // (any sample not served at its own LoD requests its brick) and LRU stamps.
+// A ray alternates between the bricks of two neighbouring LoDs, so the two
+// slots stamped last are remembered; a stamp is a plain store (every writer
+// stores the same frame index).
 struct RayBook {
-    int64_t rk = -1;
+    int32_t rk = -1;
     uint32_t rc = 0;
-    int32_t last_slot = -1;
-    __device__ void note(const FrameDev& f, const SampleRes& s) {
+    int32_t ls0 = -1, ls1 = -1;
+    __device__ void note(const FrameDev& f, ColdRef c, const SampleRes& s) {
         if (f.mode != CINR_CACHED || s.status == S_SKIP) return;
         if (s.status != S_HIT) {
             if (s.req_key != rk) {
-                flush_requests(f, rk, rc);
+                flush_requests(c, rk, rc);
                 rk = s.req_key;
                 rc = 1;
             } else {
                 ++rc;
             }
         }
-        if (s.slot >= 0 && s.slot != last_slot) {
-            // many rays stamp the same slot: store only if not yet stamped in
-            // this frame, so that the L2 does not serialise identical stores
-            if (f.last_used[s.slot] != f.frame) f.last_used[s.slot] = f.frame;
-            last_slot = s.slot;
+        if (s.slot >= 0 && s.slot != ls0 && s.slot != ls1) {
+            f.last_used[s.slot] = f.frame;
+            ls1 = ls0;
+            ls0 = s.slot;
         }
     }
-    __device__ void flush(const FrameDev& f) {
-        flush_requests(f, rk, rc);
+    __device__ void flush(ColdRef c) {
+        flush_requests(c, rk, rc);
         rk = -1;
         rc = 0;
     }
@@ -289,7 +350,7 @@ struct UnitQueue {
 // samples together.  Every lane of a wave runs the same trips of the unit loop
 // so that list reservations can be made per wave.
 // (at least 4 waves per SIMD: the register budget is 128 VGPRs)
-template <int kPipe, bool kLdsFlags>
+template <int kPipe, bool kLdsFlags, bool kFast>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_march(FrameDev f, int32_t it, uint32_t n0) {
     __shared__ float4 tfs[256];
     __shared__ LodGeom lgs[kMaxLods];
@@ -306,10 +367,30 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
 
     // iteration 0: all pixels in 8x8 tiles (unit = tile); later: the rays
     // re-queued by k_shade, 64 per unit
+    __shared__ MarchCold cold_s;
+    if (threadIdx.x == 0) {
+        MarchCold& c = cold_s;
+        c.cam = f.cam;
+        c.rgba = f.rgba;
+        c.k_next = f.k_next;
+        c.cur = (it & 1) ? f.live1 : f.live0;
+        c.pend_pix = f.pend_pix;
+        c.pend_n = f.pend_n;
+        c.vals = f.vals;
+        c.miss_rec = f.miss_rec;
+        c.pending = &f.ctr[it].pending;
+        c.misses = &f.ctr[it].misses;
+        c.misslog = f.misslog;
+        c.n_misslog = f.n_misslog;
+        c.misslog_cap = f.misslog_cap;
+        c.req = f.req;
+        c.touched = f.touched;
+        c.n_touched = f.n_touched;
+    }
+    __syncthreads();
+    const ColdRef cold = &cold_s;
     const uint32_t n = it == 0 ? n0 : f.ctr[it].live;
-    const int32_t* cur = (it & 1) ? f.live1 : f.live0;
     UnitQueue q(f.claim + (it & 1) * 8 * kClaimStride, (n + 63u) / 64u, (uint32_t)f.xcd_bands);
-    const int32_t tiles_x = (f.cam.W + 7) / 8;
     const int32_t S = f.S;
     Tally tally;
     SlotCache sc;  // residency is constant within a frame: valid across rays
@@ -321,22 +402,26 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
         int32_t pix = 0;
         float o[3], d[3], ts = 0.0f, te = -1.0f;
         if (has) {
+            const CamDev cam = load_cam(cold->cam);
             int32_t i, j;
             if (it == 0) {
+                const uint32_t tiles_x = (uint32_t)(cam.W + 7) / 8u;
                 const uint32_t tile = r >> 6, w = r & 63u;
-                i = (int32_t)(tile % (uint32_t)tiles_x) * 8 + (int32_t)(w & 7u);
-                j = (int32_t)(tile / (uint32_t)tiles_x) * 8 + (int32_t)(w >> 3);
-                has = i < f.cam.W && j < f.cam.H;
+                i = (int32_t)(tile % tiles_x) * 8 + (int32_t)(w & 7u);
+                j = (int32_t)(tile / tiles_x) * 8 + (int32_t)(w >> 3);
+                has = i < cam.W && j < cam.H;
             } else {
+                const int32_t* cur = cold->cur;
                 pix = cur[r];
-                i = pix % f.cam.W;
-                j = pix / f.cam.W;
+                i = pix % cam.W;
+                j = pix / cam.W;
             }
             if (has) {
-                if (it == 0) pix = j * f.cam.W + i;
-                const bool hit = ray_setup(f.cam, f.vm1, i, j, o, d, ts, te);
+                if (it == 0) pix = j * cam.W + i;
+                const bool hit = ray_setup(cam, f.vm1, i, j, o, d, ts, te);
                 if (it == 0) {
-                    if (!hit) f.rgba[pix] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    float4* rgba = cold->rgba;
+                    if (!hit) rgba[pix] = make_float4(0.f, 0.f, 0.f, 0.f);
                     tally.rays += hit;
                 }
                 has = hit;
@@ -346,8 +431,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
         int32_t k = 0;
         float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
         if (has && it > 0) {
-            k = f.k_next[pix];
-            acc = f.rgba[pix];
+            const int32_t* kn = cold->k_next;
+            const float4* rgba = cold->rgba;
+            k = kn[pix];
+            acc = rgba[pix];
         }
         RayBook book;
         bool pend = false;
@@ -364,7 +451,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
 #pragma unroll
                 for (int u = 0; u < kPipe; ++u) {
                     if (cnt == u && sample_pos(o, d, ts, te, f.step, k + u, f.vm1, p)) {
-                        grp[u] = sample_cache(f, lgs, fl, p, sc);
+                        grp[u] = sample_cache<kFast>(f, lgs, fl, p, sc);
                         ++cnt;
                     }
                 }
@@ -374,7 +461,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
                     if (u >= cnt) break;
                     const SampleRes& sr = grp[u];
                     tally.add(sr.status);
-                    book.note(f, sr);
+                    book.note(f, cold, sr);
                     if (sr.status == S_MISS) {
                         pend = true;
                         run = false;
@@ -391,44 +478,49 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
         }
         // a wavefront step of S samples starting at the miss
         if (__ballot(pend) != 0ull) {
-            const uint32_t pi = wave_reserve(pend ? 1u : 0u, &f.ctr[it].pending);
+            const uint32_t pi = wave_reserve(pend ? 1u : 0u, cold->pending);
             uint64_t mask = 0;
             int32_t nc = 0;
             if (pend) {
-                f.pend_pix[pi] = pix;
-                float* vb = f.vals + (int64_t)pi * S;
+                int32_t* pp = cold->pend_pix;
+                pp[pi] = pix;
+                float* vb = cold->vals + (int64_t)pi * S;
                 mask = 1;
                 nc = 1;
                 while (nc < S) {
                     float qp[3];
                     if (!sample_pos(o, d, ts, te, f.step, k + nc, f.vm1, qp)) break;
-                    const SampleRes sr = sample_cache(f, lgs, fl, qp, sc);
+                    const SampleRes sr = sample_cache<kFast>(f, lgs, fl, qp, sc);
                     tally.add(sr.status);
-                    book.note(f, sr);
+                    book.note(f, cold, sr);
                     if (sr.status == S_MISS)
                         mask |= 1ull << nc;
                     else
                         vb[nc] = sr.status == S_SKIP ? -1.0f : sr.value;
                     ++nc;
                 }
-                f.pend_n[pi] = nc;
-                f.k_next[pix] = k;
+                int32_t* pn = cold->pend_n;
+                int32_t* kn = cold->k_next;
+                pn[pi] = nc;
+                kn[pix] = k;
             }
             // true-miss records (position, destination slot), reserved per wave
-            uint32_t mb = wave_reserve((uint32_t)__popcll(mask), &f.ctr[it].misses);
+            uint32_t mb = wave_reserve((uint32_t)__popcll(mask), cold->misses);
             if (pend) {
+                float4* mr = cold->miss_rec;
                 for (int32_t sidx = 0; sidx < nc; ++sidx) {
                     if (!((mask >> sidx) & 1ull)) continue;
                     float qp[3];
                     sample_pos(o, d, ts, te, f.step, k + sidx, f.vm1, qp);
-                    f.miss_rec[mb++] = make_float4(qp[0], qp[1], qp[2], __uint_as_float(pi * (uint32_t)S + (uint32_t)sidx));
-                    log_miss(f, pix, k + sidx, qp);
+                    mr[mb++] = make_float4(qp[0], qp[1], qp[2], __uint_as_float(pi * (uint32_t)S + (uint32_t)sidx));
+                    log_miss(cold, pix, k + sidx, qp);
                 }
             }
         }
         if (has) {
-            book.flush(f);
-            f.rgba[pix] = acc;
+            book.flush(cold);
+            float4* rgba = cold->rgba;
+            rgba[pix] = acc;
         }
     }
     tally.commit(f.stats);
@@ -505,7 +597,7 @@ hipError_t launch_frame_begin(const FrameDev& f, int32_t n_iter_ctr, const float
 
 // Workgroups of one k_march instantiation that are resident at once on the
 // current device (the grid of the persistent kernel), cached per device.
-template <int P, bool LDS>
+template <int P, bool LDS, bool FAST>
 static hipError_t resident_blocks(int* out) {
     static int cache[64] = {0};
     int dev = 0;
@@ -514,7 +606,7 @@ static hipError_t resident_blocks(int* out) {
     if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
     if (cache[dev] == 0) {
         int per_cu = 0, n_cu = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_march<P, LDS>, kBlock, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_march<P, LDS, FAST>, kBlock, 0);
         if (e != hipSuccess) return e;
         e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess) return e;
@@ -524,23 +616,34 @@ static hipError_t resident_blocks(int* out) {
     return hipSuccess;
 }
 
-template <int P, bool LDS>
+template <int P, bool LDS, bool FAST>
 static hipError_t launch_march_t(const FrameDev& f, int it, int64_t max_rays, uint32_t n0, hipStream_t s) {
     int cap = 0;
-    hipError_t e = resident_blocks<P, LDS>(&cap);
+    hipError_t e = resident_blocks<P, LDS, FAST>(&cap);
     if (e != hipSuccess) return e;
     // one work unit (64 rays) per wave at least
     int64_t b = (max_rays + kBlock - 1) / kBlock;
     if (b < 1) b = 1;
     if (b > cap) b = cap;
-    hipLaunchKernelGGL((k_march<P, LDS>), dim3((unsigned)b), dim3(kBlock), 0, s, f, it, n0);
+    hipLaunchKernelGGL((k_march<P, LDS, FAST>), dim3((unsigned)b), dim3(kBlock), 0, s, f, it, n0);
     return hipGetLastError();
+}
+
+template <int P, bool LDS>
+static hipError_t launch_march_l(const FrameDev& f, int it, int64_t max_rays, uint32_t n0, hipStream_t s) {
+    // 16^3 bricks in a pool of less than 4 GiB (or the uncached mode, which
+    // reads no pool) and 16^3 macro-cells (or none)
+    const bool fast = (f.mode != CINR_CACHED ||
+                       (f.geo.brick == 16 && (uint64_t)f.pool_bricks * 16384ull < (1ull << 32))) &&
+                      (!f.flags || f.mc_N == 16);
+    if (fast) return launch_march_t<P, LDS, true>(f, it, max_rays, n0, s);
+    return launch_march_t<P, LDS, false>(f, it, max_rays, n0, s);
 }
 
 template <int P>
 static hipError_t launch_march_p(const FrameDev& f, int it, int64_t max_rays, uint32_t n0, hipStream_t s) {
-    if (f.flags && f.flag_words <= kMaxLdsFlagWords) return launch_march_t<P, true>(f, it, max_rays, n0, s);
-    return launch_march_t<P, false>(f, it, max_rays, n0, s);
+    if (f.flags && f.flag_words <= kMaxLdsFlagWords) return launch_march_l<P, true>(f, it, max_rays, n0, s);
+    return launch_march_l<P, false>(f, it, max_rays, n0, s);
 }
 
 hipError_t launch_march(const FrameDev& f, int it, int64_t max_rays, hipStream_t s) {
@@ -548,11 +651,10 @@ hipError_t launch_march(const FrameDev& f, int it, int64_t max_rays, hipStream_t
     // `max_rays` re-queued rays
     const uint32_t n0 = (uint32_t)(((f.cam.W + 7) / 8) * ((f.cam.H + 7) / 8)) * 64u;
     const int64_t n = it == 0 ? (int64_t)n0 : max_rays;
-    // kPipe: samples decided and fetched ahead per ray
+    // kPipe: samples decided and fetched ahead per ray (8 runs as 4)
     switch (f.pipe) {
         case 1: return launch_march_p<1>(f, it, n, n0, s);
         case 2: return launch_march_p<2>(f, it, n, n0, s);
-        case 8: return launch_march_p<8>(f, it, n, n0, s);
         default: return launch_march_p<4>(f, it, n, n0, s);
     }
 }
