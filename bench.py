@@ -38,6 +38,27 @@ HBM_PEAK_GBS = 8000.0
 # budget for up to 4 LoDs); each marched ray reads and writes its colour
 # (32 B), its sample index and its live-list entry (8 B)
 BYTES_SERVED, BYTES_MISS, BYTES_RAY = 36, 16, 40
+# HBM bytes per sampler launch measured with rocprofv3 (FETCH_SIZE and
+# WRITE_SIZE scaled by a copy-kernel calibration); valid only while the
+# sampler's sources are the ones that were profiled
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_march_inr512_1080p.json")
+
+
+def measured_traffic():
+    """HBM bytes per sampler launch from the committed profile, or None when
+    the profiled sources have changed since (or no profile exists)."""
+    import hashlib
+    try:
+        prof = json.load(open(TRAFFIC_PROFILE))
+        h = hashlib.sha256()
+        for rel in prof["sources"]:
+            with open(os.path.join(ROOT, rel), "rb") as fh:
+                h.update(fh.read())
+    except (OSError, ValueError, KeyError):
+        return None
+    if h.hexdigest() != prof.get("sources_sha256"):
+        return None
+    return int(prof["traffic_bytes_per_launch"])
 
 
 def log(*a):
@@ -288,7 +309,8 @@ def main():
         "stage_ms_per_frame": {k: round(v[0] / K, 4) for k, v in stages.items()},
         "frame_totals": tot,
         "roofline": {"kernel": "k_march", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+                     "algorithmic_bytes_per_launch": round(alg_bytes / max(march_n, 1)),
                      "launches": march_n, "avg_launch_ms": round(march_ms / max(march_n, 1), 5),
                      "launches_before_timed": warm_stages["march"][1]},
         "cpu_baseline": cpu,
