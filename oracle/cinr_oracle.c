@@ -1258,6 +1258,49 @@ double orc_loss_grad(const orc_inr* m, const double* u, const double* target, in
     return loss / (double)n;
 }
 
+/* Uniform training points from a counter-based generator (one Philox block
+ * per point; 24 bits per coordinate). */
+void orc_train_points(uint64_t seed, int64_t step, int64_t n, double* u) {
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int64_t i = 0; i < n; ++i) {
+        const uint32_t ctr[4] = {(uint32_t)i, (uint32_t)((uint64_t)i >> 32), (uint32_t)step,
+                                 (uint32_t)((uint64_t)step >> 32)};
+        uint32_t r[4];
+        orc_philox4x32_10(ctr, key, r);
+        for (int a = 0; a < 3; ++a) u[3 * i + a] = (double)(r[a] >> 8) * (1.0 / 16777216.0);
+    }
+}
+
+/* Trilinear interpolation of a voxel grid whose samples sit at cell centres
+ * of the unit cube: position x = u * V - 0.5 in voxel units, clamped to the
+ * sample range; the cell is clamped so that its upper corner exists. */
+void orc_grid_trilinear(const float* grid, const int32_t dims[3], const double* u, int64_t n, double* out) {
+    const int64_t sx = 1, sy = dims[0], sz = (int64_t)dims[0] * dims[1];
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c[3];
+        double f[3];
+        for (int a = 0; a < 3; ++a) {
+            double x = u[3 * i + a] * (double)dims[a] - 0.5;
+            if (x < 0.0) x = 0.0;
+            if (x > (double)(dims[a] - 1)) x = (double)(dims[a] - 1);
+            int64_t j = (int64_t)floor(x);
+            if (j > dims[a] - 2) j = dims[a] - 2;
+            if (j < 0) j = 0;
+            c[a] = j;
+            f[a] = dims[a] > 1 ? x - (double)j : 0.0;
+        }
+        const float* g = grid + c[2] * sz + c[1] * sy + c[0] * sx;
+        const int64_t dx = dims[0] > 1 ? sx : 0, dy = dims[1] > 1 ? sy : 0, dz = dims[2] > 1 ? sz : 0;
+        double v = 0.0;
+        for (int k = 0; k < 8; ++k) {
+            const int bx = k & 1, by = (k >> 1) & 1, bz = k >> 2;
+            const double w = (bx ? f[0] : 1.0 - f[0]) * (by ? f[1] : 1.0 - f[1]) * (bz ? f[2] : 1.0 - f[2]);
+            v += w * (double)g[bx * dx + by * dy + bz * dz];
+        }
+        out[i] = v;
+    }
+}
+
 /* Adam (Kingma and Ba 2015) with bias correction; `step` counts from 1. */
 void orc_adam_step(double* p, double* m1, double* m2, const double* g, int64_t n, int64_t step, double lr, double b1,
                    double b2, double eps) {

@@ -143,7 +143,15 @@ void orc_cache_set_miss_logging(orc_cache* c, int on);
 void orc_cache_set_ert_trace(orc_cache* c, int on);
 int64_t orc_cache_ert_trace(const orc_cache* c, int32_t* out, int64_t cap);
 
-/* --- training (the learned part): loss and analytic gradients --- */
+/* --- training (the learned part) --- */
+/* Training batch of `step`: point i is u = (r0, r1, r2) >> 8 * 2^-24 in
+ * [0,1)^3, where (r0, r1, r2, r3) = Philox-4x32-10(counter = (i mod 2^32,
+ * i >> 32, step mod 2^32, step >> 32), key = (seed mod 2^32, seed >> 32)). */
+void orc_train_points(uint64_t seed, int64_t step, int64_t n, double* u /*[n][3]*/);
+/* Ground truth of a training point: trilinear interpolation of the explicit
+ * grid (f32 [Vz][Vy][Vx], x fastest) at x = clamp(u * V - 0.5, 0, V - 1). */
+void orc_grid_trilinear(const float* grid, const int32_t dims[3], const double* u, int64_t n, double* out);
+
 double orc_loss_grad(const orc_inr* m, const double* u, const double* target, int64_t n,
                      double* g_table, double* g_weights);
 void orc_adam_step(double* p, double* m1, double* m2, const double* g, int64_t n, int64_t step,

@@ -422,6 +422,23 @@ def loss_grad(inr: OracleInr, u, target):
     return loss, gt, gw
 
 
+def train_points(seed, step, n):
+    """Training batch `step` (n points in [0,1)^3), float64 [n][3]."""
+    u = np.zeros((n, 3), np.float64)
+    lib().orc_train_points(C.c_uint64(seed), C.c_int64(step), C.c_int64(n), _ptr(u))
+    return u
+
+
+def grid_trilinear(grid, u):
+    """Trilinear ground truth of points u in the explicit grid (float32 [Vz][Vy][Vx])."""
+    g = np.ascontiguousarray(grid, np.float32)
+    dims = np.array([g.shape[2], g.shape[1], g.shape[0]], np.int32)
+    uu = np.ascontiguousarray(u, np.float64).reshape(-1, 3)
+    out = np.zeros(uu.shape[0], np.float64)
+    lib().orc_grid_trilinear(_ptr(g), _ptr(dims), _ptr(uu), C.c_int64(uu.shape[0]), _ptr(out))
+    return out
+
+
 def set_threads(n):
     lib().orc_set_threads(int(n))
 

@@ -59,3 +59,55 @@ def test_adam_matches_torch_optim_adam():
         tp.grad = torch.tensor(g, dtype=torch.float64)
         opt.step()
     np.testing.assert_allclose(p, tp.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_training_points_of_seed_zero_step_zero_follow_the_philox_known_answer():
+    # point 0 of (seed 0, step 0) uses counter 0 and key 0: the Philox-4x32-10
+    # known answer (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, ...), top 24 bits each
+    u = O.train_points(0, 0, 4)
+    assert u[0].tolist() == [0x6627E8 / 2 ** 24, 0xE169C5 / 2 ** 24, 0xBC57AC / 2 ** 24]
+
+
+def test_training_points_are_uniform_and_independent():
+    from scipy import stats
+    u = O.train_points(1234, 7, 1 << 16)
+    assert u.min() >= 0.0 and u.max() < 1.0
+    assert np.all(u * 2 ** 24 == np.floor(u * 2 ** 24))  # 24-bit grid
+    for a in range(3):
+        assert stats.kstest(u[:, a], "uniform").pvalue > 1e-3
+        assert abs(u[:, a].mean() - 0.5) < 3 * np.sqrt(1 / 12 / u.shape[0])
+    c = np.corrcoef(u.T)
+    assert np.abs(c - np.eye(3)).max() < 0.02
+    # other steps and seeds give other points; the same arguments the same points
+    assert not np.array_equal(u[:100], O.train_points(1234, 8, 100))
+    assert not np.array_equal(u[:100], O.train_points(1235, 7, 100))
+    assert np.array_equal(u[:100], O.train_points(1234, 7, 100))
+
+
+def _grid_of(fn, dims):
+    z, y, x = np.meshgrid(*[np.arange(d, dtype=np.float64) for d in dims[::-1]], indexing="ij")
+    return fn(x, y, z).astype(np.float32)
+
+
+def test_grid_trilinear_is_exact_on_trilinear_fields():
+    # span{1, x, y, z, xy, xz, yz, xyz} is reproduced exactly inside each cell
+    dims = (9, 7, 5)
+    fn = lambda x, y, z: 0.25 + 0.5 * x - 0.25 * y + 0.125 * z + 0.0625 * x * y * z
+    g = _grid_of(fn, dims)
+    rng = np.random.default_rng(3)
+    V = np.array(dims, np.float64)
+    x = rng.uniform(0.0, 1.0, size=(500, 3)) * (V - 1)
+    u = (x + 0.5) / V
+    ref = fn(x[:, 0], x[:, 1], x[:, 2])
+    np.testing.assert_allclose(O.grid_trilinear(g, u), ref, rtol=0, atol=1e-12)
+
+
+def test_grid_trilinear_at_voxel_centres_and_clamped_outside():
+    dims = (4, 4, 4)
+    g = np.random.default_rng(5).uniform(size=(4, 4, 4)).astype(np.float32)
+    i = np.array([[0, 0, 0], [3, 1, 2], [2, 3, 3]])
+    u = (i + 0.5) / 4.0
+    np.testing.assert_array_equal(O.grid_trilinear(g, u), g[i[:, 2], i[:, 1], i[:, 0]].astype(np.float64))
+    # below the first sample centre and above the last one: the boundary samples
+    u = np.array([[0.0, 0.0, 0.0], [0.9999, 0.9999, 0.9999]])
+    np.testing.assert_array_equal(O.grid_trilinear(g, u), [g[0, 0, 0], g[3, 3, 3]])
