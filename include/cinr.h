@@ -283,6 +283,61 @@ cinr_status cinr_collect_timing(cinr_volume vol, double* ms, int64_t* launches);
 cinr_status cinr_cache_dump(cinr_cache cache, int32_t kind, void* host_dst, size_t bytes, size_t* needed,
                             void* stream);
 
+/* ------------------------------------------------------------------------
+ * Training of the volume's INR (the learned part; Section 4.1 fits the INR
+ * to the data).  Loss: mean over a batch of (y - target)^2, with y the raw
+ * MLP output (no value normalisation) at points u in [0,1)^3.  Gradients flow
+ * through the MLP and the hash-grid interpolation into every table entry and
+ * weight; Adam (Kingma and Ba) updates all of them.  The trainer writes the
+ * volume's parameter buffers (d_table, d_weights) in place: they must be
+ * writable, and the volume's value_scale/value_offset should be 1/0.
+ *
+ * Points of step s: Philox-4x32-10 with counter (i, s) and key `seed`, 24 bits
+ * per coordinate.  Target of a point: trilinear interpolation of an explicit
+ * grid (f32 [Vz][Vy][Vx], x fastest) at x = clamp(u * V - 0.5, 0, V - 1).
+ * Supported shapes are those of cinr_infer_points; the MLP runs in F32 or
+ * BF16 (MFMA, FP32 accumulation), encoding and gradients in FP32.
+ * ------------------------------------------------------------------------ */
+typedef struct cinr_trainer_s* cinr_trainer;
+
+typedef struct {
+    int64_t batch;                /* points per step, >= 1 */
+    float lr, beta1, beta2, eps;  /* Adam; the step index s uses bias corrections of time s + 1 */
+    uint64_t seed;                /* key of the point generator */
+    int32_t mlp_dtype;            /* CINR_F32 or CINR_BF16 */
+} cinr_train_desc;
+
+/* Size of the caller-provided training workspace (Adam moments, gradients,
+ * per-wave partial sums, one batch of points and targets). */
+cinr_status cinr_train_workspace_size(cinr_volume vol, const cinr_train_desc* desc, size_t* bytes);
+/* Creates a trainer over a caller workspace; zeroes the Adam moments and
+ * gradients on `stream`.  The volume must outlive the trainer. */
+cinr_status cinr_train_create(cinr_volume vol, const cinr_train_desc* desc, void* d_workspace, size_t ws_bytes,
+                              void* stream, cinr_trainer* out);
+void cinr_train_destroy(cinr_trainer t);
+/* The `batch` points of step `step` into d_u (f32 [batch][3]) and, when
+ * d_grid is given (dims grid_dims[3] = Vx, Vy, Vz), their targets into
+ * d_target (f32 [batch]). */
+cinr_status cinr_train_points(cinr_trainer t, const float* d_grid, const int32_t* grid_dims, int64_t step,
+                              float* d_u, float* d_target, void* stream);
+/* Loss (f32 [1], nullable) and gradients of n caller points: d_g_table
+ * (f32 [entries][F], level-major like the table) and d_g_weights (f32, the
+ * weight layout) are overwritten.  Uses the trainer's partial-sum buffer. */
+cinr_status cinr_train_gradients(cinr_trainer t, const float* d_u, const float* d_target, int64_t n, float* d_loss,
+                                 float* d_g_table, float* d_g_weights, void* stream);
+/* One training step: points and targets of `step`, gradients, Adam on the
+ * volume's parameters.  d_loss (nullable) receives the batch loss before the
+ * update. */
+cinr_status cinr_train_step(cinr_trainer t, const float* d_grid, const int32_t* grid_dims, int64_t step,
+                            float* d_loss, void* stream);
+/* Learning rate of the following steps (for schedules). */
+cinr_status cinr_train_set_lr(cinr_trainer t, float lr);
+/* Elementwise Adam update of n parameters: m = b1 m + (1-b1) g, v = b2 v +
+ * (1-b2) g^2, p -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps);
+ * step >= 1; the gradient is zeroed afterwards when clear_grad != 0. */
+cinr_status cinr_adam_update(float* d_p, float* d_m, float* d_v, float* d_g, int64_t n, int64_t step, float lr,
+                             float beta1, float beta2, float eps, int32_t clear_grad, void* stream);
+
 /* Thread-local description of the last failure. */
 const char* cinr_last_error(void);
 

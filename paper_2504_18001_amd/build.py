@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libcinr.so")
-SOURCES = ["inr.hip", "render.hip", "cache.hip", "api.hip"]
+SOURCES = ["inr.hip", "render.hip", "cache.hip", "train.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -ffp-contract=off: the sampler's decision plane is a fixed sequence of

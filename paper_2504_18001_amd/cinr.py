@@ -57,6 +57,11 @@ class RenderParams(C.Structure):
                 ("mlp_dtype", C.c_int32), ("pipe_depth", C.c_int32), ("xcd_bands", C.c_int32)]
 
 
+class TrainDesc(C.Structure):
+    _fields_ = [("batch", C.c_int64), ("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float), ("seed", C.c_uint64), ("mlp_dtype", C.c_int32)]
+
+
 STAGES = ("setup", "march", "infer", "shade", "cm", "decode")
 STAT_FIELDS = ("rays", "samples", "hits", "fallbacks", "misses", "skipped", "requested", "selected", "evicted",
                "iterations")
@@ -89,6 +94,14 @@ def lib():
             "cinr_last_error": [],
             "cinr_set_timing": [P, i32],
             "cinr_collect_timing": [P, P, P],
+            "cinr_train_workspace_size": [P, P, P],
+            "cinr_train_create": [P, P, P, sz, P, P],
+            "cinr_train_destroy": [P],
+            "cinr_train_points": [P, P, P, i64, P, P, P],
+            "cinr_train_gradients": [P, P, P, i64, P, P, P, P],
+            "cinr_train_step": [P, P, P, i64, P, P],
+            "cinr_adam_update": [P, P, P, P, i64, i64, C.c_float, C.c_float, C.c_float, C.c_float, i32, P],
+            "cinr_train_set_lr": [P, C.c_float],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -96,6 +109,7 @@ def lib():
             f.restype = C.c_int
         L.cinr_destroy_volume.restype = None
         L.cinr_destroy_cache.restype = None
+        L.cinr_train_destroy.restype = None
         L.cinr_last_error.restype = C.c_char_p
         _lib = L
     return _lib
@@ -304,3 +318,71 @@ class Renderer:
     def last_stats(self):
         v = self._last_stats.cpu().numpy()
         return {k: int(v[i]) for i, k in enumerate(STAT_FIELDS)}
+
+
+class Trainer:
+    """GPU training of a Volume's INR (its table and weights are updated in
+    place) against an explicit grid; Adam state lives in a torch workspace."""
+
+    def __init__(self, volume: Volume, batch=1 << 18, lr=1e-2, beta1=0.9, beta2=0.99, eps=1e-15, seed=0,
+                 dtype="bf16"):
+        self.volume = volume
+        d = TrainDesc()
+        d.batch, d.lr, d.beta1, d.beta2, d.eps = int(batch), float(lr), float(beta1), float(beta2), float(eps)
+        d.seed, d.mlp_dtype = int(seed) & 0xFFFFFFFFFFFFFFFF, _dtype(dtype)
+        self.desc = d
+        ws = C.c_size_t()
+        _check(lib().cinr_train_workspace_size(volume.h, C.byref(d), C.byref(ws)))
+        self.workspace = torch.empty(ws.value, dtype=torch.uint8, device=volume.table.device)
+        h = C.c_void_p()
+        _check(lib().cinr_train_create(volume.h, C.byref(d), _ptr(self.workspace), ws.value, _stream(), C.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.cinr_train_destroy(self.h)
+            self.h = None
+
+    @staticmethod
+    def _grid(grid):
+        if grid is None:
+            return None, None
+        dims = np.array([grid.shape[2], grid.shape[1], grid.shape[0]], np.int32)
+        return grid.contiguous(), dims
+
+    def points(self, step, grid=None):
+        """(u [batch][3], target [batch] or None) of training step `step`."""
+        g, dims = self._grid(grid)
+        dev = self.volume.table.device
+        u = torch.empty((self.desc.batch, 3), dtype=torch.float32, device=dev)
+        t = torch.empty(self.desc.batch, dtype=torch.float32, device=dev) if g is not None else None
+        _check(lib().cinr_train_points(self.h, _ptr(g), dims.ctypes.data_as(C.c_void_p) if dims is not None else None,
+                                       int(step), _ptr(u), _ptr(t), _stream()))
+        return u, t
+
+    def gradients(self, u, target):
+        """(loss, table gradient [entries][F], weight gradient) of the given points."""
+        u = u.contiguous()
+        target = target.contiguous()
+        v = self.volume
+        gt = torch.empty_like(v.table)
+        gw = torch.empty_like(v.weights)
+        loss = torch.empty(1, dtype=torch.float32, device=u.device)
+        _check(lib().cinr_train_gradients(self.h, _ptr(u), _ptr(target), u.shape[0], _ptr(loss), _ptr(gt), _ptr(gw),
+                                          _stream()))
+        return loss, gt, gw
+
+    def set_lr(self, lr):
+        _check(lib().cinr_train_set_lr(self.h, float(lr)))
+
+    def step(self, grid, step, loss=None):
+        """One Adam step on batch `step`; `loss` (f32 [1] tensor) receives the batch loss."""
+        g, dims = self._grid(grid)
+        _check(lib().cinr_train_step(self.h, _ptr(g), dims.ctypes.data_as(C.c_void_p), int(step), _ptr(loss),
+                                     _stream()))
+
+
+def adam_update(p, m, v, g, step, lr=1e-2, beta1=0.9, beta2=0.99, eps=1e-15, clear_grad=False):
+    """In-place Adam update of float32 tensors (the trainer's optimiser)."""
+    _check(lib().cinr_adam_update(_ptr(p), _ptr(m), _ptr(v), _ptr(g), p.numel(), int(step), float(lr), float(beta1),
+                                  float(beta2), float(eps), 1 if clear_grad else 0, _stream()))

@@ -101,6 +101,7 @@ struct cinr_volume_s {
     InrDev m;
     int32_t n_cells = 0;
     int32_t M[3] = {0, 0, 0};
+    int64_t table_entries = 0;  // hash-table entries over all levels
     int32_t* pinned = nullptr;  // readback of the live-ray count
     hipEvent_t ev = nullptr;
     Timing timing;
@@ -191,6 +192,7 @@ extern "C" cinr_status cinr_create_volume_inr(const cinr_volume_desc* d, cinr_vo
             return fail(CINR_INVALID_ARG, "hash table too large");
         }
     }
+    v->table_entries = (int64_t)off;
     m.value_scale = d->value_scale;
     m.value_offset = d->value_offset;
     m.table = d->d_table;
@@ -697,5 +699,176 @@ extern "C" cinr_status cinr_cache_dump(cinr_cache c, int32_t kind, void* dst, si
             return a.pix != b.pix ? a.pix < b.pix : a.k < b.k;
         });
     }
+    return CINR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Training (the learned part)
+// ---------------------------------------------------------------------------
+
+struct cinr_trainer_s {
+    cinr_volume vol;
+    cinr_train_desc desc;
+    int64_t n_table, n_weights, max_waves;
+    float *m_t, *v_t, *g_t, *m_w, *v_w, *g_w, *partial, *u, *target, *loss;
+};
+
+namespace {
+
+cinr_status check_train(cinr_volume v, const cinr_train_desc* d) {
+    if (!v || !d) return fail(CINR_INVALID_ARG, "null argument");
+    if (!train_shape_supported(v->m))
+        return fail(CINR_UNSUPPORTED, "no training kernel for %d levels x %d features, hidden width %d",
+                    v->m.n_levels, v->m.n_features, v->m.hidden);
+    if (d->mlp_dtype != CINR_F32 && d->mlp_dtype != CINR_BF16)
+        return fail(CINR_UNSUPPORTED, "training runs its MLP in F32 or BF16 (dtype %d)", d->mlp_dtype);
+    if (d->batch < 1 || d->batch > (1ll << 31)) return fail(CINR_INVALID_ARG, "batch = %lld", (long long)d->batch);
+    if (!(d->lr > 0.0f) || !(d->beta1 >= 0.0f && d->beta1 < 1.0f) || !(d->beta2 >= 0.0f && d->beta2 < 1.0f) ||
+        !(d->eps >= 0.0f))
+        return fail(CINR_INVALID_ARG, "Adam needs lr > 0, 0 <= beta < 1, eps >= 0");
+    return CINR_OK;
+}
+
+int64_t train_waves() {
+    int dev = 0, n_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1024;
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu < 1) return 1024;
+    return 4ll * n_cu;
+}
+
+size_t train_layout(const cinr_train_desc* d, int64_t n_table, int64_t nw, int64_t waves, cinr_trainer_s* t,
+                    void* base) {
+    Carver cv(base);
+    cinr_trainer_s x{};
+    x.m_t = cv.take<float>(n_table);
+    x.v_t = cv.take<float>(n_table);
+    x.g_t = cv.take<float>(n_table);
+    x.m_w = cv.take<float>(nw);
+    x.v_w = cv.take<float>(nw);
+    x.g_w = cv.take<float>(nw);
+    x.partial = cv.take<float>((size_t)waves * (nw + 1));
+    x.u = cv.take<float>((size_t)d->batch * 3);
+    x.target = cv.take<float>(d->batch);
+    x.loss = cv.take<float>(1);
+    if (t) {
+        t->m_t = x.m_t;
+        t->v_t = x.v_t;
+        t->g_t = x.g_t;
+        t->m_w = x.m_w;
+        t->v_w = x.v_w;
+        t->g_w = x.g_w;
+        t->partial = x.partial;
+        t->u = x.u;
+        t->target = x.target;
+        t->loss = x.loss;
+    }
+    return cv.off;
+}
+
+cinr_status check_grid(const float* grid, const int32_t* dims) {
+    if (!grid) return CINR_OK;
+    if (!dims) return fail(CINR_INVALID_ARG, "grid without dimensions");
+    for (int a = 0; a < 3; ++a)
+        if (dims[a] < 1 || dims[a] > (1 << 24)) return fail(CINR_INVALID_ARG, "grid dims[%d] = %d", a, dims[a]);
+    return CINR_OK;
+}
+
+}  // namespace
+
+extern "C" cinr_status cinr_train_workspace_size(cinr_volume v, const cinr_train_desc* d, size_t* bytes) {
+    cinr_status st = check_train(v, d);
+    if (st) return st;
+    if (!bytes) return fail(CINR_INVALID_ARG, "null argument");
+    const int64_t nt = v->table_entries * v->m.n_features;
+    *bytes = train_layout(d, nt, train_n_weights(v->m), train_waves(), nullptr, nullptr);
+    return CINR_OK;
+}
+
+extern "C" cinr_status cinr_train_create(cinr_volume v, const cinr_train_desc* d, void* d_ws, size_t ws_bytes,
+                                         void* stream, cinr_trainer* out) {
+    cinr_status st = check_train(v, d);
+    if (st) return st;
+    if (!out) return fail(CINR_INVALID_ARG, "null argument");
+    const int64_t nt = v->table_entries * v->m.n_features, nw = train_n_weights(v->m), waves = train_waves();
+    const size_t need = train_layout(d, nt, nw, waves, nullptr, nullptr);
+    if (!d_ws || ws_bytes < need) return fail(CINR_OUT_OF_MEMORY, "training workspace of %zu bytes < %zu needed", ws_bytes, need);
+    cinr_trainer t = new cinr_trainer_s();
+    t->vol = v;
+    t->desc = *d;
+    t->n_table = nt;
+    t->n_weights = nw;
+    t->max_waves = waves;
+    train_layout(d, nt, nw, waves, t, d_ws);
+    hipStream_t s = (hipStream_t)stream;
+    // Adam moments and the table gradient start at zero
+    hipError_t e = fill_f32(t->m_t, nt, 0.0f, s);
+    if (e == hipSuccess) e = fill_f32(t->v_t, nt, 0.0f, s);
+    if (e == hipSuccess) e = fill_f32(t->g_t, nt, 0.0f, s);
+    if (e == hipSuccess) e = fill_f32(t->m_w, nw, 0.0f, s);
+    if (e == hipSuccess) e = fill_f32(t->v_w, nw, 0.0f, s);
+    if (e == hipSuccess) e = fill_f32(t->g_w, nw, 0.0f, s);
+    if (e != hipSuccess) {
+        delete t;
+        return fail(CINR_HIP_ERROR, "initialising the trainer: %s", hipGetErrorString(e));
+    }
+    *out = t;
+    return CINR_OK;
+}
+
+extern "C" void cinr_train_destroy(cinr_trainer t) { delete t; }
+
+extern "C" cinr_status cinr_train_points(cinr_trainer t, const float* d_grid, const int32_t* grid_dims, int64_t step,
+                                         float* d_u, float* d_target, void* stream) {
+    if (!t || !d_u || (d_grid && !d_target)) return fail(CINR_INVALID_ARG, "null argument");
+    if (step < 0) return fail(CINR_INVALID_ARG, "step < 0");
+    cinr_status st = check_grid(d_grid, grid_dims);
+    if (st) return st;
+    HIP_TRY(train_points(t->desc.seed, step, t->desc.batch, d_grid, grid_dims, d_u, d_target, (hipStream_t)stream));
+    return CINR_OK;
+}
+
+extern "C" cinr_status cinr_train_gradients(cinr_trainer t, const float* d_u, const float* d_target, int64_t n,
+                                            float* d_loss, float* d_g_table, float* d_g_weights, void* stream) {
+    if (!t || !d_g_table || !d_g_weights || (n > 0 && (!d_u || !d_target))) return fail(CINR_INVALID_ARG, "null argument");
+    if (n < 0 || n > (1ll << 31)) return fail(CINR_INVALID_ARG, "n = %lld", (long long)n);
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(fill_f32(d_g_table, t->n_table, 0.0f, s));
+    HIP_TRY(train_gradients(t->vol->m, t->desc.mlp_dtype, d_u, d_target, n, n > 0 ? 2.0f / (float)n : 0.0f, d_g_table,
+                            d_g_weights, d_loss, t->partial, t->max_waves, s));
+    return CINR_OK;
+}
+
+extern "C" cinr_status cinr_train_step(cinr_trainer t, const float* d_grid, const int32_t* grid_dims, int64_t step,
+                                       float* d_loss, void* stream) {
+    if (!t || !d_grid) return fail(CINR_INVALID_ARG, "null argument");
+    if (step < 0) return fail(CINR_INVALID_ARG, "step < 0");
+    cinr_status st = check_grid(d_grid, grid_dims);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const cinr_train_desc& d = t->desc;
+    const int64_t n = d.batch;
+    HIP_TRY(train_points(d.seed, step, n, d_grid, grid_dims, t->u, t->target, s));
+    // the table gradient is zero here: cleared at creation and by every Adam update
+    HIP_TRY(train_gradients(t->vol->m, d.mlp_dtype, t->u, t->target, n, 2.0f / (float)n, t->g_t, t->g_w,
+                            d_loss ? d_loss : t->loss, t->partial, t->max_waves, s));
+    float* table = const_cast<float*>(t->vol->desc.d_table);
+    float* weights = const_cast<float*>(t->vol->desc.d_weights);
+    HIP_TRY(adam_update(table, t->m_t, t->v_t, t->g_t, t->n_table, d.lr, d.beta1, d.beta2, d.eps, step + 1, true, s));
+    HIP_TRY(adam_update(weights, t->m_w, t->v_w, t->g_w, t->n_weights, d.lr, d.beta1, d.beta2, d.eps, step + 1, false, s));
+    return CINR_OK;
+}
+
+extern "C" cinr_status cinr_train_set_lr(cinr_trainer t, float lr) {
+    if (!t) return fail(CINR_INVALID_ARG, "null argument");
+    if (!(lr > 0.0f) || !isfinite(lr)) return fail(CINR_INVALID_ARG, "lr must be > 0");
+    t->desc.lr = lr;
+    return CINR_OK;
+}
+
+extern "C" cinr_status cinr_adam_update(float* d_p, float* d_m, float* d_v, float* d_g, int64_t n, int64_t step,
+                                        float lr, float beta1, float beta2, float eps, int32_t clear_grad, void* stream) {
+    if (n < 0 || (n > 0 && (!d_p || !d_m || !d_v || !d_g))) return fail(CINR_INVALID_ARG, "null argument");
+    if (step < 1) return fail(CINR_INVALID_ARG, "Adam steps count from 1");
+    HIP_TRY(adam_update(d_p, d_m, d_v, d_g, n, lr, beta1, beta2, eps, step, clear_grad != 0, (hipStream_t)stream));
     return CINR_OK;
 }

@@ -190,4 +190,16 @@ hipError_t inr_macrocells(const InrDev& m, int32_t N, float* minmax, int prec, h
 hipError_t inr_infer_misses(const InrDev& m, const float4* rec, const uint32_t* n_dev, int64_t cap, float* vals,
                             int prec, hipStream_t s);
 
+// train.hip launchers
+bool train_shape_supported(const InrDev& m);
+int32_t train_n_weights(const InrDev& m);
+hipError_t train_gradients(const InrDev& m, int prec, const float* u, const float* target, int64_t n, float scale,
+                           float* g_table, float* g_weights, float* loss, float* partial, int64_t max_waves,
+                           hipStream_t s);
+hipError_t train_points(uint64_t seed, int64_t step, int64_t n, const float* grid, const int32_t dims[3], float* u,
+                        float* target, hipStream_t s);
+hipError_t adam_update(float* p, float* m1, float* m2, float* g, int64_t n, float lr, float b1, float b2, float eps,
+                       int64_t step, bool clear, hipStream_t s);
+hipError_t fill_f32(float* p, int64_t n, float v, hipStream_t s);
+
 }  // namespace cinr

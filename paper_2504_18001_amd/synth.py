@@ -219,6 +219,33 @@ def fourier_modes(n_modes=512, kmax=128, seed=0):
     return k, amp, ph
 
 
+def fourier_field(V: int, modes, device="cpu", z_block=32):
+    """The periodic field sum_j A_j cos(2 pi k_j . x / V + phi_j) on the V^3
+    lattice x in [0, V)^3, normalised to [0, 1] by its minimum and maximum;
+    float32 [V][V][V] (z, y, x).  Evaluated as a separable complex product
+    (per z slice a [V x J] by [J x V] product) with torch on `device`."""
+    import torch
+    k, amp, ph = modes
+    dev = torch.device(device)
+    kk = torch.as_tensor(k, dtype=torch.float64, device=dev)
+    c = torch.as_tensor(amp, dtype=torch.float64, device=dev) * torch.exp(
+        1j * torch.as_tensor(ph, dtype=torch.float64, device=dev))
+    xs = torch.arange(V, dtype=torch.float64, device=dev)
+    # E_a[j][x] = exp(i 2 pi k_ja x / V)
+    E = [torch.exp(2j * math.pi * kk[:, a:a + 1] * xs[None, :] / V) for a in range(3)]
+    ex = E[0].to(torch.complex64)  # [J][V]
+    out = torch.empty((V, V, V), dtype=torch.float32, device=dev)
+    for z0 in range(0, V, z_block):
+        z1 = min(V, z0 + z_block)
+        # P[z][y][j] = c_j Ez[j][z] Ey[j][y]
+        pz = (c[:, None] * E[2][:, z0:z1]).T  # [Z][J]
+        P = (pz[:, None, :] * E[1].T[None, :, :]).to(torch.complex64)  # [Z][V(y)][J]
+        out[z0:z1] = torch.matmul(P.real, ex.real) - torch.matmul(P.imag, ex.imag)
+    lo, hi = out.min(), out.max()
+    out.sub_(lo).div_(hi - lo)
+    return out
+
+
 # ----------------------------------------------------------------------------
 # Random brick requests / residency
 # ----------------------------------------------------------------------------
