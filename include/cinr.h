@@ -196,6 +196,22 @@ typedef struct cinr_cache_s* cinr_cache;
 /* Validates the description and binds the borrowed parameter buffers.
  * Computes the per-level table layout on the host.  No device work. */
 cinr_status cinr_create_volume_inr(const cinr_volume_desc* desc, cinr_volume* out);
+
+/* A volume defined by an explicit voxel grid (the fallback source of the
+ * learned part and the reference its INR is judged against): d_grid is f32
+ * [Vz][Vy][Vx], x fastest, borrowed for the volume's lifetime.  The value at
+ * voxel coordinate x is the trilinear interpolation of the samples at x
+ * (clamped to [0, V-1]), then clamp(value_scale * v + value_offset, 0, 1).
+ * Every volume operation accepts it (their mlp_dtype arguments are
+ * ignored); training does not. */
+typedef struct {
+    int32_t dims[3];       /* >= 2 each */
+    const float* d_grid;
+    float value_scale, value_offset;
+    const float* d_macrocells;  /* optional, as for INR volumes */
+    int32_t macrocell_size;
+} cinr_grid_desc;
+cinr_status cinr_create_volume_grid(const cinr_grid_desc* desc, cinr_volume* out);
 void cinr_destroy_volume(cinr_volume vol);
 
 /* LoD lattice and bricks of Section 4.3.2: at LoD L the lattice step is 2^L,

@@ -181,22 +181,53 @@ void orc_mlp(const orc_inr* m, const double* feat, int64_t n, double* y) {
     for (int64_t i = 0; i < n; ++i) y[i] = mlp_one(m, feat + nf * i);
 }
 
+/* Trilinear interpolation of the explicit grid at voxel coordinate x
+ * (clamped to [0, V-1]; the last cell serves the upper faces). */
+static double grid_value(const orc_inr* m, const double x[3]) {
+    int64_t j[3];
+    double f[3];
+    for (int a = 0; a < 3; ++a) {
+        double xa = x[a];
+        const double hi = (double)(m->dims[a] - 1);
+        if (xa < 0.0) xa = 0.0;
+        if (xa > hi) xa = hi;
+        int64_t ja = (int64_t)floor(xa);
+        if (ja > m->dims[a] - 2) ja = m->dims[a] - 2;
+        j[a] = ja;
+        f[a] = xa - (double)ja;
+    }
+    const int64_t sy = m->dims[0], sz = (int64_t)m->dims[0] * m->dims[1];
+    double v = 0.0;
+    for (int k = 0; k < 8; ++k) {
+        const int bx = k & 1, by = (k >> 1) & 1, bz = k >> 2;
+        const double w = (bx ? f[0] : 1.0 - f[0]) * (by ? f[1] : 1.0 - f[1]) * (bz ? f[2] : 1.0 - f[2]);
+        v += w * (double)m->grid[(j[2] + bz) * sz + (j[1] + by) * sy + j[0] + bx];
+    }
+    return v;
+}
+
 /* Normalised INR value at LoD-0 voxel coordinate x: the coordinate is
  * clamped to [0, V-1], mapped to u = (x + 0.5) / V inside (0,1)^3, encoded,
  * passed through the MLP, then de-normalised with the stored value range and
- * clamped to [0,1] (Section 4.1: training runs on [0,1)^3 and [0,1] data). */
+ * clamped to [0,1] (Section 4.1: training runs on [0,1)^3 and [0,1] data).
+ * An explicit-grid source replaces encoding and MLP by grid_value. */
 static double value_one(const orc_inr* m, const double x[3]) {
     double u[3];
     double feat[ORC_MAX_LEVELS * 8];
-    for (int a = 0; a < 3; ++a) {
-        double xa = x[a];
-        double hi = (double)(m->dims[a] - 1);
-        if (xa < 0.0) xa = 0.0;
-        if (xa > hi) xa = hi;
-        u[a] = (xa + 0.5) / (double)m->dims[a];
+    double y;
+    if (m->grid) {
+        y = grid_value(m, x);
+    } else {
+        for (int a = 0; a < 3; ++a) {
+            double xa = x[a];
+            double hi = (double)(m->dims[a] - 1);
+            if (xa < 0.0) xa = 0.0;
+            if (xa > hi) xa = hi;
+            u[a] = (xa + 0.5) / (double)m->dims[a];
+        }
+        encode_one(m, u, feat);
+        y = mlp_one(m, feat);
     }
-    encode_one(m, u, feat);
-    double y = mlp_one(m, feat);
     double v = (double)m->value_scale * y + (double)m->value_offset;
     if (v < 0.0) v = 0.0;
     if (v > 1.0) v = 1.0;

@@ -40,6 +40,10 @@ typedef struct {
     float value_scale, value_offset;
     const float* table;
     const float* weights;
+    /* explicit-grid source: when set, the value at voxel coordinate x is the
+     * trilinear interpolation of these f32 [Vz][Vy][Vx] samples at x (clamped)
+     * instead of the INR, before the same normalisation */
+    const float* grid;
 } orc_inr;
 
 typedef struct {

@@ -24,7 +24,8 @@ class Inr(C.Structure):
     _fields_ = [("dims", C.c_int32 * 3), ("n_levels", C.c_int32), ("n_features", C.c_int32),
                 ("log2_table", C.c_int32), ("level_res", C.c_int32 * MAX_LEVELS), ("n_layers", C.c_int32),
                 ("widths", C.c_int32 * (MAX_LAYERS + 1)), ("value_scale", C.c_float),
-                ("value_offset", C.c_float), ("table", C.c_void_p), ("weights", C.c_void_p)]
+                ("value_offset", C.c_float), ("table", C.c_void_p), ("weights", C.c_void_p),
+                ("grid", C.c_void_p)]
 
 
 class Camera(C.Structure):
@@ -155,6 +156,23 @@ class OracleInr:
 
     def ref(self):
         return C.byref(self.desc)
+
+    @classmethod
+    def from_grid(cls, grid, value_scale=1.0, value_offset=0.0):
+        """A value source backed by an explicit grid (float32 [Vz][Vy][Vx]):
+        trilinear at voxel coordinates, then the same normalisation."""
+        self = cls.__new__(cls)
+        self.arch = None
+        self.grid = np.ascontiguousarray(grid, dtype=np.float32)
+        d = Inr()
+        dims = (self.grid.shape[2], self.grid.shape[1], self.grid.shape[0])
+        for a in range(3):
+            d.dims[a] = int(dims[a])
+        d.value_scale, d.value_offset = float(value_scale), float(value_offset)
+        d.grid = self.grid.ctypes.data
+        self.desc = d
+        self.dims = tuple(int(x) for x in dims)
+        return self
 
     def encode(self, u):
         u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1, 3)

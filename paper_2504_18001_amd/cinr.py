@@ -57,6 +57,11 @@ class RenderParams(C.Structure):
                 ("mlp_dtype", C.c_int32), ("pipe_depth", C.c_int32), ("xcd_bands", C.c_int32)]
 
 
+class GridDesc(C.Structure):
+    _fields_ = [("dims", C.c_int32 * 3), ("d_grid", C.c_void_p), ("value_scale", C.c_float),
+                ("value_offset", C.c_float), ("d_macrocells", C.c_void_p), ("macrocell_size", C.c_int32)]
+
+
 class TrainDesc(C.Structure):
     _fields_ = [("batch", C.c_int64), ("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
                 ("eps", C.c_float), ("seed", C.c_uint64), ("mlp_dtype", C.c_int32)]
@@ -79,6 +84,7 @@ def lib():
         P, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
         sig = {
             "cinr_create_volume_inr": [P, P],
+            "cinr_create_volume_grid": [P, P],
             "cinr_destroy_volume": [P],
             "cinr_lod_geometry": [P, i32, i32, P, P],
             "cinr_infer_points": [P, P, i64, P, i32, P],
@@ -132,39 +138,8 @@ def _dtype(d):
     return DTYPES[d] if isinstance(d, str) else int(d)
 
 
-class Volume:
-    """A volume defined by a hash-grid INR whose parameters live on the GPU."""
-
-    def __init__(self, arch, table, weights, value_scale=1.0, value_offset=0.0, macrocells=None, macro_cell=0,
-                 dims=None, device="cuda"):
-        self.arch = arch
-        self.dims = tuple(int(x) for x in (arch.dims if dims is None else dims))
-        self.table = torch.as_tensor(np.asarray(table, np.float32)).to(device).contiguous() \
-            if not torch.is_tensor(table) else table.to(device=device, dtype=torch.float32).contiguous()
-        self.weights = torch.as_tensor(np.asarray(weights, np.float32)).to(device).contiguous() \
-            if not torch.is_tensor(weights) else weights.to(device=device, dtype=torch.float32).contiguous()
-        self.macrocells = None
-        if macrocells is not None:
-            mc = macrocells if torch.is_tensor(macrocells) else torch.as_tensor(np.asarray(macrocells, np.float32))
-            self.macrocells = mc.to(device=device, dtype=torch.float32).contiguous()
-        d = VolumeDesc()
-        for a in range(3):
-            d.dims[a] = self.dims[a]
-        d.n_levels, d.n_features, d.log2_table = arch.n_levels, arch.n_features, arch.log2_table
-        for l, n in enumerate(arch.level_res):
-            d.level_res[l] = n
-        d.n_layers = len(arch.widths) - 1
-        for i, w in enumerate(arch.widths):
-            d.widths[i] = w
-        d.value_scale, d.value_offset = float(value_scale), float(value_offset)
-        d.d_table = self.table.data_ptr()
-        d.d_weights = self.weights.data_ptr()
-        d.d_macrocells = self.macrocells.data_ptr() if self.macrocells is not None else None
-        d.macrocell_size = int(macro_cell) if self.macrocells is not None else 0
-        self.desc = d
-        h = C.c_void_p()
-        _check(lib().cinr_create_volume_inr(C.byref(d), C.byref(h)))
-        self.h = h
+class _VolumeOps:
+    """Operations shared by INR and grid volumes (handle `h`, `dims`, `device`)."""
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -204,9 +179,71 @@ class Volume:
 
     def build_macrocells(self, cell, dtype="f32"):
         M = [(d + cell - 1) // cell for d in self.dims]
-        out = torch.empty((M[2], M[1], M[0], 2), dtype=torch.float32, device=self.table.device)
+        out = torch.empty((M[2], M[1], M[0], 2), dtype=torch.float32, device=self.device)
         _check(lib().cinr_build_macrocells(self.h, cell, _ptr(out), _dtype(dtype), _stream()))
         return out
+
+
+class GridVolume(_VolumeOps):
+    """A volume defined by an explicit voxel grid (f32 [Vz][Vy][Vx] on the GPU)."""
+
+    def __init__(self, grid, value_scale=1.0, value_offset=0.0, macrocells=None, macro_cell=0):
+        self.grid = grid.to(torch.float32).contiguous()
+        self.device = self.grid.device
+        self.dims = (int(grid.shape[2]), int(grid.shape[1]), int(grid.shape[0]))
+        self.macrocells = None
+        if macrocells is not None:
+            self.macrocells = macrocells.to(device=self.device, dtype=torch.float32).contiguous()
+        d = GridDesc()
+        for a in range(3):
+            d.dims[a] = self.dims[a]
+        d.d_grid = self.grid.data_ptr()
+        d.value_scale, d.value_offset = float(value_scale), float(value_offset)
+        d.d_macrocells = self.macrocells.data_ptr() if self.macrocells is not None else None
+        d.macrocell_size = int(macro_cell) if self.macrocells is not None else 0
+        self.desc = d
+        h = C.c_void_p()
+        _check(lib().cinr_create_volume_grid(C.byref(d), C.byref(h)))
+        self.h = h
+
+
+class Volume(_VolumeOps):
+    """A volume defined by a hash-grid INR whose parameters live on the GPU."""
+
+    def __init__(self, arch, table, weights, value_scale=1.0, value_offset=0.0, macrocells=None, macro_cell=0,
+                 dims=None, device="cuda"):
+        self.arch = arch
+        self.dims = tuple(int(x) for x in (arch.dims if dims is None else dims))
+        self.table = torch.as_tensor(np.asarray(table, np.float32)).to(device).contiguous() \
+            if not torch.is_tensor(table) else table.to(device=device, dtype=torch.float32).contiguous()
+        self.weights = torch.as_tensor(np.asarray(weights, np.float32)).to(device).contiguous() \
+            if not torch.is_tensor(weights) else weights.to(device=device, dtype=torch.float32).contiguous()
+        self.macrocells = None
+        if macrocells is not None:
+            mc = macrocells if torch.is_tensor(macrocells) else torch.as_tensor(np.asarray(macrocells, np.float32))
+            self.macrocells = mc.to(device=device, dtype=torch.float32).contiguous()
+        d = VolumeDesc()
+        for a in range(3):
+            d.dims[a] = self.dims[a]
+        d.n_levels, d.n_features, d.log2_table = arch.n_levels, arch.n_features, arch.log2_table
+        for l, n in enumerate(arch.level_res):
+            d.level_res[l] = n
+        d.n_layers = len(arch.widths) - 1
+        for i, w in enumerate(arch.widths):
+            d.widths[i] = w
+        d.value_scale, d.value_offset = float(value_scale), float(value_offset)
+        d.d_table = self.table.data_ptr()
+        d.d_weights = self.weights.data_ptr()
+        d.d_macrocells = self.macrocells.data_ptr() if self.macrocells is not None else None
+        d.macrocell_size = int(macro_cell) if self.macrocells is not None else 0
+        self.desc = d
+        h = C.c_void_p()
+        _check(lib().cinr_create_volume_inr(C.byref(d), C.byref(h)))
+        self.h = h
+
+    @property
+    def device(self):
+        return self.table.device
 
 
 class Cache:
@@ -224,7 +261,7 @@ class Cache:
         self.desc = d
         ws = C.c_size_t()
         _check(lib().cinr_cache_workspace_size(volume.h, C.byref(d), C.byref(ws)))
-        dev = volume.table.device
+        dev = volume.device
         self.pool = torch.empty(max(pool_bricks, 1) * brick ** 3, dtype=torch.float32, device=dev)
         self.workspace = torch.empty(ws.value, dtype=torch.uint8, device=dev)
         h = C.c_void_p()

@@ -207,6 +207,37 @@ extern "C" cinr_status cinr_create_volume_inr(const cinr_volume_desc* d, cinr_vo
     return CINR_OK;
 }
 
+extern "C" cinr_status cinr_create_volume_grid(const cinr_grid_desc* d, cinr_volume* out) {
+    if (!d || !out || !d->d_grid) return fail(CINR_INVALID_ARG, "null argument");
+    for (int a = 0; a < 3; ++a)
+        if (d->dims[a] < 2 || d->dims[a] > (1 << 24)) return fail(CINR_INVALID_ARG, "dims[%d] = %d out of [2, 2^24]", a, d->dims[a]);
+    if (d->d_macrocells && d->macrocell_size < 1) return fail(CINR_INVALID_ARG, "macrocell_size must be >= 1");
+    cinr_volume v = new cinr_volume_s();
+    v->desc = cinr_volume_desc{};
+    for (int a = 0; a < 3; ++a) v->desc.dims[a] = d->dims[a];
+    v->desc.value_scale = d->value_scale;
+    v->desc.value_offset = d->value_offset;
+    v->desc.d_macrocells = d->d_macrocells;
+    v->desc.macrocell_size = d->macrocell_size;
+    InrDev& m = v->m;
+    m = InrDev{};
+    for (int a = 0; a < 3; ++a) {
+        m.dims[a] = d->dims[a];
+        m.vm1[a] = (float)(d->dims[a] - 1);
+        m.inv_dims[a] = 1.0 / (double)d->dims[a];
+    }
+    m.value_scale = d->value_scale;
+    m.value_offset = d->value_offset;
+    m.hidden = -1;
+    m.grid = d->d_grid;
+    if (d->d_macrocells) {
+        for (int a = 0; a < 3; ++a) v->M[a] = (d->dims[a] + d->macrocell_size - 1) / d->macrocell_size;
+        v->n_cells = v->M[0] * v->M[1] * v->M[2];
+    }
+    *out = v;
+    return CINR_OK;
+}
+
 extern "C" void cinr_destroy_volume(cinr_volume v) {
     if (!v) return;
     if (v->pinned) (void)hipHostFree(v->pinned);
@@ -261,6 +292,7 @@ extern "C" cinr_status cinr_lod_geometry(cinr_volume v, int32_t brick, int32_t n
 static cinr_status check_shape(cinr_volume v, int32_t prec) {
     if (prec != CINR_F32 && prec != CINR_BF16 && prec != CINR_F16 && prec != CINR_BF16X3)
         return fail(CINR_INVALID_ARG, "mlp_dtype = %d", prec);
+    if (v->m.grid) return CINR_OK;
     if (v->m.hidden < 0 || !inr_shape_supported(v->m))
         return fail(CINR_UNSUPPORTED, "no gfx950 kernel for this INR shape (3 layers, levels x features in {8x2, 16x2, 16x4}, hidden 32 or 64)");
     return CINR_OK;

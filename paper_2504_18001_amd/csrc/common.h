@@ -35,6 +35,7 @@ struct InrDev {
     const float* table;
     const float* weights;
     int32_t in, hidden;            // widths[0], hidden width
+    const float* grid;             // explicit-grid source (f32 [Vz][Vy][Vx]); null for an INR
 };
 
 // Exact unsigned division by a frame-invariant divisor d >= 1 for dividends

@@ -94,11 +94,11 @@ struct BrickDst {
 // Kernels
 // ---------------------------------------------------------------------------
 
-template <class Cfg, class Src, class Dst>
+template <class Eng, class Src, class Dst>
 __global__ __launch_bounds__(kBlock) void k_inr_points(const InrDev m, const Src src, const Dst dst) {
-    InrEngine<Cfg> eng;
+    Eng eng;
     eng.load_weights(m);
-    __shared__ typename InrEngine<Cfg>::Lds lds;
+    __shared__ typename Eng::Lds lds;
     const int64_t n = src.count();
     for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n; base += (int64_t)gridDim.x * kBlock) {
         const int64_t idx = base + threadIdx.x;
@@ -111,11 +111,11 @@ __global__ __launch_bounds__(kBlock) void k_inr_points(const InrDev m, const Src
 }
 
 // Brick decoding: like k_inr_points, invalid requests produce NaN bricks.
-template <class Cfg>
+template <class Eng>
 __global__ __launch_bounds__(kBlock) void k_decode(const InrDev m, const BrickSrc src, const BrickDst dst) {
-    InrEngine<Cfg> eng;
+    Eng eng;
     eng.load_weights(m);
-    __shared__ typename InrEngine<Cfg>::Lds lds;
+    __shared__ typename Eng::Lds lds;
     const int64_t n = src.count();
     for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n; base += (int64_t)gridDim.x * kBlock) {
         const int64_t idx = base + threadIdx.x;
@@ -129,12 +129,12 @@ __global__ __launch_bounds__(kBlock) void k_decode(const InrDev m, const BrickSr
 
 // Macro-cells (Section 5.2): one workgroup per cell, min/max of the lattice
 // values in the cell's closed region.
-template <class Cfg>
+template <class Eng>
 __global__ __launch_bounds__(kBlock) void k_macrocells(const InrDev m, int32_t N, int32_t Mx, int32_t My,
                                                        int32_t Mz, float* minmax) {
-    InrEngine<Cfg> eng;
+    Eng eng;
     eng.load_weights(m);
-    __shared__ typename InrEngine<Cfg>::Lds lds;
+    __shared__ typename Eng::Lds lds;
     __shared__ float red[2][kBlock / 64];
     const int64_t ncell = (int64_t)Mx * My * Mz;
     for (int64_t c = blockIdx.x; c < ncell; c += gridDim.x) {
@@ -216,13 +216,13 @@ static int grid_for(int64_t points, int max_blocks) {
 
 constexpr int kMaxInrBlocks = 256 * 8;  // 8 workgroups per CU on 256 CUs
 
-template <class Cfg>
+template <class Eng>
 static hipError_t launch_all(int what, const InrDev& m, const void* a, hipStream_t s) {
     switch (what) {
         case 0: {
             const PosSrc* src = (const PosSrc*)((const void* const*)a)[0];
             const LinearDst* dst = (const LinearDst*)((const void* const*)a)[1];
-            hipLaunchKernelGGL((k_inr_points<Cfg, PosSrc, LinearDst>), dim3(grid_for(src->n, kMaxInrBlocks)),
+            hipLaunchKernelGGL((k_inr_points<Eng, PosSrc, LinearDst>), dim3(grid_for(src->n, kMaxInrBlocks)),
                                dim3(kBlock), 0, s, m, *src, *dst);
             break;
         }
@@ -230,7 +230,7 @@ static hipError_t launch_all(int what, const InrDev& m, const void* a, hipStream
             const BrickSrc* src = (const BrickSrc*)((const void* const*)a)[0];
             const BrickDst* dst = (const BrickDst*)((const void* const*)a)[1];
             const int64_t cap = (int64_t)src->n_host * src->B3;
-            hipLaunchKernelGGL((k_decode<Cfg>), dim3(grid_for(cap, kMaxInrBlocks)), dim3(kBlock), 0, s, m, *src,
+            hipLaunchKernelGGL((k_decode<Eng>), dim3(grid_for(cap, kMaxInrBlocks)), dim3(kBlock), 0, s, m, *src,
                                *dst);
             break;
         }
@@ -238,7 +238,7 @@ static hipError_t launch_all(int what, const InrDev& m, const void* a, hipStream
             const int32_t* p = (const int32_t*)((const void* const*)a)[0];
             float* mm = (float*)((const void* const*)a)[1];
             const int64_t nc = (int64_t)p[1] * p[2] * p[3];
-            hipLaunchKernelGGL((k_macrocells<Cfg>), dim3((int)(nc < kMaxInrBlocks * 4 ? nc : kMaxInrBlocks * 4)),
+            hipLaunchKernelGGL((k_macrocells<Eng>), dim3((int)(nc < kMaxInrBlocks * 4 ? nc : kMaxInrBlocks * 4)),
                                dim3(kBlock), 0, s, m, p[0], p[1], p[2], p[3], mm);
             break;
         }
@@ -246,7 +246,7 @@ static hipError_t launch_all(int what, const InrDev& m, const void* a, hipStream
             const MissSrc* src = (const MissSrc*)((const void* const*)a)[0];
             const MissDst* dst = (const MissDst*)((const void* const*)a)[1];
             const int64_t cap = *(const int64_t*)((const void* const*)a)[2];
-            hipLaunchKernelGGL((k_inr_points<Cfg, MissSrc, MissDst>), dim3(grid_for(cap, kMaxInrBlocks)),
+            hipLaunchKernelGGL((k_inr_points<Eng, MissSrc, MissDst>), dim3(grid_for(cap, kMaxInrBlocks)),
                                dim3(kBlock), 0, s, m, *src, *dst);
             break;
         }
@@ -259,21 +259,23 @@ static hipError_t launch_all(int what, const InrDev& m, const void* a, hipStream
 template <int NL, int F, int H>
 static hipError_t dispatch_prec(int prec, int what, const InrDev& m, const void* a, hipStream_t s) {
     switch (prec) {
-        case CINR_F32: return launch_all<EngCfg<NL, F, H, CINR_F32>>(what, m, a, s);
-        case CINR_BF16: return launch_all<EngCfg<NL, F, H, CINR_BF16>>(what, m, a, s);
-        case CINR_F16: return launch_all<EngCfg<NL, F, H, CINR_F16>>(what, m, a, s);
-        case CINR_BF16X3: return launch_all<EngCfg<NL, F, H, CINR_BF16X3>>(what, m, a, s);
+        case CINR_F32: return launch_all<InrEngine<EngCfg<NL, F, H, CINR_F32>>>(what, m, a, s);
+        case CINR_BF16: return launch_all<InrEngine<EngCfg<NL, F, H, CINR_BF16>>>(what, m, a, s);
+        case CINR_F16: return launch_all<InrEngine<EngCfg<NL, F, H, CINR_F16>>>(what, m, a, s);
+        case CINR_BF16X3: return launch_all<InrEngine<EngCfg<NL, F, H, CINR_BF16X3>>>(what, m, a, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 bool inr_shape_supported(const InrDev& m) {
+    if (m.grid) return true;
     const int NL = m.n_levels, F = m.n_features, H = m.hidden;
     return (NL == 8 && F == 2 && H == 32) || (NL == 16 && F == 2 && H == 64) || (NL == 16 && F == 4 && H == 64) ||
            (NL == 8 && F == 2 && H == 64) || (NL == 16 && F == 2 && H == 32);
 }
 
 static hipError_t dispatch(int prec, int what, const InrDev& m, const void* a, hipStream_t s) {
+    if (m.grid) return launch_all<GridEngine>(what, m, a, s);
     const int NL = m.n_levels, F = m.n_features, H = m.hidden;
     if (NL == 8 && F == 2 && H == 32) return dispatch_prec<8, 2, 32>(prec, what, m, a, s);
     if (NL == 8 && F == 2 && H == 64) return dispatch_prec<8, 2, 64>(prec, what, m, a, s);

@@ -147,6 +147,39 @@ __device__ inline float finish_value(const InrDev& m, float y) {
     return v;
 }
 
+// Explicit voxel grid (the fallback source): trilinear interpolation of the
+// samples at voxel coordinate x (clamped to [0, V-1]; the last cell is used at
+// the upper faces), then the value normalisation.  Same interface as the INR
+// engines; no workgroup synchronisation.
+struct GridEngine {
+    struct Lds {
+        int unused;
+    };
+    __device__ void load_weights(const InrDev&) {}
+    __device__ float eval(const InrDev& m, const double x[3], Lds&) const {
+        int32_t j[3];
+        float f[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            float xa = (float)x[a];
+            xa = xa < 0.0f ? 0.0f : (xa > m.vm1[a] ? m.vm1[a] : xa);
+            int32_t ja = (int32_t)xa;
+            ja = ja > m.dims[a] - 2 ? m.dims[a] - 2 : ja;
+            j[a] = ja;
+            f[a] = xa - (float)ja;
+        }
+        const int64_t sy = m.dims[0], sz = (int64_t)m.dims[0] * m.dims[1];
+        const float* b = m.grid + j[2] * sz + j[1] * sy + j[0];
+        const float c00 = __builtin_fmaf(f[0], b[1] - b[0], b[0]);
+        const float c10 = __builtin_fmaf(f[0], b[sy + 1] - b[sy], b[sy]);
+        const float c01 = __builtin_fmaf(f[0], b[sz + 1] - b[sz], b[sz]);
+        const float c11 = __builtin_fmaf(f[0], b[sz + sy + 1] - b[sz + sy], b[sz + sy]);
+        const float c0 = __builtin_fmaf(f[1], c10 - c00, c00);
+        const float c1 = __builtin_fmaf(f[1], c11 - c01, c01);
+        return finish_value(m, __builtin_fmaf(f[2], c1 - c0, c0));
+    }
+};
+
 template <class Cfg, bool IS_F32 = (Cfg::PREC == CINR_F32)>
 struct InrEngine;
 

@@ -525,7 +525,7 @@ static hipError_t launch_grad_p(int prec, const InrDev& m, const TrainArgs& a, i
     return launch_grad_t<EngCfg<NL, F, H, CINR_F32>, CINR_F32>(m, a, max_waves, used, s);
 }
 
-bool train_shape_supported(const InrDev& m) { return inr_shape_supported(m); }
+bool train_shape_supported(const InrDev& m) { return !m.grid && inr_shape_supported(m); }
 
 int32_t train_n_weights(const InrDev& m) { return m.hidden * m.in + m.hidden * m.hidden + m.hidden; }
 
