@@ -157,10 +157,14 @@ typedef struct {
  *  mode          cinr_mode.
  *  mlp_dtype     cinr_dtype of brick decoding and true-miss inference.
  *  pipe_depth    tuning: samples each ray decides and fetches ahead while
- *                marching (1, 2 or 4; 8 is accepted and runs as 4; 0 =
- *                default 2).  Results do not depend on it.
+ *                marching (1, 2 or 4; 8 is accepted and runs as 4).
  *  xcd_bands     tuning: image bands per XCD in the sampler's work split
- *                (0 = default 4).  Results do not depend on it. */
+ *                (1 to 64).
+ *                Results depend on neither.  0 in either field tunes the
+ *                launch online, per volume and image size: the first 12
+ *                frames of that size try pipe depths {1, 2} x bands {1, 4,
+ *                16} twice each, then the fastest first-iteration march is
+ *                kept (cinr_tuned_launch reports the choice). */
 typedef struct {
     float step, lod_scale, ert_threshold;
     uint32_t seed;
@@ -292,6 +296,45 @@ typedef enum {
 } cinr_stage;
 cinr_status cinr_set_timing(cinr_volume vol, int32_t enable);
 cinr_status cinr_collect_timing(cinr_volume vol, double* ms, int64_t* launches);
+
+/* A cache shared by several volumes (for instance several INRs seen by
+ * several views): all volumes must have the same dimensions and the same
+ * kind and shape (INRs with equal levels, features and widths, or grids).
+ * Volume i owns the keys [i * K, (i + 1) * K), where K is the key count of
+ * one volume (cinr_lod_geometry); page table, request counts, ranks and the
+ * pool are shared, and the bricks selected in a frame are decoded in one
+ * persistent launch whatever their volumes.  The volumes must outlive the
+ * cache.  cinr_create_cache is the case of one volume. */
+cinr_status cinr_cache_workspace_size_multi(const cinr_volume* vols, int32_t n_vols, const cinr_cache_desc* desc,
+                                            size_t* bytes);
+cinr_status cinr_create_cache_multi(const cinr_volume* vols, int32_t n_vols, const cinr_cache_desc* desc,
+                                    float* d_pool, size_t pool_bytes, void* d_workspace, size_t ws_bytes,
+                                    void* stream, cinr_cache* out);
+
+/* One view of a multi-view frame. */
+typedef struct {
+    cinr_volume volume;          /* one of the cache's volumes */
+    cinr_camera camera;
+    const float* d_tf;           /* f32 [256][4] */
+    cinr_render_params params;   /* CACHED; frame_index and mlp_dtype equal in all views */
+    float* d_rgba;               /* f32 [H][W][4] */
+    cinr_frame_stats* d_stats;   /* nullable; the request counters are the frame's */
+    void* d_workspace;           /* this view's render workspace (cinr_render_workspace_size) */
+    size_t workspace_bytes;
+} cinr_view;
+
+/* Renders one frame of several views through a shared cache: every view is
+ * marched against the residency at the start of the frame, then one cache
+ * manager pass ranks the requests of all views and the selected bricks are
+ * decoded in one launch (the frame advances the cache by exactly one frame,
+ * as cinr_render_frame does for one view).  The views' first iterations are
+ * launched back to back and synchronised once. */
+cinr_status cinr_render_views(cinr_cache cache, int32_t n_views, const cinr_view* views, void* stream);
+
+/* The sampler launch shape tuned online for a volume and image size (see
+ * cinr_render_params), and the trial frames still to run (0 once tuned). */
+cinr_status cinr_tuned_launch(cinr_volume vol, int32_t width, int32_t height, int32_t* pipe_depth,
+                              int32_t* xcd_bands, int32_t* trials_left);
 
 /* Copies one piece of cache state to host memory.  If `bytes` is too small
  * (or host_dst is NULL) nothing is copied, *needed receives the size and

@@ -540,7 +540,10 @@ typedef struct {
 } miss_rec;
 
 struct orc_cache {
-    orc_inr inr;
+    orc_inr inr;                    /* volume 0 */
+    orc_inr inrs[ORC_MAX_VOLS];     /* all volumes sharing the cache */
+    int32_t n_vols;
+    int64_t keys_per_vol;           /* volume v owns keys [v K, (v+1) K) */
     orc_cache_desc d;
     lod_geom g[ORC_MAX_LODS];
     int64_t n_keys;
@@ -563,17 +566,27 @@ struct orc_cache {
     int64_t n_ert_trace;
 };
 
-orc_cache* orc_cache_create(const orc_inr* m, const orc_cache_desc* d) {
+orc_cache* orc_cache_create(const orc_inr* m, const orc_cache_desc* d) { return orc_cache_create_multi(m, 1, d); }
+
+orc_cache* orc_cache_create_multi(const orc_inr* ms, int32_t n_vols, const orc_cache_desc* d) {
     if (d->brick < 2 || d->n_lods < 1 || d->n_lods > ORC_MAX_LODS || d->pool_bricks < 0 || d->max_requests < 0)
         return NULL;
+    if (n_vols < 1 || n_vols > ORC_MAX_VOLS) return NULL;
+    for (int i = 1; i < n_vols; ++i)
+        for (int a = 0; a < 3; ++a)
+            if (ms[i].dims[a] != ms[0].dims[a]) return NULL;
     orc_cache* c = (orc_cache*)calloc(1, sizeof(orc_cache));
-    c->inr = *m;
+    c->inr = ms[0];
+    for (int i = 0; i < n_vols; ++i) c->inrs[i] = ms[i];
+    c->n_vols = n_vols;
     c->d = *d;
-    int64_t off = 0;
+    int64_t kpv = 0;
     for (int L = 0; L < d->n_lods; ++L) {
-        make_geom(m->dims, d->brick, L, off, &c->g[L]);
-        off += c->g[L].count;
+        make_geom(ms[0].dims, d->brick, L, kpv, &c->g[L]);
+        kpv += c->g[L].count;
     }
+    c->keys_per_vol = kpv;
+    const int64_t off = kpv * n_vols;
     c->n_keys = off;
     const int64_t B3 = (int64_t)d->brick * d->brick * d->brick;
     c->pt = (int32_t*)malloc(sizeof(int32_t) * off);
@@ -704,13 +717,14 @@ static void decode_inserted(orc_cache* c, const int32_t* keys, const int32_t* sl
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t i = 0; i < n; ++i) {
         if (slots[i] < 0) continue;
-        const int32_t key = keys[i];
+        const int32_t vol = (int32_t)(keys[i] / c->keys_per_vol);
+        const int64_t key = keys[i] - (int64_t)vol * c->keys_per_vol;
         int L = 0;
         while (L + 1 < c->d.n_lods && key >= c->g[L + 1].off) ++L;
         const int64_t local = key - c->g[L].off;
         const int32_t b[3] = {(int32_t)(local % c->g[L].nb[0]), (int32_t)((local / c->g[L].nb[0]) % c->g[L].nb[1]),
                               (int32_t)(local / ((int64_t)c->g[L].nb[0] * c->g[L].nb[1]))};
-        decode_brick(&c->inr, L, b, c->d.brick, c->pool + (int64_t)slots[i] * B3);
+        decode_brick(&c->inrs[vol], L, b, c->d.brick, c->pool + (int64_t)slots[i] * B3);
     }
 }
 
@@ -741,6 +755,7 @@ enum { S_HIT = 0, S_FALLBACK = 1, S_MISS = 2, S_SKIP = 3 };
 typedef struct {
     const orc_inr* m;
     orc_cache* c;           /* NULL in the uncached modes */
+    int64_t key_base;       /* first key of the frame's volume in a shared cache */
     int readonly;           /* no request counts, no stamps */
     const orc_camera* cam;
     const orc_params* p;
@@ -830,7 +845,7 @@ static void sample_decide(const frame_ctx* fc, const float o[3], const float d[3
         }
         const int64_t key = g->off + ((int64_t)b[2] * g->nb[1] + b[1]) * g->nb[0] + b[0];
         if (Lp == L) req_key = key;
-        const int32_t slot = c->pt[key];
+        const int32_t slot = c->pt[fc->key_base + key];
         if (slot < 0) continue;
         /* served by this brick */
         const int64_t B3 = (int64_t)B * B * B;
@@ -855,7 +870,7 @@ static void sample_decide(const frame_ctx* fc, const float o[3], const float d[3
     }
     if (so->status != S_HIT && !fc->readonly) {
 #pragma omp atomic
-        c->req[req_key] += 1u;
+        c->req[fc->key_base + req_key] += 1u;
     }
 }
 
@@ -1164,6 +1179,54 @@ int orc_cache_render(orc_cache* c, const orc_camera* cam, const float* tf, const
     render_pass(&fc, tf, rgba, st, c->log_misses, trace);
     free((void*)fc.flags);
     finish_frame(c, p->frame_index, st);
+    return 0;
+}
+
+/* One frame of several views through a shared cache: every view is rendered
+ * against the residency at the start of the frame (its requests and stamps
+ * accumulate), then one end-of-frame step ranks the requests of all views.
+ * View i shows volume vol[i]; images are written to rgba + 4 * (sum of the
+ * previous views' pixels); the miss list holds the misses of all views. */
+int orc_cache_render_views(orc_cache* c, int32_t n, const int32_t* vol, const orc_camera* cams, const float* tfs,
+                           const orc_params* ps, double* rgba, orc_stats* sts) {
+    if (n < 1) return -1;
+    for (int i = 0; i < n; ++i)
+        if (ps[i].mode != ORC_CACHED || vol[i] < 0 || vol[i] >= c->n_vols || ps[i].frame_index != ps[0].frame_index)
+            return -1;
+    miss_rec* all = NULL;
+    int64_t n_all = 0;
+    double* out = rgba;
+    for (int i = 0; i < n; ++i) {
+        frame_ctx fc;
+        memset(&fc, 0, sizeof(fc));
+        fc.m = &c->inrs[vol[i]];
+        fc.c = c;
+        fc.key_base = (int64_t)vol[i] * c->keys_per_vol;
+        fc.cam = &cams[i];
+        fc.p = &ps[i];
+        for (int a = 0; a < 3; ++a) fc.vm1[a] = (float)(fc.m->dims[a] - 1);
+        fc.flags = make_flags(fc.m, &ps[i], tfs + 1024 * i, fc.M);
+        fc.frame_seed = orc_frame_seed(ps[i].seed, (uint32_t)ps[i].frame_index);
+        fc.lod_floor = orc_lod_floor(ps[i].frame_index, c->d.preload_period, c->d.n_lods);
+        render_pass(&fc, tfs + 1024 * i, out, &sts[i], c->log_misses, NULL);
+        free((void*)fc.flags);
+        out += 4 * (int64_t)cams[i].width * cams[i].height;
+        all = (miss_rec*)realloc(all, sizeof(miss_rec) * (size_t)(n_all + c->n_misses + 1));
+        memcpy(all + n_all, c->misses, sizeof(miss_rec) * c->n_misses);
+        n_all += c->n_misses;
+    }
+    free(c->misses);
+    c->misses = all;
+    c->n_misses = n_all;
+    qsort(c->misses, c->n_misses, sizeof(miss_rec), cmp_miss);
+    orc_stats fs;
+    memset(&fs, 0, sizeof(fs));
+    finish_frame(c, ps[0].frame_index, &fs);
+    for (int i = 0; i < n; ++i) {
+        sts[i].requested = fs.requested;
+        sts[i].selected = fs.selected;
+        sts[i].evicted = fs.evicted;
+    }
     return 0;
 }
 

@@ -25,6 +25,7 @@ extern "C" {
 #define ORC_MAX_LEVELS 32
 #define ORC_MAX_LAYERS 8
 #define ORC_MAX_LODS 16
+#define ORC_MAX_VOLS 64
 
 /* Hash-grid INR (Section 3, Figure 2): n_levels grids, each a table of
  * T_l = min(2^log2_table, (N_l+1)^3) entries of n_features floats, stored
@@ -126,6 +127,13 @@ int orc_render_pixels(const orc_inr* m, orc_cache* c, const orc_camera* cam, con
 
 /* --- cached renderer --- */
 orc_cache* orc_cache_create(const orc_inr* m, const orc_cache_desc* d);
+/* A cache shared by n_vols volumes of equal dimensions (ms: array of
+ * descriptors); volume v owns keys [v K, (v + 1) K), K = keys of one volume. */
+orc_cache* orc_cache_create_multi(const orc_inr* ms, int32_t n_vols, const orc_cache_desc* d);
+/* One frame of n views (view i shows volume vol[i]; tfs: n tables of 256x4;
+ * rgba: the views' images back to back), then one end-of-frame step. */
+int orc_cache_render_views(orc_cache* c, int32_t n, const int32_t* vol, const orc_camera* cams, const float* tfs,
+                           const orc_params* ps, double* rgba, orc_stats* sts);
 void orc_cache_destroy(orc_cache* c);
 int orc_cache_render(orc_cache* c, const orc_camera* cam, const float* tf, const orc_params* p,
                      double* rgba, orc_stats* st);

@@ -88,6 +88,10 @@ def lib():
             "orc_render_uncached": (C.c_int, [P, P, P, P, P, P]),
             "orc_render_pixels": (C.c_int, [P, P, P, P, P, P, i64, P]),
             "orc_cache_create": (P, [P, P]),
+            "orc_cache_create_multi": (P, [P, i32, P]),
+            "orc_cache_render_views": (C.c_int, [P, i32, P, P, P, P, P, P]),
+            "orc_train_points": (None, [C.c_uint64, i64, i64, P]),
+            "orc_grid_trilinear": (None, [P, P, P, i64, P]),
             "orc_cache_destroy": (None, [P]),
             "orc_cache_render": (C.c_int, [P, P, P, P, P, P]),
             "orc_cache_prefill": (C.c_int, [P, P, i64, i32]),
@@ -325,14 +329,20 @@ def render_pixels(inr: OracleInr, cam, tf, params: Params, pixels, cache=None):
 
 
 class OracleCache:
-    def __init__(self, inr: OracleInr, brick, n_lods, pool_bricks, max_requests, rank_window=1000, ranking=1,
+    """Oracle brick cache of one volume, or shared by a list of volumes of
+    equal dimensions (volume i owns keys [i K, (i+1) K))."""
+
+    def __init__(self, inr, brick, n_lods, pool_bricks, max_requests, rank_window=1000, ranking=1,
                  preload_period=0, log_misses=False, trace_ert=False):
-        self.inr = inr
+        inrs = list(inr) if isinstance(inr, (list, tuple)) else [inr]
+        self.inrs = inrs
+        self.inr = inrs[0]
         d = CacheDesc()
         d.brick, d.n_lods, d.pool_bricks, d.max_requests = brick, n_lods, pool_bricks, max_requests
         d.rank_window, d.ranking, d.preload_period = rank_window, ranking, preload_period
         self.desc = d
-        self.h = lib().orc_cache_create(inr.ref(), C.byref(d))
+        self._descs = (Inr * len(inrs))(*[m.desc for m in inrs])
+        self.h = lib().orc_cache_create_multi(C.cast(self._descs, C.c_void_p), len(inrs), C.byref(d))
         if not self.h:
             raise ValueError("invalid cache description")
         self.n_keys = int(lib().orc_cache_n_keys(self.h))
@@ -352,6 +362,26 @@ class OracleCache:
         rc = lib().orc_cache_render(self.h, C.byref(c), _ptr(t), C.byref(params), _ptr(out), C.byref(st))
         assert rc == 0
         return out, st.as_dict()
+
+    def render_views(self, views, params):
+        """One frame of several views: views = [(volume index, camera, tf)],
+        params = [Params] (one per view).  Returns [(image, stats)]."""
+        n = len(views)
+        vol = np.array([v[0] for v in views], np.int32)
+        cams = (Camera * n)(*[camera_struct(v[1]) for v in views])
+        tfs = np.ascontiguousarray(np.stack([np.asarray(v[2], np.float32) for v in views]), np.float32)
+        ps = (Params * n)(*params)
+        sizes = [v[1].width * v[1].height for v in views]
+        out = np.zeros(4 * sum(sizes), np.float64)
+        sts = (Stats * n)()
+        rc = lib().orc_cache_render_views(self.h, n, _ptr(vol), C.cast(cams, C.c_void_p), _ptr(tfs),
+                                          C.cast(ps, C.c_void_p), _ptr(out), C.cast(sts, C.c_void_p))
+        assert rc == 0
+        res, o = [], 0
+        for (vi, cam, tf), sz, st in zip(views, sizes, sts):
+            res.append((out[4 * o:4 * (o + sz)].reshape(cam.height, cam.width, 4), st.as_dict()))
+            o += sz
+        return res
 
     def prefill(self, keys, stamp=0):
         k = np.ascontiguousarray(keys, np.int32)

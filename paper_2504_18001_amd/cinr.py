@@ -108,6 +108,10 @@ def lib():
             "cinr_train_step": [P, P, P, i64, P, P],
             "cinr_adam_update": [P, P, P, P, i64, i64, C.c_float, C.c_float, C.c_float, C.c_float, i32, P],
             "cinr_train_set_lr": [P, C.c_float],
+            "cinr_cache_workspace_size_multi": [P, i32, P, P],
+            "cinr_create_cache_multi": [P, i32, P, P, sz, P, sz, P, P],
+            "cinr_render_views": [P, i32, P, P],
+            "cinr_tuned_launch": [P, i32, i32, P, P, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -247,11 +251,16 @@ class Volume(_VolumeOps):
 
 
 class Cache:
-    """Multi-resolution brick cache over a torch-allocated pool and workspace."""
+    """Multi-resolution brick cache over a torch-allocated pool and workspace,
+    for one volume or shared by a list of volumes of the same shape (volume i
+    owns keys [i K, (i+1) K), K = keys of one volume)."""
 
-    def __init__(self, volume: Volume, brick, n_lods, pool_bricks, max_requests, rank_window=1000,
+    def __init__(self, volume, brick, n_lods, pool_bricks, max_requests, rank_window=1000,
                  ranking=RANK_PRIORITY, preload_period=0, miss_log_capacity=0, evict_log_capacity=4096,
                  keep_request_counts=False):
+        vols = list(volume) if isinstance(volume, (list, tuple)) else [volume]
+        self.volumes = vols
+        volume = vols[0]
         self.volume = volume
         d = CacheDesc()
         d.brick, d.n_lods, d.pool_bricks, d.max_requests = brick, n_lods, pool_bricks, max_requests
@@ -260,17 +269,19 @@ class Cache:
         d.keep_request_counts = 1 if keep_request_counts else 0
         self.desc = d
         ws = C.c_size_t()
-        _check(lib().cinr_cache_workspace_size(volume.h, C.byref(d), C.byref(ws)))
+        hs = (C.c_void_p * len(vols))(*[v.h.value for v in vols])
+        _check(lib().cinr_cache_workspace_size_multi(hs, len(vols), C.byref(d), C.byref(ws)))
         dev = volume.device
         self.pool = torch.empty(max(pool_bricks, 1) * brick ** 3, dtype=torch.float32, device=dev)
         self.workspace = torch.empty(ws.value, dtype=torch.uint8, device=dev)
         h = C.c_void_p()
-        _check(lib().cinr_create_cache(volume.h, C.byref(d), _ptr(self.pool), self.pool.numel() * 4,
-                                       _ptr(self.workspace), ws.value, _stream(), C.byref(h)))
+        _check(lib().cinr_create_cache_multi(hs, len(vols), C.byref(d), _ptr(self.pool), self.pool.numel() * 4,
+                                             _ptr(self.workspace), ws.value, _stream(), C.byref(h)))
         self.h = h
         nb, off = volume.geometry(brick, n_lods)
         self.nb, self.key_offset = nb, off
-        self.n_keys = int(off[-1])
+        self.keys_per_volume = int(off[-1])
+        self.n_keys = self.keys_per_volume * len(vols)
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -423,3 +434,65 @@ def adam_update(p, m, v, g, step, lr=1e-2, beta1=0.9, beta2=0.99, eps=1e-15, cle
     """In-place Adam update of float32 tensors (the trainer's optimiser)."""
     _check(lib().cinr_adam_update(_ptr(p), _ptr(m), _ptr(v), _ptr(g), p.numel(), int(step), float(lr), float(beta1),
                                   float(beta2), float(eps), 1 if clear_grad else 0, _stream()))
+
+
+class ViewDesc(C.Structure):
+    _fields_ = [("volume", C.c_void_p), ("camera", CameraDesc), ("d_tf", C.c_void_p), ("params", RenderParams),
+                ("d_rgba", C.c_void_p), ("d_stats", C.c_void_p), ("d_workspace", C.c_void_p),
+                ("workspace_bytes", C.c_size_t)]
+
+
+class MultiViewRenderer:
+    """Renders frames of several views through one shared cache
+    (cinr_render_views); owns each view's render workspace and statistics."""
+
+    def __init__(self, n_views, device="cuda"):
+        self.device = device
+        self.ws = [None] * n_views
+        self.stats = torch.zeros((n_views, len(STAT_FIELDS)), dtype=torch.int64, device=device)
+        self._keep = []
+
+    def render(self, cache: Cache, views, step, lod_scale=0.0, frame_index=0, seed=0, ert_threshold=2.0,
+               samples_per_iter=32, dtype="f32", outs=None, pipe_depth=0, xcd_bands=0):
+        """views: list of (volume, camera, tf); returns the list of RGBA images."""
+        n = len(views)
+        arr = (ViewDesc * n)()
+        outs = outs or [None] * n
+        keep = []
+        for i, (vol, cam, tf) in enumerate(views):
+            need = C.c_size_t()
+            _check(lib().cinr_render_workspace_size(vol.h, cam.width, cam.height, samples_per_iter, C.byref(need)))
+            if self.ws[i] is None or self.ws[i].numel() < need.value:
+                self.ws[i] = torch.empty(need.value, dtype=torch.uint8, device=self.device)
+            if outs[i] is None:
+                outs[i] = torch.empty((cam.height, cam.width, 4), dtype=torch.float32, device=self.device)
+            t = tf if torch.is_tensor(tf) else torch.as_tensor(np.asarray(tf, np.float32))
+            t = t.to(device=self.device, dtype=torch.float32).contiguous()
+            keep.append(t)
+            v = arr[i]
+            v.volume = vol.h.value
+            v.camera = camera_desc(cam)
+            v.d_tf = t.data_ptr()
+            p = v.params
+            p.step, p.lod_scale, p.ert_threshold = float(step), float(lod_scale), float(ert_threshold)
+            p.seed, p.frame_index, p.samples_per_iter = int(seed) & 0xFFFFFFFF, int(frame_index), int(samples_per_iter)
+            p.mode, p.mlp_dtype = CACHED, _dtype(dtype)
+            p.pipe_depth, p.xcd_bands = int(pipe_depth), int(xcd_bands)
+            v.d_rgba = outs[i].data_ptr()
+            v.d_stats = self.stats[i].data_ptr()
+            v.d_workspace = self.ws[i].data_ptr()
+            v.workspace_bytes = self.ws[i].numel()
+        self._keep = keep
+        _check(lib().cinr_render_views(cache.h, n, arr, _stream()))
+        return outs
+
+    def last_stats(self):
+        v = self.stats.cpu().numpy()
+        return [{k: int(row[i]) for i, k in enumerate(STAT_FIELDS)} for row in v]
+
+
+def tuned_launch(volume, width, height):
+    """(pipe_depth, xcd_bands, trials_left) of the online launch tuning."""
+    p, b, t = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(lib().cinr_tuned_launch(volume.h, int(width), int(height), C.byref(p), C.byref(b), C.byref(t)))
+    return p.value, b.value, t.value

@@ -6,6 +6,7 @@
 #include <stdio.h>
 
 #include <algorithm>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -69,6 +70,8 @@ bool geometry(const int32_t dims[3], int32_t B, int32_t n_lods, CacheGeom& g) {
         g.lod[L].off = off;
         off += cnt;
     }
+    g.keys_per_vol = off;
+    g.n_vols = 1;
     g.n_keys = off;
     return true;
 }
@@ -96,15 +99,32 @@ struct Timing {
     }
 };
 
+// Online tuning of the sampler's launch shape (pipe depth, XCD bands) for one
+// image size: the first frames try every candidate twice (results do not
+// depend on the shape), the fastest first-iteration march is kept.
+struct SamplerTuner {
+    static constexpr int kCand = 6;
+    static constexpr int kPipe[kCand] = {1, 2, 1, 2, 1, 2};
+    static constexpr int kBands[kCand] = {1, 1, 4, 4, 16, 16};
+    static constexpr int kRounds = 2;
+    int trial = 0;           // frames tried so far
+    float ms[kCand] = {0, 0, 0, 0, 0, 0};
+    int best = -1;
+    hipEvent_t a = nullptr, b = nullptr;
+    bool pending = false;    // events of the current trial recorded, not yet read
+    int cand() const { return best >= 0 ? best : trial % kCand; }
+};
+
 struct cinr_volume_s {
     cinr_volume_desc desc;
     InrDev m;
     int32_t n_cells = 0;
     int32_t M[3] = {0, 0, 0};
     int64_t table_entries = 0;  // hash-table entries over all levels
-    int32_t* pinned = nullptr;  // readback of the live-ray count
+    int32_t* pinned = nullptr;  // readback of the live-ray counts (one per view)
     hipEvent_t ev = nullptr;
     Timing timing;
+    std::map<uint64_t, SamplerTuner> tuners;  // by image size
 };
 
 namespace {
@@ -130,14 +150,23 @@ struct StageTimer {
 };
 }  // namespace
 
+constexpr int kMaxCacheVols = 64;
+constexpr int kMaxViews = 64;
+
 struct cinr_cache_s {
-    cinr_volume vol;
+    std::vector<cinr_volume> vols;  // volume v owns keys [v * keys_per_vol, (v + 1) * keys_per_vol)
     cinr_cache_desc desc;
     CacheGeom g;
     CacheDev c;
+    InrDev* d_vols = nullptr;  // device copies of the volumes' descriptors
     TopkPlan plan_sel, plan_vic;
     int32_t lim;          // request list length bound: min(max_requests, pool)
     int64_t used_bound;   // host upper bound on occupied slots (no LRU pass needed below the pool size)
+    int index_of(cinr_volume v) const {
+        for (size_t i = 0; i < vols.size(); ++i)
+            if (vols[i] == v) return (int)i;
+        return -1;
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -330,21 +359,35 @@ extern "C" cinr_status cinr_build_macrocells(cinr_volume v, int32_t cell, float*
 // Cache
 // ---------------------------------------------------------------------------
 
-static cinr_status check_cache_desc(cinr_volume v, const cinr_cache_desc* d, CacheGeom& g) {
-    if (!v || !d) return fail(CINR_INVALID_ARG, "null argument");
+static cinr_status check_cache_desc(const cinr_volume* vols, int32_t n_vols, const cinr_cache_desc* d, CacheGeom& g) {
+    if (!vols || !d) return fail(CINR_INVALID_ARG, "null argument");
+    if (n_vols < 1 || n_vols > kMaxCacheVols) return fail(CINR_INVALID_ARG, "%d volumes (1 to %d)", n_vols, kMaxCacheVols);
+    for (int i = 0; i < n_vols; ++i) {
+        const cinr_volume v = vols[i];
+        if (!v) return fail(CINR_INVALID_ARG, "null volume %d", i);
+        const InrDev& a = vols[0]->m;
+        const InrDev& b = v->m;
+        for (int k = 0; k < 3; ++k)
+            if (b.dims[k] != a.dims[k]) return fail(CINR_INVALID_ARG, "volume %d: dimensions differ from volume 0", i);
+        if ((a.grid == nullptr) != (b.grid == nullptr) ||
+            (!a.grid && (a.n_levels != b.n_levels || a.n_features != b.n_features || a.in != b.in || a.hidden != b.hidden)))
+            return fail(CINR_INVALID_ARG, "volume %d: shape differs from volume 0 (a shared cache decodes all volumes in one launch)", i);
+    }
     if (d->brick < 2 || d->brick > 64) return fail(CINR_INVALID_ARG, "brick = %d out of [2, 64]", d->brick);
     if (d->n_lods < 1 || d->n_lods > CINR_MAX_LODS) return fail(CINR_INVALID_ARG, "n_lods = %d", d->n_lods);
     if (d->pool_bricks < 0 || d->max_requests < 0 || d->max_requests > kMaxRequests)
         return fail(CINR_INVALID_ARG, "pool_bricks >= 0 and 0 <= max_requests <= %d required", kMaxRequests);
     if (d->rank_window < 0) return fail(CINR_INVALID_ARG, "rank_window < 0");
     if (d->miss_log_capacity < 0 || d->evict_log_capacity < 0) return fail(CINR_INVALID_ARG, "negative log capacity");
-    if (!geometry(v->desc.dims, d->brick, d->n_lods, g)) return fail(CINR_INVALID_ARG, "invalid geometry");
+    if (!geometry(vols[0]->desc.dims, d->brick, d->n_lods, g)) return fail(CINR_INVALID_ARG, "invalid geometry");
+    g.n_vols = n_vols;
+    g.n_keys = g.keys_per_vol * n_vols;
     if (g.n_keys > 0x7FFFFFFF) return fail(CINR_UNSUPPORTED, "more than 2^31 bricks");
     return CINR_OK;
 }
 
 static size_t cache_layout(const cinr_cache_desc* d, const CacheGeom& g, CacheDev* c, TopkPlan* ps, TopkPlan* pv,
-                           void* base) {
+                           void* base, InrDev** vols_out = nullptr) {
     const int64_t nk = g.n_keys;
     const int32_t P = d->pool_bricks;
     const int32_t lim = std::max(1, std::min(d->max_requests, P));
@@ -367,6 +410,7 @@ static size_t cache_layout(const cinr_cache_desc* d, const CacheGeom& g, CacheDe
     x.ins_keys = cv.take<int32_t>(ins_cap);
     x.ins_slots = cv.take<int32_t>(ins_cap);
     x.ins_reqs = cv.take<int32_t>((size_t)ins_cap * 4);
+    x.ins_vols = cv.take<int32_t>(ins_cap);
     x.topk[0] = cv.take<uint64_t>(buf);
     x.topk[1] = cv.take<uint64_t>(buf);
     x.sel = cv.take<uint64_t>(lim);
@@ -376,6 +420,7 @@ static size_t cache_layout(const cinr_cache_desc* d, const CacheGeom& g, CacheDe
     x.evlog = cv.take<int32_t>((size_t)d->evict_log_capacity * 4);
     x.evlog_cap = d->evict_log_capacity;
     x.ctr = cv.take<CacheCtr>(1);
+    if (vols_out) *vols_out = cv.take<InrDev>(g.n_vols);
     x.pool_bricks = P;
     x.max_requests = d->max_requests;
     x.rank_window = d->rank_window;
@@ -388,37 +433,50 @@ static size_t cache_layout(const cinr_cache_desc* d, const CacheGeom& g, CacheDe
     return cv.off;
 }
 
-extern "C" cinr_status cinr_cache_workspace_size(cinr_volume v, const cinr_cache_desc* d, size_t* bytes) {
+extern "C" cinr_status cinr_cache_workspace_size_multi(const cinr_volume* vols, int32_t n_vols, const cinr_cache_desc* d,
+                                                     size_t* bytes) {
     CacheGeom g;
-    cinr_status st = check_cache_desc(v, d, g);
+    cinr_status st = check_cache_desc(vols, n_vols, d, g);
     if (st) return st;
     if (!bytes) return fail(CINR_INVALID_ARG, "null bytes");
-    *bytes = cache_layout(d, g, nullptr, nullptr, nullptr, nullptr);
+    InrDev* unused = nullptr;
+    *bytes = cache_layout(d, g, nullptr, nullptr, nullptr, nullptr, &unused);
     return CINR_OK;
 }
 
-extern "C" cinr_status cinr_create_cache(cinr_volume v, const cinr_cache_desc* d, float* d_pool, size_t pool_bytes,
-                                         void* d_ws, size_t ws_bytes, void* stream, cinr_cache* out) {
+extern "C" cinr_status cinr_cache_workspace_size(cinr_volume v, const cinr_cache_desc* d, size_t* bytes) {
+    return cinr_cache_workspace_size_multi(&v, 1, d, bytes);
+}
+
+extern "C" cinr_status cinr_create_cache_multi(const cinr_volume* vols, int32_t n_vols, const cinr_cache_desc* d,
+                                               float* d_pool, size_t pool_bytes, void* d_ws, size_t ws_bytes,
+                                               void* stream, cinr_cache* out) {
     if (!out) return fail(CINR_INVALID_ARG, "null out");
     *out = nullptr;
     CacheGeom g;
-    cinr_status st = check_cache_desc(v, d, g);
+    cinr_status st = check_cache_desc(vols, n_vols, d, g);
     if (st) return st;
     const size_t B3 = (size_t)d->brick * d->brick * d->brick;
     if (pool_bytes < (size_t)d->pool_bricks * B3 * sizeof(float))
         return fail(CINR_OUT_OF_MEMORY, "pool of %zu bytes < %zu needed", pool_bytes, (size_t)d->pool_bricks * B3 * 4);
     if (d->pool_bricks > 0 && !d_pool) return fail(CINR_INVALID_ARG, "null pool");
-    const size_t need = cache_layout(d, g, nullptr, nullptr, nullptr, nullptr);
+    InrDev* unused = nullptr;
+    const size_t need = cache_layout(d, g, nullptr, nullptr, nullptr, nullptr, &unused);
     if (!d_ws || ws_bytes < need) return fail(CINR_OUT_OF_MEMORY, "workspace of %zu bytes < %zu needed", ws_bytes, need);
     cinr_cache c = new cinr_cache_s();
-    c->vol = v;
+    c->vols.assign(vols, vols + n_vols);
     c->desc = *d;
     c->g = g;
-    cache_layout(d, g, &c->c, &c->plan_sel, &c->plan_vic, d_ws);
+    cache_layout(d, g, &c->c, &c->plan_sel, &c->plan_vic, d_ws, &c->d_vols);
     c->c.pool = d_pool;
     c->lim = std::max(1, std::min(d->max_requests, d->pool_bricks));
     c->used_bound = 0;
-    hipError_t e = launch_cache_init(c->c, g.n_keys, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<InrDev> host(n_vols);
+    for (int i = 0; i < n_vols; ++i) host[i] = vols[i]->m;
+    hipError_t e = launch_cache_init(c->c, g.n_keys, s);
+    // the copy is staged from pageable memory before the call returns
+    if (e == hipSuccess) e = hipMemcpyAsync(c->d_vols, host.data(), sizeof(InrDev) * n_vols, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) {
         delete c;
         return fail(CINR_HIP_ERROR, "cache init: %s", hipGetErrorString(e));
@@ -427,20 +485,34 @@ extern "C" cinr_status cinr_create_cache(cinr_volume v, const cinr_cache_desc* d
     return CINR_OK;
 }
 
+extern "C" cinr_status cinr_create_cache(cinr_volume v, const cinr_cache_desc* d, float* d_pool, size_t pool_bytes,
+                                         void* d_ws, size_t ws_bytes, void* stream, cinr_cache* out) {
+    return cinr_create_cache_multi(&v, 1, d, d_pool, pool_bytes, d_ws, ws_bytes, stream, out);
+}
+
+// Decoding of the bricks selected for insertion (at most n_cap of them).
+static hipError_t decode_selected(cinr_cache c, int32_t n_cap, int32_t prec, hipStream_t s) {
+    const CacheDev& cd = c->c;
+    if (c->vols.size() == 1)
+        return inr_decode_bricks(c->vols[0]->m, c->g, cd.ins_reqs, &cd.ctr->n_sel, n_cap, cd.ins_slots, cd.pool, prec, s);
+    return inr_decode_bricks_multi(c->d_vols, c->vols[0]->m, c->g, cd.ins_reqs, cd.ins_vols, &cd.ctr->n_sel, n_cap,
+                                   cd.ins_slots, cd.pool, prec, s);
+}
+
 extern "C" void cinr_destroy_cache(cinr_cache c) { delete c; }
 
 extern "C" cinr_status cinr_cache_prefill(cinr_cache c, const int32_t* d_keys, int32_t n, int32_t stamp, int32_t prec,
                                           void* stream) {
     if (!c || n < 0 || (n > 0 && !d_keys)) return fail(CINR_INVALID_ARG, "invalid arguments");
     if (n > c->c.ins_cap) return fail(CINR_INVALID_ARG, "prefill of %d bricks exceeds %d", n, c->c.ins_cap);
-    cinr_status st = check_shape(c->vol, prec);
+    cinr_status st = check_shape(c->vols[0], prec);
     if (st) return st;
     if (n == 0) return CINR_OK;
     hipStream_t s = (hipStream_t)stream;
     c->used_bound = std::min<int64_t>(c->used_bound + n, c->c.pool_bricks);
     HIP_TRY(launch_prefill_setup(c->c, d_keys, n, s));
     HIP_TRY(launch_insert(c->c, c->g, stamp, n, s));
-    HIP_TRY(inr_decode_bricks(c->vol->m, c->g, c->c.ins_reqs, &c->c.ctr->n_sel, n, c->c.ins_slots, c->c.pool, prec, s));
+    HIP_TRY(decode_selected(c, n, prec, s));
     return CINR_OK;
 }
 
@@ -487,24 +559,45 @@ extern "C" cinr_status cinr_render_workspace_size(cinr_volume v, int32_t W, int3
     return CINR_OK;
 }
 
-extern "C" cinr_status cinr_render_frame(cinr_cache c, cinr_volume v, const cinr_camera* cam, const float* d_tf,
-                                         const cinr_render_params* rp, float* d_rgba, cinr_frame_stats* d_stats,
-                                         void* d_ws, size_t ws_bytes, void* stream) {
-    if (!v || !cam || !d_tf || !rp || !d_rgba) return fail(CINR_INVALID_ARG, "null argument");
+namespace {
+
+// One view of a frame: its volume, descriptor and workspace, and the state of
+// its wavefront iterations.
+struct ViewRun {
+    cinr_volume v = nullptr;
+    FrameDev f{};
+    RenderLayout L{};
+    int64_t npix = 0, max_iters = 0, queued = 0;
+    int32_t prec = 0;
+    int n_iters = 0;
+    bool live = true;       // iterations left
+    SamplerTuner* tuner = nullptr;
+    bool timing_trial = false;
+};
+
+cinr_status check_camera(const cinr_camera* cam) {
     if (cam->width < 1 || cam->height < 1) return fail(CINR_INVALID_ARG, "empty image");
     if (cam->projection != CINR_PERSPECTIVE && cam->projection != CINR_ORTHOGRAPHIC)
         return fail(CINR_INVALID_ARG, "projection = %d", cam->projection);
-    {
-        const float* vs[4] = {cam->eye, cam->forward, cam->right, cam->up};
-        for (const float* q : vs)
-            for (int a = 0; a < 3; ++a)
-                if (!isfinite(q[a])) return fail(CINR_INVALID_ARG, "non-finite camera vector");
-        const float sc[4] = {cam->tan_half_x, cam->tan_half_y, cam->ortho_w, cam->ortho_h};
-        for (float x : sc)
-            if (!isfinite(x)) return fail(CINR_INVALID_ARG, "non-finite camera extent");
-        if (cam->forward[0] == 0.0f && cam->forward[1] == 0.0f && cam->forward[2] == 0.0f)
-            return fail(CINR_INVALID_ARG, "zero forward vector");
-    }
+    const float* vs[4] = {cam->eye, cam->forward, cam->right, cam->up};
+    for (const float* q : vs)
+        for (int a = 0; a < 3; ++a)
+            if (!isfinite(q[a])) return fail(CINR_INVALID_ARG, "non-finite camera vector");
+    const float sc[4] = {cam->tan_half_x, cam->tan_half_y, cam->ortho_w, cam->ortho_h};
+    for (float x : sc)
+        if (!isfinite(x)) return fail(CINR_INVALID_ARG, "non-finite camera extent");
+    if (cam->forward[0] == 0.0f && cam->forward[1] == 0.0f && cam->forward[2] == 0.0f)
+        return fail(CINR_INVALID_ARG, "zero forward vector");
+    return CINR_OK;
+}
+
+// Validates one view and fills its frame descriptor.
+cinr_status prepare_view(cinr_cache c, cinr_volume v, const cinr_camera* cam, const float* d_tf,
+                         const cinr_render_params* rp, float* d_rgba, cinr_frame_stats* d_stats, void* d_ws,
+                         size_t ws_bytes, ViewRun& r) {
+    if (!v || !cam || !d_tf || !rp || !d_rgba) return fail(CINR_INVALID_ARG, "null argument");
+    cinr_status st = check_camera(cam);
+    if (st) return st;
     if (rp->mode != CINR_CACHED && rp->mode != CINR_UNCACHED_DIRECT) return fail(CINR_INVALID_ARG, "mode = %d", rp->mode);
     if (!(rp->step > 0.0f) || !isfinite(rp->step)) return fail(CINR_INVALID_ARG, "step must be > 0");
     if (!(rp->lod_scale >= 0.0f)) return fail(CINR_INVALID_ARG, "lod_scale must be >= 0");
@@ -515,9 +608,10 @@ extern "C" cinr_status cinr_render_frame(cinr_cache c, cinr_volume v, const cinr
         return fail(CINR_INVALID_ARG, "samples_per_iter must be in [1, 64]");
     const bool cached = rp->mode == CINR_CACHED;
     if (cached && !c) return fail(CINR_INVALID_ARG, "the cached mode needs a cache");
-    if (cached && c->vol != v) return fail(CINR_INVALID_ARG, "cache belongs to another volume");
+    const int vi = cached ? c->index_of(v) : -1;
+    if (cached && vi < 0) return fail(CINR_INVALID_ARG, "the volume is not one of the cache's volumes");
     if (cached && rp->frame_index < 0) return fail(CINR_INVALID_ARG, "frame_index must be >= 0");
-    cinr_status st = check_shape(v, rp->mlp_dtype);
+    st = check_shape(v, rp->mlp_dtype);
     if (st) return st;
     const int64_t npix = (int64_t)cam->width * cam->height;
     const int32_t S = rp->samples_per_iter;
@@ -530,15 +624,15 @@ extern "C" cinr_status cinr_render_frame(cinr_cache c, cinr_volume v, const cinr
     const double max_samples = ceil(sqrt(diag) / (double)rp->step) + 2.0;
     const int64_t max_iters = (int64_t)ceil(max_samples / S) + 2;
     if (max_iters > kMaxIters) return fail(CINR_INVALID_ARG, "step too small for samples_per_iter (needs %lld iterations)", (long long)max_iters);
-    hipStream_t s = (hipStream_t)stream;
-    if (!v->pinned) {
-        HIP_TRY(hipHostMalloc((void**)&v->pinned, 64, hipHostMallocDefault));
-        HIP_TRY(hipEventCreateWithFlags(&v->ev, hipEventDisableTiming));
-    }
-    RenderLayout L;
-    render_layout(npix, S, v->n_cells, &L, d_ws);
-
-    FrameDev f{};
+    r.v = v;
+    r.npix = npix;
+    r.max_iters = max_iters;
+    r.queued = npix;
+    r.prec = rp->mlp_dtype;
+    render_layout(npix, S, v->n_cells, &r.L, d_ws);
+    const RenderLayout& L = r.L;
+    FrameDev& f = r.f;
+    f = FrameDev{};
     f.cam.proj = cam->projection;
     f.cam.W = cam->width;
     f.cam.H = cam->height;
@@ -562,8 +656,18 @@ extern "C" cinr_status cinr_render_frame(cinr_cache c, cinr_volume v, const cinr
     f.frame = rp->frame_index;
     f.S = S;
     f.mode = rp->mode;
-    f.xcd_bands = rp->xcd_bands > 0 ? rp->xcd_bands : 4;
-    f.pipe = rp->pipe_depth > 0 ? rp->pipe_depth : 2;
+    // launch shape: given, or tuned online for this image size
+    if (rp->pipe_depth == 0 || rp->xcd_bands == 0) {
+        const uint64_t key = ((uint64_t)(uint32_t)cam->width << 32) | (uint32_t)cam->height;
+        r.tuner = &v->tuners[key];
+        const int cand = r.tuner->cand();
+        f.pipe = rp->pipe_depth > 0 ? rp->pipe_depth : SamplerTuner::kPipe[cand];
+        f.xcd_bands = rp->xcd_bands > 0 ? rp->xcd_bands : SamplerTuner::kBands[cand];
+        r.timing_trial = r.tuner->best < 0;
+    } else {
+        f.pipe = rp->pipe_depth;
+        f.xcd_bands = rp->xcd_bands;
+    }
     f.mc_N = v->desc.macrocell_size;
     f.div_mc = make_fastdiv((uint32_t)(f.mc_N > 0 ? f.mc_N : 1));
     f.flags = v->n_cells > 0 ? L.flags : nullptr;
@@ -580,7 +684,6 @@ extern "C" cinr_status cinr_render_frame(cinr_cache c, cinr_volume v, const cinr
     f.miss_rec = L.miss_rec;
     f.ctr = L.ctr;
     f.stats = d_stats ? reinterpret_cast<unsigned long long*>(d_stats) : L.stats;
-    CacheCtr* cctr = nullptr;
     if (cached) {
         const cinr_cache_desc& cd = c->desc;
         // per-frame seed of the stochastic LoD: high half of SplitMix64 of (seed << 32 | frame)
@@ -596,7 +699,8 @@ extern "C" cinr_status cinr_render_frame(cinr_cache c, cinr_volume v, const cinr
         }
         f.lod_floor = floor_;
         f.geo = c->g;
-        f.pt = c->c.pt;
+        f.key_base = (int32_t)(vi * c->g.keys_per_vol);
+        f.pt = c->c.pt + f.key_base;
         f.last_used = c->c.last_used;
         f.req = c->c.req;
         f.touched = c->c.touched;
@@ -606,44 +710,134 @@ extern "C" cinr_status cinr_render_frame(cinr_cache c, cinr_volume v, const cinr
         f.misslog = c->c.misslog;
         f.n_misslog = &c->c.ctr->n_misslog;
         f.misslog_cap = c->c.misslog_cap;
-        cctr = c->c.ctr;
     } else {
         f.geo.n_lods = 1;
         f.geo.brick = 2;
     }
-    const int32_t n_ctr = (int32_t)std::min<int64_t>(max_iters + 2, kMaxIters + 2);
-    Timing& tm = v->timing;
+    return CINR_OK;
+}
+
+cinr_status ensure_readback(cinr_volume v) {
+    if (!v->pinned) {
+        HIP_TRY(hipHostMalloc((void**)&v->pinned, sizeof(uint32_t) * kMaxViews, hipHostMallocDefault));
+        HIP_TRY(hipEventCreateWithFlags(&v->ev, hipEventDisableTiming));
+    }
+    return CINR_OK;
+}
+
+// First launches of a view's frame: counters, macro-cell flags, march 0.
+// `first` clears the frame-wide cache counters.
+cinr_status view_begin(cinr_cache c, ViewRun& r, bool first, hipStream_t s) {
+    cinr_volume v = r.v;
+    const bool cached = r.f.mode == CINR_CACHED;
+    CacheCtr* cctr = cached && first ? c->c.ctr : nullptr;
+    const int32_t n_ctr = (int32_t)std::min<int64_t>(r.max_iters + 2, kMaxIters + 2);
     {
-        StageTimer st_(tm, s, CINR_STAGE_SETUP);
-        HIP_TRY(launch_frame_begin(f, n_ctr, v->desc.d_macrocells, v->n_cells, cctr, s));
-        if (cached && c->c.last_req) HIP_TRY(launch_clear_last_req(c->c, c->g.n_keys, s));
+        StageTimer st_(v->timing, s, CINR_STAGE_SETUP);
+        HIP_TRY(launch_frame_begin(r.f, n_ctr, v->desc.d_macrocells, v->n_cells, cctr, s));
+        if (cached && first && c->c.last_req) HIP_TRY(launch_clear_last_req(c->c, c->g.n_keys, s));
     }
-    // wavefront iterations: march; stop when no ray gathered a step with a
-    // true miss; otherwise infer the misses and composite the gathered steps
-    int n_iters = 0;
-    int64_t queued = npix;  // rays iteration `it` may find re-queued (<= the previous iteration's pending steps)
-    for (int it = 0; it < max_iters; ++it) {
-        {
-            StageTimer st_(tm, s, CINR_STAGE_MARCH);
-            HIP_TRY(launch_march(f, it, queued, s));
+    SamplerTuner* t = r.tuner;
+    if (r.timing_trial) {
+        if (!t->a) {
+            HIP_TRY(hipEventCreate(&t->a));
+            HIP_TRY(hipEventCreate(&t->b));
         }
-        n_iters = it + 1;
-        HIP_TRY(hipMemcpyAsync(v->pinned, &f.ctr[it].pending, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipEventRecord(v->ev, s));
-        HIP_TRY(hipEventSynchronize(v->ev));
-        queued = *(volatile uint32_t*)v->pinned;
-        if (queued == 0) break;
-        {
-            StageTimer st_(tm, s, CINR_STAGE_INFER);
-            HIP_TRY(inr_infer_misses(v->m, f.miss_rec, &f.ctr[it].misses, npix * S, f.vals, rp->mlp_dtype, s));
+        HIP_TRY(hipEventRecord(t->a, s));
+    }
+    {
+        StageTimer st_(v->timing, s, CINR_STAGE_MARCH);
+        HIP_TRY(launch_march(r.f, 0, r.queued, s));
+    }
+    if (r.timing_trial) {
+        HIP_TRY(hipEventRecord(t->b, s));
+        t->pending = true;
+    }
+    r.n_iters = 1;
+    return CINR_OK;
+}
+
+// After the pending count of iteration it is known: stop, or infer the misses,
+// composite the gathered steps and march the next iteration.
+cinr_status view_continue(ViewRun& r, uint32_t pending, hipStream_t s) {
+    const int it = r.n_iters - 1;
+    r.queued = pending;
+    if (pending == 0 || r.n_iters >= r.max_iters) {
+        r.live = false;
+        return CINR_OK;
+    }
+    cinr_volume v = r.v;
+    {
+        StageTimer st_(v->timing, s, CINR_STAGE_INFER);
+        HIP_TRY(inr_infer_misses(v->m, r.f.miss_rec, &r.f.ctr[it].misses, r.npix * r.f.S, r.f.vals, r.prec, s));
+    }
+    {
+        StageTimer st_(v->timing, s, CINR_STAGE_SHADE);
+        HIP_TRY(launch_shade(r.f, it, r.npix, s));
+    }
+    {
+        StageTimer st_(v->timing, s, CINR_STAGE_MARCH);
+        HIP_TRY(launch_march(r.f, it + 1, r.queued, s));
+    }
+    r.n_iters += 1;
+    return CINR_OK;
+}
+
+// Tuner bookkeeping once the view's first march has completed.
+cinr_status tuner_collect(ViewRun& r) {
+    SamplerTuner* t = r.tuner;
+    if (!r.timing_trial || !t || !t->pending) return CINR_OK;
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, t->a, t->b));
+    t->pending = false;
+    t->ms[t->trial % SamplerTuner::kCand] += ms;
+    t->trial += 1;
+    if (t->trial >= SamplerTuner::kCand * SamplerTuner::kRounds) {
+        int best = 0;
+        for (int i = 1; i < SamplerTuner::kCand; ++i)
+            if (t->ms[i] < t->ms[best]) best = i;
+        t->best = best;
+    }
+    return CINR_OK;
+}
+
+// Runs the wavefront iterations of all views to completion; the pending
+// counts of all live views are read back with one synchronisation per round.
+cinr_status run_views(cinr_cache c, std::vector<ViewRun>& runs, hipStream_t s) {
+    cinr_volume rv = runs[0].v;
+    cinr_status st = ensure_readback(rv);
+    if (st) return st;
+    for (size_t i = 0; i < runs.size(); ++i) {
+        st = view_begin(c, runs[i], i == 0, s);
+        if (st) return st;
+    }
+    for (;;) {
+        int n_live = 0;
+        for (size_t i = 0; i < runs.size(); ++i) {
+            if (!runs[i].live) continue;
+            const int it = runs[i].n_iters - 1;
+            HIP_TRY(hipMemcpyAsync(rv->pinned + i, &runs[i].f.ctr[it].pending, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+            ++n_live;
         }
-        {
-            StageTimer st_(tm, s, CINR_STAGE_SHADE);
-            HIP_TRY(launch_shade(f, it, npix, s));
+        if (n_live == 0) break;
+        HIP_TRY(hipEventRecord(rv->ev, s));
+        HIP_TRY(hipEventSynchronize(rv->ev));
+        for (size_t i = 0; i < runs.size(); ++i) {
+            if (!runs[i].live) continue;
+            st = tuner_collect(runs[i]);
+            if (st) return st;
+            st = view_continue(runs[i], ((volatile uint32_t*)rv->pinned)[i], s);
+            if (st) return st;
         }
     }
-    if (cached) {
-        const CacheDev& cd = c->c;
+    return CINR_OK;
+}
+
+// End of a cached frame: ranking and selection of the requests of all views,
+// insertion (free slots, then LRU victims) and decoding of the new bricks.
+cinr_status cache_end_frame(cinr_cache c, int32_t frame_index, int32_t prec, Timing& tm, hipStream_t s) {
+    const CacheDev& cd = c->c;
+    {
         StageTimer st_(tm, s, CINR_STAGE_CM);
         // ranking of the requested bricks fused into the first selection pass;
         // the request list is published by the last pass
@@ -653,7 +847,7 @@ extern "C" cinr_status cinr_render_frame(cinr_cache c, cinr_volume v, const cinr
         ta.cap0 = (uint64_t)c->g.n_keys;
         ta.k = c->lim;
         ta.mode = TOPK_RANK;
-        ta.ra = RankArgs{cd.touched, cd.req, cd.last_req, cd.rank, rp->frame_index, cd.rank_window, cd.ranking};
+        ta.ra = RankArgs{cd.touched, cd.req, cd.last_req, cd.rank, frame_index, cd.rank_window, cd.ranking};
         SelectArgs sel{cd.ins_keys, cd.ctr, cd.pool_bricks, c->lim};
         HIP_TRY(launch_topk(ta, c->plan_sel, cd.topk[0], cd.topk[1], cd.sel, &sel, s));
         // LRU victims, only when the pool may be full
@@ -668,15 +862,75 @@ extern "C" cinr_status cinr_render_frame(cinr_cache c, cinr_volume v, const cinr
             HIP_TRY(launch_topk(tv, c->plan_vic, cd.topk[0], cd.topk[1], cd.vic, nullptr, s));
         }
         c->used_bound = std::min<int64_t>(c->used_bound + c->lim, cd.pool_bricks);
-        HIP_TRY(launch_insert(cd, c->g, rp->frame_index + 1, c->lim, s));
+        HIP_TRY(launch_insert(cd, c->g, frame_index + 1, c->lim, s));
     }
-    if (cached) {
-        const CacheDev& cd = c->c;
+    {
         StageTimer st_(tm, s, CINR_STAGE_DECODE);
-        HIP_TRY(inr_decode_bricks(v->m, c->g, cd.ins_reqs, &cd.ctr->n_sel, c->lim, cd.ins_slots, cd.pool,
-                                  rp->mlp_dtype, s));
+        HIP_TRY(decode_selected(c, c->lim, prec, s));
     }
-    HIP_TRY(launch_frame_end(f, n_iters, cctr, s));
+    return CINR_OK;
+}
+
+}  // namespace
+
+extern "C" cinr_status cinr_render_frame(cinr_cache c, cinr_volume v, const cinr_camera* cam, const float* d_tf,
+                                         const cinr_render_params* rp, float* d_rgba, cinr_frame_stats* d_stats,
+                                         void* d_ws, size_t ws_bytes, void* stream) {
+    std::vector<ViewRun> runs(1);
+    cinr_status st = prepare_view(c, v, cam, d_tf, rp, d_rgba, d_stats, d_ws, ws_bytes, runs[0]);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    st = run_views(c, runs, s);
+    if (st) return st;
+    const bool cached = rp->mode == CINR_CACHED;
+    if (cached) {
+        st = cache_end_frame(c, rp->frame_index, rp->mlp_dtype, v->timing, s);
+        if (st) return st;
+    }
+    HIP_TRY(launch_frame_end(runs[0].f, runs[0].n_iters, cached ? c->c.ctr : nullptr, true, s));
+    return CINR_OK;
+}
+
+extern "C" cinr_status cinr_render_views(cinr_cache c, int32_t n_views, const cinr_view* views, void* stream) {
+    if (!c || !views) return fail(CINR_INVALID_ARG, "null argument");
+    if (n_views < 1 || n_views > kMaxViews) return fail(CINR_INVALID_ARG, "%d views (1 to %d)", n_views, kMaxViews);
+    std::vector<ViewRun> runs(n_views);
+    for (int i = 0; i < n_views; ++i) {
+        const cinr_view& w = views[i];
+        if (w.params.mode != CINR_CACHED) return fail(CINR_INVALID_ARG, "view %d: views render in the cached mode", i);
+        if (w.params.frame_index != views[0].params.frame_index || w.params.mlp_dtype != views[0].params.mlp_dtype)
+            return fail(CINR_INVALID_ARG, "view %d: frame_index and mlp_dtype must equal those of view 0", i);
+        for (int j = 0; j < i; ++j)
+            if (views[j].d_workspace == w.d_workspace) return fail(CINR_INVALID_ARG, "views %d and %d share a workspace", j, i);
+        cinr_status st = prepare_view(c, w.volume, &w.camera, w.d_tf, &w.params, w.d_rgba, w.d_stats, w.d_workspace,
+                                      w.workspace_bytes, runs[i]);
+        if (st) return fail(st, "view %d: %s", i, cinr_last_error());
+    }
+    hipStream_t s = (hipStream_t)stream;
+    cinr_status st = run_views(c, runs, s);
+    if (st) return st;
+    st = cache_end_frame(c, views[0].params.frame_index, views[0].params.mlp_dtype, views[0].volume->timing, s);
+    if (st) return st;
+    for (int i = 0; i < n_views; ++i)
+        HIP_TRY(launch_frame_end(runs[i].f, runs[i].n_iters, c->c.ctr, i == n_views - 1, s));
+    return CINR_OK;
+}
+
+extern "C" cinr_status cinr_tuned_launch(cinr_volume v, int32_t width, int32_t height, int32_t* pipe_depth,
+                                         int32_t* xcd_bands, int32_t* trials_left) {
+    if (!v || !pipe_depth || !xcd_bands || !trials_left) return fail(CINR_INVALID_ARG, "null argument");
+    const uint64_t key = ((uint64_t)(uint32_t)width << 32) | (uint32_t)height;
+    auto it = v->tuners.find(key);
+    if (it == v->tuners.end()) {
+        *pipe_depth = *xcd_bands = 0;
+        *trials_left = SamplerTuner::kCand * SamplerTuner::kRounds;
+        return CINR_OK;
+    }
+    const SamplerTuner& t = it->second;
+    const int cand = t.cand();
+    *pipe_depth = SamplerTuner::kPipe[cand];
+    *xcd_bands = SamplerTuner::kBands[cand];
+    *trials_left = t.best >= 0 ? 0 : SamplerTuner::kCand * SamplerTuner::kRounds - t.trial;
     return CINR_OK;
 }
 

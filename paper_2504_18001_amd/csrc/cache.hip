@@ -164,10 +164,13 @@ __global__ void k_insert(CacheDev c, CacheGeom g, int32_t stamp, int32_t finish_
             c.owner[slot] = key;
             c.last_used[slot] = stamp;
         }
-        // brick coordinates of the key
+        // volume and brick coordinates of the key
+        const int32_t vol = ok ? (int32_t)((int64_t)key / g.keys_per_vol) : 0;
+        const int64_t vkey = ok ? (int64_t)key - (int64_t)vol * g.keys_per_vol : 0;
         int32_t L = 0;
-        while (L + 1 < g.n_lods && (int64_t)key >= g.lod[L + 1].off) ++L;
-        const int64_t local = ok ? (int64_t)key - g.lod[L].off : 0;
+        while (L + 1 < g.n_lods && vkey >= g.lod[L + 1].off) ++L;
+        const int64_t local = vkey - g.lod[L].off;
+        c.ins_vols[t] = vol;
         const int32_t nbx = g.lod[L].nb[0], nby = g.lod[L].nb[1];
         c.ins_slots[t] = ok ? slot : -1;  // an invalid entry is not decoded
         int32_t* q = c.ins_reqs + 4 * (int64_t)t;

@@ -67,12 +67,16 @@ struct LodGeom {
     int64_t off;     // first key of the LoD
 };
 
+// Keys of a cache shared by n_vols volumes of the same dimensions: volume v
+// owns keys [v * keys_per_vol, (v + 1) * keys_per_vol), numbered LoD by LoD.
 struct CacheGeom {
     int32_t brick;
     FastDiv div_b1;  // division by brick - 1
     int32_t n_lods;
     LodGeom lod[kMaxLods];
-    int64_t n_keys;
+    int64_t keys_per_vol;
+    int32_t n_vols;
+    int64_t n_keys;  // n_vols * keys_per_vol
 };
 
 // ---------------------------------------------------------------------------

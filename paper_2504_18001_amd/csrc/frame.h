@@ -51,6 +51,7 @@ struct CacheDev {
     int32_t* ins_keys;    // [ins_cap]
     int32_t* ins_slots;   // [ins_cap]
     int32_t* ins_reqs;    // [ins_cap][4]
+    int32_t* ins_vols;    // [ins_cap] volume of each inserted brick
     uint64_t* topk[2];    // ping-pong buffers of the selection passes
     uint64_t* sel;        // final selection (sorted scores)
     uint64_t* vic;        // final victim list (sorted scores)
@@ -83,7 +84,9 @@ struct FrameDev {
     uint32_t* claim;     // [2][8] work-unit counters of the march kernel (one set per iteration
                          // parity), kClaimStride words apart
     CacheGeom geo;
-    // cache (null in the uncached mode)
+    // cache (null in the uncached mode); pt and request keys are those of this
+    // frame's volume: global key = key_base + key
+    int32_t key_base;
     const int32_t* pt;
     int32_t* last_used;
     uint32_t* req;
@@ -171,7 +174,7 @@ hipError_t launch_frame_begin(const FrameDev& f, int32_t n_iter_ctr, const float
                               CacheCtr* cctr, hipStream_t s);
 hipError_t launch_march(const FrameDev& f, int it, int64_t max_rays, hipStream_t s);
 hipError_t launch_shade(const FrameDev& f, int it, int64_t cap_rays, hipStream_t s);
-hipError_t launch_frame_end(const FrameDev& f, int n_iters, CacheCtr* cctr, hipStream_t s);
+hipError_t launch_frame_end(const FrameDev& f, int n_iters, CacheCtr* cctr, bool reset, hipStream_t s);
 
 // cache launchers
 hipError_t launch_cache_init(const CacheDev& c, int64_t n_keys, hipStream_t s);
@@ -189,6 +192,11 @@ hipError_t inr_decode_bricks(const InrDev& m, const CacheGeom& g, const int32_t*
 hipError_t inr_macrocells(const InrDev& m, int32_t N, float* minmax, int prec, hipStream_t s);
 hipError_t inr_infer_misses(const InrDev& m, const float4* rec, const uint32_t* n_dev, int64_t cap, float* vals,
                             int prec, hipStream_t s);
+// bricks of several volumes of one shape (d_vols: device array of their
+// descriptors, `shape` any of them on the host)
+hipError_t inr_decode_bricks_multi(const InrDev* d_vols, const InrDev& shape, const CacheGeom& g, const int32_t* reqs,
+                                   const int32_t* vols, const uint32_t* n_dev, int32_t n_cap, const int32_t* slots,
+                                   float* out, int prec, hipStream_t s);
 
 // train.hip launchers
 bool train_shape_supported(const InrDev& m);

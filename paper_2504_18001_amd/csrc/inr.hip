@@ -127,6 +127,38 @@ __global__ __launch_bounds__(kBlock) void k_decode(const InrDev m, const BrickSr
     }
 }
 
+// Persistent decoding of the bricks of several volumes of one shape (a cache
+// shared by several INRs): workgroup rounds walk (brick, 256-sample chunk)
+// items, so that every round stays inside one brick; a workgroup reloads the
+// MLP weights only when its next brick belongs to another volume.  The list
+// may mix volumes and LoDs in any order.
+template <class Eng>
+__global__ __launch_bounds__(kBlock) void k_decode_multi(const InrDev* vols, const BrickSrc src, const int32_t* req_vol,
+                                                         const BrickDst dst) {
+    Eng eng;
+    int32_t cur = -1;
+    __shared__ typename Eng::Lds lds;
+    const int64_t n_bricks = src.n_dev ? (int64_t)*src.n_dev : (int64_t)src.n_host;
+    const int32_t chunks = (src.B3 + kBlock - 1) / kBlock;
+    const int64_t items = n_bricks * chunks;
+    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const int64_t r = it / chunks;
+        const int32_t i = (int32_t)(it - r * chunks) * kBlock + threadIdx.x;
+        const bool valid = i < src.B3;
+        const int64_t idx = r * src.B3 + (valid ? i : 0);
+        const int32_t v = req_vol[r];
+        const InrDev& m = vols[v < 0 ? 0 : v];
+        if (v != cur) {
+            eng.load_weights(m);
+            cur = v;
+        }
+        double x[3];
+        const bool ok = src.position(idx, x) && v >= 0;
+        const float val = eng.eval(m, x, lds);
+        if (valid) dst.store(idx, ok ? val : __builtin_nanf(""));
+    }
+}
+
 // Macro-cells (Section 5.2): one workgroup per cell, min/max of the lattice
 // values in the cell's closed region.
 template <class Eng>
@@ -242,6 +274,16 @@ static hipError_t launch_all(int what, const InrDev& m, const void* a, hipStream
                                dim3(kBlock), 0, s, m, p[0], p[1], p[2], p[3], mm);
             break;
         }
+        case 4: {
+            const BrickSrc* src = (const BrickSrc*)((const void* const*)a)[0];
+            const BrickDst* dst = (const BrickDst*)((const void* const*)a)[1];
+            const InrDev* vols = (const InrDev*)((const void* const*)a)[2];
+            const int32_t* req_vol = (const int32_t*)((const void* const*)a)[3];
+            const int64_t items = (int64_t)src->n_host * ((src->B3 + kBlock - 1) / kBlock);
+            const int blocks = (int)(items < kMaxInrBlocks ? (items < 1 ? 1 : items) : kMaxInrBlocks);
+            hipLaunchKernelGGL((k_decode_multi<Eng>), dim3(blocks), dim3(kBlock), 0, s, vols, *src, req_vol, *dst);
+            break;
+        }
         case 3: {
             const MissSrc* src = (const MissSrc*)((const void* const*)a)[0];
             const MissDst* dst = (const MissDst*)((const void* const*)a)[1];
@@ -309,6 +351,25 @@ hipError_t inr_decode_bricks(const InrDev& m, const CacheGeom& g, const int32_t*
     BrickDst dst{out, slots, src.B3};
     const void* a[2] = {&src, &dst};
     return dispatch(prec, 1, m, a, s);
+}
+
+hipError_t inr_decode_bricks_multi(const InrDev* d_vols, const InrDev& shape, const CacheGeom& g, const int32_t* reqs,
+                                   const int32_t* vols, const uint32_t* n_dev, int32_t n_cap, const int32_t* slots,
+                                   float* out, int prec, hipStream_t s) {
+    if (n_cap <= 0) return hipSuccess;
+    BrickSrc src;
+    src.reqs = reqs;
+    src.n_dev = n_dev;
+    src.n_host = n_cap;
+    src.B = g.brick;
+    src.B3 = g.brick * g.brick * g.brick;
+    src.n_lods = g.n_lods;
+    for (int L = 0; L < kMaxLods; ++L)
+        for (int a = 0; a < 3; ++a) src.nb[L][a] = L < g.n_lods ? g.lod[L].nb[a] : 0;
+    for (int a = 0; a < 3; ++a) src.dims[a] = shape.dims[a];
+    BrickDst dst{out, slots, src.B3};
+    const void* a[4] = {&src, &dst, d_vols, vols};
+    return dispatch(prec, 4, shape, a, s);
 }
 
 hipError_t inr_macrocells(const InrDev& m, int32_t N, float* minmax, int prec, hipStream_t s) {

@@ -167,9 +167,10 @@ struct MarchCold {
     MissLogRec* misslog;
     uint32_t* n_misslog;
     int32_t misslog_cap;
-    uint32_t* req;
+    uint32_t* req;      // request counts of this frame's volume (offset by key_base)
     int32_t* touched;
     uint32_t* n_touched;
+    int32_t key_base;   // global key of the volume's first brick
 };
 using ColdRef = const volatile MarchCold*;
 
@@ -199,7 +200,7 @@ __device__ inline void flush_requests(ColdRef c, int32_t key, uint32_t cnt) {
     if (old == 0u) {
         const uint32_t i = atomicAdd(c->n_touched, 1u);
         int32_t* touched = c->touched;
-        touched[i] = key;
+        touched[i] = c->key_base + key;
     }
 }
 
@@ -383,9 +384,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
         c.misslog = f.misslog;
         c.n_misslog = f.n_misslog;
         c.misslog_cap = f.misslog_cap;
-        c.req = f.req;
+        c.req = f.req ? f.req + f.key_base : nullptr;
         c.touched = f.touched;
         c.n_touched = f.n_touched;
+        c.key_base = f.key_base;
     }
     __syncthreads();
     const ColdRef cold = &cold_s;
@@ -564,14 +566,16 @@ __global__ __launch_bounds__(kBlock) void k_shade(FrameDev f, int32_t it) {
     }
 }
 
-__global__ void k_frame_end(FrameDev f, int32_t n_iters, CacheCtr* cctr) {
+// Frame statistics of one view; the cache manager's counters are those of the
+// whole frame (all views).  `reset` (the last view) clears the request list.
+__global__ void k_frame_end(FrameDev f, int32_t n_iters, CacheCtr* cctr, int32_t reset) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         f.stats[ST_ITERS] = (unsigned long long)n_iters;
         if (cctr) {
             f.stats[ST_REQUESTED] = cctr->n_touched;
             f.stats[ST_SELECTED] = cctr->n_sel;
             f.stats[ST_EVICTED] = cctr->need_evict;
-            cctr->n_touched = 0u;  // the next frame's requests start empty
+            if (reset) cctr->n_touched = 0u;  // the next frame's requests start empty
         }
     }
 }
@@ -664,8 +668,8 @@ hipError_t launch_shade(const FrameDev& f, int it, int64_t cap_rays, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_frame_end(const FrameDev& f, int n_iters, CacheCtr* cctr, hipStream_t s) {
-    hipLaunchKernelGGL(k_frame_end, dim3(1), dim3(64), 0, s, f, n_iters, cctr);
+hipError_t launch_frame_end(const FrameDev& f, int n_iters, CacheCtr* cctr, bool reset, hipStream_t s) {
+    hipLaunchKernelGGL(k_frame_end, dim3(1), dim3(64), 0, s, f, n_iters, cctr, reset ? 1 : 0);
     return hipGetLastError();
 }
 
