@@ -126,6 +126,71 @@ def decode_throughput(vol, w, dtype, n_bricks, reps=5):
     return n_bricks / (ms * 1e-3), ms
 
 
+def multiview_leg(warmup, steps, dtype):
+    """Frames of 16 views of 4 INRs through one shared cache (one cache
+    manager pass and one multi-INR decode launch per frame)."""
+    import torch
+    from paper_2504_18001_amd import cinr, configs, synth
+    mv = configs.MULTIVIEW
+    vols = []
+    for i in range(mv.n_inrs):
+        table, weights = synth.random_inr_params(mv.arch, i)
+        s, o = load_value_range(f"inr512/{i}")
+        base = cinr.Volume(mv.arch, table, weights, s, o)
+        mm = base.build_macrocells(16, "f32")
+        vols.append(cinr.Volume(mv.arch, base.table, base.weights, s, o, macrocells=mm, macro_cell=16))
+    cs = mv.cache
+    cache = cinr.Cache(vols, cs.brick, cs.n_lods, cs.pool_bricks, cs.max_requests, preload_period=cs.preload_period)
+    r = cinr.MultiViewRenderer(mv.n_views)
+    tfs = {k: torch.as_tensor(mv.tf(k)).cuda() for k in (0, 30)}
+    outs = [torch.empty((mv.view_size(v), mv.view_size(v), 4), device="cuda") for v in range(mv.n_views)]
+
+    def frame(f):
+        views = [(vols[mv.view_inr(v)], mv.camera(v, f), tfs[0 if f % 60 < 30 else 30]) for v in range(mv.n_views)]
+        r.render(cache, views, mv.step, mv.lod_scale, frame_index=f, seed=mv.seed, ert_threshold=mv.ert_threshold,
+                 samples_per_iter=mv.samples_per_iter, dtype=dtype, outs=outs)
+
+    for f in range(warmup):
+        frame(f)
+    torch.cuda.synchronize()
+    for v in vols:
+        v.set_timing(True)
+    t0 = time.perf_counter()
+    for f in range(warmup, warmup + steps):
+        frame(f)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stages = {}
+    for v in vols:
+        for k, (ms, n) in v.collect_timing().items():
+            a = stages.setdefault(k, [0.0, 0])
+            a[0] += ms
+            a[1] += n
+        v.set_timing(False)
+    st = r.last_stats()
+    pixels = sum(mv.view_size(v) ** 2 for v in range(mv.n_views))
+    # decoding throughput of the shared cache: a prefill of bricks of all INRs in one launch
+    K = cache.keys_per_volume
+    fresh = cinr.Cache(vols, cs.brick, cs.n_lods, 8192, 256)
+    import numpy as np
+    keys = torch.from_numpy(np.concatenate([np.arange(256, dtype=np.int32) + i * K for i in range(mv.n_inrs)])).cuda()
+    fresh.prefill(keys[:256], 0, dtype)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    fresh.prefill(keys[256:], 0, dtype)
+    e1.record()
+    torch.cuda.synchronize()
+    dec = (keys.numel() - 256) / (e0.elapsed_time(e1) * 1e-3)
+    return {"workload": mv.name, "views": mv.n_views, "inrs": mv.n_inrs, "pixels_per_frame": pixels,
+            "frames": steps, "frame_ms": round(dt / steps * 1e3, 4),
+            "aggregate_view_fps": round(mv.n_views * steps / dt, 2),
+            "pixels_per_s": round(pixels * steps / dt, 1),
+            "stage_ms_per_frame": {k: round(v[0] / steps, 4) for k, v in stages.items()},
+            "requested_selected_last_frame": [st[0]["requested"], st[0]["selected"]],
+            "multi_inr_decode_bricks_per_s": round(dec, 1)}
+
+
 def cpu_baseline(w, budget_s):
     """The CPU oracle on a bounded sample of the same workload: cached frames
     from a cold cache at 1/8 x 1/8 of the resolution."""
@@ -172,6 +237,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-cached", action="store_true", help="skip the comparison precisions")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-multiview", action="store_true", help="skip the 16-view shared-cache leg")
+    ap.add_argument("--multiview-steps", type=int, default=60)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain elementwise copy of this many MiB (y = x * 1) five times, to scale "
                          "hardware traffic counters, and exit")
@@ -275,6 +342,11 @@ def main():
         bps[dt], _ = decode_throughput(vol, w, dt, args.decode_bricks)
     log(f"[bench] decode bricks/s {bps}")
 
+    multi = None
+    if not args.no_multiview:
+        multi = multiview_leg(60, args.multiview_steps, args.dtype)
+        log(f"[bench] multiview {multi}")
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, args.cpu_budget)
@@ -313,6 +385,7 @@ def main():
                      "algorithmic_bytes_per_launch": round(alg_bytes / max(march_n, 1)),
                      "launches": march_n, "avg_launch_ms": round(march_ms / max(march_n, 1), 5),
                      "launches_before_timed": warm_stages["march"][1]},
+        "multiview": multi,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

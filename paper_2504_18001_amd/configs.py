@@ -108,3 +108,47 @@ HD512 = Workload(
 def scaled(w: Workload, width: int, height: int, **kw) -> Workload:
     """Same workload at another resolution (and optional overrides)."""
     return replace(w, width=width, height=height, **kw)
+
+
+# 16 views of 4 random-init INRs of the 512^3 architecture (seeds 0-3):
+# view v shows INR v mod 4 at (256 * 2^(v // 4))^2 pixels, perspective 45
+# degrees, orbiting the volume centre at the radius where the bounding sphere
+# fills the view; each view has its own orbit (start angle, elevation and
+# speed from a generator seeded with 100 + v).  One cache of 16^3 bricks, 4
+# LoDs and a shared 32 GiB pool serves all views.
+@dataclass
+class MultiView:
+    name: str = "multiview16_inr512x4"
+    arch: InrArch = ARCH_512
+    n_views: int = 16
+    n_inrs: int = 4
+    step: float = 0.5
+    lod_scale: float = 1.0 / 800.0
+    ert_threshold: float = 0.999
+    samples_per_iter: int = 32
+    seed: int = 1234
+    radius: float = 1159.0
+    cache: CacheShape = field(default_factory=lambda: CacheShape(
+        brick=16, n_lods=4, pool_bricks=(32 << 30) // (16 ** 3 * 4), max_requests=256, preload_period=4))
+
+    def view_inr(self, v: int) -> int:
+        return v % self.n_inrs
+
+    def view_size(self, v: int) -> int:
+        return 256 << (v // 4)
+
+    def camera(self, v: int, frame: int) -> synth.Camera:
+        import numpy as np
+        rng = np.random.default_rng(100 + v)
+        start = rng.uniform(0.0, 360.0)
+        elev = rng.uniform(-45.0, 45.0)
+        speed = rng.uniform(2.0, 8.0)
+        n = self.view_size(v)
+        return synth.orbit_camera(synth.PERSPECTIVE, self.arch.dims, self.radius, start + speed * frame, elev, n, n,
+                                  45.0)
+
+    def tf(self, frame: int):
+        return synth.tf_ramp() if (frame % 60) < 30 else synth.tf_random(77)
+
+
+MULTIVIEW = MultiView()
