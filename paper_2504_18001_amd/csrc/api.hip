@@ -159,6 +159,17 @@ struct cinr_cache_s {
     CacheGeom g;
     CacheDev c;
     InrDev* d_vols = nullptr;  // device copies of the volumes' descriptors
+    // side streams of multi-view frames (default priority), created on first use
+    static constexpr int kViewStreams = 4;
+    hipStream_t vs[kViewStreams] = {};
+    hipEvent_t fork = nullptr, join[kViewStreams] = {};
+    ~cinr_cache_s() {
+        for (int i = 0; i < kViewStreams; ++i) {
+            if (vs[i]) (void)hipStreamDestroy(vs[i]);
+            if (join[i]) (void)hipEventDestroy(join[i]);
+        }
+        if (fork) (void)hipEventDestroy(fork);
+    }
     TopkPlan plan_sel, plan_vic;
     int32_t lim;          // request list length bound: min(max_requests, pool)
     int64_t used_bound;   // host upper bound on occupied slots (no LRU pass needed below the pool size)
@@ -565,6 +576,7 @@ namespace {
 // its wavefront iterations.
 struct ViewRun {
     cinr_volume v = nullptr;
+    hipStream_t st = nullptr;  // stream of this view's launches
     FrameDev f{};
     RenderLayout L{};
     int64_t npix = 0, max_iters = 0, queued = 0;
@@ -725,18 +737,22 @@ cinr_status ensure_readback(cinr_volume v) {
     return CINR_OK;
 }
 
-// First launches of a view's frame: counters, macro-cell flags, march 0.
-// `first` clears the frame-wide cache counters.
-cinr_status view_begin(cinr_cache c, ViewRun& r, bool first, hipStream_t s) {
+// Frame start of a view: counters and macro-cell flags.  `first` also clears
+// the frame-wide cache counters (miss log, previous request counts).
+cinr_status view_setup(cinr_cache c, ViewRun& r, bool first, hipStream_t s) {
     cinr_volume v = r.v;
     const bool cached = r.f.mode == CINR_CACHED;
     CacheCtr* cctr = cached && first ? c->c.ctr : nullptr;
     const int32_t n_ctr = (int32_t)std::min<int64_t>(r.max_iters + 2, kMaxIters + 2);
-    {
-        StageTimer st_(v->timing, s, CINR_STAGE_SETUP);
-        HIP_TRY(launch_frame_begin(r.f, n_ctr, v->desc.d_macrocells, v->n_cells, cctr, s));
-        if (cached && first && c->c.last_req) HIP_TRY(launch_clear_last_req(c->c, c->g.n_keys, s));
-    }
+    StageTimer st_(v->timing, s, CINR_STAGE_SETUP);
+    HIP_TRY(launch_frame_begin(r.f, n_ctr, v->desc.d_macrocells, v->n_cells, cctr, s));
+    if (cached && first && c->c.last_req) HIP_TRY(launch_clear_last_req(c->c, c->g.n_keys, s));
+    return CINR_OK;
+}
+
+// First march of a view (timed when its launch shape is being tuned).
+cinr_status view_march0(ViewRun& r, hipStream_t s) {
+    cinr_volume v = r.v;
     SamplerTuner* t = r.tuner;
     if (r.timing_trial) {
         if (!t->a) {
@@ -803,12 +819,34 @@ cinr_status tuner_collect(ViewRun& r) {
 
 // Runs the wavefront iterations of all views to completion; the pending
 // counts of all live views are read back with one synchronisation per round.
+// Several views of a cached frame run on the cache's side streams (forked from
+// and joined back into `s`) so that their marches overlap; the frame-wide
+// counters are cleared on `s` before the fork.
 cinr_status run_views(cinr_cache c, std::vector<ViewRun>& runs, hipStream_t s) {
     cinr_volume rv = runs[0].v;
     cinr_status st = ensure_readback(rv);
     if (st) return st;
+    const bool side = c && runs.size() > 1;
+    if (side && !c->fork) {
+        for (int k = 0; k < cinr_cache_s::kViewStreams; ++k) {
+            HIP_TRY(hipStreamCreateWithFlags(&c->vs[k], hipStreamNonBlocking));
+            HIP_TRY(hipEventCreateWithFlags(&c->join[k], hipEventDisableTiming));
+        }
+        HIP_TRY(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
+    }
+    for (size_t i = 0; i < runs.size(); ++i) runs[i].st = side ? c->vs[i % cinr_cache_s::kViewStreams] : s;
+    st = view_setup(c, runs[0], true, s);
+    if (st) return st;
+    if (side) {
+        HIP_TRY(hipEventRecord(c->fork, s));
+        for (int k = 0; k < cinr_cache_s::kViewStreams; ++k) HIP_TRY(hipStreamWaitEvent(c->vs[k], c->fork, 0));
+    }
     for (size_t i = 0; i < runs.size(); ++i) {
-        st = view_begin(c, runs[i], i == 0, s);
+        if (i > 0) {
+            st = view_setup(c, runs[i], false, runs[i].st);
+            if (st) return st;
+        }
+        st = view_march0(runs[i], runs[i].st);
         if (st) return st;
     }
     for (;;) {
@@ -816,18 +854,31 @@ cinr_status run_views(cinr_cache c, std::vector<ViewRun>& runs, hipStream_t s) {
         for (size_t i = 0; i < runs.size(); ++i) {
             if (!runs[i].live) continue;
             const int it = runs[i].n_iters - 1;
-            HIP_TRY(hipMemcpyAsync(rv->pinned + i, &runs[i].f.ctr[it].pending, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(rv->pinned + i, &runs[i].f.ctr[it].pending, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                   runs[i].st));
             ++n_live;
         }
         if (n_live == 0) break;
-        HIP_TRY(hipEventRecord(rv->ev, s));
-        HIP_TRY(hipEventSynchronize(rv->ev));
+        if (side) {
+            for (int k = 0; k < cinr_cache_s::kViewStreams; ++k) HIP_TRY(hipEventRecord(c->join[k], c->vs[k]));
+            for (int k = 0; k < cinr_cache_s::kViewStreams; ++k) HIP_TRY(hipEventSynchronize(c->join[k]));
+        } else {
+            HIP_TRY(hipEventRecord(rv->ev, s));
+            HIP_TRY(hipEventSynchronize(rv->ev));
+        }
         for (size_t i = 0; i < runs.size(); ++i) {
             if (!runs[i].live) continue;
             st = tuner_collect(runs[i]);
             if (st) return st;
-            st = view_continue(runs[i], ((volatile uint32_t*)rv->pinned)[i], s);
+            st = view_continue(runs[i], ((volatile uint32_t*)rv->pinned)[i], runs[i].st);
             if (st) return st;
+        }
+    }
+    if (side) {
+        // everything of the views precedes the cache manager on `s`
+        for (int k = 0; k < cinr_cache_s::kViewStreams; ++k) {
+            HIP_TRY(hipEventRecord(c->join[k], c->vs[k]));
+            HIP_TRY(hipStreamWaitEvent(s, c->join[k], 0));
         }
     }
     return CINR_OK;
