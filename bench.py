@@ -153,13 +153,17 @@ def multiview_leg(warmup, steps, dtype):
     for f in range(warmup):
         frame(f)
     torch.cuda.synchronize()
-    for v in vols:
-        v.set_timing(True)
     t0 = time.perf_counter()
     for f in range(warmup, warmup + steps):
         frame(f)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # the same frames again with stage timing (events around every stage)
+    for v in vols:
+        v.set_timing(True)
+    for f in range(warmup + steps, warmup + 2 * steps):
+        frame(f)
+    torch.cuda.synchronize()
     stages = {}
     for v in vols:
         for k, (ms, n) in v.collect_timing().items():
@@ -169,6 +173,28 @@ def multiview_leg(warmup, steps, dtype):
         v.set_timing(False)
     st = r.last_stats()
     pixels = sum(mv.view_size(v) ** 2 for v in range(mv.n_views))
+    # the same sequence as captured frames (cinr_frame_graph) on a fresh cache;
+    # the launch shapes were tuned by the frames above
+    gcache = cinr.Cache(vols, cs.brick, cs.n_lods, cs.pool_bricks, cs.max_requests, preload_period=cs.preload_period)
+    fg = cinr.FrameGraph(gcache, [(vols[mv.view_inr(v)], mv.camera(v, 0), tfs[0]) for v in range(mv.n_views)],
+                         mv.step, mv.lod_scale, seed=mv.seed, ert_threshold=mv.ert_threshold,
+                         samples_per_iter=mv.samples_per_iter, dtype=dtype)
+
+    def gframe(f):
+        if f % 30 == 0:
+            for t in fg.tfs:
+                t.copy_(tfs[0 if f % 60 < 30 else 30])
+        fg.render([mv.camera(v, f) for v in range(mv.n_views)], f)
+
+    for f in range(warmup):
+        gframe(f)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for f in range(warmup, warmup + steps):
+        gframe(f)
+    torch.cuda.synchronize()
+    dtg = time.perf_counter() - t0
+    n_graph, n_eager, n_tail = fg.counts()
     # decoding throughput of the shared cache: a prefill of bricks of all INRs in one launch
     K = cache.keys_per_volume
     fresh = cinr.Cache(vols, cs.brick, cs.n_lods, 8192, 256)
@@ -187,6 +213,9 @@ def multiview_leg(warmup, steps, dtype):
             "aggregate_view_fps": round(mv.n_views * steps / dt, 2),
             "pixels_per_s": round(pixels * steps / dt, 1),
             "stage_ms_per_frame": {k: round(v[0] / steps, 4) for k, v in stages.items()},
+            "graph_frame_ms": round(dtg / steps * 1e3, 4),
+            "graph_aggregate_view_fps": round(mv.n_views * steps / dtg, 2),
+            "graph_frames_replayed_eager_tail": [n_graph, n_eager, n_tail],
             "requested_selected_last_frame": [st[0]["requested"], st[0]["selected"]],
             "multi_inr_decode_bricks_per_s": round(dec, 1)}
 

@@ -331,6 +331,42 @@ typedef struct {
  * launched back to back and synchronised once. */
 cinr_status cinr_render_views(cinr_cache cache, int32_t n_views, const cinr_view* views, void* stream);
 
+/* Captured multi-view frames (hipGraph).  A frame graph is made for a fixed
+ * set of views: volumes, image sizes and projections, TF, image, statistics
+ * and workspace pointers, and every render parameter except frame_index.
+ * Each cinr_frame_graph_render call renders one frame of those views with new
+ * cameras and a new frame index, with the same results as cinr_render_views
+ * (bit for bit), by replaying two captured graphs:
+ *   - start: set-up and first march of every view (on the cache's side
+ *     streams, as in cinr_render_views) and the pending-ray counts of all
+ *     views, written to pinned host memory;
+ *   - end: ranking, request selection, insertion, decoding and frame ends.
+ * The host waits once between the two; views that still have pending rays
+ * (true misses) finish their wavefront iterations with ordinary launches
+ * before the end graph.  The camera, frame index and LoD seed are read from
+ * device memory that the start graph fills from a host block, so the graphs
+ * do not change from frame to frame; two end graphs are kept, with and
+ * without the LRU victim pass.  While a view's launch shape is being tuned
+ * online (pipe_depth or xcd_bands 0), frames are rendered as by
+ * cinr_render_views and nothing is captured.  Stage timing does not cover
+ * graph frames.  The TF contents may change between frames (the macro-cell
+ * visibility is recomputed by every frame).  The graph borrows the cache,
+ * the volumes and every buffer of the views; destroy it first.  Calls on one
+ * graph, or on graphs of one cache, must not overlap.
+ * Errors: CINR_INVALID_ARG (as cinr_render_views; a camera whose size or
+ * projection differs from the one the graph was made with), CINR_HIP_ERROR
+ * (capture, instantiation or launch). */
+typedef struct cinr_frame_graph_s* cinr_frame_graph;
+cinr_status cinr_frame_graph_create(cinr_cache cache, int32_t n_views, const cinr_view* views, cinr_frame_graph* out);
+/* cameras: [n_views], in the order of the views given at creation. */
+cinr_status cinr_frame_graph_render(cinr_frame_graph graph, const cinr_camera* cameras, int32_t frame_index,
+                                    void* stream);
+/* Frames rendered from the graphs, frames rendered eagerly (launch shape
+ * still being tuned), and graph frames that needed further iterations. */
+cinr_status cinr_frame_graph_counts(cinr_frame_graph graph, int64_t* graph_frames, int64_t* eager_frames,
+                                    int64_t* tail_frames);
+void cinr_frame_graph_destroy(cinr_frame_graph graph);
+
 /* The sampler launch shape tuned online for a volume and image size (see
  * cinr_render_params), and the trial frames still to run (0 once tuned). */
 cinr_status cinr_tuned_launch(cinr_volume vol, int32_t width, int32_t height, int32_t* pipe_depth,

@@ -112,6 +112,10 @@ def lib():
             "cinr_create_cache_multi": [P, i32, P, P, sz, P, sz, P, P],
             "cinr_render_views": [P, i32, P, P],
             "cinr_tuned_launch": [P, i32, i32, P, P, P],
+            "cinr_frame_graph_create": [P, i32, P, P],
+            "cinr_frame_graph_render": [P, P, i32, P],
+            "cinr_frame_graph_counts": [P, P, P, P],
+            "cinr_frame_graph_destroy": [P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -120,6 +124,7 @@ def lib():
         L.cinr_destroy_volume.restype = None
         L.cinr_destroy_cache.restype = None
         L.cinr_train_destroy.restype = None
+        L.cinr_frame_graph_destroy.restype = None
         L.cinr_last_error.restype = C.c_char_p
         _lib = L
     return _lib
@@ -452,9 +457,10 @@ class MultiViewRenderer:
         self.stats = torch.zeros((n_views, len(STAT_FIELDS)), dtype=torch.int64, device=device)
         self._keep = []
 
-    def render(self, cache: Cache, views, step, lod_scale=0.0, frame_index=0, seed=0, ert_threshold=2.0,
-               samples_per_iter=32, dtype="f32", outs=None, pipe_depth=0, xcd_bands=0):
-        """views: list of (volume, camera, tf); returns the list of RGBA images."""
+    def describe(self, views, step, lod_scale=0.0, frame_index=0, seed=0, ert_threshold=2.0, samples_per_iter=32,
+                 dtype="f32", outs=None, pipe_depth=0, xcd_bands=0):
+        """The cinr_view array of `views` (list of (volume, camera, tf)) and
+        their output images; the TF tensors are kept alive by the renderer."""
         n = len(views)
         arr = (ViewDesc * n)()
         outs = outs or [None] * n
@@ -483,12 +489,62 @@ class MultiViewRenderer:
             v.d_workspace = self.ws[i].data_ptr()
             v.workspace_bytes = self.ws[i].numel()
         self._keep = keep
-        _check(lib().cinr_render_views(cache.h, n, arr, _stream()))
+        return arr, outs
+
+    def render(self, cache: Cache, views, step, lod_scale=0.0, frame_index=0, seed=0, ert_threshold=2.0,
+               samples_per_iter=32, dtype="f32", outs=None, pipe_depth=0, xcd_bands=0):
+        """views: list of (volume, camera, tf); returns the list of RGBA images."""
+        arr, outs = self.describe(views, step, lod_scale, frame_index, seed, ert_threshold, samples_per_iter, dtype,
+                                  outs, pipe_depth, xcd_bands)
+        _check(lib().cinr_render_views(cache.h, len(views), arr, _stream()))
         return outs
 
     def last_stats(self):
         v = self.stats.cpu().numpy()
         return [{k: int(row[i]) for i, k in enumerate(STAT_FIELDS)} for row in v]
+
+
+class FrameGraph:
+    """Captured multi-view frames (cinr_frame_graph_*): made once for a fixed
+    set of views (list of (volume, camera, tf)) and parameters; each render()
+    replays the frame with new cameras (same sizes and projections) and a new
+    frame index.  The TF tensors (`tfs`) may be updated in place between
+    frames.  Owns the views' workspaces, images and statistics."""
+
+    def __init__(self, cache: Cache, views, step, lod_scale=0.0, seed=0, ert_threshold=2.0, samples_per_iter=32,
+                 dtype="f32", pipe_depth=0, xcd_bands=0, device="cuda"):
+        self.cache = cache
+        self.volumes = [v for v, _, _ in views]
+        self.mv = MultiViewRenderer(len(views), device)
+        arr, self.outs = self.mv.describe(views, step, lod_scale, 0, seed, ert_threshold, samples_per_iter, dtype,
+                                          None, pipe_depth, xcd_bands)
+        self.tfs = list(self.mv._keep)
+        self.n = len(views)
+        h = C.c_void_p()
+        _check(lib().cinr_frame_graph_create(cache.h, self.n, arr, C.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.cinr_frame_graph_destroy(self.h)
+            self.h = None
+
+    def render(self, cameras, frame_index):
+        """Renders one frame; returns the list of RGBA images (the same tensors every frame)."""
+        if len(cameras) != self.n:
+            raise ValueError(f"{len(cameras)} cameras for {self.n} views")
+        arr = (CameraDesc * self.n)(*[camera_desc(c) for c in cameras])
+        _check(lib().cinr_frame_graph_render(self.h, arr, int(frame_index), _stream()))
+        return self.outs
+
+    def counts(self):
+        """(graph frames, eager frames, graph frames with further iterations)."""
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().cinr_frame_graph_counts(self.h, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+    def last_stats(self):
+        return self.mv.last_stats()
 
 
 def tuned_launch(volume, width, height):

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -122,6 +123,7 @@ struct cinr_volume_s {
     int32_t M[3] = {0, 0, 0};
     int64_t table_entries = 0;  // hash-table entries over all levels
     int32_t* pinned = nullptr;  // readback of the live-ray counts (one per view)
+    FrameVar* stage = nullptr;  // per-frame values of the views (pinned host, read by k_frame_begin)
     hipEvent_t ev = nullptr;
     Timing timing;
     std::map<uint64_t, SamplerTuner> tuners;  // by image size
@@ -281,6 +283,7 @@ extern "C" cinr_status cinr_create_volume_grid(const cinr_grid_desc* d, cinr_vol
 extern "C" void cinr_destroy_volume(cinr_volume v) {
     if (!v) return;
     if (v->pinned) (void)hipHostFree(v->pinned);
+    if (v->stage) (void)hipHostFree(v->stage);
     if (v->ev) (void)hipEventDestroy(v->ev);
     for (auto& r : v->timing.recs) {
         (void)hipEventDestroy(r.a);
@@ -521,8 +524,8 @@ extern "C" cinr_status cinr_cache_prefill(cinr_cache c, const int32_t* d_keys, i
     if (n == 0) return CINR_OK;
     hipStream_t s = (hipStream_t)stream;
     c->used_bound = std::min<int64_t>(c->used_bound + n, c->c.pool_bricks);
-    HIP_TRY(launch_prefill_setup(c->c, d_keys, n, s));
-    HIP_TRY(launch_insert(c->c, c->g, stamp, n, s));
+    HIP_TRY(launch_prefill_setup(c->c, d_keys, n, stamp, s));
+    HIP_TRY(launch_insert(c->c, c->g, n, s));
     HIP_TRY(decode_selected(c, n, prec, s));
     return CINR_OK;
 }
@@ -543,6 +546,7 @@ struct RenderLayout {
     uint32_t* claim;
     uint64_t* flags;
     unsigned long long* stats;
+    FrameVar* var;
 };
 
 static size_t render_layout(int64_t npix, int32_t S, int64_t n_cells, RenderLayout* r, void* base) {
@@ -559,6 +563,7 @@ static size_t render_layout(int64_t npix, int32_t S, int64_t n_cells, RenderLayo
     x.claim = cv.take<uint32_t>(16 * kClaimStride);
     x.flags = cv.take<uint64_t>((size_t)(n_cells + 63) / 64);
     x.stats = cv.take<unsigned long long>(ST_COUNT);
+    x.var = cv.take<FrameVar>(1);
     if (r) *r = x;
     return cv.off;
 }
@@ -578,6 +583,8 @@ struct ViewRun {
     cinr_volume v = nullptr;
     hipStream_t st = nullptr;  // stream of this view's launches
     FrameDev f{};
+    FrameVar hv{};              // this frame's camera, index and LoD seed (host copy)
+    FrameVar* stage = nullptr;  // pinned host block that k_frame_begin reads hv from
     RenderLayout L{};
     int64_t npix = 0, max_iters = 0, queued = 0;
     int32_t prec = 0;
@@ -601,6 +608,41 @@ cinr_status check_camera(const cinr_camera* cam) {
     if (cam->forward[0] == 0.0f && cam->forward[1] == 0.0f && cam->forward[2] == 0.0f)
         return fail(CINR_INVALID_ARG, "zero forward vector");
     return CINR_OK;
+}
+
+// Per-frame values of a view: camera, frame index, and the per-frame seed and
+// LoD floor of the cached mode (Sec. 4.3.4 pre-load, Sec. 5.3 seed).
+FrameVar frame_var(cinr_cache c, const cinr_camera* cam, const cinr_render_params* rp) {
+    FrameVar h{};
+    h.cam.proj = cam->projection;
+    h.cam.W = cam->width;
+    h.cam.H = cam->height;
+    for (int a = 0; a < 3; ++a) {
+        h.cam.eye[a] = cam->eye[a];
+        h.cam.fwd[a] = cam->forward[a];
+        h.cam.right[a] = cam->right[a];
+        h.cam.up[a] = cam->up[a];
+    }
+    h.cam.tanx = cam->tan_half_x;
+    h.cam.tany = cam->tan_half_y;
+    h.cam.ow = cam->ortho_w;
+    h.cam.oh = cam->ortho_h;
+    h.frame = rp->frame_index;
+    if (c) {
+        // per-frame seed of the stochastic LoD: high half of SplitMix64 of (seed << 32 | frame)
+        uint64_t z = (((uint64_t)rp->seed << 32) | (uint64_t)(uint32_t)rp->frame_index) + 0x9e3779b97f4a7c15ull;
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+        z = z ^ (z >> 31);
+        h.frame_seed = (uint32_t)(z >> 32);
+        int32_t floor_ = 0;
+        if (c->desc.preload_period > 0) {
+            floor_ = c->desc.n_lods - 1 - rp->frame_index / c->desc.preload_period;
+            if (floor_ < 0) floor_ = 0;
+        }
+        h.lod_floor = floor_;
+    }
+    return h;
 }
 
 // Validates one view and fills its frame descriptor.
@@ -645,27 +687,19 @@ cinr_status prepare_view(cinr_cache c, cinr_volume v, const cinr_camera* cam, co
     const RenderLayout& L = r.L;
     FrameDev& f = r.f;
     f = FrameDev{};
-    f.cam.proj = cam->projection;
-    f.cam.W = cam->width;
-    f.cam.H = cam->height;
+    f.W = cam->width;
+    f.H = cam->height;
+    f.var = L.var;
     for (int a = 0; a < 3; ++a) {
-        f.cam.eye[a] = cam->eye[a];
-        f.cam.fwd[a] = cam->forward[a];
-        f.cam.right[a] = cam->right[a];
-        f.cam.up[a] = cam->up[a];
         f.dims[a] = v->desc.dims[a];
         f.vm1[a] = (float)(v->desc.dims[a] - 1);
         f.M[a] = v->M[a];
     }
-    f.cam.tanx = cam->tan_half_x;
-    f.cam.tany = cam->tan_half_y;
-    f.cam.ow = cam->ortho_w;
-    f.cam.oh = cam->ortho_h;
+    r.hv = frame_var(cached ? c : nullptr, cam, rp);
     f.step = rp->step;
     f.lod_scale = rp->lod_scale;
     f.ert = rp->ert_threshold;
     f.ert_on = rp->ert_threshold <= 1.0f;
-    f.frame = rp->frame_index;
     f.S = S;
     f.mode = rp->mode;
     // launch shape: given, or tuned online for this image size
@@ -697,19 +731,6 @@ cinr_status prepare_view(cinr_cache c, cinr_volume v, const cinr_camera* cam, co
     f.ctr = L.ctr;
     f.stats = d_stats ? reinterpret_cast<unsigned long long*>(d_stats) : L.stats;
     if (cached) {
-        const cinr_cache_desc& cd = c->desc;
-        // per-frame seed of the stochastic LoD: high half of SplitMix64 of (seed << 32 | frame)
-        uint64_t z = (((uint64_t)rp->seed << 32) | (uint64_t)(uint32_t)rp->frame_index) + 0x9e3779b97f4a7c15ull;
-        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
-        z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
-        z = z ^ (z >> 31);
-        f.frame_seed = (uint32_t)(z >> 32);
-        int32_t floor_ = 0;
-        if (cd.preload_period > 0) {
-            floor_ = cd.n_lods - 1 - rp->frame_index / cd.preload_period;
-            if (floor_ < 0) floor_ = 0;
-        }
-        f.lod_floor = floor_;
         f.geo = c->g;
         f.key_base = (int32_t)(vi * c->g.keys_per_vol);
         f.pt = c->c.pt + f.key_base;
@@ -732,6 +753,7 @@ cinr_status prepare_view(cinr_cache c, cinr_volume v, const cinr_camera* cam, co
 cinr_status ensure_readback(cinr_volume v) {
     if (!v->pinned) {
         HIP_TRY(hipHostMalloc((void**)&v->pinned, sizeof(uint32_t) * kMaxViews, hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc((void**)&v->stage, sizeof(FrameVar) * kMaxViews, hipHostMallocDefault));
         HIP_TRY(hipEventCreateWithFlags(&v->ev, hipEventDisableTiming));
     }
     return CINR_OK;
@@ -744,6 +766,10 @@ cinr_status view_setup(cinr_cache c, ViewRun& r, bool first, hipStream_t s) {
     const bool cached = r.f.mode == CINR_CACHED;
     CacheCtr* cctr = cached && first ? c->c.ctr : nullptr;
     const int32_t n_ctr = (int32_t)std::min<int64_t>(r.max_iters + 2, kMaxIters + 2);
+    // the host block is read by this frame's k_frame_begin; every frame call
+    // waits for its first marches before returning, so the block is free again
+    *r.stage = r.hv;
+    r.f.var_src = r.stage;
     StageTimer st_(v->timing, s, CINR_STAGE_SETUP);
     HIP_TRY(launch_frame_begin(r.f, n_ctr, v->desc.d_macrocells, v->n_cells, cctr, s));
     if (cached && first && c->c.last_req) HIP_TRY(launch_clear_last_req(c->c, c->g.n_keys, s));
@@ -817,25 +843,30 @@ cinr_status tuner_collect(ViewRun& r) {
     return CINR_OK;
 }
 
-// Runs the wavefront iterations of all views to completion; the pending
-// counts of all live views are read back with one synchronisation per round.
-// Several views of a cached frame run on the cache's side streams (forked from
-// and joined back into `s`) so that their marches overlap; the frame-wide
-// counters are cleared on `s` before the fork.
-cinr_status run_views(cinr_cache c, std::vector<ViewRun>& runs, hipStream_t s) {
-    cinr_volume rv = runs[0].v;
-    cinr_status st = ensure_readback(rv);
-    if (st) return st;
-    const bool side = c && runs.size() > 1;
-    if (side && !c->fork) {
-        for (int k = 0; k < cinr_cache_s::kViewStreams; ++k) {
-            HIP_TRY(hipStreamCreateWithFlags(&c->vs[k], hipStreamNonBlocking));
-            HIP_TRY(hipEventCreateWithFlags(&c->join[k], hipEventDisableTiming));
-        }
-        HIP_TRY(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
+cinr_status ensure_side_streams(cinr_cache c) {
+    if (c->fork) return CINR_OK;
+    for (int k = 0; k < cinr_cache_s::kViewStreams; ++k) {
+        HIP_TRY(hipStreamCreateWithFlags(&c->vs[k], hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&c->join[k], hipEventDisableTiming));
     }
-    for (size_t i = 0; i < runs.size(); ++i) runs[i].st = side ? c->vs[i % cinr_cache_s::kViewStreams] : s;
-    st = view_setup(c, runs[0], true, s);
+    HIP_TRY(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
+    return CINR_OK;
+}
+
+// Joins the side streams of a multi-view frame back into `s`.
+cinr_status join_side_streams(cinr_cache c, hipStream_t s) {
+    for (int k = 0; k < cinr_cache_s::kViewStreams; ++k) {
+        HIP_TRY(hipEventRecord(c->join[k], c->vs[k]));
+        HIP_TRY(hipStreamWaitEvent(s, c->join[k], 0));
+    }
+    return CINR_OK;
+}
+
+// Frame start of all views: set-up and first march of each, on the view's
+// stream (runs[i].st).  With `side`, the views' streams are forked from `s`
+// after the first view's set-up, which clears the frame-wide counters.
+cinr_status start_views(cinr_cache c, std::vector<ViewRun>& runs, bool side, hipStream_t s) {
+    cinr_status st = view_setup(c, runs[0], true, s);
     if (st) return st;
     if (side) {
         HIP_TRY(hipEventRecord(c->fork, s));
@@ -849,44 +880,79 @@ cinr_status run_views(cinr_cache c, std::vector<ViewRun>& runs, hipStream_t s) {
         st = view_march0(runs[i], runs[i].st);
         if (st) return st;
     }
-    for (;;) {
-        int n_live = 0;
-        for (size_t i = 0; i < runs.size(); ++i) {
-            if (!runs[i].live) continue;
-            const int it = runs[i].n_iters - 1;
-            HIP_TRY(hipMemcpyAsync(rv->pinned + i, &runs[i].f.ctr[it].pending, sizeof(uint32_t), hipMemcpyDeviceToHost,
-                                   runs[i].st));
-            ++n_live;
-        }
-        if (n_live == 0) break;
-        if (side) {
-            for (int k = 0; k < cinr_cache_s::kViewStreams; ++k) HIP_TRY(hipEventRecord(c->join[k], c->vs[k]));
-            for (int k = 0; k < cinr_cache_s::kViewStreams; ++k) HIP_TRY(hipEventSynchronize(c->join[k]));
-        } else {
-            HIP_TRY(hipEventRecord(rv->ev, s));
-            HIP_TRY(hipEventSynchronize(rv->ev));
-        }
-        for (size_t i = 0; i < runs.size(); ++i) {
-            if (!runs[i].live) continue;
-            st = tuner_collect(runs[i]);
-            if (st) return st;
-            st = view_continue(runs[i], ((volatile uint32_t*)rv->pinned)[i], runs[i].st);
-            if (st) return st;
-        }
-    }
-    if (side) {
-        // everything of the views precedes the cache manager on `s`
-        for (int k = 0; k < cinr_cache_s::kViewStreams; ++k) {
-            HIP_TRY(hipEventRecord(c->join[k], c->vs[k]));
-            HIP_TRY(hipStreamWaitEvent(s, c->join[k], 0));
-        }
-    }
     return CINR_OK;
 }
 
+// Wavefront iterations after the first march, to completion; the pending
+// counts of all live views are read back with one synchronisation per round
+// (into `pinned`).  `known`, when given, holds the counts of the first round,
+// already on the host.  With `side`, the view streams are joined into `s` at
+// the end, so that everything of the views precedes the cache manager.
+cinr_status continue_views(cinr_cache c, std::vector<ViewRun>& runs, bool side, uint32_t* pinned, hipEvent_t ev,
+                           const uint32_t* known, hipStream_t s) {
+    for (bool have = known != nullptr;; have = false) {
+        if (!have) {
+            int n_live = 0;
+            for (size_t i = 0; i < runs.size(); ++i) {
+                if (!runs[i].live) continue;
+                const int it = runs[i].n_iters - 1;
+                HIP_TRY(hipMemcpyAsync(pinned + i, &runs[i].f.ctr[it].pending, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                       runs[i].st));
+                ++n_live;
+            }
+            if (n_live == 0) break;
+            if (side) {
+                for (int k = 0; k < cinr_cache_s::kViewStreams; ++k) HIP_TRY(hipEventRecord(c->join[k], c->vs[k]));
+                for (int k = 0; k < cinr_cache_s::kViewStreams; ++k) HIP_TRY(hipEventSynchronize(c->join[k]));
+            } else {
+                HIP_TRY(hipEventRecord(ev, s));
+                HIP_TRY(hipEventSynchronize(ev));
+            }
+        }
+        for (size_t i = 0; i < runs.size(); ++i) {
+            if (!runs[i].live) continue;
+            cinr_status st = tuner_collect(runs[i]);
+            if (st) return st;
+            st = view_continue(runs[i], have ? known[i] : ((volatile uint32_t*)pinned)[i], runs[i].st);
+            if (st) return st;
+        }
+    }
+    if (side) return join_side_streams(c, s);
+    return CINR_OK;
+}
+
+// Runs the wavefront iterations of all views to completion.  Several views of
+// a cached frame run on the cache's side streams so that their marches
+// overlap.
+cinr_status run_views(cinr_cache c, std::vector<ViewRun>& runs, hipStream_t s) {
+    cinr_volume rv = runs[0].v;
+    cinr_status st = ensure_readback(rv);
+    if (st) return st;
+    const bool side = c && runs.size() > 1;
+    if (side) {
+        st = ensure_side_streams(c);
+        if (st) return st;
+    }
+    for (size_t i = 0; i < runs.size(); ++i) {
+        runs[i].st = side ? c->vs[i % cinr_cache_s::kViewStreams] : s;
+        runs[i].stage = rv->stage + i;
+    }
+    st = start_views(c, runs, side, s);
+    if (st) return st;
+    return continue_views(c, runs, side, (uint32_t*)rv->pinned, rv->ev, nullptr, s);
+}
+
+// Whether the next cache-manager pass may need LRU victims (host bound on the
+// occupied slots).
+bool lru_pass_needed(cinr_cache c) {
+    return c->c.pool_bricks > 0 && c->used_bound + c->lim > c->c.pool_bricks;
+}
+
+void note_insertions(cinr_cache c) { c->used_bound = std::min<int64_t>(c->used_bound + c->lim, c->c.pool_bricks); }
+
 // End of a cached frame: ranking and selection of the requests of all views,
 // insertion (free slots, then LRU victims) and decoding of the new bricks.
-cinr_status cache_end_frame(cinr_cache c, int32_t frame_index, int32_t prec, Timing& tm, hipStream_t s) {
+cinr_status cache_end_frame(cinr_cache c, int32_t prec, bool lru_pass, Timing& tm, hipStream_t s) {
     const CacheDev& cd = c->c;
     {
         StageTimer st_(tm, s, CINR_STAGE_CM);
@@ -898,11 +964,12 @@ cinr_status cache_end_frame(cinr_cache c, int32_t frame_index, int32_t prec, Tim
         ta.cap0 = (uint64_t)c->g.n_keys;
         ta.k = c->lim;
         ta.mode = TOPK_RANK;
-        ta.ra = RankArgs{cd.touched, cd.req, cd.last_req, cd.rank, frame_index, cd.rank_window, cd.ranking};
+        ta.ra = RankArgs{cd.touched, cd.req, cd.last_req, cd.rank, &cd.ctr->frame, cd.rank_window, cd.ranking};
         SelectArgs sel{cd.ins_keys, cd.ctr, cd.pool_bricks, c->lim};
         HIP_TRY(launch_topk(ta, c->plan_sel, cd.topk[0], cd.topk[1], cd.sel, &sel, s));
-        // LRU victims, only when the pool may be full
-        if (cd.pool_bricks > 0 && c->used_bound + c->lim > cd.pool_bricks) {
+        // LRU victims, only when the pool may be full (the pass is also gated
+        // on the device by the number of slots to evict)
+        if (lru_pass) {
             TopkArgs tv{};
             tv.count_dev = &cd.ctr->n_used;
             tv.cap0 = (uint64_t)cd.pool_bricks;
@@ -912,8 +979,7 @@ cinr_status cache_end_frame(cinr_cache c, int32_t frame_index, int32_t prec, Tim
             tv.lru_last_used = cd.last_used;
             HIP_TRY(launch_topk(tv, c->plan_vic, cd.topk[0], cd.topk[1], cd.vic, nullptr, s));
         }
-        c->used_bound = std::min<int64_t>(c->used_bound + c->lim, cd.pool_bricks);
-        HIP_TRY(launch_insert(cd, c->g, frame_index + 1, c->lim, s));
+        HIP_TRY(launch_insert(cd, c->g, c->lim, s));
     }
     {
         StageTimer st_(tm, s, CINR_STAGE_DECODE);
@@ -935,17 +1001,21 @@ extern "C" cinr_status cinr_render_frame(cinr_cache c, cinr_volume v, const cinr
     if (st) return st;
     const bool cached = rp->mode == CINR_CACHED;
     if (cached) {
-        st = cache_end_frame(c, rp->frame_index, rp->mlp_dtype, v->timing, s);
+        st = cache_end_frame(c, rp->mlp_dtype, lru_pass_needed(c), v->timing, s);
         if (st) return st;
+        note_insertions(c);
     }
-    HIP_TRY(launch_frame_end(runs[0].f, runs[0].n_iters, cached ? c->c.ctr : nullptr, true, s));
+    HIP_TRY(launch_frame_end(runs[0].f, (int)runs[0].max_iters, cached ? c->c.ctr : nullptr, true, s));
     return CINR_OK;
 }
 
-extern "C" cinr_status cinr_render_views(cinr_cache c, int32_t n_views, const cinr_view* views, void* stream) {
+namespace {
+
+// Validation and descriptors of the views of one multi-view frame.
+cinr_status prepare_views(cinr_cache c, int32_t n_views, const cinr_view* views, std::vector<ViewRun>& runs) {
     if (!c || !views) return fail(CINR_INVALID_ARG, "null argument");
     if (n_views < 1 || n_views > kMaxViews) return fail(CINR_INVALID_ARG, "%d views (1 to %d)", n_views, kMaxViews);
-    std::vector<ViewRun> runs(n_views);
+    runs.assign(n_views, ViewRun{});
     for (int i = 0; i < n_views; ++i) {
         const cinr_view& w = views[i];
         if (w.params.mode != CINR_CACHED) return fail(CINR_INVALID_ARG, "view %d: views render in the cached mode", i);
@@ -957,13 +1027,212 @@ extern "C" cinr_status cinr_render_views(cinr_cache c, int32_t n_views, const ci
                                       w.workspace_bytes, runs[i]);
         if (st) return fail(st, "view %d: %s", i, cinr_last_error());
     }
+    return CINR_OK;
+}
+
+// Cache manager, decoding and frame ends of a multi-view frame.
+cinr_status end_views(cinr_cache c, std::vector<ViewRun>& runs, bool lru_pass, Timing& tm, hipStream_t s) {
+    cinr_status st = cache_end_frame(c, runs[0].prec, lru_pass, tm, s);
+    if (st) return st;
+    const size_t n = runs.size();
+    for (size_t i = 0; i < n; ++i)
+        HIP_TRY(launch_frame_end(runs[i].f, (int)runs[i].max_iters, c->c.ctr, i + 1 == n, s));
+    return CINR_OK;
+}
+
+}  // namespace
+
+extern "C" cinr_status cinr_render_views(cinr_cache c, int32_t n_views, const cinr_view* views, void* stream) {
+    std::vector<ViewRun> runs;
+    cinr_status st = prepare_views(c, n_views, views, runs);
+    if (st) return st;
     hipStream_t s = (hipStream_t)stream;
-    cinr_status st = run_views(c, runs, s);
+    st = run_views(c, runs, s);
     if (st) return st;
-    st = cache_end_frame(c, views[0].params.frame_index, views[0].params.mlp_dtype, views[0].volume->timing, s);
+    st = end_views(c, runs, lru_pass_needed(c), views[0].volume->timing, s);
     if (st) return st;
-    for (int i = 0; i < n_views; ++i)
-        HIP_TRY(launch_frame_end(runs[i].f, runs[i].n_iters, c->c.ctr, i == n_views - 1, s));
+    note_insertions(c);
+    return CINR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Captured multi-view frames
+// ---------------------------------------------------------------------------
+
+struct cinr_frame_graph_s {
+    cinr_cache c = nullptr;
+    std::vector<cinr_view> views;
+    FrameVar* stage = nullptr;    // pinned [n]: per-frame values, read by the captured k_frame_begin launches
+    uint32_t* pending = nullptr;  // pinned [n]: rays pending after the first marches, written by the start graph
+    hipStream_t cs = nullptr;     // capture stream (default priority)
+    hipEvent_t ev = nullptr;
+    hipGraphExec_t start = nullptr;               // set-up and first march of every view, pending counts
+    hipGraphExec_t end[2] = {nullptr, nullptr};   // cache manager, decoding, frame ends; [1] with the LRU pass
+    int64_t n_graph = 0, n_eager = 0, n_tail = 0;
+    ~cinr_frame_graph_s() {
+        if (start) (void)hipGraphExecDestroy(start);
+        for (hipGraphExec_t e : end)
+            if (e) (void)hipGraphExecDestroy(e);
+        if (ev) (void)hipEventDestroy(ev);
+        if (cs) (void)hipStreamDestroy(cs);
+        if (stage) (void)hipHostFree(stage);
+        if (pending) (void)hipHostFree(pending);
+    }
+};
+
+namespace {
+
+// Switches stage timing off for the volumes of a frame while it is captured
+// (timing events are not part of a graph).
+struct TimingOff {
+    std::vector<std::pair<cinr_volume, bool>> saved;
+    explicit TimingOff(const std::vector<ViewRun>& runs) {
+        for (const ViewRun& r : runs) {
+            saved.emplace_back(r.v, r.v->timing.on);
+            r.v->timing.on = false;
+        }
+    }
+    ~TimingOff() {
+        for (auto it = saved.rbegin(); it != saved.rend(); ++it) it->first->timing.on = it->second;
+    }
+};
+
+// Captures `body(stream)` on the graph's capture stream into *exec.
+template <class Body>
+cinr_status capture(cinr_frame_graph g, hipGraphExec_t* exec, Body body) {
+    HIP_TRY(hipStreamBeginCapture(g->cs, hipStreamCaptureModeRelaxed));
+    const cinr_status st = body(g->cs);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(g->cs, &graph);
+    if (st) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return fail(CINR_HIP_ERROR, "graph capture: %s", hipGetErrorString(e));
+    const hipError_t e2 = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e2 != hipSuccess) return fail(CINR_HIP_ERROR, "graph instantiation: %s", hipGetErrorString(e2));
+    return CINR_OK;
+}
+
+}  // namespace
+
+extern "C" cinr_status cinr_frame_graph_create(cinr_cache c, int32_t n_views, const cinr_view* views,
+                                               cinr_frame_graph* out) {
+    if (!out) return fail(CINR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    std::vector<ViewRun> runs;
+    cinr_status st = prepare_views(c, n_views, views, runs);
+    if (st) return st;
+    st = ensure_readback(runs[0].v);
+    if (st) return st;
+    if (n_views > 1) {
+        st = ensure_side_streams(c);
+        if (st) return st;
+    }
+    std::unique_ptr<cinr_frame_graph_s> g(new cinr_frame_graph_s);
+    g->c = c;
+    g->views.assign(views, views + n_views);
+    HIP_TRY(hipHostMalloc((void**)&g->stage, sizeof(FrameVar) * n_views, hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void**)&g->pending, sizeof(uint32_t) * n_views, hipHostMallocDefault));
+    HIP_TRY(hipStreamCreateWithFlags(&g->cs, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&g->ev, hipEventDisableTiming));
+    *out = g.release();
+    return CINR_OK;
+}
+
+extern "C" void cinr_frame_graph_destroy(cinr_frame_graph g) { delete g; }
+
+extern "C" cinr_status cinr_frame_graph_render(cinr_frame_graph g, const cinr_camera* cameras, int32_t frame_index,
+                                               void* stream) {
+    if (!g || !cameras) return fail(CINR_INVALID_ARG, "null argument");
+    const int32_t n = (int32_t)g->views.size();
+    std::vector<cinr_view> vw = g->views;
+    for (int32_t i = 0; i < n; ++i) {
+        const cinr_camera& a = cameras[i];
+        const cinr_camera& b = g->views[i].camera;
+        if (a.width != b.width || a.height != b.height || a.projection != b.projection)
+            return fail(CINR_INVALID_ARG, "view %d: the camera's size and projection must stay those the graph was made with", i);
+        vw[i].camera = a;
+        vw[i].params.frame_index = frame_index;
+    }
+    cinr_cache c = g->c;
+    std::vector<ViewRun> runs;
+    cinr_status st = prepare_views(c, n, vw.data(), runs);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    // launch shapes still being tuned online: eager frames
+    bool tuned = true;
+    for (const ViewRun& r : runs) tuned = tuned && !r.timing_trial;
+    if (!tuned) {
+        g->n_eager += 1;
+        st = run_views(c, runs, s);
+        if (st) return st;
+        st = end_views(c, runs, lru_pass_needed(c), runs[0].v->timing, s);
+        if (st) return st;
+        note_insertions(c);
+        return CINR_OK;
+    }
+    const bool side = n > 1;
+    for (int32_t i = 0; i < n; ++i) {
+        runs[i].st = side ? c->vs[i % cinr_cache_s::kViewStreams] : g->cs;
+        runs[i].stage = g->stage + i;
+    }
+    if (!g->start) {
+        TimingOff off(runs);
+        st = capture(g, &g->start, [&](hipStream_t cs) -> cinr_status {
+            cinr_status r = start_views(c, runs, side, cs);
+            if (r) return r;
+            if (side) {
+                r = join_side_streams(c, cs);
+                if (r) return r;
+            }
+            std::vector<const FrameDev*> fs;
+            for (const ViewRun& v : runs) fs.push_back(&v.f);
+            HIP_TRY(launch_pending_gather(fs.data(), n, g->pending, cs));
+            return CINR_OK;
+        });
+        if (st) return st;
+    }
+    const bool lru = lru_pass_needed(c);
+    if (!g->end[lru]) {
+        TimingOff off(runs);
+        Timing none;
+        st = capture(g, &g->end[lru], [&](hipStream_t cs) { return end_views(c, runs, lru, none, cs); });
+        if (st) return st;
+    }
+    for (int32_t i = 0; i < n; ++i) g->stage[i] = runs[i].hv;
+    HIP_TRY(hipGraphLaunch(g->start, s));
+    HIP_TRY(hipEventRecord(g->ev, s));
+    HIP_TRY(hipEventSynchronize(g->ev));
+    std::vector<uint32_t> known(n);
+    bool tail = false;
+    for (int32_t i = 0; i < n; ++i) {
+        known[i] = ((volatile uint32_t*)g->pending)[i];
+        runs[i].n_iters = 1;
+        runs[i].st = s;
+        tail = tail || known[i] != 0u;
+    }
+    if (tail) {
+        // rays left after the first marches (true misses): the remaining
+        // iterations run eagerly on `s`
+        g->n_tail += 1;
+        cinr_volume rv = runs[0].v;
+        st = continue_views(c, runs, false, (uint32_t*)rv->pinned, rv->ev, known.data(), s);
+        if (st) return st;
+    }
+    HIP_TRY(hipGraphLaunch(g->end[lru], s));
+    note_insertions(c);
+    g->n_graph += 1;
+    return CINR_OK;
+}
+
+extern "C" cinr_status cinr_frame_graph_counts(cinr_frame_graph g, int64_t* graph_frames, int64_t* eager_frames,
+                                               int64_t* tail_frames) {
+    if (!g || !graph_frames || !eager_frames || !tail_frames) return fail(CINR_INVALID_ARG, "null argument");
+    *graph_frames = g->n_graph;
+    *eager_frames = g->n_eager;
+    *tail_frames = g->n_tail;
     return CINR_OK;
 }
 

@@ -14,6 +14,8 @@
 //           (last_used, slot) -- the same top-k on ~(last_used << 32 | slot).
 //           Evicted bricks are unmapped and their ranks forgotten; new bricks
 //           are mapped and stamped f + 1, then decoded into their slots.
+//  The frame index f is read from the cache counters (set by the frame's
+//  first k_frame_begin), so that these launches can be replayed unchanged.
 #include "frame.h"
 
 namespace cinr {
@@ -30,7 +32,7 @@ __global__ void k_cache_init(CacheDev c, int64_t n_keys) {
         c.owner[t] = -1;
         c.last_used[t] = -1;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) *c.ctr = CacheCtr{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+    if (blockIdx.x == 0 && threadIdx.x == 0) *c.ctr = CacheCtr{};
 }
 
 // Clears the request counts kept for dumps (before the frame's sampler).
@@ -40,13 +42,13 @@ __global__ void k_clear_last_req(CacheDev c, int64_t n_keys) {
 }
 
 // Score of touched brick `idx` after its rank update (first selection pass).
-__device__ inline uint64_t rank_score(const RankArgs& ra, uint64_t idx) {
+__device__ inline uint64_t rank_score(const RankArgs& ra, int32_t frame, uint64_t idx) {
     const int32_t key = ra.touched[idx];
     const uint32_t cnt = ra.req[key];
     if (ra.last_req) ra.last_req[key] = cnt;
     const int64_t old = ra.rank[key];
-    int64_t r = old < 0 ? (int64_t)ra.frame + (int64_t)cnt - 1 : old + (int64_t)cnt;
-    const int64_t cap = (int64_t)ra.frame + ra.window;
+    int64_t r = old < 0 ? (int64_t)frame + (int64_t)cnt - 1 : old + (int64_t)cnt;
+    const int64_t cap = (int64_t)frame + ra.window;
     if (r > cap) r = cap;
     ra.rank[key] = r;
     ra.req[key] = 0u;
@@ -75,6 +77,7 @@ __global__ __launch_bounds__(256) void k_topk(TopkArgs a) {
     const uint32_t have = base >= c ? 0u : (uint32_t)(c - base < kTopkChunk ? c - base : kTopkChunk);
     uint32_t m = 1;
     while (m < have) m <<= 1;
+    const int32_t frame = (a.pass == 0 && a.mode == TOPK_RANK) ? *a.ra.frame : 0;
     for (uint32_t e = threadIdx.x; e < m; e += 256) {
         const uint64_t idx = base + e;
         uint64_t v = 0ull;
@@ -82,7 +85,7 @@ __global__ __launch_bounds__(256) void k_topk(TopkArgs a) {
             if (a.pass == 0 && a.mode == TOPK_LRU)
                 v = ~(((uint64_t)(uint32_t)a.lru_last_used[idx] << 32) | idx);
             else if (a.pass == 0 && a.mode == TOPK_RANK)
-                v = rank_score(a.ra, idx);
+                v = rank_score(a.ra, frame, idx);
             else
                 v = a.in[idx];
         }
@@ -130,21 +133,23 @@ __global__ __launch_bounds__(256) void k_topk(TopkArgs a) {
 }
 
 // Prefill: the given keys are inserted into free slots only.
-__global__ void k_prefill_setup(CacheDev c, const int32_t* keys, int32_t n) {
+__global__ void k_prefill_setup(CacheDev c, const int32_t* keys, int32_t n, int32_t stamp) {
     for (int32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) c.ins_keys[t] = keys[t];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         CacheCtr* ctr = c.ctr;
         const uint32_t n_free = (uint32_t)c.pool_bricks - ctr->n_used;
         const uint32_t nn = (uint32_t)n <= n_free ? (uint32_t)n : n_free;
         if ((uint32_t)n > n_free) ctr->error |= 1u;
+        ctr->frame = stamp - 1;  // k_insert stamps frame + 1
         ctr->n_sel = nn;
         ctr->n_free = n_free;
         ctr->need_evict = 0u;
     }
 }
 
-__global__ void k_insert(CacheDev c, CacheGeom g, int32_t stamp, int32_t finish_inline) {
+__global__ void k_insert(CacheDev c, CacheGeom g, int32_t finish_inline) {
     const CacheCtr ctr = *c.ctr;
+    const int32_t stamp = ctr.frame + 1;
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ctr.n_sel; t += gridDim.x * blockDim.x) {
         const int32_t key = c.ins_keys[t];
         int32_t slot;
@@ -239,21 +244,21 @@ hipError_t launch_topk(const TopkArgs& base, const TopkPlan& plan, uint64_t* buf
     return hipGetLastError();
 }
 
-hipError_t launch_prefill_setup(const CacheDev& c, const int32_t* keys, int32_t n, hipStream_t s) {
+hipError_t launch_prefill_setup(const CacheDev& c, const int32_t* keys, int32_t n, int32_t stamp, hipStream_t s) {
     int b = (n + 255) / 256;
     b = b < 1 ? 1 : (b > 1024 ? 1024 : b);
-    hipLaunchKernelGGL(k_prefill_setup, dim3(b), dim3(256), 0, s, c, keys, n);
+    hipLaunchKernelGGL(k_prefill_setup, dim3(b), dim3(256), 0, s, c, keys, n, stamp);
     return hipGetLastError();
 }
 
-hipError_t launch_insert(const CacheDev& c, const CacheGeom& g, int32_t stamp, int32_t cap, hipStream_t s) {
+hipError_t launch_insert(const CacheDev& c, const CacheGeom& g, int32_t cap, hipStream_t s) {
     if (cap <= 256) {
-        hipLaunchKernelGGL(k_insert, dim3(1), dim3(256), 0, s, c, g, stamp, 1);
+        hipLaunchKernelGGL(k_insert, dim3(1), dim3(256), 0, s, c, g, 1);
         return hipGetLastError();
     }
     int b = (cap + 255) / 256;
     b = b > 1024 ? 1024 : b;
-    hipLaunchKernelGGL(k_insert, dim3(b), dim3(256), 0, s, c, g, stamp, 0);
+    hipLaunchKernelGGL(k_insert, dim3(b), dim3(256), 0, s, c, g, 0);
     hipLaunchKernelGGL(k_insert_finish, dim3(1), dim3(64), 0, s, c);
     return hipGetLastError();
 }

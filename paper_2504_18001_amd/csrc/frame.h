@@ -31,6 +31,7 @@ struct CacheCtr {
     uint32_t n_misslog;
     uint32_t n_evlog;
     uint32_t error;
+    int32_t frame;        // frame whose requests are ranked; insertions are stamped frame + 1
 };
 
 struct MissLogRec {
@@ -63,15 +64,28 @@ struct CacheDev {
     int32_t pool_bricks, max_requests, rank_window, ranking, ins_cap;
 };
 
-struct FrameDev {
+// Values of a view that change from one frame to the next while its launch
+// sequence stays the same: the camera, the frame index, and the seed and floor
+// of the stochastic LoD.  The kernels read them from device memory, where
+// k_frame_begin copies them from a host block, so that the launches of a frame
+// can be captured once and replayed.
+struct FrameVar {
     CamDev cam;
+    int32_t frame;
+    uint32_t frame_seed;
+    int32_t lod_floor;
+    int32_t pad[10];
+};
+static_assert(sizeof(FrameVar) == 128, "FrameVar is copied as 32 words");
+
+struct FrameDev {
+    int32_t W, H;  // image size (fixed for a view; the camera itself is in *var)
+    FrameVar* var;            // device copy of the frame's values
+    const FrameVar* var_src;  // host block (pinned) read by k_frame_begin
     int32_t dims[3];
     float vm1[3];
     float step, lod_scale, ert;
     int32_t ert_on;
-    uint32_t frame_seed;
-    int32_t frame;
-    int32_t lod_floor;
     int32_t S;
     int32_t mode;
     int32_t xcd_bands;  // image bands per XCD in the march kernel's work split
@@ -142,7 +156,8 @@ struct RankArgs {
     uint32_t* req;
     uint32_t* last_req;  // nullable
     int64_t* rank;
-    int32_t frame, window, ranking;
+    const int32_t* frame;  // the cache's frame index (CacheCtr::frame)
+    int32_t window, ranking;
 };
 
 struct SelectArgs {
@@ -174,14 +189,15 @@ hipError_t launch_frame_begin(const FrameDev& f, int32_t n_iter_ctr, const float
                               CacheCtr* cctr, hipStream_t s);
 hipError_t launch_march(const FrameDev& f, int it, int64_t max_rays, hipStream_t s);
 hipError_t launch_shade(const FrameDev& f, int it, int64_t cap_rays, hipStream_t s);
-hipError_t launch_frame_end(const FrameDev& f, int n_iters, CacheCtr* cctr, bool reset, hipStream_t s);
+hipError_t launch_frame_end(const FrameDev& f, int max_iters, CacheCtr* cctr, bool reset, hipStream_t s);
+hipError_t launch_pending_gather(const FrameDev* const* fs, int n, uint32_t* host_out, hipStream_t s);
 
 // cache launchers
 hipError_t launch_cache_init(const CacheDev& c, int64_t n_keys, hipStream_t s);
 hipError_t launch_topk(const TopkArgs& base, const TopkPlan& plan, uint64_t* buf0, uint64_t* buf1, uint64_t* final_out,
                        const SelectArgs* epilogue, hipStream_t s);
-hipError_t launch_prefill_setup(const CacheDev& c, const int32_t* keys, int32_t n, hipStream_t s);
-hipError_t launch_insert(const CacheDev& c, const CacheGeom& g, int32_t stamp, int32_t cap, hipStream_t s);
+hipError_t launch_prefill_setup(const CacheDev& c, const int32_t* keys, int32_t n, int32_t stamp, hipStream_t s);
+hipError_t launch_insert(const CacheDev& c, const CacheGeom& g, int32_t cap, hipStream_t s);
 hipError_t launch_clear_last_req(const CacheDev& c, int64_t n_keys, hipStream_t s);
 
 // inr.hip launchers

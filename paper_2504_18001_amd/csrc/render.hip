@@ -59,6 +59,25 @@ struct GlobalFlags {
     __device__ bool get(uint32_t cell) const { return (w[cell >> 6] >> (cell & 63u)) & 1ull; }
 };
 
+// Per-frame values that the sampler reads for every sample (loaded once per
+// launch from the frame's device block).
+struct FrameHot {
+    float eye[3];
+    uint32_t seed;
+    int32_t lod_floor;
+    int32_t frame;
+};
+
+__device__ inline FrameHot load_hot(const FrameVar* v) {
+    FrameHot h;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) h.eye[a] = v->cam.eye[a];
+    h.seed = v->frame_seed;
+    h.lod_floor = v->lod_floor;
+    h.frame = v->frame;
+    return h;
+}
+
 // Sampler of Algorithm 2 for one position: macro-cell skip, stochastic LoD,
 // page-table lookup at that LoD and every coarser one, trilinear fetch.  The
 // flag read and the first page-table read are issued together; a skipped
@@ -66,8 +85,8 @@ struct GlobalFlags {
 // 4 GiB (compile-time brick offsets, 32-bit byte offsets into the pool) and
 // macro-cells of 16^3 voxels.
 template <bool kFast, class Flags>
-__device__ inline SampleRes sample_cache(const FrameDev& f, const LodGeom* lg, const Flags& fl, const float p[3],
-                                         SlotCache& sc) {
+__device__ inline SampleRes sample_cache(const FrameDev& f, const FrameHot& h, const LodGeom* lg, const Flags& fl,
+                                         const float p[3], SlotCache& sc) {
     constexpr int kB = kFast ? 16 : 0;
     SampleRes s;
     s.slot = -1;
@@ -88,7 +107,7 @@ __device__ inline SampleRes sample_cache(const FrameDev& f, const LodGeom* lg, c
         return s;
     }
     const int32_t nl = f.geo.n_lods;
-    const int32_t L = select_lod(p, f.cam.eye, f.lod_scale, f.frame_seed, f.lod_floor, nl);
+    const int32_t L = select_lod(p, h.eye, f.lod_scale, h.seed, h.lod_floor, nl);
     const int32_t B = kFast ? kB : f.geo.brick;
     s.status = S_MISS;
     for (int32_t Lp = L; Lp < nl; ++Lp) {
@@ -252,7 +271,7 @@ struct RayBook {
     int32_t rk = -1;
     uint32_t rc = 0;
     int32_t ls0 = -1, ls1 = -1;
-    __device__ void note(const FrameDev& f, ColdRef c, const SampleRes& s) {
+    __device__ void note(const FrameDev& f, int32_t frame, ColdRef c, const SampleRes& s) {
         if (f.mode != CINR_CACHED || s.status == S_SKIP) return;
         if (s.status != S_HIT) {
             if (s.req_key != rk) {
@@ -264,7 +283,7 @@ struct RayBook {
             }
         }
         if (s.slot >= 0 && s.slot != ls0 && s.slot != ls1) {
-            f.last_used[s.slot] = f.frame;
+            f.last_used[s.slot] = frame;
             ls1 = ls0;
             ls0 = s.slot;
         }
@@ -282,6 +301,9 @@ __global__ __launch_bounds__(kBlock) void k_frame_begin(FrameDev f, int32_t n_ct
     alpha[threadIdx.x] = f.tf[4 * threadIdx.x + 3];
     __syncthreads();
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    // the frame's camera, index and LoD seed: host block -> device
+    if (t < 32) reinterpret_cast<uint32_t*>(f.var)[t] = reinterpret_cast<const uint32_t*>(f.var_src)[t];
+    if (t == 0 && cctr) cctr->frame = f.var_src->frame;
     if (t < n_ctr) f.ctr[t] = IterCtr{0u, 0u, 0u, 0u};
     if (t < 16) f.claim[t * kClaimStride] = 0u;
     if (t < ST_COUNT) f.stats[t] = 0ull;
@@ -353,6 +375,7 @@ struct UnitQueue {
 // (at least 4 waves per SIMD: the register budget is 128 VGPRs)
 template <int kPipe, bool kLdsFlags, bool kFast>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_march(FrameDev f, int32_t it, uint32_t n0) {
+    const FrameHot hot = load_hot(f.var);  // before any store of this kernel
     __shared__ float4 tfs[256];
     __shared__ LodGeom lgs[kMaxLods];
     __shared__ uint64_t sflags[kLdsFlags ? kMaxLdsFlagWords : 1];
@@ -371,7 +394,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
     __shared__ MarchCold cold_s;
     if (threadIdx.x == 0) {
         MarchCold& c = cold_s;
-        c.cam = f.cam;
+        c.cam = f.var->cam;
         c.rgba = f.rgba;
         c.k_next = f.k_next;
         c.cur = (it & 1) ? f.live1 : f.live0;
@@ -453,7 +476,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
 #pragma unroll
                 for (int u = 0; u < kPipe; ++u) {
                     if (cnt == u && sample_pos(o, d, ts, te, f.step, k + u, f.vm1, p)) {
-                        grp[u] = sample_cache<kFast>(f, lgs, fl, p, sc);
+                        grp[u] = sample_cache<kFast>(f, hot, lgs, fl, p, sc);
                         ++cnt;
                     }
                 }
@@ -463,7 +486,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
                     if (u >= cnt) break;
                     const SampleRes& sr = grp[u];
                     tally.add(sr.status);
-                    book.note(f, cold, sr);
+                    book.note(f, hot.frame, cold, sr);
                     if (sr.status == S_MISS) {
                         pend = true;
                         run = false;
@@ -492,9 +515,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
                 while (nc < S) {
                     float qp[3];
                     if (!sample_pos(o, d, ts, te, f.step, k + nc, f.vm1, qp)) break;
-                    const SampleRes sr = sample_cache<kFast>(f, lgs, fl, qp, sc);
+                    const SampleRes sr = sample_cache<kFast>(f, hot, lgs, fl, qp, sc);
                     tally.add(sr.status);
-                    book.note(f, cold, sr);
+                    book.note(f, hot.frame, cold, sr);
                     if (sr.status == S_MISS)
                         mask |= 1ull << nc;
                     else
@@ -529,6 +552,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
 }
 
 __global__ __launch_bounds__(kBlock) void k_shade(FrameDev f, int32_t it) {
+    const CamDev cam = f.var->cam;
     __shared__ float4 tfs[256];
     tfs[threadIdx.x] = reinterpret_cast<const float4*>(f.tf)[threadIdx.x];
     __syncthreads();
@@ -552,9 +576,9 @@ __global__ __launch_bounds__(kBlock) void k_shade(FrameDev f, int32_t it) {
         }
         if (!done) {
             k += nc;
-            const int32_t i = pix % f.cam.W, j = pix / f.cam.W;
+            const int32_t i = pix % f.W, j = pix / f.W;
             float o[3], d[3], ts, te;
-            ray_setup(f.cam, f.vm1, i, j, o, d, ts, te);
+            ray_setup(cam, f.vm1, i, j, o, d, ts, te);
             float q[3];
             if (sample_pos(o, d, ts, te, f.step, k, f.vm1, q)) {
                 const int64_t li = wave_append(true, &f.ctr[it + 1].live);
@@ -568,9 +592,13 @@ __global__ __launch_bounds__(kBlock) void k_shade(FrameDev f, int32_t it) {
 
 // Frame statistics of one view; the cache manager's counters are those of the
 // whole frame (all views).  `reset` (the last view) clears the request list.
-__global__ void k_frame_end(FrameDev f, int32_t n_iters, CacheCtr* cctr, int32_t reset) {
+// The view ran march launches 0 .. n-1, where n - 1 is the first iteration
+// that left no ray pending, or max_iters - 1.
+__global__ void k_frame_end(FrameDev f, int32_t max_iters, CacheCtr* cctr, int32_t reset) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        f.stats[ST_ITERS] = (unsigned long long)n_iters;
+        int32_t n = 1;
+        while (n < max_iters && f.ctr[n - 1].pending != 0u) ++n;
+        f.stats[ST_ITERS] = (unsigned long long)n;
         if (cctr) {
             f.stats[ST_REQUESTED] = cctr->n_touched;
             f.stats[ST_SELECTED] = cctr->n_sel;
@@ -653,7 +681,7 @@ static hipError_t launch_march_p(const FrameDev& f, int it, int64_t max_rays, ui
 hipError_t launch_march(const FrameDev& f, int it, int64_t max_rays, hipStream_t s) {
     // iteration 0 walks all pixels in 8x8 tiles; later iterations at most
     // `max_rays` re-queued rays
-    const uint32_t n0 = (uint32_t)(((f.cam.W + 7) / 8) * ((f.cam.H + 7) / 8)) * 64u;
+    const uint32_t n0 = (uint32_t)(((f.W + 7) / 8) * ((f.H + 7) / 8)) * 64u;
     const int64_t n = it == 0 ? (int64_t)n0 : max_rays;
     // kPipe: samples decided and fetched ahead per ray (8 runs as 4)
     switch (f.pipe) {
@@ -668,8 +696,28 @@ hipError_t launch_shade(const FrameDev& f, int it, int64_t cap_rays, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_frame_end(const FrameDev& f, int n_iters, CacheCtr* cctr, bool reset, hipStream_t s) {
-    hipLaunchKernelGGL(k_frame_end, dim3(1), dim3(64), 0, s, f, n_iters, cctr, reset ? 1 : 0);
+hipError_t launch_frame_end(const FrameDev& f, int max_iters, CacheCtr* cctr, bool reset, hipStream_t s) {
+    hipLaunchKernelGGL(k_frame_end, dim3(1), dim3(64), 0, s, f, max_iters, cctr, reset ? 1 : 0);
+    return hipGetLastError();
+}
+
+// Pending-ray counts of the first march of up to 64 views, written straight
+// into (pinned) host memory: one launch instead of one copy per view.
+struct PendingSrc {
+    const uint32_t* p[64];
+};
+
+__global__ void k_pending_gather(PendingSrc src, int32_t n, uint32_t* host_out) {
+    const int32_t t = threadIdx.x;
+    if (t < n) host_out[t] = *src.p[t];
+    __threadfence_system();
+}
+
+hipError_t launch_pending_gather(const FrameDev* const* fs, int n, uint32_t* host_out, hipStream_t s) {
+    if (n < 1 || n > 64) return hipErrorInvalidValue;
+    PendingSrc src{};
+    for (int i = 0; i < n; ++i) src.p[i] = &fs[i]->ctr[0].pending;
+    hipLaunchKernelGGL(k_pending_gather, dim3(1), dim3(64), 0, s, src, n, host_out);
     return hipGetLastError();
 }
 
