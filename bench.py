@@ -330,6 +330,28 @@ def main():
                  BYTES_RAY * tot["rays"])
     achieved = alg_bytes / (march_ms * 1e-3) / 1e9 if march_ms > 0 else 0.0
 
+    # --- the same cached sequence as captured frames (cinr_frame_graph) --------
+    gcache = new_cache(vol, w)
+    fg = cinr.FrameGraph(gcache, [(vol, cams[0], tfs[0])], w.step, w.lod_scale, seed=w.seed,
+                         ert_threshold=w.ert_threshold, samples_per_iter=w.samples_per_iter, dtype=args.dtype)
+
+    def graph_frames(frames):
+        for f in frames:
+            fg.tfs[0].copy_(tfs[f % w.n_frames])
+            fg.render([cams[f % w.n_frames]], f)
+
+    graph_frames(range(Wm))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    graph_frames(range(Wm, Wm + K))
+    torch.cuda.synchronize()
+    fps_graph = K / (time.perf_counter() - t0)
+    graph_same = bool(torch.equal(fg.outs[0], cached_img))
+    graph_counts = fg.counts()
+    del fg, gcache
+    log(f"[bench] captured frames {args.dtype}: {fps_graph:.1f} fps; image equal to eager: {graph_same}; "
+        f"counts {graph_counts}")
+
     # --- uncached FP32 INR renderer on the same frames ------------------------
     KU = args.uncached_steps or K
     r2 = cinr.Renderer()
@@ -399,6 +421,8 @@ def main():
                    "n_lods": w.cache.n_lods, "pool_bricks": w.cache.pool_bricks,
                    "max_requests": w.cache.max_requests, "step": w.step, "ert": w.ert_threshold,
                    "orbit_frames": w.n_frames},
+        "captured_frames_fps": round(fps_graph, 2),
+        "captured_frames_image_equal": graph_same,
         "uncached_fp32_fps": round(fps_unc, 2),
         "speedup_vs_uncached_fp32": round(fps / fps_unc, 3),
         "mlp_precision": {"bf16x3": "BF16 MFMA, operands split into hi+lo BF16, FP32 accumulation",
@@ -413,7 +437,8 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                      "algorithmic_bytes_per_launch": round(alg_bytes / max(march_n, 1)),
                      "launches": march_n, "avg_launch_ms": round(march_ms / max(march_n, 1), 5),
-                     "launches_before_timed": warm_stages["march"][1]},
+                     "launches_before_timed": warm_stages["march"][1],
+                     "launch_shape": dict(zip(("pipe_depth", "xcd_bands"), cinr.tuned_launch(vol, w.width, w.height)[:2]))},
         "multiview": multi,
         "cpu_baseline": cpu,
     }

@@ -357,7 +357,7 @@ extern "C" cinr_status cinr_decode_bricks(cinr_volume v, const int32_t* d_reqs, 
     if (st) return st;
     CacheGeom g;
     geometry(v->desc.dims, brick, kMaxLods, g);
-    HIP_TRY(inr_decode_bricks(v->m, g, d_reqs, nullptr, n, nullptr, d_out, prec, (hipStream_t)stream));
+    HIP_TRY(inr_decode_bricks(v->m, g, d_reqs, nullptr, nullptr, n, nullptr, d_out, prec, (hipStream_t)stream));
     return CINR_OK;
 }
 
@@ -504,13 +504,15 @@ extern "C" cinr_status cinr_create_cache(cinr_volume v, const cinr_cache_desc* d
     return cinr_create_cache_multi(&v, 1, d, d_pool, pool_bytes, d_ws, ws_bytes, stream, out);
 }
 
-// Decoding of the bricks selected for insertion (at most n_cap of them).
-static hipError_t decode_selected(cinr_cache c, int32_t n_cap, int32_t prec, hipStream_t s) {
+// Decoding of the bricks selected for insertion (at most n_cap of them;
+// none unless *gate != 0 when a gate is given).
+static hipError_t decode_selected(cinr_cache c, int32_t n_cap, int32_t prec, const uint32_t* gate, hipStream_t s) {
     const CacheDev& cd = c->c;
     if (c->vols.size() == 1)
-        return inr_decode_bricks(c->vols[0]->m, c->g, cd.ins_reqs, &cd.ctr->n_sel, n_cap, cd.ins_slots, cd.pool, prec, s);
-    return inr_decode_bricks_multi(c->d_vols, c->vols[0]->m, c->g, cd.ins_reqs, cd.ins_vols, &cd.ctr->n_sel, n_cap,
-                                   cd.ins_slots, cd.pool, prec, s);
+        return inr_decode_bricks(c->vols[0]->m, c->g, cd.ins_reqs, &cd.ctr->n_sel, gate, n_cap, cd.ins_slots, cd.pool,
+                                 prec, s);
+    return inr_decode_bricks_multi(c->d_vols, c->vols[0]->m, c->g, cd.ins_reqs, cd.ins_vols, &cd.ctr->n_sel, gate,
+                                   n_cap, cd.ins_slots, cd.pool, prec, s);
 }
 
 extern "C" void cinr_destroy_cache(cinr_cache c) { delete c; }
@@ -525,8 +527,8 @@ extern "C" cinr_status cinr_cache_prefill(cinr_cache c, const int32_t* d_keys, i
     hipStream_t s = (hipStream_t)stream;
     c->used_bound = std::min<int64_t>(c->used_bound + n, c->c.pool_bricks);
     HIP_TRY(launch_prefill_setup(c->c, d_keys, n, stamp, s));
-    HIP_TRY(launch_insert(c->c, c->g, n, s));
-    HIP_TRY(decode_selected(c, n, prec, s));
+    HIP_TRY(launch_insert(c->c, c->g, n, nullptr, s));
+    HIP_TRY(decode_selected(c, n, prec, nullptr, s));
     return CINR_OK;
 }
 
@@ -547,6 +549,7 @@ struct RenderLayout {
     uint64_t* flags;
     unsigned long long* stats;
     FrameVar* var;
+    uint32_t* gate;  // frame-end gate (view 0's is the frame's)
 };
 
 static size_t render_layout(int64_t npix, int32_t S, int64_t n_cells, RenderLayout* r, void* base) {
@@ -564,6 +567,7 @@ static size_t render_layout(int64_t npix, int32_t S, int64_t n_cells, RenderLayo
     x.flags = cv.take<uint64_t>((size_t)(n_cells + 63) / 64);
     x.stats = cv.take<unsigned long long>(ST_COUNT);
     x.var = cv.take<FrameVar>(1);
+    x.gate = cv.take<uint32_t>(1);
     if (r) *r = x;
     return cv.off;
 }
@@ -921,10 +925,41 @@ cinr_status continue_views(cinr_cache c, std::vector<ViewRun>& runs, bool side, 
     return CINR_OK;
 }
 
-// Runs the wavefront iterations of all views to completion.  Several views of
-// a cached frame run on the cache's side streams so that their marches
-// overlap.
-cinr_status run_views(cinr_cache c, std::vector<ViewRun>& runs, hipStream_t s) {
+// Whether the next cache-manager pass may need LRU victims (host bound on the
+// occupied slots).
+bool lru_pass_needed(cinr_cache c) {
+    return c->c.pool_bricks > 0 && c->used_bound + c->lim > c->c.pool_bricks;
+}
+
+void note_insertions(cinr_cache c) { c->used_bound = std::min<int64_t>(c->used_bound + c->lim, c->c.pool_bricks); }
+
+cinr_status cache_end_frame(cinr_cache c, int32_t prec, bool lru_pass, Timing& tm, const uint32_t* gate, hipStream_t s);
+
+// Frame end of the views: cache manager and decoding (cached frames, c set)
+// and each view's statistics; nothing runs unless *gate != 0 when a gate is
+// given.
+cinr_status end_views(cinr_cache c, std::vector<ViewRun>& runs, bool lru_pass, Timing& tm, const uint32_t* gate,
+                      hipStream_t s) {
+    if (c) {
+        cinr_status st = cache_end_frame(c, runs[0].prec, lru_pass, tm, gate, s);
+        if (st) return st;
+    }
+    const size_t n = runs.size();
+    for (size_t i = 0; i < n; ++i)
+        HIP_TRY(launch_frame_end(runs[i].f, (int)runs[i].max_iters, c ? c->c.ctr : nullptr, i + 1 == n, gate, s));
+    return CINR_OK;
+}
+
+// One frame of the views `runs` (through cache c when it is cached), to
+// completion.  The first marches of all views are followed by one launch that
+// copies their pending-ray counts to the host and sets the frame-end gate
+// (no ray pending); the frame end is queued right behind it, gated, so that
+// the GPU does not wait for the host between the marches and the cache
+// manager.  When a view has rays pending (true misses), the gated end does
+// nothing: the remaining iterations run, then the end is launched again
+// without the gate.  Several views of a cached frame run on the cache's side
+// streams so that their marches overlap.
+cinr_status render_frame_views(cinr_cache c, std::vector<ViewRun>& runs, Timing& tm, hipStream_t s) {
     cinr_volume rv = runs[0].v;
     cinr_status st = ensure_readback(rv);
     if (st) return st;
@@ -939,20 +974,48 @@ cinr_status run_views(cinr_cache c, std::vector<ViewRun>& runs, hipStream_t s) {
     }
     st = start_views(c, runs, side, s);
     if (st) return st;
-    return continue_views(c, runs, side, (uint32_t*)rv->pinned, rv->ev, nullptr, s);
+    if (side) {
+        st = join_side_streams(c, s);
+        if (st) return st;
+    }
+    uint32_t* gate = runs[0].L.gate;
+    std::vector<const FrameDev*> fs;
+    for (const ViewRun& r : runs) fs.push_back(&r.f);
+    uint32_t* pinned = (uint32_t*)rv->pinned;
+    HIP_TRY(launch_pending_gather(fs.data(), (int)runs.size(), pinned, gate, s));
+    HIP_TRY(hipEventRecord(rv->ev, s));
+    const bool lru = c && lru_pass_needed(c);
+    st = end_views(c, runs, lru, tm, gate, s);
+    if (st) return st;
+    HIP_TRY(hipEventSynchronize(rv->ev));
+    std::vector<uint32_t> known(runs.size());
+    bool tail = false;
+    for (size_t i = 0; i < runs.size(); ++i) {
+        known[i] = ((volatile uint32_t*)pinned)[i];
+        tail = tail || known[i] != 0u;
+    }
+    if (tail) {
+        if (side) {
+            HIP_TRY(hipEventRecord(c->fork, s));
+            for (int k = 0; k < cinr_cache_s::kViewStreams; ++k) HIP_TRY(hipStreamWaitEvent(c->vs[k], c->fork, 0));
+        }
+        st = continue_views(c, runs, side, pinned, rv->ev, known.data(), s);
+        if (st) return st;
+        st = end_views(c, runs, lru, tm, nullptr, s);
+        if (st) return st;
+    } else {
+        for (ViewRun& r : runs) {
+            st = tuner_collect(r);
+            if (st) return st;
+        }
+    }
+    if (c) note_insertions(c);
+    return CINR_OK;
 }
-
-// Whether the next cache-manager pass may need LRU victims (host bound on the
-// occupied slots).
-bool lru_pass_needed(cinr_cache c) {
-    return c->c.pool_bricks > 0 && c->used_bound + c->lim > c->c.pool_bricks;
-}
-
-void note_insertions(cinr_cache c) { c->used_bound = std::min<int64_t>(c->used_bound + c->lim, c->c.pool_bricks); }
 
 // End of a cached frame: ranking and selection of the requests of all views,
 // insertion (free slots, then LRU victims) and decoding of the new bricks.
-cinr_status cache_end_frame(cinr_cache c, int32_t prec, bool lru_pass, Timing& tm, hipStream_t s) {
+cinr_status cache_end_frame(cinr_cache c, int32_t prec, bool lru_pass, Timing& tm, const uint32_t* gate, hipStream_t s) {
     const CacheDev& cd = c->c;
     {
         StageTimer st_(tm, s, CINR_STAGE_CM);
@@ -964,6 +1027,7 @@ cinr_status cache_end_frame(cinr_cache c, int32_t prec, bool lru_pass, Timing& t
         ta.cap0 = (uint64_t)c->g.n_keys;
         ta.k = c->lim;
         ta.mode = TOPK_RANK;
+        ta.frame_gate = gate;
         ta.ra = RankArgs{cd.touched, cd.req, cd.last_req, cd.rank, &cd.ctr->frame, cd.rank_window, cd.ranking};
         SelectArgs sel{cd.ins_keys, cd.ctr, cd.pool_bricks, c->lim};
         HIP_TRY(launch_topk(ta, c->plan_sel, cd.topk[0], cd.topk[1], cd.sel, &sel, s));
@@ -976,14 +1040,15 @@ cinr_status cache_end_frame(cinr_cache c, int32_t prec, bool lru_pass, Timing& t
             tv.k = c->lim;
             tv.gate = &cd.ctr->need_evict;
             tv.mode = TOPK_LRU;
+            tv.frame_gate = gate;
             tv.lru_last_used = cd.last_used;
             HIP_TRY(launch_topk(tv, c->plan_vic, cd.topk[0], cd.topk[1], cd.vic, nullptr, s));
         }
-        HIP_TRY(launch_insert(cd, c->g, c->lim, s));
+        HIP_TRY(launch_insert(cd, c->g, c->lim, gate, s));
     }
     {
         StageTimer st_(tm, s, CINR_STAGE_DECODE);
-        HIP_TRY(decode_selected(c, c->lim, prec, s));
+        HIP_TRY(decode_selected(c, c->lim, prec, gate, s));
     }
     return CINR_OK;
 }
@@ -996,17 +1061,7 @@ extern "C" cinr_status cinr_render_frame(cinr_cache c, cinr_volume v, const cinr
     std::vector<ViewRun> runs(1);
     cinr_status st = prepare_view(c, v, cam, d_tf, rp, d_rgba, d_stats, d_ws, ws_bytes, runs[0]);
     if (st) return st;
-    hipStream_t s = (hipStream_t)stream;
-    st = run_views(c, runs, s);
-    if (st) return st;
-    const bool cached = rp->mode == CINR_CACHED;
-    if (cached) {
-        st = cache_end_frame(c, rp->mlp_dtype, lru_pass_needed(c), v->timing, s);
-        if (st) return st;
-        note_insertions(c);
-    }
-    HIP_TRY(launch_frame_end(runs[0].f, (int)runs[0].max_iters, cached ? c->c.ctr : nullptr, true, s));
-    return CINR_OK;
+    return render_frame_views(rp->mode == CINR_CACHED ? c : nullptr, runs, v->timing, (hipStream_t)stream);
 }
 
 namespace {
@@ -1030,29 +1085,13 @@ cinr_status prepare_views(cinr_cache c, int32_t n_views, const cinr_view* views,
     return CINR_OK;
 }
 
-// Cache manager, decoding and frame ends of a multi-view frame.
-cinr_status end_views(cinr_cache c, std::vector<ViewRun>& runs, bool lru_pass, Timing& tm, hipStream_t s) {
-    cinr_status st = cache_end_frame(c, runs[0].prec, lru_pass, tm, s);
-    if (st) return st;
-    const size_t n = runs.size();
-    for (size_t i = 0; i < n; ++i)
-        HIP_TRY(launch_frame_end(runs[i].f, (int)runs[i].max_iters, c->c.ctr, i + 1 == n, s));
-    return CINR_OK;
-}
-
 }  // namespace
 
 extern "C" cinr_status cinr_render_views(cinr_cache c, int32_t n_views, const cinr_view* views, void* stream) {
     std::vector<ViewRun> runs;
     cinr_status st = prepare_views(c, n_views, views, runs);
     if (st) return st;
-    hipStream_t s = (hipStream_t)stream;
-    st = run_views(c, runs, s);
-    if (st) return st;
-    st = end_views(c, runs, lru_pass_needed(c), views[0].volume->timing, s);
-    if (st) return st;
-    note_insertions(c);
-    return CINR_OK;
+    return render_frame_views(c, runs, views[0].volume->timing, (hipStream_t)stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -1166,12 +1205,7 @@ extern "C" cinr_status cinr_frame_graph_render(cinr_frame_graph g, const cinr_ca
     for (const ViewRun& r : runs) tuned = tuned && !r.timing_trial;
     if (!tuned) {
         g->n_eager += 1;
-        st = run_views(c, runs, s);
-        if (st) return st;
-        st = end_views(c, runs, lru_pass_needed(c), runs[0].v->timing, s);
-        if (st) return st;
-        note_insertions(c);
-        return CINR_OK;
+        return render_frame_views(c, runs, runs[0].v->timing, s);
     }
     const bool side = n > 1;
     for (int32_t i = 0; i < n; ++i) {
@@ -1189,7 +1223,7 @@ extern "C" cinr_status cinr_frame_graph_render(cinr_frame_graph g, const cinr_ca
             }
             std::vector<const FrameDev*> fs;
             for (const ViewRun& v : runs) fs.push_back(&v.f);
-            HIP_TRY(launch_pending_gather(fs.data(), n, g->pending, cs));
+            HIP_TRY(launch_pending_gather(fs.data(), n, g->pending, runs[0].L.gate, cs));
             return CINR_OK;
         });
         if (st) return st;
@@ -1198,12 +1232,14 @@ extern "C" cinr_status cinr_frame_graph_render(cinr_frame_graph g, const cinr_ca
     if (!g->end[lru]) {
         TimingOff off(runs);
         Timing none;
-        st = capture(g, &g->end[lru], [&](hipStream_t cs) { return end_views(c, runs, lru, none, cs); });
+        st = capture(g, &g->end[lru], [&](hipStream_t cs) { return end_views(c, runs, lru, none, runs[0].L.gate, cs); });
         if (st) return st;
     }
     for (int32_t i = 0; i < n; ++i) g->stage[i] = runs[i].hv;
+    // the end graph is gated: it does nothing if a view still has rays pending
     HIP_TRY(hipGraphLaunch(g->start, s));
     HIP_TRY(hipEventRecord(g->ev, s));
+    HIP_TRY(hipGraphLaunch(g->end[lru], s));
     HIP_TRY(hipEventSynchronize(g->ev));
     std::vector<uint32_t> known(n);
     bool tail = false;
@@ -1215,13 +1251,15 @@ extern "C" cinr_status cinr_frame_graph_render(cinr_frame_graph g, const cinr_ca
     }
     if (tail) {
         // rays left after the first marches (true misses): the remaining
-        // iterations run eagerly on `s`
+        // iterations and the frame end run eagerly on `s`
         g->n_tail += 1;
         cinr_volume rv = runs[0].v;
         st = continue_views(c, runs, false, (uint32_t*)rv->pinned, rv->ev, known.data(), s);
         if (st) return st;
+        Timing none;
+        st = end_views(c, runs, lru, none, nullptr, s);
+        if (st) return st;
     }
-    HIP_TRY(hipGraphLaunch(g->end[lru], s));
     note_insertions(c);
     g->n_graph += 1;
     return CINR_OK;

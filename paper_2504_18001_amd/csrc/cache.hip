@@ -69,6 +69,7 @@ __global__ __launch_bounds__(256) void k_topk(TopkArgs a) {
     __shared__ uint64_t s[kTopkChunk];
     __shared__ uint32_t nsel;
     if (a.gate && *a.gate == 0u) return;
+    if (a.frame_gate && *a.frame_gate == 0u) return;
     uint64_t c = a.cap0;
     if (a.count_dev && (uint64_t)*a.count_dev < c) c = *a.count_dev;
     for (int q = 0; q < a.pass; ++q) c = ((c + kTopkChunk - 1) / kTopkChunk) * (uint64_t)a.k;
@@ -147,7 +148,8 @@ __global__ void k_prefill_setup(CacheDev c, const int32_t* keys, int32_t n, int3
     }
 }
 
-__global__ void k_insert(CacheDev c, CacheGeom g, int32_t finish_inline) {
+__global__ void k_insert(CacheDev c, CacheGeom g, int32_t finish_inline, const uint32_t* gate) {
+    if (gate && *gate == 0u) return;
     const CacheCtr ctr = *c.ctr;
     const int32_t stamp = ctr.frame + 1;
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ctr.n_sel; t += gridDim.x * blockDim.x) {
@@ -202,7 +204,8 @@ __global__ void k_insert(CacheDev c, CacheGeom g, int32_t finish_inline) {
     }
 }
 
-__global__ void k_insert_finish(CacheDev c) {
+__global__ void k_insert_finish(CacheDev c, const uint32_t* gate) {
+    if (gate && *gate == 0u) return;
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         CacheCtr* ctr = c.ctr;
         const uint32_t filled = ctr->n_sel < ctr->n_free ? ctr->n_sel : ctr->n_free;
@@ -251,15 +254,15 @@ hipError_t launch_prefill_setup(const CacheDev& c, const int32_t* keys, int32_t 
     return hipGetLastError();
 }
 
-hipError_t launch_insert(const CacheDev& c, const CacheGeom& g, int32_t cap, hipStream_t s) {
+hipError_t launch_insert(const CacheDev& c, const CacheGeom& g, int32_t cap, const uint32_t* gate, hipStream_t s) {
     if (cap <= 256) {
-        hipLaunchKernelGGL(k_insert, dim3(1), dim3(256), 0, s, c, g, 1);
+        hipLaunchKernelGGL(k_insert, dim3(1), dim3(256), 0, s, c, g, 1, gate);
         return hipGetLastError();
     }
     int b = (cap + 255) / 256;
     b = b > 1024 ? 1024 : b;
-    hipLaunchKernelGGL(k_insert, dim3(b), dim3(256), 0, s, c, g, 0);
-    hipLaunchKernelGGL(k_insert_finish, dim3(1), dim3(64), 0, s, c);
+    hipLaunchKernelGGL(k_insert, dim3(b), dim3(256), 0, s, c, g, 0, gate);
+    hipLaunchKernelGGL(k_insert_finish, dim3(1), dim3(64), 0, s, c, gate);
     return hipGetLastError();
 }
 

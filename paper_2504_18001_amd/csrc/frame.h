@@ -174,6 +174,7 @@ struct TopkArgs {
     uint64_t* out;
     int32_t k;
     const uint32_t* gate;       // nullable: skip when *gate == 0
+    const uint32_t* frame_gate; // nullable: skip when *frame_gate == 0 (frame end queued ahead)
     int32_t mode;               // TopkMode of pass 0
     const int32_t* lru_last_used;
     RankArgs ra;
@@ -189,29 +190,37 @@ hipError_t launch_frame_begin(const FrameDev& f, int32_t n_iter_ctr, const float
                               CacheCtr* cctr, hipStream_t s);
 hipError_t launch_march(const FrameDev& f, int it, int64_t max_rays, hipStream_t s);
 hipError_t launch_shade(const FrameDev& f, int it, int64_t cap_rays, hipStream_t s);
-hipError_t launch_frame_end(const FrameDev& f, int max_iters, CacheCtr* cctr, bool reset, hipStream_t s);
-hipError_t launch_pending_gather(const FrameDev* const* fs, int n, uint32_t* host_out, hipStream_t s);
+// `gate` (nullable) on the frame-end launches: they do nothing unless *gate is
+// non-zero, which k_pending_gather sets when no view has a ray pending after
+// its first march.  The end of a frame can so be queued before the host has
+// read the pending counts.
+hipError_t launch_frame_end(const FrameDev& f, int max_iters, CacheCtr* cctr, bool reset, const uint32_t* gate,
+                            hipStream_t s);
+hipError_t launch_pending_gather(const FrameDev* const* fs, int n, uint32_t* host_out, uint32_t* gate, hipStream_t s);
 
 // cache launchers
 hipError_t launch_cache_init(const CacheDev& c, int64_t n_keys, hipStream_t s);
 hipError_t launch_topk(const TopkArgs& base, const TopkPlan& plan, uint64_t* buf0, uint64_t* buf1, uint64_t* final_out,
                        const SelectArgs* epilogue, hipStream_t s);
 hipError_t launch_prefill_setup(const CacheDev& c, const int32_t* keys, int32_t n, int32_t stamp, hipStream_t s);
-hipError_t launch_insert(const CacheDev& c, const CacheGeom& g, int32_t cap, hipStream_t s);
+hipError_t launch_insert(const CacheDev& c, const CacheGeom& g, int32_t cap, const uint32_t* gate, hipStream_t s);
 hipError_t launch_clear_last_req(const CacheDev& c, int64_t n_keys, hipStream_t s);
 
 // inr.hip launchers
 bool inr_shape_supported(const InrDev& m);
 hipError_t inr_infer_points(const InrDev& m, const float* pos, int64_t n, float* out, int prec, hipStream_t s);
+// gate: nullable, as for the frame-end launches (no brick is decoded unless *gate != 0)
 hipError_t inr_decode_bricks(const InrDev& m, const CacheGeom& g, const int32_t* reqs, const uint32_t* n_dev,
-                             int32_t n_cap, const int32_t* slots, float* out, int prec, hipStream_t s);
+                             const uint32_t* gate, int32_t n_cap, const int32_t* slots, float* out, int prec,
+                             hipStream_t s);
 hipError_t inr_macrocells(const InrDev& m, int32_t N, float* minmax, int prec, hipStream_t s);
 hipError_t inr_infer_misses(const InrDev& m, const float4* rec, const uint32_t* n_dev, int64_t cap, float* vals,
                             int prec, hipStream_t s);
 // bricks of several volumes of one shape (d_vols: device array of their
 // descriptors, `shape` any of them on the host)
 hipError_t inr_decode_bricks_multi(const InrDev* d_vols, const InrDev& shape, const CacheGeom& g, const int32_t* reqs,
-                                   const int32_t* vols, const uint32_t* n_dev, int32_t n_cap, const int32_t* slots,
+                                   const int32_t* vols, const uint32_t* n_dev, const uint32_t* gate, int32_t n_cap,
+                                   const int32_t* slots,
                                    float* out, int prec, hipStream_t s);
 
 // train.hip launchers

@@ -45,16 +45,18 @@ struct LinearDst {
 struct BrickSrc {
     const int32_t* reqs;      // [n][4]
     const uint32_t* n_dev;    // device count of requests (nullable)
+    const uint32_t* gate;     // nullable: no request unless *gate != 0
     int32_t n_host;
     int32_t B;
     int32_t B3;
     int32_t n_lods;
     int32_t nb[kMaxLods][3];
     int32_t dims[3];
-    __device__ int64_t count() const {
-        const int64_t n = n_dev ? (int64_t)*n_dev : (int64_t)n_host;
-        return n * B3;
+    __device__ int64_t n_requests() const {
+        if (gate && *gate == 0u) return 0;
+        return n_dev ? (int64_t)*n_dev : (int64_t)n_host;
     }
+    __device__ int64_t count() const { return n_requests() * B3; }
     // returns false for an invalid request
     __device__ bool position(int64_t idx, double x[3]) const {
         const int32_t r = (int32_t)(idx / B3);
@@ -138,7 +140,7 @@ __global__ __launch_bounds__(kBlock) void k_decode_multi(const InrDev* vols, con
     Eng eng;
     int32_t cur = -1;
     __shared__ typename Eng::Lds lds;
-    const int64_t n_bricks = src.n_dev ? (int64_t)*src.n_dev : (int64_t)src.n_host;
+    const int64_t n_bricks = src.n_requests();
     const int32_t chunks = (src.B3 + kBlock - 1) / kBlock;
     const int64_t items = n_bricks * chunks;
     for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
@@ -336,11 +338,13 @@ hipError_t inr_infer_points(const InrDev& m, const float* pos, int64_t n, float*
 }
 
 hipError_t inr_decode_bricks(const InrDev& m, const CacheGeom& g, const int32_t* reqs, const uint32_t* n_dev,
-                             int32_t n_cap, const int32_t* slots, float* out, int prec, hipStream_t s) {
+                             const uint32_t* gate, int32_t n_cap, const int32_t* slots, float* out, int prec,
+                             hipStream_t s) {
     if (n_cap <= 0) return hipSuccess;
     BrickSrc src;
     src.reqs = reqs;
     src.n_dev = n_dev;
+    src.gate = gate;
     src.n_host = n_cap;
     src.B = g.brick;
     src.B3 = g.brick * g.brick * g.brick;
@@ -354,12 +358,13 @@ hipError_t inr_decode_bricks(const InrDev& m, const CacheGeom& g, const int32_t*
 }
 
 hipError_t inr_decode_bricks_multi(const InrDev* d_vols, const InrDev& shape, const CacheGeom& g, const int32_t* reqs,
-                                   const int32_t* vols, const uint32_t* n_dev, int32_t n_cap, const int32_t* slots,
-                                   float* out, int prec, hipStream_t s) {
+                                   const int32_t* vols, const uint32_t* n_dev, const uint32_t* gate, int32_t n_cap,
+                                   const int32_t* slots, float* out, int prec, hipStream_t s) {
     if (n_cap <= 0) return hipSuccess;
     BrickSrc src;
     src.reqs = reqs;
     src.n_dev = n_dev;
+    src.gate = gate;
     src.n_host = n_cap;
     src.B = g.brick;
     src.B3 = g.brick * g.brick * g.brick;

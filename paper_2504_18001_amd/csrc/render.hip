@@ -297,8 +297,10 @@ struct RayBook {
 
 __global__ __launch_bounds__(kBlock) void k_frame_begin(FrameDev f, int32_t n_ctr, const float* minmax,
                                                         int64_t n_cells, CacheCtr* cctr) {
-    __shared__ float alpha[256];
-    alpha[threadIdx.x] = f.tf[4 * threadIdx.x + 3];
+    // bit r of nz: TF row r has a non-zero opacity (4 waves x 64 rows)
+    __shared__ uint64_t nz[4];
+    const uint64_t m = __ballot(f.tf[4 * threadIdx.x + 3] > 0.0f);
+    if (lane_id() == 0) nz[threadIdx.x >> 6] = m;
     __syncthreads();
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     // the frame's camera, index and LoD seed: host block -> device
@@ -309,8 +311,10 @@ __global__ __launch_bounds__(kBlock) void k_frame_begin(FrameDev f, int32_t n_ct
     if (t < ST_COUNT) f.stats[t] = 0ull;
     if (t == 0 && cctr) cctr->n_misslog = 0u;
     // macro-cell flags (Section 5.2): maximum opacity over the TF rows a
-    // cell's value range can reach; zero means the cell is skipped.  One bit
-    // per cell, 64 cells (one wave) per word.
+    // cell's value range can reach; zero means the cell is skipped.  That
+    // maximum is positive exactly when one of the rows lo..hi has a positive
+    // opacity, which the row bits answer a word at a time.  One bit per cell,
+    // 64 cells (one wave) per word.
     if (f.flags && (t >> 6) < f.flag_words) {
         bool vis = false;
         if (t < n_cells) {
@@ -319,9 +323,12 @@ __global__ __launch_bounds__(kBlock) void k_frame_begin(FrameDev f, int32_t n_ct
             int32_t lo = (int32_t)__builtin_floorf(a), hi = (int32_t)__builtin_ceilf(b);
             lo = lo < 0 ? 0 : lo;
             hi = hi > 255 ? 255 : hi;
-            float mu = 0.0f;
-            for (int32_t r = lo; r <= hi; ++r) mu = alpha[r] > mu ? alpha[r] : mu;
-            vis = mu > 0.0f;
+            for (int32_t w = lo >> 6; w <= (hi >> 6) && lo <= hi; ++w) {
+                const int32_t a0 = lo > 64 * w ? lo - 64 * w : 0;
+                const int32_t a1 = hi < 64 * w + 63 ? hi - 64 * w : 63;
+                const uint64_t range = (~0ull << a0) & (~0ull >> (63 - a1));
+                vis = vis || (nz[w] & range) != 0ull;
+            }
         }
         const uint64_t word = __ballot(vis);
         if (lane_id() == 0) f.flags[t >> 6] = word;
@@ -594,7 +601,8 @@ __global__ __launch_bounds__(kBlock) void k_shade(FrameDev f, int32_t it) {
 // whole frame (all views).  `reset` (the last view) clears the request list.
 // The view ran march launches 0 .. n-1, where n - 1 is the first iteration
 // that left no ray pending, or max_iters - 1.
-__global__ void k_frame_end(FrameDev f, int32_t max_iters, CacheCtr* cctr, int32_t reset) {
+__global__ void k_frame_end(FrameDev f, int32_t max_iters, CacheCtr* cctr, int32_t reset, const uint32_t* gate) {
+    if (gate && *gate == 0u) return;
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         int32_t n = 1;
         while (n < max_iters && f.ctr[n - 1].pending != 0u) ++n;
@@ -696,28 +704,33 @@ hipError_t launch_shade(const FrameDev& f, int it, int64_t cap_rays, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_frame_end(const FrameDev& f, int max_iters, CacheCtr* cctr, bool reset, hipStream_t s) {
-    hipLaunchKernelGGL(k_frame_end, dim3(1), dim3(64), 0, s, f, max_iters, cctr, reset ? 1 : 0);
+hipError_t launch_frame_end(const FrameDev& f, int max_iters, CacheCtr* cctr, bool reset, const uint32_t* gate,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_frame_end, dim3(1), dim3(64), 0, s, f, max_iters, cctr, reset ? 1 : 0, gate);
     return hipGetLastError();
 }
 
 // Pending-ray counts of the first march of up to 64 views, written straight
-// into (pinned) host memory: one launch instead of one copy per view.
+// into (pinned) host memory: one launch instead of one copy per view.  The
+// gate of the frame end is set when none is pending.
 struct PendingSrc {
     const uint32_t* p[64];
 };
 
-__global__ void k_pending_gather(PendingSrc src, int32_t n, uint32_t* host_out) {
+__global__ void k_pending_gather(PendingSrc src, int32_t n, uint32_t* host_out, uint32_t* gate) {
     const int32_t t = threadIdx.x;
-    if (t < n) host_out[t] = *src.p[t];
+    const uint32_t v = t < n ? *src.p[t] : 0u;
+    if (t < n) host_out[t] = v;
+    const uint64_t any = __ballot(v != 0u);
+    if (t == 0) *gate = any == 0ull ? 1u : 0u;
     __threadfence_system();
 }
 
-hipError_t launch_pending_gather(const FrameDev* const* fs, int n, uint32_t* host_out, hipStream_t s) {
+hipError_t launch_pending_gather(const FrameDev* const* fs, int n, uint32_t* host_out, uint32_t* gate, hipStream_t s) {
     if (n < 1 || n > 64) return hipErrorInvalidValue;
     PendingSrc src{};
     for (int i = 0; i < n; ++i) src.p[i] = &fs[i]->ctr[0].pending;
-    hipLaunchKernelGGL(k_pending_gather, dim3(1), dim3(64), 0, s, src, n, host_out);
+    hipLaunchKernelGGL(k_pending_gather, dim3(1), dim3(64), 0, s, src, n, host_out, gate);
     return hipGetLastError();
 }
 
