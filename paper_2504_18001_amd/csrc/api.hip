@@ -434,6 +434,7 @@ static size_t cache_layout(const cinr_cache_desc* d, const CacheGeom& g, CacheDe
     x.evlog = cv.take<int32_t>((size_t)d->evict_log_capacity * 4);
     x.evlog_cap = d->evict_log_capacity;
     x.ctr = cv.take<CacheCtr>(1);
+    x.views = cv.take<ViewEnd>(kMaxFrameViews);
     if (vols_out) *vols_out = cv.take<InrDev>(g.n_vols);
     x.pool_bricks = P;
     x.max_requests = d->max_requests;
@@ -691,6 +692,9 @@ cinr_status prepare_view(cinr_cache c, cinr_volume v, const cinr_camera* cam, co
     const RenderLayout& L = r.L;
     FrameDev& f = r.f;
     f = FrameDev{};
+    f.max_iters = (int32_t)max_iters;
+    f.view_index = 0;
+    f.n_views = 1;
     f.W = cam->width;
     f.H = cam->height;
     f.var = L.var;
@@ -735,6 +739,7 @@ cinr_status prepare_view(cinr_cache c, cinr_volume v, const cinr_camera* cam, co
     f.ctr = L.ctr;
     f.stats = d_stats ? reinterpret_cast<unsigned long long*>(d_stats) : L.stats;
     if (cached) {
+        f.view_table = c->c.views;
         f.geo = c->g;
         f.key_base = (int32_t)(vi * c->g.keys_per_vol);
         f.pt = c->c.pt + f.key_base;
@@ -935,18 +940,15 @@ void note_insertions(cinr_cache c) { c->used_bound = std::min<int64_t>(c->used_b
 
 cinr_status cache_end_frame(cinr_cache c, int32_t prec, bool lru_pass, Timing& tm, const uint32_t* gate, hipStream_t s);
 
-// Frame end of the views: cache manager and decoding (cached frames, c set)
-// and each view's statistics; nothing runs unless *gate != 0 when a gate is
-// given.
+// Frame end of the views: cache manager and decoding (cached frames, c set;
+// the selection launch also writes every view's statistics) or each view's
+// statistics (uncached); nothing runs unless *gate != 0 when a gate is given.
 cinr_status end_views(cinr_cache c, std::vector<ViewRun>& runs, bool lru_pass, Timing& tm, const uint32_t* gate,
                       hipStream_t s) {
-    if (c) {
-        cinr_status st = cache_end_frame(c, runs[0].prec, lru_pass, tm, gate, s);
-        if (st) return st;
-    }
+    if (c) return cache_end_frame(c, runs[0].prec, lru_pass, tm, gate, s);
     const size_t n = runs.size();
     for (size_t i = 0; i < n; ++i)
-        HIP_TRY(launch_frame_end(runs[i].f, (int)runs[i].max_iters, c ? c->c.ctr : nullptr, i + 1 == n, gate, s));
+        HIP_TRY(launch_frame_end(runs[i].f, (int)runs[i].max_iters, nullptr, i + 1 == n, gate, s));
     return CINR_OK;
 }
 
@@ -1014,7 +1016,10 @@ cinr_status render_frame_views(cinr_cache c, std::vector<ViewRun>& runs, Timing&
 }
 
 // End of a cached frame: ranking and selection of the requests of all views,
-// insertion (free slots, then LRU victims) and decoding of the new bricks.
+// insertion (free slots, then LRU victims), the views' statistics and
+// decoding of the new bricks.  Without an LRU pass, ranking, selection,
+// insertion and statistics are one launch (when the selection takes two
+// passes, its last workgroup runs the second).
 cinr_status cache_end_frame(cinr_cache c, int32_t prec, bool lru_pass, Timing& tm, const uint32_t* gate, hipStream_t s) {
     const CacheDev& cd = c->c;
     {
@@ -1030,7 +1035,12 @@ cinr_status cache_end_frame(cinr_cache c, int32_t prec, bool lru_pass, Timing& t
         ta.frame_gate = gate;
         ta.ra = RankArgs{cd.touched, cd.req, cd.last_req, cd.rank, &cd.ctr->frame, cd.rank_window, cd.ranking};
         SelectArgs sel{cd.ins_keys, cd.ctr, cd.pool_bricks, c->lim};
-        HIP_TRY(launch_topk(ta, c->plan_sel, cd.topk[0], cd.topk[1], cd.sel, &sel, s));
+        ta.tail.insert = lru_pass ? 0 : 1;
+        ta.tail.stats = 1;
+        ta.tail.c = cd;
+        ta.tail.g = c->g;
+        uint32_t* fuse = c->plan_sel.n_pass == 2 ? &cd.ctr->select_done : nullptr;
+        HIP_TRY(launch_topk(ta, c->plan_sel, cd.topk[0], cd.topk[1], cd.sel, &sel, fuse, s));
         // LRU victims, only when the pool may be full (the pass is also gated
         // on the device by the number of slots to evict)
         if (lru_pass) {
@@ -1042,9 +1052,9 @@ cinr_status cache_end_frame(cinr_cache c, int32_t prec, bool lru_pass, Timing& t
             tv.mode = TOPK_LRU;
             tv.frame_gate = gate;
             tv.lru_last_used = cd.last_used;
-            HIP_TRY(launch_topk(tv, c->plan_vic, cd.topk[0], cd.topk[1], cd.vic, nullptr, s));
+            HIP_TRY(launch_topk(tv, c->plan_vic, cd.topk[0], cd.topk[1], cd.vic, nullptr, nullptr, s));
+            HIP_TRY(launch_insert(cd, c->g, c->lim, gate, s));
         }
-        HIP_TRY(launch_insert(cd, c->g, c->lim, gate, s));
     }
     {
         StageTimer st_(tm, s, CINR_STAGE_DECODE);
@@ -1081,6 +1091,8 @@ cinr_status prepare_views(cinr_cache c, int32_t n_views, const cinr_view* views,
         cinr_status st = prepare_view(c, w.volume, &w.camera, w.d_tf, &w.params, w.d_rgba, w.d_stats, w.d_workspace,
                                       w.workspace_bytes, runs[i]);
         if (st) return fail(st, "view %d: %s", i, cinr_last_error());
+        runs[i].f.view_index = i;
+        runs[i].f.n_views = n_views;
     }
     return CINR_OK;
 }

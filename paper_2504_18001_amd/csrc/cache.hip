@@ -56,43 +56,9 @@ __device__ inline uint64_t rank_score(const RankArgs& ra, int32_t frame, uint64_
     return ra.ranking ? (((uint64_t)r << 32) | low) : low;
 }
 
-// One tournament pass: workgroup b sorts its elements [b*2048, (b+1)*2048)
-// of the pass input in descending order and writes the best k to
-// out[b*k ...].  The number of live input elements of pass p follows from
-// the device count of pass 0 (each pass keeps k per 2048), so empty
-// workgroups return at once and partial ones sort only a power of two
-// covering their elements.  Sources of pass 0: a score array, the LRU order
-// of the slots [0, count) scored ~(last_used << 32 | slot), or the touched
-// bricks ranked on the fly.  The final pass may also publish the request
-// list (select epilogue).
-__global__ __launch_bounds__(256) void k_topk(TopkArgs a) {
-    __shared__ uint64_t s[kTopkChunk];
-    __shared__ uint32_t nsel;
-    if (a.gate && *a.gate == 0u) return;
-    if (a.frame_gate && *a.frame_gate == 0u) return;
-    uint64_t c = a.cap0;
-    if (a.count_dev && (uint64_t)*a.count_dev < c) c = *a.count_dev;
-    for (int q = 0; q < a.pass; ++q) c = ((c + kTopkChunk - 1) / kTopkChunk) * (uint64_t)a.k;
-    const uint64_t base = (uint64_t)blockIdx.x * kTopkChunk;
-    if (base >= c && blockIdx.x > 0) return;
-    const uint32_t have = base >= c ? 0u : (uint32_t)(c - base < kTopkChunk ? c - base : kTopkChunk);
-    uint32_t m = 1;
-    while (m < have) m <<= 1;
-    const int32_t frame = (a.pass == 0 && a.mode == TOPK_RANK) ? *a.ra.frame : 0;
-    for (uint32_t e = threadIdx.x; e < m; e += 256) {
-        const uint64_t idx = base + e;
-        uint64_t v = 0ull;
-        if (e < have) {
-            if (a.pass == 0 && a.mode == TOPK_LRU)
-                v = ~(((uint64_t)(uint32_t)a.lru_last_used[idx] << 32) | idx);
-            else if (a.pass == 0 && a.mode == TOPK_RANK)
-                v = rank_score(a.ra, frame, idx);
-            else
-                v = a.in[idx];
-        }
-        s[e] = v;
-    }
-    __syncthreads();
+// Bitonic sort of s[0, m) in descending order (m a power of two, <= 2048),
+// by the 256 threads of the workgroup.
+__device__ void sort_desc(uint64_t* s, uint32_t m) {
     for (uint32_t len = 2; len <= m; len <<= 1) {
         for (uint32_t j = len >> 1; j > 0; j >>= 1) {
             for (uint32_t e = threadIdx.x; e < m; e += 256) {
@@ -109,50 +75,22 @@ __global__ __launch_bounds__(256) void k_topk(TopkArgs a) {
             __syncthreads();
         }
     }
-    for (int32_t e = threadIdx.x; e < a.k; e += 256)
-        a.out[(uint64_t)blockIdx.x * a.k + e] = (uint32_t)e < m ? s[e] : 0ull;
-    if (a.sel.ctr) {
-        // request list: keys of the non-zero scores, best first
-        if (threadIdx.x == 0) nsel = 0u;
-        __syncthreads();
-        for (int32_t t = threadIdx.x; t < a.sel.lim; t += 256) {
-            const uint64_t v = (uint32_t)t < m ? s[t] : 0ull;
-            if (v != 0ull) {
-                a.sel.ins_keys[t] = (int32_t)(0xFFFFFFFFull - (v & 0xFFFFFFFFull));
-                atomicAdd(&nsel, 1u);
-            }
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            CacheCtr* ctr = a.sel.ctr;
-            const uint32_t n_free = (uint32_t)a.sel.pool_bricks - ctr->n_used;
-            ctr->n_sel = nsel;
-            ctr->n_free = n_free;
-            ctr->need_evict = nsel > n_free ? nsel - n_free : 0u;
-        }
-    }
 }
 
-// Prefill: the given keys are inserted into free slots only.
-__global__ void k_prefill_setup(CacheDev c, const int32_t* keys, int32_t n, int32_t stamp) {
-    for (int32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) c.ins_keys[t] = keys[t];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        CacheCtr* ctr = c.ctr;
-        const uint32_t n_free = (uint32_t)c.pool_bricks - ctr->n_used;
-        const uint32_t nn = (uint32_t)n <= n_free ? (uint32_t)n : n_free;
-        if ((uint32_t)n > n_free) ctr->error |= 1u;
-        ctr->frame = stamp - 1;  // k_insert stamps frame + 1
-        ctr->n_sel = nn;
-        ctr->n_free = n_free;
-        ctr->need_evict = 0u;
-    }
+__device__ inline uint32_t pow2_at_least(uint32_t n) {
+    uint32_t m = 1;
+    while (m < n) m <<= 1;
+    return m;
 }
 
-__global__ void k_insert(CacheDev c, CacheGeom g, int32_t finish_inline, const uint32_t* gate) {
-    if (gate && *gate == 0u) return;
-    const CacheCtr ctr = *c.ctr;
+// Insertion of the selected bricks [t0, n_sel) step `stride` (Section 4.3.1):
+// the lowest free slots first, then the LRU victims; evicted bricks are
+// unmapped and their ranks forgotten, new bricks are mapped, stamped and
+// queued for decoding.  `ctr` is the counters' state after the selection.
+__device__ void insert_entries(const CacheDev& c, const CacheGeom& g, const CacheCtr& ctr, uint32_t t0,
+                               uint32_t stride) {
     const int32_t stamp = ctr.frame + 1;
-    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ctr.n_sel; t += gridDim.x * blockDim.x) {
+    for (uint32_t t = t0; t < ctr.n_sel; t += stride) {
         const int32_t key = c.ins_keys[t];
         int32_t slot;
         if (t < ctr.n_free)
@@ -194,23 +132,162 @@ __global__ void k_insert(CacheDev c, CacheGeom g, int32_t finish_inline, const u
             r[3] = key;
         }
     }
+}
+
+// Occupancy and eviction-log counters after an insertion (one thread).
+__device__ inline void insert_counters(CacheCtr* out, const CacheCtr& ctr) {
+    const uint32_t filled = ctr.n_sel < ctr.n_free ? ctr.n_sel : ctr.n_free;
+    out->n_used = ctr.n_used + filled;
+    out->n_evlog = ctr.n_evlog + ctr.n_sel;
+}
+
+// Frame statistics of the views of the frame (one thread): iterations from
+// each view's per-iteration counters (launches 0 .. n-1, where n - 1 is the
+// first iteration that left no ray pending, or max_iters - 1), the cache
+// manager's counters of the whole frame.  Clears the request list.
+__device__ void views_frame_stats(const CacheDev& c, uint32_t n_touched, uint32_t n_sel, uint32_t need_evict) {
+    const uint32_t nv = c.ctr->n_views < (uint32_t)kMaxFrameViews ? c.ctr->n_views : (uint32_t)kMaxFrameViews;
+    for (uint32_t v = 0; v < nv; ++v) {
+        const ViewEnd e = c.views[v];
+        int32_t n = 1;
+        while (n < e.max_iters && e.ctr[n - 1].pending != 0u) ++n;
+        e.stats[ST_ITERS] = (unsigned long long)n;
+        e.stats[ST_REQUESTED] = n_touched;
+        e.stats[ST_SELECTED] = n_sel;
+        e.stats[ST_EVICTED] = need_evict;
+    }
+    c.ctr->n_touched = 0u;  // the next frame's requests start empty
+}
+
+// One tournament pass: workgroup b sorts its elements [b*2048, (b+1)*2048)
+// of the pass input in descending order and writes the best k to
+// out[b*k ...].  The number of live input elements of pass p follows from
+// the device count of pass 0 (each pass keeps k per 2048), so empty
+// workgroups skip the sort and partial ones sort only a power of two
+// covering their elements.  Sources of pass 0: a score array, the LRU order
+// of the slots [0, count) scored ~(last_used << 32 | slot), or the touched
+// bricks ranked on the fly.  The final pass may also publish the request
+// list (select epilogue), then insert the selected bricks and write the
+// views' frame statistics (tail).  A fused launch is pass 0 followed, in
+// the last of its workgroups to finish, by pass 1 (two-pass selections).
+__global__ __launch_bounds__(256) void k_topk(TopkArgs a) {
+    __shared__ uint64_t s[kTopkChunk];
+    __shared__ uint32_t nsel, ticket;
+    if (a.gate && *a.gate == 0u) return;
+    if (a.frame_gate && *a.frame_gate == 0u) return;
+    uint64_t c = a.cap0;
+    if (a.count_dev && (uint64_t)*a.count_dev < c) c = *a.count_dev;
+    const uint64_t n_touched = c;
+    for (int q = 0; q < a.pass; ++q) c = ((c + kTopkChunk - 1) / kTopkChunk) * (uint64_t)a.k;
+    const uint64_t base = (uint64_t)blockIdx.x * kTopkChunk;
+    if (base >= c && blockIdx.x > 0 && !a.fused) return;
+    const uint32_t have = base >= c ? 0u : (uint32_t)(c - base < kTopkChunk ? c - base : kTopkChunk);
+    uint32_t m = pow2_at_least(have);
+    if (have > 0 || blockIdx.x == 0) {
+        const int32_t frame = (a.pass == 0 && a.mode == TOPK_RANK) ? *a.ra.frame : 0;
+        for (uint32_t e = threadIdx.x; e < m; e += 256) {
+            const uint64_t idx = base + e;
+            uint64_t v = 0ull;
+            if (e < have) {
+                if (a.pass == 0 && a.mode == TOPK_LRU)
+                    v = ~(((uint64_t)(uint32_t)a.lru_last_used[idx] << 32) | idx);
+                else if (a.pass == 0 && a.mode == TOPK_RANK)
+                    v = rank_score(a.ra, frame, idx);
+                else
+                    v = a.in[idx];
+            }
+            s[e] = v;
+        }
+        __syncthreads();
+        sort_desc(s, m);
+        for (int32_t e = threadIdx.x; e < a.k; e += 256)
+            a.out[(uint64_t)blockIdx.x * a.k + e] = (uint32_t)e < m ? s[e] : 0ull;
+    }
+    if (a.fused) {
+        // the last workgroup to finish pass 0 completes the selection
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) ticket = atomicAdd(a.done, 1u);
+        __syncthreads();
+        if (ticket != gridDim.x - 1u) return;
+        __threadfence();
+        if (threadIdx.x == 0) *a.done = 0u;
+        // pass 1 over pass 0's live output: at most 2048 entries (the host
+        // fuses only selections of two passes)
+        const uint64_t cc = ((c + kTopkChunk - 1) / kTopkChunk) * (uint64_t)a.k;
+        const uint32_t h = (uint32_t)(cc < kTopkChunk ? cc : kTopkChunk);
+        m = pow2_at_least(h);
+        __syncthreads();
+        for (uint32_t e = threadIdx.x; e < m; e += 256) s[e] = e < h ? a.out[e] : 0ull;
+        __syncthreads();
+        sort_desc(s, m);
+        for (int32_t e = threadIdx.x; e < a.k; e += 256) a.final_out[e] = (uint32_t)e < m ? s[e] : 0ull;
+    }
+    if (a.sel.ctr) {
+        // request list: keys of the non-zero scores, best first
+        if (threadIdx.x == 0) nsel = 0u;
+        __syncthreads();
+        for (int32_t t = threadIdx.x; t < a.sel.lim; t += 256) {
+            const uint64_t v = (uint32_t)t < m ? s[t] : 0ull;
+            if (v != 0ull) {
+                a.sel.ins_keys[t] = (int32_t)(0xFFFFFFFFull - (v & 0xFFFFFFFFull));
+                atomicAdd(&nsel, 1u);
+            }
+        }
+        __syncthreads();
+        CacheCtr* ctr = a.sel.ctr;
+        const uint32_t n_free = (uint32_t)a.sel.pool_bricks - ctr->n_used;
+        const uint32_t need_evict = nsel > n_free ? nsel - n_free : 0u;
+        if (threadIdx.x == 0) {
+            ctr->n_sel = nsel;
+            ctr->n_free = n_free;
+            ctr->need_evict = need_evict;
+        }
+        if (a.tail.insert) {
+            // the selection is at most 256 bricks: one entry per thread
+            CacheCtr snap = *ctr;
+            snap.n_sel = nsel;
+            snap.n_free = n_free;
+            snap.need_evict = need_evict;
+            __syncthreads();
+            insert_entries(a.tail.c, a.tail.g, snap, threadIdx.x, 256u);
+            __syncthreads();
+            if (threadIdx.x == 0) insert_counters(ctr, snap);
+        }
+        if (a.tail.stats && threadIdx.x == 0) views_frame_stats(a.tail.c, (uint32_t)n_touched, nsel, need_evict);
+    }
+}
+
+// Prefill: the given keys are inserted into free slots only.
+__global__ void k_prefill_setup(CacheDev c, const int32_t* keys, int32_t n, int32_t stamp) {
+    for (int32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) c.ins_keys[t] = keys[t];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        CacheCtr* ctr = c.ctr;
+        const uint32_t n_free = (uint32_t)c.pool_bricks - ctr->n_used;
+        const uint32_t nn = (uint32_t)n <= n_free ? (uint32_t)n : n_free;
+        if ((uint32_t)n > n_free) ctr->error |= 1u;
+        ctr->frame = stamp - 1;  // k_insert stamps frame + 1
+        ctr->n_sel = nn;
+        ctr->n_free = n_free;
+        ctr->need_evict = 0u;
+    }
+}
+
+__global__ void k_insert(CacheDev c, CacheGeom g, int32_t finish_inline, const uint32_t* gate) {
+    if (gate && *gate == 0u) return;
+    const CacheCtr ctr = *c.ctr;
+    insert_entries(c, g, ctr, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
     if (finish_inline) {  // single-workgroup launch: update the counters here
         __syncthreads();
-        if (threadIdx.x == 0) {
-            const uint32_t filled = ctr.n_sel < ctr.n_free ? ctr.n_sel : ctr.n_free;
-            c.ctr->n_used = ctr.n_used + filled;
-            c.ctr->n_evlog = ctr.n_evlog + ctr.n_sel;
-        }
+        if (threadIdx.x == 0) insert_counters(c.ctr, ctr);
     }
 }
 
 __global__ void k_insert_finish(CacheDev c, const uint32_t* gate) {
     if (gate && *gate == 0u) return;
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        CacheCtr* ctr = c.ctr;
-        const uint32_t filled = ctr->n_sel < ctr->n_free ? ctr->n_sel : ctr->n_free;
-        ctr->n_used += filled;
-        ctr->n_evlog += ctr->n_sel;
+        const CacheCtr ctr = *c.ctr;
+        insert_counters(c.ctr, ctr);
     }
 }
 
@@ -232,7 +309,19 @@ hipError_t launch_clear_last_req(const CacheDev& c, int64_t n_keys, hipStream_t 
 }
 
 hipError_t launch_topk(const TopkArgs& base, const TopkPlan& plan, uint64_t* buf0, uint64_t* buf1, uint64_t* final_out,
-                       const SelectArgs* epilogue, hipStream_t s) {
+                       const SelectArgs* epilogue, uint32_t* fuse_done, hipStream_t s) {
+    if (fuse_done && plan.n_pass == 2) {
+        // one launch: pass 0, then pass 1 in its last workgroup
+        TopkArgs a = base;
+        a.pass = 0;
+        a.out = buf0;
+        a.final_out = final_out;
+        a.fused = 1;
+        a.done = fuse_done;
+        a.sel = epilogue ? *epilogue : SelectArgs{};
+        hipLaunchKernelGGL(k_topk, dim3(plan.blocks[0]), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
     const uint64_t* src = base.in;
     for (int p = 0; p < plan.n_pass; ++p) {
         TopkArgs a = base;

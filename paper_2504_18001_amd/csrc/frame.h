@@ -32,7 +32,18 @@ struct CacheCtr {
     uint32_t n_evlog;
     uint32_t error;
     int32_t frame;        // frame whose requests are ranked; insertions are stamped frame + 1
+    uint32_t select_done; // workgroups of the fused selection launch that have finished
+    uint32_t n_views;     // views of the current frame (their statistics targets are in CacheDev::views)
 };
+
+// Where a view's frame statistics go: written into the cache's table by the
+// view's k_frame_begin, read at the end of the frame's selection.
+struct ViewEnd {
+    unsigned long long* stats;
+    const IterCtr* ctr;
+    int32_t max_iters, pad;
+};
+constexpr int kMaxFrameViews = 64;
 
 struct MissLogRec {
     int32_t pix, k;
@@ -61,6 +72,7 @@ struct CacheDev {
     int32_t* evlog;
     int32_t evlog_cap;
     CacheCtr* ctr;
+    ViewEnd* views;       // [kMaxFrameViews]
     int32_t pool_bricks, max_requests, rank_window, ranking, ins_cap;
 };
 
@@ -87,6 +99,9 @@ struct FrameDev {
     float step, lod_scale, ert;
     int32_t ert_on;
     int32_t S;
+    int32_t max_iters;    // bound on the wavefront iterations
+    int32_t view_index, n_views;  // this view's place in the frame's views
+    ViewEnd* view_table;  // nullable: the cache's table of the views' statistics targets
     int32_t mode;
     int32_t xcd_bands;  // image bands per XCD in the march kernel's work split
     int32_t pipe;       // samples fetched ahead per ray in the march kernel
@@ -166,6 +181,15 @@ struct SelectArgs {
     int32_t pool_bricks, lim;
 };
 
+// Work the final selection workgroup does after publishing the request list:
+// the insertion (when no LRU pass comes between) and the views' frame
+// statistics.
+struct SelectTail {
+    int32_t insert, stats;
+    CacheDev c;
+    CacheGeom g;
+};
+
 struct TopkArgs {
     const uint64_t* in;
     const uint32_t* count_dev;  // live elements of pass 0 (nullable)
@@ -179,6 +203,12 @@ struct TopkArgs {
     const int32_t* lru_last_used;
     RankArgs ra;
     SelectArgs sel;
+    // fused launch of a two-pass selection: the workgroups of pass 0, then
+    // the last of them to finish runs pass 1 alone into final_out
+    int32_t fused;
+    uint32_t* done;         // count of finished workgroups (reset by the last)
+    uint64_t* final_out;
+    SelectTail tail;
 };
 
 // render.cpp launchers
@@ -200,8 +230,10 @@ hipError_t launch_pending_gather(const FrameDev* const* fs, int n, uint32_t* hos
 
 // cache launchers
 hipError_t launch_cache_init(const CacheDev& c, int64_t n_keys, hipStream_t s);
+// fuse_done (nullable): count of finished workgroups for a single fused
+// launch of a two-pass plan (pass 0, then pass 1 in its last workgroup).
 hipError_t launch_topk(const TopkArgs& base, const TopkPlan& plan, uint64_t* buf0, uint64_t* buf1, uint64_t* final_out,
-                       const SelectArgs* epilogue, hipStream_t s);
+                       const SelectArgs* epilogue, uint32_t* fuse_done, hipStream_t s);
 hipError_t launch_prefill_setup(const CacheDev& c, const int32_t* keys, int32_t n, int32_t stamp, hipStream_t s);
 hipError_t launch_insert(const CacheDev& c, const CacheGeom& g, int32_t cap, const uint32_t* gate, hipStream_t s);
 hipError_t launch_clear_last_req(const CacheDev& c, int64_t n_keys, hipStream_t s);

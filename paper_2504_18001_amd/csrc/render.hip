@@ -305,7 +305,11 @@ __global__ __launch_bounds__(kBlock) void k_frame_begin(FrameDev f, int32_t n_ct
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     // the frame's camera, index and LoD seed: host block -> device
     if (t < 32) reinterpret_cast<uint32_t*>(f.var)[t] = reinterpret_cast<const uint32_t*>(f.var_src)[t];
-    if (t == 0 && cctr) cctr->frame = f.var_src->frame;
+    if (t == 0 && cctr) {
+        cctr->frame = f.var_src->frame;
+        cctr->n_views = (uint32_t)f.n_views;
+    }
+    if (t == 0 && f.view_table) f.view_table[f.view_index] = ViewEnd{f.stats, f.ctr, f.max_iters, 0};
     if (t < n_ctr) f.ctr[t] = IterCtr{0u, 0u, 0u, 0u};
     if (t < 16) f.claim[t * kClaimStride] = 0u;
     if (t < ST_COUNT) f.stats[t] = 0ull;
