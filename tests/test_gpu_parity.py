@@ -189,3 +189,11 @@ def test_cached_sequence_512_arch_reduced():
     # 120x104x96 virtual volume, 4 LoDs, B = 16, pre-load of the coarsest LoD
     w = configs.scaled(configs.HD512, 80, 45, orbit_radius=260.0, lod_scale=1.0 / 180.0)
     run_cached_sequence(w, range(8), 80, 45, dims=(120, 104, 96), pool=300, max_req=12, preload=2)
+
+
+def test_cached_sequence_two_pass_selection():
+    # 128x120x112 virtual volume, B = 8, 2 LoDs: about 5,800 keys, so the
+    # selection takes two passes (one fused launch); the 160-slot pool fills
+    # after 7 frames, then the LRU pass and a separate insertion run
+    w = configs.SMALL
+    run_cached_sequence(w, range(12), 96, 96, dims=(128, 120, 112), pool=160, max_req=24)
