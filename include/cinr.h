@@ -284,7 +284,9 @@ cinr_status cinr_render_frame(cinr_cache cache, cinr_volume vol, const cinr_came
  * events on the caller's stream (no synchronisation is added);
  * cinr_collect_timing synchronises on the last event, writes the summed
  * milliseconds and the number of bracketed launches per stage
- * (arrays of CINR_STAGE_COUNT) and clears the record. */
+ * (arrays of CINR_STAGE_COUNT) and clears the record.  enable: 0 off,
+ * 1 every stage, 2 the march stage only (two events per march launch, the
+ * least overhead). */
 typedef enum {
     CINR_STAGE_SETUP = 0,   /* frame initialisation, macro-cell flags, ray generation */
     CINR_STAGE_MARCH = 1,   /* sampler: cache lookups, compositing, miss gathering */

@@ -176,8 +176,9 @@ class _VolumeOps:
         _check(lib().cinr_decode_bricks(self.h, _ptr(reqs), n, brick, _ptr(out), _dtype(dtype), _stream()))
         return out
 
-    def set_timing(self, on: bool):
-        _check(lib().cinr_set_timing(self.h, 1 if on else 0))
+    def set_timing(self, on, march_only=False):
+        """Stage timing off, on (every stage) or, with march_only, on the march launches only."""
+        _check(lib().cinr_set_timing(self.h, (2 if march_only else 1) if on else 0))
 
     def collect_timing(self):
         """{stage: (milliseconds, launches)} since the last collection."""

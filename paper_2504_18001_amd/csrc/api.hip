@@ -82,6 +82,7 @@ bool geometry(const int32_t dims[3], int32_t B, int32_t n_lods, CacheGeom& g) {
 // Per-stage event timing (optional).
 struct Timing {
     bool on = false;
+    bool march_only = false;  // bracket only the march launches
     std::vector<hipEvent_t> pool;  // free timing events
     struct Rec {
         int stage;
@@ -137,13 +138,14 @@ struct StageTimer {
     int stage;
     hipEvent_t a = nullptr;
     StageTimer(Timing& t_, hipStream_t s_, int stage_) : t(t_), s(s_), stage(stage_) {
+        if (t.on && t.march_only && stage != CINR_STAGE_MARCH) return;
         if (t.on) {
             a = t.get();
             (void)hipEventRecord(a, s);
         }
     }
     ~StageTimer() {
-        if (t.on) {
+        if (a) {
             hipEvent_t b = t.get();
             (void)hipEventRecord(b, s);
             t.recs.push_back(Timing::Rec{stage, a, b});
@@ -295,7 +297,9 @@ extern "C" void cinr_destroy_volume(cinr_volume v) {
 
 extern "C" cinr_status cinr_set_timing(cinr_volume v, int32_t enable) {
     if (!v) return fail(CINR_INVALID_ARG, "null volume");
+    if (enable < 0 || enable > 2) return fail(CINR_INVALID_ARG, "timing mode %d (0, 1 or 2)", enable);
     v->timing.on = enable != 0;
+    v->timing.march_only = enable == 2;
     return CINR_OK;
 }
 
