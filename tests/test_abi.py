@@ -167,3 +167,26 @@ def test_render_workspace_covers_the_per_ray_buffers():
         assert L.cinr_render_workspace_size(h, 0, 1080, 32, C.byref(b)) == INVALID_ARG
     finally:
         L.cinr_destroy_volume(h)
+
+
+def test_timing_modes():
+    _, h, _ = fake_volume(configs.ARCH_SMALL)
+    L = cinr.lib()
+    try:
+        for mode in (0, 1, 2, 0):
+            assert L.cinr_set_timing(h, mode) == OK
+        assert L.cinr_set_timing(h, 3) == INVALID_ARG
+        assert L.cinr_set_timing(h, -1) == INVALID_ARG
+        assert b"timing mode" in L.cinr_last_error()
+        assert L.cinr_set_timing(None, 1) == INVALID_ARG
+    finally:
+        L.cinr_destroy_volume(h)
+
+
+def test_frame_graph_arguments_are_checked_before_any_device_work():
+    L = cinr.lib()
+    g = C.c_void_p()
+    assert L.cinr_frame_graph_create(None, 1, None, C.byref(g)) == INVALID_ARG
+    assert L.cinr_frame_graph_render(None, None, 0, None) == INVALID_ARG
+    a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+    assert L.cinr_frame_graph_counts(None, C.byref(a), C.byref(b), C.byref(c)) == INVALID_ARG
