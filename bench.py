@@ -126,7 +126,7 @@ def decode_throughput(vol, w, dtype, n_bricks, reps=5):
     return n_bricks / (ms * 1e-3), ms
 
 
-def multiview_leg(warmup, steps, dtype):
+def multiview_leg(warmup, steps, dtype, oracle=True):
     """Frames of 16 views of 4 INRs through one shared cache (one cache
     manager pass and one multi-INR decode launch per frame)."""
     import torch
@@ -208,6 +208,7 @@ def multiview_leg(warmup, steps, dtype):
     e1.record()
     torch.cuda.synchronize()
     dec = (keys.numel() - 256) / (e0.elapsed_time(e1) * 1e-3)
+    cpu = multiview_oracle(mv) if oracle else None
     return {"workload": mv.name, "views": mv.n_views, "inrs": mv.n_inrs, "pixels_per_frame": pixels,
             "frames": steps, "frame_ms": round(dt / steps * 1e3, 4),
             "aggregate_view_fps": round(mv.n_views * steps / dt, 2),
@@ -217,10 +218,43 @@ def multiview_leg(warmup, steps, dtype):
             "graph_aggregate_view_fps": round(mv.n_views * steps / dtg, 2),
             "graph_frames_replayed_eager_tail": [n_graph, n_eager, n_tail],
             "requested_selected_last_frame": [st[0]["requested"], st[0]["selected"]],
-            "multi_inr_decode_bricks_per_s": round(dec, 1)}
+            "multi_inr_decode_bricks_per_s": round(dec, 1),
+            "cpu_oracle": cpu}
 
 
-def training_leg(warmup, steps):
+def multiview_oracle(mv):
+    """The CPU oracle on frame 0 of the 16 views (cold shared cache) at 1/8 x
+    1/8 of each view's pixels: view pixels per second of the oracle."""
+    import numpy as np
+    from oracle import oracle as O
+    from paper_2504_18001_amd import synth
+    ms = []
+    for i in range(mv.n_inrs):
+        table, weights = synth.random_inr_params(mv.arch, i)
+        s, o = load_value_range(f"inr512/{i}")
+        ms.append(O.OracleInr(mv.arch, table, weights, s, o))
+    cs = mv.cache
+    # one frame from a cold cache inserts at most max_requests bricks: a small
+    # pool gives the same frame (the 32 GiB FP32 pool would be 64 GiB in FP64)
+    oc = O.OracleCache(ms, brick=cs.brick, n_lods=cs.n_lods, pool_bricks=4096, max_requests=cs.max_requests,
+                       preload_period=cs.preload_period)
+    views, params, pixels = [], [], 0
+    for v in range(mv.n_views):
+        cam = mv.camera(v, 0)
+        cam.width, cam.height = cam.width // 8, cam.height // 8
+        pixels += cam.width * cam.height
+        views.append((mv.view_inr(v), cam, mv.tf(0)))
+        params.append(O.make_params(mv.step, mv.lod_scale, seed=mv.seed, frame_index=0, ert_threshold=mv.ert_threshold,
+                                    samples_per_iter=mv.samples_per_iter))
+    t0 = time.perf_counter()
+    oc.render_views(views, params)
+    dt = time.perf_counter() - t0
+    return {"view_pixels_per_s": round(pixels / dt, 1), "cores": O.get_threads(), "kind": "oracle",
+            "sample": f"frame 0 of the 16 views from a cold cache at 1/8 x 1/8 of their sizes ({pixels} pixels, "
+                      f"{dt:.2f} s)"}
+
+
+def training_leg(warmup, steps, oracle=True):
     """GPU training of the learned INR (16 levels x 2, T = 2^20, 32-64-64-1,
     BF16 MLP) on the 1024^3 Fourier field: 2^18 Philox points per step.
     Reports the step time and a breakdown (batch, gradients, Adam) with the
@@ -263,6 +297,20 @@ def training_leg(warmup, steps):
     adam_ms = timed(lambda: cinr.adam_update(p_, m_, v_, g_, 1, clear_grad=True))
     adam_bytes = 32 * n  # reads p, m, v, g; writes p, m, v and the cleared g
     adam_gbs = adam_bytes / (adam_ms * 1e-3) / 1e9
+    cpu = None
+    if oracle:
+        # the CPU oracle's loss and gradients (FP64) on the first 4096 points of a batch
+        import numpy as np
+        from oracle import oracle as O
+        m = O.OracleInr(arch, table, weights)
+        un = u[:4096].double().cpu().numpy()
+        tn = t[:4096].double().cpu().numpy()
+        t0 = time.perf_counter()
+        O.loss_grad(m, un, tn)
+        dt = time.perf_counter() - t0
+        cpu = {"points_per_s": round(4096 / dt, 1), "cores": O.get_threads(), "kind": "oracle",
+               "sample": f"loss and all gradients of 4096 points of one batch in FP64 ({dt:.2f} s, with the "
+                         f"16 M-entry table gradient)"}
     return {"workload": "learn1024_inr16x2_T2^20", "points_per_step": batch, "steps": steps,
             "step_ms": round(step_ms, 4), "points_per_s": round(batch / (step_ms * 1e-3), 1),
             "batch_ms": round(pts_ms, 4), "gradients_ms": round(grad_ms, 4), "adam_ms": round(adam_ms, 4),
@@ -271,7 +319,7 @@ def training_leg(warmup, steps):
                               "note": "4 arrays of 16.06 M floats (257 MB) updated back to back: part of them stays "
                                       "in the 256 MB Infinity Cache between launches, so the rate can pass the HBM "
                                       "peak"},
-            "final_batch_loss": float(loss.item())}
+            "final_batch_loss": float(loss.item()), "cpu_oracle": cpu}
 
 
 def cpu_baseline(w, budget_s):
@@ -458,12 +506,12 @@ def main():
 
     multi = None
     if not args.no_multiview:
-        multi = multiview_leg(60, args.multiview_steps, args.dtype)
+        multi = multiview_leg(60, args.multiview_steps, args.dtype, oracle=not args.no_cpu_baseline)
         log(f"[bench] multiview {multi}")
 
     train = None
     if not args.no_training:
-        train = training_leg(10, args.training_steps)
+        train = training_leg(10, args.training_steps, oracle=not args.no_cpu_baseline)
         log(f"[bench] training {train}")
 
     cpu = None

@@ -593,13 +593,17 @@ orc_cache* orc_cache_create_multi(const orc_inr* ms, int32_t n_vols, const orc_c
     c->rank = (int64_t*)malloc(sizeof(int64_t) * off);
     c->req = (uint32_t*)calloc(off, sizeof(uint32_t));
     c->last_req = (uint32_t*)calloc(off, sizeof(uint32_t));
+    const int64_t P = d->pool_bricks > 0 ? d->pool_bricks : 1;
+    c->owner = (int32_t*)malloc(sizeof(int32_t) * P);
+    c->last_used = (int32_t*)malloc(sizeof(int32_t) * P);
+    if (!c->pt || !c->rank || !c->req || !c->last_req || !c->owner || !c->last_used) {
+        orc_cache_destroy(c);
+        return NULL;
+    }
     for (int64_t k = 0; k < off; ++k) {
         c->pt[k] = -1;
         c->rank[k] = -1;
     }
-    const int64_t P = d->pool_bricks > 0 ? d->pool_bricks : 1;
-    c->owner = (int32_t*)malloc(sizeof(int32_t) * P);
-    c->last_used = (int32_t*)malloc(sizeof(int32_t) * P);
     for (int64_t s = 0; s < P; ++s) {
         c->owner[s] = -1;
         c->last_used[s] = -1;
@@ -608,6 +612,10 @@ orc_cache* orc_cache_create_multi(const orc_inr* ms, int32_t n_vols, const orc_c
     c->req_list = (int32_t*)malloc(sizeof(int32_t) * (d->max_requests > 0 ? d->max_requests : 1));
     c->cap_evlog = 1024;
     c->evlog = (int32_t*)malloc(sizeof(int32_t) * 4 * c->cap_evlog);
+    if (!c->pool || !c->req_list || !c->evlog) {  // e.g. an FP64 pool larger than host memory
+        orc_cache_destroy(c);
+        return NULL;
+    }
     return c;
 }
 

@@ -344,7 +344,7 @@ class OracleCache:
         self._descs = (Inr * len(inrs))(*[m.desc for m in inrs])
         self.h = lib().orc_cache_create_multi(C.cast(self._descs, C.c_void_p), len(inrs), C.byref(d))
         if not self.h:
-            raise ValueError("invalid cache description")
+            raise ValueError("invalid cache description, or not enough host memory for it")
         self.n_keys = int(lib().orc_cache_n_keys(self.h))
         lib().orc_cache_set_miss_logging(self.h, 1 if log_misses else 0)
         lib().orc_cache_set_ert_trace(self.h, 1 if trace_ert else 0)
