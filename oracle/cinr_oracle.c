@@ -365,6 +365,37 @@ void orc_macrocells(const orc_inr* m, int32_t N, float* minmax) {
 /* Maximum opacity over the transfer-function rows a cell's value range can
  * touch, [floor(min*255), ceil(max*255)]; the flag is 0 exactly when that
  * maximum is 0 (fully transparent cell, skipped by the sampler). */
+/* Maximum opacity over the rows [floor(min*255), ceil(max*255)] of cell c. */
+static float cell_mu(const float* minmax, int64_t c, const float* tf) {
+    float a = minmax[2 * c] * 255.0f;
+    float b = minmax[2 * c + 1] * 255.0f;
+    int lo = (int)floorf(a), hi = (int)ceilf(b);
+    if (lo < 0) lo = 0;
+    if (hi > 255) hi = 255;
+    float mu = 0.0f;
+    for (int r = lo; r <= hi; ++r)
+        if (tf[4 * r + 3] > mu) mu = tf[4 * r + 3];
+    return mu;
+}
+
+/* floor(-log2 mu) for 0 < mu < 1 from the binary32 fields: mu = m 2^x with
+ * m in [1, 2) gives -log2 mu in (-x - 1, -x], equal to -x exactly when m = 1. */
+int32_t orc_step_exp(float mu, int32_t E) {
+    if (mu >= 1.0f) return 0;
+    uint32_t bits;
+    memcpy(&bits, &mu, 4);
+    const int32_t x = (int32_t)((bits >> 23) & 0xFFu) - 127;
+    const int32_t e = (bits & 0x7FFFFFu) == 0u ? -x : -x - 1;
+    return e < E ? e : E;
+}
+
+void orc_macrocell_step_codes(const float* minmax, int64_t n_cells, const float* tf, int32_t E, uint8_t* codes) {
+    for (int64_t c = 0; c < n_cells; ++c) {
+        const float mu = cell_mu(minmax, c, tf);
+        codes[c] = mu > 0.0f ? (uint8_t)orc_step_exp(mu, E) : (uint8_t)0xFF;
+    }
+}
+
 void orc_macrocell_flags(const float* minmax, int64_t n_cells, const float* tf, uint8_t* flags) {
     for (int64_t c = 0; c < n_cells; ++c) {
         float a = minmax[2 * c] * 255.0f;
@@ -778,6 +809,7 @@ typedef struct {
     int status;
     double value;
     float pos[3];
+    int exp;  /* step exponent of the sample's cell (0 without adaptive sampling) */
 } sample_out;
 
 typedef struct {
@@ -793,6 +825,7 @@ typedef struct {
  * not served at its own LoD raises a request for its brick at that LoD. */
 static void sample_decide(const frame_ctx* fc, const float o[3], const float d[3], float t, sample_out* so) {
     const orc_params* P = fc->p;
+    so->exp = 0;
     float pos[3];
     for (int a = 0; a < 3; ++a) {
         float td = t * d[a];
@@ -808,7 +841,17 @@ static void sample_decide(const frame_ctx* fc, const float o[3], const float d[3
             ci[a] = (int32_t)pos[a] / P->macro_cell;
             if (ci[a] > fc->M[a] - 1) ci[a] = fc->M[a] - 1;
         }
-        if (!fc->flags[((int64_t)ci[2] * fc->M[1] + ci[1]) * fc->M[0] + ci[0]]) {
+        const uint8_t code = fc->flags[((int64_t)ci[2] * fc->M[1] + ci[1]) * fc->M[0] + ci[0]];
+        if (P->adapt_max_exp >= 0) {
+            /* adaptive rate: the cell's step exponent, the largest one across a transparent cell */
+            if (code == 0xFF) {
+                so->exp = P->adapt_max_exp;
+                so->status = S_SKIP;
+                so->value = 0.0;
+                return;
+            }
+            so->exp = code;
+        } else if (!code) {
             so->status = S_SKIP;
             so->value = 0.0;
             return;
@@ -899,7 +942,7 @@ static void acc_miss(thread_acc* ta, int32_t pix, int32_t k, const float pos[3])
  * directly from the INR at the sample position (Algorithm 1, InferINR and
  * InsertMisses, within the same sampling step). */
 static int run_sample(const frame_ctx* fc, thread_acc* ta, int32_t pix, int32_t k, const float o[3],
-                      const float d[3], float ts, double* value, int log_miss) {
+                      const float d[3], float ts, double* value, int* exp, int log_miss) {
     const float kk = (float)k * fc->p->step;
     const float t = ts + kk;
     sample_out so;
@@ -917,6 +960,7 @@ static int run_sample(const frame_ctx* fc, thread_acc* ta, int32_t pix, int32_t 
         }
     }
     *value = so.value;
+    *exp = so.exp;
     return so.status;
 }
 
@@ -953,17 +997,21 @@ static int32_t march(const frame_ctx* fc, thread_acc* ta, const float* tf, int32
     ray_acc acc = {{0.0, 0.0, 0.0}, 0.0};
     double* vals = (double*)malloc(sizeof(double) * S);
     int* stat = (int*)malloc(sizeof(int) * S);
+    int* exps = (int*)malloc(sizeof(int) * S);
+    /* k: index of the next sample on the ray's grid t_k = ts + k*step; a
+     * sample whose cell has step exponent e is followed by sample k + 2^e,
+     * and its opacity is corrected to its own step 2^e*step */
     int32_t k = 0;
     int done = 0;
     while (!done && k < nk) {
         /* one sample at a time until the first true miss */
-        int st = S_HIT;
+        int st = S_HIT, e = 0;
         double v = 0.0;
         while (k < nk) {
-            st = run_sample(fc, ta, pix, k, o, d, ts, &v, log_miss);
+            st = run_sample(fc, ta, pix, k, o, d, ts, &v, &e, log_miss);
             if (st == S_MISS) break;
-            if (st != S_SKIP) composite(&acc, tf, v, step);
-            ++k;
+            if (st != S_SKIP) composite(&acc, tf, v, ldexp(step, e));
+            k += 1 << e;
             if (ert && acc.A >= thr) {
                 done = 1;
                 break;
@@ -973,22 +1021,26 @@ static int32_t march(const frame_ctx* fc, thread_acc* ta, const float* tf, int32
         /* a wavefront step of S samples starting at the miss */
         int32_t n = 0;
         vals[n] = v;
+        exps[n] = e;
         stat[n++] = st;
-        while (n < S && k + n < nk) {
-            stat[n] = run_sample(fc, ta, pix, k + n, o, d, ts, &vals[n], log_miss);
+        int32_t kn = k + (1 << e);
+        while (n < S && kn < nk) {
+            stat[n] = run_sample(fc, ta, pix, kn, o, d, ts, &vals[n], &exps[n], log_miss);
+            kn += 1 << exps[n];
             ++n;
         }
         for (int32_t s = 0; s < n; ++s) {
-            if (stat[s] != S_SKIP) composite(&acc, tf, vals[s], step);
+            if (stat[s] != S_SKIP) composite(&acc, tf, vals[s], ldexp(step, exps[s]));
             if (ert && acc.A >= thr) {
                 done = 1;
                 break;
             }
         }
-        k += n;
+        k = kn;
     }
     free(vals);
     free(stat);
+    free(exps);
     out[0] = acc.C[0];
     out[1] = acc.C[1];
     out[2] = acc.C[2];
@@ -1051,12 +1103,16 @@ static int render_pass(frame_ctx* fc, const float* tf, double* rgba, orc_stats* 
     return 0;
 }
 
+/* Per-cell flags (visible or not), or step codes with adaptive sampling. */
 static uint8_t* make_flags(const orc_inr* m, const orc_params* p, const float* tf, int32_t M[3]) {
     if (p->macro_cell <= 0 || !p->macro_minmax) return NULL;
     for (int a = 0; a < 3; ++a) M[a] = (m->dims[a] + p->macro_cell - 1) / p->macro_cell;
     int64_t n = (int64_t)M[0] * M[1] * M[2];
     uint8_t* f = (uint8_t*)malloc(n);
-    orc_macrocell_flags(p->macro_minmax, n, tf, f);
+    if (p->adapt_max_exp >= 0)
+        orc_macrocell_step_codes(p->macro_minmax, n, tf, p->adapt_max_exp, f);
+    else
+        orc_macrocell_flags(p->macro_minmax, n, tf, f);
     return f;
 }
 

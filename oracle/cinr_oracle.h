@@ -66,6 +66,8 @@ typedef struct {
     int32_t mode;
     int32_t macro_cell;  /* macro-cell side N; 0 = no empty-space skipping */
     const float* macro_minmax; /* [Mz][My][Mx][2] */
+    int32_t adapt_max_exp; /* adaptive sampling rate (Section 5.2): < 0 off; else E, the largest step
+                              exponent (steps of 2^e sample spacings, e in [0, E]) */
 } orc_params;
 
 typedef struct {
@@ -109,6 +111,12 @@ int orc_decode_bricks(const orc_inr* m, const int32_t* reqs, int64_t n, int32_t 
 /* --- macro-cells (Section 5.2) --- */
 void orc_macrocells(const orc_inr* m, int32_t cell, float* minmax);
 void orc_macrocell_flags(const float* minmax, int64_t n_cells, const float* tf, uint8_t* flags);
+/* Step exponent of a cell of maximum opacity mu (> 0): min(E, floor(-log2 mu)),
+ * 0 for mu >= 1. */
+int32_t orc_step_exp(float mu, int32_t E);
+/* Per-cell code of the adaptive sampler: 0xFF for a transparent cell, else
+ * its step exponent (orc_step_exp of the cell's maximum opacity). */
+void orc_macrocell_step_codes(const float* minmax, int64_t n_cells, const float* tf, int32_t E, uint8_t* codes);
 
 /* --- decision-plane pieces exposed for pinning --- */
 int orc_ray_setup(const orc_camera* c, const int32_t dims[3], int32_t i, int32_t j,

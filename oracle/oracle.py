@@ -38,7 +38,8 @@ class Camera(C.Structure):
 class Params(C.Structure):
     _fields_ = [("step", C.c_float), ("lod_scale", C.c_float), ("ert_threshold", C.c_float),
                 ("seed", C.c_uint32), ("frame_index", C.c_int32), ("samples_per_iter", C.c_int32),
-                ("mode", C.c_int32), ("macro_cell", C.c_int32), ("macro_minmax", C.c_void_p)]
+                ("mode", C.c_int32), ("macro_cell", C.c_int32), ("macro_minmax", C.c_void_p),
+                ("adapt_max_exp", C.c_int32)]
 
 
 class CacheDesc(C.Structure):
@@ -82,6 +83,8 @@ def lib():
             "orc_decode_bricks": (C.c_int, [P, P, i64, i32, i32, P]),
             "orc_macrocells": (None, [P, i32, P]),
             "orc_macrocell_flags": (None, [P, i64, P, P]),
+            "orc_step_exp": (i32, [C.c_float, i32]),
+            "orc_macrocell_step_codes": (None, [P, i64, P, i32, P]),
             "orc_ray_setup": (C.c_int, [P, P, i32, i32, P, P, P, P]),
             "orc_select_lod": (i32, [P, P, C.c_float, u32, i32, i32]),
             "orc_lod_floor": (i32, [i32, i32, i32]),
@@ -286,6 +289,21 @@ def macrocell_flags(minmax, tf):
     return out
 
 
+def step_exp(mu, E):
+    """Step exponent of a macro-cell of maximum opacity mu > 0 (adaptive sampling)."""
+    return int(lib().orc_step_exp(float(mu), int(E)))
+
+
+def macrocell_step_codes(minmax, tf, E):
+    """Per-cell codes of the adaptive sampler: 255 transparent, else the step exponent."""
+    mm = np.ascontiguousarray(minmax, np.float32)
+    n = mm.size // 2
+    out = np.zeros(n, np.uint8)
+    t = np.ascontiguousarray(tf, np.float32)
+    lib().orc_macrocell_step_codes(_ptr(mm), n, _ptr(t), int(E), _ptr(out))
+    return out
+
+
 def philox4x32_10(ctr, key):
     c = np.asarray(ctr, np.uint32)
     k = np.asarray(key, np.uint32)
@@ -295,8 +313,11 @@ def philox4x32_10(ctr, key):
 
 
 def make_params(step, lod_scale, seed=0, frame_index=0, ert_threshold=2.0, samples_per_iter=8, mode=CACHED,
-                macro_cell=0, macro_minmax=None):
+                macro_cell=0, macro_minmax=None, adapt_max_exp=-1):
+    """adapt_max_exp: adaptive sampling rate with steps of up to 2^E sample
+    spacings (Section 5.2); -1 (or 0) for the fixed step."""
     p = Params()
+    p.adapt_max_exp = adapt_max_exp
     p.step, p.lod_scale, p.ert_threshold = step, lod_scale, ert_threshold
     p.seed, p.frame_index, p.samples_per_iter, p.mode = seed & 0xFFFFFFFF, frame_index, samples_per_iter, mode
     p.macro_cell = macro_cell if macro_minmax is not None else 0
