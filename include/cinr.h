@@ -164,7 +164,16 @@ typedef struct {
  *                launch online, per volume and image size: the first 12
  *                frames of that size try pipe depths {1, 2} x bands {1, 4,
  *                16} twice each, then the fastest first-iteration march is
- *                kept (cinr_tuned_launch reports the choice). */
+ *                kept (cinr_tuned_launch reports the choice).
+ *  adapt_max_exp adaptive sampling rate (Section 5.2), with the volume's
+ *                macro-cells: E > 0 lets a ray cross a macro-cell of maximum
+ *                TF opacity mu in steps of 2^e sample spacings, e =
+ *                min(E, floor(-log2 mu)), still on its grid ts + k*step
+ *                (sample k is followed by sample k + 2^e), each sample's
+ *                opacity corrected to its own step; a transparent cell is
+ *                crossed in steps of 2^E with its samples skipped.  0 (or
+ *                no macro-cells) is the fixed step; at most 14.  The march
+ *                runs with pipe depth 1 in this mode. */
 typedef struct {
     float step, lod_scale, ert_threshold;
     uint32_t seed;
@@ -174,6 +183,7 @@ typedef struct {
     int32_t mlp_dtype;
     int32_t pipe_depth;
     int32_t xcd_bands;
+    int32_t adapt_max_exp;
 } cinr_render_params;
 
 /* Frame counters written (not accumulated) by cinr_render_frame. */

@@ -54,7 +54,8 @@ class CameraDesc(C.Structure):
 class RenderParams(C.Structure):
     _fields_ = [("step", C.c_float), ("lod_scale", C.c_float), ("ert_threshold", C.c_float), ("seed", C.c_uint32),
                 ("frame_index", C.c_int32), ("samples_per_iter", C.c_int32), ("mode", C.c_int32),
-                ("mlp_dtype", C.c_int32), ("pipe_depth", C.c_int32), ("xcd_bands", C.c_int32)]
+                ("mlp_dtype", C.c_int32), ("pipe_depth", C.c_int32), ("xcd_bands", C.c_int32),
+                ("adapt_max_exp", C.c_int32)]
 
 
 class GridDesc(C.Structure):
@@ -347,7 +348,7 @@ class Renderer:
 
     def render(self, volume: Volume, cam, tf, step, lod_scale=0.0, frame_index=0, seed=0, ert_threshold=2.0,
                samples_per_iter=32, mode=CACHED, dtype="f32", cache: Cache = None, out=None, stats=None,
-               pipe_depth=0, xcd_bands=0):
+               pipe_depth=0, xcd_bands=0, adapt_max_exp=0):
         need = C.c_size_t()
         _check(lib().cinr_render_workspace_size(volume.h, cam.width, cam.height, samples_per_iter, C.byref(need)))
         if self.ws is None or self.ws.numel() < need.value:
@@ -361,6 +362,7 @@ class Renderer:
         p.seed, p.frame_index, p.samples_per_iter = int(seed) & 0xFFFFFFFF, int(frame_index), int(samples_per_iter)
         p.mode, p.mlp_dtype = int(mode), _dtype(dtype)
         p.pipe_depth, p.xcd_bands = int(pipe_depth), int(xcd_bands)
+        p.adapt_max_exp = int(adapt_max_exp)
         cd = camera_desc(cam)
         st = self.stats if stats is None else stats
         _check(lib().cinr_render_frame(cache.h if cache is not None else None, volume.h, C.byref(cd), _ptr(tf),
@@ -459,7 +461,7 @@ class MultiViewRenderer:
         self._keep = []
 
     def describe(self, views, step, lod_scale=0.0, frame_index=0, seed=0, ert_threshold=2.0, samples_per_iter=32,
-                 dtype="f32", outs=None, pipe_depth=0, xcd_bands=0):
+                 dtype="f32", outs=None, pipe_depth=0, xcd_bands=0, adapt_max_exp=0):
         """The cinr_view array of `views` (list of (volume, camera, tf)) and
         their output images; the TF tensors are kept alive by the renderer."""
         n = len(views)
@@ -485,6 +487,7 @@ class MultiViewRenderer:
             p.seed, p.frame_index, p.samples_per_iter = int(seed) & 0xFFFFFFFF, int(frame_index), int(samples_per_iter)
             p.mode, p.mlp_dtype = CACHED, _dtype(dtype)
             p.pipe_depth, p.xcd_bands = int(pipe_depth), int(xcd_bands)
+            p.adapt_max_exp = int(adapt_max_exp)
             v.d_rgba = outs[i].data_ptr()
             v.d_stats = self.stats[i].data_ptr()
             v.d_workspace = self.ws[i].data_ptr()
@@ -493,10 +496,10 @@ class MultiViewRenderer:
         return arr, outs
 
     def render(self, cache: Cache, views, step, lod_scale=0.0, frame_index=0, seed=0, ert_threshold=2.0,
-               samples_per_iter=32, dtype="f32", outs=None, pipe_depth=0, xcd_bands=0):
+               samples_per_iter=32, dtype="f32", outs=None, pipe_depth=0, xcd_bands=0, adapt_max_exp=0):
         """views: list of (volume, camera, tf); returns the list of RGBA images."""
         arr, outs = self.describe(views, step, lod_scale, frame_index, seed, ert_threshold, samples_per_iter, dtype,
-                                  outs, pipe_depth, xcd_bands)
+                                  outs, pipe_depth, xcd_bands, adapt_max_exp)
         _check(lib().cinr_render_views(cache.h, len(views), arr, _stream()))
         return outs
 
@@ -513,12 +516,12 @@ class FrameGraph:
     frames.  Owns the views' workspaces, images and statistics."""
 
     def __init__(self, cache: Cache, views, step, lod_scale=0.0, seed=0, ert_threshold=2.0, samples_per_iter=32,
-                 dtype="f32", pipe_depth=0, xcd_bands=0, device="cuda"):
+                 dtype="f32", pipe_depth=0, xcd_bands=0, adapt_max_exp=0, device="cuda"):
         self.cache = cache
         self.volumes = [v for v, _, _ in views]
         self.mv = MultiViewRenderer(len(views), device)
         arr, self.outs = self.mv.describe(views, step, lod_scale, 0, seed, ert_threshold, samples_per_iter, dtype,
-                                          None, pipe_depth, xcd_bands)
+                                          None, pipe_depth, xcd_bands, adapt_max_exp)
         self.tfs = list(self.mv._keep)
         self.n = len(views)
         h = C.c_void_p()

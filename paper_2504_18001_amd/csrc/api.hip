@@ -555,6 +555,8 @@ struct RenderLayout {
     unsigned long long* stats;
     FrameVar* var;
     uint32_t* gate;  // frame-end gate (view 0's is the frame's)
+    uint8_t* cell_code;  // adaptive sampling: per macro-cell step codes
+    uint8_t* vexp;       // adaptive sampling: step exponent of each gathered sample
 };
 
 static size_t render_layout(int64_t npix, int32_t S, int64_t n_cells, RenderLayout* r, void* base) {
@@ -573,6 +575,8 @@ static size_t render_layout(int64_t npix, int32_t S, int64_t n_cells, RenderLayo
     x.stats = cv.take<unsigned long long>(ST_COUNT);
     x.var = cv.take<FrameVar>(1);
     x.gate = cv.take<uint32_t>(1);
+    x.cell_code = cv.take<uint8_t>((size_t)(n_cells > 0 ? n_cells : 1));
+    x.vexp = cv.take<uint8_t>((size_t)npix * S);
     if (r) *r = x;
     return cv.off;
 }
@@ -669,6 +673,8 @@ cinr_status prepare_view(cinr_cache c, cinr_volume v, const cinr_camera* cam, co
     if (rp->xcd_bands < 0 || rp->xcd_bands > 64) return fail(CINR_INVALID_ARG, "xcd_bands must be in [0, 64]");
     if (rp->samples_per_iter < 1 || rp->samples_per_iter > 64)
         return fail(CINR_INVALID_ARG, "samples_per_iter must be in [1, 64]");
+    if (rp->adapt_max_exp < 0 || rp->adapt_max_exp > 14)
+        return fail(CINR_INVALID_ARG, "adapt_max_exp must be in [0, 14]");
     const bool cached = rp->mode == CINR_CACHED;
     if (cached && !c) return fail(CINR_INVALID_ARG, "the cached mode needs a cache");
     const int vi = cached ? c->index_of(v) : -1;
@@ -730,6 +736,12 @@ cinr_status prepare_view(cinr_cache c, cinr_volume v, const cinr_camera* cam, co
     f.div_mc = make_fastdiv((uint32_t)(f.mc_N > 0 ? f.mc_N : 1));
     f.flags = v->n_cells > 0 ? L.flags : nullptr;
     f.flag_words = (int32_t)((v->n_cells + 63) / 64);
+    // adaptive sampling needs the macro-cells; its codes replace the bits
+    f.adapt = v->n_cells > 0 ? rp->adapt_max_exp : 0;
+    f.n_cells = v->n_cells;
+    f.cell_code = L.cell_code;
+    f.vexp = L.vexp;
+    if (f.adapt > 0) f.flags = nullptr;
     f.claim = L.claim;
     f.tf = d_tf;
     f.rgba = reinterpret_cast<float4*>(d_rgba);

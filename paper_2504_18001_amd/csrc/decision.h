@@ -94,6 +94,18 @@ __device__ inline bool sample_pos(const float o[3], const float d[3], float ts, 
     return true;
 }
 
+// Step exponent of a macro-cell of maximum opacity mu > 0 under the adaptive
+// sampling rate (Section 5.2): min(E, floor(-log2 mu)), 0 for mu >= 1, from
+// the binary32 fields (mu = m 2^x with m in [1, 2): -log2 mu is in
+// (-x - 1, -x], equal to -x when m = 1).
+__device__ inline int32_t step_exp(float mu, int32_t E) {
+    if (mu >= 1.0f) return 0;
+    const uint32_t bits = __float_as_uint(mu);
+    const int32_t x = (int32_t)((bits >> 23) & 0xFFu) - 127;
+    const int32_t e = (bits & 0x7FFFFFu) == 0u ? -x : -x - 1;
+    return e < E ? e : E;
+}
+
 __device__ inline uint32_t xorshift32(uint32_t x) {
     x ^= x << 13;
     x ^= x >> 17;

@@ -110,6 +110,12 @@ struct FrameDev {
     int32_t M[3];
     uint64_t* flags;     // nullable: one bit per macro-cell, set when the cell is visible
     int32_t flag_words;  // 64-bit words of `flags`
+    // adaptive sampling rate: E > 0, then per macro-cell a code (0xFF
+    // transparent, else the step exponent e <= E); 0: fixed step
+    int32_t adapt;
+    int32_t n_cells;
+    uint8_t* cell_code;  // [n_cells]
+    uint8_t* vexp;       // [W*H*S] step exponent of each gathered sample
     uint32_t* claim;     // [2][8] work-unit counters of the march kernel (one set per iteration
                          // parity), kClaimStride words apart
     CacheGeom geo;
@@ -215,6 +221,8 @@ struct TopkArgs {
 // Macro-cell flags are staged in LDS by the march kernel up to this many words
 // (131072 cells); larger grids are read from global memory.
 constexpr int kMaxLdsFlagWords = 2048;
+// ... and the adaptive sampler's one-byte cell codes up to this many cells.
+constexpr int kMaxLdsCells = 32768;
 
 hipError_t launch_frame_begin(const FrameDev& f, int32_t n_iter_ctr, const float* minmax, int64_t n_cells,
                               CacheCtr* cctr, hipStream_t s);

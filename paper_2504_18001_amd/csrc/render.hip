@@ -23,6 +23,7 @@ struct SampleRes {
     int32_t slot;
     int32_t req_key;
     float value;
+    int32_t e;  // step exponent of the sample's macro-cell (adaptive sampling)
 };
 
 // The two most recent page-table lookups of a ray.  Residency is constant
@@ -58,6 +59,15 @@ struct GlobalFlags {
     const uint64_t* w;
     __device__ bool get(uint32_t cell) const { return (w[cell >> 6] >> (cell & 63u)) & 1ull; }
 };
+// One-byte macro-cell codes of the adaptive sampler (0xFF: transparent).
+struct LdsCodes {
+    const uint8_t* c;
+    __device__ uint32_t code(uint32_t cell) const { return c[cell]; }
+};
+struct GlobalCodes {
+    const uint8_t* c;
+    __device__ uint32_t code(uint32_t cell) const { return c[cell]; }
+};
 
 // Per-frame values that the sampler reads for every sample (loaded once per
 // launch from the frame's device block).
@@ -83,8 +93,9 @@ __device__ inline FrameHot load_hot(const FrameVar* v) {
 // flag read and the first page-table read are issued together; a skipped
 // sample discards the lookup.  kFast: bricks of 16^3 in a pool of less than
 // 4 GiB (compile-time brick offsets, 32-bit byte offsets into the pool) and
-// macro-cells of 16^3 voxels.
-template <bool kFast, class Flags>
+// macro-cells of 16^3 voxels.  kAdapt: the cell's code (Flags reads codes)
+// gives the sample's step exponent; a transparent cell's samples are skipped.
+template <bool kFast, bool kAdapt, class Flags>
 __device__ inline SampleRes sample_cache(const FrameDev& f, const FrameHot& h, const LodGeom* lg, const Flags& fl,
                                          const float p[3], SlotCache& sc) {
     constexpr int kB = kFast ? 16 : 0;
@@ -92,15 +103,23 @@ __device__ inline SampleRes sample_cache(const FrameDev& f, const FrameHot& h, c
     s.slot = -1;
     s.req_key = -1;
     s.value = 0.0f;
+    s.e = 0;
     bool live = true;
-    if (f.flags) {
+    if (kAdapt || f.flags) {
         uint32_t ci[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             ci[a] = kFast ? (uint32_t)(int32_t)p[a] >> 4 : fast_div((uint32_t)(int32_t)p[a], f.div_mc);
             if (ci[a] > (uint32_t)f.M[a] - 1u) ci[a] = (uint32_t)f.M[a] - 1u;
         }
-        live = fl.get((ci[2] * (uint32_t)f.M[1] + ci[1]) * (uint32_t)f.M[0] + ci[0]);
+        const uint32_t cell = (ci[2] * (uint32_t)f.M[1] + ci[1]) * (uint32_t)f.M[0] + ci[0];
+        if constexpr (kAdapt) {
+            const uint32_t code = fl.code(cell);
+            live = code != 0xFFu;
+            s.e = live ? (int32_t)code : f.adapt;
+        } else {
+            live = fl.get(cell);
+        }
     }
     if (f.mode != CINR_CACHED) {
         s.status = live ? S_MISS : S_SKIP;
@@ -337,6 +356,31 @@ __global__ __launch_bounds__(kBlock) void k_frame_begin(FrameDev f, int32_t n_ct
         const uint64_t word = __ballot(vis);
         if (lane_id() == 0) f.flags[t >> 6] = word;
     }
+    // adaptive sampling rate: each cell's code from the exact maximum opacity
+    // over its rows, through a sparse table (st[l][r]: rows r .. r + 2^l - 1)
+    if (f.adapt > 0) {
+        __shared__ float st[9][256];
+        st[0][threadIdx.x] = f.tf[4 * threadIdx.x + 3];
+        __syncthreads();
+        for (int l = 1; l < 9; ++l) {
+            const int r2 = (int)threadIdx.x + (1 << (l - 1));
+            st[l][threadIdx.x] = fmaxf(st[l - 1][threadIdx.x], st[l - 1][r2 < 256 ? r2 : 255]);
+            __syncthreads();
+        }
+        if (t < n_cells) {
+            const float a = minmax[2 * t] * 255.0f;
+            const float b = minmax[2 * t + 1] * 255.0f;
+            int32_t lo = (int32_t)__builtin_floorf(a), hi = (int32_t)__builtin_ceilf(b);
+            lo = lo < 0 ? 0 : lo;
+            hi = hi > 255 ? 255 : hi;
+            float mu = 0.0f;
+            if (lo <= hi) {
+                const int l = 31 - __builtin_clz((uint32_t)(hi - lo + 1));
+                mu = fmaxf(st[l][lo], st[l][hi - (1 << l) + 1]);
+            }
+            f.cell_code[t] = mu > 0.0f ? (uint8_t)step_exp(mu, f.adapt) : (uint8_t)0xFFu;
+        }
+    }
 }
 
 // Work units of one march launch, claimed by waves.  Units are cut into
@@ -384,21 +428,36 @@ struct UnitQueue {
 // samples together.  Every lane of a wave runs the same trips of the unit loop
 // so that list reservations can be made per wave.
 // (at least 4 waves per SIMD: the register budget is 128 VGPRs)
-template <int kPipe, bool kLdsFlags, bool kFast>
+// kAdapt: adaptive sampling rate (macro-cell codes instead of visibility
+// bits); a sample of step exponent e is followed by sample k + 2^e.
+template <int kPipe, bool kLdsFlags, bool kFast, bool kAdapt>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_march(FrameDev f, int32_t it, uint32_t n0) {
+    static_assert(!kAdapt || kPipe == 1, "the adaptive sampler decides one sample ahead at most");
     const FrameHot hot = load_hot(f.var);  // before any store of this kernel
     __shared__ float4 tfs[256];
     __shared__ LodGeom lgs[kMaxLods];
-    __shared__ uint64_t sflags[kLdsFlags ? kMaxLdsFlagWords : 1];
+    __shared__ uint64_t sflags[kLdsFlags ? (kAdapt ? kMaxLdsCells / 8 : kMaxLdsFlagWords) : 1];
     tfs[threadIdx.x] = reinterpret_cast<const float4*>(f.tf)[threadIdx.x];
     if (threadIdx.x < kMaxLods) lgs[threadIdx.x] = f.geo.lod[threadIdx.x];
-    if (kLdsFlags)
-        for (int32_t w = threadIdx.x; w < f.flag_words; w += kBlock) sflags[w] = f.flags[w];
+    if (kLdsFlags) {
+        if (kAdapt) {
+            const uint64_t* src = reinterpret_cast<const uint64_t*>(f.cell_code);
+            for (int32_t w = threadIdx.x; w < (f.n_cells + 7) / 8; w += kBlock) sflags[w] = src[w];
+        } else {
+            for (int32_t w = threadIdx.x; w < f.flag_words; w += kBlock) sflags[w] = f.flags[w];
+        }
+    }
     // the counters of the next iteration were last used two launches ago
     if (blockIdx.x == 0 && threadIdx.x < 8) f.claim[(((it + 1) & 1) * 8 + threadIdx.x) * kClaimStride] = 0u;
     __syncthreads();
-    using Flags = typename std::conditional<kLdsFlags, LdsFlags, GlobalFlags>::type;
-    const Flags fl{kLdsFlags ? (const uint64_t*)sflags : (const uint64_t*)f.flags};
+    using Flags = typename std::conditional<
+        kAdapt, typename std::conditional<kLdsFlags, LdsCodes, GlobalCodes>::type,
+        typename std::conditional<kLdsFlags, LdsFlags, GlobalFlags>::type>::type;
+    Flags fl;
+    if constexpr (kAdapt)
+        fl.c = kLdsFlags ? reinterpret_cast<const uint8_t*>(sflags) : f.cell_code;
+    else
+        fl.w = kLdsFlags ? (const uint64_t*)sflags : (const uint64_t*)f.flags;
 
     // iteration 0: all pixels in 8x8 tiles (unit = tile); later: the rays
     // re-queued by k_shade, 64 per unit
@@ -474,6 +533,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
         }
         RayBook book;
         bool pend = false;
+        int32_t e_miss = 0;  // step exponent of the sample that missed
         if (has) {
             // Fast phase, software-pipelined: decide and fetch a group of
             // kPipe samples, then commit them in order (bookkeeping,
@@ -487,7 +547,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
 #pragma unroll
                 for (int u = 0; u < kPipe; ++u) {
                     if (cnt == u && sample_pos(o, d, ts, te, f.step, k + u, f.vm1, p)) {
-                        grp[u] = sample_cache<kFast>(f, hot, lgs, fl, p, sc);
+                        grp[u] = sample_cache<kFast, kAdapt>(f, hot, lgs, fl, p, sc);
                         ++cnt;
                     }
                 }
@@ -501,10 +561,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
                     if (sr.status == S_MISS) {
                         pend = true;
                         run = false;
+                        e_miss = sr.e;
                         break;
                     }
-                    if (sr.status != S_SKIP) composite(acc, sr.value, tfs, f.step);
-                    ++k;
+                    if (sr.status != S_SKIP)
+                        composite(acc, sr.value, tfs, kAdapt ? __builtin_ldexpf(f.step, sr.e) : f.step);
+                    k += kAdapt ? (1 << sr.e) : 1;
                     if (f.ert_on && acc.w >= f.ert) {
                         run = false;
                         break;
@@ -521,18 +583,23 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
                 int32_t* pp = cold->pend_pix;
                 pp[pi] = pix;
                 float* vb = cold->vals + (int64_t)pi * S;
+                uint8_t* ve = f.vexp + (int64_t)pi * S;  // adaptive: each sample's step exponent
+                if (kAdapt) ve[0] = (uint8_t)e_miss;
                 mask = 1;
                 nc = 1;
+                int32_t kg = k + (kAdapt ? (1 << e_miss) : 1);  // grid index of the next sample
                 while (nc < S) {
                     float qp[3];
-                    if (!sample_pos(o, d, ts, te, f.step, k + nc, f.vm1, qp)) break;
-                    const SampleRes sr = sample_cache<kFast>(f, hot, lgs, fl, qp, sc);
+                    if (!sample_pos(o, d, ts, te, f.step, kg, f.vm1, qp)) break;
+                    const SampleRes sr = sample_cache<kFast, kAdapt>(f, hot, lgs, fl, qp, sc);
                     tally.add(sr.status);
                     book.note(f, hot.frame, cold, sr);
                     if (sr.status == S_MISS)
                         mask |= 1ull << nc;
                     else
                         vb[nc] = sr.status == S_SKIP ? -1.0f : sr.value;
+                    if (kAdapt) ve[nc] = (uint8_t)sr.e;
+                    kg += kAdapt ? (1 << sr.e) : 1;
                     ++nc;
                 }
                 int32_t* pn = cold->pend_n;
@@ -544,12 +611,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
             uint32_t mb = wave_reserve((uint32_t)__popcll(mask), cold->misses);
             if (pend) {
                 float4* mr = cold->miss_rec;
+                const uint8_t* ve = f.vexp + (int64_t)pi * S;
+                int32_t kg = k;  // grid index of gathered sample sidx
                 for (int32_t sidx = 0; sidx < nc; ++sidx) {
-                    if (!((mask >> sidx) & 1ull)) continue;
-                    float qp[3];
-                    sample_pos(o, d, ts, te, f.step, k + sidx, f.vm1, qp);
-                    mr[mb++] = make_float4(qp[0], qp[1], qp[2], __uint_as_float(pi * (uint32_t)S + (uint32_t)sidx));
-                    log_miss(cold, pix, k + sidx, qp);
+                    if ((mask >> sidx) & 1ull) {
+                        float qp[3];
+                        sample_pos(o, d, ts, te, f.step, kg, f.vm1, qp);
+                        mr[mb++] = make_float4(qp[0], qp[1], qp[2], __uint_as_float(pi * (uint32_t)S + (uint32_t)sidx));
+                        log_miss(cold, pix, kg, qp);
+                    }
+                    kg += kAdapt ? (1 << ve[sidx]) : 1;
                 }
             }
         }
@@ -576,17 +647,21 @@ __global__ __launch_bounds__(kBlock) void k_shade(FrameDev f, int32_t it) {
         int32_t k = f.k_next[pix];
         float4 acc = f.rgba[pix];
         const float* vb = f.vals + (int64_t)pi * S;
+        const uint8_t* ve = f.vexp + (int64_t)pi * S;
         bool done = false;
+        int32_t kg = k;  // grid index after the composited samples
         for (int32_t s = 0; s < nc; ++s) {
             const float v = vb[s];
-            if (v >= 0.0f) composite(acc, v, tfs, f.step);
+            const int32_t e = f.adapt > 0 ? (int32_t)ve[s] : 0;
+            if (v >= 0.0f) composite(acc, v, tfs, e ? __builtin_ldexpf(f.step, e) : f.step);
+            kg += 1 << e;
             if (f.ert_on && acc.w >= f.ert) {
                 done = true;
                 break;
             }
         }
         if (!done) {
-            k += nc;
+            k = kg;
             const int32_t i = pix % f.W, j = pix / f.W;
             float o[3], d[3], ts, te;
             ray_setup(cam, f.vm1, i, j, o, d, ts, te);
@@ -632,16 +707,17 @@ static int blocks_for(int64_t n, int64_t cap) {
 hipError_t launch_frame_begin(const FrameDev& f, int32_t n_iter_ctr, const float* minmax, int64_t n_cells,
                               CacheCtr* cctr, hipStream_t s) {
     int64_t n = n_iter_ctr;
-    if (f.flags && n_cells > n) n = n_cells;
+    const bool cells = f.flags || f.adapt > 0;
+    if (cells && n_cells > n) n = n_cells;
     if (n < ST_COUNT) n = ST_COUNT;
     hipLaunchKernelGGL(k_frame_begin, dim3(blocks_for(n, 1 << 20)), dim3(kBlock), 0, s, f, n_iter_ctr, minmax,
-                       f.flags ? n_cells : 0, cctr);
+                       cells ? n_cells : 0, cctr);
     return hipGetLastError();
 }
 
 // Workgroups of one k_march instantiation that are resident at once on the
 // current device (the grid of the persistent kernel), cached per device.
-template <int P, bool LDS, bool FAST>
+template <int P, bool LDS, bool FAST, bool A>
 static hipError_t resident_blocks(int* out) {
     static int cache[64] = {0};
     int dev = 0;
@@ -650,7 +726,7 @@ static hipError_t resident_blocks(int* out) {
     if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
     if (cache[dev] == 0) {
         int per_cu = 0, n_cu = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_march<P, LDS, FAST>, kBlock, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_march<P, LDS, FAST, A>, kBlock, 0);
         if (e != hipSuccess) return e;
         e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess) return e;
@@ -660,34 +736,36 @@ static hipError_t resident_blocks(int* out) {
     return hipSuccess;
 }
 
-template <int P, bool LDS, bool FAST>
+template <int P, bool LDS, bool FAST, bool A>
 static hipError_t launch_march_t(const FrameDev& f, int it, int64_t max_rays, uint32_t n0, hipStream_t s) {
     int cap = 0;
-    hipError_t e = resident_blocks<P, LDS, FAST>(&cap);
+    hipError_t e = resident_blocks<P, LDS, FAST, A>(&cap);
     if (e != hipSuccess) return e;
     // one work unit (64 rays) per wave at least
     int64_t b = (max_rays + kBlock - 1) / kBlock;
     if (b < 1) b = 1;
     if (b > cap) b = cap;
-    hipLaunchKernelGGL((k_march<P, LDS, FAST>), dim3((unsigned)b), dim3(kBlock), 0, s, f, it, n0);
+    hipLaunchKernelGGL((k_march<P, LDS, FAST, A>), dim3((unsigned)b), dim3(kBlock), 0, s, f, it, n0);
     return hipGetLastError();
 }
 
-template <int P, bool LDS>
+template <int P, bool LDS, bool A>
 static hipError_t launch_march_l(const FrameDev& f, int it, int64_t max_rays, uint32_t n0, hipStream_t s) {
     // 16^3 bricks in a pool of less than 4 GiB (or the uncached mode, which
     // reads no pool) and 16^3 macro-cells (or none)
+    const bool cells = A || f.flags;
     const bool fast = (f.mode != CINR_CACHED ||
                        (f.geo.brick == 16 && (uint64_t)f.pool_bricks * 16384ull < (1ull << 32))) &&
-                      (!f.flags || f.mc_N == 16);
-    if (fast) return launch_march_t<P, LDS, true>(f, it, max_rays, n0, s);
-    return launch_march_t<P, LDS, false>(f, it, max_rays, n0, s);
+                      (!cells || f.mc_N == 16);
+    if (fast) return launch_march_t<P, LDS, true, A>(f, it, max_rays, n0, s);
+    return launch_march_t<P, LDS, false, A>(f, it, max_rays, n0, s);
 }
 
-template <int P>
+template <int P, bool A>
 static hipError_t launch_march_p(const FrameDev& f, int it, int64_t max_rays, uint32_t n0, hipStream_t s) {
-    if (f.flags && f.flag_words <= kMaxLdsFlagWords) return launch_march_l<P, true>(f, it, max_rays, n0, s);
-    return launch_march_l<P, false>(f, it, max_rays, n0, s);
+    const bool lds = A ? f.n_cells <= kMaxLdsCells : (f.flags && f.flag_words <= kMaxLdsFlagWords);
+    if (lds) return launch_march_l<P, true, A>(f, it, max_rays, n0, s);
+    return launch_march_l<P, false, A>(f, it, max_rays, n0, s);
 }
 
 hipError_t launch_march(const FrameDev& f, int it, int64_t max_rays, hipStream_t s) {
@@ -695,11 +773,13 @@ hipError_t launch_march(const FrameDev& f, int it, int64_t max_rays, hipStream_t
     // `max_rays` re-queued rays
     const uint32_t n0 = (uint32_t)(((f.W + 7) / 8) * ((f.H + 7) / 8)) * 64u;
     const int64_t n = it == 0 ? (int64_t)n0 : max_rays;
+    // the adaptive sampler decides its next sample after the current one
+    if (f.adapt > 0) return launch_march_p<1, true>(f, it, n, n0, s);
     // kPipe: samples decided and fetched ahead per ray (8 runs as 4)
     switch (f.pipe) {
-        case 1: return launch_march_p<1>(f, it, n, n0, s);
-        case 2: return launch_march_p<2>(f, it, n, n0, s);
-        default: return launch_march_p<4>(f, it, n, n0, s);
+        case 1: return launch_march_p<1, false>(f, it, n, n0, s);
+        case 2: return launch_march_p<2, false>(f, it, n, n0, s);
+        default: return launch_march_p<4, false>(f, it, n, n0, s);
     }
 }
 
