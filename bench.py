@@ -463,6 +463,45 @@ def main():
     log(f"[bench] captured frames {args.dtype}: {fps_graph:.1f} fps; image equal to eager: {graph_same}; "
         f"counts {graph_counts}")
 
+    # --- adaptive sampling rate (Section 5.2) ----------------------------------
+    # the same orbit with the TFs' opacity scaled by 0.1 (a semi-transparent
+    # rendering, where the macro-cells' maximum opacities are low), fixed step
+    # (E = 0) against steps of up to 2^E grid samples
+    tfs_low = []
+    for t in tfs:
+        t2 = t.clone()
+        t2[:, 3] *= 0.1
+        tfs_low.append(t2)
+    adaptive = {}
+    ref_low = None
+    for E in (0, 1, 2, 3):
+        c3 = new_cache(vol, w)
+        r3 = cinr.Renderer()
+        out3 = torch.empty_like(out)
+        st3 = torch.zeros((K, len(cinr.STAT_FIELDS)), dtype=torch.int64, device="cuda")
+
+        def adaptive_frames(frames, stats=None):
+            for i, f in enumerate(frames):
+                r3.render(vol, cams[f % w.n_frames], tfs_low[f % w.n_frames], w.step, w.lod_scale, frame_index=f,
+                          seed=w.seed, ert_threshold=w.ert_threshold, samples_per_iter=w.samples_per_iter,
+                          mode=cinr.CACHED, dtype=args.dtype, cache=c3, out=out3,
+                          stats=None if stats is None else stats[i], adapt_max_exp=E)
+
+        adaptive_frames(range(Wm))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        adaptive_frames(range(Wm, Wm + K), st3)
+        torch.cuda.synchronize()
+        fps_e = K / (time.perf_counter() - t0)
+        img = out3.cpu().numpy()
+        if E == 0:
+            ref_low = img
+        adaptive[f"E{E}"] = {"fps": round(fps_e, 2),
+                             "samples_per_frame": int(st3[:, cinr.STAT_FIELDS.index("samples")].sum()) // K,
+                             "psnr_vs_fixed_step_db": round(psnr(ref_low, img), 2)}
+        del c3
+    log(f"[bench] adaptive sampling rate (TF opacity x 0.1): {adaptive}")
+
     # --- uncached FP32 INR renderer on the same frames ------------------------
     KU = args.uncached_steps or K
     r2 = cinr.Renderer()
@@ -545,6 +584,7 @@ def main():
                           "bf16": "BF16 MFMA, FP32 accumulation", "f16": "FP16 MFMA, FP32 accumulation",
                           "f32": "FP32 MFMA"}.get(args.dtype, args.dtype),
         "cached_other_precisions": other,
+        "adaptive_sampling": {"tf": "the orbit's TFs with opacity x 0.1", "by_max_exponent": adaptive},
         "bricks_per_s": {k: round(v, 1) for k, v in bps.items()},
         "psnr_cached_vs_uncached_db": round(q_unc, 2),
         "stage_ms_per_frame": {k: round(v[0] / K, 4) for k, v in all_stages.items()},
