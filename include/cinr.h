@@ -111,7 +111,7 @@ typedef struct {
  *                share one sample per face, so a LoD-L brick spans
  *                (B-1)*2^L voxels (Section 4.3.2).
  *  n_lods        LoDs 0..n_lods-1 (<= 16).
- *  pool_bricks   brick slots in the pool (f32, B^3 values each).
+ *  pool_bricks   brick slots in the pool (B^3 values each, of pool_dtype).
  *  max_requests  bricks requested and decoded per frame (maxNumRequests,
  *                at most 256).
  *  rank_window   ranks are clamped to timestamp + rank_window (1000).
@@ -122,7 +122,11 @@ typedef struct {
  *  miss_log_capacity   true-miss records kept per frame for dumps (0 = off).
  *  evict_log_capacity  insertion/eviction records kept for dumps.
  *  keep_request_counts nonzero: keep each frame's per-brick request counts
- *                for CINR_DUMP_REQ_COUNT. */
+ *                for CINR_DUMP_REQ_COUNT.
+ *  pool_dtype    CINR_F32 (0) or CINR_F16: binary16 brick values (decoded
+ *                values rounded to nearest, ties to even), half the pool
+ *                memory; the sampler interpolates them in FP32 (a reduced-
+ *                precision pool, the paper's future work, Sec. 7). */
 typedef struct {
     int32_t brick, n_lods, pool_bricks, max_requests, rank_window;
     int32_t ranking;
@@ -130,6 +134,7 @@ typedef struct {
     int32_t miss_log_capacity;
     int32_t evict_log_capacity;
     int32_t keep_request_counts;
+    int32_t pool_dtype;
 } cinr_cache_desc;
 
 /* Pinhole or orthographic camera.  Basis vectors are unit length; pixel
@@ -201,7 +206,7 @@ typedef enum {
     CINR_DUMP_REQUEST_LIST = 5, /* int32 [n]: keys selected at the end of the last frame, in order */
     CINR_DUMP_MISS_LIST = 6,    /* {int32 pixel, int32 k, float x, y, z} [n] of the last frame, sorted by (pixel, k) */
     CINR_DUMP_EVICTION_LOG = 7, /* {int32 stamp, slot, old_key, new_key} [n] since creation */
-    CINR_DUMP_POOL = 8          /* float [pool_bricks][B][B][B] */
+    CINR_DUMP_POOL = 8          /* pool_dtype values [pool_bricks][B][B][B]: float, or binary16 bits */
 } cinr_dump_kind;
 
 typedef struct cinr_volume_s* cinr_volume;
@@ -260,7 +265,7 @@ cinr_status cinr_cache_workspace_size(cinr_volume vol, const cinr_cache_desc* de
 /* Creates a cache over a caller-provided pool (f32, >= pool_bricks*B^3
  * values) and workspace; initialises the workspace on `stream` (all bricks
  * unmapped, all slots free). */
-cinr_status cinr_create_cache(cinr_volume vol, const cinr_cache_desc* desc, float* d_pool, size_t pool_bytes,
+cinr_status cinr_create_cache(cinr_volume vol, const cinr_cache_desc* desc, void* d_pool, size_t pool_bytes,
                               void* d_workspace, size_t ws_bytes, void* stream, cinr_cache* out);
 void cinr_destroy_cache(cinr_cache cache);
 
@@ -320,7 +325,7 @@ cinr_status cinr_collect_timing(cinr_volume vol, double* ms, int64_t* launches);
 cinr_status cinr_cache_workspace_size_multi(const cinr_volume* vols, int32_t n_vols, const cinr_cache_desc* desc,
                                             size_t* bytes);
 cinr_status cinr_create_cache_multi(const cinr_volume* vols, int32_t n_vols, const cinr_cache_desc* desc,
-                                    float* d_pool, size_t pool_bytes, void* d_workspace, size_t ws_bytes,
+                                    void* d_pool, size_t pool_bytes, void* d_workspace, size_t ws_bytes,
                                     void* stream, cinr_cache* out);
 
 /* One view of a multi-view frame. */

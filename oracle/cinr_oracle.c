@@ -749,7 +749,22 @@ static void insert_brick(orc_cache* c, int32_t key, int32_t stamp, uint8_t* fill
     e[3] = key;
 }
 
-/* Pre-loading into free slots only (never evicts). */
+double orc_round_half(double x) {
+    if (x == 0.0 || isnan(x) || isinf(x)) return x;
+    const double a = fabs(x);
+    int e2;
+    frexp(a, &e2);                       /* a = f 2^e2, f in [0.5, 1): the leading bit has weight 2^(e2-1) */
+    int lead = e2 - 1;
+    if (lead < -14) lead = -14;          /* below the normal range the spacing stays 2^-24 */
+    const double quantum = ldexp(1.0, lead - 10);
+    double q = a / quantum;              /* exact: a division by a power of two */
+    const double fl = floor(q), rem = q - fl;
+    q = rem > 0.5 ? fl + 1.0 : rem < 0.5 ? fl : (fmod(fl, 2.0) == 0.0 ? fl : fl + 1.0);
+    const double r = q * quantum;
+    if (r > 65504.0) return x > 0 ? INFINITY : -INFINITY;
+    return x > 0 ? r : -r;
+}
+
 /* Decodes the bricks just inserted (key -> slot) into their pool slots. */
 static void decode_inserted(orc_cache* c, const int32_t* keys, const int32_t* slots, int64_t n) {
     const int64_t B3 = (int64_t)c->d.brick * c->d.brick * c->d.brick;
@@ -763,10 +778,14 @@ static void decode_inserted(orc_cache* c, const int32_t* keys, const int32_t* sl
         const int64_t local = key - c->g[L].off;
         const int32_t b[3] = {(int32_t)(local % c->g[L].nb[0]), (int32_t)((local / c->g[L].nb[0]) % c->g[L].nb[1]),
                               (int32_t)(local / ((int64_t)c->g[L].nb[0] * c->g[L].nb[1]))};
-        decode_brick(&c->inrs[vol], L, b, c->d.brick, c->pool + (int64_t)slots[i] * B3);
+        double* dst = c->pool + (int64_t)slots[i] * B3;
+        decode_brick(&c->inrs[vol], L, b, c->d.brick, dst);
+        if (c->d.pool_f16)
+            for (int64_t v = 0; v < B3; ++v) dst[v] = orc_round_half(dst[v]);
     }
 }
 
+/* Pre-loading into free slots only (never evicts). */
 int orc_cache_prefill(orc_cache* c, const int32_t* keys, int64_t n, int32_t stamp) {
     int64_t n_free = 0;
     for (int32_t s = 0; s < c->d.pool_bricks; ++s) n_free += c->owner[s] < 0;

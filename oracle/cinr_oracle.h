@@ -78,6 +78,8 @@ typedef struct {
     int32_t rank_window;  /* ranking clamp above the timestamp (1000) */
     int32_t ranking;      /* 0 = key order of this frame's requests, 1 = priority rank */
     int32_t preload_period; /* frames per LoD step of the coarse-LoD pre-load; 0 = off */
+    int32_t pool_f16;     /* nonzero: inserted brick values are rounded to binary16 (a reduced-precision
+                             pool, Section 7's future work); 0 = values kept as decoded */
 } orc_cache_desc;
 
 typedef struct {
@@ -135,6 +137,11 @@ int orc_render_pixels(const orc_inr* m, orc_cache* c, const orc_camera* cam, con
 
 /* --- cached renderer --- */
 orc_cache* orc_cache_create(const orc_inr* m, const orc_cache_desc* d);
+
+/* x rounded to the nearest IEEE 754 binary16 value, ties to even (11-bit
+ * significand, normal exponents -14..15, subnormal quantum 2^-24), returned
+ * as a double; magnitudes that round above 65504 give +-infinity. */
+double orc_round_half(double x);
 /* A cache shared by n_vols volumes of equal dimensions (ms: array of
  * descriptors); volume v owns keys [v K, (v + 1) K), K = keys of one volume. */
 orc_cache* orc_cache_create_multi(const orc_inr* ms, int32_t n_vols, const orc_cache_desc* d);

@@ -45,7 +45,7 @@ class Params(C.Structure):
 class CacheDesc(C.Structure):
     _fields_ = [("brick", C.c_int32), ("n_lods", C.c_int32), ("pool_bricks", C.c_int32),
                 ("max_requests", C.c_int32), ("rank_window", C.c_int32), ("ranking", C.c_int32),
-                ("preload_period", C.c_int32)]
+                ("preload_period", C.c_int32), ("pool_f16", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -84,6 +84,7 @@ def lib():
             "orc_macrocells": (None, [P, i32, P]),
             "orc_macrocell_flags": (None, [P, i64, P, P]),
             "orc_step_exp": (i32, [C.c_float, i32]),
+            "orc_round_half": (C.c_double, [C.c_double]),
             "orc_macrocell_step_codes": (None, [P, i64, P, i32, P]),
             "orc_ray_setup": (C.c_int, [P, P, i32, i32, P, P, P, P]),
             "orc_select_lod": (i32, [P, P, C.c_float, u32, i32, i32]),
@@ -289,6 +290,11 @@ def macrocell_flags(minmax, tf):
     return out
 
 
+def round_half(x):
+    """x rounded to the nearest binary16 value, ties to even (IEEE 754)."""
+    return float(lib().orc_round_half(float(x)))
+
+
 def step_exp(mu, E):
     """Step exponent of a macro-cell of maximum opacity mu > 0 (adaptive sampling)."""
     return int(lib().orc_step_exp(float(mu), int(E)))
@@ -354,13 +360,14 @@ class OracleCache:
     equal dimensions (volume i owns keys [i K, (i+1) K))."""
 
     def __init__(self, inr, brick, n_lods, pool_bricks, max_requests, rank_window=1000, ranking=1,
-                 preload_period=0, log_misses=False, trace_ert=False):
+                 preload_period=0, log_misses=False, trace_ert=False, pool_f16=False):
         inrs = list(inr) if isinstance(inr, (list, tuple)) else [inr]
         self.inrs = inrs
         self.inr = inrs[0]
         d = CacheDesc()
         d.brick, d.n_lods, d.pool_bricks, d.max_requests = brick, n_lods, pool_bricks, max_requests
         d.rank_window, d.ranking, d.preload_period = rank_window, ranking, preload_period
+        d.pool_f16 = 1 if pool_f16 else 0
         self.desc = d
         self._descs = (Inr * len(inrs))(*[m.desc for m in inrs])
         self.h = lib().orc_cache_create_multi(C.cast(self._descs, C.c_void_p), len(inrs), C.byref(d))

@@ -42,7 +42,7 @@ class VolumeDesc(C.Structure):
 class CacheDesc(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("brick", "n_lods", "pool_bricks", "max_requests", "rank_window", "ranking",
                                           "preload_period", "miss_log_capacity", "evict_log_capacity",
-                                          "keep_request_counts")]
+                                          "keep_request_counts", "pool_dtype")]
 
 
 class CameraDesc(C.Structure):
@@ -264,7 +264,7 @@ class Cache:
 
     def __init__(self, volume, brick, n_lods, pool_bricks, max_requests, rank_window=1000,
                  ranking=RANK_PRIORITY, preload_period=0, miss_log_capacity=0, evict_log_capacity=4096,
-                 keep_request_counts=False):
+                 keep_request_counts=False, pool_dtype="f32"):
         vols = list(volume) if isinstance(volume, (list, tuple)) else [volume]
         self.volumes = vols
         volume = vols[0]
@@ -274,15 +274,21 @@ class Cache:
         d.rank_window, d.ranking, d.preload_period = rank_window, ranking, preload_period
         d.miss_log_capacity, d.evict_log_capacity = miss_log_capacity, evict_log_capacity
         d.keep_request_counts = 1 if keep_request_counts else 0
+        if pool_dtype not in ("f32", "f16"):
+            raise ValueError(f"pool_dtype {pool_dtype!r}: 'f32' or 'f16'")
+        d.pool_dtype = _dtype(pool_dtype)
+        self.pool_dtype = pool_dtype
         self.desc = d
         ws = C.c_size_t()
         hs = (C.c_void_p * len(vols))(*[v.h.value for v in vols])
         _check(lib().cinr_cache_workspace_size_multi(hs, len(vols), C.byref(d), C.byref(ws)))
         dev = volume.device
-        self.pool = torch.empty(max(pool_bricks, 1) * brick ** 3, dtype=torch.float32, device=dev)
+        tdt = torch.float16 if pool_dtype == "f16" else torch.float32
+        self.pool = torch.empty(max(pool_bricks, 1) * brick ** 3, dtype=tdt, device=dev)
         self.workspace = torch.empty(ws.value, dtype=torch.uint8, device=dev)
         h = C.c_void_p()
-        _check(lib().cinr_create_cache_multi(hs, len(vols), C.byref(d), _ptr(self.pool), self.pool.numel() * 4,
+        _check(lib().cinr_create_cache_multi(hs, len(vols), C.byref(d), _ptr(self.pool),
+                                             self.pool.numel() * self.pool.element_size(),
                                              _ptr(self.workspace), ws.value, _stream(), C.byref(h)))
         self.h = h
         nb, off = volume.geometry(brick, n_lods)
@@ -321,7 +327,7 @@ class Cache:
             return buf.view(np.int32).reshape(-1, 4)
         if kind == DUMP_POOL:
             B = self.desc.brick
-            return buf.view(np.float32).reshape(-1, B, B, B)
+            return buf.view(np.float16 if self.pool_dtype == "f16" else np.float32).reshape(-1, B, B, B)
         return buf
 
 

@@ -361,7 +361,7 @@ extern "C" cinr_status cinr_decode_bricks(cinr_volume v, const int32_t* d_reqs, 
     if (st) return st;
     CacheGeom g;
     geometry(v->desc.dims, brick, kMaxLods, g);
-    HIP_TRY(inr_decode_bricks(v->m, g, d_reqs, nullptr, nullptr, n, nullptr, d_out, prec, (hipStream_t)stream));
+    HIP_TRY(inr_decode_bricks(v->m, g, d_reqs, nullptr, nullptr, n, nullptr, d_out, 0, prec, (hipStream_t)stream));
     return CINR_OK;
 }
 
@@ -397,6 +397,8 @@ static cinr_status check_cache_desc(const cinr_volume* vols, int32_t n_vols, con
         return fail(CINR_INVALID_ARG, "pool_bricks >= 0 and 0 <= max_requests <= %d required", kMaxRequests);
     if (d->rank_window < 0) return fail(CINR_INVALID_ARG, "rank_window < 0");
     if (d->miss_log_capacity < 0 || d->evict_log_capacity < 0) return fail(CINR_INVALID_ARG, "negative log capacity");
+    if (d->pool_dtype != CINR_F32 && d->pool_dtype != CINR_F16)
+        return fail(CINR_INVALID_ARG, "pool_dtype = %d (CINR_F32 or CINR_F16)", d->pool_dtype);
     if (!geometry(vols[0]->desc.dims, d->brick, d->n_lods, g)) return fail(CINR_INVALID_ARG, "invalid geometry");
     g.n_vols = n_vols;
     g.n_keys = g.keys_per_vol * n_vols;
@@ -468,7 +470,7 @@ extern "C" cinr_status cinr_cache_workspace_size(cinr_volume v, const cinr_cache
 }
 
 extern "C" cinr_status cinr_create_cache_multi(const cinr_volume* vols, int32_t n_vols, const cinr_cache_desc* d,
-                                               float* d_pool, size_t pool_bytes, void* d_ws, size_t ws_bytes,
+                                               void* d_pool, size_t pool_bytes, void* d_ws, size_t ws_bytes,
                                                void* stream, cinr_cache* out) {
     if (!out) return fail(CINR_INVALID_ARG, "null out");
     *out = nullptr;
@@ -476,8 +478,9 @@ extern "C" cinr_status cinr_create_cache_multi(const cinr_volume* vols, int32_t 
     cinr_status st = check_cache_desc(vols, n_vols, d, g);
     if (st) return st;
     const size_t B3 = (size_t)d->brick * d->brick * d->brick;
-    if (pool_bytes < (size_t)d->pool_bricks * B3 * sizeof(float))
-        return fail(CINR_OUT_OF_MEMORY, "pool of %zu bytes < %zu needed", pool_bytes, (size_t)d->pool_bricks * B3 * 4);
+    const size_t elem = d->pool_dtype == CINR_F16 ? 2 : 4;
+    if (pool_bytes < (size_t)d->pool_bricks * B3 * elem)
+        return fail(CINR_OUT_OF_MEMORY, "pool of %zu bytes < %zu needed", pool_bytes, (size_t)d->pool_bricks * B3 * elem);
     if (d->pool_bricks > 0 && !d_pool) return fail(CINR_INVALID_ARG, "null pool");
     InrDev* unused = nullptr;
     const size_t need = cache_layout(d, g, nullptr, nullptr, nullptr, nullptr, &unused);
@@ -488,6 +491,7 @@ extern "C" cinr_status cinr_create_cache_multi(const cinr_volume* vols, int32_t 
     c->g = g;
     cache_layout(d, g, &c->c, &c->plan_sel, &c->plan_vic, d_ws, &c->d_vols);
     c->c.pool = d_pool;
+    c->c.pool_f16 = d->pool_dtype == CINR_F16 ? 1 : 0;
     c->lim = std::max(1, std::min(d->max_requests, d->pool_bricks));
     c->used_bound = 0;
     hipStream_t s = (hipStream_t)stream;
@@ -504,7 +508,7 @@ extern "C" cinr_status cinr_create_cache_multi(const cinr_volume* vols, int32_t 
     return CINR_OK;
 }
 
-extern "C" cinr_status cinr_create_cache(cinr_volume v, const cinr_cache_desc* d, float* d_pool, size_t pool_bytes,
+extern "C" cinr_status cinr_create_cache(cinr_volume v, const cinr_cache_desc* d, void* d_pool, size_t pool_bytes,
                                          void* d_ws, size_t ws_bytes, void* stream, cinr_cache* out) {
     return cinr_create_cache_multi(&v, 1, d, d_pool, pool_bytes, d_ws, ws_bytes, stream, out);
 }
@@ -515,9 +519,9 @@ static hipError_t decode_selected(cinr_cache c, int32_t n_cap, int32_t prec, con
     const CacheDev& cd = c->c;
     if (c->vols.size() == 1)
         return inr_decode_bricks(c->vols[0]->m, c->g, cd.ins_reqs, &cd.ctr->n_sel, gate, n_cap, cd.ins_slots, cd.pool,
-                                 prec, s);
+                                 cd.pool_f16, prec, s);
     return inr_decode_bricks_multi(c->d_vols, c->vols[0]->m, c->g, cd.ins_reqs, cd.ins_vols, &cd.ctr->n_sel, gate,
-                                   n_cap, cd.ins_slots, cd.pool, prec, s);
+                                   n_cap, cd.ins_slots, cd.pool, cd.pool_f16, prec, s);
 }
 
 extern "C" void cinr_destroy_cache(cinr_cache c) { delete c; }
@@ -764,6 +768,7 @@ cinr_status prepare_view(cinr_cache c, cinr_volume v, const cinr_camera* cam, co
         f.touched = c->c.touched;
         f.n_touched = &c->c.ctr->n_touched;
         f.pool = c->c.pool;
+        f.pool_f16 = c->c.pool_f16;
         f.pool_bricks = c->c.pool_bricks;
         f.misslog = c->c.misslog;
         f.n_misslog = &c->c.ctr->n_misslog;
@@ -1357,7 +1362,7 @@ extern "C" cinr_status cinr_cache_dump(cinr_cache c, int32_t kind, void* dst, si
             n = m * 16;
             break;
         }
-        case CINR_DUMP_POOL: src = cd.pool; n = P * B3 * 4; break;
+        case CINR_DUMP_POOL: src = cd.pool; n = P * B3 * (cd.pool_f16 ? 2 : 4); break;
         default: return fail(CINR_INVALID_ARG, "dump kind %d", kind);
     }
     *needed = n;

@@ -1,6 +1,7 @@
 // Internal definitions shared by the HIP sources of libcinr (gfx950 only).
 #pragma once
 
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 

@@ -59,7 +59,7 @@ struct CacheDev {
     uint64_t* cand;
     int32_t* owner;
     int32_t* last_used;
-    float* pool;
+    void* pool;           // f32 or f16 values (pool_f16)
     int32_t* ins_keys;    // [ins_cap]
     int32_t* ins_slots;   // [ins_cap]
     int32_t* ins_reqs;    // [ins_cap][4]
@@ -74,6 +74,7 @@ struct CacheDev {
     CacheCtr* ctr;
     ViewEnd* views;       // [kMaxFrameViews]
     int32_t pool_bricks, max_requests, rank_window, ranking, ins_cap;
+    int32_t pool_f16;
 };
 
 // Values of a view that change from one frame to the next while its launch
@@ -127,7 +128,8 @@ struct FrameDev {
     uint32_t* req;
     int32_t* touched;
     uint32_t* n_touched;
-    const float* pool;
+    const void* pool;
+    int32_t pool_f16;  // binary16 brick values
     int32_t pool_bricks;
     MissLogRec* misslog;
     uint32_t* n_misslog;
@@ -251,8 +253,8 @@ bool inr_shape_supported(const InrDev& m);
 hipError_t inr_infer_points(const InrDev& m, const float* pos, int64_t n, float* out, int prec, hipStream_t s);
 // gate: nullable, as for the frame-end launches (no brick is decoded unless *gate != 0)
 hipError_t inr_decode_bricks(const InrDev& m, const CacheGeom& g, const int32_t* reqs, const uint32_t* n_dev,
-                             const uint32_t* gate, int32_t n_cap, const int32_t* slots, float* out, int prec,
-                             hipStream_t s);
+                             const uint32_t* gate, int32_t n_cap, const int32_t* slots, void* out, int out_f16,
+                             int prec, hipStream_t s);
 hipError_t inr_macrocells(const InrDev& m, int32_t N, float* minmax, int prec, hipStream_t s);
 hipError_t inr_infer_misses(const InrDev& m, const float4* rec, const uint32_t* n_dev, int64_t cap, float* vals,
                             int prec, hipStream_t s);
@@ -260,8 +262,7 @@ hipError_t inr_infer_misses(const InrDev& m, const float4* rec, const uint32_t* 
 // descriptors, `shape` any of them on the host)
 hipError_t inr_decode_bricks_multi(const InrDev* d_vols, const InrDev& shape, const CacheGeom& g, const int32_t* reqs,
                                    const int32_t* vols, const uint32_t* n_dev, const uint32_t* gate, int32_t n_cap,
-                                   const int32_t* slots,
-                                   float* out, int prec, hipStream_t s);
+                                   const int32_t* slots, void* out, int out_f16, int prec, hipStream_t s);
 
 // train.hip launchers
 bool train_shape_supported(const InrDev& m);

@@ -81,14 +81,19 @@ struct BrickSrc {
 };
 
 struct BrickDst {
-    float* out;
+    void* out;             // f32, or f16 values rounded to nearest even (f16)
     const int32_t* slots;  // nullable: brick r goes to slot slots[r] (skipped if negative), else to r
     int32_t B3;
+    int32_t f16;
     __device__ void store(int64_t idx, float v) const {
         const int32_t r = (int32_t)(idx / B3);
         const int32_t i = (int32_t)(idx - (int64_t)r * B3);
         const int64_t s = slots ? (int64_t)slots[r] : (int64_t)r;
-        if (s >= 0) out[s * B3 + i] = v;
+        if (s < 0) return;
+        if (f16)
+            static_cast<__half*>(out)[s * B3 + i] = __float2half_rn(v);
+        else
+            static_cast<float*>(out)[s * B3 + i] = v;
     }
 };
 
@@ -338,8 +343,8 @@ hipError_t inr_infer_points(const InrDev& m, const float* pos, int64_t n, float*
 }
 
 hipError_t inr_decode_bricks(const InrDev& m, const CacheGeom& g, const int32_t* reqs, const uint32_t* n_dev,
-                             const uint32_t* gate, int32_t n_cap, const int32_t* slots, float* out, int prec,
-                             hipStream_t s) {
+                             const uint32_t* gate, int32_t n_cap, const int32_t* slots, void* out, int out_f16,
+                             int prec, hipStream_t s) {
     if (n_cap <= 0) return hipSuccess;
     BrickSrc src;
     src.reqs = reqs;
@@ -352,14 +357,14 @@ hipError_t inr_decode_bricks(const InrDev& m, const CacheGeom& g, const int32_t*
     for (int L = 0; L < kMaxLods; ++L)
         for (int a = 0; a < 3; ++a) src.nb[L][a] = L < g.n_lods ? g.lod[L].nb[a] : 0;
     for (int a = 0; a < 3; ++a) src.dims[a] = m.dims[a];
-    BrickDst dst{out, slots, src.B3};
+    BrickDst dst{out, slots, src.B3, out_f16};
     const void* a[2] = {&src, &dst};
     return dispatch(prec, 1, m, a, s);
 }
 
 hipError_t inr_decode_bricks_multi(const InrDev* d_vols, const InrDev& shape, const CacheGeom& g, const int32_t* reqs,
                                    const int32_t* vols, const uint32_t* n_dev, const uint32_t* gate, int32_t n_cap,
-                                   const int32_t* slots, float* out, int prec, hipStream_t s) {
+                                   const int32_t* slots, void* out, int out_f16, int prec, hipStream_t s) {
     if (n_cap <= 0) return hipSuccess;
     BrickSrc src;
     src.reqs = reqs;
@@ -372,7 +377,7 @@ hipError_t inr_decode_bricks_multi(const InrDev* d_vols, const InrDev& shape, co
     for (int L = 0; L < kMaxLods; ++L)
         for (int a = 0; a < 3; ++a) src.nb[L][a] = L < g.n_lods ? g.lod[L].nb[a] : 0;
     for (int a = 0; a < 3; ++a) src.dims[a] = shape.dims[a];
-    BrickDst dst{out, slots, src.B3};
+    BrickDst dst{out, slots, src.B3, out_f16};
     const void* a[4] = {&src, &dst, d_vols, vols};
     return dispatch(prec, 4, shape, a, s);
 }

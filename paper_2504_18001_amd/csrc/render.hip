@@ -95,7 +95,11 @@ __device__ inline FrameHot load_hot(const FrameVar* v) {
 // 4 GiB (compile-time brick offsets, 32-bit byte offsets into the pool) and
 // macro-cells of 16^3 voxels.  kAdapt: the cell's code (Flags reads codes)
 // gives the sample's step exponent; a transparent cell's samples are skipped.
-template <bool kFast, bool kAdapt, class Flags>
+// kHalf: binary16 pool values, interpolated in FP32.
+__device__ inline float pool_value(float x) { return x; }
+__device__ inline float pool_value(__half x) { return __half2float(x); }
+
+template <bool kFast, bool kAdapt, bool kHalf, class Flags>
 __device__ inline SampleRes sample_cache(const FrameDev& f, const FrameHot& h, const LodGeom* lg, const Flags& fl,
                                          const float p[3], SlotCache& sc) {
     constexpr int kB = kFast ? 16 : 0;
@@ -139,17 +143,22 @@ __device__ inline SampleRes sample_cache(const FrameDev& f, const FrameHot& h, c
             return s;
         }
         if (slot < 0) continue;
-        const float* br;
+        using T = typename std::conditional<kHalf, __half, float>::type;
+        const T* br;
         if (kFast) {
             const uint32_t off = (((uint32_t)slot * (uint32_t)(kB * kB * kB) +
-                                   ((uint32_t)a.lj[2] * kB + (uint32_t)a.lj[1]) * kB + (uint32_t)a.lj[0])) * 4u;
-            br = reinterpret_cast<const float*>(reinterpret_cast<const char*>(f.pool) + off);
+                                   ((uint32_t)a.lj[2] * kB + (uint32_t)a.lj[1]) * kB + (uint32_t)a.lj[0])) *
+                                 (uint32_t)sizeof(T);
+            br = reinterpret_cast<const T*>(reinterpret_cast<const char*>(f.pool) + off);
         } else {
-            br = f.pool + (int64_t)slot * (B * B * B) + ((int64_t)a.lj[2] * B + a.lj[1]) * B + a.lj[0];
+            br = static_cast<const T*>(f.pool) + (int64_t)slot * (B * B * B) + ((int64_t)a.lj[2] * B + a.lj[1]) * B +
+                 a.lj[0];
         }
         const int32_t B2 = B * B;
-        const float c000 = br[0], c100 = br[1], c010 = br[B], c110 = br[B + 1];
-        const float c001 = br[B2], c101 = br[B2 + 1], c011 = br[B2 + B], c111 = br[B2 + B + 1];
+        const float c000 = pool_value(br[0]), c100 = pool_value(br[1]), c010 = pool_value(br[B]),
+                    c110 = pool_value(br[B + 1]);
+        const float c001 = pool_value(br[B2]), c101 = pool_value(br[B2 + 1]), c011 = pool_value(br[B2 + B]),
+                    c111 = pool_value(br[B2 + B + 1]);
         const float fx = a.frac[0], fy = a.frac[1], fz = a.frac[2];
         const float x00 = __builtin_fmaf(fx, c100 - c000, c000);
         const float x10 = __builtin_fmaf(fx, c110 - c010, c010);
@@ -429,8 +438,9 @@ struct UnitQueue {
 // so that list reservations can be made per wave.
 // (at least 4 waves per SIMD: the register budget is 128 VGPRs)
 // kAdapt: adaptive sampling rate (macro-cell codes instead of visibility
-// bits); a sample of step exponent e is followed by sample k + 2^e.
-template <int kPipe, bool kLdsFlags, bool kFast, bool kAdapt>
+// bits); a sample of step exponent e is followed by sample k + 2^e.  kHalf:
+// binary16 pool.
+template <int kPipe, bool kLdsFlags, bool kFast, bool kAdapt, bool kHalf>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_march(FrameDev f, int32_t it, uint32_t n0) {
     static_assert(!kAdapt || kPipe == 1, "the adaptive sampler decides one sample ahead at most");
     const FrameHot hot = load_hot(f.var);  // before any store of this kernel
@@ -547,7 +557,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
 #pragma unroll
                 for (int u = 0; u < kPipe; ++u) {
                     if (cnt == u && sample_pos(o, d, ts, te, f.step, k + u, f.vm1, p)) {
-                        grp[u] = sample_cache<kFast, kAdapt>(f, hot, lgs, fl, p, sc);
+                        grp[u] = sample_cache<kFast, kAdapt, kHalf>(f, hot, lgs, fl, p, sc);
                         ++cnt;
                     }
                 }
@@ -591,7 +601,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
                 while (nc < S) {
                     float qp[3];
                     if (!sample_pos(o, d, ts, te, f.step, kg, f.vm1, qp)) break;
-                    const SampleRes sr = sample_cache<kFast, kAdapt>(f, hot, lgs, fl, qp, sc);
+                    const SampleRes sr = sample_cache<kFast, kAdapt, kHalf>(f, hot, lgs, fl, qp, sc);
                     tally.add(sr.status);
                     book.note(f, hot.frame, cold, sr);
                     if (sr.status == S_MISS)
@@ -717,7 +727,7 @@ hipError_t launch_frame_begin(const FrameDev& f, int32_t n_iter_ctr, const float
 
 // Workgroups of one k_march instantiation that are resident at once on the
 // current device (the grid of the persistent kernel), cached per device.
-template <int P, bool LDS, bool FAST, bool A>
+template <int P, bool LDS, bool FAST, bool A, bool H>
 static hipError_t resident_blocks(int* out) {
     static int cache[64] = {0};
     int dev = 0;
@@ -726,7 +736,7 @@ static hipError_t resident_blocks(int* out) {
     if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
     if (cache[dev] == 0) {
         int per_cu = 0, n_cu = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_march<P, LDS, FAST, A>, kBlock, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_march<P, LDS, FAST, A, H>, kBlock, 0);
         if (e != hipSuccess) return e;
         e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess) return e;
@@ -736,36 +746,49 @@ static hipError_t resident_blocks(int* out) {
     return hipSuccess;
 }
 
-template <int P, bool LDS, bool FAST, bool A>
+template <int P, bool LDS, bool FAST, bool A, bool H>
 static hipError_t launch_march_t(const FrameDev& f, int it, int64_t max_rays, uint32_t n0, hipStream_t s) {
     int cap = 0;
-    hipError_t e = resident_blocks<P, LDS, FAST, A>(&cap);
+    hipError_t e = resident_blocks<P, LDS, FAST, A, H>(&cap);
     if (e != hipSuccess) return e;
     // one work unit (64 rays) per wave at least
     int64_t b = (max_rays + kBlock - 1) / kBlock;
     if (b < 1) b = 1;
     if (b > cap) b = cap;
-    hipLaunchKernelGGL((k_march<P, LDS, FAST, A>), dim3((unsigned)b), dim3(kBlock), 0, s, f, it, n0);
+    hipLaunchKernelGGL((k_march<P, LDS, FAST, A, H>), dim3((unsigned)b), dim3(kBlock), 0, s, f, it, n0);
     return hipGetLastError();
 }
 
-template <int P, bool LDS, bool A>
+template <int P, bool LDS, bool A, bool H>
 static hipError_t launch_march_l(const FrameDev& f, int it, int64_t max_rays, uint32_t n0, hipStream_t s) {
     // 16^3 bricks in a pool of less than 4 GiB (or the uncached mode, which
     // reads no pool) and 16^3 macro-cells (or none)
     const bool cells = A || f.flags;
+    const uint64_t brick_bytes = 4096ull * (H ? 2ull : 4ull);
     const bool fast = (f.mode != CINR_CACHED ||
-                       (f.geo.brick == 16 && (uint64_t)f.pool_bricks * 16384ull < (1ull << 32))) &&
+                       (f.geo.brick == 16 && (uint64_t)f.pool_bricks * brick_bytes < (1ull << 32))) &&
                       (!cells || f.mc_N == 16);
-    if (fast) return launch_march_t<P, LDS, true, A>(f, it, max_rays, n0, s);
-    return launch_march_t<P, LDS, false, A>(f, it, max_rays, n0, s);
+    if (fast) return launch_march_t<P, LDS, true, A, H>(f, it, max_rays, n0, s);
+    return launch_march_t<P, LDS, false, A, H>(f, it, max_rays, n0, s);
 }
 
-template <int P, bool A>
+template <int P, bool A, bool H>
 static hipError_t launch_march_p(const FrameDev& f, int it, int64_t max_rays, uint32_t n0, hipStream_t s) {
     const bool lds = A ? f.n_cells <= kMaxLdsCells : (f.flags && f.flag_words <= kMaxLdsFlagWords);
-    if (lds) return launch_march_l<P, true, A>(f, it, max_rays, n0, s);
-    return launch_march_l<P, false, A>(f, it, max_rays, n0, s);
+    if (lds) return launch_march_l<P, true, A, H>(f, it, max_rays, n0, s);
+    return launch_march_l<P, false, A, H>(f, it, max_rays, n0, s);
+}
+
+template <bool H>
+static hipError_t launch_march_h(const FrameDev& f, int it, int64_t n, uint32_t n0, hipStream_t s) {
+    // the adaptive sampler decides its next sample after the current one
+    if (f.adapt > 0) return launch_march_p<1, true, H>(f, it, n, n0, s);
+    // kPipe: samples decided and fetched ahead per ray (8 runs as 4)
+    switch (f.pipe) {
+        case 1: return launch_march_p<1, false, H>(f, it, n, n0, s);
+        case 2: return launch_march_p<2, false, H>(f, it, n, n0, s);
+        default: return launch_march_p<4, false, H>(f, it, n, n0, s);
+    }
 }
 
 hipError_t launch_march(const FrameDev& f, int it, int64_t max_rays, hipStream_t s) {
@@ -773,14 +796,8 @@ hipError_t launch_march(const FrameDev& f, int it, int64_t max_rays, hipStream_t
     // `max_rays` re-queued rays
     const uint32_t n0 = (uint32_t)(((f.W + 7) / 8) * ((f.H + 7) / 8)) * 64u;
     const int64_t n = it == 0 ? (int64_t)n0 : max_rays;
-    // the adaptive sampler decides its next sample after the current one
-    if (f.adapt > 0) return launch_march_p<1, true>(f, it, n, n0, s);
-    // kPipe: samples decided and fetched ahead per ray (8 runs as 4)
-    switch (f.pipe) {
-        case 1: return launch_march_p<1, false>(f, it, n, n0, s);
-        case 2: return launch_march_p<2, false>(f, it, n, n0, s);
-        default: return launch_march_p<4, false>(f, it, n, n0, s);
-    }
+    if (f.pool_f16) return launch_march_h<true>(f, it, n, n0, s);
+    return launch_march_h<false>(f, it, n, n0, s);
 }
 
 hipError_t launch_shade(const FrameDev& f, int it, int64_t cap_rays, hipStream_t s) {

@@ -127,10 +127,11 @@ def test_invalid_brick_geometry_is_rejected():
         cinr.lib().cinr_destroy_volume(h)
 
 
-def cache_desc(brick=8, n_lods=2, pool=96, max_requests=16):
+def cache_desc(brick=8, n_lods=2, pool=96, max_requests=16, pool_dtype=cinr.F32):
     d = cinr.CacheDesc()
     d.brick, d.n_lods, d.pool_bricks, d.max_requests = brick, n_lods, pool, max_requests
     d.rank_window, d.ranking = 1000, cinr.RANK_PRIORITY
+    d.pool_dtype = pool_dtype
     return d
 
 
@@ -150,6 +151,10 @@ def test_cache_workspace_grows_with_the_pool_and_rejects_bad_descriptors():
         assert L.cinr_cache_workspace_size(h, C.byref(cache_desc(max_requests=-1)), C.byref(b)) == INVALID_ARG
         assert L.cinr_cache_workspace_size(h, C.byref(cache_desc(max_requests=257)), C.byref(b)) == INVALID_ARG
         assert L.cinr_cache_workspace_size(h, C.byref(cache_desc(pool=-1)), C.byref(b)) == INVALID_ARG
+        # the pool holds binary32 or binary16 values, nothing else
+        assert L.cinr_cache_workspace_size(h, C.byref(cache_desc(pool_dtype=cinr.F16)), C.byref(b)) == OK
+        for bad in (cinr.BF16, cinr.BF16X3, -1):
+            assert L.cinr_cache_workspace_size(h, C.byref(cache_desc(pool_dtype=bad)), C.byref(b)) == INVALID_ARG
     finally:
         L.cinr_destroy_volume(h)
 

@@ -11,7 +11,9 @@ properties that hold at any size and outputs it can compute one by one:
    renderer on the same residency; in parity mode (no early termination,
    FP32 MLP) the full per-brick request counts, the request list and the
    page table after the frame are bit-exact against a full oracle frame;
- - decoded bricks of the prefilled pool against oracle decoding.
+ - decoded bricks of the prefilled pool against oracle decoding;
+ - the binary16 pool in the bench configuration against the oracle's
+   rounded pool.
 """
 import numpy as np
 import pytest
@@ -64,18 +66,18 @@ def _prefill_keys(off, seed=5):
     return np.sort(np.concatenate(keys)).astype(np.int32)
 
 
-def _gpu_cache(vol, keep=False):
+def _gpu_cache(vol, keep=False, pool_dtype="f32"):
     from paper_2504_18001_amd import cinr
     cs = W.cache
     return cinr.Cache(vol, cs.brick, cs.n_lods, cs.pool_bricks, cs.max_requests, preload_period=cs.preload_period,
-                      keep_request_counts=keep, evict_log_capacity=64)
+                      keep_request_counts=keep, evict_log_capacity=64, pool_dtype=pool_dtype)
 
 
-def _oracle_cache(m):
+def _oracle_cache(m, pool_f16=False):
     from oracle import oracle as O
     cs = W.cache
     return O.OracleCache(m, brick=cs.brick, n_lods=cs.n_lods, pool_bricks=cs.pool_bricks, max_requests=cs.max_requests,
-                         preload_period=cs.preload_period)
+                         preload_period=cs.preload_period, pool_f16=pool_f16)
 
 
 def test_frame0_equals_uncached_inr_on_sampled_pixels(scene):
@@ -157,16 +159,16 @@ def test_prefilled_fullsize_parity_mode_bit_exact_requests(scene):
 MAXABS = {"bf16x3": 8e-3, "f16": 8e-3, "bf16": 2.5e-2}
 
 
-@pytest.mark.parametrize("dtype", ["bf16x3", "f16", "bf16"])
-def test_prefilled_fullsize_bench_configuration_pixels(scene, dtype):
+@pytest.mark.parametrize("dtype,pool_dtype", [("bf16x3", "f32"), ("f16", "f32"), ("bf16", "f32"), ("bf16x3", "f16")])
+def test_prefilled_fullsize_bench_configuration_pixels(scene, dtype, pool_dtype):
     from oracle import oracle as O
     from paper_2504_18001_amd import cinr
     vol, m, mm = scene
     off = vol.geometry(W.cache.brick, W.cache.n_lods)[1]
     keys = _prefill_keys(off, seed=9)
-    cache = _gpu_cache(vol)
+    cache = _gpu_cache(vol, pool_dtype=pool_dtype)
     cache.prefill(torch.from_numpy(keys).cuda(), stamp=0, dtype=dtype)
-    oc = _oracle_cache(m)
+    oc = _oracle_cache(m, pool_f16=pool_dtype == "f16")
     oc.prefill(keys, 0)
     f = 40  # random transfer function part of the orbit
     cam, tf = W.camera(f), W.tf(f)
@@ -181,6 +183,6 @@ def test_prefilled_fullsize_bench_configuration_pixels(scene, dtype):
     d = np.abs(got - ref)
     mse = float((d ** 2).mean())
     psnr = 10 * np.log10(1.0 / mse) if mse > 0 else float("inf")
-    print(f"prefilled {dtype} bench-configuration pixels: max abs", d.max(), "PSNR", psnr)
+    print(f"prefilled {dtype} MLP, {pool_dtype} pool, bench-configuration pixels: max abs", d.max(), "PSNR", psnr)
     assert d.max() <= MAXABS[dtype]
     assert psnr >= 45.0

@@ -28,15 +28,17 @@ def view_cam(i, f):
     return c
 
 
-def test_shared_cache_views_match_oracle():
+@pytest.mark.parametrize("pool_dtype", ["f32", "f16"])
+def test_shared_cache_views_match_oracle(pool_dtype):
     from oracle import oracle as O
     from paper_2504_18001_amd import cinr
     vols = [gpu_volume(s) for s in range(3)]
     ms = [oracle_inr(W.arch, s) for s in range(3)]
     B, nl, pool, req = 8, 2, 150, 24
     gc = cinr.Cache(vols, B, nl, pool, req, miss_log_capacity=1 << 20, evict_log_capacity=1 << 14,
-                    keep_request_counts=True)
-    oc = O.OracleCache(ms, brick=B, n_lods=nl, pool_bricks=pool, max_requests=req, log_misses=True)
+                    keep_request_counts=True, pool_dtype=pool_dtype)
+    oc = O.OracleCache(ms, brick=B, n_lods=nl, pool_bricks=pool, max_requests=req, log_misses=True,
+                       pool_f16=pool_dtype == "f16")
     assert gc.n_keys == oc.n_keys == 3 * gc.keys_per_volume
     mv = cinr.MultiViewRenderer(len(SIZES))
     for f in range(10):
