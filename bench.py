@@ -84,11 +84,12 @@ def make_scene(w, dtype_decode="bf16"):
     return vol, cams, tfs
 
 
-def new_cache(vol, w):
+def new_cache(vol, w, pool_dtype="f32", pool_bricks=None):
     from paper_2504_18001_amd import cinr
     cs = w.cache
-    return cinr.Cache(vol, cs.brick, cs.n_lods, cs.pool_bricks, cs.max_requests, rank_window=cs.rank_window,
-                      ranking=cs.ranking, preload_period=cs.preload_period)
+    return cinr.Cache(vol, cs.brick, cs.n_lods, pool_bricks or cs.pool_bricks, cs.max_requests,
+                      rank_window=cs.rank_window, ranking=cs.ranking, preload_period=cs.preload_period,
+                      pool_dtype=pool_dtype)
 
 
 def run_frames(r, vol, cams, tfs, w, frames, mode, dtype, cache, stats=None, out=None):
@@ -124,6 +125,35 @@ def decode_throughput(vol, w, dtype, n_bricks, reps=5):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
     return n_bricks / (ms * 1e-3), ms
+
+
+def pool_f16_leg(vol, cams, tfs, w, Wm, K, dtype, ref_img):
+    """The headline sequence over a binary16 pool: the same slot count (half
+    the bytes) and the same bytes (twice the slots), against the FP32 pool."""
+    import torch
+    from paper_2504_18001_amd import cinr
+    res = {}
+    for name, slots in (("same_slots", w.cache.pool_bricks), ("same_bytes", 2 * w.cache.pool_bricks)):
+        c = new_cache(vol, w, pool_dtype="f16", pool_bricks=slots)
+        r = cinr.Renderer()
+        out = torch.empty((w.height, w.width, 4), dtype=torch.float32, device="cuda")
+        st = torch.zeros((K, len(cinr.STAT_FIELDS)), dtype=torch.int64, device="cuda")
+        run_frames(r, vol, cams, tfs, w, range(Wm), cinr.CACHED, dtype, c, out=out)
+        torch.cuda.synchronize()
+        vol.set_timing(True, march_only=True)
+        t0 = time.perf_counter()
+        run_frames(r, vol, cams, tfs, w, range(Wm, Wm + K), cinr.CACHED, dtype, c, stats=st, out=out)
+        torch.cuda.synchronize()
+        fps = K / (time.perf_counter() - t0)
+        vol.set_timing(False)
+        ms, n = vol.collect_timing()["march"]
+        tot = st.sum(0).cpu().numpy()
+        res[name] = {"fps": round(fps, 2), "pool_slots": slots, "pool_gib": round(c.pool.numel() * 2 / 2 ** 30, 3),
+                     "march_ms_per_launch": round(ms / max(n, 1), 4),
+                     "true_misses_per_frame": int(tot[cinr.STAT_FIELDS.index("misses")]) // K,
+                     "psnr_vs_f32_pool_db": round(psnr(ref_img, out.cpu().numpy()), 2)}
+        del c
+    return res
 
 
 def multiview_leg(warmup, steps, dtype, oracle=True):
@@ -369,6 +399,8 @@ def main():
     ap.add_argument("--no-fp32-cached", action="store_true", help="skip the comparison precisions")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-multiview", action="store_true", help="skip the 16-view shared-cache leg")
+    ap.add_argument("--no-adaptive", action="store_true", help="skip the adaptive sampling leg")
+    ap.add_argument("--no-pool-f16", action="store_true", help="skip the binary16 pool leg")
     ap.add_argument("--multiview-steps", type=int, default=60)
     ap.add_argument("--no-training", action="store_true", help="skip the INR training leg")
     ap.add_argument("--training-steps", type=int, default=50)
@@ -474,7 +506,7 @@ def main():
         tfs_low.append(t2)
     adaptive = {}
     ref_low = None
-    for E in (0, 1, 2, 3):
+    for E in () if args.no_adaptive else (0, 1, 2, 3):
         c3 = new_cache(vol, w)
         r3 = cinr.Renderer()
         out3 = torch.empty_like(out)
@@ -501,6 +533,12 @@ def main():
                              "psnr_vs_fixed_step_db": round(psnr(ref_low, img), 2)}
         del c3
     log(f"[bench] adaptive sampling rate (TF opacity x 0.1): {adaptive}")
+
+    # --- binary16 brick pool (reduced-precision pool) -------------------------
+    pool16 = None
+    if not args.no_pool_f16:
+        pool16 = pool_f16_leg(vol, cams, tfs, w, Wm, K, args.dtype, cached_img.cpu().numpy())
+        log(f"[bench] binary16 pool: {pool16}")
 
     # --- uncached FP32 INR renderer on the same frames ------------------------
     KU = args.uncached_steps or K
@@ -585,6 +623,7 @@ def main():
                           "f32": "FP32 MFMA"}.get(args.dtype, args.dtype),
         "cached_other_precisions": other,
         "adaptive_sampling": {"tf": "the orbit's TFs with opacity x 0.1", "by_max_exponent": adaptive},
+        "binary16_pool": pool16,
         "bricks_per_s": {k: round(v, 1) for k, v in bps.items()},
         "psnr_cached_vs_uncached_db": round(q_unc, 2),
         "stage_ms_per_frame": {k: round(v[0] / K, 4) for k, v in all_stages.items()},
