@@ -827,9 +827,48 @@ typedef struct {
 typedef struct {
     int status;
     double value;
+    float value32; /* the value in binary32, for decisions that depend on it (path tracing) */
     float pos[3];
     int exp;  /* step exponent of the sample's cell (0 without adaptive sampling) */
 } sample_out;
+
+/* Binary32 linear interpolation a + t (b - a), rounded once. */
+static float lerp32(float a, float b, float t) { return fmaf(t, b - a, a); }
+
+/* Trilinear interpolation in binary32, along x, then y, then z; corners
+ * c[dx + 2 dy + 4 dz]. */
+static float trilinear32(const float c[8], const float f[3]) {
+    const float x00 = lerp32(c[0], c[1], f[0]), x10 = lerp32(c[2], c[3], f[0]);
+    const float x01 = lerp32(c[4], c[5], f[0]), x11 = lerp32(c[6], c[7], f[0]);
+    const float y0 = lerp32(x00, x10, f[1]), y1 = lerp32(x01, x11, f[1]);
+    return lerp32(y0, y1, f[2]);
+}
+
+/* Binary32 value of a true miss: an explicit grid is interpolated in binary32
+ * at the (clamped) position, then mapped by value_scale * v + value_offset
+ * (rounded once) and clamped to [0, 1]; an INR's value is its FP64 value
+ * rounded to binary32. */
+static float miss_value32(const orc_inr* m, const float pos[3], double v64) {
+    if (!m->grid) return (float)v64;
+    float c[8], f[3];
+    int32_t j[3];
+    for (int a = 0; a < 3; ++a) {
+        const float hi = (float)(m->dims[a] - 1);
+        float xa = pos[a];
+        if (xa < 0.0f) xa = 0.0f;
+        if (xa > hi) xa = hi;
+        j[a] = (int32_t)xa;
+        if (j[a] > m->dims[a] - 2) j[a] = m->dims[a] - 2;
+        f[a] = xa - (float)j[a];
+    }
+    const int64_t sy = m->dims[0], sz = (int64_t)m->dims[0] * m->dims[1];
+    for (int n = 0; n < 8; ++n)
+        c[n] = m->grid[(j[2] + ((n >> 2) & 1)) * sz + (j[1] + ((n >> 1) & 1)) * sy + j[0] + (n & 1)];
+    float v = fmaf(m->value_scale, trilinear32(c, f), m->value_offset);
+    if (v < 0.0f) v = 0.0f;
+    if (v > 1.0f) v = 1.0f;
+    return v;
+}
 
 typedef struct {
     int64_t samples, hits, fallbacks, misses, skipped;
@@ -845,6 +884,7 @@ typedef struct {
 static void sample_decide(const frame_ctx* fc, const float o[3], const float d[3], float t, sample_out* so) {
     const orc_params* P = fc->p;
     so->exp = 0;
+    so->value32 = 0.0f;
     float pos[3];
     for (int a = 0; a < 3; ++a) {
         float td = t * d[a];
@@ -888,12 +928,16 @@ static void sample_decide(const frame_ctx* fc, const float o[3], const float d[3
             if (j[a] > fc->m->dims[a] - 2) j[a] = fc->m->dims[a] - 2;
             f[a] = (double)(pos[a] - (float)j[a]);
         }
+        float c32[8], f32[3];
         for (int n = 0; n < 8; ++n) {
             double x[3] = {(double)(j[0] + (n & 1)), (double)(j[1] + ((n >> 1) & 1)), (double)(j[2] + ((n >> 2) & 1))};
             corner[n] = value_one(fc->m, x);
+            c32[n] = (float)corner[n];
         }
+        for (int a = 0; a < 3; ++a) f32[a] = pos[a] - (float)j[a];
         so->status = S_HIT;
         so->value = trilinear8(corner, f);
+        so->value32 = trilinear32(c32, f32);
         return;
     }
     orc_cache* c = fc->c;
@@ -922,15 +966,19 @@ static void sample_decide(const frame_ctx* fc, const float o[3], const float d[3
         const double* br = c->pool + (int64_t)slot * B3;
         int32_t l[3];
         double f[3], corner[8];
+        float c32[8], f32[3];
         for (int a = 0; a < 3; ++a) {
             l[a] = j[a] - b[a] * (B - 1);
-            f[a] = (double)(q[a] - (float)j[a]);
+            f32[a] = q[a] - (float)j[a];
+            f[a] = (double)f32[a];
         }
         for (int n = 0; n < 8; ++n) {
             int dx = n & 1, dy = (n >> 1) & 1, dz = (n >> 2) & 1;
             corner[n] = br[((int64_t)(l[2] + dz) * B + (l[1] + dy)) * B + (l[0] + dx)];
+            c32[n] = (float)corner[n];
         }
         so->value = trilinear8(corner, f);
+        so->value32 = trilinear32(c32, f32);
         so->status = (Lp == L) ? S_HIT : S_FALLBACK;
         if (!fc->readonly) {
 #pragma omp atomic write
@@ -1067,6 +1115,288 @@ static int32_t march(const frame_ctx* fc, thread_acc* ta, const float* tf, int32
     return k;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Path tracing (Section 5.1: a second wavefront pipeline with Woodcock delta */
+/* tracking through the same sampler)                                          */
+/* ------------------------------------------------------------------------- */
+
+/* The medium: extinction sigma(x) = pt_density * alpha(v(x)) with alpha the TF
+ * opacity, so pt_density is a majorant; scattering albedo = TF colour at v;
+ * isotropic phase function; one directional light toward pt_light_dir whose
+ * term pt_light already carries the phase factor; the environment pt_ambient
+ * lights scattered rays that leave the box.  Per path: delta tracking along
+ * the primary ray; at every real collision the throughput takes the albedo,
+ * a shadow ray toward the light is tracked the same way (transmittance 0 or
+ * 1) and adds throughput * pt_light when it leaves the box, then the path
+ * scatters isotropically, up to pt_max_bounces collisions.  A pixel's colour
+ * is the mean radiance of its pt_spp paths, its opacity the fraction of paths
+ * whose primary ray collides, over the paths completed within the event
+ * budget ORC_PT_MAX_EVENTS.
+ *
+ * Randomness: Philox-4x32-10 with key (pt_seed, frame index) and counter
+ * (pixel, n, 0, 0), n the pixel's event count (one draw per tentative
+ * collision and per direction trial), continued across its paths. */
+
+float orc_pt_uniform(uint32_t r) { return (float)(r >> 8) * 5.9604644775390625e-08f; }
+
+float orc_pt_free_flight(uint32_t r) {
+    const double xi = ((double)(r >> 8) + 1.0) * 5.9604644775390625e-08; /* exact, in (0, 1] */
+    return (float)(-log(xi));
+}
+
+float orc_pt_segment_exit(const float p[3], const float d[3], const float vm1[3]) {
+    float t = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] == 0.0f) continue;
+        const float wall = d[a] > 0.0f ? vm1[a] : 0.0f;
+        const float ta = (wall - p[a]) / d[a];
+        if (ta < t) t = ta;
+    }
+    if (!(t >= 0.0f) || t == INFINITY) t = 0.0f;
+    return t;
+}
+
+float orc_tf_alpha32(const float* tf, float v) {
+    const float x = v * 255.0f;
+    int32_t i0 = (int32_t)x;
+    if (i0 > 254) i0 = 254;
+    if (i0 < 0) i0 = 0;
+    const float t = x - (float)i0;
+    float a = lerp32(tf[4 * i0 + 3], tf[4 * (i0 + 1) + 3], t);
+    if (a < 0.0f) a = 0.0f;
+    if (a > 1.0f) a = 1.0f;
+    return a;
+}
+
+static void pt_draw(uint32_t pix, uint32_t n, const uint32_t key[2], uint32_t r[4]) {
+    const uint32_t ctr[4] = {pix, n, 0u, 0u};
+    orc_philox4x32_10(ctr, key, r);
+}
+
+/* Marsaglia (1972): (u1, u2) uniform in the square [-1, 1)^2 until
+ * s = u1^2 + u2^2 lies in (0, 1); then (2 u1 sqrt(1-s), 2 u2 sqrt(1-s), 1-2s)
+ * is uniform on the unit sphere. */
+static int marsaglia(const uint32_t r[4], float d[3]) {
+    const float u1 = 2.0f * orc_pt_uniform(r[0]) - 1.0f;
+    const float u2 = 2.0f * orc_pt_uniform(r[1]) - 1.0f;
+    const float a = u1 * u1, b = u2 * u2;
+    const float s = a + b;
+    if (s >= 1.0f || s == 0.0f) return 0;
+    const float q = sqrtf(1.0f - s);
+    d[0] = (2.0f * u1) * q;
+    d[1] = (2.0f * u2) * q;
+    d[2] = 1.0f - 2.0f * s;
+    return 1;
+}
+
+uint32_t orc_pt_direction(uint32_t pix, uint32_t n0, const uint32_t key[2], float d[3]) {
+    uint32_t n = n0, r[4];
+    do pt_draw(pix, n++, key, r);
+    while (!marsaglia(r, d));
+    return n;
+}
+
+#define PT_GATHER_MAX 8
+
+typedef struct {
+    const frame_ctx* fc;
+    thread_acc* ta;
+    const float* tf;
+    int32_t pix;
+    uint32_t key[2];
+    uint32_t n;      /* next event */
+    int capped;      /* the event budget is spent */
+    int log_miss;
+    int gather;      /* tentative collisions looked up from a true miss on: min(samples_per_iter, 8) */
+    float inv_sigma; /* 1 / pt_density in binary32 */
+} pt_ctx;
+
+/* Position o + t d, clamped to the box (as the ray marcher's samples). */
+static void pt_pos(const frame_ctx* fc, const float o[3], const float d[3], float t, float p[3]) {
+    for (int a = 0; a < 3; ++a) {
+        float td = t * d[a];
+        float q = o[a] + td;
+        if (q < 0.0f) q = 0.0f;
+        if (q > fc->vm1[a]) q = fc->vm1[a];
+        p[a] = q;
+    }
+}
+
+/* One sampler lookup of tentative collision `event` at t: counted, requests
+ * and stamps as for any sample, a true miss inferred (and logged with k =
+ * event). */
+static void pt_lookup(pt_ctx* c, const float o[3], const float d[3], float t, uint32_t event, sample_out* so) {
+    const frame_ctx* fc = c->fc;
+    thread_acc* ta = c->ta;
+    sample_decide(fc, o, d, t, so);
+    ta->samples++;
+    switch (so->status) {
+        case S_HIT: ta->hits++; break;
+        case S_FALLBACK: ta->fallbacks++; break;
+        case S_SKIP: ta->skipped++; break;
+        default: {
+            ta->misses++;
+            double x[3] = {so->pos[0], so->pos[1], so->pos[2]};
+            so->value = value_one(fc->m, x);
+            so->value32 = miss_value32(fc->m, so->pos, so->value);
+            if (c->log_miss) acc_miss(ta, c->pix, (int32_t)event, so->pos);
+        }
+    }
+}
+
+/* Woodcock delta tracking along o + t d from t0 to te: tentative collisions
+ * at free-flight steps -ln(xi) / pt_density; a tentative collision is real
+ * when a second uniform falls below the TF opacity at the sampled value
+ * (decided in binary32; a skipped sample has opacity 0).  Returns 1 at a real
+ * collision (its position and FP64 value), 0 when the segment is left or the
+ * event budget ends.  From a true miss on, the next tentative collisions of
+ * the segment (up to `gather` with the miss, those before te) are looked up
+ * at once, as the wavefront step of the ray marcher; their values then serve
+ * those events, and lookups beyond a real collision are unused. */
+static int pt_track(pt_ctx* c, const float o[3], const float d[3], float t0, float te, float pos[3], double* v64) {
+    sample_out g[PT_GATHER_MAX];
+    uint32_t g_first = 0, g_n = 0; /* gathered events [g_first, g_first + g_n) */
+    float t = t0;
+    for (;;) {
+        if (c->n >= ORC_PT_MAX_EVENTS) {
+            c->capped = 1;
+            return 0;
+        }
+        const uint32_t e = c->n++;
+        uint32_t r[4];
+        pt_draw(c->pix, e, c->key, r);
+        const float step = orc_pt_free_flight(r[0]) * c->inv_sigma;
+        t = t + step;
+        if (t > te) return 0;
+        sample_out so;
+        if (e >= g_first && e < g_first + g_n) {
+            so = g[e - g_first];
+        } else {
+            pt_lookup(c, o, d, t, e, &so);
+            if (so.status == S_MISS) {
+                g[0] = so;
+                g_first = e;
+                g_n = 1;
+                float tg = t;
+                while ((int)g_n < c->gather) {
+                    const uint32_t eg = e + g_n;
+                    uint32_t rg[4];
+                    pt_draw(c->pix, eg, c->key, rg);
+                    const float sg = orc_pt_free_flight(rg[0]) * c->inv_sigma;
+                    tg = tg + sg;
+                    if (tg > te) break;
+                    pt_lookup(c, o, d, tg, eg, &g[g_n]);
+                    ++g_n;
+                }
+            }
+        }
+        const float alpha = so.status == S_SKIP ? 0.0f : orc_tf_alpha32(c->tf, so.value32);
+        if (orc_pt_uniform(r[1]) < alpha) {
+            for (int a = 0; a < 3; ++a) pos[a] = so.pos[a];
+            *v64 = so.value;
+            return 1;
+        }
+    }
+}
+
+/* All pt_spp paths of pixel (i, j). */
+static void pt_pixel(const frame_ctx* fc, thread_acc* ta, const float* tf, int32_t i, int32_t j, double out[4],
+                     int log_miss) {
+    const orc_params* P = fc->p;
+    out[0] = out[1] = out[2] = out[3] = 0.0;
+    float o0[3], d0[3], ts, te;
+    if (!orc_ray_setup(fc->cam, fc->m->dims, i, j, o0, d0, &ts, &te)) return;
+    pt_ctx c;
+    memset(&c, 0, sizeof(c));
+    c.fc = fc;
+    c.ta = ta;
+    c.tf = tf;
+    c.pix = j * fc->cam->width + i;
+    c.key[0] = P->pt_seed;
+    c.key[1] = (uint32_t)P->frame_index;
+    c.log_miss = log_miss;
+    c.gather = P->samples_per_iter < PT_GATHER_MAX ? P->samples_per_iter : PT_GATHER_MAX;
+    if (c.gather < 1) c.gather = 1;
+    c.inv_sigma = 1.0f / P->pt_density;
+    double sum[3] = {0.0, 0.0, 0.0};
+    int64_t hits = 0, done = 0;
+    for (int32_t path = 0; path < P->pt_spp && !c.capped; ++path) {
+        double beta[3] = {1.0, 1.0, 1.0}, L[3] = {0.0, 0.0, 0.0};
+        int hit = 0;
+        float o[3], d[3], t0 = ts, t1 = te;
+        memcpy(o, o0, sizeof o);
+        memcpy(d, d0, sizeof d);
+        for (int32_t bounce = 0;;) {
+            float p[3];
+            double v;
+            if (!pt_track(&c, o, d, t0, t1, p, &v)) {
+                if (!c.capped && bounce > 0)
+                    for (int k = 0; k < 3; ++k) L[k] += beta[k] * (double)P->pt_ambient[k];
+                break;
+            }
+            if (bounce == 0) hit = 1;
+            double rgba[4];
+            tf_lookup(tf, v, rgba);
+            for (int k = 0; k < 3; ++k) beta[k] *= rgba[k];
+            /* next-event estimate: a shadow ray toward the light */
+            const float tl = orc_pt_segment_exit(p, P->pt_light_dir, fc->vm1);
+            float ps[3];
+            double vs;
+            const int blocked = pt_track(&c, p, P->pt_light_dir, 0.0f, tl, ps, &vs);
+            if (c.capped) break;
+            if (!blocked)
+                for (int k = 0; k < 3; ++k) L[k] += beta[k] * (double)P->pt_light[k];
+            if (++bounce == P->pt_max_bounces) break;
+            /* isotropic scattering */
+            int ok = 0;
+            while (!ok) {
+                if (c.n >= ORC_PT_MAX_EVENTS) {
+                    c.capped = 1;
+                    break;
+                }
+                uint32_t r[4];
+                pt_draw(c.pix, c.n++, c.key, r);
+                ok = marsaglia(r, d);
+            }
+            if (!ok) break;
+            memcpy(o, p, sizeof o);
+            t0 = 0.0f;
+            t1 = orc_pt_segment_exit(p, d, fc->vm1);
+        }
+        if (c.capped) break; /* a path cut by the event budget is dropped */
+        for (int k = 0; k < 3; ++k) sum[k] += L[k];
+        hits += hit;
+        done += 1;
+    }
+    if (done == 0) return;
+    const double J = (double)done;
+    out[0] = sum[0] / J;
+    out[1] = sum[1] / J;
+    out[2] = sum[2] / J;
+    out[3] = (double)hits / J;
+}
+
+/* One pixel of the frame's pipeline. */
+static void render_pixel(const frame_ctx* fc, thread_acc* ta, const float* tf, int32_t i, int32_t j, double out[4],
+                         int log_miss, int32_t* nproc) {
+    if (fc->p->pipeline == 1) {
+        pt_pixel(fc, ta, tf, i, j, out, log_miss);
+        if (nproc) *nproc = 0;
+    } else {
+        const int32_t k = march(fc, ta, tf, i, j, out, log_miss);
+        if (nproc) *nproc = k;
+    }
+}
+
+/* Parameters the path tracer needs. */
+static int pt_params_ok(const orc_params* p) {
+    if (p->pipeline == 0) return 1;
+    if (p->pipeline != 1) return 0;
+    if (!(p->pt_density > 0.0f) || !isfinite(p->pt_density)) return 0;
+    if (p->pt_spp < 1 || p->pt_max_bounces < 1 || p->adapt_max_exp >= 0) return 0;
+    return 1;
+}
+
 static int cmp_miss(const void* a, const void* b) {
     const miss_rec* x = (const miss_rec*)a;
     const miss_rec* y = (const miss_rec*)b;
@@ -1089,7 +1419,8 @@ static int render_pass(frame_ctx* fc, const float* tf, double* rgba, orc_stats* 
 #pragma omp for schedule(dynamic, 16)
         for (int64_t px = 0; px < (int64_t)W * H; ++px) {
             int32_t i = (int32_t)(px % W), j = (int32_t)(px / W);
-            int32_t nproc = march(fc, ta, tf, i, j, rgba + 4 * px, log_miss);
+            int32_t nproc = 0;
+            render_pixel(fc, ta, tf, i, j, rgba + 4 * px, log_miss, &nproc);
             if (trace) trace[px] = nproc;
             float o[3], d[3], ts, te;
             if (orc_ray_setup(fc->cam, fc->m->dims, i, j, o, d, &ts, &te)) rays++;
@@ -1138,6 +1469,7 @@ static uint8_t* make_flags(const orc_inr* m, const orc_params* p, const float* t
 int orc_render_uncached(const orc_inr* m, const orc_camera* c, const float* tf, const orc_params* p, double* rgba,
                         orc_stats* st) {
     if (p->mode != ORC_UNCACHED_DIRECT && p->mode != ORC_UNCACHED_LATTICE) return -1;
+    if (!pt_params_ok(p)) return -1;
     frame_ctx fc;
     memset(&fc, 0, sizeof(fc));
     fc.m = m;
@@ -1242,6 +1574,7 @@ int orc_cache_end_frame(orc_cache* c, int32_t frame, orc_stats* st) {
 int orc_cache_render(orc_cache* c, const orc_camera* cam, const float* tf, const orc_params* p, double* rgba,
                      orc_stats* st) {
     if (p->mode != ORC_CACHED) return -1;
+    if (!pt_params_ok(p)) return -1;
     frame_ctx fc;
     memset(&fc, 0, sizeof(fc));
     fc.m = &c->inr;
@@ -1274,7 +1607,8 @@ int orc_cache_render_views(orc_cache* c, int32_t n, const int32_t* vol, const or
                            const orc_params* ps, double* rgba, orc_stats* sts) {
     if (n < 1) return -1;
     for (int i = 0; i < n; ++i)
-        if (ps[i].mode != ORC_CACHED || vol[i] < 0 || vol[i] >= c->n_vols || ps[i].frame_index != ps[0].frame_index)
+        if (ps[i].mode != ORC_CACHED || vol[i] < 0 || vol[i] >= c->n_vols || ps[i].frame_index != ps[0].frame_index ||
+            !pt_params_ok(&ps[i]))
             return -1;
     miss_rec* all = NULL;
     int64_t n_all = 0;
@@ -1319,6 +1653,7 @@ int orc_cache_render_views(orc_cache* c, int32_t n, const int32_t* vol, const or
 int orc_render_pixels(const orc_inr* m, orc_cache* c, const orc_camera* cam, const float* tf, const orc_params* p,
                       const int32_t* pix, int64_t n, double* rgba) {
     if ((p->mode == ORC_CACHED) != (c != NULL)) return -1;
+    if (!pt_params_ok(p)) return -1;
     frame_ctx fc;
     memset(&fc, 0, sizeof(fc));
     fc.m = c ? &c->inr : m;
@@ -1344,7 +1679,7 @@ int orc_render_pixels(const orc_inr* m, orc_cache* c, const orc_camera* cam, con
 #pragma omp for schedule(dynamic, 4)
         for (int64_t q = 0; q < n; ++q) {
             const int32_t i = pix[q] % cam->width, j = pix[q] / cam->width;
-            march(&fc, ta, tf, i, j, rgba + 4 * q, 0);
+            render_pixel(&fc, ta, tf, i, j, rgba + 4 * q, 0, NULL);
         }
     }
     for (int t = 0; t < nt; ++t) free(acc[t].misses_buf);

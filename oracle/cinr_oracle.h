@@ -68,7 +68,21 @@ typedef struct {
     const float* macro_minmax; /* [Mz][My][Mx][2] */
     int32_t adapt_max_exp; /* adaptive sampling rate (Section 5.2): < 0 off; else E, the largest step
                               exponent (steps of 2^e sample spacings, e in [0, E]) */
+    /* path tracing with Woodcock delta tracking through the same sampler (Section 5.1) */
+    int32_t pipeline;      /* 0 = ray marching, 1 = path tracing */
+    float pt_density;      /* majorant extinction per LoD-0 voxel; extinction = pt_density * TF opacity */
+    float pt_light_dir[3]; /* unit vector toward the directional light */
+    float pt_light[3];     /* light term of an unblocked next-event estimate (radiance times phase) */
+    float pt_ambient[3];   /* environment radiance seen by scattered rays that leave the box */
+    int32_t pt_max_bounces;/* real collisions (scattering events) per path, >= 1 */
+    int32_t pt_spp;        /* paths per pixel, >= 1 */
+    uint32_t pt_seed;      /* Philox key word 0; word 1 is the frame index */
 } orc_params;
+
+/* Events (Philox draws) a pixel may use per frame in path tracing; a pixel
+ * that reaches the budget stops: the path in progress is dropped, no further
+ * path starts, and the pixel is the mean of the paths it completed. */
+#define ORC_PT_MAX_EVENTS 8000
 
 typedef struct {
     int32_t brick;        /* stored brick side B */
@@ -137,6 +151,23 @@ int orc_render_pixels(const orc_inr* m, orc_cache* c, const orc_camera* cam, con
 
 /* --- cached renderer --- */
 orc_cache* orc_cache_create(const orc_inr* m, const orc_cache_desc* d);
+
+/* Path tracing primitives (binary32 decision plane).
+ * orc_pt_uniform: (r >> 8) * 2^-24, in [0, 1).
+ * orc_pt_free_flight: -ln(xi), xi = ((r >> 8) + 1) * 2^-24 in (0, 1], computed
+ *   in binary64 and rounded to binary32 (an Exp(1) variate).
+ * orc_pt_direction: isotropic direction by Marsaglia's method from the
+ *   pixel's events n0, n0+1, ... (Philox counter (pix, n, 0, 0)); returns the
+ *   first unused event.
+ * orc_pt_segment_exit: distance from p (inside the box [0, vm1]) along d to
+ *   the box boundary.
+ * orc_tf_alpha32: TF opacity at v in binary32 (rows floor(255 v) and the
+ *   next, each interpolation rounded once), clamped to [0, 1]. */
+float orc_pt_uniform(uint32_t r);
+float orc_pt_free_flight(uint32_t r);
+uint32_t orc_pt_direction(uint32_t pix, uint32_t n0, const uint32_t key[2], float d[3]);
+float orc_pt_segment_exit(const float p[3], const float d[3], const float vm1[3]);
+float orc_tf_alpha32(const float* tf, float v);
 
 /* x rounded to the nearest IEEE 754 binary16 value, ties to even (11-bit
  * significand, normal exponents -14..15, subnormal quantum 2^-24), returned

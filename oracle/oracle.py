@@ -39,7 +39,10 @@ class Params(C.Structure):
     _fields_ = [("step", C.c_float), ("lod_scale", C.c_float), ("ert_threshold", C.c_float),
                 ("seed", C.c_uint32), ("frame_index", C.c_int32), ("samples_per_iter", C.c_int32),
                 ("mode", C.c_int32), ("macro_cell", C.c_int32), ("macro_minmax", C.c_void_p),
-                ("adapt_max_exp", C.c_int32)]
+                ("adapt_max_exp", C.c_int32),
+                ("pipeline", C.c_int32), ("pt_density", C.c_float), ("pt_light_dir", C.c_float * 3),
+                ("pt_light", C.c_float * 3), ("pt_ambient", C.c_float * 3), ("pt_max_bounces", C.c_int32),
+                ("pt_spp", C.c_int32), ("pt_seed", C.c_uint32)]
 
 
 class CacheDesc(C.Structure):
@@ -85,6 +88,11 @@ def lib():
             "orc_macrocell_flags": (None, [P, i64, P, P]),
             "orc_step_exp": (i32, [C.c_float, i32]),
             "orc_round_half": (C.c_double, [C.c_double]),
+            "orc_pt_uniform": (C.c_float, [C.c_uint32]),
+            "orc_pt_free_flight": (C.c_float, [C.c_uint32]),
+            "orc_pt_direction": (C.c_uint32, [C.c_uint32, C.c_uint32, P, P]),
+            "orc_pt_segment_exit": (C.c_float, [P, P, P]),
+            "orc_tf_alpha32": (C.c_float, [P, C.c_float]),
             "orc_macrocell_step_codes": (None, [P, i64, P, i32, P]),
             "orc_ray_setup": (C.c_int, [P, P, i32, i32, P, P, P, P]),
             "orc_select_lod": (i32, [P, P, C.c_float, u32, i32, i32]),
@@ -290,6 +298,38 @@ def macrocell_flags(minmax, tf):
     return out
 
 
+PT_MAX_EVENTS = 8000
+
+
+def pt_uniform(r):
+    return float(lib().orc_pt_uniform(int(r) & 0xFFFFFFFF))
+
+
+def pt_free_flight(r):
+    return float(lib().orc_pt_free_flight(int(r) & 0xFFFFFFFF))
+
+
+def pt_direction(pix, n0, key):
+    """Isotropic direction from events n0, n0+1, ... of pixel `pix` (Philox
+    key (key[0], key[1])): (direction, first unused event)."""
+    k = np.asarray(key, np.uint32)
+    d = np.zeros(3, np.float32)
+    n = lib().orc_pt_direction(pix, n0, _ptr(k), _ptr(d))
+    return d, int(n)
+
+
+def pt_segment_exit(p, d, vm1):
+    p = np.asarray(p, np.float32)
+    d = np.asarray(d, np.float32)
+    v = np.asarray(vm1, np.float32)
+    return float(lib().orc_pt_segment_exit(_ptr(p), _ptr(d), _ptr(v)))
+
+
+def tf_alpha32(tf, v):
+    t = np.ascontiguousarray(tf, np.float32)
+    return float(lib().orc_tf_alpha32(_ptr(t), float(v)))
+
+
 def round_half(x):
     """x rounded to the nearest binary16 value, ties to even (IEEE 754)."""
     return float(lib().orc_round_half(float(x)))
@@ -319,11 +359,23 @@ def philox4x32_10(ctr, key):
 
 
 def make_params(step, lod_scale, seed=0, frame_index=0, ert_threshold=2.0, samples_per_iter=8, mode=CACHED,
-                macro_cell=0, macro_minmax=None, adapt_max_exp=-1):
+                macro_cell=0, macro_minmax=None, adapt_max_exp=-1, path=None):
     """adapt_max_exp: adaptive sampling rate with steps of up to 2^E sample
-    spacings (Section 5.2); -1 (or 0) for the fixed step."""
+    spacings (Section 5.2); -1 (or 0) for the fixed step.  path: None for ray
+    marching, else a dict of path-tracing parameters (density, light_dir,
+    light, ambient, max_bounces, spp, seed)."""
     p = Params()
     p.adapt_max_exp = adapt_max_exp
+    if path is not None:
+        p.pipeline = 1
+        p.pt_density = path.get("density", 0.05)
+        for a in range(3):
+            p.pt_light_dir[a] = path.get("light_dir", (0.0, 0.0, 1.0))[a]
+            p.pt_light[a] = path.get("light", (1.0, 1.0, 1.0))[a]
+            p.pt_ambient[a] = path.get("ambient", (0.0, 0.0, 0.0))[a]
+        p.pt_max_bounces = path.get("max_bounces", 1)
+        p.pt_spp = path.get("spp", 1)
+        p.pt_seed = path.get("seed", 0) & 0xFFFFFFFF
     p.step, p.lod_scale, p.ert_threshold = step, lod_scale, ert_threshold
     p.seed, p.frame_index, p.samples_per_iter, p.mode = seed & 0xFFFFFFFF, frame_index, samples_per_iter, mode
     p.macro_cell = macro_cell if macro_minmax is not None else 0
