@@ -189,7 +189,42 @@ typedef struct {
     int32_t pipe_depth;
     int32_t xcd_bands;
     int32_t adapt_max_exp;
+    /* Path tracing (pipeline = CINR_PATH_TRACE): the second wavefront
+     * pipeline of Section 5.1, Woodcock delta tracking through the same
+     * sampler and cache.  The medium has extinction pt_density * TF opacity
+     * per LoD-0 voxel (pt_density is the majorant), the TF colour as
+     * scattering albedo and an isotropic phase function.  Each path tracks
+     * the primary ray; at a real collision its throughput takes the albedo, a
+     * shadow ray toward pt_light_dir (unit vector, used as given) is tracked
+     * the same way and adds throughput * pt_light when it leaves the box
+     * (pt_light carries the phase factor), then the path scatters in a
+     * uniform direction (Marsaglia's method), up to pt_max_bounces
+     * collisions; a scattered ray that leaves the box adds throughput *
+     * pt_ambient.  A tentative collision is real when a uniform falls below
+     * the TF opacity at the sampled value (binary32); free flights are
+     * -ln(xi) / pt_density with xi = ((r >> 8) + 1) 2^-24, the logarithm in
+     * binary64 rounded to binary32.  Random words: Philox-4x32-10, key
+     * (pt_seed, frame_index), counter (pixel, event, 0, 0), events numbered
+     * per pixel across its paths; a pixel draws at most 8000 events per frame
+     * (a path cut by that budget is dropped).  The pixel's colour is the mean
+     * radiance of its pt_spp paths, its opacity the fraction of those whose
+     * primary ray collides.  From a true miss on, up to min(samples_per_iter,
+     * 8) tentative collisions of the segment are looked up and inferred
+     * together (the wavefront step of the ray marcher); this changes the
+     * lookup counts, never a path.  step, ert_threshold and the tuning
+     * fields are not used; adapt_max_exp must be 0.  The workspace is sized
+     * by cinr_path_workspace_size. */
+    int32_t pipeline;         /* cinr_pipeline */
+    float pt_density;         /* > 0 */
+    float pt_light_dir[3];
+    float pt_light[3];
+    float pt_ambient[3];
+    int32_t pt_max_bounces;   /* >= 1 */
+    int32_t pt_spp;           /* 1 .. 65535 */
+    uint32_t pt_seed;
 } cinr_render_params;
+
+typedef enum { CINR_RAY_MARCH = 0, CINR_PATH_TRACE = 1 } cinr_pipeline;
 
 /* Frame counters written (not accumulated) by cinr_render_frame. */
 typedef struct {
@@ -204,7 +239,10 @@ typedef enum {
     CINR_DUMP_RANK = 3,         /* int64 [n_keys]: rank, -1 undefined */
     CINR_DUMP_REQ_COUNT = 4,    /* uint32 [n_keys]: requests of the last frame (keep_request_counts) */
     CINR_DUMP_REQUEST_LIST = 5, /* int32 [n]: keys selected at the end of the last frame, in order */
-    CINR_DUMP_MISS_LIST = 6,    /* {int32 pixel, int32 k, float x, y, z} [n] of the last frame, sorted by (pixel, k) */
+    CINR_DUMP_MISS_LIST = 6,    /* {int32 pixel, int32 k, float x, y, z} [n] of the last frame, sorted by (pixel, k);
+                                   k is the sample index (ray marching) or the event index (path tracing, where a
+                                   (pixel, k) pair can repeat: an event looked up ahead after a true miss is drawn
+                                   again by the segment that follows a real collision) */
     CINR_DUMP_EVICTION_LOG = 7, /* {int32 stamp, slot, old_key, new_key} [n] since creation */
     CINR_DUMP_POOL = 8          /* pool_dtype values [pool_bricks][B][B][B]: float, or binary16 bits */
 } cinr_dump_kind;
@@ -280,6 +318,16 @@ cinr_status cinr_cache_prefill(cinr_cache cache, const int32_t* d_keys, int32_t 
  * records, counters, macro-cell flags) for a width x height image. */
 cinr_status cinr_render_workspace_size(cinr_volume vol, int32_t width, int32_t height, int32_t samples_per_iter,
                                        size_t* bytes);
+
+/* Size of the render workspace of the path tracer: the ray marcher's plus
+ * 128 bytes of path state per pixel (width * height < 2^27). */
+cinr_status cinr_path_workspace_size(cinr_volume vol, int32_t width, int32_t height, int32_t samples_per_iter,
+                                     size_t* bytes);
+
+/* The path tracer's free-flight lengths for n random words (device arrays):
+ * d_out[i] = -ln(((d_words[i] >> 8) + 1) * 2^-24), computed in binary64 and
+ * rounded to binary32, exactly as the renderer draws them. */
+cinr_status cinr_pt_free_flight(const uint32_t* d_words, int64_t n, float* d_out, void* stream);
 
 /* Renders one frame into d_rgba (f32 [H][W][4], straight colour and
  * opacity, no background).

@@ -1144,6 +1144,11 @@ float orc_pt_free_flight(uint32_t r) {
     return (float)(-log(xi));
 }
 
+void orc_pt_free_flights(const uint32_t* words, int64_t n, float* out) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) out[i] = orc_pt_free_flight(words[i]);
+}
+
 float orc_pt_segment_exit(const float p[3], const float d[3], const float vm1[3]) {
     float t = INFINITY;
     for (int a = 0; a < 3; ++a) {

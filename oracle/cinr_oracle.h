@@ -165,6 +165,7 @@ orc_cache* orc_cache_create(const orc_inr* m, const orc_cache_desc* d);
  *   next, each interpolation rounded once), clamped to [0, 1]. */
 float orc_pt_uniform(uint32_t r);
 float orc_pt_free_flight(uint32_t r);
+void orc_pt_free_flights(const uint32_t* words, int64_t n, float* out);
 uint32_t orc_pt_direction(uint32_t pix, uint32_t n0, const uint32_t key[2], float d[3]);
 float orc_pt_segment_exit(const float p[3], const float d[3], const float vm1[3]);
 float orc_tf_alpha32(const float* tf, float v);

@@ -90,6 +90,7 @@ def lib():
             "orc_round_half": (C.c_double, [C.c_double]),
             "orc_pt_uniform": (C.c_float, [C.c_uint32]),
             "orc_pt_free_flight": (C.c_float, [C.c_uint32]),
+            "orc_pt_free_flights": (None, [P, i64, P]),
             "orc_pt_direction": (C.c_uint32, [C.c_uint32, C.c_uint32, P, P]),
             "orc_pt_segment_exit": (C.c_float, [P, P, P]),
             "orc_tf_alpha32": (C.c_float, [P, C.c_float]),
@@ -307,6 +308,14 @@ def pt_uniform(r):
 
 def pt_free_flight(r):
     return float(lib().orc_pt_free_flight(int(r) & 0xFFFFFFFF))
+
+
+def pt_free_flights(words):
+    """Free-flight lengths of an array of random words (vectorised)."""
+    w = np.ascontiguousarray(words, np.uint32)
+    out = np.empty(w.shape, np.float32)
+    lib().orc_pt_free_flights(_ptr(w), w.size, _ptr(out))
+    return out
 
 
 def pt_direction(pix, n0, key):

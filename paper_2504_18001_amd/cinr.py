@@ -55,7 +55,46 @@ class RenderParams(C.Structure):
     _fields_ = [("step", C.c_float), ("lod_scale", C.c_float), ("ert_threshold", C.c_float), ("seed", C.c_uint32),
                 ("frame_index", C.c_int32), ("samples_per_iter", C.c_int32), ("mode", C.c_int32),
                 ("mlp_dtype", C.c_int32), ("pipe_depth", C.c_int32), ("xcd_bands", C.c_int32),
-                ("adapt_max_exp", C.c_int32)]
+                ("adapt_max_exp", C.c_int32),
+                ("pipeline", C.c_int32), ("pt_density", C.c_float), ("pt_light_dir", C.c_float * 3),
+                ("pt_light", C.c_float * 3), ("pt_ambient", C.c_float * 3), ("pt_max_bounces", C.c_int32),
+                ("pt_spp", C.c_int32), ("pt_seed", C.c_uint32)]
+
+
+RAY_MARCH, PATH_TRACE = 0, 1
+
+
+def _set_path(p, path):
+    """Path-tracing fields of RenderParams p from a dict (density, light_dir,
+    light, ambient, max_bounces, spp, seed), or ray marching for None."""
+    if path is None:
+        p.pipeline = RAY_MARCH
+        return
+    p.pipeline = PATH_TRACE
+    p.pt_density = float(path.get("density", 0.05))
+    for a in range(3):
+        p.pt_light_dir[a] = float(path.get("light_dir", (0.0, 0.0, 1.0))[a])
+        p.pt_light[a] = float(path.get("light", (1.0, 1.0, 1.0))[a])
+        p.pt_ambient[a] = float(path.get("ambient", (0.0, 0.0, 0.0))[a])
+    p.pt_max_bounces = int(path.get("max_bounces", 1))
+    p.pt_spp = int(path.get("spp", 1))
+    p.pt_seed = int(path.get("seed", 0)) & 0xFFFFFFFF
+
+
+def _workspace_size(vol, width, height, samples_per_iter, path):
+    need = C.c_size_t()
+    fn = lib().cinr_path_workspace_size if path is not None else lib().cinr_render_workspace_size
+    _check(fn(vol.h, width, height, samples_per_iter, C.byref(need)))
+    return need.value
+
+
+def pt_free_flight(words):
+    """The path tracer's free-flight lengths for a device tensor of 32-bit
+    random words (int32 bit patterns), on the GPU."""
+    w = words.to(torch.int32).contiguous()
+    out = torch.empty(w.shape, dtype=torch.float32, device=w.device)
+    _check(lib().cinr_pt_free_flight(_ptr(w), w.numel(), _ptr(out), _stream()))
+    return out
 
 
 class GridDesc(C.Structure):
@@ -114,6 +153,8 @@ def lib():
             "cinr_render_views": [P, i32, P, P],
             "cinr_tuned_launch": [P, i32, i32, P, P, P],
             "cinr_frame_graph_create": [P, i32, P, P],
+            "cinr_path_workspace_size": [P, i32, i32, i32, P],
+            "cinr_pt_free_flight": [P, i64, P, P],
             "cinr_frame_graph_render": [P, P, i32, P],
             "cinr_frame_graph_counts": [P, P, P, P],
             "cinr_frame_graph_destroy": [P],
@@ -354,11 +395,12 @@ class Renderer:
 
     def render(self, volume: Volume, cam, tf, step, lod_scale=0.0, frame_index=0, seed=0, ert_threshold=2.0,
                samples_per_iter=32, mode=CACHED, dtype="f32", cache: Cache = None, out=None, stats=None,
-               pipe_depth=0, xcd_bands=0, adapt_max_exp=0):
-        need = C.c_size_t()
-        _check(lib().cinr_render_workspace_size(volume.h, cam.width, cam.height, samples_per_iter, C.byref(need)))
-        if self.ws is None or self.ws.numel() < need.value:
-            self.ws = torch.empty(need.value, dtype=torch.uint8, device=self.device)
+               pipe_depth=0, xcd_bands=0, adapt_max_exp=0, path=None):
+        """path: None for ray marching, else the path tracer's parameters
+        (dict: density, light_dir, light, ambient, max_bounces, spp, seed)."""
+        need = _workspace_size(volume, cam.width, cam.height, samples_per_iter, path)
+        if self.ws is None or self.ws.numel() < need:
+            self.ws = torch.empty(need, dtype=torch.uint8, device=self.device)
         out = torch.empty((cam.height, cam.width, 4), dtype=torch.float32, device=self.device) if out is None else out
         tf = tf if torch.is_tensor(tf) else torch.as_tensor(np.asarray(tf, np.float32))
         tf = tf.to(device=self.device, dtype=torch.float32).contiguous()
@@ -369,6 +411,7 @@ class Renderer:
         p.mode, p.mlp_dtype = int(mode), _dtype(dtype)
         p.pipe_depth, p.xcd_bands = int(pipe_depth), int(xcd_bands)
         p.adapt_max_exp = int(adapt_max_exp)
+        _set_path(p, path)
         cd = camera_desc(cam)
         st = self.stats if stats is None else stats
         _check(lib().cinr_render_frame(cache.h if cache is not None else None, volume.h, C.byref(cd), _ptr(tf),
@@ -467,7 +510,7 @@ class MultiViewRenderer:
         self._keep = []
 
     def describe(self, views, step, lod_scale=0.0, frame_index=0, seed=0, ert_threshold=2.0, samples_per_iter=32,
-                 dtype="f32", outs=None, pipe_depth=0, xcd_bands=0, adapt_max_exp=0):
+                 dtype="f32", outs=None, pipe_depth=0, xcd_bands=0, adapt_max_exp=0, path=None):
         """The cinr_view array of `views` (list of (volume, camera, tf)) and
         their output images; the TF tensors are kept alive by the renderer."""
         n = len(views)
@@ -475,10 +518,9 @@ class MultiViewRenderer:
         outs = outs or [None] * n
         keep = []
         for i, (vol, cam, tf) in enumerate(views):
-            need = C.c_size_t()
-            _check(lib().cinr_render_workspace_size(vol.h, cam.width, cam.height, samples_per_iter, C.byref(need)))
-            if self.ws[i] is None or self.ws[i].numel() < need.value:
-                self.ws[i] = torch.empty(need.value, dtype=torch.uint8, device=self.device)
+            need = _workspace_size(vol, cam.width, cam.height, samples_per_iter, path)
+            if self.ws[i] is None or self.ws[i].numel() < need:
+                self.ws[i] = torch.empty(need, dtype=torch.uint8, device=self.device)
             if outs[i] is None:
                 outs[i] = torch.empty((cam.height, cam.width, 4), dtype=torch.float32, device=self.device)
             t = tf if torch.is_tensor(tf) else torch.as_tensor(np.asarray(tf, np.float32))
@@ -494,6 +536,7 @@ class MultiViewRenderer:
             p.mode, p.mlp_dtype = CACHED, _dtype(dtype)
             p.pipe_depth, p.xcd_bands = int(pipe_depth), int(xcd_bands)
             p.adapt_max_exp = int(adapt_max_exp)
+            _set_path(p, path)
             v.d_rgba = outs[i].data_ptr()
             v.d_stats = self.stats[i].data_ptr()
             v.d_workspace = self.ws[i].data_ptr()
@@ -502,10 +545,10 @@ class MultiViewRenderer:
         return arr, outs
 
     def render(self, cache: Cache, views, step, lod_scale=0.0, frame_index=0, seed=0, ert_threshold=2.0,
-               samples_per_iter=32, dtype="f32", outs=None, pipe_depth=0, xcd_bands=0, adapt_max_exp=0):
+               samples_per_iter=32, dtype="f32", outs=None, pipe_depth=0, xcd_bands=0, adapt_max_exp=0, path=None):
         """views: list of (volume, camera, tf); returns the list of RGBA images."""
         arr, outs = self.describe(views, step, lod_scale, frame_index, seed, ert_threshold, samples_per_iter, dtype,
-                                  outs, pipe_depth, xcd_bands, adapt_max_exp)
+                                  outs, pipe_depth, xcd_bands, adapt_max_exp, path)
         _check(lib().cinr_render_views(cache.h, len(views), arr, _stream()))
         return outs
 
@@ -522,12 +565,12 @@ class FrameGraph:
     frames.  Owns the views' workspaces, images and statistics."""
 
     def __init__(self, cache: Cache, views, step, lod_scale=0.0, seed=0, ert_threshold=2.0, samples_per_iter=32,
-                 dtype="f32", pipe_depth=0, xcd_bands=0, adapt_max_exp=0, device="cuda"):
+                 dtype="f32", pipe_depth=0, xcd_bands=0, adapt_max_exp=0, device="cuda", path=None):
         self.cache = cache
         self.volumes = [v for v, _, _ in views]
         self.mv = MultiViewRenderer(len(views), device)
         arr, self.outs = self.mv.describe(views, step, lod_scale, 0, seed, ert_threshold, samples_per_iter, dtype,
-                                          None, pipe_depth, xcd_bands, adapt_max_exp)
+                                          None, pipe_depth, xcd_bands, adapt_max_exp, path)
         self.tfs = list(self.mv._keep)
         self.n = len(views)
         h = C.c_void_p()

@@ -561,9 +561,10 @@ struct RenderLayout {
     uint32_t* gate;  // frame-end gate (view 0's is the frame's)
     uint8_t* cell_code;  // adaptive sampling: per macro-cell step codes
     uint8_t* vexp;       // adaptive sampling: step exponent of each gathered sample
+    PtState* pts;        // path tracing: per-pixel path state (null for ray marching)
 };
 
-static size_t render_layout(int64_t npix, int32_t S, int64_t n_cells, RenderLayout* r, void* base) {
+static size_t render_layout(int64_t npix, int32_t S, int64_t n_cells, bool path, RenderLayout* r, void* base) {
     Carver cv(base);
     RenderLayout x;
     x.live0 = cv.take<int32_t>(npix);
@@ -581,14 +582,33 @@ static size_t render_layout(int64_t npix, int32_t S, int64_t n_cells, RenderLayo
     x.gate = cv.take<uint32_t>(1);
     x.cell_code = cv.take<uint8_t>((size_t)(n_cells > 0 ? n_cells : 1));
     x.vexp = cv.take<uint8_t>((size_t)npix * S);
+    x.pts = path ? cv.take<PtState>((size_t)npix) : nullptr;
     if (r) *r = x;
     return cv.off;
 }
 
+// Pixels of a path-traced image: the inference writes into the path state at
+// 32-bit word indices pixel * 32 + k.
+constexpr int64_t kMaxPathPixels = int64_t(1) << 27;
+
 extern "C" cinr_status cinr_render_workspace_size(cinr_volume v, int32_t W, int32_t H, int32_t S, size_t* bytes) {
     if (!v || !bytes || W < 1 || H < 1 || S < 1 || S > 64) return fail(CINR_INVALID_ARG, "invalid arguments");
     if ((int64_t)W * H * S > 0xFFFFFFFFll) return fail(CINR_INVALID_ARG, "width*height*samples_per_iter >= 2^32");
-    *bytes = render_layout((int64_t)W * H, S, v->n_cells, nullptr, nullptr);
+    *bytes = render_layout((int64_t)W * H, S, v->n_cells, false, nullptr, nullptr);
+    return CINR_OK;
+}
+
+extern "C" cinr_status cinr_path_workspace_size(cinr_volume v, int32_t W, int32_t H, int32_t S, size_t* bytes) {
+    if (!v || !bytes || W < 1 || H < 1 || S < 1 || S > 64) return fail(CINR_INVALID_ARG, "invalid arguments");
+    if ((int64_t)W * H >= kMaxPathPixels) return fail(CINR_INVALID_ARG, "width*height >= 2^27 for the path tracer");
+    if ((int64_t)W * H * S > 0xFFFFFFFFll) return fail(CINR_INVALID_ARG, "width*height*samples_per_iter >= 2^32");
+    *bytes = render_layout((int64_t)W * H, S, v->n_cells, true, nullptr, nullptr);
+    return CINR_OK;
+}
+
+extern "C" cinr_status cinr_pt_free_flight(const uint32_t* d_words, int64_t n, float* d_out, void* stream) {
+    if (n < 0 || (n > 0 && (!d_words || !d_out))) return fail(CINR_INVALID_ARG, "invalid arguments");
+    HIP_TRY(launch_pt_free_flight(d_words, n, d_out, (hipStream_t)stream));
     return CINR_OK;
 }
 
@@ -679,6 +699,20 @@ cinr_status prepare_view(cinr_cache c, cinr_volume v, const cinr_camera* cam, co
         return fail(CINR_INVALID_ARG, "samples_per_iter must be in [1, 64]");
     if (rp->adapt_max_exp < 0 || rp->adapt_max_exp > 14)
         return fail(CINR_INVALID_ARG, "adapt_max_exp must be in [0, 14]");
+    if (rp->pipeline != CINR_RAY_MARCH && rp->pipeline != CINR_PATH_TRACE)
+        return fail(CINR_INVALID_ARG, "pipeline = %d", rp->pipeline);
+    const bool path = rp->pipeline == CINR_PATH_TRACE;
+    if (path) {
+        if (!(rp->pt_density > 0.0f) || !isfinite(rp->pt_density)) return fail(CINR_INVALID_ARG, "pt_density must be > 0");
+        if (rp->pt_max_bounces < 1) return fail(CINR_INVALID_ARG, "pt_max_bounces must be >= 1");
+        if (rp->pt_spp < 1 || rp->pt_spp > 65535) return fail(CINR_INVALID_ARG, "pt_spp must be in [1, 65535]");
+        if (rp->adapt_max_exp != 0) return fail(CINR_INVALID_ARG, "the path tracer has no adaptive sampling rate");
+        for (int a = 0; a < 3; ++a)
+            if (!isfinite(rp->pt_light_dir[a]) || !isfinite(rp->pt_light[a]) || !isfinite(rp->pt_ambient[a]))
+                return fail(CINR_INVALID_ARG, "non-finite light parameters");
+        if ((int64_t)cam->width * cam->height >= kMaxPathPixels)
+            return fail(CINR_INVALID_ARG, "width*height >= 2^27 for the path tracer");
+    }
     const bool cached = rp->mode == CINR_CACHED;
     if (cached && !c) return fail(CINR_INVALID_ARG, "the cached mode needs a cache");
     const int vi = cached ? c->index_of(v) : -1;
@@ -689,20 +723,24 @@ cinr_status prepare_view(cinr_cache c, cinr_volume v, const cinr_camera* cam, co
     const int64_t npix = (int64_t)cam->width * cam->height;
     const int32_t S = rp->samples_per_iter;
     if (npix * S > 0xFFFFFFFFll) return fail(CINR_INVALID_ARG, "width*height*samples_per_iter >= 2^32");
-    const size_t need = render_layout(npix, S, v->n_cells, nullptr, nullptr);
+    const size_t need = render_layout(npix, S, v->n_cells, path, nullptr, nullptr);
     if (!d_ws || ws_bytes < need) return fail(CINR_OUT_OF_MEMORY, "render workspace of %zu bytes < %zu needed", ws_bytes, need);
-    // bound on the wavefront iterations: every iteration advances a live ray by >= S samples
-    double diag = 0.0;
-    for (int a = 0; a < 3; ++a) diag += (double)(v->desc.dims[a] - 1) * (double)(v->desc.dims[a] - 1);
-    const double max_samples = ceil(sqrt(diag) / (double)rp->step) + 2.0;
-    const int64_t max_iters = (int64_t)ceil(max_samples / S) + 2;
+    // bound on the wavefront iterations: every iteration advances a live ray
+    // by >= S samples; a waiting path consumes >= 1 event per iteration
+    int64_t max_iters = (int64_t)kPtMaxEvents + 2;
+    if (!path) {
+        double diag = 0.0;
+        for (int a = 0; a < 3; ++a) diag += (double)(v->desc.dims[a] - 1) * (double)(v->desc.dims[a] - 1);
+        const double max_samples = ceil(sqrt(diag) / (double)rp->step) + 2.0;
+        max_iters = (int64_t)ceil(max_samples / S) + 2;
+    }
     if (max_iters > kMaxIters) return fail(CINR_INVALID_ARG, "step too small for samples_per_iter (needs %lld iterations)", (long long)max_iters);
     r.v = v;
     r.npix = npix;
     r.max_iters = max_iters;
     r.queued = npix;
     r.prec = rp->mlp_dtype;
-    render_layout(npix, S, v->n_cells, &r.L, d_ws);
+    render_layout(npix, S, v->n_cells, path, &r.L, d_ws);
     const RenderLayout& L = r.L;
     FrameDev& f = r.f;
     f = FrameDev{};
@@ -749,12 +787,28 @@ cinr_status prepare_view(cinr_cache c, cinr_volume v, const cinr_camera* cam, co
     f.claim = L.claim;
     f.tf = d_tf;
     f.rgba = reinterpret_cast<float4*>(d_rgba);
+    if (path) {
+        PtDev& pd = f.path;
+        pd.on = 1;
+        pd.inv_sigma = 1.0f / rp->pt_density;
+        for (int a = 0; a < 3; ++a) {
+            pd.ldir[a] = rp->pt_light_dir[a];
+            pd.light[a] = rp->pt_light[a];
+            pd.ambient[a] = rp->pt_ambient[a];
+        }
+        pd.bounces = rp->pt_max_bounces;
+        pd.spp = rp->pt_spp;
+        pd.gather = S < kPtGather ? S : kPtGather;
+        pd.seed = rp->pt_seed;
+        pd.st = L.pts;
+    }
     f.k_next = L.k_next;
     f.live0 = L.live0;
     f.live1 = L.live1;
     f.pend_pix = L.pend_pix;
     f.pend_n = L.pend_n;
-    f.vals = L.vals;
+    // the path tracer's misses are inferred straight into its path state
+    f.vals = path ? reinterpret_cast<float*>(L.pts) : L.vals;
     f.miss_rec = L.miss_rec;
     f.ctr = L.ctr;
     f.stats = d_stats ? reinterpret_cast<unsigned long long*>(d_stats) : L.stats;

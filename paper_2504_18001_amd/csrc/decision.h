@@ -174,4 +174,58 @@ __device__ inline BrickAddr brick_addr(const LodGeom& lg, int32_t brick, FastDiv
     return r;
 }
 
+// Path tracing draws (Section 5.1; binary32 decision plane).
+// A uniform in [0, 1) from the top 24 bits of a random word.
+__device__ inline float pt_uniform(uint32_t r) { return (float)(r >> 8) * 5.9604644775390625e-08f; }
+
+// Free-flight length in units of 1 / majorant: -ln(xi), xi = ((r >> 8) + 1)
+// 2^-24 in (0, 1], the logarithm in binary64 rounded once to binary32.
+__device__ inline float pt_free_flight(uint32_t r) {
+    const double xi = ((double)(r >> 8) + 1.0) * 5.9604644775390625e-08;
+    return (float)(-log(xi));
+}
+
+// Marsaglia (1972): (u1, u2) uniform in [-1, 1)^2, accepted when
+// s = u1^2 + u2^2 is in (0, 1); then (2 u1 sqrt(1-s), 2 u2 sqrt(1-s), 1-2s)
+// is uniform on the unit sphere.
+__device__ inline bool pt_marsaglia(const uint32_t r[4], float d[3]) {
+    const float u1 = 2.0f * pt_uniform(r[0]) - 1.0f;
+    const float u2 = 2.0f * pt_uniform(r[1]) - 1.0f;
+    const float a = u1 * u1;
+    const float b = u2 * u2;
+    const float s = a + b;
+    if (s >= 1.0f || s == 0.0f) return false;
+    const float q = __builtin_sqrtf(1.0f - s);
+    d[0] = (2.0f * u1) * q;
+    d[1] = (2.0f * u2) * q;
+    d[2] = 1.0f - 2.0f * s;
+    return true;
+}
+
+// Distance from p (in the box [0, vm1]) along d to the box boundary.
+__device__ inline float pt_segment_exit(const float p[3], const float d[3], const float vm1[3]) {
+    float t = __builtin_inff();
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] == 0.0f) continue;
+        const float wall = d[a] > 0.0f ? vm1[a] : 0.0f;
+        const float ta = (wall - p[a]) / d[a];
+        if (ta < t) t = ta;
+    }
+    if (!(t >= 0.0f) || t == __builtin_inff()) t = 0.0f;
+    return t;
+}
+
+// Position o + t d, clamped to the box.
+__device__ inline void pt_pos(const float o[3], const float d[3], float t, const float vm1[3], float p[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float td = t * d[a];
+        float q = o[a] + td;
+        if (q < 0.0f) q = 0.0f;
+        if (q > vm1[a]) q = vm1[a];
+        p[a] = q;
+    }
+}
+
 }  // namespace cinr

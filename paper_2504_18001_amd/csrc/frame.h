@@ -2,6 +2,8 @@
 // launch functions of the render and cache kernels.
 #pragma once
 
+#include <stddef.h>
+
 #include "common.h"
 #include "decision.h"
 
@@ -91,6 +93,37 @@ struct FrameVar {
 };
 static_assert(sizeof(FrameVar) == 128, "FrameVar is copied as 32 words");
 
+// Path tracing: the state of a pixel's paths between wavefront iterations
+// (a pixel waits for the inference of its true misses), 128 bytes.
+enum : uint32_t { PT_PRIMARY = 0, PT_SCATTER = 1, PT_SHADOW = 2 };
+constexpr int kPtGather = 8;         // tentative collisions looked up from a true miss on, at most
+constexpr uint32_t kPtMaxEvents = 8000;  // Philox events per pixel and frame
+constexpr int kPtValsWord = 24;      // word offset of `vals` (inference writes there)
+struct PtState {
+    float o[3], d[3];      // current segment: origin and direction
+    float t, te;           // t before the next event; end of the segment
+    float beta[3];         // throughput of the path in progress
+    float lp[3];           // radiance of the path in progress
+    float sum[3];          // radiance of the completed paths
+    uint32_t n;            // next event
+    uint32_t path;         // index of the path in progress
+    uint32_t done, hits;   // completed paths, and those whose primary ray collided
+    uint32_t kind;         // PT_* | bounce << 2 | (primary collision) << 31
+    uint32_t nc;           // values gathered from event n on
+    uint32_t pad;
+    float vals[kPtGather]; // their values (-1: skipped sample)
+};
+static_assert(sizeof(PtState) == 128 && offsetof(PtState, vals) == 4 * kPtValsWord, "PtState layout");
+
+struct PtDev {
+    int32_t on;            // the frame runs the path tracer
+    float inv_sigma;       // 1 / pt_density (binary32)
+    float ldir[3], light[3], ambient[3];
+    int32_t bounces, spp, gather;
+    uint32_t seed;
+    PtState* st;           // [W*H]
+};
+
 struct FrameDev {
     int32_t W, H;  // image size (fixed for a view; the camera itself is in *var)
     FrameVar* var;            // device copy of the frame's values
@@ -117,6 +150,7 @@ struct FrameDev {
     int32_t n_cells;
     uint8_t* cell_code;  // [n_cells]
     uint8_t* vexp;       // [W*H*S] step exponent of each gathered sample
+    PtDev path;          // path tracing (path.on), else ray marching
     uint32_t* claim;     // [2][8] work-unit counters of the march kernel (one set per iteration
                          // parity), kClaimStride words apart
     CacheGeom geo;
@@ -230,6 +264,7 @@ hipError_t launch_frame_begin(const FrameDev& f, int32_t n_iter_ctr, const float
                               CacheCtr* cctr, hipStream_t s);
 hipError_t launch_march(const FrameDev& f, int it, int64_t max_rays, hipStream_t s);
 hipError_t launch_shade(const FrameDev& f, int it, int64_t cap_rays, hipStream_t s);
+hipError_t launch_pt_free_flight(const uint32_t* words, int64_t n, float* out, hipStream_t s);
 // `gate` (nullable) on the frame-end launches: they do nothing unless *gate is
 // non-zero, which k_pending_gather sets when no view has a ray pending after
 // its first march.  The end of a frame can so be queued before the host has

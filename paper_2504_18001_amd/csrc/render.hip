@@ -686,6 +686,363 @@ __global__ __launch_bounds__(kBlock) void k_shade(FrameDev f, int32_t it) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Path tracing (Section 5.1): the second wavefront pipeline, Woodcock delta
+// tracking through the same sampler.  One lane per pixel runs the pixel's
+// paths one after the other until they are done or a tentative collision is a
+// true miss; then the next tentative collisions of the segment (up to
+// `gather`, those before its end) are looked up too, their misses queued for
+// inference straight into the pixel's state, and the pixel resumes in the
+// next iteration.  Lookups count, request and stamp exactly as the ray
+// marcher's samples.
+// ---------------------------------------------------------------------------
+
+// TF at v (rows floor(255 v) and the next, each interpolation rounded once),
+// opacity clamped to [0, 1]: the lookup of the compositing step.
+__device__ inline float4 tf_at(const float4* tfs, float v) {
+    const float x = v * 255.0f;
+    int32_t i0 = (int32_t)x;
+    i0 = i0 > 254 ? 254 : (i0 < 0 ? 0 : i0);
+    const float t = x - (float)i0;
+    const float4 a = tfs[i0], b = tfs[i0 + 1];
+    float4 r;
+    r.x = __builtin_fmaf(t, b.x - a.x, a.x);
+    r.y = __builtin_fmaf(t, b.y - a.y, a.y);
+    r.z = __builtin_fmaf(t, b.z - a.z, a.z);
+    r.w = __builtin_fmaf(t, b.w - a.w, a.w);
+    r.w = r.w < 0.0f ? 0.0f : (r.w > 1.0f ? 1.0f : r.w);
+    return r;
+}
+
+// A pixel's paths in registers (PtState without the gathered values, which
+// are read from memory as they are consumed).
+struct PtLane {
+    float o[3], d[3], t, te, beta[3], lp[3], sum[3];
+    uint32_t n, path, done, hits, kind, nc, gi;
+
+    __device__ void load(const PtState& g) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            o[a] = g.o[a];
+            d[a] = g.d[a];
+            beta[a] = g.beta[a];
+            lp[a] = g.lp[a];
+            sum[a] = g.sum[a];
+        }
+        t = g.t;
+        te = g.te;
+        n = g.n;
+        path = g.path;
+        done = g.done;
+        hits = g.hits;
+        kind = g.kind;
+        nc = g.nc;
+        gi = 0;
+    }
+    __device__ void store(PtState& g) const {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            g.o[a] = o[a];
+            g.d[a] = d[a];
+            g.beta[a] = beta[a];
+            g.lp[a] = lp[a];
+            g.sum[a] = sum[a];
+        }
+        g.t = t;
+        g.te = te;
+        g.n = n;
+        g.path = path;
+        g.done = done;
+        g.hits = hits;
+        g.kind = kind;
+        g.nc = nc;
+    }
+    // a new path: the primary ray's segment
+    __device__ void begin(const CamDev& cam, const float vm1[3], int32_t i, int32_t j) {
+        float ts, te_;
+        ray_setup(cam, vm1, i, j, o, d, ts, te_);
+        t = ts;
+        te = te_;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            beta[a] = 1.0f;
+            lp[a] = 0.0f;
+        }
+        kind = PT_PRIMARY;
+        nc = gi = 0;
+    }
+    // a new segment from o along dir
+    __device__ void segment(const float dir[3], uint32_t k, const float vm1[3]) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) d[a] = dir[a];
+        t = 0.0f;
+        te = pt_segment_exit(o, d, vm1);
+        kind = (kind & ~3u) | k;
+        nc = gi = 0;
+    }
+};
+
+// The lane's pixel after its last path (or the event budget): the mean over
+// the completed paths.
+__device__ inline float4 pt_pixel_value(const PtLane& s) {
+    if (s.done == 0) return make_float4(0.f, 0.f, 0.f, 0.f);
+    const float J = (float)s.done;
+    return make_float4(s.sum[0] / J, s.sum[1] / J, s.sum[2] / J, (float)s.hits / J);
+}
+
+template <bool kLdsFlags, bool kFast, bool kHalf>
+__global__ __launch_bounds__(kBlock) void k_path(FrameDev f, int32_t it, uint32_t n0) {
+    const FrameHot hot = load_hot(f.var);  // before any store of this kernel
+    __shared__ float4 tfs[256];
+    __shared__ LodGeom lgs[kMaxLods];
+    __shared__ uint64_t sflags[kLdsFlags ? kMaxLdsFlagWords : 1];
+    tfs[threadIdx.x] = reinterpret_cast<const float4*>(f.tf)[threadIdx.x];
+    if (threadIdx.x < kMaxLods) lgs[threadIdx.x] = f.geo.lod[threadIdx.x];
+    if (kLdsFlags)
+        for (int32_t w = threadIdx.x; w < f.flag_words; w += kBlock) sflags[w] = f.flags[w];
+    // the counters of the next iteration were last used two launches ago
+    if (blockIdx.x == 0 && threadIdx.x < 8) f.claim[(((it + 1) & 1) * 8 + threadIdx.x) * kClaimStride] = 0u;
+    __shared__ MarchCold cold_s;
+    if (threadIdx.x == 0) {
+        MarchCold& c = cold_s;
+        c.cam = f.var->cam;
+        c.rgba = f.rgba;
+        c.pending = &f.ctr[it].pending;
+        c.misses = &f.ctr[it].misses;
+        c.miss_rec = f.miss_rec;
+        c.misslog = f.misslog;
+        c.n_misslog = f.n_misslog;
+        c.misslog_cap = f.misslog_cap;
+        c.req = f.req ? f.req + f.key_base : nullptr;
+        c.touched = f.touched;
+        c.n_touched = f.n_touched;
+        c.key_base = f.key_base;
+    }
+    __syncthreads();
+    using Flags = typename std::conditional<kLdsFlags, LdsFlags, GlobalFlags>::type;
+    Flags fl;
+    fl.w = kLdsFlags ? (const uint64_t*)sflags : (const uint64_t*)f.flags;
+    const ColdRef cold = &cold_s;
+    // iteration 0: all pixels in 8x8 tiles; later: the pixels left waiting
+    // by the previous iteration
+    const uint32_t n = it == 0 ? n0 : f.ctr[it - 1].pending;
+    const int32_t* cur = (it & 1) ? f.live1 : f.live0;
+    int32_t* next = (it & 1) ? f.live0 : f.live1;
+    UnitQueue q(f.claim + (it & 1) * 8 * kClaimStride, (n + 63u) / 64u, (uint32_t)f.xcd_bands);
+    const PtDev P = f.path;
+    const uint32_t key1 = (uint32_t)hot.frame;
+    Tally tally;
+    SlotCache sc;  // residency is constant within a frame
+    for (;;) {
+        const int64_t unit = q.claim();
+        if (unit < 0) break;
+        const uint32_t r = (uint32_t)unit * 64u + (uint32_t)lane_id();
+        bool has = r < n;
+        int32_t pix = 0, pi_ = 0, pj = 0;
+        PtLane s;
+        if (has) {
+            const CamDev cam = load_cam(cold->cam);
+            if (it == 0) {
+                const uint32_t tiles_x = (uint32_t)(cam.W + 7) / 8u;
+                const uint32_t tile = r >> 6, w = r & 63u;
+                pi_ = (int32_t)(tile % tiles_x) * 8 + (int32_t)(w & 7u);
+                pj = (int32_t)(tile / tiles_x) * 8 + (int32_t)(w >> 3);
+                has = pi_ < cam.W && pj < cam.H;
+                if (has) {
+                    pix = pj * cam.W + pi_;
+                    float o[3], d[3], ts, te;
+                    const bool hit = ray_setup(cam, f.vm1, pi_, pj, o, d, ts, te);
+                    if (!hit) {
+                        float4* rgba = cold->rgba;
+                        rgba[pix] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    }
+                    tally.rays += hit;
+                    has = hit;
+                    if (hit) {
+                        s.begin(cam, f.vm1, pi_, pj);
+                        s.n = s.path = s.done = s.hits = 0;
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) s.sum[a] = 0.0f;
+                    }
+                }
+            } else {
+                pix = cur[r];
+                pi_ = pix % cam.W;
+                pj = pix / cam.W;
+                s.load(P.st[pix]);
+            }
+        }
+        if (__ballot(has) == 0ull) continue;
+        RayBook book;
+        bool pend = false, fin = false;
+        float t_miss = 0.0f;  // t of the tentative collision that missed
+        if (has) {
+            const float* gvals = P.st[pix].vals;
+            while (!fin && !pend) {
+                if (s.n >= kPtMaxEvents) {  // budget spent: the path in progress is dropped
+                    fin = true;
+                    break;
+                }
+                const uint32_t e = s.n;
+                uint32_t w[4] = {(uint32_t)pix, e, 0u, 0u};
+                philox4x32_10(w, P.seed, key1);
+                const float step = pt_free_flight(w[0]) * P.inv_sigma;
+                const float t = s.t + step;
+                const uint32_t kind = s.kind & 3u;
+                bool collided = false;
+                float v = 0.0f;
+                float p[3];
+                if (t > s.te) {
+                    s.n = e + 1;
+                    s.t = t;
+                } else {
+                    pt_pos(s.o, s.d, t, f.vm1, p);
+                    bool skip;
+                    if (s.gi < s.nc) {
+                        v = gvals[s.gi];
+                        ++s.gi;
+                        skip = v < 0.0f;
+                    } else {
+                        const SampleRes sr = sample_cache<kFast, false, kHalf>(f, hot, lgs, fl, p, sc);
+                        tally.add(sr.status);
+                        book.note(f, hot.frame, cold, sr);
+                        if (sr.status == S_MISS) {
+                            pend = true;  // s.n and s.t stay before event e
+                            t_miss = t;
+                            break;
+                        }
+                        skip = sr.status == S_SKIP;
+                        v = sr.value;
+                    }
+                    s.n = e + 1;
+                    s.t = t;
+                    const float alpha = skip ? 0.0f : tf_at(tfs, v).w;
+                    if (pt_uniform(w[1]) >= alpha) continue;  // null collision
+                    collided = true;
+                }
+                // the segment ends: a real collision at p, or the segment is left
+                bool after_shadow = false;
+                if (collided && kind != PT_SHADOW) {
+                    if (kind == PT_PRIMARY) s.kind |= 1u << 31;
+                    const float4 c = tf_at(tfs, v);
+                    s.beta[0] *= c.x;
+                    s.beta[1] *= c.y;
+                    s.beta[2] *= c.z;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) s.o[a] = p[a];
+                    s.segment(P.ldir, PT_SHADOW, f.vm1);
+                    continue;
+                }
+                bool path_end = false;
+                if (collided) {  // the shadow ray is blocked
+                    after_shadow = true;
+                } else if (kind == PT_SHADOW) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) s.lp[a] = __builtin_fmaf(s.beta[a], P.light[a], s.lp[a]);
+                    after_shadow = true;
+                } else {
+                    if (kind == PT_SCATTER)
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) s.lp[a] = __builtin_fmaf(s.beta[a], P.ambient[a], s.lp[a]);
+                    path_end = true;
+                }
+                if (after_shadow) {
+                    const uint32_t bounce = ((s.kind >> 2) & 0xFFFFu) + 1u;
+                    s.kind = (s.kind & ~(0xFFFFu << 2)) | (bounce << 2);
+                    if ((int32_t)bounce == P.bounces) {
+                        path_end = true;
+                    } else {
+                        // isotropic scattering from the collision (the shadow ray's origin)
+                        float dir[3];
+                        bool ok = false;
+                        while (!ok) {
+                            if (s.n >= kPtMaxEvents) break;
+                            uint32_t wd[4] = {(uint32_t)pix, s.n, 0u, 0u};
+                            philox4x32_10(wd, P.seed, key1);
+                            ++s.n;
+                            ok = pt_marsaglia(wd, dir);
+                        }
+                        if (!ok) {
+                            fin = true;
+                            break;
+                        }
+                        s.segment(dir, PT_SCATTER, f.vm1);
+                    }
+                }
+                if (path_end) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) s.sum[a] += s.lp[a];
+                    s.hits += s.kind >> 31;
+                    s.done += 1;
+                    s.path += 1;
+                    if ((int32_t)s.path == P.spp) {
+                        fin = true;
+                    } else {
+                        const CamDev cam = load_cam(cold->cam);
+                        s.begin(cam, f.vm1, pi_, pj);
+                    }
+                }
+            }
+        }
+        // a true miss: look up the next tentative collisions of the segment
+        // as well, then queue the pixel and its misses
+        uint64_t mask = 0;
+        uint32_t nc = 0;
+        if (pend) {
+            float* sv = P.st[pix].vals;
+            mask = 1;
+            nc = 1;
+            float tg = t_miss;
+            while ((int32_t)nc < P.gather) {
+                uint32_t w[4] = {(uint32_t)pix, s.n + nc, 0u, 0u};
+                philox4x32_10(w, P.seed, key1);
+                const float t2 = tg + pt_free_flight(w[0]) * P.inv_sigma;
+                if (t2 > s.te) break;
+                tg = t2;
+                float p[3];
+                pt_pos(s.o, s.d, tg, f.vm1, p);
+                const SampleRes sr = sample_cache<kFast, false, kHalf>(f, hot, lgs, fl, p, sc);
+                tally.add(sr.status);
+                book.note(f, hot.frame, cold, sr);
+                if (sr.status == S_MISS)
+                    mask |= 1ull << nc;
+                else
+                    sv[nc] = sr.status == S_SKIP ? -1.0f : sr.value;
+                ++nc;
+            }
+            s.nc = nc;
+        }
+        const uint32_t qi = wave_reserve(pend ? 1u : 0u, cold->pending);
+        uint32_t mb = wave_reserve(pend ? (uint32_t)__popcll(mask) : 0u, cold->misses);
+        if (pend) {
+            next[qi] = pix;
+            float4* mr = cold->miss_rec;
+            float tg = s.t;
+            for (uint32_t k = 0; k < nc; ++k) {
+                uint32_t w[4] = {(uint32_t)pix, s.n + k, 0u, 0u};
+                philox4x32_10(w, P.seed, key1);
+                tg = tg + pt_free_flight(w[0]) * P.inv_sigma;
+                if ((mask >> k) & 1ull) {
+                    float p[3];
+                    pt_pos(s.o, s.d, tg, f.vm1, p);
+                    const uint32_t dst = (uint32_t)pix * 32u + (uint32_t)kPtValsWord + k;
+                    mr[mb++] = make_float4(p[0], p[1], p[2], __uint_as_float(dst));
+                    log_miss(cold, pix, (int32_t)(s.n + k), p);
+                }
+            }
+            s.store(P.st[pix]);
+        }
+        if (has) {
+            book.flush(cold);
+            if (fin) {
+                float4* rgba = cold->rgba;
+                rgba[pix] = pt_pixel_value(s);
+            }
+        }
+    }
+    tally.commit(f.stats);
+}
+
 // Frame statistics of one view; the cache manager's counters are those of the
 // whole frame (all views).  `reset` (the last view) clears the request list.
 // The view ran march launches 0 .. n-1, where n - 1 is the first iteration
@@ -791,17 +1148,66 @@ static hipError_t launch_march_h(const FrameDev& f, int it, int64_t n, uint32_t 
     }
 }
 
+// The path tracer's persistent grid, as resident_blocks for k_march.
+template <bool LDS, bool FAST, bool H>
+static hipError_t launch_path_t(const FrameDev& f, int it, int64_t max_px, uint32_t n0, hipStream_t s) {
+    static int cache[64] = {0};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    if (cache[dev] == 0) {
+        int per_cu = 0, n_cu = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_path<LDS, FAST, H>, kBlock, 0);
+        if (e != hipSuccess) return e;
+        e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        cache[dev] = (per_cu > 0 ? per_cu : 1) * (n_cu > 0 ? n_cu : 1);
+    }
+    int64_t b = (max_px + kBlock - 1) / kBlock;
+    if (b < 1) b = 1;
+    if (b > cache[dev]) b = cache[dev];
+    hipLaunchKernelGGL((k_path<LDS, FAST, H>), dim3((unsigned)b), dim3(kBlock), 0, s, f, it, n0);
+    return hipGetLastError();
+}
+
+template <bool H>
+static hipError_t launch_path_h(const FrameDev& f, int it, int64_t n, uint32_t n0, hipStream_t s) {
+    const uint64_t brick_bytes = 4096ull * (H ? 2ull : 4ull);
+    const bool fast = (f.mode != CINR_CACHED ||
+                       (f.geo.brick == 16 && (uint64_t)f.pool_bricks * brick_bytes < (1ull << 32))) &&
+                      (!f.flags || f.mc_N == 16);
+    const bool lds = f.flags && f.flag_words <= kMaxLdsFlagWords;
+    if (lds) return fast ? launch_path_t<true, true, H>(f, it, n, n0, s) : launch_path_t<true, false, H>(f, it, n, n0, s);
+    return fast ? launch_path_t<false, true, H>(f, it, n, n0, s) : launch_path_t<false, false, H>(f, it, n, n0, s);
+}
+
 hipError_t launch_march(const FrameDev& f, int it, int64_t max_rays, hipStream_t s) {
     // iteration 0 walks all pixels in 8x8 tiles; later iterations at most
     // `max_rays` re-queued rays
     const uint32_t n0 = (uint32_t)(((f.W + 7) / 8) * ((f.H + 7) / 8)) * 64u;
     const int64_t n = it == 0 ? (int64_t)n0 : max_rays;
+    if (f.path.on) return f.pool_f16 ? launch_path_h<true>(f, it, n, n0, s) : launch_path_h<false>(f, it, n, n0, s);
     if (f.pool_f16) return launch_march_h<true>(f, it, n, n0, s);
     return launch_march_h<false>(f, it, n, n0, s);
 }
 
 hipError_t launch_shade(const FrameDev& f, int it, int64_t cap_rays, hipStream_t s) {
+    // the path tracer consumes its gathered values in its next march launch
+    if (f.path.on) return hipSuccess;
     hipLaunchKernelGGL(k_shade, dim3(blocks_for(cap_rays, 2048)), dim3(kBlock), 0, s, f, it);
+    return hipGetLastError();
+}
+
+// Free-flight lengths of the path tracer for given random words.
+__global__ void k_pt_free_flight(const uint32_t* words, int64_t n, float* out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = pt_free_flight(words[i]);
+}
+
+hipError_t launch_pt_free_flight(const uint32_t* words, int64_t n, float* out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pt_free_flight, dim3(blocks_for(n, 4096)), dim3(kBlock), 0, s, words, n, out);
     return hipGetLastError();
 }
 

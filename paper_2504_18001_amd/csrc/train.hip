@@ -411,24 +411,9 @@ __global__ void k_train_reduce(const float* partial, int64_t n_waves, int32_t nw
         *loss = s * inv_n;
 }
 
-// Training points and targets: Philox-4x32-10 (Salmon et al. 2011) per point,
-// counter (i, step), key (seed); 24 bits per coordinate; target = trilinear
-// interpolation of the grid at x = clamp(u V - 0.5, 0, V - 1).
-__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
-        c[1] = (uint32_t)p1;
-        c[3] = (uint32_t)p0;
-        c[0] = n0;
-        c[2] = n2;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-}
+// Training points and targets: Philox-4x32-10 per point, counter (i, step),
+// key (seed); 24 bits per coordinate; target = trilinear interpolation of the
+// grid at x = clamp(u V - 0.5, 0, V - 1).
 
 __global__ void k_train_points(uint64_t seed, int64_t step, int64_t n, const float* grid, int32_t vx, int32_t vy,
                                int32_t vz, float* u_out, float* target) {

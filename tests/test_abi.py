@@ -195,3 +195,43 @@ def test_frame_graph_arguments_are_checked_before_any_device_work():
     assert L.cinr_frame_graph_render(None, None, 0, None) == INVALID_ARG
     a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
     assert L.cinr_frame_graph_counts(None, C.byref(a), C.byref(b), C.byref(c)) == INVALID_ARG
+
+
+def test_path_tracer_workspace_and_arguments():
+    _, h, _ = fake_volume(configs.ARCH_SMALL)
+    L = cinr.lib()
+    try:
+        rb, pb = C.c_size_t(), C.c_size_t()
+        assert L.cinr_render_workspace_size(h, 64, 48, 8, C.byref(rb)) == OK
+        assert L.cinr_path_workspace_size(h, 64, 48, 8, C.byref(pb)) == OK
+        # 128 bytes of path state per pixel on top of the ray marcher's workspace
+        assert 64 * 48 * 128 <= pb.value - rb.value < 64 * 48 * 128 + 512
+        assert L.cinr_path_workspace_size(h, 1 << 14, 1 << 13, 1, C.byref(pb)) == INVALID_ARG  # 2^27 pixels
+        assert L.cinr_pt_free_flight(None, -1, None, None) == INVALID_ARG
+        assert L.cinr_pt_free_flight(None, 0, None, None) == OK
+        cam = configs.SMALL.camera(0)
+        cam.width, cam.height = 64, 48
+        cd = cinr.camera_desc(cam)
+        ws = C.c_void_p(0x40000)  # placeholders: every call below fails before any device work
+
+        def params(**kw):
+            p = cinr.RenderParams()
+            p.step, p.lod_scale, p.ert_threshold, p.samples_per_iter = 0.5, 0.01, 2.0, 8
+            p.mode, p.mlp_dtype = cinr.UNCACHED_DIRECT, cinr.F32
+            cinr._set_path(p, dict(density=0.05, spp=2, max_bounces=2))
+            for k, v in kw.items():
+                setattr(p, k, v)
+            return p
+
+        def render(p, ws_bytes):
+            return L.cinr_render_frame(None, h, C.byref(cd), C.c_void_p(0x50000), C.byref(p), C.c_void_p(0x60000),
+                                       None, ws, ws_bytes, None)
+
+        big = pb.value * 4
+        for bad in (dict(pipeline=2), dict(pt_density=0.0), dict(pt_density=float("nan")), dict(pt_spp=0),
+                    dict(pt_spp=65536), dict(pt_max_bounces=0), dict(adapt_max_exp=1)):
+            assert render(params(**bad), big) == INVALID_ARG, bad
+        # a ray-marching workspace is too small for the path tracer
+        assert render(params(), rb.value) == -2
+    finally:
+        L.cinr_destroy_volume(h)
