@@ -156,6 +156,79 @@ def pool_f16_leg(vol, cams, tfs, w, Wm, K, dtype, ref_img):
     return res
 
 
+def path_leg(vol, cams, tfs, w, Wm, K, dtype, K_unc, oracle=True):
+    """Path tracing of the headline orbit (Woodcock delta tracking through the
+    same sampler and cache): cached frames (the headline cache, bricks decoded
+    in `dtype`) against uncached frames (every tentative collision inferred in
+    FP32), as the two path-tracing columns of Table 1."""
+    import torch
+    from paper_2504_18001_amd import cinr, configs
+    path = configs.PATH_HD512.as_dict()
+    nst = len(cinr.STAT_FIELDS)
+
+    def frames(r, c, rng, mode, dt, st=None, out=None):
+        for i, f in enumerate(rng):
+            r.render(vol, cams[f % w.n_frames], tfs[f % w.n_frames], w.step, w.lod_scale, frame_index=f, seed=w.seed,
+                     samples_per_iter=w.samples_per_iter, mode=mode, dtype=dt, cache=c, out=out,
+                     stats=None if st is None else st[i], path=path)
+
+    c = new_cache(vol, w)
+    r = cinr.Renderer()
+    out = torch.empty((w.height, w.width, 4), dtype=torch.float32, device="cuda")
+    st = torch.zeros((K, nst), dtype=torch.int64, device="cuda")
+    frames(r, c, range(Wm), cinr.CACHED, dtype, out=out)
+    torch.cuda.synchronize()
+    vol.set_timing(True, march_only=True)
+    t0 = time.perf_counter()
+    frames(r, c, range(Wm, Wm + K), cinr.CACHED, dtype, st, out)
+    torch.cuda.synchronize()
+    fps = K / (time.perf_counter() - t0)
+    vol.set_timing(False)
+    ms, n = vol.collect_timing()["march"]
+    tot = {k: int(v) for k, v in zip(cinr.STAT_FIELDS, st.sum(0).cpu().numpy())}
+    del c
+    ru = cinr.Renderer()
+    outu = torch.empty_like(out)
+    stu = torch.zeros((K_unc, nst), dtype=torch.int64, device="cuda")
+    frames(ru, None, range(Wm, Wm + 1), cinr.UNCACHED_DIRECT, "f32", out=outu)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    frames(ru, None, range(Wm, Wm + K_unc), cinr.UNCACHED_DIRECT, "f32", stu, outu)
+    torch.cuda.synchronize()
+    fps_u = K_unc / (time.perf_counter() - t0)
+    totu = {k: int(v) for k, v in zip(cinr.STAT_FIELDS, stu.sum(0).cpu().numpy())}
+    res = {"params": path, "fps_cached": round(fps, 2), "fps_uncached_fp32": round(fps_u, 2),
+           "speedup": round(fps / fps_u, 3),
+           "lookups_per_frame": tot["samples"] // K, "true_misses_per_frame": tot["misses"] // K,
+           "iterations_per_frame": round(tot["iterations"] / K, 2),
+           "path_kernel_ms_per_frame": round(ms / K, 4), "path_launches_per_frame": round(n / K, 2),
+           "uncached_inferred_per_frame": totu["misses"] // K_unc,
+           "uncached_iterations_per_frame": round(totu["iterations"] / K_unc, 2)}
+    if oracle:
+        res["oracle"] = path_oracle(w, cams, tfs, Wm, path)
+    return res
+
+
+def path_oracle(w, cams, tfs, f, path):
+    """The CPU oracle's uncached path tracer on 2048 sampled pixels of frame f:
+    pixels per second."""
+    import numpy as np
+    from oracle import oracle as O
+    from paper_2504_18001_amd import synth
+    table, weights = synth.random_inr_params(w.arch, w.inr_seed)
+    s, o = load_value_range(f"inr512/{w.inr_seed}")
+    m = O.OracleInr(w.arch, table, weights, s, o)
+    px = np.random.default_rng(4).choice(w.width * w.height, size=2048, replace=False).astype(np.int32)
+    p = O.make_params(w.step, w.lod_scale, seed=w.seed, frame_index=f, samples_per_iter=w.samples_per_iter,
+                      mode=O.UNCACHED_DIRECT, path=path)
+    tf = tfs[f % w.n_frames].cpu().numpy()
+    t0 = time.perf_counter()
+    O.render_pixels(m, cams[f % w.n_frames], tf, p, px)
+    dt = time.perf_counter() - t0
+    return {"pixels_per_s": round(px.size / dt, 1), "cores": O.get_threads(), "kind": "oracle",
+            "sample": f"uncached path tracing of 2048 random pixels of frame {f} ({dt:.2f} s)"}
+
+
 def multiview_leg(warmup, steps, dtype, oracle=True):
     """Frames of 16 views of 4 INRs through one shared cache (one cache
     manager pass and one multi-INR decode launch per frame)."""
@@ -401,6 +474,8 @@ def main():
     ap.add_argument("--no-multiview", action="store_true", help="skip the 16-view shared-cache leg")
     ap.add_argument("--no-adaptive", action="store_true", help="skip the adaptive sampling leg")
     ap.add_argument("--no-pool-f16", action="store_true", help="skip the binary16 pool leg")
+    ap.add_argument("--no-path", action="store_true", help="skip the path-tracing leg")
+    ap.add_argument("--path-uncached-steps", type=int, default=5)
     ap.add_argument("--multiview-steps", type=int, default=60)
     ap.add_argument("--no-training", action="store_true", help="skip the INR training leg")
     ap.add_argument("--training-steps", type=int, default=50)
@@ -540,6 +615,13 @@ def main():
         pool16 = pool_f16_leg(vol, cams, tfs, w, Wm, K, args.dtype, cached_img.cpu().numpy())
         log(f"[bench] binary16 pool: {pool16}")
 
+    # --- path tracing through the same sampler and cache ----------------------
+    pt = None
+    if not args.no_path:
+        pt = path_leg(vol, cams, tfs, w, Wm, K, args.dtype, args.path_uncached_steps,
+                      oracle=not args.no_cpu_baseline)
+        log(f"[bench] path tracing: {pt}")
+
     # --- uncached FP32 INR renderer on the same frames ------------------------
     KU = args.uncached_steps or K
     r2 = cinr.Renderer()
@@ -624,6 +706,7 @@ def main():
         "cached_other_precisions": other,
         "adaptive_sampling": {"tf": "the orbit's TFs with opacity x 0.1", "by_max_exponent": adaptive},
         "binary16_pool": pool16,
+        "path_tracing": pt,
         "bricks_per_s": {k: round(v, 1) for k, v in bps.items()},
         "psnr_cached_vs_uncached_db": round(q_unc, 2),
         "stage_ms_per_frame": {k: round(v[0] / K, 4) for k, v in all_stages.items()},

@@ -105,6 +105,29 @@ HD512 = Workload(
 )
 
 
+@dataclass
+class PathShape:
+    """Path-tracing parameters (the renderer's `path` argument)."""
+    density: float            # majorant extinction per LoD-0 voxel
+    light_dir: tuple          # unit vector toward the light (binary32 values)
+    light: tuple
+    ambient: tuple
+    max_bounces: int
+    spp: int
+    seed: int
+
+    def as_dict(self):
+        return dict(density=self.density, light_dir=self.light_dir, light=self.light, ambient=self.ambient,
+                    max_bounces=self.max_bounces, spp=self.spp, seed=self.seed)
+
+
+# Path tracing of the 1080p workload: mean free path 50 voxels at TF opacity 1,
+# a light along (1, 3, 2) / sqrt(14), a dim blue environment, up to 4
+# scattering events and one path per pixel per frame.
+PATH_HD512 = PathShape(density=0.02, light_dir=(0.26726124, 0.8017837, 0.5345225), light=(3.0, 3.0, 3.0),
+                       ambient=(0.25, 0.3, 0.35), max_bounces=4, spp=1, seed=99)
+
+
 def scaled(w: Workload, width: int, height: int, **kw) -> Workload:
     """Same workload at another resolution (and optional overrides)."""
     return replace(w, width=width, height=height, **kw)

@@ -186,3 +186,37 @@ def test_prefilled_fullsize_bench_configuration_pixels(scene, dtype, pool_dtype)
     print(f"prefilled {dtype} MLP, {pool_dtype} pool, bench-configuration pixels: max abs", d.max(), "PSNR", psnr)
     assert d.max() <= MAXABS[dtype]
     assert psnr >= 45.0
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16x3"])
+def test_prefilled_fullsize_path_tracing_pixels(scene, dtype):
+    # the path tracer in the bench's path-tracing configuration; a decision
+    # can flip only where the GPU's and the oracle's values straddle a
+    # uniform, so nearly every sampled pixel agrees within the FP32 bound
+    from oracle import oracle as O
+    from paper_2504_18001_amd import cinr
+    vol, m, mm = scene
+    off = vol.geometry(W.cache.brick, W.cache.n_lods)[1]
+    keys = _prefill_keys(off, seed=11)
+    cache = _gpu_cache(vol)
+    cache.prefill(torch.from_numpy(keys).cuda(), stamp=0, dtype=dtype)
+    oc = _oracle_cache(m)
+    oc.prefill(keys, 0)
+    f = 12
+    cam, tf = W.camera(f), W.tf(f)
+    path = configs.PATH_HD512.as_dict()
+    r = cinr.Renderer()
+    img = r.render(vol, cam, tf, W.step, W.lod_scale, frame_index=f, seed=W.seed, samples_per_iter=W.samples_per_iter,
+                   mode=cinr.CACHED, dtype=dtype, cache=cache, path=path)
+    st = r.last_stats()
+    px = _pixels(3)
+    got = img.reshape(-1, 4)[torch.from_numpy(px).long().cuda()].cpu().numpy().astype(np.float64)
+    p = O.make_params(W.step, W.lod_scale, seed=W.seed, frame_index=f, samples_per_iter=W.samples_per_iter,
+                      mode=O.CACHED, macro_cell=W.macro_cell, macro_minmax=mm, path=path)
+    ref = O.render_pixels(m, cam, tf, p, px, cache=oc)
+    d = np.abs(got - ref).max(axis=-1)
+    frac = float((d > 2e-3).mean())
+    print(f"path tracing {dtype}: {st}; sampled pixels beyond 2e-3: {frac:.4f}, lit {float((ref[:, 3] > 0).mean()):.3f}")
+    assert frac <= 0.01
+    assert st["misses"] == 0 and st["samples"] > st["rays"] > 0  # the coarsest LoD is resident
+    assert (ref[:, 3] > 0).mean() > 0.05

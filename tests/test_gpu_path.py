@@ -189,3 +189,74 @@ def test_inr_path_sequence_against_oracle():
         assert frac <= 0.01
         assert abs(st["samples"] - rst["samples"]) <= 0.01 * rst["samples"]
         assert st["rays"] == rst["rays"]
+
+
+MV_SIZES = [(40, 32), (32, 32), (48, 40), (24, 40)]
+MV_VOLS = [0, 1, 2, 0]
+
+
+def _mv_setup():
+    from oracle import oracle as O
+    dims = (37, 29, 23)
+    w = configs.scaled(configs.SMALL, 40, 32, orbit_radius=60.0, lod_scale=1.0 / 60.0, ortho_extent=60.0)
+    trip = [grid_volumes(dims, 0, seed=s) for s in (5, 6, 7)]
+    ms, vols = [t[0] for t in trip], [t[1] for t in trip]
+
+    def cam(i, f):
+        c = w.camera(f + 3 * i, dims)
+        c.width, c.height = MV_SIZES[i]
+        return c
+
+    oc = O.OracleCache(ms, brick=8, n_lods=2, pool_bricks=70, max_requests=12, log_misses=True)
+    return w, ms, vols, cam, oc
+
+
+def _mv_cache(vols):
+    from paper_2504_18001_amd import cinr
+    return cinr.Cache(vols, 8, 2, 70, 12, miss_log_capacity=1 << 20, evict_log_capacity=1 << 14,
+                      keep_request_counts=True)
+
+
+def test_grid_path_views_through_a_shared_cache():
+    from oracle import oracle as O
+    from paper_2504_18001_amd import cinr
+    w, ms, vols, cam, oc = _mv_setup()
+    gc = _mv_cache(vols)
+    mv = cinr.MultiViewRenderer(len(MV_SIZES))
+    tf = synth.tf_window(40, 255)
+    n = len(MV_SIZES)
+    for f in range(6):
+        imgs = mv.render(gc, [(vols[MV_VOLS[i]], cam(i, f), tf) for i in range(n)], w.step, w.lod_scale,
+                         frame_index=f, seed=w.seed, samples_per_iter=4, path=PATH)
+        gst = mv.last_stats()
+        ref = oc.render_views([(MV_VOLS[i], cam(i, f), tf) for i in range(n)],
+                              [_params(w, f, 4, O.CACHED) for _ in range(n)])
+        for i, ((rimg, rst), img) in enumerate(zip(ref, imgs)):
+            for k in KEYS:
+                assert gst[i][k] == rst[k], (f, i, k, gst[i][k], rst[k])
+            assert np.abs(img.cpu().numpy().astype(np.float64) - rimg).max() <= TOL["f32"], (f, i)
+        _compare_state(gc, oc, f, check_misses=False)
+        _compare_misses(gc, oc, f)
+        print(f"path views frame {f}: {gst[0]}", flush=True)
+
+
+def test_grid_path_captured_frames_equal_eager_frames():
+    from paper_2504_18001_amd import cinr
+    w, ms, vols, cam, _ = _mv_setup()
+    ge, gg = _mv_cache(vols), _mv_cache(vols)
+    n = len(MV_SIZES)
+    tf = synth.tf_window(40, 255)
+    kw = dict(lod_scale=w.lod_scale, seed=w.seed, samples_per_iter=4, pipe_depth=1, xcd_bands=4, path=PATH)
+    mv = cinr.MultiViewRenderer(n)
+    fg = cinr.FrameGraph(gg, [(vols[MV_VOLS[i]], cam(i, 0), tf) for i in range(n)], w.step, **kw)
+    for f in range(8):
+        eager = mv.render(ge, [(vols[MV_VOLS[i]], cam(i, f), tf) for i in range(n)], w.step, frame_index=f, **kw)
+        imgs = fg.render([cam(i, f) for i in range(n)], f)
+        se, sg = mv.last_stats(), fg.last_stats()
+        for i in range(n):
+            np.testing.assert_array_equal(imgs[i].cpu().numpy(), eager[i].cpu().numpy(), err_msg=f"{f} {i}")
+            assert sg[i] == se[i], (f, i, sg[i], se[i])
+        for kind in (cinr.DUMP_PAGE_TABLE, cinr.DUMP_SLOT_OWNER, cinr.DUMP_LAST_USED, cinr.DUMP_RANK,
+                     cinr.DUMP_REQUEST_LIST, cinr.DUMP_EVICTION_LOG):
+            np.testing.assert_array_equal(gg.dump(kind), ge.dump(kind), err_msg=f"frame {f} dump {kind}")
+    assert fg.counts()[0] > 0
