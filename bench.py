@@ -156,6 +156,55 @@ def pool_f16_leg(vol, cams, tfs, w, Wm, K, dtype, ref_img):
     return res
 
 
+def lod_context_leg(vol, cams, tfs, w, Wm, K, dtype, laps=21):
+    """The headline sequence with the context-aware LoD (macro-cell value
+    ranges scale the LoD distance): fps, requests and misses per frame, and
+    PSNR of the last frame against the uncached renderer (LoD 0 everywhere),
+    both after the headline's warm-up and after `laps` orbits, when 40 bricks
+    per frame have loaded every brick of the volume (the pool holds them all)."""
+    import torch
+    from paper_2504_18001_amd import cinr
+    nst = len(cinr.STAT_FIELDS)
+    last = Wm + K - 1  # the same orbit frame at every lap
+    ru = cinr.Renderer()
+    ref = ru.render(vol, cams[last % w.n_frames], tfs[last % w.n_frames], w.step, w.lod_scale, frame_index=last,
+                    seed=w.seed, ert_threshold=w.ert_threshold, samples_per_iter=w.samples_per_iter,
+                    mode=cinr.UNCACHED_DIRECT, dtype="f32").cpu().numpy()
+    Wl = laps * w.n_frames
+    res = {"converged_after_frames": Wl + Wm}
+    for kappa in (0.0, 0.5, 1.0):
+        c = new_cache(vol, w)
+        r = cinr.Renderer()
+        out = torch.empty((w.height, w.width, 4), dtype=torch.float32, device="cuda")
+        st = torch.zeros((K, nst), dtype=torch.int64, device="cuda")
+
+        def frames(rng, stats=None):
+            for i, f in enumerate(rng):
+                r.render(vol, cams[f % w.n_frames], tfs[f % w.n_frames], w.step, w.lod_scale, frame_index=f,
+                         seed=w.seed, ert_threshold=w.ert_threshold, samples_per_iter=w.samples_per_iter,
+                         mode=cinr.CACHED, dtype=dtype, cache=c, out=out, stats=None if stats is None else stats[i],
+                         lod_context=kappa)
+
+        def timed(first):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            frames(range(first, first + K), st)
+            torch.cuda.synchronize()
+            fps = K / (time.perf_counter() - t0)
+            tot = dict(zip(cinr.STAT_FIELDS, st.sum(0).cpu().numpy().tolist()))
+            return {"fps": round(fps, 2), "requested_per_frame": tot["requested"] // K,
+                    "true_misses_per_frame": tot["misses"] // K, "fallbacks_per_frame": tot["fallbacks"] // K,
+                    "psnr_vs_uncached_db": round(psnr(ref, out.cpu().numpy()), 2)}
+
+        frames(range(Wm))
+        early = timed(Wm)
+        frames(range(Wm + K, Wl + Wm))
+        late = timed(Wl + Wm)
+        res[f"kappa_{kappa}"] = {"after_warmup": early, "converged": late}
+        del c
+    return res
+
+
 def path_leg(vol, cams, tfs, w, Wm, K, dtype, K_unc, oracle=True):
     """Path tracing of the headline orbit (Woodcock delta tracking through the
     same sampler and cache): cached frames (the headline cache, bricks decoded
@@ -476,6 +525,7 @@ def main():
     ap.add_argument("--no-adaptive", action="store_true", help="skip the adaptive sampling leg")
     ap.add_argument("--no-pool-f16", action="store_true", help="skip the binary16 pool leg")
     ap.add_argument("--no-path", action="store_true", help="skip the path-tracing leg")
+    ap.add_argument("--no-lod-context", action="store_true", help="skip the context-aware LoD leg")
     ap.add_argument("--path-uncached-steps", type=int, default=5)
     ap.add_argument("--multiview-steps", type=int, default=60)
     ap.add_argument("--no-training", action="store_true", help="skip the INR training leg")
@@ -616,6 +666,12 @@ def main():
         pool16 = pool_f16_leg(vol, cams, tfs, w, Wm, K, args.dtype, cached_img.cpu().numpy())
         log(f"[bench] binary16 pool: {pool16}")
 
+    # --- context-aware LoD from the macro-cells' value ranges ------------------
+    lodc = None
+    if not args.no_lod_context:
+        lodc = lod_context_leg(vol, cams, tfs, w, Wm, K, args.dtype)
+        log(f"[bench] context-aware LoD: {lodc}")
+
     # --- path tracing through the same sampler and cache ----------------------
     pt = None
     if not args.no_path:
@@ -708,6 +764,7 @@ def main():
         "adaptive_sampling": {"tf": "the orbit's TFs with opacity x 0.1", "by_max_exponent": adaptive},
         "binary16_pool": pool16,
         "path_tracing": pt,
+        "context_aware_lod": lodc,
         "bricks_per_s": {k: round(v, 1) for k, v in bps.items()},
         "psnr_cached_vs_uncached_db": round(q_unc, 2),
         "stage_ms_per_frame": {k: round(v[0] / K, 4) for k, v in all_stages.items()},

@@ -222,6 +222,13 @@ typedef struct {
     int32_t pt_max_bounces;   /* >= 1 */
     int32_t pt_spp;           /* 1 .. 65535 */
     uint32_t pt_seed;
+    /* Context-aware LoD (the direction of Section 7: use the macro-cells'
+     * value ranges to pick finer LoDs where the data has structure): with
+     * macro-cells, the LoD distance of a sample in a cell of values
+     * [min, max] is (|p - eye| * lod_scale) * (1 - lod_context * (max - min)),
+     * in binary32; 0 (or no macro-cells) is Algorithm 2's distance rule.
+     * In [0, 1]. */
+    float lod_context;
 } cinr_render_params;
 
 typedef enum { CINR_RAY_MARCH = 0, CINR_PATH_TRACE = 1 } cinr_pipeline;

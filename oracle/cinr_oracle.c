@@ -485,6 +485,13 @@ static uint32_t float_bits(float f) {
  * so that the expected LoD equals D.  Then clamped to [lod_floor, n_lods-1]. */
 int32_t orc_select_lod(const float p[3], const float eye[3], float lod_scale, uint32_t frame_seed,
                        int32_t lod_floor, int32_t n_lods) {
+    return orc_select_lod_scaled(p, eye, lod_scale, 1.0f, frame_seed, lod_floor, n_lods);
+}
+
+/* The same with the distance scaled by `factor` (context-aware LoD):
+ * D = (|p - eye| * lod_scale) * factor. */
+int32_t orc_select_lod_scaled(const float p[3], const float eye[3], float lod_scale, float factor,
+                              uint32_t frame_seed, int32_t lod_floor, int32_t n_lods) {
     float dx = p[0] - eye[0];
     float dy = p[1] - eye[1];
     float dz = p[2] - eye[2];
@@ -493,7 +500,8 @@ int32_t orc_select_lod(const float p[3], const float eye[3], float lod_scale, ui
     float sz = dz * dz;
     s = s + sy;
     s = s + sz;
-    float D = sqrtf(s) * lod_scale;
+    float D0 = sqrtf(s) * lod_scale;
+    float D = D0 * factor;
     float fl = floorf(D);
     float fr = D - fl;
     uint32_t r = orc_xorshift32(float_bits(D) ^ frame_seed);
@@ -894,13 +902,21 @@ static void sample_decide(const frame_ctx* fc, const float o[3], const float d[3
         pos[a] = q;
         so->pos[a] = q;
     }
+    float lod_factor = 1.0f;
     if (fc->flags) {
         int32_t ci[3];
         for (int a = 0; a < 3; ++a) {
             ci[a] = (int32_t)pos[a] / P->macro_cell;
             if (ci[a] > fc->M[a] - 1) ci[a] = fc->M[a] - 1;
         }
-        const uint8_t code = fc->flags[((int64_t)ci[2] * fc->M[1] + ci[1]) * fc->M[0] + ci[0]];
+        const int64_t cell = ((int64_t)ci[2] * fc->M[1] + ci[1]) * fc->M[0] + ci[0];
+        const uint8_t code = fc->flags[cell];
+        if (P->lod_context > 0.0f) {
+            /* context-aware LoD: 1 - kappa * (value range of the cell), binary32 */
+            const float range = P->macro_minmax[2 * cell + 1] - P->macro_minmax[2 * cell];
+            const float k = P->lod_context * range;
+            lod_factor = 1.0f - k;
+        }
         if (P->adapt_max_exp >= 0) {
             /* adaptive rate: the cell's step exponent, the largest one across a transparent cell */
             if (code == 0xFF) {
@@ -943,7 +959,8 @@ static void sample_decide(const frame_ctx* fc, const float o[3], const float d[3
     orc_cache* c = fc->c;
     const int32_t B = c->d.brick;
     const int32_t nl = c->d.n_lods;
-    const int32_t L = orc_select_lod(pos, fc->cam->eye, P->lod_scale, fc->frame_seed, fc->lod_floor, nl);
+    const int32_t L = orc_select_lod_scaled(pos, fc->cam->eye, P->lod_scale, lod_factor, fc->frame_seed,
+                                            fc->lod_floor, nl);
     int64_t req_key = -1;
     so->status = S_MISS;
     for (int32_t Lp = L; Lp < nl; ++Lp) {
@@ -1393,8 +1410,10 @@ static void render_pixel(const frame_ctx* fc, thread_acc* ta, const float* tf, i
     }
 }
 
-/* Parameters the path tracer needs. */
-static int pt_params_ok(const orc_params* p) {
+/* Parameters a frame needs: the context-aware LoD weight in [0, 1], and
+ * those of the path tracer. */
+static int params_ok(const orc_params* p) {
+    if (!(p->lod_context >= 0.0f && p->lod_context <= 1.0f)) return 0;
     if (p->pipeline == 0) return 1;
     if (p->pipeline != 1) return 0;
     if (!(p->pt_density > 0.0f) || !isfinite(p->pt_density)) return 0;
@@ -1474,7 +1493,7 @@ static uint8_t* make_flags(const orc_inr* m, const orc_params* p, const float* t
 int orc_render_uncached(const orc_inr* m, const orc_camera* c, const float* tf, const orc_params* p, double* rgba,
                         orc_stats* st) {
     if (p->mode != ORC_UNCACHED_DIRECT && p->mode != ORC_UNCACHED_LATTICE) return -1;
-    if (!pt_params_ok(p)) return -1;
+    if (!params_ok(p)) return -1;
     frame_ctx fc;
     memset(&fc, 0, sizeof(fc));
     fc.m = m;
@@ -1579,7 +1598,7 @@ int orc_cache_end_frame(orc_cache* c, int32_t frame, orc_stats* st) {
 int orc_cache_render(orc_cache* c, const orc_camera* cam, const float* tf, const orc_params* p, double* rgba,
                      orc_stats* st) {
     if (p->mode != ORC_CACHED) return -1;
-    if (!pt_params_ok(p)) return -1;
+    if (!params_ok(p)) return -1;
     frame_ctx fc;
     memset(&fc, 0, sizeof(fc));
     fc.m = &c->inr;
@@ -1613,7 +1632,7 @@ int orc_cache_render_views(orc_cache* c, int32_t n, const int32_t* vol, const or
     if (n < 1) return -1;
     for (int i = 0; i < n; ++i)
         if (ps[i].mode != ORC_CACHED || vol[i] < 0 || vol[i] >= c->n_vols || ps[i].frame_index != ps[0].frame_index ||
-            !pt_params_ok(&ps[i]))
+            !params_ok(&ps[i]))
             return -1;
     miss_rec* all = NULL;
     int64_t n_all = 0;
@@ -1658,7 +1677,7 @@ int orc_cache_render_views(orc_cache* c, int32_t n, const int32_t* vol, const or
 int orc_render_pixels(const orc_inr* m, orc_cache* c, const orc_camera* cam, const float* tf, const orc_params* p,
                       const int32_t* pix, int64_t n, double* rgba) {
     if ((p->mode == ORC_CACHED) != (c != NULL)) return -1;
-    if (!pt_params_ok(p)) return -1;
+    if (!params_ok(p)) return -1;
     frame_ctx fc;
     memset(&fc, 0, sizeof(fc));
     fc.m = c ? &c->inr : m;

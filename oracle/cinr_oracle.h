@@ -77,6 +77,11 @@ typedef struct {
     int32_t pt_max_bounces;/* real collisions (scattering events) per path, >= 1 */
     int32_t pt_spp;        /* paths per pixel, >= 1 */
     uint32_t pt_seed;      /* Philox key word 0; word 1 is the frame index */
+    /* context-aware LoD (Section 7): with macro-cells, the LoD distance of a
+     * sample is scaled by 1 - lod_context * (max - min) of its cell's values,
+     * so that cells with a wide value range are sampled at finer LoDs;
+     * 0 is the distance-only rule of Algorithm 2 */
+    float lod_context;
 } orc_params;
 
 /* Events (Philox draws) a pixel may use per frame in path tracing; a pixel
@@ -139,6 +144,8 @@ int orc_ray_setup(const orc_camera* c, const int32_t dims[3], int32_t i, int32_t
                   float o[3], float d[3], float* ts, float* te);
 int32_t orc_select_lod(const float p[3], const float eye[3], float lod_scale, uint32_t frame_seed,
                        int32_t lod_floor, int32_t n_lods);
+int32_t orc_select_lod_scaled(const float p[3], const float eye[3], float lod_scale, float factor,
+                              uint32_t frame_seed, int32_t lod_floor, int32_t n_lods);
 int32_t orc_lod_floor(int32_t frame, int32_t period, int32_t n_lods);
 
 /* --- uncached renderers (no cache state) --- */

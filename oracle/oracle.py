@@ -42,7 +42,7 @@ class Params(C.Structure):
                 ("adapt_max_exp", C.c_int32),
                 ("pipeline", C.c_int32), ("pt_density", C.c_float), ("pt_light_dir", C.c_float * 3),
                 ("pt_light", C.c_float * 3), ("pt_ambient", C.c_float * 3), ("pt_max_bounces", C.c_int32),
-                ("pt_spp", C.c_int32), ("pt_seed", C.c_uint32)]
+                ("pt_spp", C.c_int32), ("pt_seed", C.c_uint32), ("lod_context", C.c_float)]
 
 
 class CacheDesc(C.Structure):
@@ -94,6 +94,7 @@ def lib():
             "orc_pt_direction": (C.c_uint32, [C.c_uint32, C.c_uint32, P, P]),
             "orc_pt_segment_exit": (C.c_float, [P, P, P]),
             "orc_tf_alpha32": (C.c_float, [P, C.c_float]),
+            "orc_select_lod_scaled": (i32, [P, P, C.c_float, C.c_float, C.c_uint32, i32, i32]),
             "orc_macrocell_step_codes": (None, [P, i64, P, i32, P]),
             "orc_ray_setup": (C.c_int, [P, P, i32, i32, P, P, P, P]),
             "orc_select_lod": (i32, [P, P, C.c_float, u32, i32, i32]),
@@ -290,6 +291,13 @@ def select_lod(p, eye, lod_scale, frame_seed, lod_floor, n_lods):
                                     lod_floor, n_lods))
 
 
+def select_lod_scaled(p, eye, lod_scale, factor, frame_seed, lod_floor, n_lods):
+    pp = np.asarray(p, np.float32)
+    ee = np.asarray(eye, np.float32)
+    return int(lib().orc_select_lod_scaled(_ptr(pp), _ptr(ee), float(lod_scale), float(factor),
+                                           int(frame_seed) & 0xFFFFFFFF, lod_floor, n_lods))
+
+
 def macrocell_flags(minmax, tf):
     mm = np.ascontiguousarray(minmax, np.float32)
     n = mm.size // 2
@@ -368,13 +376,15 @@ def philox4x32_10(ctr, key):
 
 
 def make_params(step, lod_scale, seed=0, frame_index=0, ert_threshold=2.0, samples_per_iter=8, mode=CACHED,
-                macro_cell=0, macro_minmax=None, adapt_max_exp=-1, path=None):
+                macro_cell=0, macro_minmax=None, adapt_max_exp=-1, path=None, lod_context=0.0):
     """adapt_max_exp: adaptive sampling rate with steps of up to 2^E sample
     spacings (Section 5.2); -1 (or 0) for the fixed step.  path: None for ray
     marching, else a dict of path-tracing parameters (density, light_dir,
-    light, ambient, max_bounces, spp, seed)."""
+    light, ambient, max_bounces, spp, seed).  lod_context: context-aware
+    LoD weight in [0, 1] (needs macro-cells)."""
     p = Params()
     p.adapt_max_exp = adapt_max_exp
+    p.lod_context = lod_context
     if path is not None:
         p.pipeline = 1
         p.pt_density = path.get("density", 0.05)

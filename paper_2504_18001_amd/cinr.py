@@ -58,7 +58,7 @@ class RenderParams(C.Structure):
                 ("adapt_max_exp", C.c_int32),
                 ("pipeline", C.c_int32), ("pt_density", C.c_float), ("pt_light_dir", C.c_float * 3),
                 ("pt_light", C.c_float * 3), ("pt_ambient", C.c_float * 3), ("pt_max_bounces", C.c_int32),
-                ("pt_spp", C.c_int32), ("pt_seed", C.c_uint32)]
+                ("pt_spp", C.c_int32), ("pt_seed", C.c_uint32), ("lod_context", C.c_float)]
 
 
 RAY_MARCH, PATH_TRACE = 0, 1
@@ -395,9 +395,10 @@ class Renderer:
 
     def render(self, volume: Volume, cam, tf, step, lod_scale=0.0, frame_index=0, seed=0, ert_threshold=2.0,
                samples_per_iter=32, mode=CACHED, dtype="f32", cache: Cache = None, out=None, stats=None,
-               pipe_depth=0, xcd_bands=0, adapt_max_exp=0, path=None):
+               pipe_depth=0, xcd_bands=0, adapt_max_exp=0, path=None, lod_context=0.0):
         """path: None for ray marching, else the path tracer's parameters
-        (dict: density, light_dir, light, ambient, max_bounces, spp, seed)."""
+        (dict: density, light_dir, light, ambient, max_bounces, spp, seed).
+        lod_context: context-aware LoD weight in [0, 1]."""
         need = _workspace_size(volume, cam.width, cam.height, samples_per_iter, path)
         if self.ws is None or self.ws.numel() < need:
             self.ws = torch.empty(need, dtype=torch.uint8, device=self.device)
@@ -411,6 +412,7 @@ class Renderer:
         p.mode, p.mlp_dtype = int(mode), _dtype(dtype)
         p.pipe_depth, p.xcd_bands = int(pipe_depth), int(xcd_bands)
         p.adapt_max_exp = int(adapt_max_exp)
+        p.lod_context = float(lod_context)
         _set_path(p, path)
         cd = camera_desc(cam)
         st = self.stats if stats is None else stats
@@ -510,7 +512,7 @@ class MultiViewRenderer:
         self._keep = []
 
     def describe(self, views, step, lod_scale=0.0, frame_index=0, seed=0, ert_threshold=2.0, samples_per_iter=32,
-                 dtype="f32", outs=None, pipe_depth=0, xcd_bands=0, adapt_max_exp=0, path=None):
+                 dtype="f32", outs=None, pipe_depth=0, xcd_bands=0, adapt_max_exp=0, path=None, lod_context=0.0):
         """The cinr_view array of `views` (list of (volume, camera, tf)) and
         their output images; the TF tensors are kept alive by the renderer."""
         n = len(views)
@@ -536,6 +538,7 @@ class MultiViewRenderer:
             p.mode, p.mlp_dtype = CACHED, _dtype(dtype)
             p.pipe_depth, p.xcd_bands = int(pipe_depth), int(xcd_bands)
             p.adapt_max_exp = int(adapt_max_exp)
+            p.lod_context = float(lod_context)
             _set_path(p, path)
             v.d_rgba = outs[i].data_ptr()
             v.d_stats = self.stats[i].data_ptr()
@@ -545,10 +548,11 @@ class MultiViewRenderer:
         return arr, outs
 
     def render(self, cache: Cache, views, step, lod_scale=0.0, frame_index=0, seed=0, ert_threshold=2.0,
-               samples_per_iter=32, dtype="f32", outs=None, pipe_depth=0, xcd_bands=0, adapt_max_exp=0, path=None):
+               samples_per_iter=32, dtype="f32", outs=None, pipe_depth=0, xcd_bands=0, adapt_max_exp=0, path=None,
+               lod_context=0.0):
         """views: list of (volume, camera, tf); returns the list of RGBA images."""
         arr, outs = self.describe(views, step, lod_scale, frame_index, seed, ert_threshold, samples_per_iter, dtype,
-                                  outs, pipe_depth, xcd_bands, adapt_max_exp, path)
+                                  outs, pipe_depth, xcd_bands, adapt_max_exp, path, lod_context)
         _check(lib().cinr_render_views(cache.h, len(views), arr, _stream()))
         return outs
 
@@ -565,12 +569,12 @@ class FrameGraph:
     frames.  Owns the views' workspaces, images and statistics."""
 
     def __init__(self, cache: Cache, views, step, lod_scale=0.0, seed=0, ert_threshold=2.0, samples_per_iter=32,
-                 dtype="f32", pipe_depth=0, xcd_bands=0, adapt_max_exp=0, device="cuda", path=None):
+                 dtype="f32", pipe_depth=0, xcd_bands=0, adapt_max_exp=0, device="cuda", path=None, lod_context=0.0):
         self.cache = cache
         self.volumes = [v for v, _, _ in views]
         self.mv = MultiViewRenderer(len(views), device)
         arr, self.outs = self.mv.describe(views, step, lod_scale, 0, seed, ert_threshold, samples_per_iter, dtype,
-                                          None, pipe_depth, xcd_bands, adapt_max_exp, path)
+                                          None, pipe_depth, xcd_bands, adapt_max_exp, path, lod_context)
         self.tfs = list(self.mv._keep)
         self.n = len(views)
         h = C.c_void_p()

@@ -699,6 +699,8 @@ cinr_status prepare_view(cinr_cache c, cinr_volume v, const cinr_camera* cam, co
         return fail(CINR_INVALID_ARG, "samples_per_iter must be in [1, 64]");
     if (rp->adapt_max_exp < 0 || rp->adapt_max_exp > 14)
         return fail(CINR_INVALID_ARG, "adapt_max_exp must be in [0, 14]");
+    if (!(rp->lod_context >= 0.0f && rp->lod_context <= 1.0f))
+        return fail(CINR_INVALID_ARG, "lod_context must be in [0, 1]");
     if (rp->pipeline != CINR_RAY_MARCH && rp->pipeline != CINR_PATH_TRACE)
         return fail(CINR_INVALID_ARG, "pipeline = %d", rp->pipeline);
     const bool path = rp->pipeline == CINR_PATH_TRACE;
@@ -784,6 +786,8 @@ cinr_status prepare_view(cinr_cache c, cinr_volume v, const cinr_camera* cam, co
     f.cell_code = L.cell_code;
     f.vexp = L.vexp;
     if (f.adapt > 0) f.flags = nullptr;
+    f.lod_ctx = v->n_cells > 0 ? rp->lod_context : 0.0f;
+    f.minmax = v->desc.d_macrocells;
     f.claim = L.claim;
     f.tf = d_tf;
     f.rgba = reinterpret_cast<float4*>(d_rgba);

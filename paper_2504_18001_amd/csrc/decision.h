@@ -117,8 +117,8 @@ __device__ inline uint32_t xorshift32(uint32_t x) {
 // integer part of D, one level coarser when a uniform variate from xorshift
 // of (bits of D) XOR (frame seed) is below the fractional part; clamped to
 // [lod_floor, n_lods - 1].
-__device__ inline int32_t select_lod(const float p[3], const float eye[3], float lod_scale, uint32_t frame_seed,
-                                     int32_t lod_floor, int32_t n_lods) {
+__device__ inline int32_t select_lod(const float p[3], const float eye[3], float lod_scale, float factor,
+                                     uint32_t frame_seed, int32_t lod_floor, int32_t n_lods) {
     const float dx = p[0] - eye[0];
     const float dy = p[1] - eye[1];
     const float dz = p[2] - eye[2];
@@ -127,7 +127,8 @@ __device__ inline int32_t select_lod(const float p[3], const float eye[3], float
     const float sz = dz * dz;
     s = s + sy;
     s = s + sz;
-    const float D = __builtin_sqrtf(s) * lod_scale;
+    const float D0 = __builtin_sqrtf(s) * lod_scale;
+    const float D = D0 * factor;  // context-aware LoD (1 otherwise)
     const float fl = __builtin_floorf(D);
     const float fr = D - fl;
     const uint32_t r = xorshift32(__float_as_uint(D) ^ frame_seed);

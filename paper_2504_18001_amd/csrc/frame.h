@@ -151,6 +151,8 @@ struct FrameDev {
     uint8_t* cell_code;  // [n_cells]
     uint8_t* vexp;       // [W*H*S] step exponent of each gathered sample
     PtDev path;          // path tracing (path.on), else ray marching
+    float lod_ctx;       // context-aware LoD weight (0: off)
+    const float* minmax; // the volume's macro-cells [n_cells][2] (context-aware LoD)
     uint32_t* claim;     // [2][8] work-unit counters of the march kernel (one set per iteration
                          // parity), kClaimStride words apart
     CacheGeom geo;

@@ -109,6 +109,7 @@ __device__ inline SampleRes sample_cache(const FrameDev& f, const FrameHot& h, c
     s.value = 0.0f;
     s.e = 0;
     bool live = true;
+    float lod_factor = 1.0f;
     if (kAdapt || f.flags) {
         uint32_t ci[3];
 #pragma unroll
@@ -117,6 +118,13 @@ __device__ inline SampleRes sample_cache(const FrameDev& f, const FrameHot& h, c
             if (ci[a] > (uint32_t)f.M[a] - 1u) ci[a] = (uint32_t)f.M[a] - 1u;
         }
         const uint32_t cell = (ci[2] * (uint32_t)f.M[1] + ci[1]) * (uint32_t)f.M[0] + ci[0];
+        if (f.lod_ctx > 0.0f) {
+            // context-aware LoD: 1 - kappa * (value range of the cell)
+            const float2 mm = reinterpret_cast<const float2*>(f.minmax)[cell];
+            const float range = mm.y - mm.x;
+            const float k = f.lod_ctx * range;
+            lod_factor = 1.0f - k;
+        }
         if constexpr (kAdapt) {
             const uint32_t code = fl.code(cell);
             live = code != 0xFFu;
@@ -130,7 +138,7 @@ __device__ inline SampleRes sample_cache(const FrameDev& f, const FrameHot& h, c
         return s;
     }
     const int32_t nl = f.geo.n_lods;
-    const int32_t L = select_lod(p, h.eye, f.lod_scale, h.seed, h.lod_floor, nl);
+    const int32_t L = select_lod(p, h.eye, f.lod_scale, lod_factor, h.seed, h.lod_floor, nl);
     const int32_t B = kFast ? kB : f.geo.brick;
     s.status = S_MISS;
     for (int32_t Lp = L; Lp < nl; ++Lp) {

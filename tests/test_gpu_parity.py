@@ -89,11 +89,12 @@ def test_macrocells_match_oracle():
 
 
 def _render_gpu(vol, cam, tf, w, frame, mode, dtype="f32", cache=None, ert=2.0, S=None, renderer=None, adapt=0,
-                step=None):
+                step=None, lod_context=0.0):
     from paper_2504_18001_amd import cinr
     r = renderer or cinr.Renderer()
     img = r.render(vol, cam, tf, step or w.step, w.lod_scale, frame_index=frame, seed=w.seed, ert_threshold=ert,
-                   samples_per_iter=S or w.samples_per_iter, mode=mode, dtype=dtype, cache=cache, adapt_max_exp=adapt)
+                   samples_per_iter=S or w.samples_per_iter, mode=mode, dtype=dtype, cache=cache, adapt_max_exp=adapt,
+                   lod_context=lod_context)
     return img.cpu().numpy().astype(np.float64), r.last_stats()
 
 
@@ -136,7 +137,7 @@ def _compare_state(gc, oc, frame, check_misses=True):
 
 def run_cached_sequence(w, frames, width, height, dtype="f32", dims=None, pool=None, max_req=None, ranking=1,
                         preload=None, S=None, macro=False, tf_fn=None, n_lods=None, brick=None, adapt=0,
-                        pool_dtype="f32"):
+                        pool_dtype="f32", lod_context=0.0):
     from oracle import oracle as O
     from paper_2504_18001_amd import cinr
     arch = w.arch
@@ -159,10 +160,11 @@ def run_cached_sequence(w, frames, width, height, dtype="f32", dims=None, pool=N
         cam = w.camera(f, dims)
         cam.width, cam.height = width, height
         tf = tf_fn(f) if tf_fn else w.tf(f)
-        img, st = _render_gpu(vol, cam, tf, w, f, cinr.CACHED, dtype, cache=gc, S=S, renderer=r, adapt=adapt)
+        img, st = _render_gpu(vol, cam, tf, w, f, cinr.CACHED, dtype, cache=gc, S=S, renderer=r, adapt=adapt,
+                              lod_context=lod_context)
         p = O.make_params(w.step, w.lod_scale, seed=w.seed, frame_index=f, samples_per_iter=S or w.samples_per_iter,
                           mode=O.CACHED, macro_cell=w.macro_cell if macro else 0, macro_minmax=mm,
-                          adapt_max_exp=adapt)
+                          adapt_max_exp=adapt, lod_context=lod_context)
         ref, rst = oc.render(cam, tf, p)
         err = np.abs(img - ref).max()
         worst = max(worst, err)
