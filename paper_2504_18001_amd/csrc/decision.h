@@ -17,6 +17,10 @@ struct CamDev {
 
 // Primary ray through the centre of pixel (i, j) (row 0 at the top) and its
 // parametric overlap [ts, te] with the box [0, V-1]^3 (slab test).
+// kOFirst only orders the stores of the perspective branch (o before d, as
+// the orthographic branch): the path tracer keeps its o and d in registers
+// that way, while the ray marcher's register allocation prefers d first.
+template <bool kOFirst = false>
 __device__ inline bool ray_setup(const CamDev& c, const float vm1[3], int32_t i, int32_t j, float o[3], float d[3],
                                  float& ts, float& te) {
     const float fx = ((float)i + 0.5f) / (float)c.W;
@@ -38,10 +42,18 @@ __device__ inline bool ray_setup(const CamDev& c, const float vm1[3], int32_t i,
         n2 = n2 + y2;
         n2 = n2 + z2;
         const float n = __builtin_sqrtf(n2);
+        if constexpr (kOFirst) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            d[a] = dir[a] / n;
-            o[a] = c.eye[a];
+            for (int a = 0; a < 3; ++a) {
+                o[a] = c.eye[a];
+                d[a] = dir[a] / n;
+            }
+        } else {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                d[a] = dir[a] / n;
+                o[a] = c.eye[a];
+            }
         }
     } else {
         const float ox = (fx - 0.5f) * c.ow;

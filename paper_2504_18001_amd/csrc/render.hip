@@ -329,6 +329,26 @@ struct RayBook {
         rk = -1;
         rc = 0;
     }
+    // The same for scattered lookups (the path tracer): a stamp is stored
+    // only when the slot does not hold it yet, so that lookups spread over
+    // many slots do not dirty a cache line each.
+    __device__ void note_scattered(const FrameDev& f, int32_t frame, ColdRef c, const SampleRes& s) {
+        if (f.mode != CINR_CACHED || s.status == S_SKIP) return;
+        if (s.status != S_HIT) {
+            if (s.req_key != rk) {
+                flush_requests(c, rk, rc);
+                rk = s.req_key;
+                rc = 1;
+            } else {
+                ++rc;
+            }
+        }
+        if (s.slot >= 0 && s.slot != ls0 && s.slot != ls1) {
+            if (f.last_used[s.slot] != frame) f.last_used[s.slot] = frame;
+            ls1 = ls0;
+            ls0 = s.slot;
+        }
+    }
 };
 
 __global__ __launch_bounds__(kBlock) void k_frame_begin(FrameDev f, int32_t n_ctr, const float* minmax,
@@ -765,10 +785,10 @@ struct PtLane {
         g.kind = kind;
         g.nc = nc;
     }
-    // a new path: the primary ray's segment
-    __device__ void begin(const CamDev& cam, const float vm1[3], int32_t i, int32_t j) {
+    // a new path: the primary ray's segment (false when it misses the box)
+    __device__ bool begin(const CamDev& cam, const float vm1[3], int32_t i, int32_t j) {
         float ts, te_;
-        ray_setup(cam, vm1, i, j, o, d, ts, te_);
+        const bool hit = ray_setup<true>(cam, vm1, i, j, o, d, ts, te_);
         t = ts;
         te = te_;
 #pragma unroll
@@ -778,6 +798,7 @@ struct PtLane {
         }
         kind = PT_PRIMARY;
         nc = gi = 0;
+        return hit;
     }
     // a new segment from o along dir
     __device__ void segment(const float dir[3], uint32_t k, const float vm1[3]) {
@@ -798,8 +819,9 @@ __device__ inline float4 pt_pixel_value(const PtLane& s) {
     return make_float4(s.sum[0] / J, s.sum[1] / J, s.sum[2] / J, (float)s.hits / J);
 }
 
+// (3 waves per SIMD: 158 VGPRs without spills; 4 would spill)
 template <bool kLdsFlags, bool kFast, bool kHalf>
-__global__ __launch_bounds__(kBlock) void k_path(FrameDev f, int32_t it, uint32_t n0) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_path(FrameDev f, int32_t it, uint32_t n0) {
     const FrameHot hot = load_hot(f.var);  // before any store of this kernel
     __shared__ float4 tfs[256];
     __shared__ LodGeom lgs[kMaxLods];
@@ -848,6 +870,7 @@ __global__ __launch_bounds__(kBlock) void k_path(FrameDev f, int32_t it, uint32_
         bool has = r < n;
         int32_t pix = 0, pi_ = 0, pj = 0;
         PtLane s;
+        bool begin_path = false;  // the pixel's next path starts at the top of the event loop
         if (has) {
             const CamDev cam = load_cam(cold->cam);
             if (it == 0) {
@@ -858,20 +881,10 @@ __global__ __launch_bounds__(kBlock) void k_path(FrameDev f, int32_t it, uint32_
                 has = pi_ < cam.W && pj < cam.H;
                 if (has) {
                     pix = pj * cam.W + pi_;
-                    float o[3], d[3], ts, te;
-                    const bool hit = ray_setup(cam, f.vm1, pi_, pj, o, d, ts, te);
-                    if (!hit) {
-                        float4* rgba = cold->rgba;
-                        rgba[pix] = make_float4(0.f, 0.f, 0.f, 0.f);
-                    }
-                    tally.rays += hit;
-                    has = hit;
-                    if (hit) {
-                        s.begin(cam, f.vm1, pi_, pj);
-                        s.n = s.path = s.done = s.hits = 0;
+                    s.n = s.path = s.done = s.hits = 0;
 #pragma unroll
-                        for (int a = 0; a < 3; ++a) s.sum[a] = 0.0f;
-                    }
+                    for (int a = 0; a < 3; ++a) s.sum[a] = 0.0f;
+                    begin_path = true;
                 }
             } else {
                 pix = cur[r];
@@ -887,6 +900,19 @@ __global__ __launch_bounds__(kBlock) void k_path(FrameDev f, int32_t it, uint32_
         if (has) {
             const float* gvals = P.st[pix].vals;
             while (!fin && !pend) {
+                if (begin_path) {
+                    // the one place where a pixel's primary ray is set up
+                    begin_path = false;
+                    const CamDev cam = load_cam(cold->cam);
+                    const bool hit = s.begin(cam, f.vm1, pi_, pj);
+                    if (s.path == 0) {
+                        tally.rays += hit;
+                        if (!hit) {  // a ray that misses the box: no paths
+                            fin = true;
+                            break;
+                        }
+                    }
+                }
                 if (s.n >= kPtMaxEvents) {  // budget spent: the path in progress is dropped
                     fin = true;
                     break;
@@ -913,7 +939,7 @@ __global__ __launch_bounds__(kBlock) void k_path(FrameDev f, int32_t it, uint32_
                     } else {
                         const SampleRes sr = sample_cache<kFast, false, kHalf>(f, hot, lgs, fl, p, sc);
                         tally.add(sr.status);
-                        book.note(f, hot.frame, cold, sr);
+                        book.note_scattered(f, hot.frame, cold, sr);
                         if (sr.status == S_MISS) {
                             pend = true;  // s.n and s.t stay before event e
                             t_miss = t;
@@ -983,12 +1009,10 @@ __global__ __launch_bounds__(kBlock) void k_path(FrameDev f, int32_t it, uint32_
                     s.hits += s.kind >> 31;
                     s.done += 1;
                     s.path += 1;
-                    if ((int32_t)s.path == P.spp) {
+                    if ((int32_t)s.path == P.spp)
                         fin = true;
-                    } else {
-                        const CamDev cam = load_cam(cold->cam);
-                        s.begin(cam, f.vm1, pi_, pj);
-                    }
+                    else
+                        begin_path = true;
                 }
             }
         }
@@ -1011,7 +1035,7 @@ __global__ __launch_bounds__(kBlock) void k_path(FrameDev f, int32_t it, uint32_
                 pt_pos(s.o, s.d, tg, f.vm1, p);
                 const SampleRes sr = sample_cache<kFast, false, kHalf>(f, hot, lgs, fl, p, sc);
                 tally.add(sr.status);
-                book.note(f, hot.frame, cold, sr);
+                book.note_scattered(f, hot.frame, cold, sr);
                 if (sr.status == S_MISS)
                     mask |= 1ull << nc;
                 else
