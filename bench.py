@@ -774,7 +774,8 @@ def main():
                      "algorithmic_bytes_per_launch": round(alg_bytes / max(march_n, 1)),
                      "launches": march_n, "avg_launch_ms": round(march_ms / max(march_n, 1), 5),
                      "launches_before_timed": warm_stages["march"][1],
-                     "launch_shape": dict(zip(("pipe_depth", "xcd_bands"), cinr.tuned_launch(vol, w.width, w.height)[:2]))},
+                     "launch_shape": dict(zip(("pipe_depth", "xcd_bands", "trials_left", "waves_per_simd"),
+                                              cinr.tuned_launch(vol, w.width, w.height)))},
         "multiview": multi,
         "training": train,
         "cpu_baseline": cpu,

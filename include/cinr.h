@@ -165,11 +165,15 @@ typedef struct {
  *                marching (1, 2 or 4; 8 is accepted and runs as 4).
  *  xcd_bands     tuning: image bands per XCD in the sampler's work split
  *                (1 to 64).
- *                Results depend on neither.  0 in either field tunes the
- *                launch online, per volume and image size: the first 12
- *                frames of that size try pipe depths {1, 2} x bands {1, 4,
- *                16} twice each, then the fastest first-iteration march is
- *                kept (cinr_tuned_launch reports the choice).
+ *  waves_per_simd tuning: the sampler's register budget, 3 waves per SIMD
+ *                (168 registers, no spills) or 4 (128 registers); 0 takes
+ *                the tuned value, or 3 when the launch is not tuned.
+ *                Results depend on none of them.  0 in pipe_depth or
+ *                xcd_bands tunes the launch online, per volume and image
+ *                size: the first 24 frames of that size try pipe depths
+ *                {1, 2} x bands {1, 4, 16} x waves {3, 4} twice each, then
+ *                the fastest first-iteration march is kept
+ *                (cinr_tuned_launch reports the choice).
  *  adapt_max_exp adaptive sampling rate (Section 5.2), with the volume's
  *                macro-cells: E > 0 lets a ray cross a macro-cell of maximum
  *                TF opacity mu in steps of 2^e sample spacings, e =
@@ -189,6 +193,7 @@ typedef struct {
     int32_t pipe_depth;
     int32_t xcd_bands;
     int32_t adapt_max_exp;
+    int32_t waves_per_simd;   /* tuning (see above): 3, 4, or 0 */
     /* Path tracing (pipeline = CINR_PATH_TRACE): the second wavefront
      * pipeline of Section 5.1, Woodcock delta tracking through the same
      * sampler and cache.  The medium has extinction pt_density * TF opacity
@@ -442,7 +447,7 @@ void cinr_frame_graph_destroy(cinr_frame_graph graph);
 /* The sampler launch shape tuned online for a volume and image size (see
  * cinr_render_params), and the trial frames still to run (0 once tuned). */
 cinr_status cinr_tuned_launch(cinr_volume vol, int32_t width, int32_t height, int32_t* pipe_depth,
-                              int32_t* xcd_bands, int32_t* trials_left);
+                              int32_t* xcd_bands, int32_t* waves_per_simd, int32_t* trials_left);
 
 /* Copies one piece of cache state to host memory.  If `bytes` is too small
  * (or host_dst is NULL) nothing is copied, *needed receives the size and

@@ -55,7 +55,7 @@ class RenderParams(C.Structure):
     _fields_ = [("step", C.c_float), ("lod_scale", C.c_float), ("ert_threshold", C.c_float), ("seed", C.c_uint32),
                 ("frame_index", C.c_int32), ("samples_per_iter", C.c_int32), ("mode", C.c_int32),
                 ("mlp_dtype", C.c_int32), ("pipe_depth", C.c_int32), ("xcd_bands", C.c_int32),
-                ("adapt_max_exp", C.c_int32),
+                ("adapt_max_exp", C.c_int32), ("waves_per_simd", C.c_int32),
                 ("pipeline", C.c_int32), ("pt_density", C.c_float), ("pt_light_dir", C.c_float * 3),
                 ("pt_light", C.c_float * 3), ("pt_ambient", C.c_float * 3), ("pt_max_bounces", C.c_int32),
                 ("pt_spp", C.c_int32), ("pt_seed", C.c_uint32), ("lod_context", C.c_float)]
@@ -151,7 +151,7 @@ def lib():
             "cinr_cache_workspace_size_multi": [P, i32, P, P],
             "cinr_create_cache_multi": [P, i32, P, P, sz, P, sz, P, P],
             "cinr_render_views": [P, i32, P, P],
-            "cinr_tuned_launch": [P, i32, i32, P, P, P],
+            "cinr_tuned_launch": [P, i32, i32, P, P, P, P],
             "cinr_frame_graph_create": [P, i32, P, P],
             "cinr_path_workspace_size": [P, i32, i32, i32, P],
             "cinr_pt_free_flight": [P, i64, P, P],
@@ -395,7 +395,7 @@ class Renderer:
 
     def render(self, volume: Volume, cam, tf, step, lod_scale=0.0, frame_index=0, seed=0, ert_threshold=2.0,
                samples_per_iter=32, mode=CACHED, dtype="f32", cache: Cache = None, out=None, stats=None,
-               pipe_depth=0, xcd_bands=0, adapt_max_exp=0, path=None, lod_context=0.0):
+               pipe_depth=0, xcd_bands=0, adapt_max_exp=0, path=None, lod_context=0.0, waves_per_simd=0):
         """path: None for ray marching, else the path tracer's parameters
         (dict: density, light_dir, light, ambient, max_bounces, spp, seed).
         lod_context: context-aware LoD weight in [0, 1]."""
@@ -413,6 +413,7 @@ class Renderer:
         p.pipe_depth, p.xcd_bands = int(pipe_depth), int(xcd_bands)
         p.adapt_max_exp = int(adapt_max_exp)
         p.lod_context = float(lod_context)
+        p.waves_per_simd = int(waves_per_simd)
         _set_path(p, path)
         cd = camera_desc(cam)
         st = self.stats if stats is None else stats
@@ -605,7 +606,9 @@ class FrameGraph:
 
 
 def tuned_launch(volume, width, height):
-    """(pipe_depth, xcd_bands, trials_left) of the online launch tuning."""
-    p, b, t = C.c_int32(), C.c_int32(), C.c_int32()
-    _check(lib().cinr_tuned_launch(volume.h, int(width), int(height), C.byref(p), C.byref(b), C.byref(t)))
-    return p.value, b.value, t.value
+    """(pipe_depth, xcd_bands, trials_left, waves_per_simd) of the online
+    launch tuning."""
+    p, b, w, t = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    _check(lib().cinr_tuned_launch(volume.h, int(width), int(height), C.byref(p), C.byref(b), C.byref(w),
+                                   C.byref(t)))
+    return p.value, b.value, t.value, w.value

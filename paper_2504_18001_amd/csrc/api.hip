@@ -105,12 +105,13 @@ struct Timing {
 // image size: the first frames try every candidate twice (results do not
 // depend on the shape), the fastest first-iteration march is kept.
 struct SamplerTuner {
-    static constexpr int kCand = 6;
-    static constexpr int kPipe[kCand] = {1, 2, 1, 2, 1, 2};
-    static constexpr int kBands[kCand] = {1, 1, 4, 4, 16, 16};
+    static constexpr int kCand = 12;
+    static constexpr int kPipe[kCand] = {1, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 2};
+    static constexpr int kBands[kCand] = {1, 1, 4, 4, 16, 16, 1, 1, 4, 4, 16, 16};
+    static constexpr int kWaves[kCand] = {3, 3, 3, 3, 3, 3, 4, 4, 4, 4, 4, 4};
     static constexpr int kRounds = 2;
     int trial = 0;           // frames tried so far
-    float ms[kCand] = {0, 0, 0, 0, 0, 0};
+    float ms[kCand] = {};
     int best = -1;
     hipEvent_t a = nullptr, b = nullptr;
     bool pending = false;    // events of the current trial recorded, not yet read
@@ -695,6 +696,8 @@ cinr_status prepare_view(cinr_cache c, cinr_volume v, const cinr_camera* cam, co
     if (rp->pipe_depth != 0 && rp->pipe_depth != 1 && rp->pipe_depth != 2 && rp->pipe_depth != 4 && rp->pipe_depth != 8)
         return fail(CINR_INVALID_ARG, "pipe_depth must be 0, 1, 2, 4 or 8");
     if (rp->xcd_bands < 0 || rp->xcd_bands > 64) return fail(CINR_INVALID_ARG, "xcd_bands must be in [0, 64]");
+    if (rp->waves_per_simd != 0 && rp->waves_per_simd != 3 && rp->waves_per_simd != 4)
+        return fail(CINR_INVALID_ARG, "waves_per_simd must be 0, 3 or 4");
     if (rp->samples_per_iter < 1 || rp->samples_per_iter > 64)
         return fail(CINR_INVALID_ARG, "samples_per_iter must be in [1, 64]");
     if (rp->adapt_max_exp < 0 || rp->adapt_max_exp > 14)
@@ -771,10 +774,12 @@ cinr_status prepare_view(cinr_cache c, cinr_volume v, const cinr_camera* cam, co
         const int cand = r.tuner->cand();
         f.pipe = rp->pipe_depth > 0 ? rp->pipe_depth : SamplerTuner::kPipe[cand];
         f.xcd_bands = rp->xcd_bands > 0 ? rp->xcd_bands : SamplerTuner::kBands[cand];
+        f.waves = rp->waves_per_simd > 0 ? rp->waves_per_simd : SamplerTuner::kWaves[cand];
         r.timing_trial = r.tuner->best < 0;
     } else {
         f.pipe = rp->pipe_depth;
         f.xcd_bands = rp->xcd_bands;
+        f.waves = rp->waves_per_simd > 0 ? rp->waves_per_simd : 3;
     }
     f.mc_N = v->desc.macrocell_size;
     f.div_mc = make_fastdiv((uint32_t)(f.mc_N > 0 ? f.mc_N : 1));
@@ -1366,12 +1371,13 @@ extern "C" cinr_status cinr_frame_graph_counts(cinr_frame_graph g, int64_t* grap
 }
 
 extern "C" cinr_status cinr_tuned_launch(cinr_volume v, int32_t width, int32_t height, int32_t* pipe_depth,
-                                         int32_t* xcd_bands, int32_t* trials_left) {
-    if (!v || !pipe_depth || !xcd_bands || !trials_left) return fail(CINR_INVALID_ARG, "null argument");
+                                         int32_t* xcd_bands, int32_t* waves_per_simd, int32_t* trials_left) {
+    if (!v || !pipe_depth || !xcd_bands || !waves_per_simd || !trials_left)
+        return fail(CINR_INVALID_ARG, "null argument");
     const uint64_t key = ((uint64_t)(uint32_t)width << 32) | (uint32_t)height;
     auto it = v->tuners.find(key);
     if (it == v->tuners.end()) {
-        *pipe_depth = *xcd_bands = 0;
+        *pipe_depth = *xcd_bands = *waves_per_simd = 0;
         *trials_left = SamplerTuner::kCand * SamplerTuner::kRounds;
         return CINR_OK;
     }
@@ -1379,6 +1385,7 @@ extern "C" cinr_status cinr_tuned_launch(cinr_volume v, int32_t width, int32_t h
     const int cand = t.cand();
     *pipe_depth = SamplerTuner::kPipe[cand];
     *xcd_bands = SamplerTuner::kBands[cand];
+    *waves_per_simd = SamplerTuner::kWaves[cand];
     *trials_left = t.best >= 0 ? 0 : SamplerTuner::kCand * SamplerTuner::kRounds - t.trial;
     return CINR_OK;
 }

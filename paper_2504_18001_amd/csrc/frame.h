@@ -139,6 +139,7 @@ struct FrameDev {
     int32_t mode;
     int32_t xcd_bands;  // image bands per XCD in the march kernel's work split
     int32_t pipe;       // samples fetched ahead per ray in the march kernel
+    int32_t waves;      // waves per SIMD of the march kernel's register budget (3 or 4)
     int32_t mc_N;
     FastDiv div_mc;  // division by mc_N
     int32_t M[3];

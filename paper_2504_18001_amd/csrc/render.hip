@@ -464,12 +464,15 @@ struct UnitQueue {
 // marches them in lockstep, so that neighbouring rays read neighbouring brick
 // samples together.  Every lane of a wave runs the same trips of the unit loop
 // so that list reservations can be made per wave.
-// (at least 4 waves per SIMD: the register budget is 128 VGPRs)
+// kWaves: waves per SIMD the register budget allows (3: up to 168 VGPRs, no
+// spills; 4: 128 VGPRs with some spills but more latency hiding).  Neither
+// wins everywhere (short rays favour 3, long ones 4), so the online tuner
+// tries both.
 // kAdapt: adaptive sampling rate (macro-cell codes instead of visibility
 // bits); a sample of step exponent e is followed by sample k + 2^e.  kHalf:
 // binary16 pool.
-template <int kPipe, bool kLdsFlags, bool kFast, bool kAdapt, bool kHalf>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_march(FrameDev f, int32_t it, uint32_t n0) {
+template <int kPipe, bool kLdsFlags, bool kFast, bool kAdapt, bool kHalf, int kWaves>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves, 8))) void k_march(FrameDev f, int32_t it, uint32_t n0) {
     static_assert(!kAdapt || kPipe == 1, "the adaptive sampler decides one sample ahead at most");
     const FrameHot hot = load_hot(f.var);  // before any store of this kernel
     __shared__ float4 tfs[256];
@@ -1116,7 +1119,7 @@ hipError_t launch_frame_begin(const FrameDev& f, int32_t n_iter_ctr, const float
 
 // Workgroups of one k_march instantiation that are resident at once on the
 // current device (the grid of the persistent kernel), cached per device.
-template <int P, bool LDS, bool FAST, bool A, bool H>
+template <int P, bool LDS, bool FAST, bool A, bool H, int W>
 static hipError_t resident_blocks(int* out) {
     static int cache[64] = {0};
     int dev = 0;
@@ -1125,7 +1128,7 @@ static hipError_t resident_blocks(int* out) {
     if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
     if (cache[dev] == 0) {
         int per_cu = 0, n_cu = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_march<P, LDS, FAST, A, H>, kBlock, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_march<P, LDS, FAST, A, H, W>, kBlock, 0);
         if (e != hipSuccess) return e;
         e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess) return e;
@@ -1135,20 +1138,20 @@ static hipError_t resident_blocks(int* out) {
     return hipSuccess;
 }
 
-template <int P, bool LDS, bool FAST, bool A, bool H>
+template <int P, bool LDS, bool FAST, bool A, bool H, int W>
 static hipError_t launch_march_t(const FrameDev& f, int it, int64_t max_rays, uint32_t n0, hipStream_t s) {
     int cap = 0;
-    hipError_t e = resident_blocks<P, LDS, FAST, A, H>(&cap);
+    hipError_t e = resident_blocks<P, LDS, FAST, A, H, W>(&cap);
     if (e != hipSuccess) return e;
     // one work unit (64 rays) per wave at least
     int64_t b = (max_rays + kBlock - 1) / kBlock;
     if (b < 1) b = 1;
     if (b > cap) b = cap;
-    hipLaunchKernelGGL((k_march<P, LDS, FAST, A, H>), dim3((unsigned)b), dim3(kBlock), 0, s, f, it, n0);
+    hipLaunchKernelGGL((k_march<P, LDS, FAST, A, H, W>), dim3((unsigned)b), dim3(kBlock), 0, s, f, it, n0);
     return hipGetLastError();
 }
 
-template <int P, bool LDS, bool A, bool H>
+template <int P, bool LDS, bool A, bool H, int W>
 static hipError_t launch_march_l(const FrameDev& f, int it, int64_t max_rays, uint32_t n0, hipStream_t s) {
     // 16^3 bricks in a pool of less than 4 GiB (or the uncached mode, which
     // reads no pool) and 16^3 macro-cells (or none)
@@ -1157,27 +1160,33 @@ static hipError_t launch_march_l(const FrameDev& f, int it, int64_t max_rays, ui
     const bool fast = (f.mode != CINR_CACHED ||
                        (f.geo.brick == 16 && (uint64_t)f.pool_bricks * brick_bytes < (1ull << 32))) &&
                       (!cells || f.mc_N == 16);
-    if (fast) return launch_march_t<P, LDS, true, A, H>(f, it, max_rays, n0, s);
-    return launch_march_t<P, LDS, false, A, H>(f, it, max_rays, n0, s);
+    if (fast) return launch_march_t<P, LDS, true, A, H, W>(f, it, max_rays, n0, s);
+    return launch_march_t<P, LDS, false, A, H, W>(f, it, max_rays, n0, s);
 }
 
-template <int P, bool A, bool H>
+template <int P, bool A, bool H, int W>
 static hipError_t launch_march_p(const FrameDev& f, int it, int64_t max_rays, uint32_t n0, hipStream_t s) {
     const bool lds = A ? f.n_cells <= kMaxLdsCells : (f.flags && f.flag_words <= kMaxLdsFlagWords);
-    if (lds) return launch_march_l<P, true, A, H>(f, it, max_rays, n0, s);
-    return launch_march_l<P, false, A, H>(f, it, max_rays, n0, s);
+    if (lds) return launch_march_l<P, true, A, H, W>(f, it, max_rays, n0, s);
+    return launch_march_l<P, false, A, H, W>(f, it, max_rays, n0, s);
+}
+
+template <bool H, int W>
+static hipError_t launch_march_w(const FrameDev& f, int it, int64_t n, uint32_t n0, hipStream_t s) {
+    // the adaptive sampler decides its next sample after the current one
+    if (f.adapt > 0) return launch_march_p<1, true, H, W>(f, it, n, n0, s);
+    // kPipe: samples decided and fetched ahead per ray (8 runs as 4)
+    switch (f.pipe) {
+        case 1: return launch_march_p<1, false, H, W>(f, it, n, n0, s);
+        case 2: return launch_march_p<2, false, H, W>(f, it, n, n0, s);
+        default: return launch_march_p<4, false, H, W>(f, it, n, n0, s);
+    }
 }
 
 template <bool H>
 static hipError_t launch_march_h(const FrameDev& f, int it, int64_t n, uint32_t n0, hipStream_t s) {
-    // the adaptive sampler decides its next sample after the current one
-    if (f.adapt > 0) return launch_march_p<1, true, H>(f, it, n, n0, s);
-    // kPipe: samples decided and fetched ahead per ray (8 runs as 4)
-    switch (f.pipe) {
-        case 1: return launch_march_p<1, false, H>(f, it, n, n0, s);
-        case 2: return launch_march_p<2, false, H>(f, it, n, n0, s);
-        default: return launch_march_p<4, false, H>(f, it, n, n0, s);
-    }
+    if (f.waves == 4) return launch_march_w<H, 4>(f, it, n, n0, s);
+    return launch_march_w<H, 3>(f, it, n, n0, s);
 }
 
 // The path tracer's persistent grid, as resident_blocks for k_march.

@@ -229,7 +229,8 @@ def test_path_tracer_workspace_and_arguments():
 
         big = pb.value * 4
         for bad in (dict(pipeline=2), dict(pt_density=0.0), dict(pt_density=float("nan")), dict(pt_spp=0),
-                    dict(pt_spp=65536), dict(pt_max_bounces=0), dict(adapt_max_exp=1)):
+                    dict(pt_spp=65536), dict(pt_max_bounces=0), dict(adapt_max_exp=1), dict(waves_per_simd=5),
+                    dict(waves_per_simd=-1), dict(lod_context=-0.5), dict(lod_context=2.0)):
             assert render(params(**bad), big) == INVALID_ARG, bad
         # a ray-marching workspace is too small for the path tracer
         assert render(params(), rb.value) == -2

@@ -80,7 +80,7 @@ def test_online_launch_tuning_converges_and_changes_nothing():
         cache = cinr.Cache(vol, 16, 4, 400, 20, preload_period=2)
         r = cinr.Renderer()
         out = []
-        for f in range(16):
+        for f in range(28):
             kw = dict(pipe_depth=0, xcd_bands=0) if mode == "tuned" else dict(pipe_depth=2, xcd_bands=4)
             img = r.render(vol, w.camera(f, dims), w.tf(f), w.step, w.lod_scale, frame_index=f, seed=w.seed,
                            ert_threshold=w.ert_threshold, samples_per_iter=w.samples_per_iter, mode=cinr.CACHED,
@@ -88,8 +88,8 @@ def test_online_launch_tuning_converges_and_changes_nothing():
             out.append(img.cpu().numpy())
         imgs[mode] = out
         if mode == "tuned":
-            p, b, left = cinr.tuned_launch(vol, 160, 96)
-            print("tuned launch", p, b, left)
-            assert left == 0 and p in (1, 2) and b in (1, 4, 16)
+            p, b, left, waves = cinr.tuned_launch(vol, 160, 96)
+            print("tuned launch", p, b, waves, left)
+            assert left == 0 and p in (1, 2) and b in (1, 4, 16) and waves in (3, 4)
     for a, b in zip(imgs["tuned"], imgs["fixed"]):
         np.testing.assert_array_equal(a, b)
