@@ -279,7 +279,7 @@ def path_oracle(w, cams, tfs, f, path):
             "sample": f"uncached path tracing of 1/16 of the pixels of frame {f} ({px.size} pixels, {dt:.2f} s)"}
 
 
-def multiview_leg(warmup, steps, dtype, oracle=True):
+def multiview_leg(warmup, steps, dtype, oracle=True, waves=0):
     """Frames of 16 views of 4 INRs through one shared cache (one cache
     manager pass and one multi-INR decode launch per frame)."""
     import torch
@@ -301,7 +301,7 @@ def multiview_leg(warmup, steps, dtype, oracle=True):
     def frame(f):
         views = [(vols[mv.view_inr(v)], mv.camera(v, f), tfs[0 if f % 60 < 30 else 30]) for v in range(mv.n_views)]
         r.render(cache, views, mv.step, mv.lod_scale, frame_index=f, seed=mv.seed, ert_threshold=mv.ert_threshold,
-                 samples_per_iter=mv.samples_per_iter, dtype=dtype, outs=outs)
+                 samples_per_iter=mv.samples_per_iter, dtype=dtype, outs=outs, waves_per_simd=waves)
 
     for f in range(warmup):
         frame(f)
@@ -331,7 +331,7 @@ def multiview_leg(warmup, steps, dtype, oracle=True):
     gcache = cinr.Cache(vols, cs.brick, cs.n_lods, cs.pool_bricks, cs.max_requests, preload_period=cs.preload_period)
     fg = cinr.FrameGraph(gcache, [(vols[mv.view_inr(v)], mv.camera(v, 0), tfs[0]) for v in range(mv.n_views)],
                          mv.step, mv.lod_scale, seed=mv.seed, ert_threshold=mv.ert_threshold,
-                         samples_per_iter=mv.samples_per_iter, dtype=dtype)
+                         samples_per_iter=mv.samples_per_iter, dtype=dtype, waves_per_simd=waves)
 
     def gframe(f):
         if f % 30 == 0:

@@ -167,7 +167,9 @@ typedef struct {
  *                (1 to 64).
  *  waves_per_simd tuning: the sampler's register budget, 3 waves per SIMD
  *                (168 registers, no spills) or 4 (128 registers); 0 takes
- *                the tuned value, or 3 when the launch is not tuned.
+ *                the tuned value, or 3 when the launch is not tuned; frames
+ *                of several views (cinr_render_views, frame graphs) take 4,
+ *                since their views march concurrently.
  *                Results depend on none of them.  0 in pipe_depth or
  *                xcd_bands tunes the launch online, per volume and image
  *                size: the first 24 frames of that size try pipe depths

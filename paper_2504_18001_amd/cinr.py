@@ -513,7 +513,8 @@ class MultiViewRenderer:
         self._keep = []
 
     def describe(self, views, step, lod_scale=0.0, frame_index=0, seed=0, ert_threshold=2.0, samples_per_iter=32,
-                 dtype="f32", outs=None, pipe_depth=0, xcd_bands=0, adapt_max_exp=0, path=None, lod_context=0.0):
+                 dtype="f32", outs=None, pipe_depth=0, xcd_bands=0, adapt_max_exp=0, path=None, lod_context=0.0,
+                 waves_per_simd=0):
         """The cinr_view array of `views` (list of (volume, camera, tf)) and
         their output images; the TF tensors are kept alive by the renderer."""
         n = len(views)
@@ -540,6 +541,7 @@ class MultiViewRenderer:
             p.pipe_depth, p.xcd_bands = int(pipe_depth), int(xcd_bands)
             p.adapt_max_exp = int(adapt_max_exp)
             p.lod_context = float(lod_context)
+            p.waves_per_simd = int(waves_per_simd)
             _set_path(p, path)
             v.d_rgba = outs[i].data_ptr()
             v.d_stats = self.stats[i].data_ptr()
@@ -550,10 +552,10 @@ class MultiViewRenderer:
 
     def render(self, cache: Cache, views, step, lod_scale=0.0, frame_index=0, seed=0, ert_threshold=2.0,
                samples_per_iter=32, dtype="f32", outs=None, pipe_depth=0, xcd_bands=0, adapt_max_exp=0, path=None,
-               lod_context=0.0):
+               lod_context=0.0, waves_per_simd=0):
         """views: list of (volume, camera, tf); returns the list of RGBA images."""
         arr, outs = self.describe(views, step, lod_scale, frame_index, seed, ert_threshold, samples_per_iter, dtype,
-                                  outs, pipe_depth, xcd_bands, adapt_max_exp, path, lod_context)
+                                  outs, pipe_depth, xcd_bands, adapt_max_exp, path, lod_context, waves_per_simd)
         _check(lib().cinr_render_views(cache.h, len(views), arr, _stream()))
         return outs
 
@@ -570,12 +572,14 @@ class FrameGraph:
     frames.  Owns the views' workspaces, images and statistics."""
 
     def __init__(self, cache: Cache, views, step, lod_scale=0.0, seed=0, ert_threshold=2.0, samples_per_iter=32,
-                 dtype="f32", pipe_depth=0, xcd_bands=0, adapt_max_exp=0, device="cuda", path=None, lod_context=0.0):
+                 dtype="f32", pipe_depth=0, xcd_bands=0, adapt_max_exp=0, device="cuda", path=None, lod_context=0.0,
+                 waves_per_simd=0):
         self.cache = cache
         self.volumes = [v for v, _, _ in views]
         self.mv = MultiViewRenderer(len(views), device)
         arr, self.outs = self.mv.describe(views, step, lod_scale, 0, seed, ert_threshold, samples_per_iter, dtype,
-                                          None, pipe_depth, xcd_bands, adapt_max_exp, path, lod_context)
+                                          None, pipe_depth, xcd_bands, adapt_max_exp, path, lod_context,
+                                          waves_per_simd)
         self.tfs = list(self.mv._keep)
         self.n = len(views)
         h = C.c_void_p()

@@ -1175,6 +1175,10 @@ cinr_status prepare_views(cinr_cache c, int32_t n_views, const cinr_view* views,
         cinr_status st = prepare_view(c, w.volume, &w.camera, w.d_tf, &w.params, w.d_rgba, w.d_stats, w.d_workspace,
                                       w.workspace_bytes, runs[i]);
         if (st) return fail(st, "view %d: %s", i, cinr_last_error());
+        // views march concurrently on side streams: the 4-wave register
+        // budget lets the views' waves share the CUs (the tuner times each
+        // view alone, which favours 3); a caller's choice is kept
+        if (n_views > 1 && w.params.waves_per_simd == 0) runs[i].f.waves = 4;
         runs[i].f.view_index = i;
         runs[i].f.n_views = n_views;
     }
