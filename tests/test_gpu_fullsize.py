@@ -220,3 +220,39 @@ def test_prefilled_fullsize_path_tracing_pixels(scene, dtype):
     assert frac <= 0.01
     assert st["misses"] == 0 and st["samples"] > st["rays"] > 0  # the coarsest LoD is resident
     assert (ref[:, 3] > 0).mean() > 0.05
+
+
+@pytest.mark.parametrize("adapt,kappa", [(2, 0.0), (0, 0.5), (3, 0.7)])
+def test_prefilled_fullsize_adaptive_rate_and_lod_context_pixels(scene, adapt, kappa):
+    # the bench configuration with the adaptive sampling rate (the TF's
+    # opacity scaled by 0.1, so that cells take step exponents up to 3)
+    # and/or the context-aware LoD, on sampled pixels against the oracle
+    from oracle import oracle as O
+    from paper_2504_18001_amd import cinr
+    vol, m, mm = scene
+    off = vol.geometry(W.cache.brick, W.cache.n_lods)[1]
+    keys = _prefill_keys(off, seed=13)
+    cache = _gpu_cache(vol)
+    cache.prefill(torch.from_numpy(keys).cuda(), stamp=0, dtype="bf16x3")
+    oc = _oracle_cache(m)
+    oc.prefill(keys, 0)
+    f = 12
+    cam = W.camera(f)
+    tf = np.array(W.tf(f), np.float32)
+    tf[:, 3] *= 0.1
+    r = cinr.Renderer()
+    img = r.render(vol, cam, tf, W.step, W.lod_scale, frame_index=f, seed=W.seed, ert_threshold=W.ert_threshold,
+                   samples_per_iter=W.samples_per_iter, mode=cinr.CACHED, dtype="bf16x3", cache=cache,
+                   adapt_max_exp=adapt, lod_context=kappa)
+    px = _pixels(4)
+    got = img.reshape(-1, 4)[torch.from_numpy(px).long().cuda()].cpu().numpy().astype(np.float64)
+    p = O.make_params(W.step, W.lod_scale, seed=W.seed, frame_index=f, ert_threshold=W.ert_threshold,
+                      samples_per_iter=W.samples_per_iter, mode=O.CACHED, macro_cell=W.macro_cell, macro_minmax=mm,
+                      adapt_max_exp=adapt if adapt > 0 else -1, lod_context=kappa)
+    ref = O.render_pixels(m, cam, tf, p, px, cache=oc)
+    d = np.abs(got - ref)
+    mse = float((d ** 2).mean())
+    psnr = 10 * np.log10(1.0 / mse) if mse > 0 else float("inf")
+    print(f"adaptive E={adapt}, kappa={kappa}: {r.last_stats()}; max abs {d.max():.2e}, PSNR {psnr:.1f}")
+    assert d.max() <= 8e-3 and psnr >= 45.0
+    assert ref[:, 3].max() > 0.05
