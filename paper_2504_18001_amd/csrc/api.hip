@@ -560,6 +560,7 @@ struct RenderLayout {
     unsigned long long* stats;
     FrameVar* var;
     uint32_t* gate;  // frame-end gate (view 0's is the frame's)
+    uint32_t* ticket;  // finished workgroups of the first march (fused gather)
     uint8_t* cell_code;  // adaptive sampling: per macro-cell step codes
     uint8_t* vexp;       // adaptive sampling: step exponent of each gathered sample
     PtState* pts;        // path tracing: per-pixel path state (null for ray marching)
@@ -581,6 +582,7 @@ static size_t render_layout(int64_t npix, int32_t S, int64_t n_cells, bool path,
     x.stats = cv.take<unsigned long long>(ST_COUNT);
     x.var = cv.take<FrameVar>(1);
     x.gate = cv.take<uint32_t>(1);
+    x.ticket = cv.take<uint32_t>(1);
     x.cell_code = cv.take<uint8_t>((size_t)(n_cells > 0 ? n_cells : 1));
     x.vexp = cv.take<uint8_t>((size_t)npix * S);
     x.pts = path ? cv.take<PtState>((size_t)npix) : nullptr;
@@ -1058,17 +1060,25 @@ cinr_status render_frame_views(cinr_cache c, std::vector<ViewRun>& runs, Timing&
         runs[i].st = side ? c->vs[i % cinr_cache_s::kViewStreams] : s;
         runs[i].stage = rv->stage + i;
     }
+    uint32_t* gate = runs[0].L.gate;
+    uint32_t* pinned = (uint32_t*)rv->pinned;
+    // one ray-marched view: its first march hands over the pending count
+    const bool fused = runs.size() == 1 && !runs[0].f.path.on;
+    if (fused) {
+        runs[0].f.gather_host = pinned;
+        runs[0].f.gather_gate = gate;
+        runs[0].f.exit_ticket = runs[0].L.ticket;
+    }
     st = start_views(c, runs, side, s);
+    if (fused) runs[0].f.gather_host = runs[0].f.gather_gate = runs[0].f.exit_ticket = nullptr;
     if (st) return st;
     if (side) {
         st = join_side_streams(c, s);
         if (st) return st;
     }
-    uint32_t* gate = runs[0].L.gate;
     std::vector<const FrameDev*> fs;
     for (const ViewRun& r : runs) fs.push_back(&r.f);
-    uint32_t* pinned = (uint32_t*)rv->pinned;
-    HIP_TRY(launch_pending_gather(fs.data(), (int)runs.size(), pinned, gate, s));
+    if (!fused) HIP_TRY(launch_pending_gather(fs.data(), (int)runs.size(), pinned, gate, s));
     HIP_TRY(hipEventRecord(rv->ev, s));
     const bool lru = c && lru_pass_needed(c);
     st = end_views(c, runs, lru, tm, gate, s);

@@ -153,6 +153,13 @@ struct FrameDev {
     uint8_t* vexp;       // [W*H*S] step exponent of each gathered sample
     PtDev path;          // path tracing (path.on), else ray marching
     float lod_ctx;       // context-aware LoD weight (0: off)
+    // Single-view frames: the first march's last workgroup writes the pending
+    // count to *gather_host (pinned) and sets *gather_gate, in place of a
+    // separate gather launch (null otherwise); exit_ticket counts its
+    // finished workgroups (cleared by k_frame_begin).
+    uint32_t* gather_host;
+    uint32_t* gather_gate;
+    uint32_t* exit_ticket;
     const float* minmax; // the volume's macro-cells [n_cells][2] (context-aware LoD)
     uint32_t* claim;     // [2][8] work-unit counters of the march kernel (one set per iteration
                          // parity), kClaimStride words apart

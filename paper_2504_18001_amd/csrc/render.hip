@@ -366,6 +366,7 @@ __global__ __launch_bounds__(kBlock) void k_frame_begin(FrameDev f, int32_t n_ct
         cctr->n_views = (uint32_t)f.n_views;
     }
     if (t == 0 && f.view_table) f.view_table[f.view_index] = ViewEnd{f.stats, f.ctr, f.max_iters, 0};
+    if (t == 0 && f.exit_ticket) *f.exit_ticket = 0u;
     if (t < n_ctr) f.ctr[t] = IterCtr{0u, 0u, 0u, 0u};
     if (t < 16) f.claim[t * kClaimStride] = 0u;
     if (t < ST_COUNT) f.stats[t] = 0ull;
@@ -672,6 +673,23 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves, 
         }
     }
     tally.commit(f.stats);
+    if (it == 0 && f.gather_host) {
+        // the frame's pending count once every workgroup has finished: the
+        // last one to take a ticket reads it (all reservations precede the
+        // fences) and hands it to the host and to the frame-end gate
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence();
+            const uint32_t ticket = atomicAdd(f.exit_ticket, 1u);
+            if (ticket == gridDim.x - 1u) {
+                __threadfence();
+                const uint32_t pending = atomicAdd(&f.ctr[0].pending, 0u);
+                f.gather_host[f.view_index] = pending;
+                *f.gather_gate = pending == 0u ? 1u : 0u;
+                __threadfence_system();
+            }
+        }
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_shade(FrameDev f, int32_t it) {

@@ -1,6 +1,7 @@
 """The learned part end to end at its full size: an INR (16 levels x 2, T =
-2^20, 32-64-64-1) trained on the GPU for 2000 steps of 2^18 points on a
-1024^3 turbulence-like field (512 Fourier modes, amplitude |k|^-5/3), judged
+2^20, 32-64-64-1) trained on the GPU for 2000 steps of 2^18 points (the last
+200 at a tenth of the learning rate) on a 1024^3 turbulence-like field (512
+Fourier modes, amplitude |k|^-5/3), judged
 by PSNR over all 1024^3 lattice points against the explicit grid, and
 rendered at 1080p against the explicit-grid source with the same cached
 renderer.  The gain is measured against the untrained (random-init) INR;
@@ -19,6 +20,7 @@ pytestmark = pytest.mark.gpu
 
 V = 1024
 STEPS = 2000
+ANNEAL_FROM = 1800
 
 
 def psnr_lattice(vol, grid, chunk_z=16):
@@ -76,6 +78,8 @@ def test_trained_inr_gains_over_the_untrained_one_at_full_size():
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record()
     for s in range(STEPS):
+        if s == ANNEAL_FROM:
+            tr.set_lr(1e-3)  # the last tenth at a tenth of the rate
         tr.step(grid, s, loss)
     stop.record()
     torch.cuda.synchronize()
@@ -95,7 +99,5 @@ def test_trained_inr_gains_over_the_untrained_one_at_full_size():
            "train_ms_per_step": round(ms, 3), "final_batch_loss": loss.item()}
     print(json.dumps(rep))
     assert p_trained > p_random + 30.0
-    # FP32 atomics make the accumulation order, and with it the Adam
-    # trajectory, differ between runs: 42.6 to 52.4 dB have been seen
-    assert p_trained > 40.0
+    assert p_trained > 45.0
     assert p_render > 35.0
