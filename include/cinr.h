@@ -172,10 +172,13 @@ typedef struct {
  *                since their views march concurrently.
  *                Results depend on none of them.  0 in pipe_depth or
  *                xcd_bands tunes the launch online, per volume and image
- *                size: the first 24 frames of that size try pipe depths
- *                {1, 2} x bands {1, 4, 16} x waves {3, 4} twice each, then
- *                the fastest first-iteration march is kept
- *                (cinr_tuned_launch reports the choice).
+ *                size: frames of that size try pipe depths {1, 2} x bands
+ *                {1, 4, 16} x waves {3, 4} twice each (24 trials, the second
+ *                round in reverse order), then the fastest first-iteration
+ *                march is kept (cinr_tuned_launch reports the choice).  A
+ *                frame whose first march leaves rays waiting on true misses
+ *                is not counted (its march was cut short) until 96 such
+ *                frames have passed.
  *  adapt_max_exp adaptive sampling rate (Section 5.2), with the volume's
  *                macro-cells: E > 0 lets a ray cross a macro-cell of maximum
  *                TF opacity mu in steps of 2^e sample spacings, e =

@@ -110,12 +110,25 @@ struct SamplerTuner {
     static constexpr int kBands[kCand] = {1, 1, 4, 4, 16, 16, 1, 1, 4, 4, 16, 16};
     static constexpr int kWaves[kCand] = {3, 3, 3, 3, 3, 3, 4, 4, 4, 4, 4, 4};
     static constexpr int kRounds = 2;
+    // a trial counts when the view's first march left no ray pending (a whole
+    // march, as in steady state); after this many frames cut short by true
+    // misses, trials count anyway
+    static constexpr int kMaxWait = 96;
     int trial = 0;           // frames tried so far
+    int waited = 0;          // trial frames not counted
     float ms[kCand] = {};
     int best = -1;
     hipEvent_t a = nullptr, b = nullptr;
     bool pending = false;    // events of the current trial recorded, not yet read
-    int cand() const { return best >= 0 ? best : trial % kCand; }
+    // Candidate of trial t: rounds alternate in direction (0..11, then
+    // 11..0), so that each candidate's two frames sit symmetrically in the
+    // trial window and a trend in the frames' cost (a cache warming up, a
+    // pre-load floor dropping) weighs on every candidate alike.
+    static int of_trial(int t) {
+        const int i = t % kCand;
+        return (t / kCand) % 2 == 0 ? i : kCand - 1 - i;
+    }
+    int cand() const { return best >= 0 ? best : of_trial(trial); }
 };
 
 struct cinr_volume_s {
@@ -921,13 +934,17 @@ cinr_status view_continue(ViewRun& r, uint32_t pending, hipStream_t s) {
 }
 
 // Tuner bookkeeping once the view's first march has completed.
-cinr_status tuner_collect(ViewRun& r) {
+cinr_status tuner_collect(ViewRun& r, uint32_t first_pending) {
     SamplerTuner* t = r.tuner;
     if (!r.timing_trial || !t || !t->pending) return CINR_OK;
     float ms = 0.0f;
     HIP_TRY(hipEventElapsedTime(&ms, t->a, t->b));
     t->pending = false;
-    t->ms[t->trial % SamplerTuner::kCand] += ms;
+    if (first_pending != 0u && t->waited < SamplerTuner::kMaxWait) {
+        t->waited += 1;  // the same candidate is tried again on the next frame
+        return CINR_OK;
+    }
+    t->ms[SamplerTuner::of_trial(t->trial)] += ms;
     t->trial += 1;
     if (t->trial >= SamplerTuner::kCand * SamplerTuner::kRounds) {
         int best = 0;
@@ -1006,9 +1023,10 @@ cinr_status continue_views(cinr_cache c, std::vector<ViewRun>& runs, bool side, 
         }
         for (size_t i = 0; i < runs.size(); ++i) {
             if (!runs[i].live) continue;
-            cinr_status st = tuner_collect(runs[i]);
+            const uint32_t pending = have ? known[i] : ((volatile uint32_t*)pinned)[i];
+            cinr_status st = tuner_collect(runs[i], pending);
             if (st) return st;
-            st = view_continue(runs[i], have ? known[i] : ((volatile uint32_t*)pinned)[i], runs[i].st);
+            st = view_continue(runs[i], pending, runs[i].st);
             if (st) return st;
         }
     }
@@ -1101,7 +1119,7 @@ cinr_status render_frame_views(cinr_cache c, std::vector<ViewRun>& runs, Timing&
         if (st) return st;
     } else {
         for (ViewRun& r : runs) {
-            st = tuner_collect(r);
+            st = tuner_collect(r, 0u);
             if (st) return st;
         }
     }

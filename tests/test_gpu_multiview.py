@@ -80,7 +80,8 @@ def test_online_launch_tuning_converges_and_changes_nothing():
         cache = cinr.Cache(vol, 16, 4, 400, 20, preload_period=2)
         r = cinr.Renderer()
         out = []
-        for f in range(28):
+        # 24 trials, plus up to 96 frames cut short by true misses
+        for f in range(124):
             kw = dict(pipe_depth=0, xcd_bands=0) if mode == "tuned" else dict(pipe_depth=2, xcd_bands=4)
             img = r.render(vol, w.camera(f, dims), w.tf(f), w.step, w.lod_scale, frame_index=f, seed=w.seed,
                            ert_threshold=w.ert_threshold, samples_per_iter=w.samples_per_iter, mode=cinr.CACHED,
