@@ -103,10 +103,13 @@ struct BrickDst {
 
 template <class Eng, class Src, class Dst>
 __global__ __launch_bounds__(kBlock) void k_inr_points(const InrDev m, const Src src, const Dst dst) {
+    const int64_t n = src.count();
+    // grids are sized for a capacity: a workgroup with no point leaves before
+    // loading the weights (the count is the same for the whole workgroup)
+    if ((int64_t)blockIdx.x * kBlock >= n) return;
     Eng eng;
     eng.load_weights(m);
     __shared__ typename Eng::Lds lds;
-    const int64_t n = src.count();
     for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n; base += (int64_t)gridDim.x * kBlock) {
         const int64_t idx = base + threadIdx.x;
         const bool valid = idx < n;
@@ -120,10 +123,13 @@ __global__ __launch_bounds__(kBlock) void k_inr_points(const InrDev m, const Src
 // Brick decoding: like k_inr_points, invalid requests produce NaN bricks.
 template <class Eng>
 __global__ __launch_bounds__(kBlock) void k_decode(const InrDev m, const BrickSrc src, const BrickDst dst) {
+    const int64_t n = src.count();
+    // launched for the frame's request cap: with fewer (or no) selected
+    // bricks, idle workgroups leave before loading the weights
+    if ((int64_t)blockIdx.x * kBlock >= n) return;
     Eng eng;
     eng.load_weights(m);
     __shared__ typename Eng::Lds lds;
-    const int64_t n = src.count();
     for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n; base += (int64_t)gridDim.x * kBlock) {
         const int64_t idx = base + threadIdx.x;
         const bool valid = idx < n;
