@@ -611,6 +611,13 @@ orc_cache* orc_cache_create_multi(const orc_inr* ms, int32_t n_vols, const orc_c
     if (d->brick < 2 || d->n_lods < 1 || d->n_lods > ORC_MAX_LODS || d->pool_bricks < 0 || d->max_requests < 0)
         return NULL;
     if (n_vols < 1 || n_vols > ORC_MAX_VOLS) return NULL;
+    if (d->f16_lods) {
+        const uint32_t all = d->n_lods >= 32 ? 0xFFFFFFFFu : (1u << d->n_lods) - 1u;
+        const int32_t p16 = d->pool_bricks_f16, p32 = d->pool_bricks - d->pool_bricks_f16;
+        if (d->pool_f16 || (d->f16_lods & ~all) || d->f16_lods == all || p16 < 1 || p32 < 1 ||
+            d->max_requests > p16 || d->max_requests > p32)
+            return NULL;
+    }
     for (int i = 1; i < n_vols; ++i)
         for (int a = 0; a < 3; ++a)
             if (ms[i].dims[a] != ms[0].dims[a]) return NULL;
@@ -716,20 +723,49 @@ int64_t orc_cache_ert_trace(const orc_cache* c, int32_t* out, int64_t cap) {
     return c->n_ert_trace;
 }
 
+/* LoD of a key (of any volume sharing the cache). */
+static int key_lod(const orc_cache* c, int64_t key) {
+    const int64_t k = key % c->keys_per_vol;
+    int L = 0;
+    while (L + 1 < c->d.n_lods && k >= c->g[L + 1].off) ++L;
+    return L;
+}
+
+/* First binary16 slot: the pool's binary16 class is [split, pool_bricks);
+ * pool_bricks when the pool has one class. */
+static int32_t f16_split(const orc_cache* c) {
+    return c->d.f16_lods ? c->d.pool_bricks - c->d.pool_bricks_f16 : c->d.pool_bricks;
+}
+
+/* Slots [lo, hi) of the class a key's bricks are stored in. */
+static void key_slots(const orc_cache* c, int64_t key, int32_t* lo, int32_t* hi) {
+    const int32_t split = f16_split(c);
+    if (c->d.f16_lods && ((c->d.f16_lods >> key_lod(c, key)) & 1u)) {
+        *lo = split;
+        *hi = c->d.pool_bricks;
+    } else {
+        *lo = 0;
+        *hi = split;
+    }
+}
+
 /* Insert one brick (Figure 1 step (5)): lowest free slot, otherwise the least
  * recently used slot by (last_used, slot) among slots not filled by this
- * batch.  The evicted brick's page-table entry is unmapped and its rank
- * forgotten; the new brick is decoded into the slot, mapped, and stamped. */
+ * batch, both among the slots of the brick's class (the whole pool unless
+ * the pool mixes binary32 and binary16 LoDs).  The evicted brick's
+ * page-table entry is unmapped and its rank forgotten; the new brick is
+ * decoded into the slot, mapped, and stamped. */
 static void insert_brick(orc_cache* c, int32_t key, int32_t stamp, uint8_t* filled, int32_t* slot_out) {
-    const int32_t P = c->d.pool_bricks;
+    int32_t lo, hi;
+    key_slots(c, key, &lo, &hi);
     int32_t slot = -1;
-    for (int32_t s = 0; s < P; ++s)
+    for (int32_t s = lo; s < hi; ++s)
         if (c->owner[s] < 0) {
             slot = s;
             break;
         }
     if (slot < 0) {
-        for (int32_t s = 0; s < P; ++s) {
+        for (int32_t s = lo; s < hi; ++s) {
             if (filled[s]) continue;
             if (slot < 0 || c->last_used[s] < c->last_used[slot]) slot = s;
         }
@@ -788,18 +824,25 @@ static void decode_inserted(orc_cache* c, const int32_t* keys, const int32_t* sl
                               (int32_t)(local / ((int64_t)c->g[L].nb[0] * c->g[L].nb[1]))};
         double* dst = c->pool + (int64_t)slots[i] * B3;
         decode_brick(&c->inrs[vol], L, b, c->d.brick, dst);
-        if (c->d.pool_f16)
+        if (c->d.pool_f16 || slots[i] >= f16_split(c))
             for (int64_t v = 0; v < B3; ++v) dst[v] = orc_round_half(dst[v]);
     }
 }
 
 /* Pre-loading into free slots only (never evicts). */
 int orc_cache_prefill(orc_cache* c, const int32_t* keys, int64_t n, int32_t stamp) {
-    int64_t n_free = 0;
-    for (int32_t s = 0; s < c->d.pool_bricks; ++s) n_free += c->owner[s] < 0;
-    if (n > n_free) return -1;
     for (int64_t i = 0; i < n; ++i)
         if (keys[i] < 0 || keys[i] >= c->n_keys || c->pt[keys[i]] >= 0) return -1;
+    /* every key needs a free slot of its class */
+    const int32_t split = f16_split(c);
+    int64_t n_free[2] = {0, 0}, need[2] = {0, 0};
+    for (int32_t s = 0; s < c->d.pool_bricks; ++s) n_free[s >= split] += c->owner[s] < 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t lo, hi;
+        key_slots(c, keys[i], &lo, &hi);
+        need[lo > 0] += 1;  /* the binary16 class starts above slot 0 */
+    }
+    if (need[0] > n_free[0] || need[1] > n_free[1]) return -1;
     for (int64_t i = 0; i < n; ++i)
         for (int64_t j = i + 1; j < n; ++j)
             if (keys[i] == keys[j]) return -1;

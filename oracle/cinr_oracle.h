@@ -99,6 +99,15 @@ typedef struct {
     int32_t preload_period; /* frames per LoD step of the coarse-LoD pre-load; 0 = off */
     int32_t pool_f16;     /* nonzero: inserted brick values are rounded to binary16 (a reduced-precision
                              pool, Section 7's future work); 0 = values kept as decoded */
+    /* LoD-dependent mixed precision (Section 7's future work): with f16_lods
+     * nonzero, bit L set stores LoD L's bricks in the binary16 class of slots
+     * [pool_bricks - pool_bricks_f16, pool_bricks) (values rounded to binary16),
+     * the other LoDs in the binary32 class of the slots below.  A brick takes
+     * a slot of its class only: the class's lowest free slot, else the class's
+     * least recently used slot.  Requires pool_f16 = 0, a proper non-empty
+     * subset of the LoDs, and max_requests <= the slots of either class. */
+    uint32_t f16_lods;
+    int32_t pool_bricks_f16;
 } orc_cache_desc;
 
 typedef struct {

@@ -48,7 +48,8 @@ class Params(C.Structure):
 class CacheDesc(C.Structure):
     _fields_ = [("brick", C.c_int32), ("n_lods", C.c_int32), ("pool_bricks", C.c_int32),
                 ("max_requests", C.c_int32), ("rank_window", C.c_int32), ("ranking", C.c_int32),
-                ("preload_period", C.c_int32), ("pool_f16", C.c_int32)]
+                ("preload_period", C.c_int32), ("pool_f16", C.c_int32), ("f16_lods", C.c_uint32),
+                ("pool_bricks_f16", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -431,7 +432,8 @@ class OracleCache:
     equal dimensions (volume i owns keys [i K, (i+1) K))."""
 
     def __init__(self, inr, brick, n_lods, pool_bricks, max_requests, rank_window=1000, ranking=1,
-                 preload_period=0, log_misses=False, trace_ert=False, pool_f16=False):
+                 preload_period=0, log_misses=False, trace_ert=False, pool_f16=False, f16_lods=0,
+                 pool_bricks_f16=0):
         inrs = list(inr) if isinstance(inr, (list, tuple)) else [inr]
         self.inrs = inrs
         self.inr = inrs[0]
@@ -439,6 +441,7 @@ class OracleCache:
         d.brick, d.n_lods, d.pool_bricks, d.max_requests = brick, n_lods, pool_bricks, max_requests
         d.rank_window, d.ranking, d.preload_period = rank_window, ranking, preload_period
         d.pool_f16 = 1 if pool_f16 else 0
+        d.f16_lods, d.pool_bricks_f16 = f16_lods, pool_bricks_f16
         self.desc = d
         self._descs = (Inr * len(inrs))(*[m.desc for m in inrs])
         self.h = lib().orc_cache_create_multi(C.cast(self._descs, C.c_void_p), len(inrs), C.byref(d))
