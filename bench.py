@@ -84,12 +84,12 @@ def make_scene(w, dtype_decode="bf16"):
     return vol, cams, tfs
 
 
-def new_cache(vol, w, pool_dtype="f32", pool_bricks=None):
+def new_cache(vol, w, pool_dtype="f32", pool_bricks=None, f16_lods=0, pool_bricks_f16=0):
     from paper_2504_18001_amd import cinr
     cs = w.cache
     return cinr.Cache(vol, cs.brick, cs.n_lods, pool_bricks or cs.pool_bricks, cs.max_requests,
                       rank_window=cs.rank_window, ranking=cs.ranking, preload_period=cs.preload_period,
-                      pool_dtype=pool_dtype)
+                      pool_dtype=pool_dtype, f16_lods=f16_lods, pool_bricks_f16=pool_bricks_f16)
 
 
 def run_frames(r, vol, cams, tfs, w, frames, mode, dtype, cache, stats=None, out=None):
@@ -129,12 +129,21 @@ def decode_throughput(vol, w, dtype, n_bricks, reps=5):
 
 def pool_f16_leg(vol, cams, tfs, w, Wm, K, dtype, ref_img):
     """The headline sequence over a binary16 pool: the same slot count (half
-    the bytes) and the same bytes (twice the slots), against the FP32 pool."""
+    the bytes) and the same bytes (twice the slots), against the FP32 pool;
+    then LoD-dependent mixed precision with the same slot count, half of the
+    slots binary16: LoDs 1 and up in binary16 (LoD 0 kept in binary32), and
+    the reverse."""
     import torch
     from paper_2504_18001_amd import cinr
+    P = w.cache.pool_bricks
+    coarse = ((1 << w.cache.n_lods) - 1) & ~1
     res = {}
-    for name, slots in (("same_slots", w.cache.pool_bricks), ("same_bytes", 2 * w.cache.pool_bricks)):
-        c = new_cache(vol, w, pool_dtype="f16", pool_bricks=slots)
+    for name, slots, mask in (("same_slots", P, 0), ("same_bytes", 2 * P, 0), ("mixed_lod0_f32", P, coarse),
+                              ("mixed_lod0_f16", P, 1)):
+        if mask:
+            c = new_cache(vol, w, pool_bricks=slots, f16_lods=mask, pool_bricks_f16=slots // 2)
+        else:
+            c = new_cache(vol, w, pool_dtype="f16", pool_bricks=slots)
         r = cinr.Renderer()
         out = torch.empty((w.height, w.width, 4), dtype=torch.float32, device="cuda")
         st = torch.zeros((K, len(cinr.STAT_FIELDS)), dtype=torch.int64, device="cuda")
@@ -148,10 +157,14 @@ def pool_f16_leg(vol, cams, tfs, w, Wm, K, dtype, ref_img):
         vol.set_timing(False)
         ms, n = vol.collect_timing()["march"]
         tot = st.sum(0).cpu().numpy()
-        res[name] = {"fps": round(fps, 2), "pool_slots": slots, "pool_gib": round(c.pool.numel() * 2 / 2 ** 30, 3),
+        res[name] = {"fps": round(fps, 2), "pool_slots": slots,
+                     "pool_gib": round(c.pool.numel() * c.pool.element_size() / 2 ** 30, 3),
                      "march_ms_per_launch": round(ms / max(n, 1), 4),
                      "true_misses_per_frame": int(tot[cinr.STAT_FIELDS.index("misses")]) // K,
                      "psnr_vs_f32_pool_db": round(psnr(ref_img, out.cpu().numpy()), 2)}
+        if mask:
+            res[name]["f16_lods"] = mask
+            res[name]["binary16_slots"] = slots // 2
         del c
     return res
 

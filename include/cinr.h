@@ -126,7 +126,20 @@ typedef struct {
  *  pool_dtype    CINR_F32 (0) or CINR_F16: binary16 brick values (decoded
  *                values rounded to nearest, ties to even), half the pool
  *                memory; the sampler interpolates them in FP32 (a reduced-
- *                precision pool, the paper's future work, Sec. 7). */
+ *                precision pool, the paper's future work, Sec. 7).
+ *  f16_lods, pool_bricks_f16  LoD-dependent mixed precision (Sec. 7's
+ *                future work: an encoding per LoD).  0 = one class of
+ *                pool_dtype.  Otherwise bit L of f16_lods stores LoD L's
+ *                bricks as binary16 (rounded as above) in the slots
+ *                [pool_bricks - pool_bricks_f16, pool_bricks), and the other
+ *                LoDs as binary32 in the slots below.  A brick takes a slot of
+ *                its class only: the class's lowest free slot, else the
+ *                class's least recently used slot (same order as the one-class
+ *                pool).  Requires pool_dtype = CINR_F32, a non-empty proper
+ *                subset of the LoDs, and max_requests <= the slots of each
+ *                class.  A LoD whose error bound admits binary16 rounding
+ *                (at most 2^-12 for the pool's values in [0, 1]) can take
+ *                the binary16 class. */
 typedef struct {
     int32_t brick, n_lods, pool_bricks, max_requests, rank_window;
     int32_t ranking;
@@ -135,6 +148,8 @@ typedef struct {
     int32_t evict_log_capacity;
     int32_t keep_request_counts;
     int32_t pool_dtype;
+    uint32_t f16_lods;
+    int32_t pool_bricks_f16;
 } cinr_cache_desc;
 
 /* Pinhole or orthographic camera.  Basis vectors are unit length; pixel
@@ -261,7 +276,8 @@ typedef enum {
                                    (pixel, k) pair can repeat: an event looked up ahead after a true miss is drawn
                                    again by the segment that follows a real collision) */
     CINR_DUMP_EVICTION_LOG = 7, /* {int32 stamp, slot, old_key, new_key} [n] since creation */
-    CINR_DUMP_POOL = 8          /* pool_dtype values [pool_bricks][B][B][B]: float, or binary16 bits */
+    CINR_DUMP_POOL = 8          /* pool_dtype values [pool_bricks][B][B][B]: float, or binary16 bits; a mixed
+                                   pool: float [split][B][B][B], then binary16 bits [pool_bricks - split][B][B][B] */
 } cinr_dump_kind;
 
 typedef struct cinr_volume_s* cinr_volume;
@@ -317,9 +333,11 @@ cinr_status cinr_build_macrocells(cinr_volume vol, int32_t cell, float* d_minmax
  * counts, slot owners and stamps, request and log buffers). */
 cinr_status cinr_cache_workspace_size(cinr_volume vol, const cinr_cache_desc* desc, size_t* bytes);
 
-/* Creates a cache over a caller-provided pool (f32, >= pool_bricks*B^3
- * values) and workspace; initialises the workspace on `stream` (all bricks
- * unmapped, all slots free). */
+/* Creates a cache over a caller-provided pool and workspace; initialises
+ * the workspace on `stream` (all bricks unmapped, all slots free).  The pool
+ * holds pool_bricks*B^3 values of pool_dtype, or for a mixed pool
+ * (pool_bricks - pool_bricks_f16)*B^3 binary32 values followed by
+ * pool_bricks_f16*B^3 binary16 values. */
 cinr_status cinr_create_cache(cinr_volume vol, const cinr_cache_desc* desc, void* d_pool, size_t pool_bytes,
                               void* d_workspace, size_t ws_bytes, void* stream, cinr_cache* out);
 void cinr_destroy_cache(cinr_cache cache);

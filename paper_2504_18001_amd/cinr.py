@@ -42,7 +42,19 @@ class VolumeDesc(C.Structure):
 class CacheDesc(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("brick", "n_lods", "pool_bricks", "max_requests", "rank_window", "ranking",
                                           "preload_period", "miss_log_capacity", "evict_log_capacity",
-                                          "keep_request_counts", "pool_dtype")]
+                                          "keep_request_counts", "pool_dtype")] + [
+        ("f16_lods", C.c_uint32), ("pool_bricks_f16", C.c_int32)]
+
+
+# Largest rounding error of binary16 for the pool's values in [0, 1]: half
+# the spacing 2^-11 of [0.5, 1).
+F16_POOL_ERROR = 2.0 ** -12
+
+
+def f16_lods_for_bounds(bounds):
+    """The f16_lods mask of a mixed pool from per-LoD error bounds: LoD L
+    is stored in binary16 when bounds[L] admits binary16 rounding."""
+    return sum(1 << L for L, b in enumerate(bounds) if b >= F16_POOL_ERROR)
 
 
 class CameraDesc(C.Structure):
@@ -305,7 +317,7 @@ class Cache:
 
     def __init__(self, volume, brick, n_lods, pool_bricks, max_requests, rank_window=1000,
                  ranking=RANK_PRIORITY, preload_period=0, miss_log_capacity=0, evict_log_capacity=4096,
-                 keep_request_counts=False, pool_dtype="f32"):
+                 keep_request_counts=False, pool_dtype="f32", f16_lods=0, pool_bricks_f16=0):
         vols = list(volume) if isinstance(volume, (list, tuple)) else [volume]
         self.volumes = vols
         volume = vols[0]
@@ -318,14 +330,21 @@ class Cache:
         if pool_dtype not in ("f32", "f16"):
             raise ValueError(f"pool_dtype {pool_dtype!r}: 'f32' or 'f16'")
         d.pool_dtype = _dtype(pool_dtype)
-        self.pool_dtype = pool_dtype
+        d.f16_lods, d.pool_bricks_f16 = int(f16_lods), int(pool_bricks_f16)
+        self.pool_dtype = pool_dtype if not f16_lods else "mixed"
+        # binary32 slots [0, split), then binary16 slots [split, pool_bricks)
+        self.split = pool_bricks - pool_bricks_f16 if f16_lods else pool_bricks
         self.desc = d
         ws = C.c_size_t()
         hs = (C.c_void_p * len(vols))(*[v.h.value for v in vols])
         _check(lib().cinr_cache_workspace_size_multi(hs, len(vols), C.byref(d), C.byref(ws)))
         dev = volume.device
-        tdt = torch.float16 if pool_dtype == "f16" else torch.float32
-        self.pool = torch.empty(max(pool_bricks, 1) * brick ** 3, dtype=tdt, device=dev)
+        if f16_lods:
+            nbytes = (self.split * 4 + (pool_bricks - self.split) * 2) * brick ** 3
+            self.pool = torch.empty((nbytes + 3) // 4, dtype=torch.float32, device=dev)
+        else:
+            tdt = torch.float16 if pool_dtype == "f16" else torch.float32
+            self.pool = torch.empty(max(pool_bricks, 1) * brick ** 3, dtype=tdt, device=dev)
         self.workspace = torch.empty(ws.value, dtype=torch.uint8, device=dev)
         h = C.c_void_p()
         _check(lib().cinr_create_cache_multi(hs, len(vols), C.byref(d), _ptr(self.pool),
@@ -368,6 +387,12 @@ class Cache:
             return buf.view(np.int32).reshape(-1, 4)
         if kind == DUMP_POOL:
             B = self.desc.brick
+            if self.pool_dtype == "mixed":
+                # both classes as float32 (binary16 values widen exactly)
+                n32 = self.split * B ** 3 * 4
+                with np.errstate(invalid="ignore"):  # free slots hold arbitrary bits
+                    hi = buf[n32:].view(np.float16).astype(np.float32)
+                return np.concatenate([buf[:n32].view(np.float32), hi]).reshape(-1, B, B, B)
             return buf.view(np.float16 if self.pool_dtype == "f16" else np.float32).reshape(-1, B, B, B)
         return buf
 

@@ -190,13 +190,19 @@ struct cinr_cache_s {
     }
     TopkPlan plan_sel, plan_vic;
     int32_t lim;          // request list length bound: min(max_requests, pool)
-    int64_t used_bound;   // host upper bound on occupied slots (no LRU pass needed below the pool size)
+    int64_t used_bound[2];  // host upper bounds on occupied slots per class (no LRU pass needed below a class's size)
     int index_of(cinr_volume v) const {
         for (size_t i = 0; i < vols.size(); ++i)
             if (vols[i] == v) return (int)i;
         return -1;
     }
 };
+
+// At most n more occupied slots in each class.
+static void note_fill(cinr_cache c, int64_t n) {
+    c->used_bound[0] = std::min<int64_t>(c->used_bound[0] + n, c->c.split);
+    c->used_bound[1] = std::min<int64_t>(c->used_bound[1] + n, c->c.pool_bricks - c->c.split);
+}
 
 // ---------------------------------------------------------------------------
 // Volume
@@ -375,7 +381,8 @@ extern "C" cinr_status cinr_decode_bricks(cinr_volume v, const int32_t* d_reqs, 
     if (st) return st;
     CacheGeom g;
     geometry(v->desc.dims, brick, kMaxLods, g);
-    HIP_TRY(inr_decode_bricks(v->m, g, d_reqs, nullptr, nullptr, n, nullptr, d_out, 0, prec, (hipStream_t)stream));
+    const BrickOut out{d_out, nullptr, 0x7FFFFFFF};
+    HIP_TRY(inr_decode_bricks(v->m, g, d_reqs, nullptr, nullptr, n, nullptr, out, prec, (hipStream_t)stream));
     return CINR_OK;
 }
 
@@ -413,6 +420,17 @@ static cinr_status check_cache_desc(const cinr_volume* vols, int32_t n_vols, con
     if (d->miss_log_capacity < 0 || d->evict_log_capacity < 0) return fail(CINR_INVALID_ARG, "negative log capacity");
     if (d->pool_dtype != CINR_F32 && d->pool_dtype != CINR_F16)
         return fail(CINR_INVALID_ARG, "pool_dtype = %d (CINR_F32 or CINR_F16)", d->pool_dtype);
+    if (d->f16_lods != 0u) {
+        const uint32_t all = d->n_lods >= 32 ? 0xFFFFFFFFu : (1u << d->n_lods) - 1u;
+        if (d->pool_dtype != CINR_F32)
+            return fail(CINR_INVALID_ARG, "f16_lods: the classes of a mixed pool need pool_dtype = CINR_F32");
+        if ((d->f16_lods & ~all) || d->f16_lods == all)
+            return fail(CINR_INVALID_ARG, "f16_lods = 0x%x: a proper subset of the %d LoDs", d->f16_lods, d->n_lods);
+        const int32_t p16 = d->pool_bricks_f16, p32 = d->pool_bricks - d->pool_bricks_f16;
+        if (p16 < 1 || p32 < 1 || d->max_requests > p16 || d->max_requests > p32)
+            return fail(CINR_INVALID_ARG, "pool_bricks_f16 = %d of %d: each class needs max_requests (%d) slots or more",
+                        p16, d->pool_bricks, d->max_requests);
+    }
     if (!geometry(vols[0]->desc.dims, d->brick, d->n_lods, g)) return fail(CINR_INVALID_ARG, "invalid geometry");
     g.n_vols = n_vols;
     g.n_keys = g.keys_per_vol * n_vols;
@@ -449,6 +467,7 @@ static size_t cache_layout(const cinr_cache_desc* d, const CacheGeom& g, CacheDe
     x.topk[1] = cv.take<uint64_t>(buf);
     x.sel = cv.take<uint64_t>(lim);
     x.vic = cv.take<uint64_t>(lim);
+    x.vic1 = cv.take<uint64_t>(lim);
     x.misslog = cv.take<MissLogRec>(d->miss_log_capacity);
     x.misslog_cap = d->miss_log_capacity;
     x.evlog = cv.take<int32_t>((size_t)d->evict_log_capacity * 4);
@@ -492,9 +511,11 @@ extern "C" cinr_status cinr_create_cache_multi(const cinr_volume* vols, int32_t 
     cinr_status st = check_cache_desc(vols, n_vols, d, g);
     if (st) return st;
     const size_t B3 = (size_t)d->brick * d->brick * d->brick;
-    const size_t elem = d->pool_dtype == CINR_F16 ? 2 : 4;
-    if (pool_bytes < (size_t)d->pool_bricks * B3 * elem)
-        return fail(CINR_OUT_OF_MEMORY, "pool of %zu bytes < %zu needed", pool_bytes, (size_t)d->pool_bricks * B3 * elem);
+    const int32_t split = d->f16_lods ? d->pool_bricks - d->pool_bricks_f16 : d->pool_bricks;
+    const size_t bytes32 = d->pool_dtype == CINR_F16 ? 0 : (size_t)split * B3 * 4;
+    const size_t pool_need = d->pool_dtype == CINR_F16 ? (size_t)d->pool_bricks * B3 * 2
+                                                       : bytes32 + (size_t)(d->pool_bricks - split) * B3 * 2;
+    if (pool_bytes < pool_need) return fail(CINR_OUT_OF_MEMORY, "pool of %zu bytes < %zu needed", pool_bytes, pool_need);
     if (d->pool_bricks > 0 && !d_pool) return fail(CINR_INVALID_ARG, "null pool");
     InrDev* unused = nullptr;
     const size_t need = cache_layout(d, g, nullptr, nullptr, nullptr, nullptr, &unused);
@@ -505,9 +526,12 @@ extern "C" cinr_status cinr_create_cache_multi(const cinr_volume* vols, int32_t 
     c->g = g;
     cache_layout(d, g, &c->c, &c->plan_sel, &c->plan_vic, d_ws, &c->d_vols);
     c->c.pool = d_pool;
-    c->c.pool_f16 = d->pool_dtype == CINR_F16 ? 1 : 0;
+    c->c.pool_kind = d->f16_lods ? POOL_MIXED : (d->pool_dtype == CINR_F16 ? POOL_F16 : POOL_F32);
+    c->c.split = split;
+    c->c.f16_lods = d->f16_lods;
+    c->c.pool16 = d->f16_lods ? (void*)((char*)d_pool + bytes32) : nullptr;
     c->lim = std::max(1, std::min(d->max_requests, d->pool_bricks));
-    c->used_bound = 0;
+    c->used_bound[0] = c->used_bound[1] = 0;
     hipStream_t s = (hipStream_t)stream;
     std::vector<InrDev> host(n_vols);
     for (int i = 0; i < n_vols; ++i) host[i] = vols[i]->m;
@@ -531,11 +555,16 @@ extern "C" cinr_status cinr_create_cache(cinr_volume v, const cinr_cache_desc* d
 // none unless *gate != 0 when a gate is given).
 static hipError_t decode_selected(cinr_cache c, int32_t n_cap, int32_t prec, const uint32_t* gate, hipStream_t s) {
     const CacheDev& cd = c->c;
+    BrickOut out{cd.pool, cd.pool16, cd.split};
+    if (cd.pool_kind == POOL_F16) {
+        out.out16 = cd.pool;
+        out.split = 0;
+    }
     if (c->vols.size() == 1)
-        return inr_decode_bricks(c->vols[0]->m, c->g, cd.ins_reqs, &cd.ctr->n_sel, gate, n_cap, cd.ins_slots, cd.pool,
-                                 cd.pool_f16, prec, s);
+        return inr_decode_bricks(c->vols[0]->m, c->g, cd.ins_reqs, &cd.ctr->n_sel, gate, n_cap, cd.ins_slots, out,
+                                 prec, s);
     return inr_decode_bricks_multi(c->d_vols, c->vols[0]->m, c->g, cd.ins_reqs, cd.ins_vols, &cd.ctr->n_sel, gate,
-                                   n_cap, cd.ins_slots, cd.pool, cd.pool_f16, prec, s);
+                                   n_cap, cd.ins_slots, out, prec, s);
 }
 
 extern "C" void cinr_destroy_cache(cinr_cache c) { delete c; }
@@ -548,8 +577,8 @@ extern "C" cinr_status cinr_cache_prefill(cinr_cache c, const int32_t* d_keys, i
     if (st) return st;
     if (n == 0) return CINR_OK;
     hipStream_t s = (hipStream_t)stream;
-    c->used_bound = std::min<int64_t>(c->used_bound + n, c->c.pool_bricks);
-    HIP_TRY(launch_prefill_setup(c->c, d_keys, n, stamp, s));
+    note_fill(c, n);
+    HIP_TRY(launch_prefill_setup(c->c, c->g, d_keys, n, stamp, s));
     HIP_TRY(launch_insert(c->c, c->g, n, nullptr, s));
     HIP_TRY(decode_selected(c, n, prec, nullptr, s));
     return CINR_OK;
@@ -846,7 +875,9 @@ cinr_status prepare_view(cinr_cache c, cinr_volume v, const cinr_camera* cam, co
         f.touched = c->c.touched;
         f.n_touched = &c->c.ctr->n_touched;
         f.pool = c->c.pool;
-        f.pool_f16 = c->c.pool_f16;
+        f.pool16 = c->c.pool16;
+        f.pool_kind = c->c.pool_kind;
+        f.split = c->c.split;
         f.pool_bricks = c->c.pool_bricks;
         f.misslog = c->c.misslog;
         f.n_misslog = &c->c.ctr->n_misslog;
@@ -1037,10 +1068,11 @@ cinr_status continue_views(cinr_cache c, std::vector<ViewRun>& runs, bool side, 
 // Whether the next cache-manager pass may need LRU victims (host bound on the
 // occupied slots).
 bool lru_pass_needed(cinr_cache c) {
-    return c->c.pool_bricks > 0 && c->used_bound + c->lim > c->c.pool_bricks;
+    const int64_t p0 = c->c.split, p1 = c->c.pool_bricks - c->c.split;
+    return (p0 > 0 && c->used_bound[0] + c->lim > p0) || (p1 > 0 && c->used_bound[1] + c->lim > p1);
 }
 
-void note_insertions(cinr_cache c) { c->used_bound = std::min<int64_t>(c->used_bound + c->lim, c->c.pool_bricks); }
+void note_insertions(cinr_cache c) { note_fill(c, c->lim); }
 
 cinr_status cache_end_frame(cinr_cache c, int32_t prec, bool lru_pass, Timing& tm, const uint32_t* gate, hipStream_t s);
 
@@ -1158,13 +1190,21 @@ cinr_status cache_end_frame(cinr_cache c, int32_t prec, bool lru_pass, Timing& t
         if (lru_pass) {
             TopkArgs tv{};
             tv.count_dev = &cd.ctr->n_used;
-            tv.cap0 = (uint64_t)cd.pool_bricks;
+            tv.cap0 = (uint64_t)cd.split;
             tv.k = c->lim;
             tv.gate = &cd.ctr->need_evict;
             tv.mode = TOPK_LRU;
             tv.frame_gate = gate;
             tv.lru_last_used = cd.last_used;
             HIP_TRY(launch_topk(tv, c->plan_vic, cd.topk[0], cd.topk[1], cd.vic, nullptr, nullptr, s));
+            if (cd.pool_kind == POOL_MIXED) {
+                // the binary16 class's own LRU order
+                tv.count_dev = &cd.ctr->n_used1;
+                tv.cap0 = (uint64_t)(cd.pool_bricks - cd.split);
+                tv.gate = &cd.ctr->need_evict1;
+                tv.lru_base = cd.split;
+                HIP_TRY(launch_topk(tv, c->plan_vic, cd.topk[0], cd.topk[1], cd.vic1, nullptr, nullptr, s));
+            }
             HIP_TRY(launch_insert(cd, c->g, c->lim, gate, s));
         }
     }
@@ -1459,7 +1499,11 @@ extern "C" cinr_status cinr_cache_dump(cinr_cache c, int32_t kind, void* dst, si
             n = m * 16;
             break;
         }
-        case CINR_DUMP_POOL: src = cd.pool; n = P * B3 * (cd.pool_f16 ? 2 : 4); break;
+        case CINR_DUMP_POOL:
+            // binary32 slots [0, split), then binary16 slots [split, P)
+            src = cd.pool;
+            n = cd.pool_kind == POOL_F16 ? P * B3 * 2 : (size_t)cd.split * B3 * 4 + (P - (size_t)cd.split) * B3 * 2;
+            break;
         default: return fail(CINR_INVALID_ARG, "dump kind %d", kind);
     }
     *needed = n;

@@ -77,6 +77,38 @@ __device__ void sort_desc(uint64_t* s, uint32_t m) {
     }
 }
 
+// LoD of a key of any of the cache's volumes.
+__device__ inline int32_t key_lod(const CacheGeom& g, int64_t key) {
+    const int64_t k = key % g.keys_per_vol;
+    int32_t L = 0;
+    while (L + 1 < g.n_lods && k >= g.lod[L + 1].off) ++L;
+    return L;
+}
+
+// Slot class of a key: 1 for the binary16 class of a mixed pool, else 0.
+__device__ inline uint32_t key_class(const CacheDev& c, const CacheGeom& g, int32_t key) {
+    if (c.pool_kind != POOL_MIXED || key < 0 || (int64_t)key >= g.n_keys) return 0u;
+    return (c.f16_lods >> key_lod(g, key)) & 1u;
+}
+
+// Exclusive count of `pred` over the lower threads of a 256-thread
+// workgroup (4 wavefronts of 64), and the workgroup's total; every thread
+// calls it.  wc: 4 words of LDS.
+__device__ inline uint32_t block_prefix(bool pred, uint32_t* total, uint32_t* wc) {
+    const unsigned long long m = __ballot(pred);
+    const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+    if (lane == 0u) wc[w] = (uint32_t)__popcll(m);
+    __syncthreads();
+    uint32_t before = (uint32_t)__popcll(m & ((1ull << lane) - 1ull)), tot = 0u;
+    for (uint32_t k = 0; k < 4u; ++k) {
+        if (k < w) before += wc[k];
+        tot += wc[k];
+    }
+    __syncthreads();  // wc is reused by the next call
+    *total = tot;
+    return before;
+}
+
 __device__ inline uint32_t pow2_at_least(uint32_t n) {
     uint32_t m = 1;
     while (m < n) m <<= 1;
@@ -84,19 +116,24 @@ __device__ inline uint32_t pow2_at_least(uint32_t n) {
 }
 
 // Insertion of the selected bricks [t0, n_sel) step `stride` (Section 4.3.1):
-// the lowest free slots first, then the LRU victims; evicted bricks are
-// unmapped and their ranks forgotten, new bricks are mapped, stamped and
-// queued for decoding.  `ctr` is the counters' state after the selection.
+// the lowest free slots first, then the LRU victims, within the slot class
+// of each brick; evicted bricks are unmapped and their ranks forgotten, new
+// bricks are mapped, stamped and queued for decoding.  `ctr` is the
+// counters' state after the selection; ins_slots holds each entry's rank
+// among the entries of its class (overwritten with the slot).
 __device__ void insert_entries(const CacheDev& c, const CacheGeom& g, const CacheCtr& ctr, uint32_t t0,
                                uint32_t stride) {
     const int32_t stamp = ctr.frame + 1;
     for (uint32_t t = t0; t < ctr.n_sel; t += stride) {
         const int32_t key = c.ins_keys[t];
+        const uint32_t cl = key_class(c, g, key);
+        const uint32_t r = (uint32_t)c.ins_slots[t];
+        const uint32_t n_free = cl ? ctr.n_free1 : ctr.n_free;
         int32_t slot;
-        if (t < ctr.n_free)
-            slot = (int32_t)(ctr.n_used + t);
+        if (r < n_free)
+            slot = (int32_t)((cl ? (uint32_t)c.split + ctr.n_used1 : ctr.n_used) + r);
         else
-            slot = (int32_t)(uint32_t)(~c.vic[t - ctr.n_free] & 0xFFFFFFFFull);
+            slot = (int32_t)(uint32_t)(~(cl ? c.vic1 : c.vic)[r - n_free] & 0xFFFFFFFFull);
         bool ok = key >= 0 && (int64_t)key < g.n_keys && slot >= 0 && slot < c.pool_bricks;
         int32_t old = -1;
         if (ok) {
@@ -136,8 +173,9 @@ __device__ void insert_entries(const CacheDev& c, const CacheGeom& g, const Cach
 
 // Occupancy and eviction-log counters after an insertion (one thread).
 __device__ inline void insert_counters(CacheCtr* out, const CacheCtr& ctr) {
-    const uint32_t filled = ctr.n_sel < ctr.n_free ? ctr.n_sel : ctr.n_free;
-    out->n_used = ctr.n_used + filled;
+    const uint32_t n0 = ctr.n_sel - ctr.n_sel1;
+    out->n_used = ctr.n_used + (n0 < ctr.n_free ? n0 : ctr.n_free);
+    out->n_used1 = ctr.n_used1 + (ctr.n_sel1 < ctr.n_free1 ? ctr.n_sel1 : ctr.n_free1);
     out->n_evlog = ctr.n_evlog + ctr.n_sel;
 }
 
@@ -172,7 +210,7 @@ __device__ void views_frame_stats(const CacheDev& c, uint32_t n_touched, uint32_
 // the last of its workgroups to finish, by pass 1 (two-pass selections).
 __global__ __launch_bounds__(256) void k_topk(TopkArgs a) {
     __shared__ uint64_t s[kTopkChunk];
-    __shared__ uint32_t nsel, ticket;
+    __shared__ uint32_t nsel, ticket, wc[4];
     if (a.gate && *a.gate == 0u) return;
     if (a.frame_gate && *a.frame_gate == 0u) return;
     uint64_t c = a.cap0;
@@ -189,8 +227,10 @@ __global__ __launch_bounds__(256) void k_topk(TopkArgs a) {
             const uint64_t idx = base + e;
             uint64_t v = 0ull;
             if (e < have) {
-                if (a.pass == 0 && a.mode == TOPK_LRU)
-                    v = ~(((uint64_t)(uint32_t)a.lru_last_used[idx] << 32) | idx);
+                if (a.pass == 0 && a.mode == TOPK_LRU) {
+                    const uint64_t slot = idx + (uint64_t)a.lru_base;
+                    v = ~(((uint64_t)(uint32_t)a.lru_last_used[slot] << 32) | slot);
+                }
                 else if (a.pass == 0 && a.mode == TOPK_RANK)
                     v = rank_score(a.ra, frame, idx);
                 else
@@ -235,41 +275,83 @@ __global__ __launch_bounds__(256) void k_topk(TopkArgs a) {
             }
         }
         __syncthreads();
+        // each entry's rank within its slot class (the selection is at most
+        // 256 bricks: one entry per thread)
+        const CacheDev& cd = a.tail.c;
+        const uint32_t t = threadIdx.x;
+        const uint32_t cl = t < nsel ? key_class(cd, a.tail.g, a.sel.ins_keys[t]) : 0u;
+        uint32_t n1;
+        const uint32_t r1 = block_prefix(cl != 0u, &n1, wc);
+        if (t < nsel) cd.ins_slots[t] = (int32_t)(cl ? r1 : t - r1);
         CacheCtr* ctr = a.sel.ctr;
-        const uint32_t n_free = (uint32_t)a.sel.pool_bricks - ctr->n_used;
-        const uint32_t need_evict = nsel > n_free ? nsel - n_free : 0u;
+        const uint32_t n_free = (uint32_t)cd.split - ctr->n_used;
+        const uint32_t n_free1 = (uint32_t)(cd.pool_bricks - cd.split) - ctr->n_used1;
+        const uint32_t need_evict = nsel - n1 > n_free ? nsel - n1 - n_free : 0u;
+        const uint32_t need_evict1 = n1 > n_free1 ? n1 - n_free1 : 0u;
+        CacheCtr snap = *ctr;
+        snap.n_sel = nsel;
+        snap.n_free = n_free;
+        snap.need_evict = need_evict;
+        snap.n_sel1 = n1;
+        snap.n_free1 = n_free1;
+        snap.need_evict1 = need_evict1;
+        __syncthreads();
         if (threadIdx.x == 0) {
             ctr->n_sel = nsel;
             ctr->n_free = n_free;
             ctr->need_evict = need_evict;
+            ctr->n_sel1 = n1;
+            ctr->n_free1 = n_free1;
+            ctr->need_evict1 = need_evict1;
         }
         if (a.tail.insert) {
-            // the selection is at most 256 bricks: one entry per thread
-            CacheCtr snap = *ctr;
-            snap.n_sel = nsel;
-            snap.n_free = n_free;
-            snap.need_evict = need_evict;
-            __syncthreads();
-            insert_entries(a.tail.c, a.tail.g, snap, threadIdx.x, 256u);
+            insert_entries(cd, a.tail.g, snap, threadIdx.x, 256u);
             __syncthreads();
             if (threadIdx.x == 0) insert_counters(ctr, snap);
         }
-        if (a.tail.stats && threadIdx.x == 0) views_frame_stats(a.tail.c, (uint32_t)n_touched, nsel, need_evict);
+        if (a.tail.stats && threadIdx.x == 0)
+            views_frame_stats(cd, (uint32_t)n_touched, nsel, need_evict + need_evict1);
     }
 }
 
-// Prefill: the given keys are inserted into free slots only.
-__global__ void k_prefill_setup(CacheDev c, const int32_t* keys, int32_t n, int32_t stamp) {
-    for (int32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) c.ins_keys[t] = keys[t];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        CacheCtr* ctr = c.ctr;
-        const uint32_t n_free = (uint32_t)c.pool_bricks - ctr->n_used;
-        const uint32_t nn = (uint32_t)n <= n_free ? (uint32_t)n : n_free;
-        if ((uint32_t)n > n_free) ctr->error |= 1u;
+// Prefill (one workgroup): the given keys are inserted into free slots of
+// their class only; the keys that find one are listed in order, with their
+// rank in the class, and the others dropped (error bit 1).
+__global__ __launch_bounds__(256) void k_prefill_setup(CacheDev c, CacheGeom g, const int32_t* keys, int32_t n,
+                                                       int32_t stamp) {
+    __shared__ uint32_t wc[4];
+    CacheCtr* ctr = c.ctr;
+    const uint32_t n_free = (uint32_t)c.split - ctr->n_used;
+    const uint32_t n_free1 = (uint32_t)(c.pool_bricks - c.split) - ctr->n_used1;
+    uint32_t seen1 = 0u, kept = 0u, kept1 = 0u;
+    for (int32_t base = 0; base < n; base += 256) {
+        const int32_t t = base + (int32_t)threadIdx.x;
+        const bool in = t < n;
+        const int32_t key = in ? keys[t] : -1;
+        const uint32_t cl = in ? key_class(c, g, key) : 0u;
+        uint32_t tot1, tot_kept, tot_kept1;
+        const uint32_t r1 = seen1 + block_prefix(in && cl != 0u, &tot1, wc);
+        const uint32_t r = cl ? r1 : (uint32_t)t - r1;
+        const bool fit = in && r < (cl ? n_free1 : n_free);
+        const uint32_t pos = kept + block_prefix(fit, &tot_kept, wc);
+        block_prefix(fit && cl != 0u, &tot_kept1, wc);
+        if (fit) {
+            c.ins_keys[pos] = key;
+            c.ins_slots[pos] = (int32_t)r;
+        }
+        seen1 += tot1;
+        kept += tot_kept;
+        kept1 += tot_kept1;
+    }
+    if (threadIdx.x == 0) {
+        if (kept < (uint32_t)n) ctr->error |= 1u;
         ctr->frame = stamp - 1;  // k_insert stamps frame + 1
-        ctr->n_sel = nn;
+        ctr->n_sel = kept;
         ctr->n_free = n_free;
         ctr->need_evict = 0u;
+        ctr->n_sel1 = kept1;
+        ctr->n_free1 = n_free1;
+        ctr->need_evict1 = 0u;
     }
 }
 
@@ -336,10 +418,9 @@ hipError_t launch_topk(const TopkArgs& base, const TopkPlan& plan, uint64_t* buf
     return hipGetLastError();
 }
 
-hipError_t launch_prefill_setup(const CacheDev& c, const int32_t* keys, int32_t n, int32_t stamp, hipStream_t s) {
-    int b = (n + 255) / 256;
-    b = b < 1 ? 1 : (b > 1024 ? 1024 : b);
-    hipLaunchKernelGGL(k_prefill_setup, dim3(b), dim3(256), 0, s, c, keys, n, stamp);
+hipError_t launch_prefill_setup(const CacheDev& c, const CacheGeom& g, const int32_t* keys, int32_t n, int32_t stamp,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(k_prefill_setup, dim3(1), dim3(256), 0, s, c, g, keys, n, stamp);
     return hipGetLastError();
 }
 

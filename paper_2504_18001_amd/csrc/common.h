@@ -70,6 +70,15 @@ struct LodGeom {
 
 // Keys of a cache shared by n_vols volumes of the same dimensions: volume v
 // owns keys [v * keys_per_vol, (v + 1) * keys_per_vol), numbered LoD by LoD.
+// Where decoded bricks go: brick r to slot slots[r] (or r), slots below
+// `split` as binary32 at out + slot * B^3, the others as binary16 (rounded
+// to nearest even) at out16 + (slot - split) * B^3.
+struct BrickOut {
+    void* out;
+    void* out16;
+    int32_t split;
+};
+
 struct CacheGeom {
     int32_t brick;
     FastDiv div_b1;  // division by brick - 1

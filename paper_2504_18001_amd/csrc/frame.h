@@ -36,7 +36,15 @@ struct CacheCtr {
     int32_t frame;        // frame whose requests are ranked; insertions are stamped frame + 1
     uint32_t select_done; // workgroups of the fused selection launch that have finished
     uint32_t n_views;     // views of the current frame (their statistics targets are in CacheDev::views)
+    // the binary16 class of a mixed pool (slots [split, pool_bricks)); the
+    // fields above then count the binary32 class, except n_sel (all bricks)
+    uint32_t n_sel1, n_free1, need_evict1, n_used1;
 };
+
+// Storage of the pool's brick values: one binary32 or one binary16 class of
+// slots, or LoD-dependent mixed precision: binary32 slots [0, split) and
+// binary16 slots [split, pool_bricks), each LoD stored in one class.
+enum : int32_t { POOL_F32 = 0, POOL_F16 = 1, POOL_MIXED = 2 };
 
 // Where a view's frame statistics go: written into the cache's table by the
 // view's k_frame_begin, read at the end of the frame's selection.
@@ -61,7 +69,8 @@ struct CacheDev {
     uint64_t* cand;
     int32_t* owner;
     int32_t* last_used;
-    void* pool;           // f32 or f16 values (pool_f16)
+    void* pool;           // binary32 slots [0, split), or every slot of a binary16 pool
+    void* pool16;         // mixed pool: binary16 slot s at (s - split) * B^3
     int32_t* ins_keys;    // [ins_cap]
     int32_t* ins_slots;   // [ins_cap]
     int32_t* ins_reqs;    // [ins_cap][4]
@@ -76,7 +85,10 @@ struct CacheDev {
     CacheCtr* ctr;
     ViewEnd* views;       // [kMaxFrameViews]
     int32_t pool_bricks, max_requests, rank_window, ranking, ins_cap;
-    int32_t pool_f16;
+    int32_t pool_kind;    // POOL_F32, POOL_F16 or POOL_MIXED
+    int32_t split;        // first slot of the binary16 class (pool_bricks unless mixed)
+    uint32_t f16_lods;    // mixed: bit L set stores LoD L in the binary16 class
+    uint64_t* vic1;       // victim list of the binary16 class (sorted scores)
 };
 
 // Values of a view that change from one frame to the next while its launch
@@ -173,7 +185,9 @@ struct FrameDev {
     int32_t* touched;
     uint32_t* n_touched;
     const void* pool;
-    int32_t pool_f16;  // binary16 brick values
+    const void* pool16;  // binary16 class of a mixed pool
+    int32_t pool_kind;   // POOL_F32, POOL_F16 or POOL_MIXED
+    int32_t split;       // first binary16 slot of a mixed pool
     int32_t pool_bricks;
     MissLogRec* misslog;
     uint32_t* n_misslog;
@@ -253,6 +267,7 @@ struct TopkArgs {
     const uint32_t* frame_gate; // nullable: skip when *frame_gate == 0 (frame end queued ahead)
     int32_t mode;               // TopkMode of pass 0
     const int32_t* lru_last_used;
+    int32_t lru_base;           // TOPK_LRU: slots [lru_base, lru_base + count)
     RankArgs ra;
     SelectArgs sel;
     // fused launch of a two-pass selection: the workgroups of pass 0, then
@@ -289,7 +304,8 @@ hipError_t launch_cache_init(const CacheDev& c, int64_t n_keys, hipStream_t s);
 // launch of a two-pass plan (pass 0, then pass 1 in its last workgroup).
 hipError_t launch_topk(const TopkArgs& base, const TopkPlan& plan, uint64_t* buf0, uint64_t* buf1, uint64_t* final_out,
                        const SelectArgs* epilogue, uint32_t* fuse_done, hipStream_t s);
-hipError_t launch_prefill_setup(const CacheDev& c, const int32_t* keys, int32_t n, int32_t stamp, hipStream_t s);
+hipError_t launch_prefill_setup(const CacheDev& c, const CacheGeom& g, const int32_t* keys, int32_t n, int32_t stamp,
+                                hipStream_t s);
 hipError_t launch_insert(const CacheDev& c, const CacheGeom& g, int32_t cap, const uint32_t* gate, hipStream_t s);
 hipError_t launch_clear_last_req(const CacheDev& c, int64_t n_keys, hipStream_t s);
 
@@ -298,7 +314,7 @@ bool inr_shape_supported(const InrDev& m);
 hipError_t inr_infer_points(const InrDev& m, const float* pos, int64_t n, float* out, int prec, hipStream_t s);
 // gate: nullable, as for the frame-end launches (no brick is decoded unless *gate != 0)
 hipError_t inr_decode_bricks(const InrDev& m, const CacheGeom& g, const int32_t* reqs, const uint32_t* n_dev,
-                             const uint32_t* gate, int32_t n_cap, const int32_t* slots, void* out, int out_f16,
+                             const uint32_t* gate, int32_t n_cap, const int32_t* slots, const BrickOut& out,
                              int prec, hipStream_t s);
 hipError_t inr_macrocells(const InrDev& m, int32_t N, float* minmax, int prec, hipStream_t s);
 hipError_t inr_infer_misses(const InrDev& m, const float4* rec, const uint32_t* n_dev, int64_t cap, float* vals,
@@ -307,7 +323,7 @@ hipError_t inr_infer_misses(const InrDev& m, const float4* rec, const uint32_t* 
 // descriptors, `shape` any of them on the host)
 hipError_t inr_decode_bricks_multi(const InrDev* d_vols, const InrDev& shape, const CacheGeom& g, const int32_t* reqs,
                                    const int32_t* vols, const uint32_t* n_dev, const uint32_t* gate, int32_t n_cap,
-                                   const int32_t* slots, void* out, int out_f16, int prec, hipStream_t s);
+                                   const int32_t* slots, const BrickOut& out, int prec, hipStream_t s);
 
 // train.hip launchers
 bool train_shape_supported(const InrDev& m);

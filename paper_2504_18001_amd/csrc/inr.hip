@@ -81,17 +81,18 @@ struct BrickSrc {
 };
 
 struct BrickDst {
-    void* out;             // f32, or f16 values rounded to nearest even (f16)
+    void* out;             // binary32 slots [0, split)
+    void* out16;           // binary16 slots [split, ...), rounded to nearest even
     const int32_t* slots;  // nullable: brick r goes to slot slots[r] (skipped if negative), else to r
     int32_t B3;
-    int32_t f16;
+    int32_t split;
     __device__ void store(int64_t idx, float v) const {
         const int32_t r = (int32_t)(idx / B3);
         const int32_t i = (int32_t)(idx - (int64_t)r * B3);
         const int64_t s = slots ? (int64_t)slots[r] : (int64_t)r;
         if (s < 0) return;
-        if (f16)
-            static_cast<__half*>(out)[s * B3 + i] = __float2half_rn(v);
+        if (s >= split)
+            static_cast<__half*>(out16)[(s - split) * B3 + i] = __float2half_rn(v);
         else
             static_cast<float*>(out)[s * B3 + i] = v;
     }
@@ -349,7 +350,7 @@ hipError_t inr_infer_points(const InrDev& m, const float* pos, int64_t n, float*
 }
 
 hipError_t inr_decode_bricks(const InrDev& m, const CacheGeom& g, const int32_t* reqs, const uint32_t* n_dev,
-                             const uint32_t* gate, int32_t n_cap, const int32_t* slots, void* out, int out_f16,
+                             const uint32_t* gate, int32_t n_cap, const int32_t* slots, const BrickOut& out,
                              int prec, hipStream_t s) {
     if (n_cap <= 0) return hipSuccess;
     BrickSrc src;
@@ -363,14 +364,14 @@ hipError_t inr_decode_bricks(const InrDev& m, const CacheGeom& g, const int32_t*
     for (int L = 0; L < kMaxLods; ++L)
         for (int a = 0; a < 3; ++a) src.nb[L][a] = L < g.n_lods ? g.lod[L].nb[a] : 0;
     for (int a = 0; a < 3; ++a) src.dims[a] = m.dims[a];
-    BrickDst dst{out, slots, src.B3, out_f16};
+    BrickDst dst{out.out, out.out16, slots, src.B3, out.split};
     const void* a[2] = {&src, &dst};
     return dispatch(prec, 1, m, a, s);
 }
 
 hipError_t inr_decode_bricks_multi(const InrDev* d_vols, const InrDev& shape, const CacheGeom& g, const int32_t* reqs,
                                    const int32_t* vols, const uint32_t* n_dev, const uint32_t* gate, int32_t n_cap,
-                                   const int32_t* slots, void* out, int out_f16, int prec, hipStream_t s) {
+                                   const int32_t* slots, const BrickOut& out, int prec, hipStream_t s) {
     if (n_cap <= 0) return hipSuccess;
     BrickSrc src;
     src.reqs = reqs;
@@ -383,7 +384,7 @@ hipError_t inr_decode_bricks_multi(const InrDev* d_vols, const InrDev& shape, co
     for (int L = 0; L < kMaxLods; ++L)
         for (int a = 0; a < 3; ++a) src.nb[L][a] = L < g.n_lods ? g.lod[L].nb[a] : 0;
     for (int a = 0; a < 3; ++a) src.dims[a] = shape.dims[a];
-    BrickDst dst{out, slots, src.B3, out_f16};
+    BrickDst dst{out.out, out.out16, slots, src.B3, out.split};
     const void* a[4] = {&src, &dst, d_vols, vols};
     return dispatch(prec, 4, shape, a, s);
 }

@@ -95,11 +95,38 @@ __device__ inline FrameHot load_hot(const FrameVar* v) {
 // 4 GiB (compile-time brick offsets, 32-bit byte offsets into the pool) and
 // macro-cells of 16^3 voxels.  kAdapt: the cell's code (Flags reads codes)
 // gives the sample's step exponent; a transparent cell's samples are skipped.
-// kHalf: binary16 pool values, interpolated in FP32.
+// kPool: POOL_F32, POOL_F16 (binary16 values, interpolated in FP32), or
+// POOL_MIXED (binary32 slots below f.split, binary16 slots from it on).
 __device__ inline float pool_value(float x) { return x; }
 __device__ inline float pool_value(__half x) { return __half2float(x); }
 
-template <bool kFast, bool kAdapt, bool kHalf, class Flags>
+// The 8 pool values around a sample in a brick stored as T at `base`
+// (slot relative to base): c[x + 2y + 4z].
+template <bool kFast, class T>
+__device__ inline void brick_corners(const void* base, int32_t slot, const BrickAddr& a, int32_t B, float c[8]) {
+    constexpr int kB = kFast ? 16 : 0;
+    const T* br;
+    if (kFast) {
+        const uint32_t off = (((uint32_t)slot * (uint32_t)(kB * kB * kB) +
+                               ((uint32_t)a.lj[2] * kB + (uint32_t)a.lj[1]) * kB + (uint32_t)a.lj[0])) *
+                             (uint32_t)sizeof(T);
+        br = reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
+    } else {
+        br = static_cast<const T*>(base) + (int64_t)slot * (B * B * B) + ((int64_t)a.lj[2] * B + a.lj[1]) * B + a.lj[0];
+    }
+    const int32_t Bq = kFast ? kB : B;
+    const int32_t B2 = Bq * Bq;
+    c[0] = pool_value(br[0]);
+    c[1] = pool_value(br[1]);
+    c[2] = pool_value(br[Bq]);
+    c[3] = pool_value(br[Bq + 1]);
+    c[4] = pool_value(br[B2]);
+    c[5] = pool_value(br[B2 + 1]);
+    c[6] = pool_value(br[B2 + Bq]);
+    c[7] = pool_value(br[B2 + Bq + 1]);
+}
+
+template <bool kFast, bool kAdapt, int kPool, class Flags>
 __device__ inline SampleRes sample_cache(const FrameDev& f, const FrameHot& h, const LodGeom* lg, const Flags& fl,
                                          const float p[3], SlotCache& sc) {
     constexpr int kB = kFast ? 16 : 0;
@@ -151,22 +178,18 @@ __device__ inline SampleRes sample_cache(const FrameDev& f, const FrameHot& h, c
             return s;
         }
         if (slot < 0) continue;
-        using T = typename std::conditional<kHalf, __half, float>::type;
-        const T* br;
-        if (kFast) {
-            const uint32_t off = (((uint32_t)slot * (uint32_t)(kB * kB * kB) +
-                                   ((uint32_t)a.lj[2] * kB + (uint32_t)a.lj[1]) * kB + (uint32_t)a.lj[0])) *
-                                 (uint32_t)sizeof(T);
-            br = reinterpret_cast<const T*>(reinterpret_cast<const char*>(f.pool) + off);
+        float c[8];
+        if constexpr (kPool == POOL_MIXED) {
+            if (slot < f.split)
+                brick_corners<kFast, float>(f.pool, slot, a, B, c);
+            else
+                brick_corners<kFast, __half>(f.pool16, slot - f.split, a, B, c);
         } else {
-            br = static_cast<const T*>(f.pool) + (int64_t)slot * (B * B * B) + ((int64_t)a.lj[2] * B + a.lj[1]) * B +
-                 a.lj[0];
+            brick_corners<kFast, typename std::conditional<kPool == POOL_F16, __half, float>::type>(f.pool, slot, a, B,
+                                                                                                  c);
         }
-        const int32_t B2 = B * B;
-        const float c000 = pool_value(br[0]), c100 = pool_value(br[1]), c010 = pool_value(br[B]),
-                    c110 = pool_value(br[B + 1]);
-        const float c001 = pool_value(br[B2]), c101 = pool_value(br[B2 + 1]), c011 = pool_value(br[B2 + B]),
-                    c111 = pool_value(br[B2 + B + 1]);
+        const float c000 = c[0], c100 = c[1], c010 = c[2], c110 = c[3];
+        const float c001 = c[4], c101 = c[5], c011 = c[6], c111 = c[7];
         const float fx = a.frac[0], fy = a.frac[1], fz = a.frac[2];
         const float x00 = __builtin_fmaf(fx, c100 - c000, c000);
         const float x10 = __builtin_fmaf(fx, c110 - c010, c010);
@@ -470,9 +493,9 @@ struct UnitQueue {
 // wins everywhere (short rays favour 3, long ones 4), so the online tuner
 // tries both.
 // kAdapt: adaptive sampling rate (macro-cell codes instead of visibility
-// bits); a sample of step exponent e is followed by sample k + 2^e.  kHalf:
-// binary16 pool.
-template <int kPipe, bool kLdsFlags, bool kFast, bool kAdapt, bool kHalf, int kWaves>
+// bits); a sample of step exponent e is followed by sample k + 2^e.  kPool:
+// the pool's storage (binary32, binary16, or mixed per LoD).
+template <int kPipe, bool kLdsFlags, bool kFast, bool kAdapt, int kPool, int kWaves>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves, 8))) void k_march(FrameDev f, int32_t it, uint32_t n0) {
     static_assert(!kAdapt || kPipe == 1, "the adaptive sampler decides one sample ahead at most");
     const FrameHot hot = load_hot(f.var);  // before any store of this kernel
@@ -589,7 +612,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves, 
 #pragma unroll
                 for (int u = 0; u < kPipe; ++u) {
                     if (cnt == u && sample_pos(o, d, ts, te, f.step, k + u, f.vm1, p)) {
-                        grp[u] = sample_cache<kFast, kAdapt, kHalf>(f, hot, lgs, fl, p, sc);
+                        grp[u] = sample_cache<kFast, kAdapt, kPool>(f, hot, lgs, fl, p, sc);
                         ++cnt;
                     }
                 }
@@ -633,7 +656,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves, 
                 while (nc < S) {
                     float qp[3];
                     if (!sample_pos(o, d, ts, te, f.step, kg, f.vm1, qp)) break;
-                    const SampleRes sr = sample_cache<kFast, kAdapt, kHalf>(f, hot, lgs, fl, qp, sc);
+                    const SampleRes sr = sample_cache<kFast, kAdapt, kPool>(f, hot, lgs, fl, qp, sc);
                     tally.add(sr.status);
                     book.note(f, hot.frame, cold, sr);
                     if (sr.status == S_MISS)
@@ -841,7 +864,7 @@ __device__ inline float4 pt_pixel_value(const PtLane& s) {
 }
 
 // (3 waves per SIMD: 158 VGPRs without spills; 4 would spill)
-template <bool kLdsFlags, bool kFast, bool kHalf>
+template <bool kLdsFlags, bool kFast, int kPool>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_path(FrameDev f, int32_t it, uint32_t n0) {
     const FrameHot hot = load_hot(f.var);  // before any store of this kernel
     __shared__ float4 tfs[256];
@@ -958,7 +981,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                         ++s.gi;
                         skip = v < 0.0f;
                     } else {
-                        const SampleRes sr = sample_cache<kFast, false, kHalf>(f, hot, lgs, fl, p, sc);
+                        const SampleRes sr = sample_cache<kFast, false, kPool>(f, hot, lgs, fl, p, sc);
                         tally.add(sr.status);
                         book.note_scattered(f, hot.frame, cold, sr);
                         if (sr.status == S_MISS) {
@@ -1054,7 +1077,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                 tg = t2;
                 float p[3];
                 pt_pos(s.o, s.d, tg, f.vm1, p);
-                const SampleRes sr = sample_cache<kFast, false, kHalf>(f, hot, lgs, fl, p, sc);
+                const SampleRes sr = sample_cache<kFast, false, kPool>(f, hot, lgs, fl, p, sc);
                 tally.add(sr.status);
                 book.note_scattered(f, hot.frame, cold, sr);
                 if (sr.status == S_MISS)
@@ -1137,7 +1160,7 @@ hipError_t launch_frame_begin(const FrameDev& f, int32_t n_iter_ctr, const float
 
 // Workgroups of one k_march instantiation that are resident at once on the
 // current device (the grid of the persistent kernel), cached per device.
-template <int P, bool LDS, bool FAST, bool A, bool H, int W>
+template <int P, bool LDS, bool FAST, bool A, int H, int W>
 static hipError_t resident_blocks(int* out) {
     static int cache[64] = {0};
     int dev = 0;
@@ -1156,7 +1179,7 @@ static hipError_t resident_blocks(int* out) {
     return hipSuccess;
 }
 
-template <int P, bool LDS, bool FAST, bool A, bool H, int W>
+template <int P, bool LDS, bool FAST, bool A, int H, int W>
 static hipError_t launch_march_t(const FrameDev& f, int it, int64_t max_rays, uint32_t n0, hipStream_t s) {
     int cap = 0;
     hipError_t e = resident_blocks<P, LDS, FAST, A, H, W>(&cap);
@@ -1169,12 +1192,12 @@ static hipError_t launch_march_t(const FrameDev& f, int it, int64_t max_rays, ui
     return hipGetLastError();
 }
 
-template <int P, bool LDS, bool A, bool H, int W>
+template <int P, bool LDS, bool A, int H, int W>
 static hipError_t launch_march_l(const FrameDev& f, int it, int64_t max_rays, uint32_t n0, hipStream_t s) {
     // 16^3 bricks in a pool of less than 4 GiB (or the uncached mode, which
     // reads no pool) and 16^3 macro-cells (or none)
     const bool cells = A || f.flags;
-    const uint64_t brick_bytes = 4096ull * (H ? 2ull : 4ull);
+    const uint64_t brick_bytes = 4096ull * (H == POOL_F16 ? 2ull : 4ull);
     const bool fast = (f.mode != CINR_CACHED ||
                        (f.geo.brick == 16 && (uint64_t)f.pool_bricks * brick_bytes < (1ull << 32))) &&
                       (!cells || f.mc_N == 16);
@@ -1182,14 +1205,14 @@ static hipError_t launch_march_l(const FrameDev& f, int it, int64_t max_rays, ui
     return launch_march_t<P, LDS, false, A, H, W>(f, it, max_rays, n0, s);
 }
 
-template <int P, bool A, bool H, int W>
+template <int P, bool A, int H, int W>
 static hipError_t launch_march_p(const FrameDev& f, int it, int64_t max_rays, uint32_t n0, hipStream_t s) {
     const bool lds = A ? f.n_cells <= kMaxLdsCells : (f.flags && f.flag_words <= kMaxLdsFlagWords);
     if (lds) return launch_march_l<P, true, A, H, W>(f, it, max_rays, n0, s);
     return launch_march_l<P, false, A, H, W>(f, it, max_rays, n0, s);
 }
 
-template <bool H, int W>
+template <int H, int W>
 static hipError_t launch_march_w(const FrameDev& f, int it, int64_t n, uint32_t n0, hipStream_t s) {
     // the adaptive sampler decides its next sample after the current one
     if (f.adapt > 0) return launch_march_p<1, true, H, W>(f, it, n, n0, s);
@@ -1201,14 +1224,14 @@ static hipError_t launch_march_w(const FrameDev& f, int it, int64_t n, uint32_t 
     }
 }
 
-template <bool H>
+template <int H>
 static hipError_t launch_march_h(const FrameDev& f, int it, int64_t n, uint32_t n0, hipStream_t s) {
     if (f.waves == 4) return launch_march_w<H, 4>(f, it, n, n0, s);
     return launch_march_w<H, 3>(f, it, n, n0, s);
 }
 
 // The path tracer's persistent grid, as resident_blocks for k_march.
-template <bool LDS, bool FAST, bool H>
+template <bool LDS, bool FAST, int H>
 static hipError_t launch_path_t(const FrameDev& f, int it, int64_t max_px, uint32_t n0, hipStream_t s) {
     static int cache[64] = {0};
     int dev = 0;
@@ -1230,9 +1253,9 @@ static hipError_t launch_path_t(const FrameDev& f, int it, int64_t max_px, uint3
     return hipGetLastError();
 }
 
-template <bool H>
+template <int H>
 static hipError_t launch_path_h(const FrameDev& f, int it, int64_t n, uint32_t n0, hipStream_t s) {
-    const uint64_t brick_bytes = 4096ull * (H ? 2ull : 4ull);
+    const uint64_t brick_bytes = 4096ull * (H == POOL_F16 ? 2ull : 4ull);
     const bool fast = (f.mode != CINR_CACHED ||
                        (f.geo.brick == 16 && (uint64_t)f.pool_bricks * brick_bytes < (1ull << 32))) &&
                       (!f.flags || f.mc_N == 16);
@@ -1246,9 +1269,14 @@ hipError_t launch_march(const FrameDev& f, int it, int64_t max_rays, hipStream_t
     // `max_rays` re-queued rays
     const uint32_t n0 = (uint32_t)(((f.W + 7) / 8) * ((f.H + 7) / 8)) * 64u;
     const int64_t n = it == 0 ? (int64_t)n0 : max_rays;
-    if (f.path.on) return f.pool_f16 ? launch_path_h<true>(f, it, n, n0, s) : launch_path_h<false>(f, it, n, n0, s);
-    if (f.pool_f16) return launch_march_h<true>(f, it, n, n0, s);
-    return launch_march_h<false>(f, it, n, n0, s);
+    if (f.path.on) {
+        if (f.pool_kind == POOL_MIXED) return launch_path_h<POOL_MIXED>(f, it, n, n0, s);
+        if (f.pool_kind == POOL_F16) return launch_path_h<POOL_F16>(f, it, n, n0, s);
+        return launch_path_h<POOL_F32>(f, it, n, n0, s);
+    }
+    if (f.pool_kind == POOL_MIXED) return launch_march_h<POOL_MIXED>(f, it, n, n0, s);
+    if (f.pool_kind == POOL_F16) return launch_march_h<POOL_F16>(f, it, n, n0, s);
+    return launch_march_h<POOL_F32>(f, it, n, n0, s);
 }
 
 hipError_t launch_shade(const FrameDev& f, int it, int64_t cap_rays, hipStream_t s) {

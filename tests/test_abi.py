@@ -159,6 +159,36 @@ def test_cache_workspace_grows_with_the_pool_and_rejects_bad_descriptors():
         L.cinr_destroy_volume(h)
 
 
+def test_mixed_pool_descriptors():
+    _, h, _ = fake_volume(configs.ARCH_SMALL)
+    L = cinr.lib()
+
+    def size(**kw):
+        d = cache_desc(pool=40, max_requests=8)
+        for k, v in kw.items():
+            setattr(d, k, v)
+        b = C.c_size_t()
+        return L.cinr_cache_workspace_size(h, C.byref(d), C.byref(b))
+
+    try:
+        assert size(f16_lods=0b10, pool_bricks_f16=16) == OK
+        assert size(f16_lods=0b01, pool_bricks_f16=32) == OK
+        assert size(f16_lods=0b10, pool_bricks_f16=16, pool_dtype=cinr.F16) == INVALID_ARG  # classes need F32
+        assert size(f16_lods=0b11, pool_bricks_f16=16) == INVALID_ARG   # every LoD binary16: one class
+        assert size(f16_lods=0b100, pool_bricks_f16=16) == INVALID_ARG  # LoD 2 does not exist
+        assert size(f16_lods=0b10, pool_bricks_f16=0) == INVALID_ARG
+        assert size(f16_lods=0b10, pool_bricks_f16=40) == INVALID_ARG   # no binary32 slot
+        assert size(f16_lods=0b10, pool_bricks_f16=7) == INVALID_ARG    # fewer slots than max_requests
+        assert size(f16_lods=0b10, pool_bricks_f16=33) == INVALID_ARG
+    finally:
+        L.cinr_destroy_volume(h)
+
+
+def test_f16_lods_from_error_bounds():
+    assert cinr.f16_lods_for_bounds([1e-5, 2.0 ** -12, 1e-3, 0.0]) == 0b0110
+    assert cinr.f16_lods_for_bounds([0.0, 0.0]) == 0
+
+
 def test_render_workspace_covers_the_per_ray_buffers():
     _, h, _ = fake_volume(configs.ARCH_512, macro_cell=16)
     L = cinr.lib()

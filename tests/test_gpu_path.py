@@ -82,16 +82,17 @@ def _compare_misses(gc, oc, f):
     np.testing.assert_array_equal(g[np.lexsort(g.T[::-1])], o[np.lexsort(o.T[::-1])], err_msg=f"misses f{f}")
 
 
-def run_grid_sequence(frames, S, macro=0, pool=40, req=10, B=8, nl=2, pool_dtype="f32", path=PATH, size=(48, 40)):
+def run_grid_sequence(frames, S, macro=0, pool=40, req=10, B=8, nl=2, pool_dtype="f32", path=PATH, size=(48, 40),
+                      f16_lods=0, pool_bricks_f16=0):
     from oracle import oracle as O
     from paper_2504_18001_amd import cinr
     dims = (37, 29, 23)
     w = configs.scaled(configs.SMALL, size[0], size[1], orbit_radius=60.0, lod_scale=1.0 / 60.0, ortho_extent=60.0)
     m, vol, mm = grid_volumes(dims, macro)
     gc = cinr.Cache(vol, B, nl, pool, req, miss_log_capacity=1 << 20, evict_log_capacity=1 << 14,
-                    keep_request_counts=True, pool_dtype=pool_dtype)
+                    keep_request_counts=True, pool_dtype=pool_dtype, f16_lods=f16_lods, pool_bricks_f16=pool_bricks_f16)
     oc = O.OracleCache(m, brick=B, n_lods=nl, pool_bricks=pool, max_requests=req, log_misses=True,
-                       pool_f16=pool_dtype == "f16")
+                       pool_f16=pool_dtype == "f16", f16_lods=f16_lods, pool_bricks_f16=pool_bricks_f16)
     r = cinr.Renderer()
     tf = synth.tf_window(40, 255)
     worst, evicted, misses = 0.0, 0, 0
