@@ -33,10 +33,10 @@ def view_cam(i, f):
     return c
 
 
-def make_cache(vols):
+def make_cache(vols, **kw):
     from paper_2504_18001_amd import cinr
     return cinr.Cache(vols, 8, 2, 150, 24, miss_log_capacity=1 << 20, evict_log_capacity=1 << 14,
-                      keep_request_counts=True)
+                      keep_request_counts=True, **kw)
 
 
 def miss_set(cache):
@@ -46,16 +46,20 @@ def miss_set(cache):
     return g[np.lexsort(g.T[::-1])]
 
 
-@pytest.mark.parametrize("n_views", [5, 1])
-def test_graph_frames_equal_eager_frames_and_oracle(n_views):
+@pytest.mark.parametrize("n_views,mixed", [(5, False), (1, False), (5, True)])
+def test_graph_frames_equal_eager_frames_and_oracle(n_views, mixed):
     from oracle import oracle as O
     from paper_2504_18001_amd import cinr
     vols = [gpu_volume(s) for s in range(3)]
     ms = [oracle_inr(W.arch, s) for s in range(3)]
-    ge, gg = make_cache(vols), make_cache(vols)
-    oc = O.OracleCache(ms, brick=8, n_lods=2, pool_bricks=150, max_requests=24, log_misses=True)
+    # mixed: LoD 1 in a binary16 class of 75 slots, LoD 0 in 75 binary32
+    # slots, at a LoD scale that requests both LoDs
+    pool_kw = dict(f16_lods=0b10, pool_bricks_f16=75) if mixed else {}
+    ls = W.lod_scale * (0.3 if mixed else 1.0)
+    ge, gg = make_cache(vols, **pool_kw), make_cache(vols, **pool_kw)
+    oc = O.OracleCache(ms, brick=8, n_lods=2, pool_bricks=150, max_requests=24, log_misses=True, **pool_kw)
     idx = list(range(n_views))
-    kw = dict(lod_scale=W.lod_scale, seed=W.seed, samples_per_iter=W.samples_per_iter, pipe_depth=2, xcd_bands=4)
+    kw = dict(lod_scale=ls, seed=W.seed, samples_per_iter=W.samples_per_iter, pipe_depth=2, xcd_bands=4)
     mv = cinr.MultiViewRenderer(n_views)
     fg = cinr.FrameGraph(gg, [(vols[VOLS[i]], view_cam(i, 0), W.tf(0)) for i in idx], W.step, **kw)
     for f in range(12):
@@ -65,7 +69,7 @@ def test_graph_frames_equal_eager_frames_and_oracle(n_views):
             fg.tfs[i].copy_(torch.as_tensor(np.asarray(W.tf(f), np.float32)))
         imgs = fg.render([view_cam(i, f) for i in idx], f)
         se, sg = mv.last_stats(), fg.last_stats()
-        ps = [O.make_params(W.step, W.lod_scale, seed=W.seed, frame_index=f, samples_per_iter=W.samples_per_iter)
+        ps = [O.make_params(W.step, ls, seed=W.seed, frame_index=f, samples_per_iter=W.samples_per_iter)
               for _ in idx]
         ref = oc.render_views([(VOLS[i], view_cam(i, f), W.tf(f)) for i in idx], ps)
         for i in idx:
@@ -86,7 +90,10 @@ def test_graph_frames_equal_eager_frames_and_oracle(n_views):
     print("graph frames", n_graph, "eager", n_eager, "with further iterations", n_tail)
     assert n_graph == 12 and n_eager == 0
     assert n_tail >= 1  # the cold start leaves true misses after the first marches
-    assert (gg.dump(cinr.DUMP_EVICTION_LOG)[:, 2] >= 0).any()  # bricks were evicted (LRU pass in the end graph)
+    ev = gg.dump(cinr.DUMP_EVICTION_LOG)
+    assert (ev[:, 2] >= 0).any()  # bricks were evicted (LRU pass in the end graph)
+    if mixed:  # in both classes
+        assert ((ev[:, 2] >= 0) & (ev[:, 1] < 75)).any() and ((ev[:, 2] >= 0) & (ev[:, 1] >= 75)).any()
 
 
 def test_graph_frames_wait_for_online_tuning():

@@ -32,7 +32,8 @@ def _check_pool(gc, oc, split, dtype):
     from paper_2504_18001_amd import cinr
     owner = gc.dump(cinr.DUMP_SLOT_OWNER)
     np.testing.assert_array_equal(owner, oc.owner())
-    got = gc.dump(cinr.DUMP_POOL).astype(np.float64)
+    with np.errstate(invalid="ignore"):  # free slots hold arbitrary bits
+        got = gc.dump(cinr.DUMP_POOL).astype(np.float64)
     ref = oc.pool()
     used = owner >= 0
     assert used[:split].any() and used[split:].any()

@@ -28,25 +28,28 @@ def view_cam(i, f):
     return c
 
 
-@pytest.mark.parametrize("pool_dtype", ["f32", "f16"])
+@pytest.mark.parametrize("pool_dtype", ["f32", "f16", "mixed"])
 def test_shared_cache_views_match_oracle(pool_dtype):
     from oracle import oracle as O
     from paper_2504_18001_amd import cinr
     vols = [gpu_volume(s) for s in range(3)]
     ms = [oracle_inr(W.arch, s) for s in range(3)]
     B, nl, pool, req = 8, 2, 150, 24
+    # mixed: LoD 1 in a binary16 class of 75 slots, LoD 0 in 75 binary32 slots,
+    # at a LoD scale that requests both LoDs (both classes evict)
+    mixed = dict(f16_lods=0b10, pool_bricks_f16=75) if pool_dtype == "mixed" else {}
+    ls = W.lod_scale * (0.3 if mixed else 1.0)
     gc = cinr.Cache(vols, B, nl, pool, req, miss_log_capacity=1 << 20, evict_log_capacity=1 << 14,
-                    keep_request_counts=True, pool_dtype=pool_dtype)
+                    keep_request_counts=True, pool_dtype="f16" if pool_dtype == "f16" else "f32", **mixed)
     oc = O.OracleCache(ms, brick=B, n_lods=nl, pool_bricks=pool, max_requests=req, log_misses=True,
-                       pool_f16=pool_dtype == "f16")
+                       pool_f16=pool_dtype == "f16", **mixed)
     assert gc.n_keys == oc.n_keys == 3 * gc.keys_per_volume
     mv = cinr.MultiViewRenderer(len(SIZES))
     for f in range(10):
         views = [(vols[VOLS[i]], view_cam(i, f), W.tf(f)) for i in range(len(SIZES))]
-        imgs = mv.render(gc, views, W.step, W.lod_scale, frame_index=f, seed=W.seed,
-                         samples_per_iter=W.samples_per_iter)
+        imgs = mv.render(gc, views, W.step, ls, frame_index=f, seed=W.seed, samples_per_iter=W.samples_per_iter)
         gst = mv.last_stats()
-        ps = [O.make_params(W.step, W.lod_scale, seed=W.seed, frame_index=f, samples_per_iter=W.samples_per_iter)
+        ps = [O.make_params(W.step, ls, seed=W.seed, frame_index=f, samples_per_iter=W.samples_per_iter)
               for _ in SIZES]
         ref = oc.render_views([(VOLS[i], view_cam(i, f), W.tf(f)) for i in range(len(SIZES))], ps)
         for i, ((rimg, rst), img) in enumerate(zip(ref, imgs)):
