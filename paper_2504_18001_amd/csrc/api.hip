@@ -1097,6 +1097,28 @@ cinr_status end_views(cinr_cache c, std::vector<ViewRun>& runs, bool lru_pass, T
 // nothing: the remaining iterations run, then the end is launched again
 // without the gate.  Several views of a cached frame run on the cache's side
 // streams so that their marches overlap.
+// Value of the pinned pending-count word before the first march stores it.
+constexpr uint32_t kPendingUnset = 0xFFFFFFFFu;
+
+// Waits for the pending count that the first march's last workgroup stores
+// (after a system-scope fence) into pinned host memory.  Polling the word
+// returns as soon as it lands; a blocking event wait over a whole march tends
+// to sleep and wake late.  The event is queried every few thousand polls, so
+// that a failed launch ends the wait with its error.
+static cinr_status poll_pending(const uint32_t* pinned, hipEvent_t ev) {
+    const volatile uint32_t* w = pinned;
+    for (uint32_t spin = 1;; ++spin) {
+        if (w[0] != kPendingUnset) return CINR_OK;
+        if ((spin & 4095u) == 0u) {
+            const hipError_t e = hipEventQuery(ev);
+            if (e == hipErrorNotReady) continue;
+            if (e != hipSuccess) return fail(CINR_HIP_ERROR, "frame: %s", hipGetErrorString(e));
+            if (w[0] != kPendingUnset) return CINR_OK;
+            return fail(CINR_BAD_STATE, "the first march finished without storing its pending count");
+        }
+    }
+}
+
 cinr_status render_frame_views(cinr_cache c, std::vector<ViewRun>& runs, Timing& tm, hipStream_t s) {
     cinr_volume rv = runs[0].v;
     cinr_status st = ensure_readback(rv);
@@ -1115,6 +1137,9 @@ cinr_status render_frame_views(cinr_cache c, std::vector<ViewRun>& runs, Timing&
     // one ray-marched view: its first march hands over the pending count
     const bool fused = runs.size() == 1 && !runs[0].f.path.on;
     if (fused) {
+        // no GPU work of an earlier frame writes the word any more: the host
+        // read it before that frame's call returned
+        ((volatile uint32_t*)pinned)[0] = kPendingUnset;
         runs[0].f.gather_host = pinned;
         runs[0].f.gather_gate = gate;
         runs[0].f.exit_ticket = runs[0].L.ticket;
@@ -1133,7 +1158,15 @@ cinr_status render_frame_views(cinr_cache c, std::vector<ViewRun>& runs, Timing&
     const bool lru = c && lru_pass_needed(c);
     st = end_views(c, runs, lru, tm, gate, s);
     if (st) return st;
-    HIP_TRY(hipEventSynchronize(rv->ev));
+    const bool trial = runs.size() == 1 && runs[0].timing_trial && runs[0].tuner && runs[0].tuner->pending;
+    if (fused && !trial) {
+        st = poll_pending(pinned, rv->ev);
+        if (st) return st;
+    } else {
+        // several views, or a launch-shape trial whose end event must have
+        // completed before it is timed
+        HIP_TRY(hipEventSynchronize(rv->ev));
+    }
     std::vector<uint32_t> known(runs.size());
     bool tail = false;
     for (size_t i = 0; i < runs.size(); ++i) {
