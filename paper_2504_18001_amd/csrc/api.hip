@@ -1100,21 +1100,35 @@ cinr_status end_views(cinr_cache c, std::vector<ViewRun>& runs, bool lru_pass, T
 // Value of the pinned pending-count word before the first march stores it.
 constexpr uint32_t kPendingUnset = 0xFFFFFFFFu;
 
-// Waits for the pending count that the first march's last workgroup stores
-// (after a system-scope fence) into pinned host memory.  Polling the word
-// returns as soon as it lands; a blocking event wait over a whole march tends
-// to sleep and wake late.  The event is queried every few thousand polls, so
-// that a failed launch ends the wait with its error.
-static cinr_status poll_pending(const uint32_t* pinned, hipEvent_t ev) {
+// Marks the n pending-count words as not yet stored.  No GPU work of an
+// earlier frame writes them any more: the host read them before that frame's
+// call returned.
+static void reset_pending(uint32_t* pinned, int n) {
+    for (int i = 0; i < n; ++i) ((volatile uint32_t*)pinned)[i] = kPendingUnset;
+}
+
+// Waits for the n pending counts that the first marches hand over (stored
+// after a system-scope fence into pinned host memory, by the last workgroup
+// of a single view's march or by k_pending_gather).  Polling the words
+// returns as soon as they land; a blocking event wait over a whole march
+// tends to sleep and wake late.  The event, recorded after the hand-over, is
+// queried every few thousand polls, so that a failed launch ends the wait
+// with its error.
+static cinr_status poll_pending(const uint32_t* pinned, int n, hipEvent_t ev) {
     const volatile uint32_t* w = pinned;
+    auto stored = [&]() {
+        for (int i = 0; i < n; ++i)
+            if (w[i] == kPendingUnset) return false;
+        return true;
+    };
     for (uint32_t spin = 1;; ++spin) {
-        if (w[0] != kPendingUnset) return CINR_OK;
+        if (stored()) return CINR_OK;
         if ((spin & 4095u) == 0u) {
             const hipError_t e = hipEventQuery(ev);
             if (e == hipErrorNotReady) continue;
             if (e != hipSuccess) return fail(CINR_HIP_ERROR, "frame: %s", hipGetErrorString(e));
-            if (w[0] != kPendingUnset) return CINR_OK;
-            return fail(CINR_BAD_STATE, "the first march finished without storing its pending count");
+            if (stored()) return CINR_OK;
+            return fail(CINR_BAD_STATE, "the first marches finished without storing their pending counts");
         }
     }
 }
@@ -1136,10 +1150,8 @@ cinr_status render_frame_views(cinr_cache c, std::vector<ViewRun>& runs, Timing&
     uint32_t* pinned = (uint32_t*)rv->pinned;
     // one ray-marched view: its first march hands over the pending count
     const bool fused = runs.size() == 1 && !runs[0].f.path.on;
+    reset_pending(pinned, (int)runs.size());
     if (fused) {
-        // no GPU work of an earlier frame writes the word any more: the host
-        // read it before that frame's call returned
-        ((volatile uint32_t*)pinned)[0] = kPendingUnset;
         runs[0].f.gather_host = pinned;
         runs[0].f.gather_gate = gate;
         runs[0].f.exit_ticket = runs[0].L.ticket;
@@ -1158,13 +1170,14 @@ cinr_status render_frame_views(cinr_cache c, std::vector<ViewRun>& runs, Timing&
     const bool lru = c && lru_pass_needed(c);
     st = end_views(c, runs, lru, tm, gate, s);
     if (st) return st;
-    const bool trial = runs.size() == 1 && runs[0].timing_trial && runs[0].tuner && runs[0].tuner->pending;
-    if (fused && !trial) {
-        st = poll_pending(pinned, rv->ev);
+    bool trial = false;
+    for (const ViewRun& r : runs) trial = trial || (r.timing_trial && r.tuner && r.tuner->pending);
+    if (!trial) {
+        st = poll_pending(pinned, (int)runs.size(), rv->ev);
         if (st) return st;
     } else {
-        // several views, or a launch-shape trial whose end event must have
-        // completed before it is timed
+        // a launch-shape trial's end event must have completed before it is
+        // timed
         HIP_TRY(hipEventSynchronize(rv->ev));
     }
     std::vector<uint32_t> known(runs.size());
@@ -1437,11 +1450,13 @@ extern "C" cinr_status cinr_frame_graph_render(cinr_frame_graph g, const cinr_ca
         if (st) return st;
     }
     for (int32_t i = 0; i < n; ++i) g->stage[i] = runs[i].hv;
+    reset_pending(g->pending, n);
     // the end graph is gated: it does nothing if a view still has rays pending
     HIP_TRY(hipGraphLaunch(g->start, s));
     HIP_TRY(hipEventRecord(g->ev, s));
     HIP_TRY(hipGraphLaunch(g->end[lru], s));
-    HIP_TRY(hipEventSynchronize(g->ev));
+    st = poll_pending(g->pending, n, g->ev);
+    if (st) return st;
     std::vector<uint32_t> known(n);
     bool tail = false;
     for (int32_t i = 0; i < n; ++i) {
