@@ -66,18 +66,24 @@ def _prefill_keys(off, seed=5):
     return np.sort(np.concatenate(keys)).astype(np.int32)
 
 
+# LoD-dependent mixed precision at full size: LoDs 1 to 3 in a binary16 class
+# of half the slots, LoD 0 in binary32
+MIXED = dict(f16_lods=0b1110, pool_bricks_f16=W.cache.pool_bricks // 2)
+
+
 def _gpu_cache(vol, keep=False, pool_dtype="f32"):
     from paper_2504_18001_amd import cinr
     cs = W.cache
+    kw = MIXED if pool_dtype == "mixed" else dict(pool_dtype=pool_dtype)
     return cinr.Cache(vol, cs.brick, cs.n_lods, cs.pool_bricks, cs.max_requests, preload_period=cs.preload_period,
-                      keep_request_counts=keep, evict_log_capacity=64, pool_dtype=pool_dtype)
+                      keep_request_counts=keep, evict_log_capacity=64, **kw)
 
 
-def _oracle_cache(m, pool_f16=False):
+def _oracle_cache(m, pool_f16=False, mixed=False):
     from oracle import oracle as O
     cs = W.cache
     return O.OracleCache(m, brick=cs.brick, n_lods=cs.n_lods, pool_bricks=cs.pool_bricks, max_requests=cs.max_requests,
-                         preload_period=cs.preload_period, pool_f16=pool_f16)
+                         preload_period=cs.preload_period, pool_f16=pool_f16, **(MIXED if mixed else {}))
 
 
 def test_frame0_equals_uncached_inr_on_sampled_pixels(scene):
@@ -159,7 +165,8 @@ def test_prefilled_fullsize_parity_mode_bit_exact_requests(scene):
 MAXABS = {"bf16x3": 8e-3, "f16": 8e-3, "bf16": 2.5e-2}
 
 
-@pytest.mark.parametrize("dtype,pool_dtype", [("bf16x3", "f32"), ("f16", "f32"), ("bf16", "f32"), ("bf16x3", "f16")])
+@pytest.mark.parametrize("dtype,pool_dtype", [("bf16x3", "f32"), ("f16", "f32"), ("bf16", "f32"), ("bf16x3", "f16"),
+                                              ("bf16x3", "mixed")])
 def test_prefilled_fullsize_bench_configuration_pixels(scene, dtype, pool_dtype):
     from oracle import oracle as O
     from paper_2504_18001_amd import cinr
@@ -168,8 +175,11 @@ def test_prefilled_fullsize_bench_configuration_pixels(scene, dtype, pool_dtype)
     keys = _prefill_keys(off, seed=9)
     cache = _gpu_cache(vol, pool_dtype=pool_dtype)
     cache.prefill(torch.from_numpy(keys).cuda(), stamp=0, dtype=dtype)
-    oc = _oracle_cache(m, pool_f16=pool_dtype == "f16")
+    oc = _oracle_cache(m, pool_f16=pool_dtype == "f16", mixed=pool_dtype == "mixed")
     oc.prefill(keys, 0)
+    if pool_dtype == "mixed":  # both classes hold bricks
+        np.testing.assert_array_equal(cache.dump(cinr.DUMP_SLOT_OWNER), oc.owner())
+        assert (oc.owner()[:W.cache.pool_bricks // 2] >= 0).any() and (oc.owner()[W.cache.pool_bricks // 2:] >= 0).any()
     f = 40  # random transfer function part of the orbit
     cam, tf = W.camera(f), W.tf(f)
     r = cinr.Renderer()
