@@ -1123,6 +1123,7 @@ static cinr_status poll_pending(const uint32_t* pinned, int n, hipEvent_t ev) {
     };
     for (uint32_t spin = 1;; ++spin) {
         if (stored()) return CINR_OK;
+        __builtin_ia32_pause();  // a spin-wait hint to the core
         if ((spin & 4095u) == 0u) {
             const hipError_t e = hipEventQuery(ev);
             if (e == hipErrorNotReady) continue;
