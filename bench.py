@@ -234,21 +234,30 @@ def path_leg(vol, cams, tfs, w, Wm, K, dtype, K_unc, oracle=True):
                      samples_per_iter=w.samples_per_iter, mode=mode, dtype=dt, cache=c, out=out,
                      stats=None if st is None else st[i], path=path)
 
-    c = new_cache(vol, w)
-    r = cinr.Renderer()
-    out = torch.empty((w.height, w.width, 4), dtype=torch.float32, device="cuda")
-    st = torch.zeros((K, nst), dtype=torch.int64, device="cuda")
-    frames(r, c, range(Wm), cinr.CACHED, dtype, out=out)
-    torch.cuda.synchronize()
-    vol.set_timing(True, march_only=True)
-    t0 = time.perf_counter()
-    frames(r, c, range(Wm, Wm + K), cinr.CACHED, dtype, st, out)
-    torch.cuda.synchronize()
-    fps = K / (time.perf_counter() - t0)
-    vol.set_timing(False)
-    ms, n = vol.collect_timing()["march"]
-    tot = {k: int(v) for k, v in zip(cinr.STAT_FIELDS, st.sum(0).cpu().numpy())}
-    del c
+    def cached(pool_dtype):
+        c = new_cache(vol, w, pool_dtype=pool_dtype)
+        r = cinr.Renderer()
+        out = torch.empty((w.height, w.width, 4), dtype=torch.float32, device="cuda")
+        st = torch.zeros((K, nst), dtype=torch.int64, device="cuda")
+        frames(r, c, range(Wm), cinr.CACHED, dtype, out=out)
+        torch.cuda.synchronize()
+        vol.set_timing(True, march_only=True)
+        t0 = time.perf_counter()
+        frames(r, c, range(Wm, Wm + K), cinr.CACHED, dtype, st, out)
+        torch.cuda.synchronize()
+        fps = K / (time.perf_counter() - t0)
+        vol.set_timing(False)
+        ms, n = vol.collect_timing()["march"]
+        tot = {k: int(v) for k, v in zip(cinr.STAT_FIELDS, st.sum(0).cpu().numpy())}
+        del c
+        return fps, ms, n, tot, out
+
+    fps, ms, n, tot, out = cached("f32")
+    # the same paths over a binary16 pool: half the bytes per brick line for
+    # the path tracer's incoherent lookups
+    fps16, ms16, _, _, out16 = cached("f16")
+    half = {"fps_cached": round(fps16, 2), "path_kernel_ms_per_frame": round(ms16 / K, 4),
+            "psnr_vs_f32_pool_db": round(psnr(out.cpu().numpy(), out16.cpu().numpy()), 2)}
     ru = cinr.Renderer()
     outu = torch.empty_like(out)
     stu = torch.zeros((K_unc, nst), dtype=torch.int64, device="cuda")
@@ -264,6 +273,7 @@ def path_leg(vol, cams, tfs, w, Wm, K, dtype, K_unc, oracle=True):
            "lookups_per_frame": tot["samples"] // K, "true_misses_per_frame": tot["misses"] // K,
            "iterations_per_frame": round(tot["iterations"] / K, 2),
            "path_kernel_ms_per_frame": round(ms / K, 4), "path_launches_per_frame": round(n / K, 2),
+           "binary16_pool": half,
            "uncached_inferred_per_frame": totu["misses"] // K_unc,
            "uncached_iterations_per_frame": round(totu["iterations"] / K_unc, 2)}
     if oracle:
