@@ -91,9 +91,10 @@ __device__ inline FrameHot load_hot(const FrameVar* v) {
 // Sampler of Algorithm 2 for one position: macro-cell skip, stochastic LoD,
 // page-table lookup at that LoD and every coarser one, trilinear fetch.  The
 // flag read and the first page-table read are issued together; a skipped
-// sample discards the lookup.  kFast: bricks of 16^3 in a pool of less than
-// 4 GiB (compile-time brick offsets, 32-bit byte offsets into the pool) and
-// macro-cells of 16^3 voxels.  kAdapt: the cell's code (Flags reads codes)
+// sample discards the lookup.  kFast (nonzero): bricks of 16^3 (compile-time
+// brick offsets) and macro-cells of 16^3 voxels; kFast = 1: a pool of less
+// than 4 GiB, addressed by 32-bit byte offsets, kFast = 2: any pool, each
+// brick's base in 64 bits.  kAdapt: the cell's code (Flags reads codes)
 // gives the sample's step exponent; a transparent cell's samples are skipped.
 // kPool: POOL_F32, POOL_F16 (binary16 values, interpolated in FP32), or
 // POOL_MIXED (binary32 slots below f.split, binary16 slots from it on).
@@ -102,11 +103,16 @@ __device__ inline float pool_value(__half x) { return __half2float(x); }
 
 // The 8 pool values around a sample in a brick stored as T at `base`
 // (slot relative to base): c[x + 2y + 4z].
-template <bool kFast, class T>
+template <int kFast, class T>
 __device__ inline void brick_corners(const void* base, int32_t slot, const BrickAddr& a, int32_t B, float c[8]) {
     constexpr int kB = kFast ? 16 : 0;
     const T* br;
-    if (kFast) {
+    if (kFast == 2) {
+        // the brick's base in 64 bits, the sample's offset inside it in 32
+        const char* b = reinterpret_cast<const char*>(base) + (uint64_t)(uint32_t)slot * (kB * kB * kB * sizeof(T));
+        const uint32_t off = (((uint32_t)a.lj[2] * kB + (uint32_t)a.lj[1]) * kB + (uint32_t)a.lj[0]) * (uint32_t)sizeof(T);
+        br = reinterpret_cast<const T*>(b + off);
+    } else if (kFast) {
         const uint32_t off = (((uint32_t)slot * (uint32_t)(kB * kB * kB) +
                                ((uint32_t)a.lj[2] * kB + (uint32_t)a.lj[1]) * kB + (uint32_t)a.lj[0])) *
                              (uint32_t)sizeof(T);
@@ -126,7 +132,7 @@ __device__ inline void brick_corners(const void* base, int32_t slot, const Brick
     c[7] = pool_value(br[B2 + Bq + 1]);
 }
 
-template <bool kFast, bool kAdapt, int kPool, class Flags>
+template <int kFast, bool kAdapt, int kPool, class Flags>
 __device__ inline SampleRes sample_cache(const FrameDev& f, const FrameHot& h, const LodGeom* lg, const Flags& fl,
                                          const float p[3], SlotCache& sc) {
     constexpr int kB = kFast ? 16 : 0;
@@ -495,7 +501,7 @@ struct UnitQueue {
 // kAdapt: adaptive sampling rate (macro-cell codes instead of visibility
 // bits); a sample of step exponent e is followed by sample k + 2^e.  kPool:
 // the pool's storage (binary32, binary16, or mixed per LoD).
-template <int kPipe, bool kLdsFlags, bool kFast, bool kAdapt, int kPool, int kWaves>
+template <int kPipe, bool kLdsFlags, int kFast, bool kAdapt, int kPool, int kWaves>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves, 8))) void k_march(FrameDev f, int32_t it, uint32_t n0) {
     static_assert(!kAdapt || kPipe == 1, "the adaptive sampler decides one sample ahead at most");
     const FrameHot hot = load_hot(f.var);  // before any store of this kernel
@@ -864,7 +870,7 @@ __device__ inline float4 pt_pixel_value(const PtLane& s) {
 }
 
 // (3 waves per SIMD: 158 VGPRs without spills; 4 would spill)
-template <bool kLdsFlags, bool kFast, int kPool>
+template <bool kLdsFlags, int kFast, int kPool>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_path(FrameDev f, int32_t it, uint32_t n0) {
     const FrameHot hot = load_hot(f.var);  // before any store of this kernel
     __shared__ float4 tfs[256];
@@ -1160,7 +1166,14 @@ hipError_t launch_frame_begin(const FrameDev& f, int32_t n_iter_ctr, const float
 
 // Workgroups of one k_march instantiation that are resident at once on the
 // current device (the grid of the persistent kernel), cached per device.
-template <int P, bool LDS, bool FAST, bool A, int H, int W>
+// Whether every byte offset into the pool fits in 32 bits (the uncached
+// mode reads no pool).
+static bool small_pool(const FrameDev& f, int pool_kind) {
+    const uint64_t brick_bytes = (uint64_t)f.geo.brick * f.geo.brick * f.geo.brick * (pool_kind == POOL_F16 ? 2u : 4u);
+    return f.mode != CINR_CACHED || (uint64_t)f.pool_bricks * brick_bytes < (1ull << 32);
+}
+
+template <int P, bool LDS, int FAST, bool A, int H, int W>
 static hipError_t resident_blocks(int* out) {
     static int cache[64] = {0};
     int dev = 0;
@@ -1179,7 +1192,7 @@ static hipError_t resident_blocks(int* out) {
     return hipSuccess;
 }
 
-template <int P, bool LDS, bool FAST, bool A, int H, int W>
+template <int P, bool LDS, int FAST, bool A, int H, int W>
 static hipError_t launch_march_t(const FrameDev& f, int it, int64_t max_rays, uint32_t n0, hipStream_t s) {
     int cap = 0;
     hipError_t e = resident_blocks<P, LDS, FAST, A, H, W>(&cap);
@@ -1194,15 +1207,13 @@ static hipError_t launch_march_t(const FrameDev& f, int it, int64_t max_rays, ui
 
 template <int P, bool LDS, bool A, int H, int W>
 static hipError_t launch_march_l(const FrameDev& f, int it, int64_t max_rays, uint32_t n0, hipStream_t s) {
-    // 16^3 bricks in a pool of less than 4 GiB (or the uncached mode, which
-    // reads no pool) and 16^3 macro-cells (or none)
+    // 16^3 bricks (or the uncached mode, which reads no pool) and 16^3
+    // macro-cells (or none); 32-bit pool offsets below 4 GiB
     const bool cells = A || f.flags;
-    const uint64_t brick_bytes = 4096ull * (H == POOL_F16 ? 2ull : 4ull);
-    const bool fast = (f.mode != CINR_CACHED ||
-                       (f.geo.brick == 16 && (uint64_t)f.pool_bricks * brick_bytes < (1ull << 32))) &&
-                      (!cells || f.mc_N == 16);
-    if (fast) return launch_march_t<P, LDS, true, A, H, W>(f, it, max_rays, n0, s);
-    return launch_march_t<P, LDS, false, A, H, W>(f, it, max_rays, n0, s);
+    const bool fast = (f.mode != CINR_CACHED || f.geo.brick == 16) && (!cells || f.mc_N == 16);
+    if (fast && small_pool(f, H)) return launch_march_t<P, LDS, 1, A, H, W>(f, it, max_rays, n0, s);
+    if (fast) return launch_march_t<P, LDS, 2, A, H, W>(f, it, max_rays, n0, s);
+    return launch_march_t<P, LDS, 0, A, H, W>(f, it, max_rays, n0, s);
 }
 
 template <int P, bool A, int H, int W>
@@ -1231,7 +1242,7 @@ static hipError_t launch_march_h(const FrameDev& f, int it, int64_t n, uint32_t 
 }
 
 // The path tracer's persistent grid, as resident_blocks for k_march.
-template <bool LDS, bool FAST, int H>
+template <bool LDS, int FAST, int H>
 static hipError_t launch_path_t(const FrameDev& f, int it, int64_t max_px, uint32_t n0, hipStream_t s) {
     static int cache[64] = {0};
     int dev = 0;
@@ -1255,13 +1266,17 @@ static hipError_t launch_path_t(const FrameDev& f, int it, int64_t max_px, uint3
 
 template <int H>
 static hipError_t launch_path_h(const FrameDev& f, int it, int64_t n, uint32_t n0, hipStream_t s) {
-    const uint64_t brick_bytes = 4096ull * (H == POOL_F16 ? 2ull : 4ull);
-    const bool fast = (f.mode != CINR_CACHED ||
-                       (f.geo.brick == 16 && (uint64_t)f.pool_bricks * brick_bytes < (1ull << 32))) &&
-                      (!f.flags || f.mc_N == 16);
+    const bool fast = (f.mode != CINR_CACHED || f.geo.brick == 16) && (!f.flags || f.mc_N == 16);
+    const int kind = fast ? (small_pool(f, H) ? 1 : 2) : 0;
     const bool lds = f.flags && f.flag_words <= kMaxLdsFlagWords;
-    if (lds) return fast ? launch_path_t<true, true, H>(f, it, n, n0, s) : launch_path_t<true, false, H>(f, it, n, n0, s);
-    return fast ? launch_path_t<false, true, H>(f, it, n, n0, s) : launch_path_t<false, false, H>(f, it, n, n0, s);
+    if (lds) {
+        if (kind == 1) return launch_path_t<true, 1, H>(f, it, n, n0, s);
+        if (kind == 2) return launch_path_t<true, 2, H>(f, it, n, n0, s);
+        return launch_path_t<true, 0, H>(f, it, n, n0, s);
+    }
+    if (kind == 1) return launch_path_t<false, 1, H>(f, it, n, n0, s);
+    if (kind == 2) return launch_path_t<false, 2, H>(f, it, n, n0, s);
+    return launch_path_t<false, 0, H>(f, it, n, n0, s);
 }
 
 hipError_t launch_march(const FrameDev& f, int it, int64_t max_rays, hipStream_t s) {
