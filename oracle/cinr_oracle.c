@@ -526,6 +526,13 @@ int32_t orc_lod_floor(int32_t frame, int32_t period, int32_t n_lods) {
     return f < 0 ? 0 : f;
 }
 
+/* Section 4.3.4 pre-load, continued: the frames whose samples are all forced
+ * to the coarsest LoD (the first `period` frames) march every ray to the end
+ * of the volume, with early ray termination suspended, so that the coarsest
+ * bricks behind opaque material are requested too and the cache holds a
+ * low-resolution copy of nearly the whole volume to fall back on. */
+int32_t orc_preload_frame(int32_t frame, int32_t period) { return period > 0 && frame >= 0 && frame < period; }
+
 /* ------------------------------------------------------------------------- */
 /* Value plane helpers                                                        */
 /* ------------------------------------------------------------------------- */
@@ -872,6 +879,7 @@ typedef struct {
     int32_t M[3];
     uint32_t frame_seed;
     int32_t lod_floor;
+    int32_t preload;        /* a pre-load frame: early ray termination suspended */
     float vm1[3];
 } frame_ctx;
 
@@ -922,7 +930,7 @@ static float miss_value32(const orc_inr* m, const float pos[3], double v64) {
 }
 
 typedef struct {
-    int64_t samples, hits, fallbacks, misses, skipped;
+    int64_t samples, hits, fallbacks, misses, skipped, ert_violations;
     miss_rec* misses_buf;
     int64_t n_m, cap_m;
 } thread_acc;
@@ -1108,16 +1116,28 @@ static int32_t sample_count(float ts, float te, float step) {
  * wavefront step, their misses inferred, and then composited in order.  Early
  * termination is tested after every composited sample.  Without early
  * termination this is plain front-to-back compositing of every sample. */
+/* Early termination after a composited sample; `knext` is the grid index of
+ * the ray's next sample.  Without a replay: A >= threshold.  With a replay:
+ * exactly where the checked renderer ended the ray, and a replayed end that
+ * the oracle's own opacity contradicts by more than 1e-4 is counted. */
+static int ert_end(const orc_params* P, thread_acc* ta, int32_t pix, int32_t knext, double A, double thr) {
+    if (!P->ert_replay) return A >= thr;
+    const int end = P->ert_replay[pix] == knext;
+    if (end ? A < thr - 1e-4 : A >= thr + 1e-4) ta->ert_violations++;
+    return end;
+}
+
 static int32_t march(const frame_ctx* fc, thread_acc* ta, const float* tf, int32_t i, int32_t j, double out[4],
                      int log_miss) {
     const int32_t W = fc->cam->width;
     const int32_t pix = j * W + i;
     float o[3], d[3], ts, te;
     out[0] = out[1] = out[2] = out[3] = 0.0;
-    if (!orc_ray_setup(fc->cam, fc->m->dims, i, j, o, d, &ts, &te)) return 0;
     const orc_params* P = fc->p;
+    if (P->ert_record) P->ert_record[pix] = -1;
+    if (!orc_ray_setup(fc->cam, fc->m->dims, i, j, o, d, &ts, &te)) return 0;
     const int32_t nk = sample_count(ts, te, P->step);
-    const int ert = P->ert_threshold <= 1.0f;
+    const int ert = P->ert_threshold <= 1.0f && !fc->preload;
     const double thr = (double)P->ert_threshold;
     const double step = (double)P->step;
     const int32_t S = P->samples_per_iter > 0 ? P->samples_per_iter : 1;
@@ -1139,8 +1159,9 @@ static int32_t march(const frame_ctx* fc, thread_acc* ta, const float* tf, int32
             if (st == S_MISS) break;
             if (st != S_SKIP) composite(&acc, tf, v, ldexp(step, e));
             k += 1 << e;
-            if (ert && acc.A >= thr) {
+            if (ert && ert_end(P, ta, pix, k, acc.A, thr)) {
                 done = 1;
+                if (P->ert_record) P->ert_record[pix] = k;
                 break;
             }
         }
@@ -1156,10 +1177,13 @@ static int32_t march(const frame_ctx* fc, thread_acc* ta, const float* tf, int32
             kn += 1 << exps[n];
             ++n;
         }
+        int32_t kq = k; /* grid index after the composited samples */
         for (int32_t s = 0; s < n; ++s) {
             if (stat[s] != S_SKIP) composite(&acc, tf, vals[s], ldexp(step, exps[s]));
-            if (ert && acc.A >= thr) {
+            kq += 1 << exps[s];
+            if (ert && ert_end(P, ta, pix, kq, acc.A, thr)) {
                 done = 1;
+                if (P->ert_record) P->ert_record[pix] = kq;
                 break;
             }
         }
@@ -1502,6 +1526,7 @@ static int render_pass(frame_ctx* fc, const float* tf, double* rgba, orc_stats* 
         st->fallbacks += acc[t].fallbacks;
         st->misses += acc[t].misses;
         st->skipped += acc[t].skipped;
+        st->ert_violations += acc[t].ert_violations;
         nm += acc[t].n_m;
     }
     if (fc->c) {
@@ -1652,6 +1677,7 @@ int orc_cache_render(orc_cache* c, const orc_camera* cam, const float* tf, const
     fc.flags = make_flags(&c->inr, p, tf, fc.M);
     fc.frame_seed = orc_frame_seed(p->seed, (uint32_t)p->frame_index);
     fc.lod_floor = orc_lod_floor(p->frame_index, c->d.preload_period, c->d.n_lods);
+    fc.preload = orc_preload_frame(p->frame_index, c->d.preload_period);
     int32_t* trace = NULL;
     if (c->trace_ert) {
         free(c->ert_trace);
@@ -1692,6 +1718,7 @@ int orc_cache_render_views(orc_cache* c, int32_t n, const int32_t* vol, const or
         fc.flags = make_flags(fc.m, &ps[i], tfs + 1024 * i, fc.M);
         fc.frame_seed = orc_frame_seed(ps[i].seed, (uint32_t)ps[i].frame_index);
         fc.lod_floor = orc_lod_floor(ps[i].frame_index, c->d.preload_period, c->d.n_lods);
+        fc.preload = orc_preload_frame(ps[i].frame_index, c->d.preload_period);
         render_pass(&fc, tfs + 1024 * i, out, &sts[i], c->log_misses, NULL);
         free((void*)fc.flags);
         out += 4 * (int64_t)cams[i].width * cams[i].height;
@@ -1733,6 +1760,7 @@ int orc_render_pixels(const orc_inr* m, orc_cache* c, const orc_camera* cam, con
     if (c) {
         fc.frame_seed = orc_frame_seed(p->seed, (uint32_t)p->frame_index);
         fc.lod_floor = orc_lod_floor(p->frame_index, c->d.preload_period, c->d.n_lods);
+        fc.preload = orc_preload_frame(p->frame_index, c->d.preload_period);
     }
     const int nt = orc_get_threads();
     thread_acc* acc = (thread_acc*)calloc(nt, sizeof(thread_acc));

@@ -82,6 +82,19 @@ typedef struct {
      * so that cells with a wide value range are sampled at finer LoDs;
      * 0 is the distance-only rule of Algorithm 2 */
     float lod_context;
+    /* Performance-mode replay of early ray termination (ray marching): when
+     * set, int32 [height][width] holds for every pixel the sample-grid index
+     * just past the sample whose compositing ended the ray in the renderer
+     * being checked (-1: the ray was not ended early).  The oracle then ends
+     * each ray exactly there instead of testing its own opacity, so that every
+     * decision of the frame follows the same samples, and counts in
+     * orc_stats.ert_violations the replayed ends that its own opacity does not
+     * justify: an end where A < threshold - 1e-4, or a sample composited
+     * before it where A >= threshold + 1e-4.  NULL: the oracle's own test. */
+    const int32_t* ert_replay;
+    /* Optional output in the same format: for every pixel, the grid index
+     * just past the sample whose compositing ended the ray early, or -1. */
+    int32_t* ert_record;
 } orc_params;
 
 /* Events (Philox draws) a pixel may use per frame in path tracing; a pixel
@@ -113,6 +126,7 @@ typedef struct {
 typedef struct {
     int64_t rays, samples, hits, fallbacks, misses, skipped;
     int64_t requested, selected, evicted;
+    int64_t ert_violations; /* replayed early terminations not justified by the oracle's opacity */
 } orc_stats;
 
 typedef struct orc_cache orc_cache;
@@ -156,6 +170,9 @@ int32_t orc_select_lod(const float p[3], const float eye[3], float lod_scale, ui
 int32_t orc_select_lod_scaled(const float p[3], const float eye[3], float lod_scale, float factor,
                               uint32_t frame_seed, int32_t lod_floor, int32_t n_lods);
 int32_t orc_lod_floor(int32_t frame, int32_t period, int32_t n_lods);
+/* 1 in the frames of the pre-load whose samples are all forced to the coarsest
+ * LoD (frame < period, period > 0): early ray termination is suspended. */
+int32_t orc_preload_frame(int32_t frame, int32_t period);
 
 /* --- uncached renderers (no cache state) --- */
 int orc_render_uncached(const orc_inr* m, const orc_camera* c, const float* tf,

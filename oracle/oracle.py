@@ -42,7 +42,8 @@ class Params(C.Structure):
                 ("adapt_max_exp", C.c_int32),
                 ("pipeline", C.c_int32), ("pt_density", C.c_float), ("pt_light_dir", C.c_float * 3),
                 ("pt_light", C.c_float * 3), ("pt_ambient", C.c_float * 3), ("pt_max_bounces", C.c_int32),
-                ("pt_spp", C.c_int32), ("pt_seed", C.c_uint32), ("lod_context", C.c_float)]
+                ("pt_spp", C.c_int32), ("pt_seed", C.c_uint32), ("lod_context", C.c_float),
+                ("ert_replay", C.c_void_p), ("ert_record", C.c_void_p)]
 
 
 class CacheDesc(C.Structure):
@@ -54,7 +55,7 @@ class CacheDesc(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [(n, C.c_int64) for n in ("rays", "samples", "hits", "fallbacks", "misses", "skipped",
-                                          "requested", "selected", "evicted")]
+                                          "requested", "selected", "evicted", "ert_violations")]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
@@ -377,7 +378,7 @@ def philox4x32_10(ctr, key):
 
 
 def make_params(step, lod_scale, seed=0, frame_index=0, ert_threshold=2.0, samples_per_iter=8, mode=CACHED,
-                macro_cell=0, macro_minmax=None, adapt_max_exp=-1, path=None, lod_context=0.0):
+                macro_cell=0, macro_minmax=None, adapt_max_exp=-1, path=None, lod_context=0.0, ert_replay=None):
     """adapt_max_exp: adaptive sampling rate with steps of up to 2^E sample
     spacings (Section 5.2); -1 (or 0) for the fixed step.  path: None for ray
     marching, else a dict of path-tracing parameters (density, light_dir,
@@ -401,7 +402,21 @@ def make_params(step, lod_scale, seed=0, frame_index=0, ert_threshold=2.0, sampl
     p.macro_cell = macro_cell if macro_minmax is not None else 0
     p._mm = None if macro_minmax is None else np.ascontiguousarray(macro_minmax, np.float32)
     p.macro_minmax = p._mm.ctypes.data if p._mm is not None else None
+    # ert_replay: int32 [H][W] sample-grid index just past each ray's early
+    # termination in the renderer being checked, -1 where it did not end early
+    p._replay = None if ert_replay is None else np.ascontiguousarray(ert_replay, np.int32)
+    p.ert_replay = p._replay.ctypes.data if p._replay is not None else None
+    p._record = None
     return p
+
+
+def record_ert(params, width, height):
+    """Makes frames rendered with `params` record each ray's early
+    termination (see ert_replay); returns the int32 [height][width] array the
+    next render fills."""
+    params._record = np.full((height, width), -1, np.int32)
+    params.ert_record = params._record.ctypes.data
+    return params._record
 
 
 def render_uncached(inr: OracleInr, cam, tf, params: Params):

@@ -170,10 +170,52 @@ def test_I2_full_single_lod_cache_equals_lattice_image():
 # ---------------------------------------------------------------------------
 
 
-def _brute_force_frame(m, dims, B, n_lods, resident, cam, tf, step, lod_scale, seed, frame, lod_floor):
-    """Independent per-sample march: residency by set membership, the value
-    of a served sample is the trilinear interpolation of the INR's LoD-L*
-    lattice values, a true miss is the INR at the sample."""
+def _bf_decide(m, V, K, nb, off, B, n_lods, resident, o, d, t, eye, lod_scale, fseed, lod_floor):
+    """One sample of the independent march: (value, status, requested key,
+    serving slot).  Residency by set membership; a served sample is the
+    trilinear interpolation of the INR's LoD-L* lattice values; a true miss
+    is the INR at the sample."""
+    f32 = np.float32
+    p = np.array([min(max(f32(o[a] + f32(t * d[a])), f32(0)), f32(V[a] - 1)) for a in range(3)], f32)
+    L = O.select_lod(p, eye, lod_scale, fseed, lod_floor, n_lods)
+    for Lp in range(L, n_lods):
+        q = p * f32(2.0 ** -Lp)
+        jj = np.minimum(q.astype(np.int64), K[Lp] - 2)
+        b = jj // (B - 1)
+        key = int(off[Lp] + (b[2] * nb[Lp][1] + b[1]) * nb[Lp][0] + b[0])
+        if Lp == L:
+            rkey = key
+        if key in resident:
+            fr = (q - jj.astype(f32)).astype(np.float64)
+            corners = []
+            for n in range(8):
+                dlt = np.array([n & 1, (n >> 1) & 1, (n >> 2) & 1])
+                x = np.minimum((jj + dlt) << Lp, V - 1).astype(np.float64)
+                corners.append(m.value(x[None])[0])
+            c = np.array(corners).reshape(2, 2, 2)  # [z][y][x]
+            cx = c[..., 0] * (1 - fr[0]) + c[..., 1] * fr[0]
+            cy = cx[:, 0] * (1 - fr[1]) + cx[:, 1] * fr[1]
+            return cy[0] * (1 - fr[2]) + cy[1] * fr[2], ("hit" if Lp == L else "fb"), rkey, resident[key]
+    return m.value(p.astype(np.float64)[None])[0], "miss", rkey, None
+
+
+def _bf_composite(C, A, val, tf, step):
+    x = val * 255.0
+    i0 = min(int(math.floor(x)), 254)
+    tt = x - i0
+    rgba = tf[i0].astype(np.float64) * (1 - tt) + tf[i0 + 1].astype(np.float64) * tt
+    a1 = 1.0 - (1.0 - rgba[3]) ** float(step)
+    wgt = (1.0 - A) * a1
+    return C + wgt * rgba[:3], A + wgt
+
+
+def _brute_force_frame(m, dims, B, n_lods, resident, cam, tf, step, lod_scale, seed, frame, lod_floor,
+                       ert=2.0, S=1):
+    """Independent march of a frame.  Without early termination (ert > 1)
+    every sample is decided and composited in order.  With it, the wavefront
+    schedule: samples one at a time until the first true miss, then a step of
+    S samples from the miss on (all decided: requests and stamps) composited
+    in order; a ray ends at the first composited sample with A >= ert."""
     f32 = np.float32
     V = np.asarray(dims)
     K = [((V - 1) + (1 << L) - 1) // (1 << L) + 1 for L in range(n_lods)]
@@ -184,57 +226,51 @@ def _brute_force_frame(m, dims, B, n_lods, resident, cam, tf, step, lod_scale, s
     req = {}
     stamps = {}
     counts = dict(hit=0, fb=0, miss=0)
+
+    def decide(o, d, t):
+        val, stt, rkey, slot = _bf_decide(m, V, K, nb, off, B, n_lods, resident, o, d, t, cam.eye, lod_scale,
+                                          fseed, lod_floor)
+        counts[stt] += 1
+        if slot is not None:
+            stamps[slot] = frame
+        if stt != "hit":
+            req[rkey] = req.get(rkey, 0) + 1
+        return val, stt
+
     for j in range(cam.height):
         for i in range(cam.width):
             ok, o, d, ts, te = O.ray_setup(cam, dims, i, j)
             if not ok:
                 continue
-            C = np.zeros(3)
-            A = 0.0
-            k = 0
+            ts_list = []
             while True:
-                t = f32(f32(ts) + f32(f32(k) * f32(step)))
+                t = f32(f32(ts) + f32(f32(len(ts_list)) * f32(step)))
                 if t > f32(te):
                     break
-                p = np.minimum(np.maximum(o + t * d, f32(0)), (V - 1).astype(f32)).astype(f32)
-                p = np.array([min(max(f32(o[a] + f32(t * d[a])), f32(0)), f32(V[a] - 1)) for a in range(3)], f32)
-                L = O.select_lod(p, cam.eye, lod_scale, fseed, lod_floor, n_lods)
-                val = None
-                for Lp in range(L, n_lods):
-                    q = p * f32(2.0 ** -Lp)
-                    jj = np.minimum(q.astype(np.int64), K[Lp] - 2)
-                    b = jj // (B - 1)
-                    key = int(off[Lp] + (b[2] * nb[Lp][1] + b[1]) * nb[Lp][0] + b[0])
-                    if Lp == L:
-                        rkey = key
-                    if key in resident:
-                        fr = (q - jj.astype(f32)).astype(np.float64)
-                        corners = []
-                        for n in range(8):
-                            dlt = np.array([n & 1, (n >> 1) & 1, (n >> 2) & 1])
-                            x = np.minimum((jj + dlt) << Lp, V - 1).astype(np.float64)
-                            corners.append(m.value(x[None])[0])
-                        c = np.array(corners).reshape(2, 2, 2)  # [z][y][x]
-                        cx = c[..., 0] * (1 - fr[0]) + c[..., 1] * fr[0]
-                        cy = cx[:, 0] * (1 - fr[1]) + cx[:, 1] * fr[1]
-                        val = cy[0] * (1 - fr[2]) + cy[1] * fr[2]
-                        stamps[resident[key]] = frame
-                        counts["hit" if Lp == L else "fb"] += 1
+                ts_list.append(t)
+            nk = len(ts_list)
+            C, A = np.zeros(3), 0.0
+            k, done = 0, False
+            while not done and k < nk:
+                stt = None
+                while k < nk:
+                    val, stt = decide(o, d, ts_list[k])
+                    if stt == "miss" and ert <= 1.0:
                         break
-                if val is None:
-                    val = m.value(p.astype(np.float64)[None])[0]
-                    counts["miss"] += 1
-                if val is None or key != rkey or rkey not in resident:
-                    req[rkey] = req.get(rkey, 0) + 1
-                x = val * 255.0
-                i0 = min(int(math.floor(x)), 254)
-                tt = x - i0
-                rgba = tf[i0].astype(np.float64) * (1 - tt) + tf[i0 + 1].astype(np.float64) * tt
-                a1 = 1.0 - (1.0 - rgba[3]) ** float(step)
-                wgt = (1.0 - A) * a1
-                C += wgt * rgba[:3]
-                A += wgt
-                k += 1
+                    C, A = _bf_composite(C, A, val, tf, step)
+                    k += 1
+                    if A >= ert:
+                        done = True
+                        break
+                if done or k >= nk:
+                    break
+                batch = [val] + [decide(o, d, ts_list[q])[0] for q in range(k + 1, min(k + S, nk))]
+                for v in batch:
+                    C, A = _bf_composite(C, A, v, tf, step)
+                    if A >= ert:
+                        done = True
+                        break
+                k += len(batch)
             img[j, i, :3] = C
             img[j, i, 3] = A
     return img, req, stamps, counts
@@ -260,6 +296,45 @@ def test_brute_force_tiny_volume(seed, frac):
     p = O.make_params(0.5, lod_scale, seed=11, frame_index=3, samples_per_iter=5, mode=O.CACHED)
     img, st = cache.render(cam, tf, p)
     ref, req, stamps, counts = _brute_force_frame(m, dims, B, n_lods, resident, cam, tf, 0.5, lod_scale, 11, 3, 0)
+    np.testing.assert_allclose(img, ref, rtol=0, atol=1e-12)
+    rc = cache.req_count()
+    expect = np.zeros(n_keys, np.uint32)
+    for k, v in req.items():
+        expect[k] = v
+    np.testing.assert_array_equal(rc, expect)
+    lu = cache.last_used()
+    for slot, f in stamps.items():
+        assert lu[slot] == f
+    assert (st["hits"], st["fallbacks"], st["misses"]) == (counts["hit"], counts["fb"], counts["miss"])
+
+
+@pytest.mark.parametrize("seed,frac,S", [(3, 0.4, 4), (4, 0.8, 3), (5, 0.1, 6)])
+def test_brute_force_schedule_with_early_termination(seed, frac, S):
+    # the wavefront schedule with early termination on a non-constant field:
+    # the samples decided past an early termination inside a wavefront step
+    # still request and stamp, the others are never decided
+    dims = (9, 10, 11)
+    B, n_lods = 3, 3
+    m = oracle_inr(configs.ARCH_SMALL, seed, dims=dims)
+    _, nb, off = O.lod_geometry(dims, B, n_lods)
+    n_keys = int(off[-1])
+    rng = np.random.default_rng(seed)
+    keys = np.sort(rng.choice(n_keys, size=int(n_keys * frac), replace=False)).astype(np.int32)
+    cache = O.OracleCache(m, brick=B, n_lods=n_lods, pool_bricks=n_keys, max_requests=0)
+    if keys.size:
+        cache.prefill(keys, stamp=0)
+    pt = cache.page_table()
+    resident = {int(k): int(pt[k]) for k in keys}
+    cam = synth.orbit_camera(synth.PERSPECTIVE, dims, 18.0, 10.0 + 50 * seed, 15.0, 7, 6, fov_y_deg=50.0)
+    tf = synth.tf_random(seed)
+    tf[:, 3] = np.clip(tf[:, 3] * 1.5, 0, 1)
+    lod_scale, thr = 0.12, 0.9
+    p = O.make_params(0.5, lod_scale, seed=11, frame_index=3, ert_threshold=thr, samples_per_iter=S, mode=O.CACHED)
+    img, st = cache.render(cam, tf, p)
+    ref, req, stamps, counts = _brute_force_frame(m, dims, B, n_lods, resident, cam, tf, 0.5, lod_scale, 11, 3, 0,
+                                                  ert=thr, S=S)
+    full, *_ = _brute_force_frame(m, dims, B, n_lods, resident, cam, tf, 0.5, lod_scale, 11, 3, 0)
+    assert (ref[..., 3] >= thr).sum() > 5 and not np.array_equal(ref, full)  # some rays end early
     np.testing.assert_allclose(img, ref, rtol=0, atol=1e-12)
     rc = cache.req_count()
     expect = np.zeros(n_keys, np.uint32)
