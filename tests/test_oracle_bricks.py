@@ -129,6 +129,29 @@ def test_macrocells_bound_lattice_values():
                     assert lo - 1e-6 <= val <= hi + 1e-6
 
 
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_macrocells_of_a_coordinate_field_closed_form(axis):
+    # v = (x_axis + 0.5) / V_axis: a cell's range along its axis is fixed by
+    # the closed region [c N, min((c + 1) N, V - 1)] of the lattice, and does
+    # not depend on the other two cell indices (cells are stored z, y, x)
+    dims = (40, 37, 50)
+    N = 16
+    m = coordinate_inr(dims, axis)
+    mm = m.macrocells(N)
+    M = [(d + N - 1) // N for d in dims]
+    assert mm.shape == (M[2], M[1], M[0], 2)
+    V = dims[axis]
+    c = np.arange(M[axis])
+    lo = (c * N + 0.5) / V
+    hi = (np.minimum((c + 1) * N, V - 1) + 0.5) / V
+    shape = [1, 1, 1]
+    shape[2 - axis] = M[axis]
+    exp_lo = np.broadcast_to(lo.reshape(shape), mm.shape[:3])
+    exp_hi = np.broadcast_to(hi.reshape(shape), mm.shape[:3])
+    np.testing.assert_allclose(mm[..., 0], exp_lo, rtol=0, atol=2e-7)
+    np.testing.assert_allclose(mm[..., 1], exp_hi, rtol=0, atol=2e-7)
+
+
 def test_macrocell_flags_hand_cases():
     tf = synth.tf_ramp()
     tf[:100, 3] = 0.0
