@@ -118,7 +118,10 @@ typedef struct {
  *  ranking       cinr_ranking.
  *  preload_period  pre-load of Section 4.3.4: the LoD floor starts at
  *                n_lods-1 and drops by one every preload_period frames
- *                (0 = off).
+ *                (0 = off); the first preload_period frames (those forced
+ *                to the coarsest LoD) march every ray to the end of the box,
+ *                early ray termination suspended, so that the coarsest
+ *                bricks behind opaque material are requested too.
  *  miss_log_capacity   true-miss records kept per frame for dumps (0 = off).
  *  evict_log_capacity  insertion/eviction records kept for dumps.
  *  keep_request_counts nonzero: keep each frame's per-brick request counts
@@ -254,6 +257,19 @@ typedef struct {
      * in binary32; 0 (or no macro-cells) is Algorithm 2's distance rule.
      * In [0, 1]. */
     float lod_context;
+    /* Optional output (ray marching only, NULL otherwise): where each ray
+     * of the frame ended early, so that a checker can replay the frame's
+     * early terminations sample for sample (the performance mode, with
+     * early ray termination on): int32 [height][width] device memory, borrowed for the
+     * call (for frame graphs: for the graph's lifetime).  The frame writes
+     * for every pixel the sample-grid index k + 1 of the sample k whose
+     * compositing brought the accumulated opacity to ert_threshold (the
+     * grid index the ray would have sampled next; with the adaptive rate,
+     * k + 2^e), or -1 when the ray was not ended early (it left the box, did
+     * not hit it, or early termination was off).  The frames of the
+     * pre-load (frame_index < preload_period of the cache) march without
+     * early termination, so they record -1 everywhere. */
+    int32_t* ert_record;
 } cinr_render_params;
 
 typedef enum { CINR_RAY_MARCH = 0, CINR_PATH_TRACE = 1 } cinr_pipeline;

@@ -70,7 +70,8 @@ class RenderParams(C.Structure):
                 ("adapt_max_exp", C.c_int32), ("waves_per_simd", C.c_int32),
                 ("pipeline", C.c_int32), ("pt_density", C.c_float), ("pt_light_dir", C.c_float * 3),
                 ("pt_light", C.c_float * 3), ("pt_ambient", C.c_float * 3), ("pt_max_bounces", C.c_int32),
-                ("pt_spp", C.c_int32), ("pt_seed", C.c_uint32), ("lod_context", C.c_float)]
+                ("pt_spp", C.c_int32), ("pt_seed", C.c_uint32), ("lod_context", C.c_float),
+                ("ert_record", C.c_void_p)]
 
 
 RAY_MARCH, PATH_TRACE = 0, 1
@@ -91,6 +92,17 @@ def _set_path(p, path):
     p.pt_max_bounces = int(path.get("max_bounces", 1))
     p.pt_spp = int(path.get("spp", 1))
     p.pt_seed = int(path.get("seed", 0)) & 0xFFFFFFFF
+
+
+def _ert_record(rec, cam):
+    """Device pointer of an early-termination record tensor (int32 [H][W] on
+    the GPU), or None."""
+    if rec is None:
+        return None
+    if rec.dtype != torch.int32 or not rec.is_cuda or not rec.is_contiguous() or \
+            tuple(rec.shape) != (cam.height, cam.width):
+        raise ValueError("ert_record must be a contiguous int32 CUDA tensor of shape (height, width)")
+    return rec.data_ptr()
 
 
 def _workspace_size(vol, width, height, samples_per_iter, path):
@@ -420,10 +432,14 @@ class Renderer:
 
     def render(self, volume: Volume, cam, tf, step, lod_scale=0.0, frame_index=0, seed=0, ert_threshold=2.0,
                samples_per_iter=32, mode=CACHED, dtype="f32", cache: Cache = None, out=None, stats=None,
-               pipe_depth=0, xcd_bands=0, adapt_max_exp=0, path=None, lod_context=0.0, waves_per_simd=0):
+               pipe_depth=0, xcd_bands=0, adapt_max_exp=0, path=None, lod_context=0.0, waves_per_simd=0,
+               ert_record=None):
         """path: None for ray marching, else the path tracer's parameters
         (dict: density, light_dir, light, ambient, max_bounces, spp, seed).
-        lod_context: context-aware LoD weight in [0, 1]."""
+        lod_context: context-aware LoD weight in [0, 1].
+        ert_record: optional int32 [H][W] CUDA tensor that receives, per pixel,
+        the sample-grid index just past the sample that ended the ray early
+        (-1: not ended early)."""
         need = _workspace_size(volume, cam.width, cam.height, samples_per_iter, path)
         if self.ws is None or self.ws.numel() < need:
             self.ws = torch.empty(need, dtype=torch.uint8, device=self.device)
@@ -440,6 +456,7 @@ class Renderer:
         p.lod_context = float(lod_context)
         p.waves_per_simd = int(waves_per_simd)
         _set_path(p, path)
+        p.ert_record = _ert_record(ert_record, cam)
         cd = camera_desc(cam)
         st = self.stats if stats is None else stats
         _check(lib().cinr_render_frame(cache.h if cache is not None else None, volume.h, C.byref(cd), _ptr(tf),
@@ -539,9 +556,10 @@ class MultiViewRenderer:
 
     def describe(self, views, step, lod_scale=0.0, frame_index=0, seed=0, ert_threshold=2.0, samples_per_iter=32,
                  dtype="f32", outs=None, pipe_depth=0, xcd_bands=0, adapt_max_exp=0, path=None, lod_context=0.0,
-                 waves_per_simd=0):
+                 waves_per_simd=0, ert_records=None):
         """The cinr_view array of `views` (list of (volume, camera, tf)) and
-        their output images; the TF tensors are kept alive by the renderer."""
+        their output images; the TF tensors are kept alive by the renderer.
+        ert_records: optional list of per-view early-termination records."""
         n = len(views)
         arr = (ViewDesc * n)()
         outs = outs or [None] * n
@@ -568,6 +586,7 @@ class MultiViewRenderer:
             p.lod_context = float(lod_context)
             p.waves_per_simd = int(waves_per_simd)
             _set_path(p, path)
+            p.ert_record = _ert_record(None if ert_records is None else ert_records[i], cam)
             v.d_rgba = outs[i].data_ptr()
             v.d_stats = self.stats[i].data_ptr()
             v.d_workspace = self.ws[i].data_ptr()
@@ -577,10 +596,11 @@ class MultiViewRenderer:
 
     def render(self, cache: Cache, views, step, lod_scale=0.0, frame_index=0, seed=0, ert_threshold=2.0,
                samples_per_iter=32, dtype="f32", outs=None, pipe_depth=0, xcd_bands=0, adapt_max_exp=0, path=None,
-               lod_context=0.0, waves_per_simd=0):
+               lod_context=0.0, waves_per_simd=0, ert_records=None):
         """views: list of (volume, camera, tf); returns the list of RGBA images."""
         arr, outs = self.describe(views, step, lod_scale, frame_index, seed, ert_threshold, samples_per_iter, dtype,
-                                  outs, pipe_depth, xcd_bands, adapt_max_exp, path, lod_context, waves_per_simd)
+                                  outs, pipe_depth, xcd_bands, adapt_max_exp, path, lod_context, waves_per_simd,
+                                  ert_records)
         _check(lib().cinr_render_views(cache.h, len(views), arr, _stream()))
         return outs
 

@@ -723,6 +723,11 @@ FrameVar frame_var(cinr_cache c, const cinr_camera* cam, const cinr_render_param
             if (floor_ < 0) floor_ = 0;
         }
         h.lod_floor = floor_;
+        // the frames that force the coarsest LoD march without early ray
+        // termination, so that the coarsest bricks behind opaque material
+        // are requested too (Sec. 4.3.4: a low-resolution copy of nearly the
+        // whole volume to fall back on)
+        h.preload = c->desc.preload_period > 0 && rp->frame_index < c->desc.preload_period ? 1 : 0;
     }
     return h;
 }
@@ -761,6 +766,7 @@ cinr_status prepare_view(cinr_cache c, cinr_volume v, const cinr_camera* cam, co
                 return fail(CINR_INVALID_ARG, "non-finite light parameters");
         if ((int64_t)cam->width * cam->height >= kMaxPathPixels)
             return fail(CINR_INVALID_ARG, "width*height >= 2^27 for the path tracer");
+        if (rp->ert_record) return fail(CINR_INVALID_ARG, "ert_record is a ray-marching output");
     }
     const bool cached = rp->mode == CINR_CACHED;
     if (cached && !c) return fail(CINR_INVALID_ARG, "the cached mode needs a cache");
@@ -809,6 +815,7 @@ cinr_status prepare_view(cinr_cache c, cinr_volume v, const cinr_camera* cam, co
     f.lod_scale = rp->lod_scale;
     f.ert = rp->ert_threshold;
     f.ert_on = rp->ert_threshold <= 1.0f;
+    f.ert_rec = rp->ert_record;
     f.S = S;
     f.mode = rp->mode;
     // launch shape: given, or tuned online for this image size

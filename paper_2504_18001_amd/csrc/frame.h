@@ -101,7 +101,8 @@ struct FrameVar {
     int32_t frame;
     uint32_t frame_seed;
     int32_t lod_floor;
-    int32_t pad[10];
+    int32_t preload;  // a pre-load frame (Sec. 4.3.4): early ray termination suspended
+    int32_t pad[9];
 };
 static_assert(sizeof(FrameVar) == 128, "FrameVar is copied as 32 words");
 
@@ -144,6 +145,8 @@ struct FrameDev {
     float vm1[3];
     float step, lod_scale, ert;
     int32_t ert_on;
+    int32_t* ert_rec;     // nullable: per pixel, the grid index just past the sample whose
+                          // compositing ended the ray early, -1 if it did not end early
     int32_t S;
     int32_t max_iters;    // bound on the wavefront iterations
     int32_t view_index, n_views;  // this view's place in the frame's views

@@ -76,6 +76,7 @@ struct FrameHot {
     uint32_t seed;
     int32_t lod_floor;
     int32_t frame;
+    int32_t preload;
 };
 
 __device__ inline FrameHot load_hot(const FrameVar* v) {
@@ -85,6 +86,7 @@ __device__ inline FrameHot load_hot(const FrameVar* v) {
     h.seed = v->frame_seed;
     h.lod_floor = v->lod_floor;
     h.frame = v->frame;
+    h.preload = v->preload;
     return h;
 }
 
@@ -255,6 +257,7 @@ struct MarchCold {
     int32_t* touched;
     uint32_t* n_touched;
     int32_t key_base;   // global key of the volume's first brick
+    int32_t* ert_rec;   // nullable: early-termination record (FrameDev::ert_rec)
 };
 using ColdRef = const volatile MarchCold*;
 
@@ -505,6 +508,8 @@ template <int kPipe, bool kLdsFlags, int kFast, bool kAdapt, int kPool, int kWav
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves, 8))) void k_march(FrameDev f, int32_t it, uint32_t n0) {
     static_assert(!kAdapt || kPipe == 1, "the adaptive sampler decides one sample ahead at most");
     const FrameHot hot = load_hot(f.var);  // before any store of this kernel
+    // the pre-load frames march every ray to the end of the box (Sec. 4.3.4)
+    const bool ert_on = f.ert_on && hot.preload == 0;
     __shared__ float4 tfs[256];
     __shared__ LodGeom lgs[kMaxLods];
     __shared__ uint64_t sflags[kLdsFlags ? (kAdapt ? kMaxLdsCells / 8 : kMaxLdsFlagWords) : 1];
@@ -552,6 +557,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves, 
         c.touched = f.touched;
         c.n_touched = f.n_touched;
         c.key_base = f.key_base;
+        c.ert_rec = f.ert_rec;
     }
     __syncthreads();
     const ColdRef cold = &cold_s;
@@ -588,6 +594,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves, 
                 if (it == 0) {
                     float4* rgba = cold->rgba;
                     if (!hit) rgba[pix] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    int32_t* rec = cold->ert_rec;
+                    if (rec) rec[pix] = -1;
                     tally.rays += hit;
                 }
                 has = hit;
@@ -638,7 +646,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves, 
                     if (sr.status != S_SKIP)
                         composite(acc, sr.value, tfs, kAdapt ? __builtin_ldexpf(f.step, sr.e) : f.step);
                     k += kAdapt ? (1 << sr.e) : 1;
-                    if (f.ert_on && acc.w >= f.ert) {
+                    if (ert_on && acc.w >= f.ert) {
+                        int32_t* rec = cold->ert_rec;
+                        if (rec) rec[pix] = k;
                         run = false;
                         break;
                     }
@@ -729,6 +739,7 @@ __global__ __launch_bounds__(kBlock) void k_shade(FrameDev f, int32_t it) {
     const uint32_t n = f.ctr[it].pending;
     int32_t* next = (it & 1) ? f.live0 : f.live1;
     const int32_t S = f.S;
+    const bool ert_on = f.ert_on && f.var->preload == 0;  // suspended in the pre-load frames
     for (uint32_t pi = blockIdx.x * kBlock + threadIdx.x; pi < n; pi += gridDim.x * kBlock) {
         const int32_t pix = f.pend_pix[pi];
         const int32_t nc = f.pend_n[pi];
@@ -743,7 +754,8 @@ __global__ __launch_bounds__(kBlock) void k_shade(FrameDev f, int32_t it) {
             const int32_t e = f.adapt > 0 ? (int32_t)ve[s] : 0;
             if (v >= 0.0f) composite(acc, v, tfs, e ? __builtin_ldexpf(f.step, e) : f.step);
             kg += 1 << e;
-            if (f.ert_on && acc.w >= f.ert) {
+            if (ert_on && acc.w >= f.ert) {
+                if (f.ert_rec) f.ert_rec[pix] = kg;
                 done = true;
                 break;
             }
