@@ -18,7 +18,8 @@
  *  - The caller owns every device buffer (parameters, pool, workspaces,
  *    images, statistics).  The library borrows them for the lifetime of the
  *    object or call and never frees them.  Library-owned memory is limited to
- *    host structs and one small pinned host buffer per volume.
+ *    host structs, one small pinned host buffer per volume, and the fixed
+ *    device array of cinr_render_frame_noalloc.
  *  - `stream` is a hipStream_t (passed as void*); all work is enqueued on it.
  *    render_frame blocks the host until the first marching step of the frame
  *    has finished (it reads back the number of live rays to stop early);
@@ -392,6 +393,34 @@ cinr_status cinr_pt_free_flight(const uint32_t* d_words, int64_t n, float* d_out
 cinr_status cinr_render_frame(cinr_cache cache, cinr_volume vol, const cinr_camera* camera, const float* d_tf,
                               const cinr_render_params* params, float* d_rgba, cinr_frame_stats* d_stats,
                               void* d_workspace, size_t ws_bytes, void* stream);
+
+/* Allocation-free variant of cinr_render_frame, for callers that cannot
+ * allocate memory (code under stream capture, tight serving loops, harnesses
+ * that forbid allocation).  Same arguments, results and cache state machine
+ * as cinr_render_frame, without the render workspace: the frame's scratch
+ * (ray lists, gathered samples, miss records, counters) lives in a fixed
+ * device array of CINR_NOALLOC_SCRATCH_BYTES that the library holds on each
+ * device it runs on until the process ends.
+ *  - No device or pinned-host memory is allocated, no HIP event or stream is
+ *    created.  The pending-ray count is read back with a copy into host
+ *    memory followed by a synchronisation of `stream`, so this call blocks
+ *    until the frame has finished (cinr_render_frame waits only for the first
+ *    marching step).
+ *  - A launch shape left to the tuner (pipe_depth or xcd_bands 0) takes the
+ *    shape already tuned for this image size, else the first candidate; no
+ *    launch-shape trial runs.  Stage timing is not recorded.
+ *  - Returns CINR_OUT_OF_MEMORY, before any launch, when the frame needs more
+ *    than CINR_NOALLOC_SCRATCH_BYTES - 256 bytes of workspace (the size
+ *    cinr_render_workspace_size or cinr_path_workspace_size reports; about
+ *    21 * samples_per_iter + 40 bytes per pixel for ray marching).
+ *  - Every call on one device shares that device's array and leaves its
+ *    contents behind; each frame clears what it needs cleared.  Calls that
+ *    overlap on one device (several host threads, or streams that run
+ *    concurrently) race on the array and must not be issued. */
+#define CINR_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+cinr_status cinr_render_frame_noalloc(cinr_cache cache, cinr_volume vol, const cinr_camera* camera, const float* d_tf,
+                                      const cinr_render_params* params, float* d_rgba, cinr_frame_stats* d_stats,
+                                      void* stream);
 
 /* Optional per-stage GPU timing of cinr_render_frame, for profiling.
  * While enabled, every stage launch of render_frame is bracketed by HIP

@@ -23,6 +23,9 @@ RANK_TIMESTAMP, RANK_PRIORITY = 0, 1
 PERSPECTIVE, ORTHOGRAPHIC = 0, 1
 DUMP_PAGE_TABLE, DUMP_SLOT_OWNER, DUMP_LAST_USED, DUMP_RANK, DUMP_REQ_COUNT = 0, 1, 2, 3, 4
 DUMP_REQUEST_LIST, DUMP_MISS_LIST, DUMP_EVICTION_LOG, DUMP_POOL = 5, 6, 7, 8
+# bytes of the fixed device array of cinr_render_frame_noalloc (the last 256
+# hold its control words)
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 DTYPES = {"f32": F32, "fp32": F32, "bf16": BF16, "f16": F16, "fp16": F16, "bf16x3": BF16X3}
 
@@ -160,6 +163,7 @@ def lib():
             "cinr_cache_prefill": [P, P, i32, i32, i32, P],
             "cinr_render_workspace_size": [P, i32, i32, i32, P],
             "cinr_render_frame": [P, P, P, P, P, P, P, P, sz, P],
+            "cinr_render_frame_noalloc": [P, P, P, P, P, P, P, P],
             "cinr_cache_dump": [P, i32, P, sz, P, P],
             "cinr_last_error": [],
             "cinr_set_timing": [P, i32],
@@ -443,6 +447,33 @@ class Renderer:
         need = _workspace_size(volume, cam.width, cam.height, samples_per_iter, path)
         if self.ws is None or self.ws.numel() < need:
             self.ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        out, tf, p, cd, st = self._call_args(cam, tf, step, lod_scale, frame_index, seed, ert_threshold,
+                                             samples_per_iter, mode, dtype, out, stats, pipe_depth, xcd_bands,
+                                             adapt_max_exp, path, lod_context, waves_per_simd, ert_record)
+        _check(lib().cinr_render_frame(cache.h if cache is not None else None, volume.h, C.byref(cd), _ptr(tf),
+                                       C.byref(p), _ptr(out), _ptr(st), _ptr(self.ws), self.ws.numel(),
+                                       _stream()))
+        self._last_stats = st
+        return out
+
+    def render_noalloc(self, volume: Volume, cam, tf, step, lod_scale=0.0, frame_index=0, seed=0,
+                       ert_threshold=2.0, samples_per_iter=32, mode=CACHED, dtype="f32", cache: Cache = None,
+                       out=None, stats=None, pipe_depth=0, xcd_bands=0, adapt_max_exp=0, path=None,
+                       lod_context=0.0, waves_per_simd=0, ert_record=None):
+        """render() through cinr_render_frame_noalloc: no render workspace, the
+        library's fixed device array instead (NOALLOC_SCRATCH_BYTES); the call
+        returns once the frame has finished.  `out` and the TF must already be
+        CUDA tensors for the call itself to allocate nothing."""
+        out, tf, p, cd, st = self._call_args(cam, tf, step, lod_scale, frame_index, seed, ert_threshold,
+                                             samples_per_iter, mode, dtype, out, stats, pipe_depth, xcd_bands,
+                                             adapt_max_exp, path, lod_context, waves_per_simd, ert_record)
+        _check(lib().cinr_render_frame_noalloc(cache.h if cache is not None else None, volume.h, C.byref(cd),
+                                               _ptr(tf), C.byref(p), _ptr(out), _ptr(st), _stream()))
+        self._last_stats = st
+        return out
+
+    def _call_args(self, cam, tf, step, lod_scale, frame_index, seed, ert_threshold, samples_per_iter, mode, dtype,
+                   out, stats, pipe_depth, xcd_bands, adapt_max_exp, path, lod_context, waves_per_simd, ert_record):
         out = torch.empty((cam.height, cam.width, 4), dtype=torch.float32, device=self.device) if out is None else out
         tf = tf if torch.is_tensor(tf) else torch.as_tensor(np.asarray(tf, np.float32))
         tf = tf.to(device=self.device, dtype=torch.float32).contiguous()
@@ -459,11 +490,7 @@ class Renderer:
         p.ert_record = _ert_record(ert_record, cam)
         cd = camera_desc(cam)
         st = self.stats if stats is None else stats
-        _check(lib().cinr_render_frame(cache.h if cache is not None else None, volume.h, C.byref(cd), _ptr(tf),
-                                       C.byref(p), _ptr(out), _ptr(st), _ptr(self.ws), self.ws.numel(),
-                                       _stream()))
-        self._last_stats = st
-        return out
+        return out, tf, p, cd, st
 
     def last_stats(self):
         v = self._last_stats.cpu().numpy()

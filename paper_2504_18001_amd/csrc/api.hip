@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -733,9 +734,12 @@ FrameVar frame_var(cinr_cache c, const cinr_camera* cam, const cinr_render_param
 }
 
 // Validates one view and fills its frame descriptor.
+// Without `trials`, a view whose launch shape is left to the tuner takes the
+// shape already tuned for its image size, else the first candidate, and no
+// trial is timed.
 cinr_status prepare_view(cinr_cache c, cinr_volume v, const cinr_camera* cam, const float* d_tf,
                          const cinr_render_params* rp, float* d_rgba, cinr_frame_stats* d_stats, void* d_ws,
-                         size_t ws_bytes, ViewRun& r) {
+                         size_t ws_bytes, ViewRun& r, bool trials = true) {
     if (!v || !cam || !d_tf || !rp || !d_rgba) return fail(CINR_INVALID_ARG, "null argument");
     cinr_status st = check_camera(cam);
     if (st) return st;
@@ -821,12 +825,18 @@ cinr_status prepare_view(cinr_cache c, cinr_volume v, const cinr_camera* cam, co
     // launch shape: given, or tuned online for this image size
     if (rp->pipe_depth == 0 || rp->xcd_bands == 0) {
         const uint64_t key = ((uint64_t)(uint32_t)cam->width << 32) | (uint32_t)cam->height;
-        r.tuner = &v->tuners[key];
-        const int cand = r.tuner->cand();
+        int cand = 0;
+        if (trials) {
+            r.tuner = &v->tuners[key];
+            cand = r.tuner->cand();
+            r.timing_trial = r.tuner->best < 0;
+        } else {
+            const auto known = v->tuners.find(key);
+            if (known != v->tuners.end() && known->second.best >= 0) cand = known->second.best;
+        }
         f.pipe = rp->pipe_depth > 0 ? rp->pipe_depth : SamplerTuner::kPipe[cand];
         f.xcd_bands = rp->xcd_bands > 0 ? rp->xcd_bands : SamplerTuner::kBands[cand];
         f.waves = rp->waves_per_simd > 0 ? rp->waves_per_simd : SamplerTuner::kWaves[cand];
-        r.timing_trial = r.tuner->best < 0;
     } else {
         f.pipe = rp->pipe_depth;
         f.xcd_bands = rp->xcd_bands;
@@ -947,7 +957,7 @@ cinr_status view_march0(ViewRun& r, hipStream_t s) {
 
 // After the pending count of iteration it is known: stop, or infer the misses,
 // composite the gathered steps and march the next iteration.
-cinr_status view_continue(ViewRun& r, uint32_t pending, hipStream_t s) {
+cinr_status view_continue(ViewRun& r, uint32_t pending, Timing& tm, hipStream_t s) {
     const int it = r.n_iters - 1;
     r.queued = pending;
     if (pending == 0 || r.n_iters >= r.max_iters) {
@@ -956,15 +966,15 @@ cinr_status view_continue(ViewRun& r, uint32_t pending, hipStream_t s) {
     }
     cinr_volume v = r.v;
     {
-        StageTimer st_(v->timing, s, CINR_STAGE_INFER);
+        StageTimer st_(tm, s, CINR_STAGE_INFER);
         HIP_TRY(inr_infer_misses(v->m, r.f.miss_rec, &r.f.ctr[it].misses, r.npix * r.f.S, r.f.vals, r.prec, s));
     }
     {
-        StageTimer st_(v->timing, s, CINR_STAGE_SHADE);
+        StageTimer st_(tm, s, CINR_STAGE_SHADE);
         HIP_TRY(launch_shade(r.f, it, r.npix, s));
     }
     {
-        StageTimer st_(v->timing, s, CINR_STAGE_MARCH);
+        StageTimer st_(tm, s, CINR_STAGE_MARCH);
         HIP_TRY(launch_march(r.f, it + 1, r.queued, s));
     }
     r.n_iters += 1;
@@ -1064,7 +1074,7 @@ cinr_status continue_views(cinr_cache c, std::vector<ViewRun>& runs, bool side, 
             const uint32_t pending = have ? known[i] : ((volatile uint32_t*)pinned)[i];
             cinr_status st = tuner_collect(runs[i], pending);
             if (st) return st;
-            st = view_continue(runs[i], pending, runs[i].st);
+            st = view_continue(runs[i], pending, runs[i].v->timing, runs[i].st);
             if (st) return st;
         }
     }
@@ -1278,6 +1288,128 @@ extern "C" cinr_status cinr_render_frame(cinr_cache c, cinr_volume v, const cinr
     cinr_status st = prepare_view(c, v, cam, d_tf, rp, d_rgba, d_stats, d_ws, ws_bytes, runs[0]);
     if (st) return st;
     return render_frame_views(rp->mode == CINR_CACHED ? c : nullptr, runs, v->timing, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// Frames without allocation
+// ---------------------------------------------------------------------------
+
+// Fixed device array behind cinr_render_frame_noalloc.  Each device holds its
+// own copy at its own address; host code takes that address from
+// hipGetSymbolAddress (once per device) and never uses the name itself as a
+// device pointer.
+static __device__ __align__(256) unsigned char scratch[CINR_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+// the render workspace, then 256 bytes of control words (the pending-count
+// hand-over of the first march)
+constexpr size_t kNoAllocWs = CINR_NOALLOC_SCRATCH_BYTES - 256;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch[kMaxDevices] = {};
+
+// Device address of the fixed array on the current device.
+cinr_status noalloc_scratch(unsigned char** out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(CINR_UNSUPPORTED, "device %d (at most %d devices)", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(CINR_HIP_ERROR, "the fixed scratch array has no device address");
+        g_scratch[dev] = (unsigned char*)p;
+    }
+    *out = g_scratch[dev];
+    return CINR_OK;
+}
+
+// A device word on the host, in stream order (the copy goes to pageable
+// memory; the stream is synchronised).
+cinr_status read_word(const uint32_t* d, uint32_t* h, hipStream_t s) {
+    HIP_TRY(hipMemcpyAsync(h, d, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return CINR_OK;
+}
+
+}  // namespace
+
+extern "C" cinr_status cinr_render_frame_noalloc(cinr_cache c, cinr_volume v, const cinr_camera* cam,
+                                                 const float* d_tf, const cinr_render_params* rp, float* d_rgba,
+                                                 cinr_frame_stats* d_stats, void* stream) {
+    if (!v || !cam || !rp) return fail(CINR_INVALID_ARG, "null argument");
+    if (cam->width < 1 || cam->height < 1) return fail(CINR_INVALID_ARG, "empty image");
+    if (rp->samples_per_iter < 1 || rp->samples_per_iter > 64)
+        return fail(CINR_INVALID_ARG, "samples_per_iter must be in [1, 64]");
+    const int64_t npix = (int64_t)cam->width * cam->height;
+    if (npix * rp->samples_per_iter > 0xFFFFFFFFll)
+        return fail(CINR_INVALID_ARG, "width*height*samples_per_iter >= 2^32");
+    const size_t need = render_layout(npix, rp->samples_per_iter, v->n_cells, rp->pipeline == CINR_PATH_TRACE,
+                                      nullptr, nullptr);
+    if (need > kNoAllocWs)
+        return fail(CINR_OUT_OF_MEMORY, "the frame needs %zu bytes of workspace; the fixed scratch array holds %zu "
+                    "(reduce width*height or samples_per_iter)", need, kNoAllocWs);
+    unsigned char* base = nullptr;
+    cinr_status st = noalloc_scratch(&base);
+    if (st) return st;
+    ViewRun r;
+    st = prepare_view(c, v, cam, d_tf, rp, d_rgba, d_stats, base, kNoAllocWs, r, false);
+    if (st) return st;
+    cinr_cache cc = rp->mode == CINR_CACHED ? c : nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t* word = reinterpret_cast<uint32_t*>(base + kNoAllocWs);
+    Timing none;
+    r.st = s;
+    // frame values from the launch arguments instead of a pinned block
+    HIP_TRY(launch_store_var(r.hv, r.L.var, s));
+    r.f.var_src = nullptr;
+    // a ray-marched view's first march hands its pending count over to the
+    // control word and the frame-end gate; the path tracer's goes through
+    // the gather launch
+    const bool fused = !r.f.path.on;
+    if (fused) {
+        r.f.gather_host = word;
+        r.f.gather_gate = r.L.gate;
+        r.f.exit_ticket = r.L.ticket;
+    }
+    const int32_t n_ctr = (int32_t)std::min<int64_t>(r.max_iters + 2, kMaxIters + 2);
+    HIP_TRY(launch_frame_begin(r.f, n_ctr, v->desc.d_macrocells, v->n_cells, cc ? cc->c.ctr : nullptr, s));
+    if (cc && cc->c.last_req) HIP_TRY(launch_clear_last_req(cc->c, cc->g.n_keys, s));
+    HIP_TRY(launch_march(r.f, 0, r.queued, s));
+    r.n_iters = 1;
+    if (fused) {
+        r.f.gather_host = r.f.gather_gate = r.f.exit_ticket = nullptr;
+    } else {
+        const FrameDev* fp = &r.f;
+        HIP_TRY(launch_pending_gather(&fp, 1, word, r.L.gate, s));
+    }
+    // the frame end, gated on the device (nothing runs while rays pend)
+    const bool lru = cc && lru_pass_needed(cc);
+    auto frame_end = [&](const uint32_t* gate) -> cinr_status {
+        if (cc) return cache_end_frame(cc, r.prec, lru, none, gate, s);
+        HIP_TRY(launch_frame_end(r.f, (int)r.max_iters, nullptr, true, gate, s));
+        return CINR_OK;
+    };
+    st = frame_end(r.L.gate);
+    if (st) return st;
+    uint32_t pending = 0;
+    st = read_word(word, &pending, s);
+    if (st) return st;
+    if (pending != 0u) {
+        // true misses: the remaining iterations, then the frame end
+        for (;;) {
+            st = view_continue(r, pending, none, s);
+            if (st) return st;
+            if (!r.live) break;
+            st = read_word(&r.f.ctr[r.n_iters - 1].pending, &pending, s);
+            if (st) return st;
+        }
+        st = frame_end(nullptr);
+        if (st) return st;
+    }
+    if (cc) note_insertions(cc);
+    return CINR_OK;
 }
 
 namespace {

@@ -140,7 +140,7 @@ struct PtDev {
 struct FrameDev {
     int32_t W, H;  // image size (fixed for a view; the camera itself is in *var)
     FrameVar* var;            // device copy of the frame's values
-    const FrameVar* var_src;  // host block (pinned) read by k_frame_begin
+    const FrameVar* var_src;  // host block (pinned) read by k_frame_begin; null: `var` is already stored
     int32_t dims[3];
     float vm1[3];
     float step, lod_scale, ert;
@@ -293,6 +293,7 @@ hipError_t launch_frame_begin(const FrameDev& f, int32_t n_iter_ctr, const float
 hipError_t launch_march(const FrameDev& f, int it, int64_t max_rays, hipStream_t s);
 hipError_t launch_shade(const FrameDev& f, int it, int64_t cap_rays, hipStream_t s);
 hipError_t launch_pt_free_flight(const uint32_t* words, int64_t n, float* out, hipStream_t s);
+hipError_t launch_store_var(const FrameVar& v, FrameVar* dst, hipStream_t s);
 // `gate` (nullable) on the frame-end launches: they do nothing unless *gate is
 // non-zero, which k_pending_gather sets when no view has a ray pending after
 // its first march.  The end of a frame can so be queued before the host has

@@ -391,10 +391,11 @@ __global__ __launch_bounds__(kBlock) void k_frame_begin(FrameDev f, int32_t n_ct
     if (lane_id() == 0) nz[threadIdx.x >> 6] = m;
     __syncthreads();
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    // the frame's camera, index and LoD seed: host block -> device
-    if (t < 32) reinterpret_cast<uint32_t*>(f.var)[t] = reinterpret_cast<const uint32_t*>(f.var_src)[t];
+    // the frame's camera, index and LoD seed: host block -> device (without a
+    // host block, k_store_var stored them before this launch)
+    if (f.var_src && t < 32) reinterpret_cast<uint32_t*>(f.var)[t] = reinterpret_cast<const uint32_t*>(f.var_src)[t];
     if (t == 0 && cctr) {
-        cctr->frame = f.var_src->frame;
+        cctr->frame = f.var_src ? f.var_src->frame : f.var->frame;
         cctr->n_views = (uint32_t)f.n_views;
     }
     if (t == 0 && f.view_table) f.view_table[f.view_index] = ViewEnd{f.stats, f.ctr, f.max_iters, 0};
@@ -1322,6 +1323,17 @@ __global__ void k_pt_free_flight(const uint32_t* words, int64_t n, float* out) {
 hipError_t launch_pt_free_flight(const uint32_t* words, int64_t n, float* out, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_pt_free_flight, dim3(blocks_for(n, 4096)), dim3(kBlock), 0, s, words, n, out);
+    return hipGetLastError();
+}
+
+// A view's per-frame values stored from the launch's arguments (frames that
+// use no pinned host block).
+__global__ void k_store_var(FrameVar v, FrameVar* dst) {
+    if (threadIdx.x == 0) *dst = v;
+}
+
+hipError_t launch_store_var(const FrameVar& v, FrameVar* dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_store_var, dim3(1), dim3(64), 0, s, v, dst);
     return hipGetLastError();
 }
 

@@ -204,6 +204,31 @@ def test_render_workspace_covers_the_per_ray_buffers():
         L.cinr_destroy_volume(h)
 
 
+def test_noalloc_frame_checks_its_arguments_before_any_device_work():
+    """The allocation-free frame call rejects null arguments and frames whose
+    workspace exceeds its fixed device array (before touching the device)."""
+    L = cinr.lib()
+    assert L.cinr_render_frame_noalloc(None, None, None, None, None, None, None, None) == INVALID_ARG
+    _, h, _ = fake_volume(configs.ARCH_512, macro_cell=16)
+    try:
+        cam = cinr.CameraDesc()
+        cam.projection, cam.width, cam.height = cinr.PERSPECTIVE, 1920, 1080
+        p = cinr.RenderParams()
+        p.step, p.samples_per_iter, p.mode = 0.5, 8, cinr.UNCACHED_DIRECT
+        rc = L.cinr_render_frame_noalloc(None, h, C.byref(cam), C.c_void_p(0x40000), C.byref(p),
+                                         C.c_void_p(0x50000), None, None)
+        assert rc == -2  # CINR_OUT_OF_MEMORY
+        assert b"fixed scratch array" in L.cinr_last_error()
+        b = C.c_size_t()
+        assert L.cinr_render_workspace_size(h, 1920, 1080, 8, C.byref(b)) == OK
+        assert b.value > cinr.NOALLOC_SCRATCH_BYTES
+        p.samples_per_iter = 0
+        assert L.cinr_render_frame_noalloc(None, h, C.byref(cam), C.c_void_p(0x40000), C.byref(p),
+                                           C.c_void_p(0x50000), None, None) == INVALID_ARG
+    finally:
+        L.cinr_destroy_volume(h)
+
+
 def test_timing_modes():
     _, h, _ = fake_volume(configs.ARCH_SMALL)
     L = cinr.lib()
