@@ -1119,11 +1119,13 @@ static int32_t sample_count(float ts, float te, float step) {
 /* Early termination after a composited sample; `knext` is the grid index of
  * the ray's next sample.  Without a replay: A >= threshold.  With a replay:
  * exactly where the checked renderer ended the ray, and a replayed end that
- * the oracle's own opacity contradicts by more than 1e-4 is counted. */
+ * the oracle's own opacity contradicts by more than the slack (the checked
+ * renderer's allowed value error, 1e-4 unless given) is counted. */
 static int ert_end(const orc_params* P, thread_acc* ta, int32_t pix, int32_t knext, double A, double thr) {
     if (!P->ert_replay) return A >= thr;
+    const double slack = P->ert_slack > 0.0 ? P->ert_slack : 1e-4;
     const int end = P->ert_replay[pix] == knext;
-    if (end ? A < thr - 1e-4 : A >= thr + 1e-4) ta->ert_violations++;
+    if (end ? A < thr - slack : A >= thr + slack) ta->ert_violations++;
     return end;
 }
 

@@ -89,12 +89,16 @@ typedef struct {
      * each ray exactly there instead of testing its own opacity, so that every
      * decision of the frame follows the same samples, and counts in
      * orc_stats.ert_violations the replayed ends that its own opacity does not
-     * justify: an end where A < threshold - 1e-4, or a sample composited
-     * before it where A >= threshold + 1e-4.  NULL: the oracle's own test. */
+     * justify: an end where A < threshold - ert_slack, or a sample composited
+     * before it where A >= threshold + ert_slack.  NULL: the oracle's own
+     * test. */
     const int32_t* ert_replay;
     /* Optional output in the same format: for every pixel, the grid index
      * just past the sample whose compositing ended the ray early, or -1. */
     int32_t* ert_record;
+    /* Opacity margin of the replay check: the value error the checked
+     * renderer is allowed (its image tolerance); 0 takes 1e-4. */
+    double ert_slack;
 } orc_params;
 
 /* Events (Philox draws) a pixel may use per frame in path tracing; a pixel

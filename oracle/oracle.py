@@ -43,7 +43,7 @@ class Params(C.Structure):
                 ("pipeline", C.c_int32), ("pt_density", C.c_float), ("pt_light_dir", C.c_float * 3),
                 ("pt_light", C.c_float * 3), ("pt_ambient", C.c_float * 3), ("pt_max_bounces", C.c_int32),
                 ("pt_spp", C.c_int32), ("pt_seed", C.c_uint32), ("lod_context", C.c_float),
-                ("ert_replay", C.c_void_p), ("ert_record", C.c_void_p)]
+                ("ert_replay", C.c_void_p), ("ert_record", C.c_void_p), ("ert_slack", C.c_double)]
 
 
 class CacheDesc(C.Structure):
@@ -378,7 +378,8 @@ def philox4x32_10(ctr, key):
 
 
 def make_params(step, lod_scale, seed=0, frame_index=0, ert_threshold=2.0, samples_per_iter=8, mode=CACHED,
-                macro_cell=0, macro_minmax=None, adapt_max_exp=-1, path=None, lod_context=0.0, ert_replay=None):
+                macro_cell=0, macro_minmax=None, adapt_max_exp=-1, path=None, lod_context=0.0, ert_replay=None,
+                ert_slack=1e-4):
     """adapt_max_exp: adaptive sampling rate with steps of up to 2^E sample
     spacings (Section 5.2); -1 (or 0) for the fixed step.  path: None for ray
     marching, else a dict of path-tracing parameters (density, light_dir,
@@ -406,6 +407,9 @@ def make_params(step, lod_scale, seed=0, frame_index=0, ert_threshold=2.0, sampl
     # termination in the renderer being checked, -1 where it did not end early
     p._replay = None if ert_replay is None else np.ascontiguousarray(ert_replay, np.int32)
     p.ert_replay = p._replay.ctypes.data if p._replay is not None else None
+    # opacity margin of the replay check: the checked renderer's value
+    # tolerance (its reduced-precision MLP may move an opacity by that much)
+    p.ert_slack = ert_slack
     p._record = None
     return p
 

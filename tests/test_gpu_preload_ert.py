@@ -14,8 +14,10 @@ sample of the frame in the same places, so all cache state (page table,
 owners, stamps, ranks, request counts, request lists, miss lists, eviction
 log) is compared bit for bit, the images within the value tolerance, and the
 oracle counts the replayed ends its own opacity does not justify
-(A < threshold - 1e-4 at an end, A >= threshold + 1e-4 before it): none may
-occur.
+(A < threshold - slack at an end, A >= threshold + slack before it): none may
+occur.  The slack is 1e-4 for the FP32 MLP and the image tolerance (8e-3)
+for reduced precision, whose values, and so opacities, may differ by that
+much.
 """
 import numpy as np
 import pytest
@@ -70,7 +72,8 @@ def _performance_sequence(w, frames, width, height, dims=None, pool=None, max_re
         assert rec.min() >= -1, "every pixel is written"
         p = O.make_params(w.step, w.lod_scale, seed=w.seed, frame_index=f, ert_threshold=ert,
                           samples_per_iter=w.samples_per_iter, mode=O.CACHED, macro_cell=w.macro_cell if macro else 0,
-                          macro_minmax=mm, adapt_max_exp=adapt if adapt > 0 else -1, ert_replay=rec)
+                          macro_minmax=mm, adapt_max_exp=adapt if adapt > 0 else -1, ert_replay=rec,
+                          ert_slack=1e-4 if dtype == "f32" else TOL[dtype])
         ref, rst = oc.render(cam, tf, p)
         err = np.abs(img - ref).max()
         n_end = int((rec >= 0).sum())
@@ -270,7 +273,10 @@ def test_fullsize_performance_mode_replay_bit_exact(own_scene):
     _, ost = oc.render(cam, tf, p)
     print(f"ended early {(g >= 0).sum()}, skipped {st['skipped']}, pixels max abs {err:.2e}; gpu {st}; oracle {ost}")
     assert ost["ert_violations"] == 0
-    assert (g >= 0).sum() > 10000 and st["skipped"] > 0
+    # the bench's TFs give every cell a positive opacity somewhere in its
+    # range, so its frames skip no sample; the skip counts are compared below
+    # all the same (the test with a windowed TF follows)
+    assert (g >= 0).sum() > 10000
     for k in ("rays", "samples", "hits", "fallbacks", "misses", "skipped", "requested", "selected"):
         assert st[k] == ost[k], (k, st[k], ost[k])
     np.testing.assert_array_equal(cache.dump(cinr.DUMP_REQ_COUNT), oc.req_count())
@@ -278,3 +284,24 @@ def test_fullsize_performance_mode_replay_bit_exact(own_scene):
     np.testing.assert_array_equal(cache.dump(cinr.DUMP_PAGE_TABLE), oc.page_table())
     np.testing.assert_array_equal(cache.dump(cinr.DUMP_LAST_USED), oc.last_used())
     assert err <= 2e-3
+    # the next frame with a TF transparent below row 200: cells whose value
+    # range stays under it are skipped, and the skip decisions of the INR's
+    # own macro-cells are compared with the oracle's, with every request and
+    # stamp they change
+    f = 13
+    cam, tf = W.camera(f), synth.tf_window(200, 255)
+    img = r.render(vol, cam, tf, W.step, W.lod_scale, frame_index=f, seed=W.seed, ert_threshold=ERT,
+                   samples_per_iter=W.samples_per_iter, mode=cinr.CACHED, dtype="f32", cache=cache, ert_record=rec)
+    st = r.last_stats()
+    g = rec.cpu().numpy()
+    p = O.make_params(W.step, W.lod_scale, seed=W.seed, frame_index=f, ert_threshold=ERT,
+                      samples_per_iter=W.samples_per_iter, mode=O.CACHED, macro_cell=W.macro_cell, macro_minmax=mm,
+                      ert_replay=g)
+    _, ost = oc.render(cam, tf, p)
+    print(f"windowed TF: skipped {st['skipped']}; gpu {st}; oracle {ost}")
+    assert ost["ert_violations"] == 0
+    for k in ("rays", "samples", "hits", "fallbacks", "misses", "skipped", "requested", "selected"):
+        assert st[k] == ost[k], (k, st[k], ost[k])
+    np.testing.assert_array_equal(cache.dump(cinr.DUMP_REQ_COUNT), oc.req_count())
+    np.testing.assert_array_equal(cache.dump(cinr.DUMP_PAGE_TABLE), oc.page_table())
+    np.testing.assert_array_equal(cache.dump(cinr.DUMP_LAST_USED), oc.last_used())
