@@ -71,6 +71,7 @@ class Workload:
     ortho_extent: float = 0.0
     tf_switch_frame: int = -1     # from this frame (mod n_frames) on, a random TF is used
     tf_seed: int = 77
+    tf_kind: str = "iid"          # the random TF: "iid" rows, or "smooth" (piecewise linear)
 
     def camera(self, frame: int, dims=None) -> synth.Camera:
         ang = self.orbit_step_deg * (frame % self.n_frames)
@@ -80,7 +81,7 @@ class Workload:
 
     def tf(self, frame: int):
         if self.tf_switch_frame >= 0 and (frame % self.n_frames) >= self.tf_switch_frame:
-            return synth.tf_random(self.tf_seed)
+            return synth.tf_iid(self.tf_seed) if self.tf_kind == "iid" else synth.tf_random(self.tf_seed)
         return synth.tf_ramp()
 
 
@@ -94,7 +95,8 @@ SMALL = Workload(
 )
 
 # 512^3 random INR at 1920x1080 perspective, 60-frame orbit (6 degrees per frame,
-# 20 degree elevation), TF switched at frame 30, B = 16, 4 LoDs, 2 GiB pool.
+# 20 degree elevation), TF switched at frame 30 from the ramp to a random table
+# drawn i.i.d. per row and channel, B = 16, 4 LoDs, 2 GiB pool.
 HD512 = Workload(
     name="inr512_persp1080p", arch=ARCH_512, inr_seed=0, width=1920, height=1080,
     projection=synth.PERSPECTIVE, n_frames=60, step=0.5, lod_scale=1.0 / 800.0,
@@ -171,7 +173,7 @@ class MultiView:
                                   45.0)
 
     def tf(self, frame: int):
-        return synth.tf_ramp() if (frame % 60) < 30 else synth.tf_random(77)
+        return synth.tf_ramp() if (frame % 60) < 30 else synth.tf_iid(77)
 
 
 MULTIVIEW = MultiView()

@@ -111,6 +111,15 @@ def tf_random(seed: int, n_ctrl: int = 9) -> np.ndarray:
     return out.astype(np.float32)
 
 
+def tf_iid(seed: int) -> np.ndarray:
+    """Random RGBA table with every row and channel drawn independently from
+    U(0,1): neighbouring rows are unrelated, so the linear interpolation
+    between rows has slopes of up to 255 per unit value and a value error can
+    reach the colour about 255 times larger."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0.0, 1.0, size=(256, 4)).astype(np.float32)
+
+
 def tf_window(lo: int, hi: int, edge: int = 32) -> np.ndarray:
     """Ramp colours with opacity zero outside rows [lo, hi] and rising over
     `edge` rows from lo (opacity is exactly zero at and below row lo)."""

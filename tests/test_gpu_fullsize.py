@@ -157,17 +157,40 @@ def test_prefilled_fullsize_parity_mode_bit_exact_requests(scene):
     np.testing.assert_array_equal(cache.dump(cinr.DUMP_LAST_USED), oc.last_used())
 
 
-# Max abs RGBA bound per MLP precision on a frame of the random transfer
-# function (piecewise linear, slope up to 8 per unit value).  Plain BF16
-# carries 8 significant bits per operand (value errors up to about 6e-3), so
-# this transfer function amplifies them beyond the 8e-3 image bound; its
-# PSNR stays far above 45 dB.  Split BF16 and FP16 meet the bound.
-MAXABS = {"bf16x3": 8e-3, "f16": 8e-3, "bf16": 2.5e-2}
+# Precision study (the bench configuration, a prefilled cache, frame 40 of
+# the orbit): max abs RGBA against the FP64 oracle within 2e-3 for the FP32
+# MLP and 8e-3 for reduced precision, PSNR >= 45 dB.  Two random transfer
+# functions: the scope's i.i.d. table (every row and channel drawn
+# independently: interpolation slopes up to 255 per unit value, so a value
+# error reaches the colour up to 255 times larger) and a smooth one
+# (piecewise linear through 9 random rows, slopes up to 8).  FP32 and split
+# BF16 meet the bounds on both; FP16 (11 significant bits) only on the smooth
+# table; plain BF16 (8 significant bits) on neither (xfail, with the errors
+# measured on the GPU).
+MAXABS = {"f32": 2e-3, "bf16x3": 8e-3, "f16": 8e-3, "bf16": 8e-3}
+_XF = {
+    ("bf16", "smooth"): "plain BF16 on the smooth TF: max abs 1.9e-2 > 8e-3 (PSNR 61 dB)",
+    ("f16", "iid"): "FP16 on the i.i.d. TF: max abs 5.1e-2 > 8e-3 (PSNR 51 dB)",
+    ("bf16", "iid"): "plain BF16 on the i.i.d. TF: max abs 0.35 > 8e-3, PSNR 33 dB < 45 dB",
+}
 
 
-@pytest.mark.parametrize("dtype,pool_dtype", [("bf16x3", "f32"), ("f16", "f32"), ("bf16", "f32"), ("bf16x3", "f16"),
-                                              ("bf16x3", "mixed")])
-def test_prefilled_fullsize_bench_configuration_pixels(scene, dtype, pool_dtype):
+def _cases():
+    out = []
+    for tf_kind in ("iid", "smooth"):
+        for dtype in ("f32", "bf16x3", "f16", "bf16"):
+            why = _XF.get((dtype, tf_kind))
+            marks = [pytest.mark.xfail(strict=True, reason=why)] if why else []
+            out.append(pytest.param(dtype, "f32", tf_kind, marks=marks, id=f"{dtype}-f32pool-{tf_kind}"))
+    # the binary16 and mixed pools (their rounding, 2^-12, would be amplified
+    # as much as an MLP error by the i.i.d. table): split BF16, smooth TF
+    out.append(pytest.param("bf16x3", "f16", "smooth", id="bf16x3-f16pool-smooth"))
+    out.append(pytest.param("bf16x3", "mixed", "smooth", id="bf16x3-mixedpool-smooth"))
+    return out
+
+
+@pytest.mark.parametrize("dtype,pool_dtype,tf_kind", _cases())
+def test_prefilled_fullsize_bench_configuration_pixels(scene, dtype, pool_dtype, tf_kind):
     from oracle import oracle as O
     from paper_2504_18001_amd import cinr
     vol, m, mm = scene
@@ -181,7 +204,8 @@ def test_prefilled_fullsize_bench_configuration_pixels(scene, dtype, pool_dtype)
         np.testing.assert_array_equal(cache.dump(cinr.DUMP_SLOT_OWNER), oc.owner())
         assert (oc.owner()[:W.cache.pool_bricks // 2] >= 0).any() and (oc.owner()[W.cache.pool_bricks // 2:] >= 0).any()
     f = 40  # random transfer function part of the orbit
-    cam, tf = W.camera(f), W.tf(f)
+    cam = W.camera(f)
+    tf = synth.tf_iid(W.tf_seed) if tf_kind == "iid" else synth.tf_random(W.tf_seed)
     r = cinr.Renderer()
     img = r.render(vol, cam, tf, W.step, W.lod_scale, frame_index=f, seed=W.seed, ert_threshold=W.ert_threshold,
                    samples_per_iter=W.samples_per_iter, mode=cinr.CACHED, dtype=dtype, cache=cache)
@@ -193,7 +217,8 @@ def test_prefilled_fullsize_bench_configuration_pixels(scene, dtype, pool_dtype)
     d = np.abs(got - ref)
     mse = float((d ** 2).mean())
     psnr = 10 * np.log10(1.0 / mse) if mse > 0 else float("inf")
-    print(f"prefilled {dtype} MLP, {pool_dtype} pool, bench-configuration pixels: max abs", d.max(), "PSNR", psnr)
+    print(f"prefilled {dtype} MLP, {pool_dtype} pool, {tf_kind} TF, bench-configuration pixels: max abs", d.max(),
+          "PSNR", psnr)
     assert d.max() <= MAXABS[dtype]
     assert psnr >= 45.0
 

@@ -4,9 +4,13 @@
 Fourier modes, amplitude |k|^-5/3), judged
 by PSNR over all 1024^3 lattice points against the explicit grid, and
 rendered at 1080p against the explicit-grid source with the same cached
-renderer.  The gain is measured against the untrained (random-init) INR;
-the equal-memory explicit baseline (256^3 box-downsampled grid, trilinear
-upsampling) is reported beside it."""
+renderer.  The gain is measured against the untrained (random-init) INR and
+against the equal-memory explicit baseline (256^3 box-downsampled grid,
+trilinear upsampling, 64 MB like the INR's parameters).  The scope asks the
+trained INR to beat both; on this band-limited field (modes up to |k| = 128,
+exactly what a 256^3 grid resolves) it does not within 2000 steps, and that
+comparison stays in the suite as a strict expected failure naming the
+measured numbers."""
 import json
 import math
 
@@ -66,7 +70,8 @@ def render_frames(vol, w, frames, dims):
     return img
 
 
-def test_trained_inr_gains_over_the_untrained_one_at_full_size():
+@pytest.fixture(scope="module")
+def learned():
     from paper_2504_18001_amd import cinr
     arch = configs.ARCH_LEARN
     grid = synth.fourier_field(V, synth.fourier_modes(512, 128, seed=0), device="cuda")
@@ -98,6 +103,16 @@ def test_trained_inr_gains_over_the_untrained_one_at_full_size():
            "psnr_grid256_equal_memory_db": round(p_grid256, 2), "render_1080p_psnr_vs_grid_db": round(p_render, 2),
            "train_ms_per_step": round(ms, 3), "final_batch_loss": loss.item()}
     print(json.dumps(rep))
-    assert p_trained > p_random + 30.0
-    assert p_trained > 45.0
-    assert p_render > 35.0
+    return rep
+
+
+def test_trained_inr_gains_over_the_untrained_one_at_full_size(learned):
+    assert learned["psnr_trained_db"] > learned["psnr_random_init_db"] + 30.0
+    assert learned["psnr_trained_db"] > 45.0
+    assert learned["render_1080p_psnr_vs_grid_db"] > 35.0
+
+
+@pytest.mark.xfail(strict=True, reason="unmet: the trained INR reaches 52.2-52.5 dB over the 1024^3 lattice, the "
+                                       "equal-memory 256^3 grid 61.0 dB")
+def test_trained_inr_beats_the_equal_memory_grid(learned):
+    assert learned["psnr_trained_db"] > learned["psnr_grid256_equal_memory_db"]
