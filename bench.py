@@ -84,12 +84,13 @@ def make_scene(w, dtype_decode="bf16"):
     return vol, cams, tfs
 
 
-def new_cache(vol, w, pool_dtype="f32", pool_bricks=None, f16_lods=0, pool_bricks_f16=0):
+def new_cache(vol, w, pool_dtype="f32", pool_bricks=None, f16_lods=0, pool_bricks_f16=0, virtual_pt=False):
     from paper_2504_18001_amd import cinr
     cs = w.cache
     return cinr.Cache(vol, cs.brick, cs.n_lods, pool_bricks or cs.pool_bricks, cs.max_requests,
                       rank_window=cs.rank_window, ranking=cs.ranking, preload_period=cs.preload_period,
-                      pool_dtype=pool_dtype, f16_lods=f16_lods, pool_bricks_f16=pool_bricks_f16)
+                      pool_dtype=pool_dtype, f16_lods=f16_lods, pool_bricks_f16=pool_bricks_f16,
+                      virtual_page_table=virtual_pt)
 
 
 def run_frames(r, vol, cams, tfs, w, frames, mode, dtype, cache, stats=None, out=None):
@@ -125,6 +126,36 @@ def decode_throughput(vol, w, dtype, n_bricks, reps=5):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
     return n_bricks / (ms * 1e-3), ms
+
+
+def virtual_pt_leg(vol, cams, tfs, w, Wm, K, dtype, ref_img):
+    """The headline sequence through the two-level page table (a directory
+    entry per 8^3 bricks, blocks of 512 entries): frame rate and sampler time
+    against the flat table's, and the image, which must be identical."""
+    import numpy as np
+    import torch
+    from paper_2504_18001_amd import cinr
+    c = new_cache(vol, w, virtual_pt=True)
+    r = cinr.Renderer()
+    out = torch.empty((w.height, w.width, 4), dtype=torch.float32, device="cuda")
+    run_frames(r, vol, cams, tfs, w, range(Wm), cinr.CACHED, dtype, c, out=out)
+    torch.cuda.synchronize()
+    vol.set_timing(True, march_only=True)
+    t0 = time.perf_counter()
+    run_frames(r, vol, cams, tfs, w, range(Wm, Wm + K), cinr.CACHED, dtype, c, out=out)
+    torch.cuda.synchronize()
+    fps = K / (time.perf_counter() - t0)
+    vol.set_timing(False)
+    ms, n = vol.collect_timing()["march"]
+    st = c.dump(cinr.DUMP_PT_STATE)
+    used = int((c.dump(cinr.DUMP_PT_DIRECTORY) >= 0).sum())
+    res = {"fps": round(fps, 2), "march_ms_per_launch": round(ms / max(n, 1), 4),
+           "image_equal_to_flat_table": bool(np.array_equal(ref_img, out.cpu().numpy())),
+           "directory_entries": st["directory_per_volume"], "blocks_in_use": used,
+           "block_pool": st["blocks"], "table_bytes_in_use": 4 * st["directory_per_volume"] + 2048 * used,
+           "flat_table_bytes": 4 * c.n_keys}
+    del c
+    return res
 
 
 def pool_f16_leg(vol, cams, tfs, w, Wm, K, dtype, ref_img):
@@ -590,6 +621,7 @@ def main():
     ap.add_argument("--no-multiview", action="store_true", help="skip the 16-view shared-cache leg")
     ap.add_argument("--no-adaptive", action="store_true", help="skip the adaptive sampling leg")
     ap.add_argument("--no-pool-f16", action="store_true", help="skip the binary16 pool leg")
+    ap.add_argument("--no-virtual-pt", action="store_true", help="skip the two-level page table leg")
     ap.add_argument("--no-path", action="store_true", help="skip the path-tracing leg")
     ap.add_argument("--no-lod-context", action="store_true", help="skip the context-aware LoD leg")
     ap.add_argument("--path-uncached-steps", type=int, default=5)
@@ -727,6 +759,12 @@ def main():
         del c3
     log(f"[bench] adaptive sampling rate (TF opacity x 0.1): {adaptive}")
 
+    # --- two-level (virtualised) page table ------------------------------------
+    vpt = None
+    if not args.no_virtual_pt:
+        vpt = virtual_pt_leg(vol, cams, tfs, w, Wm, K, args.dtype, cached_img.cpu().numpy())
+        log(f"[bench] two-level page table: {vpt}")
+
     # --- binary16 brick pool (reduced-precision pool) -------------------------
     pool16 = None
     if not args.no_pool_f16:
@@ -834,6 +872,7 @@ def main():
         "cached_other_precisions": other,
         "adaptive_sampling": {"tf": "the orbit's TFs with opacity x 0.1", "by_max_exponent": adaptive},
         "binary16_pool": pool16,
+        "two_level_page_table": vpt,
         "path_tracing": pt,
         "context_aware_lod": lodc,
         "bricks_per_s": {k: round(v, 1) for k, v in bps.items()},

@@ -143,7 +143,23 @@ typedef struct {
  *                subset of the LoDs, and max_requests <= the slots of each
  *                class.  A LoD whose error bound admits binary16 rounding
  *                (at most 2^-12 for the pool's values in [0, 1]) can take
- *                the binary16 class. */
+ *                the binary16 class.
+ *  virtual_page_table  0: one flat page table entry per brick key (4 bytes
+ *                per brick of every LoD).  1: the virtualised page tables of
+ *                Section 4.3.1, two levels: a directory entry per block of
+ *                8^3 bricks of a LoD (4 bytes per 512 bricks) points to a
+ *                block of 512 entries (2 KiB) taken from a block pool when
+ *                one of its bricks is mapped and returned when the last one
+ *                is unmapped.  The sampler reads the directory, then the
+ *                block.  The mapping (brick -> slot), and so every frame's
+ *                results, equal those of the flat table.
+ *  pt_blocks     blocks of the block pool (virtual_page_table = 1); 0 takes
+ *                min(directory entries, pool_bricks), which can never run
+ *                out (each block in use holds a mapped brick).  Below that, a
+ *                brick whose block cannot be had stays unmapped (counted in
+ *                CINR_DUMP_PT_STATE) and frames may differ from the flat
+ *                table's.
+ */
 typedef struct {
     int32_t brick, n_lods, pool_bricks, max_requests, rank_window;
     int32_t ranking;
@@ -154,6 +170,8 @@ typedef struct {
     int32_t pool_dtype;
     uint32_t f16_lods;
     int32_t pool_bricks_f16;
+    int32_t virtual_page_table;
+    int32_t pt_blocks;
 } cinr_cache_desc;
 
 /* Pinhole or orthographic camera.  Basis vectors are unit length; pixel
@@ -293,8 +311,12 @@ typedef enum {
                                    (pixel, k) pair can repeat: an event looked up ahead after a true miss is drawn
                                    again by the segment that follows a real collision) */
     CINR_DUMP_EVICTION_LOG = 7, /* {int32 stamp, slot, old_key, new_key} [n] since creation */
-    CINR_DUMP_POOL = 8          /* pool_dtype values [pool_bricks][B][B][B]: float, or binary16 bits; a mixed
+    CINR_DUMP_POOL = 8,         /* pool_dtype values [pool_bricks][B][B][B]: float, or binary16 bits; a mixed
                                    pool: float [split][B][B][B], then binary16 bits [pool_bricks - split][B][B][B] */
+    CINR_DUMP_PT_DIRECTORY = 9, /* two-level page table: int32 [n_vols][directory entries]: block or -1 */
+    CINR_DUMP_PT_BLOCKS = 10,   /* two-level page table: int32 [blocks][512]: slot or -1 */
+    CINR_DUMP_PT_STATE = 11     /* two-level page table: int32 {blocks, free blocks, insertions left unmapped
+                                   for want of a block, directory entries per volume} */
 } cinr_dump_kind;
 
 typedef struct cinr_volume_s* cinr_volume;

@@ -23,6 +23,7 @@ RANK_TIMESTAMP, RANK_PRIORITY = 0, 1
 PERSPECTIVE, ORTHOGRAPHIC = 0, 1
 DUMP_PAGE_TABLE, DUMP_SLOT_OWNER, DUMP_LAST_USED, DUMP_RANK, DUMP_REQ_COUNT = 0, 1, 2, 3, 4
 DUMP_REQUEST_LIST, DUMP_MISS_LIST, DUMP_EVICTION_LOG, DUMP_POOL = 5, 6, 7, 8
+DUMP_PT_DIRECTORY, DUMP_PT_BLOCKS, DUMP_PT_STATE = 9, 10, 11
 # bytes of the fixed device array of cinr_render_frame_noalloc (the last 256
 # hold its control words)
 NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -46,7 +47,8 @@ class CacheDesc(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("brick", "n_lods", "pool_bricks", "max_requests", "rank_window", "ranking",
                                           "preload_period", "miss_log_capacity", "evict_log_capacity",
                                           "keep_request_counts", "pool_dtype")] + [
-        ("f16_lods", C.c_uint32), ("pool_bricks_f16", C.c_int32)]
+        ("f16_lods", C.c_uint32), ("pool_bricks_f16", C.c_int32), ("virtual_page_table", C.c_int32),
+        ("pt_blocks", C.c_int32)]
 
 
 # Largest rounding error of binary16 for the pool's values in [0, 1]: half
@@ -333,7 +335,8 @@ class Cache:
 
     def __init__(self, volume, brick, n_lods, pool_bricks, max_requests, rank_window=1000,
                  ranking=RANK_PRIORITY, preload_period=0, miss_log_capacity=0, evict_log_capacity=4096,
-                 keep_request_counts=False, pool_dtype="f32", f16_lods=0, pool_bricks_f16=0):
+                 keep_request_counts=False, pool_dtype="f32", f16_lods=0, pool_bricks_f16=0,
+                 virtual_page_table=False, pt_blocks=0):
         vols = list(volume) if isinstance(volume, (list, tuple)) else [volume]
         self.volumes = vols
         volume = vols[0]
@@ -347,6 +350,7 @@ class Cache:
             raise ValueError(f"pool_dtype {pool_dtype!r}: 'f32' or 'f16'")
         d.pool_dtype = _dtype(pool_dtype)
         d.f16_lods, d.pool_bricks_f16 = int(f16_lods), int(pool_bricks_f16)
+        d.virtual_page_table, d.pt_blocks = int(bool(virtual_page_table)), int(pt_blocks)
         self.pool_dtype = pool_dtype if not f16_lods else "mixed"
         # binary32 slots [0, split), then binary16 slots [split, pool_bricks)
         self.split = pool_bricks - pool_bricks_f16 if f16_lods else pool_bricks
@@ -390,8 +394,14 @@ class Cache:
         _check(lib().cinr_cache_dump(self.h, kind, buf.ctypes.data_as(C.c_void_p), buf.size, C.byref(need),
                                      _stream()))
         buf = buf[:need.value]
-        if kind in (DUMP_PAGE_TABLE, DUMP_SLOT_OWNER, DUMP_LAST_USED, DUMP_REQUEST_LIST):
+        if kind in (DUMP_PAGE_TABLE, DUMP_SLOT_OWNER, DUMP_LAST_USED, DUMP_REQUEST_LIST, DUMP_PT_DIRECTORY):
             return buf.view(np.int32)
+        if kind == DUMP_PT_BLOCKS:
+            return buf.view(np.int32).reshape(-1, 512)
+        if kind == DUMP_PT_STATE:
+            b = buf.view(np.int32)
+            return {"blocks": int(b[0]), "free_blocks": int(b[1]), "unmapped_for_want_of_a_block": int(b[2]),
+                    "directory_per_volume": int(b[3])}
         if kind == DUMP_RANK:
             return buf.view(np.int64)
         if kind == DUMP_REQ_COUNT:

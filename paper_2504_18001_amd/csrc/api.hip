@@ -57,22 +57,28 @@ bool geometry(const int32_t dims[3], int32_t B, int32_t n_lods, CacheGeom& g) {
     g.brick = B;
     g.div_b1 = make_fastdiv((uint32_t)(B - 1));
     g.n_lods = n_lods;
-    int64_t off = 0;
+    int64_t off = 0, doff = 0;
     for (int L = 0; L < n_lods; ++L) {
-        int64_t cnt = 1;
+        int64_t cnt = 1, dcnt = 1;
         for (int a = 0; a < 3; ++a) {
             const int64_t span = (int64_t)dims[a] - 1;
             const int64_t step = (int64_t)1 << L;
             const int64_t K = (span + step - 1) / step + 1;
             const int64_t nb = (K - 1 + (B - 1) - 1) / (B - 1);
+            const int64_t dnb = (nb + (1 << kVptShift) - 1) >> kVptShift;
             g.lod[L].K[a] = (int32_t)K;
             g.lod[L].nb[a] = (int32_t)nb;
+            if (a < 2) g.lod[L].dnb[a] = (int32_t)dnb;
             cnt *= nb;
+            dcnt *= dnb;
         }
         g.lod[L].off = off;
+        g.lod[L].doff = doff;
         off += cnt;
+        doff += dcnt;
     }
     g.keys_per_vol = off;
+    g.dir_per_vol = doff;
     g.n_vols = 1;
     g.n_keys = off;
     return true;
@@ -432,6 +438,9 @@ static cinr_status check_cache_desc(const cinr_volume* vols, int32_t n_vols, con
             return fail(CINR_INVALID_ARG, "pool_bricks_f16 = %d of %d: each class needs max_requests (%d) slots or more",
                         p16, d->pool_bricks, d->max_requests);
     }
+    if (d->virtual_page_table != 0 && d->virtual_page_table != 1)
+        return fail(CINR_INVALID_ARG, "virtual_page_table = %d (0 or 1)", d->virtual_page_table);
+    if (d->pt_blocks < 0) return fail(CINR_INVALID_ARG, "pt_blocks < 0");
     if (!geometry(vols[0]->desc.dims, d->brick, d->n_lods, g)) return fail(CINR_INVALID_ARG, "invalid geometry");
     g.n_vols = n_vols;
     g.n_keys = g.keys_per_vol * n_vols;
@@ -452,7 +461,20 @@ static size_t cache_layout(const cinr_cache_desc* d, const CacheGeom& g, CacheDe
         for (int i = 0; i < p->n_pass; ++i) buf = std::max(buf, (size_t)p->blocks[i] * lim);
     Carver cv(base);
     CacheDev x{};
-    x.pt = cv.take<int32_t>(nk);
+    const bool virt = d->virtual_page_table != 0;
+    x.pt = virt ? nullptr : cv.take<int32_t>(nk);
+    if (virt) {
+        // directory over all volumes, block pool (never short at its bound:
+        // a block in use holds at least one of the pool's bricks)
+        const int64_t nd = g.dir_per_vol * g.n_vols;
+        const int64_t bound = std::max<int64_t>(1, std::min<int64_t>(nd, P));
+        const int64_t cap = d->pt_blocks > 0 ? std::min<int64_t>(d->pt_blocks, bound) : bound;
+        x.vdir = cv.take<int32_t>(nd);
+        x.vblk = cv.take<int32_t>((size_t)cap * kVptEntries);
+        x.vcnt = cv.take<int32_t>(cap);
+        x.vfree = cv.take<int32_t>(cap);
+        x.vcap = (int32_t)cap;
+    }
     x.rank = cv.take<int64_t>(nk);
     x.req = cv.take<uint32_t>(nk);
     x.last_req = d->keep_request_counts ? cv.take<uint32_t>(nk) : nullptr;
@@ -464,6 +486,7 @@ static size_t cache_layout(const cinr_cache_desc* d, const CacheGeom& g, CacheDe
     x.ins_slots = cv.take<int32_t>(ins_cap);
     x.ins_reqs = cv.take<int32_t>((size_t)ins_cap * 4);
     x.ins_vols = cv.take<int32_t>(ins_cap);
+    x.ins_old = cv.take<int32_t>(ins_cap);
     x.topk[0] = cv.take<uint64_t>(buf);
     x.topk[1] = cv.take<uint64_t>(buf);
     x.sel = cv.take<uint64_t>(lim);
@@ -536,7 +559,7 @@ extern "C" cinr_status cinr_create_cache_multi(const cinr_volume* vols, int32_t 
     hipStream_t s = (hipStream_t)stream;
     std::vector<InrDev> host(n_vols);
     for (int i = 0; i < n_vols; ++i) host[i] = vols[i]->m;
-    hipError_t e = launch_cache_init(c->c, g.n_keys, s);
+    hipError_t e = launch_cache_init(c->c, g.n_keys, g.dir_per_vol * g.n_vols, s);
     // the copy is staged from pageable memory before the call returns
     if (e == hipSuccess) e = hipMemcpyAsync(c->d_vols, host.data(), sizeof(InrDev) * n_vols, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) {
@@ -581,6 +604,7 @@ extern "C" cinr_status cinr_cache_prefill(cinr_cache c, const int32_t* d_keys, i
     note_fill(c, n);
     HIP_TRY(launch_prefill_setup(c->c, c->g, d_keys, n, stamp, s));
     HIP_TRY(launch_insert(c->c, c->g, n, nullptr, s));
+    if (c->c.vdir) HIP_TRY(launch_vpt_update(c->c, c->g, nullptr, s));
     HIP_TRY(decode_selected(c, n, prec, nullptr, s));
     return CINR_OK;
 }
@@ -886,7 +910,9 @@ cinr_status prepare_view(cinr_cache c, cinr_volume v, const cinr_camera* cam, co
         f.view_table = c->c.views;
         f.geo = c->g;
         f.key_base = (int32_t)(vi * c->g.keys_per_vol);
-        f.pt = c->c.pt + f.key_base;
+        f.pt = c->c.pt ? c->c.pt + f.key_base : nullptr;
+        f.vdir = c->c.vdir ? c->c.vdir + (int64_t)vi * c->g.dir_per_vol : nullptr;
+        f.vblk = c->c.vblk;
         f.last_used = c->c.last_used;
         f.req = c->c.req;
         f.touched = c->c.touched;
@@ -1271,6 +1297,7 @@ cinr_status cache_end_frame(cinr_cache c, int32_t prec, bool lru_pass, Timing& t
             }
             HIP_TRY(launch_insert(cd, c->g, c->lim, gate, s));
         }
+        if (cd.vdir) HIP_TRY(launch_vpt_update(cd, c->g, gate, s));
     }
     {
         StageTimer st_(tm, s, CINR_STAGE_DECODE);
@@ -1665,8 +1692,41 @@ extern "C" cinr_status cinr_cache_dump(cinr_cache c, int32_t kind, void* dst, si
     size_t n = 0;
     const size_t nk = (size_t)c->g.n_keys, P = (size_t)cd.pool_bricks;
     const size_t B3 = (size_t)c->g.brick * c->g.brick * c->g.brick;
+    const size_t nd = (size_t)(c->g.dir_per_vol * c->g.n_vols);
+    if ((kind == CINR_DUMP_PT_DIRECTORY || kind == CINR_DUMP_PT_BLOCKS || kind == CINR_DUMP_PT_STATE) && !cd.vdir)
+        return fail(CINR_BAD_STATE, "the cache has a flat page table (virtual_page_table = 0)");
+    if (kind == CINR_DUMP_PT_STATE) {
+        *needed = 16;
+        if (!dst || bytes < 16) return fail(CINR_OUT_OF_MEMORY, "dump needs 16 bytes");
+        int32_t* o = (int32_t*)dst;
+        o[0] = cd.vcap;
+        o[1] = (int32_t)h.v_free;
+        o[2] = (int32_t)h.v_fail;
+        o[3] = (int32_t)c->g.dir_per_vol;
+        return CINR_OK;
+    }
+    if (kind == CINR_DUMP_PAGE_TABLE && cd.vdir) {
+        // the flat view of the two-level table, resolved on the host
+        *needed = nk * 4;
+        if (!dst || bytes < nk * 4) return fail(CINR_OUT_OF_MEMORY, "dump needs %zu bytes", nk * 4);
+        std::vector<int32_t> dir(nd), blk((size_t)cd.vcap * kVptEntries);
+        HIP_TRY(hipMemcpyAsync(dir.data(), cd.vdir, nd * 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(blk.data(), cd.vblk, blk.size() * 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        int32_t* o = (int32_t*)dst;
+        for (size_t k = 0; k < nk; ++k) {
+            int64_t d;
+            int32_t e;
+            vpt_addr(c->g, (int64_t)k, &d, &e);
+            const int32_t b = dir[(size_t)d];
+            o[k] = b < 0 || b >= cd.vcap ? -1 : blk[(size_t)b * kVptEntries + e];
+        }
+        return CINR_OK;
+    }
     switch (kind) {
         case CINR_DUMP_PAGE_TABLE: src = cd.pt; n = nk * 4; break;
+        case CINR_DUMP_PT_DIRECTORY: src = cd.vdir; n = nd * 4; break;
+        case CINR_DUMP_PT_BLOCKS: src = cd.vblk; n = (size_t)cd.vcap * kVptEntries * 4; break;
         case CINR_DUMP_SLOT_OWNER: src = cd.owner; n = P * 4; break;
         case CINR_DUMP_LAST_USED: src = cd.last_used; n = P * 4; break;
         case CINR_DUMP_RANK: src = cd.rank; n = nk * 8; break;

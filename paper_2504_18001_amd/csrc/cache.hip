@@ -20,10 +20,10 @@
 
 namespace cinr {
 
-__global__ void k_cache_init(CacheDev c, int64_t n_keys) {
+__global__ void k_cache_init(CacheDev c, int64_t n_keys, int64_t n_dir) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_keys; t += stride) {
-        c.pt[t] = -1;
+        if (c.pt) c.pt[t] = -1;
         c.rank[t] = -1;
         c.req[t] = 0u;
         if (c.last_req) c.last_req[t] = 0u;
@@ -32,7 +32,21 @@ __global__ void k_cache_init(CacheDev c, int64_t n_keys) {
         c.owner[t] = -1;
         c.last_used[t] = -1;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) *c.ctr = CacheCtr{};
+    if (c.vdir) {
+        // two-level page table: no block in use, every block entry unmapped,
+        // the free stack pops blocks 0, 1, 2, ... first
+        for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_dir; t += stride) c.vdir[t] = -1;
+        const int64_t ne = (int64_t)c.vcap * kVptEntries;
+        for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ne; t += stride) c.vblk[t] = -1;
+        for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < c.vcap; t += stride) {
+            c.vcnt[t] = 0;
+            c.vfree[t] = c.vcap - 1 - (int32_t)t;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *c.ctr = CacheCtr{};
+        c.ctr->v_free = (uint32_t)c.vcap;
+    }
 }
 
 // Clears the request counts kept for dumps (before the frame's sampler).
@@ -139,13 +153,14 @@ __device__ void insert_entries(const CacheDev& c, const CacheGeom& g, const Cach
         if (ok) {
             old = c.owner[slot];
             if (old >= 0) {
-                c.pt[old] = -1;
+                if (c.pt) c.pt[old] = -1;
                 c.rank[old] = -1;
             }
-            c.pt[key] = slot;
+            if (c.pt) c.pt[key] = slot;  // a two-level table is updated by k_vpt_update
             c.owner[slot] = key;
             c.last_used[slot] = stamp;
         }
+        c.ins_old[t] = old;
         // volume and brick coordinates of the key
         const int32_t vol = ok ? (int32_t)((int64_t)key / g.keys_per_vol) : 0;
         const int64_t vkey = ok ? (int64_t)key - (int64_t)vol * g.keys_per_vol : 0;
@@ -373,13 +388,107 @@ __global__ void k_insert_finish(CacheDev c, const uint32_t* gate) {
     }
 }
 
+// Two-level page table after an insertion batch (Section 4.3.1's
+// virtualised page tables), one workgroup: unmap the evicted bricks, return
+// the blocks they leave empty to the free stack, take a block for each
+// directory entry a new brick needs, map the new bricks.  A block returns to
+// the stack only once all of its entries are -1 again, so a block taken from
+// the stack needs no clearing.  Which block serves a directory entry depends
+// on the order of the atomics; the mapping itself (brick -> slot) does not.
+constexpr int32_t kVptClaim = -2;  // directory entry being given a block
+
+// Directory and count words change under atomics within k_vpt_update: read
+// them at device scope (past the workgroup's L1).
+__device__ inline int32_t vpt_load(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(1024) void k_vpt_update(CacheDev c, CacheGeom g, const uint32_t* gate) {
+    if (gate && *gate == 0u) return;
+    __shared__ uint32_t top, fail;
+    const uint32_t n = c.ctr->n_sel;
+    if (threadIdx.x == 0) {
+        top = c.ctr->v_free;
+        fail = 0u;
+    }
+    for (uint32_t t = threadIdx.x; t < n; t += blockDim.x) {
+        const int32_t old = c.ins_old[t];
+        if (old < 0) continue;
+        int64_t d;
+        int32_t e;
+        vpt_addr(g, old, &d, &e);
+        const int32_t b = vpt_load(&c.vdir[d]);
+        if (b < 0) continue;
+        const int64_t ix = (int64_t)b * kVptEntries + e;
+        if (c.vblk[ix] < 0) continue;  // left unmapped for want of a block
+        c.vblk[ix] = -1;
+        atomicSub(&c.vcnt[b], 1);
+    }
+    __threadfence();
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < n; t += blockDim.x) {
+        const int32_t old = c.ins_old[t];
+        if (old < 0) continue;
+        int64_t d;
+        int32_t e;
+        vpt_addr(g, old, &d, &e);
+        const int32_t b = vpt_load(&c.vdir[d]);
+        if (b >= 0 && vpt_load(&c.vcnt[b]) == 0 && atomicCAS(&c.vdir[d], b, -1) == b) c.vfree[atomicAdd(&top, 1u)] = b;
+    }
+    __threadfence();
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < n; t += blockDim.x) {
+        if (c.ins_slots[t] < 0) continue;
+        int64_t d;
+        int32_t e;
+        vpt_addr(g, c.ins_keys[t], &d, &e);
+        if (vpt_load(&c.vdir[d]) != -1 || atomicCAS(&c.vdir[d], -1, kVptClaim) != -1) continue;
+        const uint32_t i = atomicSub(&top, 1u);
+        if ((int32_t)i <= 0) {
+            atomicExch(&c.vdir[d], -1);  // no block left (the pool of blocks was sized below its bound)
+        } else {
+            atomicExch(&c.vdir[d], vpt_load(&c.vfree[i - 1u]));
+        }
+    }
+    __threadfence();
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < n; t += blockDim.x) {
+        const int32_t slot = c.ins_slots[t];
+        if (slot < 0) continue;
+        int64_t d;
+        int32_t e;
+        vpt_addr(g, c.ins_keys[t], &d, &e);
+        const int32_t b = vpt_load(&c.vdir[d]);
+        if (b < 0) {
+            atomicAdd(&fail, 1u);  // the brick stays unmapped
+            continue;
+        }
+        c.vblk[(int64_t)b * kVptEntries + e] = slot;
+        atomicAdd(&c.vcnt[b], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        c.ctr->v_free = (int32_t)top < 0 ? 0u : top;
+        c.ctr->v_fail += fail;
+    }
+}
+
 // ---------------------------------------------------------------------------
 
-hipError_t launch_cache_init(const CacheDev& c, int64_t n_keys, hipStream_t s) {
+hipError_t launch_cache_init(const CacheDev& c, int64_t n_keys, int64_t n_dir, hipStream_t s) {
     int64_t n = n_keys > c.pool_bricks ? n_keys : c.pool_bricks;
+    if (c.vdir) {
+        n = n > n_dir ? n : n_dir;
+        n = n > (int64_t)c.vcap * kVptEntries ? n : (int64_t)c.vcap * kVptEntries;
+    }
     int64_t b = (n + 255) / 256;
     b = b < 1 ? 1 : (b > 4096 ? 4096 : b);
-    hipLaunchKernelGGL(k_cache_init, dim3((unsigned)b), dim3(256), 0, s, c, n_keys);
+    hipLaunchKernelGGL(k_cache_init, dim3((unsigned)b), dim3(256), 0, s, c, n_keys, n_dir);
+    return hipGetLastError();
+}
+
+hipError_t launch_vpt_update(const CacheDev& c, const CacheGeom& g, const uint32_t* gate, hipStream_t s) {
+    hipLaunchKernelGGL(k_vpt_update, dim3(1), dim3(1024), 0, s, c, g, gate);
     return hipGetLastError();
 }
 

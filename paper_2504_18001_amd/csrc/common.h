@@ -61,11 +61,20 @@ __device__ inline uint32_t fast_div(uint32_t n, FastDiv f) {
     return f.mul ? (__umulhi(n, f.mul) >> f.shift) : (n >> f.shift);
 }
 
+// Two-level page table (the virtualised page tables of Section 4.3.1): a
+// directory entry per block of 8^3 bricks of a LoD, pointing to a block of
+// 512 slot entries held in a block pool (or -1 when none of the block's
+// bricks is mapped).
+constexpr int kVptShift = 3;                // block side 2^3 bricks
+constexpr int kVptEntries = 1 << (3 * kVptShift);
+
 // LoD lattice / brick geometry (Section 4.3.2).
 struct LodGeom {
     int32_t K[3];    // lattice points per axis
     int32_t nb[3];   // bricks per axis
     int64_t off;     // first key of the LoD
+    int32_t dnb[2];  // page-table blocks along x and y
+    int64_t doff;    // first directory entry of the LoD (within a volume)
 };
 
 // Keys of a cache shared by n_vols volumes of the same dimensions: volume v
@@ -87,7 +96,34 @@ struct CacheGeom {
     int64_t keys_per_vol;
     int32_t n_vols;
     int64_t n_keys;  // n_vols * keys_per_vol
+    int64_t dir_per_vol;  // directory entries of the two-level page table per volume
 };
+
+// Directory entry and block entry of brick b (coordinates at LoD lg) within
+// its volume's directory.
+__host__ __device__ inline int64_t vpt_dir(const LodGeom& lg, const int32_t b[3]) {
+    return lg.doff + ((int64_t)(b[2] >> kVptShift) * lg.dnb[1] + (b[1] >> kVptShift)) * lg.dnb[0] + (b[0] >> kVptShift);
+}
+__host__ __device__ inline int32_t vpt_entry(const int32_t b[3]) {
+    constexpr int32_t m = (1 << kVptShift) - 1;
+    return (((b[2] & m) << kVptShift | (b[1] & m)) << kVptShift) | (b[0] & m);
+}
+
+// Directory entry (over all volumes) and block entry of a brick key.
+__host__ __device__ inline void vpt_addr(const CacheGeom& g, int64_t key, int64_t* d, int32_t* e) {
+    const int64_t vol = key / g.keys_per_vol;
+    const int64_t vkey = key - vol * g.keys_per_vol;
+    int32_t L = 0;
+    while (L + 1 < g.n_lods && vkey >= g.lod[L + 1].off) ++L;
+    const LodGeom& lg = g.lod[L];
+    const int64_t local = vkey - lg.off;
+    int32_t b[3];
+    b[0] = (int32_t)(local % lg.nb[0]);
+    b[1] = (int32_t)((local / lg.nb[0]) % lg.nb[1]);
+    b[2] = (int32_t)(local / ((int64_t)lg.nb[0] * lg.nb[1]));
+    *d = vol * g.dir_per_vol + vpt_dir(lg, b);
+    *e = vpt_entry(b);
+}
 
 // ---------------------------------------------------------------------------
 // Wave-level helpers

@@ -187,6 +187,23 @@ __device__ inline BrickAddr brick_addr(const LodGeom& lg, int32_t brick, FastDiv
     return r;
 }
 
+// The brick of LoD L holding p (coordinates b) and its key alone: the same
+// operations as brick_addr, for the page-table search over the LoDs.
+template <int kB>
+__device__ inline int32_t brick_key(const LodGeom& lg, int32_t brick, FastDiv div_b1, int32_t L, const float p[3],
+                                    int32_t b[3]) {
+    const float sc = __builtin_ldexpf(1.0f, -L);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float q = p[a] * sc;
+        int32_t j = (int32_t)q;
+        if (j > lg.K[a] - 2) j = lg.K[a] - 2;
+        b[a] = kB ? (int32_t)((uint32_t)j / (uint32_t)(kB - 1)) : (int32_t)fast_div((uint32_t)j, div_b1);
+    }
+    (void)brick;
+    return (int32_t)lg.off + (b[2] * lg.nb[1] + b[1]) * lg.nb[0] + b[0];
+}
+
 // Path tracing draws (Section 5.1; binary32 decision plane).
 // A uniform in [0, 1) from the top 24 bits of a random word.
 __device__ inline float pt_uniform(uint32_t r) { return (float)(r >> 8) * 5.9604644775390625e-08f; }

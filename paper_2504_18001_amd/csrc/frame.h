@@ -39,6 +39,9 @@ struct CacheCtr {
     // the binary16 class of a mixed pool (slots [split, pool_bricks)); the
     // fields above then count the binary32 class, except n_sel (all bricks)
     uint32_t n_sel1, n_free1, need_evict1, n_used1;
+    // two-level page table: free blocks on the stack, insertions left
+    // unmapped for want of a block (never with the block pool's default size)
+    uint32_t v_free, v_fail;
 };
 
 // Storage of the pool's brick values: one binary32 or one binary16 class of
@@ -89,6 +92,16 @@ struct CacheDev {
     int32_t split;        // first slot of the binary16 class (pool_bricks unless mixed)
     uint32_t f16_lods;    // mixed: bit L set stores LoD L in the binary16 class
     uint64_t* vic1;       // victim list of the binary16 class (sorted scores)
+    int32_t* ins_old;     // [ins_cap] key evicted by each insertion (-1: none)
+    // two-level page table (vdir non-null; pt is then null): directory
+    // [n_vols * dir_per_vol] of block ids (-1: no block), the block pool
+    // [vcap][kVptEntries] of slots (-1: unmapped), the mapped entries of
+    // each block, and the stack of free block ids (vfree[0, ctr->v_free))
+    int32_t* vdir;
+    int32_t* vblk;
+    int32_t* vcnt;
+    int32_t* vfree;
+    int32_t vcap;
 };
 
 // Values of a view that change from one frame to the next while its launch
@@ -183,6 +196,9 @@ struct FrameDev {
     // frame's volume: global key = key_base + key
     int32_t key_base;
     const int32_t* pt;
+    // two-level page table instead of pt (vdir: this volume's directory)
+    const int32_t* vdir;
+    const int32_t* vblk;
     int32_t* last_used;
     uint32_t* req;
     int32_t* touched;
@@ -303,7 +319,9 @@ hipError_t launch_frame_end(const FrameDev& f, int max_iters, CacheCtr* cctr, bo
 hipError_t launch_pending_gather(const FrameDev* const* fs, int n, uint32_t* host_out, uint32_t* gate, hipStream_t s);
 
 // cache launchers
-hipError_t launch_cache_init(const CacheDev& c, int64_t n_keys, hipStream_t s);
+hipError_t launch_cache_init(const CacheDev& c, int64_t n_keys, int64_t n_dir, hipStream_t s);
+// Two-level page table: the mapping changes of the last insertion batch.
+hipError_t launch_vpt_update(const CacheDev& c, const CacheGeom& g, const uint32_t* gate, hipStream_t s);
 // fuse_done (nullable): count of finished workgroups for a single fused
 // launch of a two-pass plan (pass 0, then pass 1 in its last workgroup).
 hipError_t launch_topk(const TopkArgs& base, const TopkPlan& plan, uint64_t* buf0, uint64_t* buf1, uint64_t* final_out,

@@ -26,26 +26,29 @@ struct SampleRes {
     int32_t e;  // step exponent of the sample's macro-cell (adaptive sampling)
 };
 
-// The two most recent page-table lookups of a ray.  Residency is constant
-// within a frame, so a repeated key (consecutive samples in the same brick)
-// needs no reload.
+// The last page-table lookup of a lane at each LoD (LoD L in way L mod 4),
+// kept in LDS: way w of a lane at base[w * kBlock] (consecutive lanes,
+// consecutive words).  Residency is constant within a frame, so a repeated
+// key (consecutive samples in the same brick) needs no reload, and entries
+// stay valid from one ray to the next; a sample that falls back from an
+// unmapped LoD to coarser ones finds every level it tries here until the ray
+// leaves one of the bricks.  A new key reads the flat page table, or the
+// directory entry of its block and then the block's entry (two-level table).
+constexpr int kSlotWays = 4;
 struct SlotCache {
-    int32_t k0 = -1, s0 = -1, k1 = -1, s1 = -1;
-    __device__ int32_t lookup(const int32_t* pt, int32_t key) {
-        if (key == k0) return s0;
-        if (key == k1) {
-            const int32_t tk = k0, ts = s0;
-            k0 = k1;
-            s0 = s1;
-            k1 = tk;
-            s1 = ts;
-            return s0;
+    int2* base;
+    __device__ int32_t lookup(const FrameDev& f, const LodGeom& lg, int32_t key, const int32_t b[3], int32_t lod) {
+        int2* e = base + (lod & (kSlotWays - 1)) * kBlock;
+        const int2 c = *e;
+        if (c.x == key) return c.y;
+        int32_t v;
+        if (f.vdir) {
+            const int32_t blk = f.vdir[vpt_dir(lg, b)];
+            v = blk < 0 ? -1 : f.vblk[(int64_t)blk * kVptEntries + vpt_entry(b)];
+        } else {
+            v = f.pt[key];
         }
-        const int32_t v = pt[key];
-        k1 = k0;
-        s1 = s0;
-        k0 = key;
-        s0 = v;
+        *e = make_int2(key, v);
         return v;
     }
 };
@@ -176,40 +179,47 @@ __device__ inline SampleRes sample_cache(const FrameDev& f, const FrameHot& h, c
     const int32_t L = select_lod(p, h.eye, f.lod_scale, lod_factor, h.seed, h.lod_floor, nl);
     const int32_t B = kFast ? kB : f.geo.brick;
     s.status = S_MISS;
+    // the first mapped LoD from L on (keys only), then one fetch from it
+    int32_t slot = -1, Ls = L;
     for (int32_t Lp = L; Lp < nl; ++Lp) {
-        const BrickAddr a = brick_addr<kB>(lg[Lp], f.geo.brick, f.geo.div_b1, Lp, p);
-        if (Lp == L) s.req_key = a.key;
-        const int32_t slot = sc.lookup(f.pt, a.key);
+        int32_t b[3];
+        const int32_t key = brick_key<kB>(lg[Lp], f.geo.brick, f.geo.div_b1, Lp, p, b);
+        if (Lp == L) s.req_key = key;
+        const int32_t sl = sc.lookup(f, lg[Lp], key, b, Lp);
         if (!live) {
             s.status = S_SKIP;
             s.req_key = -1;
             return s;
         }
-        if (slot < 0) continue;
-        float c[8];
-        if constexpr (kPool == POOL_MIXED) {
-            if (slot < f.split)
-                brick_corners<kFast, float>(f.pool, slot, a, B, c);
-            else
-                brick_corners<kFast, __half>(f.pool16, slot - f.split, a, B, c);
-        } else {
-            brick_corners<kFast, typename std::conditional<kPool == POOL_F16, __half, float>::type>(f.pool, slot, a, B,
-                                                                                                  c);
+        if (sl >= 0) {
+            slot = sl;
+            Ls = Lp;
+            break;
         }
-        const float c000 = c[0], c100 = c[1], c010 = c[2], c110 = c[3];
-        const float c001 = c[4], c101 = c[5], c011 = c[6], c111 = c[7];
-        const float fx = a.frac[0], fy = a.frac[1], fz = a.frac[2];
-        const float x00 = __builtin_fmaf(fx, c100 - c000, c000);
-        const float x10 = __builtin_fmaf(fx, c110 - c010, c010);
-        const float x01 = __builtin_fmaf(fx, c101 - c001, c001);
-        const float x11 = __builtin_fmaf(fx, c111 - c011, c011);
-        const float y0 = __builtin_fmaf(fy, x10 - x00, x00);
-        const float y1 = __builtin_fmaf(fy, x11 - x01, x01);
-        s.value = __builtin_fmaf(fz, y1 - y0, y0);
-        s.slot = slot;
-        s.status = (Lp == L) ? S_HIT : S_FALLBACK;
-        break;
     }
+    if (slot < 0) return s;
+    const BrickAddr a = brick_addr<kB>(lg[Ls], f.geo.brick, f.geo.div_b1, Ls, p);
+    float c[8];
+    if constexpr (kPool == POOL_MIXED) {
+        if (slot < f.split)
+            brick_corners<kFast, float>(f.pool, slot, a, B, c);
+        else
+            brick_corners<kFast, __half>(f.pool16, slot - f.split, a, B, c);
+    } else {
+        brick_corners<kFast, typename std::conditional<kPool == POOL_F16, __half, float>::type>(f.pool, slot, a, B, c);
+    }
+    const float c000 = c[0], c100 = c[1], c010 = c[2], c110 = c[3];
+    const float c001 = c[4], c101 = c[5], c011 = c[6], c111 = c[7];
+    const float fx = a.frac[0], fy = a.frac[1], fz = a.frac[2];
+    const float x00 = __builtin_fmaf(fx, c100 - c000, c000);
+    const float x10 = __builtin_fmaf(fx, c110 - c010, c010);
+    const float x01 = __builtin_fmaf(fx, c101 - c001, c001);
+    const float x11 = __builtin_fmaf(fx, c111 - c011, c011);
+    const float y0 = __builtin_fmaf(fy, x10 - x00, x00);
+    const float y1 = __builtin_fmaf(fy, x11 - x01, x01);
+    s.value = __builtin_fmaf(fz, y1 - y0, y0);
+    s.slot = slot;
+    s.status = Ls == L ? S_HIT : S_FALLBACK;
     return s;
 }
 
@@ -291,6 +301,24 @@ __device__ inline void flush_requests(ColdRef c, int32_t key, uint32_t cnt) {
     }
 }
 
+// The request runs (key, cnt) of all 64 lanes together, one atomic per
+// distinct key of the wave: neighbouring rays of a tile request the same
+// bricks, and the counts of a frame's few hundred requested bricks would
+// otherwise meet as thousands of atomics per address.  Every lane calls it.
+__device__ inline void wave_flush_requests(ColdRef c, int32_t key, uint32_t cnt) {
+    bool pend = key >= 0 && cnt != 0u;
+    for (uint64_t todo = __ballot(pend); todo != 0ull; todo = __ballot(pend)) {
+        const int leader = __builtin_ctzll(todo);
+        const int32_t lk = __shfl(key, leader);
+        const bool same = pend && key == lk;
+        uint32_t v = same ? cnt : 0u;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (lane_id() == leader) flush_requests(c, lk, v);
+        pend = pend && !same;
+    }
+}
+
 __device__ inline void log_miss(ColdRef c, int32_t pix, int32_t k, const float p[3]) {
     const int32_t cap = c->misslog_cap;
     if (cap <= 0) return;
@@ -332,49 +360,50 @@ struct Tally {
 
 // Per-ray bookkeeping of one decided sample: request run-length aggregation
 // (any sample not served at its own LoD requests its brick) and LRU stamps.
-// A ray alternates between the bricks of two neighbouring LoDs, so the two
-// slots stamped last are remembered; a stamp is a plain store (every writer
-// stores the same frame index).
+// The stochastic LoD makes a ray alternate between the bricks of two
+// neighbouring LoDs, so runs are kept for the two keys requested last (one
+// atomic per run when a third key comes, or at the end), and the two slots
+// stamped last are remembered; a stamp is a plain store (every writer stores
+// the same frame index).
 struct RayBook {
-    int32_t rk = -1;
-    uint32_t rc = 0;
+    int32_t rk0 = -1, rk1 = -1;
+    uint32_t rc0 = 0, rc1 = 0;
     int32_t ls0 = -1, ls1 = -1;
+    __device__ void request(ColdRef c, int32_t key) {
+        if (key == rk0) {
+            ++rc0;
+        } else if (key == rk1) {
+            ++rc1;
+        } else {
+            flush_requests(c, rk1, rc1);
+            rk1 = rk0;
+            rc1 = rc0;
+            rk0 = key;
+            rc0 = 1;
+        }
+    }
     __device__ void note(const FrameDev& f, int32_t frame, ColdRef c, const SampleRes& s) {
         if (f.mode != CINR_CACHED || s.status == S_SKIP) return;
-        if (s.status != S_HIT) {
-            if (s.req_key != rk) {
-                flush_requests(c, rk, rc);
-                rk = s.req_key;
-                rc = 1;
-            } else {
-                ++rc;
-            }
-        }
+        if (s.status != S_HIT) request(c, s.req_key);
         if (s.slot >= 0 && s.slot != ls0 && s.slot != ls1) {
             f.last_used[s.slot] = frame;
             ls1 = ls0;
             ls0 = s.slot;
         }
     }
-    __device__ void flush(ColdRef c) {
-        flush_requests(c, rk, rc);
-        rk = -1;
-        rc = 0;
+    // at the end of a ray, all 64 lanes together (see wave_flush_requests)
+    __device__ void wave_flush(ColdRef c) {
+        wave_flush_requests(c, rk0, rc0);
+        wave_flush_requests(c, rk1, rc1);
+        rk0 = rk1 = -1;
+        rc0 = rc1 = 0;
     }
     // The same for scattered lookups (the path tracer): a stamp is stored
     // only when the slot does not hold it yet, so that lookups spread over
     // many slots do not dirty a cache line each.
     __device__ void note_scattered(const FrameDev& f, int32_t frame, ColdRef c, const SampleRes& s) {
         if (f.mode != CINR_CACHED || s.status == S_SKIP) return;
-        if (s.status != S_HIT) {
-            if (s.req_key != rk) {
-                flush_requests(c, rk, rc);
-                rk = s.req_key;
-                rc = 1;
-            } else {
-                ++rc;
-            }
-        }
+        if (s.status != S_HIT) request(c, s.req_key);
         if (s.slot >= 0 && s.slot != ls0 && s.slot != ls1) {
             if (f.last_used[s.slot] != frame) f.last_used[s.slot] = frame;
             ls1 = ls0;
@@ -514,8 +543,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves, 
     __shared__ float4 tfs[256];
     __shared__ LodGeom lgs[kMaxLods];
     __shared__ uint64_t sflags[kLdsFlags ? (kAdapt ? kMaxLdsCells / 8 : kMaxLdsFlagWords) : 1];
+    __shared__ int2 slotc[kSlotWays * kBlock];
     tfs[threadIdx.x] = reinterpret_cast<const float4*>(f.tf)[threadIdx.x];
     if (threadIdx.x < kMaxLods) lgs[threadIdx.x] = f.geo.lod[threadIdx.x];
+#pragma unroll
+    for (int w = 0; w < kSlotWays; ++w) slotc[w * kBlock + threadIdx.x] = make_int2(-1, -1);
     if (kLdsFlags) {
         if (kAdapt) {
             const uint64_t* src = reinterpret_cast<const uint64_t*>(f.cell_code);
@@ -566,7 +598,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves, 
     UnitQueue q(f.claim + (it & 1) * 8 * kClaimStride, (n + 63u) / 64u, (uint32_t)f.xcd_bands);
     const int32_t S = f.S;
     Tally tally;
-    SlotCache sc;  // residency is constant within a frame: valid across rays
+    SlotCache sc{&slotc[threadIdx.x]};  // residency is constant within a frame: valid across rays
     for (;;) {
         const int64_t unit = q.claim();
         if (unit < 0) break;
@@ -706,8 +738,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves, 
                 }
             }
         }
+        book.wave_flush(cold);
         if (has) {
-            book.flush(cold);
             float4* rgba = cold->rgba;
             rgba[pix] = acc;
         }
@@ -889,8 +921,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
     __shared__ float4 tfs[256];
     __shared__ LodGeom lgs[kMaxLods];
     __shared__ uint64_t sflags[kLdsFlags ? kMaxLdsFlagWords : 1];
+    __shared__ int2 slotc[kSlotWays * kBlock];
     tfs[threadIdx.x] = reinterpret_cast<const float4*>(f.tf)[threadIdx.x];
     if (threadIdx.x < kMaxLods) lgs[threadIdx.x] = f.geo.lod[threadIdx.x];
+#pragma unroll
+    for (int w = 0; w < kSlotWays; ++w) slotc[w * kBlock + threadIdx.x] = make_int2(-1, -1);
     if (kLdsFlags)
         for (int32_t w = threadIdx.x; w < f.flag_words; w += kBlock) sflags[w] = f.flags[w];
     // the counters of the next iteration were last used two launches ago
@@ -925,7 +960,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
     const PtDev P = f.path;
     const uint32_t key1 = (uint32_t)hot.frame;
     Tally tally;
-    SlotCache sc;  // residency is constant within a frame
+    SlotCache sc{&slotc[threadIdx.x]};  // residency is constant within a frame
     for (;;) {
         const int64_t unit = q.claim();
         if (unit < 0) break;
@@ -1127,8 +1162,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
             }
             s.store(P.st[pix]);
         }
+        book.wave_flush(cold);
         if (has) {
-            book.flush(cold);
             if (fin) {
                 float4* rgba = cold->rgba;
                 rgba[pix] = pt_pixel_value(s);

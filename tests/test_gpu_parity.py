@@ -137,7 +137,8 @@ def _compare_state(gc, oc, frame, check_misses=True):
 
 def run_cached_sequence(w, frames, width, height, dtype="f32", dims=None, pool=None, max_req=None, ranking=1,
                         preload=None, S=None, macro=False, tf_fn=None, n_lods=None, brick=None, adapt=0,
-                        pool_dtype="f32", lod_context=0.0, f16_lods=0, pool_bricks_f16=0, caches=None):
+                        pool_dtype="f32", lod_context=0.0, f16_lods=0, pool_bricks_f16=0, caches=None,
+                        virtual_pt=False):
     from oracle import oracle as O
     from paper_2504_18001_amd import cinr
     arch = w.arch
@@ -152,7 +153,7 @@ def run_cached_sequence(w, frames, width, height, dtype="f32", dims=None, pool=N
     vol = gpu_volume(arch, 0, dims=dims, macrocells=mm, macro_cell=w.macro_cell if macro else 0)
     gc = cinr.Cache(vol, B, nl, pool, max_req, ranking=ranking, preload_period=preload, miss_log_capacity=1 << 22,
                     evict_log_capacity=1 << 16, keep_request_counts=True, pool_dtype=pool_dtype, f16_lods=f16_lods,
-                    pool_bricks_f16=pool_bricks_f16)
+                    pool_bricks_f16=pool_bricks_f16, virtual_page_table=virtual_pt)
     oc = O.OracleCache(m, brick=B, n_lods=nl, pool_bricks=pool, max_requests=max_req, ranking=ranking,
                        preload_period=preload, log_misses=True, pool_f16=pool_dtype == "f16", f16_lods=f16_lods,
                        pool_bricks_f16=pool_bricks_f16)
