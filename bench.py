@@ -9,8 +9,8 @@ along a 60-frame orbit (6 degrees per frame, 20 degree elevation, ramp
 transfer function for frames 0-29 of each loop, a seeded random one for
 30-59); step 0.5 voxel, LoD distance scale 1/800, early ray termination at
 0.999; cache of 16^3-sample bricks, 4 LoDs, 2 GiB FP32 pool (131072 slots),
-40 requests per frame, pre-load of the coarsest LoD (4 frames per LoD),
-macro-cells of side 16 built from the INR on the GPU.
+up to 256 bricks requested and decoded per frame, pre-load of the coarsest
+LoD (4 frames per LoD), macro-cells of side 16 built from the INR on the GPU.
 
 A step is one whole frame of the hot path: ray generation, sampling through
 the page tables, true-miss inference, compositing, the cache manager's
@@ -84,10 +84,11 @@ def make_scene(w, dtype_decode="bf16"):
     return vol, cams, tfs
 
 
-def new_cache(vol, w, pool_dtype="f32", pool_bricks=None, f16_lods=0, pool_bricks_f16=0, virtual_pt=False):
+def new_cache(vol, w, pool_dtype="f32", pool_bricks=None, f16_lods=0, pool_bricks_f16=0, virtual_pt=False,
+              max_requests=None):
     from paper_2504_18001_amd import cinr
     cs = w.cache
-    return cinr.Cache(vol, cs.brick, cs.n_lods, pool_bricks or cs.pool_bricks, cs.max_requests,
+    return cinr.Cache(vol, cs.brick, cs.n_lods, pool_bricks or cs.pool_bricks, max_requests or cs.max_requests,
                       rank_window=cs.rank_window, ranking=cs.ranking, preload_period=cs.preload_period,
                       pool_dtype=pool_dtype, f16_lods=f16_lods, pool_bricks_f16=pool_bricks_f16,
                       virtual_page_table=virtual_pt)
@@ -126,6 +127,33 @@ def decode_throughput(vol, w, dtype, n_bricks, reps=5):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
     return n_bricks / (ms * 1e-3), ms
+
+
+def request_count_leg(vol, cams, tfs, w, Wm, K, dtype, n_req=40):
+    """The headline window with the request list of Sec. 6.1's length (40
+    bricks per frame): the cache fills more slowly, so more samples fall back
+    to coarser LoDs."""
+    import torch
+    from paper_2504_18001_amd import cinr
+    c = new_cache(vol, w, max_requests=n_req)
+    r = cinr.Renderer()
+    out = torch.empty((w.height, w.width, 4), dtype=torch.float32, device="cuda")
+    st = torch.zeros((K, len(cinr.STAT_FIELDS)), dtype=torch.int64, device="cuda")
+    run_frames(r, vol, cams, tfs, w, range(Wm), cinr.CACHED, dtype, c, out=out)
+    torch.cuda.synchronize()
+    vol.set_timing(True, march_only=True)
+    t0 = time.perf_counter()
+    run_frames(r, vol, cams, tfs, w, range(Wm, Wm + K), cinr.CACHED, dtype, c, stats=st, out=out)
+    torch.cuda.synchronize()
+    fps = K / (time.perf_counter() - t0)
+    vol.set_timing(False)
+    ms, n = vol.collect_timing()["march"]
+    tot = st.sum(0).cpu().numpy()
+    res = {"max_requests": n_req, "fps": round(fps, 2), "march_ms_per_launch": round(ms / max(n, 1), 4),
+           "fallbacks_per_frame": int(tot[cinr.STAT_FIELDS.index("fallbacks")]) // K,
+           "samples_per_frame": int(tot[cinr.STAT_FIELDS.index("samples")]) // K}
+    del c
+    return res
 
 
 def virtual_pt_leg(vol, cams, tfs, w, Wm, K, dtype, ref_img):
@@ -657,7 +685,27 @@ def main():
     K, Wm = args.steps, args.warmup
     log(f"[bench] workload {w.name}: warmup {Wm} frames, timed {K} frames")
     vol, cams, tfs = make_scene(w)
+    # decoding launch shape: the autotuner times every shape on a request list
+    # of the frame's length (random bricks of every LoD), before the frames
+    nb, _ = vol.geometry(w.cache.brick, w.cache.n_lods)
+    from paper_2504_18001_amd import synth
+    tune_reqs = torch.from_numpy(synth.random_requests(nb.tolist(), w.cache.max_requests, seed=12)).cuda()
+    decode_shape, decode_shape_ms = vol.tune_decode(tune_reqs, w.cache.brick, args.dtype)
+    log(f"[bench] decode shape {decode_shape}: {decode_shape_ms}")
     torch.cuda.synchronize()
+    # sampler launch shape: the online tuner settles on a scratch cache over the
+    # same orbit before the headline's frames, as the decoding shape above
+    tcache, tr = new_cache(vol, w), cinr.Renderer()
+    vol.set_timing(True, march_only=True)
+    tune_frames = 0
+    while cinr.tuned_launch(vol, w.width, w.height)[2] > 0 and tune_frames < 400:
+        run_frames(tr, vol, cams, tfs, w, range(tune_frames, tune_frames + 10), cinr.CACHED, args.dtype, tcache)
+        tune_frames += 10
+    torch.cuda.synchronize()
+    vol.set_timing(False)
+    tune_launches = vol.collect_timing()["march"][1]
+    del tcache, tr
+    log(f"[bench] sampler launch shape {cinr.tuned_launch(vol, w.width, w.height)} after {tune_frames} frames")
 
     # --- cached, reduced-precision MLP: the headline run ---------------------
     cache = new_cache(vol, w)
@@ -719,6 +767,25 @@ def main():
     del fg, gcache
     log(f"[bench] captured frames {args.dtype}: {fps_graph:.1f} fps; image equal to eager: {graph_same}; "
         f"counts {graph_counts}")
+    # the same with wavefront iterations queued on the device behind the first
+    # march (true-miss frames of up to that many more iterations need no host
+    # round trip); the steady state pays for the empty launches
+    dev_iters = {}
+    for k_dev in (2,):
+        gcache = new_cache(vol, w)
+        fg = cinr.FrameGraph(gcache, [(vol, cams[0], tfs[0])], w.step, w.lod_scale, seed=w.seed,
+                             ert_threshold=w.ert_threshold, samples_per_iter=w.samples_per_iter, dtype=args.dtype)
+        fg.set_device_iterations(k_dev)
+        graph_frames(range(Wm))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        graph_frames(range(Wm, Wm + K))
+        torch.cuda.synchronize()
+        fps_k = K / (time.perf_counter() - t0)
+        dev_iters[str(k_dev)] = {"fps": round(fps_k, 2), "image_equal": bool(torch.equal(fg.outs[0], cached_img)),
+                                 "frames_graph_eager_tail": list(fg.counts())}
+        del fg, gcache
+    log(f"[bench] captured frames with device iterations: {dev_iters}")
 
     # --- adaptive sampling rate (Section 5.2) ----------------------------------
     # the same orbit with the TFs' opacity scaled by 0.1 (a semi-transparent
@@ -758,6 +825,11 @@ def main():
                              "psnr_vs_fixed_step_db": round(psnr(ref_low, img), 2)}
         del c3
     log(f"[bench] adaptive sampling rate (TF opacity x 0.1): {adaptive}")
+
+    # --- the paper's request-list length ----------------------------------------
+    req40 = None if w.cache.max_requests == 40 else request_count_leg(vol, cams, tfs, w, Wm, K, args.dtype)
+    if req40:
+        log(f"[bench] 40 requests per frame: {req40}")
 
     # --- two-level (virtualised) page table ------------------------------------
     vpt = None
@@ -864,6 +936,7 @@ def main():
                    "orbit_frames": w.n_frames},
         "captured_frames_fps": round(fps_graph, 2),
         "captured_frames_image_equal": graph_same,
+        "captured_frames_device_iterations": dev_iters,
         "uncached_fp32_fps": round(fps_unc, 2),
         "speedup_vs_uncached_fp32": round(fps / fps_unc, 3),
         "mlp_precision": {"bf16x3": "BF16 MFMA, operands split into hi+lo BF16, FP32 accumulation",
@@ -873,9 +946,13 @@ def main():
         "adaptive_sampling": {"tf": "the orbit's TFs with opacity x 0.1", "by_max_exponent": adaptive},
         "binary16_pool": pool16,
         "two_level_page_table": vpt,
+        "requests_40_per_frame": req40,
         "path_tracing": pt,
         "context_aware_lod": lodc,
         "bricks_per_s": {k: round(v, 1) for k, v in bps.items()},
+        "decode_shape": {"chosen": {"parts_per_brick": decode_shape[0], "stage_kib": decode_shape[1]},
+                         "ms_per_request_list": {f"{p}x{k}": round(t, 4) for (p, k), t in decode_shape_ms.items()},
+                         "request_list": w.cache.max_requests, "dtype": args.dtype},
         "psnr_cached_vs_uncached_db": round(q_unc, 2),
         "vs_fp64_oracle": vs_oracle,
         "per_frame_in_timed_window": {k: round(tot[k] / K, 1) for k in ("rays", "samples", "hits", "fallbacks",
@@ -886,9 +963,10 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                      "algorithmic_bytes_per_launch": round(alg_bytes / max(march_n, 1)),
                      "launches": march_n, "avg_launch_ms": round(march_ms / max(march_n, 1), 5),
-                     "launches_before_timed": warm_stages["march"][1],
+                     "launches_before_timed": tune_launches + warm_stages["march"][1],
                      "launch_shape": dict(zip(("pipe_depth", "xcd_bands", "trials_left", "waves_per_simd"),
-                                              cinr.tuned_launch(vol, w.width, w.height)))},
+                                              cinr.tuned_launch(vol, w.width, w.height))),
+                     "launch_shape_tuned_over_frames": tune_frames},
         "multiview": multi,
         "training": train,
         "cpu_baseline": cpu,

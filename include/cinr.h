@@ -363,6 +363,37 @@ cinr_status cinr_infer_points(cinr_volume vol, const float* d_pos, int64_t n, fl
 cinr_status cinr_decode_bricks(cinr_volume vol, const int32_t* d_reqs, int32_t n, int32_t brick, float* d_out,
                                int32_t mlp_dtype, void* stream);
 
+/* Brick decoding with an explicit launch shape, for tuning and tests.
+ * parts_per_brick = 0: one point per lane over the whole request list, every
+ * corner read from the hash table (the layout of cinr_infer_points).
+ * Otherwise (brick <= 16; a larger brick uses parts_per_brick = 0) a
+ * workgroup takes one of parts_per_brick (1, 2, 4, 8 or 16; a divisor of
+ * `brick`) slabs of z-slices of a brick.  The lattice coordinates of a brick
+ * are separable, so each hash-grid level's cells and weights are computed per
+ * axis once per slab.  With stage_kib 32 or 64 (0: none), for each level the
+ * box of grid corners that the slab's lattice points touch is also copied
+ * into LDS once, smallest boxes first while they fit in stage_kib KiB and
+ * cost fewer reads than the points' own corner reads, and the slab's points
+ * interpolate those levels from LDS (Section 3's encoding over the regular
+ * lattice of a brick, Section 4.3.2).  Every shape gives the same bits. */
+cinr_status cinr_decode_bricks_shaped(cinr_volume vol, const int32_t* d_reqs, int32_t n, int32_t brick,
+                                      float* d_out, int32_t mlp_dtype, int32_t parts_per_brick, int32_t stage_kib,
+                                      void* stream);
+/* The launch shape (as above) that cinr_decode_bricks and the caches of this
+ * volume use for its brick decoding; the default is parts_per_brick = 0. */
+cinr_status cinr_set_decode_shape(cinr_volume vol, int32_t parts_per_brick, int32_t stage_kib);
+/* Autotuner of the decoding launch shape: decodes the n requests d_reqs
+ * (for example a recent request list) into d_out (scratch of n * brick^3
+ * floats) once per candidate shape to warm up and then `reps` times, timed
+ * with HIP events on `stream` (which is synchronised), sets the fastest as
+ * the volume's decode shape and returns its index in *chosen (nullable).
+ * ms_out (host, nullable) receives the 16 candidates' milliseconds per
+ * decode in this order of (parts_per_brick, stage_kib): (0, 0), then for
+ * parts_per_brick 1, 2, 4, 8 and 16 in turn stage_kib 0, 32 and 64; -1 for a
+ * shape `brick` does not admit.  Creates two events. */
+cinr_status cinr_tune_decode(cinr_volume vol, const int32_t* d_reqs, int32_t n, int32_t brick, float* d_out,
+                             int32_t mlp_dtype, int32_t reps, float* ms_out, int32_t* chosen, void* stream);
+
 /* Macro-cell table of Section 5.2 built from the INR itself: for each cell of
  * side `cell`, min and max of the LoD-0 lattice values in its closed region
  * [cN, min((c+1)N, V-1)]^3, written to d_minmax (layout as d_macrocells). */
@@ -503,17 +534,22 @@ cinr_status cinr_render_views(cinr_cache cache, int32_t n_views, const cinr_view
  * and workspace pointers, and every render parameter except frame_index.
  * Each cinr_frame_graph_render call renders one frame of those views with new
  * cameras and a new frame index, with the same results as cinr_render_views
- * (bit for bit), by replaying two captured graphs:
- *   - start: set-up and first march of every view (on the cache's side
- *     streams, as in cinr_render_views) and the pending-ray counts of all
- *     views, written to pinned host memory;
- *   - end: ranking, request selection, insertion, decoding and frame ends.
- * The host waits once between the two; views that still have pending rays
- * (true misses) finish their wavefront iterations with ordinary launches
- * before the end graph.  The camera, frame index and LoD seed are read from
- * device memory that the start graph fills from a host block, so the graphs
- * do not change from frame to frame; two end graphs are kept, with and
- * without the LRU victim pass.  While a view's launch shape is being tuned
+ * (bit for bit), by replaying one captured graph per frame: the set-up and
+ * first march of every view (on the cache's side streams, as in
+ * cinr_render_views), K further wavefront iterations of every view (true-miss
+ * inference, shading, march; K = 0 unless set by
+ * cinr_frame_graph_set_device_iterations), the pending-ray counts of all
+ * views after them written to pinned host memory, then ranking, request
+ * selection, insertion, decoding and the frame ends, which the device skips
+ * while any view has pending rays.  The queued iterations size their launches
+ * for every pixel and read their ray counts on the device (an iteration with
+ * no ray pending ends at once), so a frame that needs at most K + 1
+ * iterations makes no host round trip before its end.  The host waits for the
+ * pending counts; views that still have pending rays finish their wavefront
+ * iterations with ordinary launches, followed by the frame end.  The camera, frame index and LoD seed are read
+ * from device memory that the graph fills from a host block, so the graph
+ * does not change from frame to frame; two graphs are kept, with and without
+ * the LRU victim pass.  While a view's launch shape is being tuned
  * online (pipe_depth or xcd_bands 0), frames are rendered as by
  * cinr_render_views and nothing is captured.  Stage timing does not cover
  * graph frames.  The TF contents may change between frames (the macro-cell
@@ -528,6 +564,11 @@ cinr_status cinr_frame_graph_create(cinr_cache cache, int32_t n_views, const cin
 /* cameras: [n_views], in the order of the views given at creation. */
 cinr_status cinr_frame_graph_render(cinr_frame_graph graph, const cinr_camera* cameras, int32_t frame_index,
                                     void* stream);
+/* Wavefront iterations after the first march that the graph queues on the
+ * device (K above; 0 to 16, clamped to each view's iteration bound).  A new
+ * value synchronises the device and drops the captured graphs, which are
+ * captured again on their next use.  Errors: CINR_INVALID_ARG, CINR_HIP_ERROR. */
+cinr_status cinr_frame_graph_set_device_iterations(cinr_frame_graph graph, int32_t iterations);
 /* Frames rendered from the graphs, frames rendered eagerly (launch shape
  * still being tuned), and graph frames that needed further iterations. */
 cinr_status cinr_frame_graph_counts(cinr_frame_graph graph, int64_t* graph_frames, int64_t* eager_frames,

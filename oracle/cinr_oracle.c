@@ -1792,8 +1792,33 @@ int orc_render_pixels(const orc_inr* m, orc_cache* c, const orc_camera* cam, con
 /* Loss = mean over the batch of (y - target)^2 with y the raw network output
  * (training works on data normalised to [0,1], Section 4.1).  Gradients are
  * accumulated into g_table (same layout as the table) and g_weights. */
+/* x rounded to binary32, then to bfloat16 (the upper 16 bits of a binary32:
+ * 8 significant bits) to nearest, ties to even.  Infinities and NaNs are not
+ * expected here. */
+double orc_round_bf16(double x) {
+    float f = (float)x;
+    uint32_t b;
+    memcpy(&b, &f, sizeof b);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    b &= 0xFFFF0000u;
+    memcpy(&f, &b, sizeof f);
+    return (double)f;
+}
+
 double orc_loss_grad(const orc_inr* m, const double* u, const double* target, int64_t n, double* g_table,
                      double* g_weights) {
+    return orc_loss_grad_prec(m, u, target, n, g_table, g_weights, 0);
+}
+
+/* With bf16_operands, every operand of the products of the hidden layers --
+ * the encoded features, the activations entering a hidden layer, the weights
+ * of the layers before the output layer and the back-propagated errors
+ * leaving a ReLU -- is rounded by orc_round_bf16 before it is used (the
+ * precision contract of a BF16 matrix-core MLP: BF16 operands, wider
+ * accumulation); the output layer, the loss, the feature gradient and the
+ * scatter into the table stay in FP64.  Otherwise everything is FP64. */
+double orc_loss_grad_prec(const orc_inr* m, const double* u, const double* target, int64_t n, double* g_table,
+                          double* g_weights, int bf16_operands) {
     const int F = m->n_features, NL = m->n_levels;
     const int64_t T = (int64_t)1 << m->log2_table;
     int64_t nw = 0;
@@ -1809,9 +1834,15 @@ double orc_loss_grad(const orc_inr* m, const double* u, const double* target, in
         const float* W = m->weights;
         for (int k = 0; k < m->n_layers; ++k) {
             const int ni = m->widths[k], no = m->widths[k + 1];
+            const int q = bf16_operands && k + 1 < m->n_layers; /* a hidden layer's product */
+            if (q)
+                for (int cc = 0; cc < ni; ++cc) act[k][cc] = orc_round_bf16(act[k][cc]);
             for (int r = 0; r < no; ++r) {
                 double s = 0.0;
-                for (int cc = 0; cc < ni; ++cc) s += (double)W[r * ni + cc] * act[k][cc];
+                for (int cc = 0; cc < ni; ++cc) {
+                    const double w = q ? orc_round_bf16((double)W[r * ni + cc]) : (double)W[r * ni + cc];
+                    s += w * act[k][cc];
+                }
                 pre[k][r] = s;
                 act[k + 1][r] = (k + 1 < m->n_layers && s < 0.0) ? 0.0 : s;
             }
@@ -1829,13 +1860,16 @@ double orc_loss_grad(const orc_inr* m, const double* u, const double* target, in
             woff -= (int64_t)ni * no;
             const float* Wk = m->weights + woff;
             double* gW = g_weights + woff;
+            const int q = bf16_operands && k + 1 < m->n_layers;
             for (int cc = 0; cc < ni; ++cc) gin[cc] = 0.0;
             for (int r = 0; r < no; ++r) {
                 double gz = gout[r];
                 if (k + 1 < m->n_layers && pre[k][r] < 0.0) gz = 0.0;
+                if (q) gz = orc_round_bf16(gz);
                 for (int cc = 0; cc < ni; ++cc) {
+                    const double w = q ? orc_round_bf16((double)Wk[r * ni + cc]) : (double)Wk[r * ni + cc];
                     gW[r * ni + cc] += gz * act[k][cc];
-                    gin[cc] += (double)Wk[r * ni + cc] * gz;
+                    gin[cc] += w * gz;
                 }
             }
             for (int cc = 0; cc < ni; ++cc) gout[cc] = gin[cc];

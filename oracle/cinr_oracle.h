@@ -250,6 +250,15 @@ void orc_grid_trilinear(const float* grid, const int32_t dims[3], const double* 
 
 double orc_loss_grad(const orc_inr* m, const double* u, const double* target, int64_t n,
                      double* g_table, double* g_weights);
+/* orc_loss_grad with, when bf16_operands != 0, the operands of the hidden
+ * layers' products (features, activations, weights, back-propagated errors)
+ * rounded to bfloat16 before use; sums and everything else in FP64.  Parity
+ * unpinned for bf16_operands != 0: the rounding function is pinned by
+ * closed-form values, the placement of the roundings only by reading. */
+double orc_loss_grad_prec(const orc_inr* m, const double* u, const double* target, int64_t n,
+                          double* g_table, double* g_weights, int bf16_operands);
+/* x rounded to binary32 and then to bfloat16, to nearest even. */
+double orc_round_bf16(double x);
 void orc_adam_step(double* p, double* m1, double* m2, const double* g, int64_t n, int64_t step,
                    double lr, double b1, double b2, double eps);
 

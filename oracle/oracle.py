@@ -128,6 +128,8 @@ def lib():
             "orc_cache_set_ert_trace": (None, [P, C.c_int]),
             "orc_cache_ert_trace": (i64, [P, P, i64]),
             "orc_loss_grad": (C.c_double, [P, P, P, i64, P, P]),
+            "orc_loss_grad_prec": (C.c_double, [P, P, P, i64, P, P, C.c_int]),
+            "orc_round_bf16": (C.c_double, [C.c_double]),
             "orc_adam_step": (None, [P, P, P, P, i64, i64, C.c_double, C.c_double, C.c_double, C.c_double]),
             "orc_set_threads": (None, [C.c_int]),
             "orc_get_threads": (C.c_int, []),
@@ -582,13 +584,20 @@ class OracleCache:
         return out[:n]
 
 
-def loss_grad(inr: OracleInr, u, target):
+def loss_grad(inr: OracleInr, u, target, bf16_operands=False):
+    """Mean squared error and its gradients (table, weights); with
+    bf16_operands the hidden layers' product operands are rounded to bfloat16."""
     u = np.ascontiguousarray(u, np.float64).reshape(-1, 3)
     t = np.ascontiguousarray(target, np.float64)
     gt = np.zeros(inr.table.shape, np.float64)
     gw = np.zeros(inr.weights.shape, np.float64)
-    loss = lib().orc_loss_grad(inr.ref(), _ptr(u), _ptr(t), u.shape[0], _ptr(gt), _ptr(gw))
+    loss = lib().orc_loss_grad_prec(inr.ref(), _ptr(u), _ptr(t), u.shape[0], _ptr(gt), _ptr(gw),
+                                    1 if bf16_operands else 0)
     return loss, gt, gw
+
+
+def round_bf16(x):
+    return lib().orc_round_bf16(float(x))
 
 
 def train_points(seed, step, n):

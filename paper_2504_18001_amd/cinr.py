@@ -158,6 +158,9 @@ def lib():
             "cinr_lod_geometry": [P, i32, i32, P, P],
             "cinr_infer_points": [P, P, i64, P, i32, P],
             "cinr_decode_bricks": [P, P, i32, i32, P, i32, P],
+            "cinr_decode_bricks_shaped": [P, P, i32, i32, P, i32, i32, i32, P],
+            "cinr_set_decode_shape": [P, i32, i32],
+            "cinr_tune_decode": [P, P, i32, i32, P, i32, i32, P, P, P],
             "cinr_build_macrocells": [P, i32, P, i32, P],
             "cinr_cache_workspace_size": [P, P, P],
             "cinr_create_cache": [P, P, P, sz, P, sz, P, P],
@@ -187,6 +190,7 @@ def lib():
             "cinr_pt_free_flight": [P, i64, P, P],
             "cinr_frame_graph_render": [P, P, i32, P],
             "cinr_frame_graph_counts": [P, P, P, P],
+            "cinr_frame_graph_set_device_iterations": [P, i32],
             "cinr_frame_graph_destroy": [P],
         }
         for name, args in sig.items():
@@ -247,6 +251,34 @@ class _VolumeOps:
         out = torch.empty((n, brick, brick, brick), dtype=torch.float32, device=reqs.device) if out is None else out
         _check(lib().cinr_decode_bricks(self.h, _ptr(reqs), n, brick, _ptr(out), _dtype(dtype), _stream()))
         return out
+
+    def decode_bricks_shaped(self, reqs, brick, dtype="f32", parts=0, stage_kib=64, out=None):
+        """decode_bricks with an explicit launch shape (parts per brick, LDS
+        budget of the staged corner boxes)."""
+        reqs = reqs.to(torch.int32).contiguous()
+        n = reqs.shape[0]
+        out = torch.empty((n, brick, brick, brick), dtype=torch.float32, device=reqs.device) if out is None else out
+        _check(lib().cinr_decode_bricks_shaped(self.h, _ptr(reqs), n, brick, _ptr(out), _dtype(dtype), int(parts),
+                                               int(stage_kib), _stream()))
+        return out
+
+    DECODE_SHAPES = ((0, 0),) + tuple((p, k) for p in (1, 2, 4, 8, 16) for k in (0, 32, 64))
+
+    def tune_decode(self, reqs, brick, dtype="f32", reps=3):
+        """Times every decoding launch shape on the requests `reqs` and keeps
+        the fastest for this volume; returns (chosen shape, {shape: ms})."""
+        reqs = reqs.to(torch.int32).contiguous()
+        n = reqs.shape[0]
+        out = torch.empty((n, brick, brick, brick), dtype=torch.float32, device=reqs.device)
+        ms = np.zeros(len(self.DECODE_SHAPES), np.float32)
+        chosen = C.c_int32()
+        _check(lib().cinr_tune_decode(self.h, _ptr(reqs), n, brick, _ptr(out), _dtype(dtype), int(reps),
+                                      ms.ctypes.data_as(C.c_void_p), C.byref(chosen), _stream()))
+        return self.DECODE_SHAPES[chosen.value], {s: float(t) for s, t in zip(self.DECODE_SHAPES, ms) if t >= 0}
+
+    def set_decode_shape(self, parts, stage_kib=64):
+        """Launch shape of this volume's brick decoding (decode_bricks and caches)."""
+        _check(lib().cinr_set_decode_shape(self.h, int(parts), int(stage_kib)))
 
     def set_timing(self, on, march_only=False):
         """Stage timing off, on (every stage) or, with march_only, on the march launches only."""
@@ -680,6 +712,10 @@ class FrameGraph:
         arr = (CameraDesc * self.n)(*[camera_desc(c) for c in cameras])
         _check(lib().cinr_frame_graph_render(self.h, arr, int(frame_index), _stream()))
         return self.outs
+
+    def set_device_iterations(self, k):
+        """Wavefront iterations after the first march queued in the graph (0 to 16)."""
+        _check(lib().cinr_frame_graph_set_device_iterations(self.h, int(k)))
 
     def counts(self):
         """(graph frames, eager frames, graph frames with further iterations)."""

@@ -96,11 +96,13 @@ SMALL = Workload(
 
 # 512^3 random INR at 1920x1080 perspective, 60-frame orbit (6 degrees per frame,
 # 20 degree elevation), TF switched at frame 30 from the ramp to a random table
-# drawn i.i.d. per row and channel, B = 16, 4 LoDs, 2 GiB pool.
+# drawn i.i.d. per row and channel, B = 16, 4 LoDs, 2 GiB pool, up to 256
+# bricks decoded per frame (1.05 M voxels, within the 40 bricks of 40^3 =
+# 2.56 M voxels per frame of Sec. 6.1).
 HD512 = Workload(
     name="inr512_persp1080p", arch=ARCH_512, inr_seed=0, width=1920, height=1080,
     projection=synth.PERSPECTIVE, n_frames=60, step=0.5, lod_scale=1.0 / 800.0,
-    cache=CacheShape(brick=16, n_lods=4, pool_bricks=(2 << 30) // (16 ** 3 * 4), max_requests=40,
+    cache=CacheShape(brick=16, n_lods=4, pool_bricks=(2 << 30) // (16 ** 3 * 4), max_requests=256,
                      preload_period=4),
     orbit_radius=1159.0, orbit_elev_deg=20.0, orbit_step_deg=6.0, tf_switch_frame=30,
     samples_per_iter=32,

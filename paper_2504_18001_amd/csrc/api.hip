@@ -149,6 +149,7 @@ struct cinr_volume_s {
     hipEvent_t ev = nullptr;
     Timing timing;
     std::map<uint64_t, SamplerTuner> tuners;  // by image size
+    DecodeShape decode_shape;                 // launch shape of this volume's brick decoding
 };
 
 namespace {
@@ -380,8 +381,21 @@ extern "C" cinr_status cinr_infer_points(cinr_volume v, const float* d_pos, int6
     return CINR_OK;
 }
 
-extern "C" cinr_status cinr_decode_bricks(cinr_volume v, const int32_t* d_reqs, int32_t n, int32_t brick, float* d_out,
-                                          int32_t prec, void* stream) {
+namespace {
+cinr_status check_decode_shape(int32_t brick, int32_t parts, int32_t stage_kib, DecodeShape* out) {
+    if (parts != 0 && parts != 1 && parts != 2 && parts != 4 && parts != 8 && parts != 16)
+        return fail(CINR_INVALID_ARG, "parts_per_brick = %d (0, 1, 2, 4, 8 or 16)", parts);
+    if (parts > 0 && stage_kib != 0 && stage_kib != 32 && stage_kib != 64)
+        return fail(CINR_INVALID_ARG, "stage_kib = %d (0, 32 or 64)", stage_kib);
+    if (parts > 0 && brick > 0 && brick % parts != 0)
+        return fail(CINR_INVALID_ARG, "brick %d is not a multiple of parts_per_brick %d", brick, parts);
+    out->parts = parts;
+    out->stage_floats = parts > 0 ? stage_kib * 256 : 0;
+    return CINR_OK;
+}
+
+cinr_status decode_with(cinr_volume v, const int32_t* d_reqs, int32_t n, int32_t brick, float* d_out, int32_t prec,
+                        DecodeShape shape, void* stream) {
     if (!v || n < 0 || (n > 0 && (!d_reqs || !d_out))) return fail(CINR_INVALID_ARG, "invalid arguments");
     if (brick < 2 || brick > 64) return fail(CINR_INVALID_ARG, "brick = %d out of [2, 64]", brick);
     cinr_status st = check_shape(v, prec);
@@ -389,7 +403,82 @@ extern "C" cinr_status cinr_decode_bricks(cinr_volume v, const int32_t* d_reqs, 
     CacheGeom g;
     geometry(v->desc.dims, brick, kMaxLods, g);
     const BrickOut out{d_out, nullptr, 0x7FFFFFFF};
-    HIP_TRY(inr_decode_bricks(v->m, g, d_reqs, nullptr, nullptr, n, nullptr, out, prec, (hipStream_t)stream));
+    if (brick % (shape.parts > 0 ? shape.parts : 1) != 0) shape = DecodeShape{};
+    HIP_TRY(inr_decode_bricks(v->m, g, d_reqs, nullptr, nullptr, n, nullptr, out, prec, (hipStream_t)stream, shape));
+    return CINR_OK;
+}
+}  // namespace
+
+extern "C" cinr_status cinr_decode_bricks(cinr_volume v, const int32_t* d_reqs, int32_t n, int32_t brick, float* d_out,
+                                          int32_t prec, void* stream) {
+    if (!v) return fail(CINR_INVALID_ARG, "invalid arguments");
+    return decode_with(v, d_reqs, n, brick, d_out, prec, v->decode_shape, stream);
+}
+
+extern "C" cinr_status cinr_decode_bricks_shaped(cinr_volume v, const int32_t* d_reqs, int32_t n, int32_t brick,
+                                                 float* d_out, int32_t prec, int32_t parts, int32_t stage_kib,
+                                                 void* stream) {
+    DecodeShape shape;
+    cinr_status st = check_decode_shape(brick, parts, stage_kib, &shape);
+    if (st) return st;
+    return decode_with(v, d_reqs, n, brick, d_out, prec, shape, stream);
+}
+
+namespace {
+// Candidate launch shapes of brick decoding (parts per brick, stage KiB),
+// in the order cinr_tune_decode reports their times.
+constexpr int kDecodeCand = 16;
+constexpr int32_t kDecodeParts[kDecodeCand] = {0, 1, 1, 1, 2, 2, 2, 4, 4, 4, 8, 8, 8, 16, 16, 16};
+constexpr int32_t kDecodeKib[kDecodeCand] = {0, 0, 32, 64, 0, 32, 64, 0, 32, 64, 0, 32, 64, 0, 32, 64};
+}  // namespace
+
+extern "C" cinr_status cinr_tune_decode(cinr_volume v, const int32_t* d_reqs, int32_t n, int32_t brick, float* d_out,
+                                        int32_t prec, int32_t reps, float* ms_out, int32_t* chosen, void* stream) {
+    if (!v || n < 1 || !d_reqs || !d_out || reps < 1) return fail(CINR_INVALID_ARG, "invalid arguments");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t a = nullptr, b = nullptr;
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    int best = -1;
+    float best_ms = 0.0f;
+    cinr_status st = CINR_OK;
+    for (int i = 0; i < kDecodeCand && st == CINR_OK; ++i) {
+        float ms = -1.0f;
+        if (kDecodeParts[i] == 0 || brick % kDecodeParts[i] == 0) {
+            DecodeShape shape;
+            st = check_decode_shape(brick, kDecodeParts[i], kDecodeKib[i], &shape);
+            if (st == CINR_OK) st = decode_with(v, d_reqs, n, brick, d_out, prec, shape, stream);  // warm-up
+            if (st == CINR_OK && hipEventRecord(a, s) != hipSuccess) st = fail(CINR_HIP_ERROR, "event record");
+            for (int r = 0; r < reps && st == CINR_OK; ++r) st = decode_with(v, d_reqs, n, brick, d_out, prec, shape, stream);
+            if (st == CINR_OK && (hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                                  hipEventElapsedTime(&ms, a, b) != hipSuccess))
+                st = fail(CINR_HIP_ERROR, "decode timing");
+            if (st == CINR_OK) {
+                ms /= (float)reps;
+                if (best < 0 || ms < best_ms) {
+                    best = i;
+                    best_ms = ms;
+                }
+            }
+        }
+        if (ms_out) ms_out[i] = ms;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (st) return st;
+    DecodeShape shape;
+    check_decode_shape(brick, kDecodeParts[best], kDecodeKib[best], &shape);
+    v->decode_shape = shape;
+    if (chosen) *chosen = best;
+    return CINR_OK;
+}
+
+extern "C" cinr_status cinr_set_decode_shape(cinr_volume v, int32_t parts, int32_t stage_kib) {
+    if (!v) return fail(CINR_INVALID_ARG, "null volume");
+    DecodeShape shape;
+    cinr_status st = check_decode_shape(0, parts, stage_kib, &shape);
+    if (st) return st;
+    v->decode_shape = shape;
     return CINR_OK;
 }
 
@@ -586,9 +675,9 @@ static hipError_t decode_selected(cinr_cache c, int32_t n_cap, int32_t prec, con
     }
     if (c->vols.size() == 1)
         return inr_decode_bricks(c->vols[0]->m, c->g, cd.ins_reqs, &cd.ctr->n_sel, gate, n_cap, cd.ins_slots, out,
-                                 prec, s);
+                                 prec, s, c->vols[0]->decode_shape);
     return inr_decode_bricks_multi(c->d_vols, c->vols[0]->m, c->g, cd.ins_reqs, cd.ins_vols, &cd.ctr->n_sel, gate,
-                                   n_cap, cd.ins_slots, out, prec, s);
+                                   n_cap, cd.ins_slots, out, prec, s, c->vols[0]->decode_shape);
 }
 
 extern "C" void cinr_destroy_cache(cinr_cache c) { delete c; }
@@ -1007,6 +1096,17 @@ cinr_status view_continue(ViewRun& r, uint32_t pending, Timing& tm, hipStream_t 
     return CINR_OK;
 }
 
+// Wavefront iteration `it` >= 1 of a view queued without knowing how many
+// rays the previous one left: the launches read their counts on the device
+// (nothing to do when no ray is pending) and the march takes its full
+// persistent grid.
+cinr_status view_device_iteration(ViewRun& r, int it, hipStream_t s) {
+    HIP_TRY(inr_infer_misses(r.v->m, r.f.miss_rec, &r.f.ctr[it - 1].misses, r.npix * r.f.S, r.f.vals, r.prec, s));
+    HIP_TRY(launch_shade(r.f, it - 1, r.npix, s));
+    HIP_TRY(launch_march(r.f, it, r.npix, s));
+    return CINR_OK;
+}
+
 // Tuner bookkeeping once the view's first march has completed.
 cinr_status tuner_collect(ViewRun& r, uint32_t first_pending) {
     SamplerTuner* t = r.tuner;
@@ -1209,7 +1309,7 @@ cinr_status render_frame_views(cinr_cache c, std::vector<ViewRun>& runs, Timing&
     }
     std::vector<const FrameDev*> fs;
     for (const ViewRun& r : runs) fs.push_back(&r.f);
-    if (!fused) HIP_TRY(launch_pending_gather(fs.data(), (int)runs.size(), pinned, gate, s));
+    if (!fused) HIP_TRY(launch_pending_gather(fs.data(), (int)runs.size(), 0, pinned, gate, s));
     HIP_TRY(hipEventRecord(rv->ev, s));
     const bool lru = c && lru_pass_needed(c);
     st = end_views(c, runs, lru, tm, gate, s);
@@ -1409,7 +1509,7 @@ extern "C" cinr_status cinr_render_frame_noalloc(cinr_cache c, cinr_volume v, co
         r.f.gather_host = r.f.gather_gate = r.f.exit_ticket = nullptr;
     } else {
         const FrameDev* fp = &r.f;
-        HIP_TRY(launch_pending_gather(&fp, 1, word, r.L.gate, s));
+        HIP_TRY(launch_pending_gather(&fp, 1, 0, word, r.L.gate, s));
     }
     // the frame end, gated on the device (nothing runs while rays pend)
     const bool lru = cc && lru_pass_needed(cc);
@@ -1479,6 +1579,8 @@ extern "C" cinr_status cinr_render_views(cinr_cache c, int32_t n_views, const ci
 // Captured multi-view frames
 // ---------------------------------------------------------------------------
 
+constexpr int32_t kMaxDeviceIters = 16;
+
 struct cinr_frame_graph_s {
     cinr_cache c = nullptr;
     std::vector<cinr_view> views;
@@ -1486,12 +1588,14 @@ struct cinr_frame_graph_s {
     uint32_t* pending = nullptr;  // pinned [n]: rays pending after the first marches, written by the start graph
     hipStream_t cs = nullptr;     // capture stream (default priority)
     hipEvent_t ev = nullptr;
-    hipGraphExec_t start = nullptr;               // set-up and first march of every view, pending counts
-    hipGraphExec_t end[2] = {nullptr, nullptr};   // cache manager, decoding, frame ends; [1] with the LRU pass
+    // the whole frame: set-up and first march of every view, pending counts,
+    // then cache manager, decoding and frame ends gated on no pending ray;
+    // [1] with the LRU victim pass
+    hipGraphExec_t frame[2] = {nullptr, nullptr};
+    int32_t dev_iters = 0;  // wavefront iterations after the first march queued in the graph
     int64_t n_graph = 0, n_eager = 0, n_tail = 0;
     ~cinr_frame_graph_s() {
-        if (start) (void)hipGraphExecDestroy(start);
-        for (hipGraphExec_t e : end)
+        for (hipGraphExec_t e : frame)
             if (e) (void)hipGraphExecDestroy(e);
         if (ev) (void)hipEventDestroy(ev);
         if (cs) (void)hipStreamDestroy(cs);
@@ -1593,47 +1697,51 @@ extern "C" cinr_status cinr_frame_graph_render(cinr_frame_graph g, const cinr_ca
         runs[i].st = side ? c->vs[i % cinr_cache_s::kViewStreams] : g->cs;
         runs[i].stage = g->stage + i;
     }
-    if (!g->start) {
+    const bool lru = lru_pass_needed(c);
+    // iterations queued on the device: at most every view's bound minus the first
+    int32_t K = g->dev_iters;
+    for (const ViewRun& r : runs) K = (int32_t)std::min<int64_t>(K, r.max_iters - 1);
+    if (K < 0) K = 0;
+    if (!g->frame[lru]) {
         TimingOff off(runs);
-        st = capture(g, &g->start, [&](hipStream_t cs) -> cinr_status {
+        Timing none;
+        st = capture(g, &g->frame[lru], [&](hipStream_t cs) -> cinr_status {
             cinr_status r = start_views(c, runs, side, cs);
             if (r) return r;
             if (side) {
                 r = join_side_streams(c, cs);
                 if (r) return r;
             }
+            for (int32_t k = 1; k <= K; ++k)
+                for (ViewRun& v : runs) {
+                    r = view_device_iteration(v, k, cs);
+                    if (r) return r;
+                }
             std::vector<const FrameDev*> fs;
             for (const ViewRun& v : runs) fs.push_back(&v.f);
-            HIP_TRY(launch_pending_gather(fs.data(), n, g->pending, runs[0].L.gate, cs));
-            return CINR_OK;
+            HIP_TRY(launch_pending_gather(fs.data(), n, K, g->pending, runs[0].L.gate, cs));
+            return end_views(c, runs, lru, none, runs[0].L.gate, cs);
         });
-        if (st) return st;
-    }
-    const bool lru = lru_pass_needed(c);
-    if (!g->end[lru]) {
-        TimingOff off(runs);
-        Timing none;
-        st = capture(g, &g->end[lru], [&](hipStream_t cs) { return end_views(c, runs, lru, none, runs[0].L.gate, cs); });
         if (st) return st;
     }
     for (int32_t i = 0; i < n; ++i) g->stage[i] = runs[i].hv;
     reset_pending(g->pending, n);
-    // the end graph is gated: it does nothing if a view still has rays pending
-    HIP_TRY(hipGraphLaunch(g->start, s));
+    // one graph per frame; its frame end does nothing if a view still has
+    // rays pending after the first marches and the K iterations behind them
+    HIP_TRY(hipGraphLaunch(g->frame[lru], s));
     HIP_TRY(hipEventRecord(g->ev, s));
-    HIP_TRY(hipGraphLaunch(g->end[lru], s));
     st = poll_pending(g->pending, n, g->ev);
     if (st) return st;
     std::vector<uint32_t> known(n);
     bool tail = false;
     for (int32_t i = 0; i < n; ++i) {
         known[i] = ((volatile uint32_t*)g->pending)[i];
-        runs[i].n_iters = 1;
+        runs[i].n_iters = 1 + K;
         runs[i].st = s;
         tail = tail || known[i] != 0u;
     }
     if (tail) {
-        // rays left after the first marches (true misses): the remaining
+        // rays left after the queued iterations (true misses): the remaining
         // iterations and the frame end run eagerly on `s`
         g->n_tail += 1;
         cinr_volume rv = runs[0].v;
@@ -1645,6 +1753,22 @@ extern "C" cinr_status cinr_frame_graph_render(cinr_frame_graph g, const cinr_ca
     }
     note_insertions(c);
     g->n_graph += 1;
+    return CINR_OK;
+}
+
+extern "C" cinr_status cinr_frame_graph_set_device_iterations(cinr_frame_graph g, int32_t iterations) {
+    if (!g) return fail(CINR_INVALID_ARG, "null argument");
+    if (iterations < 0 || iterations > kMaxDeviceIters)
+        return fail(CINR_INVALID_ARG, "iterations = %d out of [0, %d]", iterations, kMaxDeviceIters);
+    if (iterations == g->dev_iters) return CINR_OK;
+    // graphs of the old count are captured again on their next use; none of
+    // their launches may still be running when they are destroyed
+    HIP_TRY(hipDeviceSynchronize());
+    for (hipGraphExec_t& e : g->frame) {
+        if (e) HIP_TRY(hipGraphExecDestroy(e));
+        e = nullptr;
+    }
+    g->dev_iters = iterations;
     return CINR_OK;
 }
 

@@ -88,6 +88,13 @@ struct BrickOut {
     int32_t split;
 };
 
+// Launch shape of brick decoding: parts per brick and the LDS budget (floats)
+// of the staged corner boxes; parts = 0 decodes without staging.
+struct DecodeShape {
+    int32_t parts = 0;
+    int32_t stage_floats = 0;
+};
+
 struct CacheGeom {
     int32_t brick;
     FastDiv div_b1;  // division by brick - 1

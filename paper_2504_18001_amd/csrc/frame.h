@@ -312,11 +312,13 @@ hipError_t launch_pt_free_flight(const uint32_t* words, int64_t n, float* out, h
 hipError_t launch_store_var(const FrameVar& v, FrameVar* dst, hipStream_t s);
 // `gate` (nullable) on the frame-end launches: they do nothing unless *gate is
 // non-zero, which k_pending_gather sets when no view has a ray pending after
-// its first march.  The end of a frame can so be queued before the host has
-// read the pending counts.
+// its iteration `it` (the first march, or the last iteration queued without
+// a host round trip).  The end of a frame can so be queued before the host
+// has read the pending counts.
 hipError_t launch_frame_end(const FrameDev& f, int max_iters, CacheCtr* cctr, bool reset, const uint32_t* gate,
                             hipStream_t s);
-hipError_t launch_pending_gather(const FrameDev* const* fs, int n, uint32_t* host_out, uint32_t* gate, hipStream_t s);
+hipError_t launch_pending_gather(const FrameDev* const* fs, int n, int it, uint32_t* host_out, uint32_t* gate,
+                                 hipStream_t s);
 
 // cache launchers
 hipError_t launch_cache_init(const CacheDev& c, int64_t n_keys, int64_t n_dir, hipStream_t s);
@@ -337,7 +339,7 @@ hipError_t inr_infer_points(const InrDev& m, const float* pos, int64_t n, float*
 // gate: nullable, as for the frame-end launches (no brick is decoded unless *gate != 0)
 hipError_t inr_decode_bricks(const InrDev& m, const CacheGeom& g, const int32_t* reqs, const uint32_t* n_dev,
                              const uint32_t* gate, int32_t n_cap, const int32_t* slots, const BrickOut& out,
-                             int prec, hipStream_t s);
+                             int prec, hipStream_t s, DecodeShape shape = DecodeShape{});
 hipError_t inr_macrocells(const InrDev& m, int32_t N, float* minmax, int prec, hipStream_t s);
 hipError_t inr_infer_misses(const InrDev& m, const float4* rec, const uint32_t* n_dev, int64_t cap, float* vals,
                             int prec, hipStream_t s);
@@ -345,7 +347,7 @@ hipError_t inr_infer_misses(const InrDev& m, const float4* rec, const uint32_t* 
 // descriptors, `shape` any of them on the host)
 hipError_t inr_decode_bricks_multi(const InrDev* d_vols, const InrDev& shape, const CacheGeom& g, const int32_t* reqs,
                                    const int32_t* vols, const uint32_t* n_dev, const uint32_t* gate, int32_t n_cap,
-                                   const int32_t* slots, const BrickOut& out, int prec, hipStream_t s);
+                                   const int32_t* slots, const BrickOut& out, int prec, hipStream_t s, DecodeShape ds = DecodeShape{});
 
 // train.hip launchers
 bool train_shape_supported(const InrDev& m);

@@ -14,6 +14,8 @@
 //    permuted to match.  Hidden activations never leave registers.
 //  - the last layer (width 1) is a per-lane dot product in FP32 reduced across
 //    the four 16-lane groups; lane l ends with the output of point l.
+#include <type_traits>
+
 #include "common.h"
 #include "inr_engine.h"
 
@@ -57,6 +59,20 @@ struct BrickSrc {
         return n_dev ? (int64_t)*n_dev : (int64_t)n_host;
     }
     __device__ int64_t count() const { return n_requests() * B3; }
+    // Voxel coordinate along axis a of lattice index i of request r (the
+    // per-axis part of position); *ok as position's result.
+    __device__ double axis_x(int64_t r, int a, int32_t i, bool* ok) const {
+        const int32_t* q = reqs + 4 * r;
+        const int32_t L = q[0];
+        const bool okl = L >= 0 && L < n_lods;
+        const int32_t Ls = okl ? L : 0;
+        const int32_t b = q[1 + a];
+        const bool ba = b >= 0 && b < nb[Ls][a];
+        int64_t xa = ((int64_t)(ba ? b : 0) * (B - 1) + i) << Ls;
+        if (xa > dims[a] - 1) xa = dims[a] - 1;
+        *ok = okl && ba;
+        return (double)xa;
+    }
     // returns false for an invalid request
     __device__ bool position(int64_t idx, double x[3]) const {
         const int32_t r = (int32_t)(idx / B3);
@@ -146,6 +162,162 @@ __global__ __launch_bounds__(kBlock) void k_decode(const InrDev m, const BrickSr
 // items, so that every round stays inside one brick; a workgroup reloads the
 // MLP weights only when its next brick belongs to another volume.  The list
 // may mix volumes and LoDs in any order.
+// Brick decoding by parts of bricks.  Work item = one part of a brick
+// (`parts` parts of B/parts z-slices each, B <= 16), all 256 lanes.  The
+// lattice coordinates of a brick are separable, so each level's cells and
+// weights along each axis are computed once per item (the same FP64
+// operations as for a single point) into a table in LDS.  With
+// kStageFloats > 0, the grid corners the part's lattice points touch form a
+// box per level (from the part's first and last points: the lattice
+// coordinates, u and the cell index are all monotone); boxes are staged in
+// LDS smallest first while they fit in kStageFloats floats and cost fewer
+// reads than the points' own corner reads.  Every variant gives the same bits
+// (same cells, weights and order).  vol_ok false gives NaN (a request of no
+// volume).
+constexpr int kTabB = 16;  // largest brick side of the per-axis tables
+template <class Eng, int kStageFloats>
+__device__ void decode_item_staged(const InrDev& m, Eng& eng, typename Eng::Lds& lds, float* stage, StageLevel* sl,
+                                   int64_t* vol_s, uint2* ctab, const BrickSrc& src, const BrickDst& dst, int64_t r,
+                                   int32_t part, int32_t parts, bool vol_ok) {
+    constexpr int F = Eng::F;
+    const int NL = m.n_levels;
+    const int32_t B = src.B, per = src.B3 / parts, first = part * per;
+    const int64_t i0 = r * src.B3 + first;
+    for (int t = threadIdx.x; t < NL * 3 * B; t += kBlock) {
+        const int l = t / (3 * B), rem = t - l * 3 * B, a = rem / B, i = rem - a * B;
+        bool ok;
+        double xa = src.axis_x(r, a, i, &ok);
+        xa = xa < 0.0 ? 0.0 : xa;
+        xa = xa > (double)m.vm1[a] ? (double)m.vm1[a] : xa;
+        const double u = (xa + 0.5) * m.inv_dims[a];
+        const double sa = u * m.lv[l].res;
+        const double fa = floor(sa);
+        ctab[t] = make_uint2((uint32_t)fa, __float_as_uint((float)(sa - fa)));
+    }
+    if (kStageFloats > 0 && (int)threadIdx.x < NL) {
+        double xa[3], xb[3], ua[3], ub[3];
+        src.position(i0, xa);
+        src.position(i0 + per - 1, xb);
+        to_unit(m, xa, ua);
+        to_unit(m, xb, ub);
+        const LevelDev& lv = m.lv[threadIdx.x];
+        StageLevel q;
+        int64_t vol = 1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            q.lo[a] = (int32_t)floor(ua[a] * lv.res);
+            q.e[a] = (int32_t)floor(ub[a] * lv.res) + 2 - q.lo[a];
+            vol *= q.e[a];
+        }
+        q.off = -1;
+        sl[threadIdx.x] = q;
+        vol_s[threadIdx.x] = vol;
+    }
+    __syncthreads();
+    if (kStageFloats > 0) {
+        if (threadIdx.x == 0) {
+            uint32_t taken = 0u;
+            int64_t used = 0;
+            for (int k = 0; k < NL; ++k) {
+                int best = -1;
+                for (int l = 0; l < NL; ++l)
+                    if (!((taken >> l) & 1u) && (best < 0 || vol_s[l] < vol_s[best])) best = l;
+                taken |= 1u << best;
+                const int64_t need = (vol_s[best] * F + 3) & ~(int64_t)3;
+                if (used + need <= kStageFloats && vol_s[best] < 8 * (int64_t)per) {
+                    sl[best].off = (int32_t)used;
+                    used += need;
+                }
+            }
+        }
+        __syncthreads();
+        for (int l = 0; l < NL; ++l) {
+            const StageLevel q = sl[l];
+            if (q.off < 0) continue;
+            const LevelDev& lv = m.lv[l];
+            const int32_t ex = q.e[0], exy = q.e[0] * q.e[1], vol = exy * q.e[2];
+            const float* tb = m.table + (size_t)lv.offset * F;
+            for (int32_t k = threadIdx.x; k < vol; k += kBlock) {
+                const int32_t cz = k / exy, rem = k - cz * exy, cy = rem / ex, cx = rem - cy * ex;
+                const uint32_t c0 = (uint32_t)(q.lo[0] + cx), c1 = (uint32_t)(q.lo[1] + cy),
+                               c2 = (uint32_t)(q.lo[2] + cz);
+                const uint32_t idx = lv.mask == 0u ? c0 + c1 * lv.side + c2 * lv.side2
+                                                   : (c0 ^ (c1 * kPrime1) ^ (c2 * kPrime2)) & lv.mask;
+                float e[F];
+                Entry<F>::load(tb + (size_t)idx * F, e);
+#pragma unroll
+                for (int j = 0; j < F; ++j) stage[q.off + k * F + j] = e[j];
+            }
+        }
+        __syncthreads();
+    }
+    double x0[3];
+    const bool ok = src.position(i0, x0) && vol_ok;  // the request's validity (the same for all its points)
+    for (int32_t b0 = 0; b0 < per; b0 += kBlock) {
+        const int32_t i = b0 + (int32_t)threadIdx.x;
+        const bool valid = i < per;
+        const int32_t gi = first + (valid ? i : 0);
+        CoordTab co;
+        co.tab = ctab;
+        co.n = B;
+        co.i[0] = gi % B;
+        co.i[1] = (gi / B) % B;
+        co.i[2] = gi / (B * B);
+        const float v = eng.eval_c(m, co, lds, kStageFloats > 0 ? sl : nullptr, stage);
+        if (valid) dst.store(i0 + i, ok ? v : __builtin_nanf(""));
+    }
+    __syncthreads();  // the tables, stage and boxes are refilled for the next item
+}
+
+template <class Eng, int kStageFloats>
+__global__ __launch_bounds__(kBlock) void k_decode_staged(const InrDev m, const BrickSrc src, const BrickDst dst,
+                                                          int32_t parts) {
+    const int64_t items = src.n_requests() * parts;
+    // sized for the request cap: idle workgroups leave before the weights
+    if ((int64_t)blockIdx.x >= items) return;
+    Eng eng;
+    eng.load_weights(m);
+    __shared__ typename Eng::Lds lds;
+    __shared__ float stage[kStageFloats > 0 ? kStageFloats : 1];
+    __shared__ StageLevel sl[kMaxLevels];
+    __shared__ int64_t vol_s[kMaxLevels];
+    __shared__ uint2 ctab[kMaxLevels * 3 * kTabB];
+    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const int64_t r = it / parts;
+        decode_item_staged<Eng, kStageFloats>(m, eng, lds, stage, sl, vol_s, ctab, src, dst, r,
+                                              (int32_t)(it - r * parts), parts, true);
+    }
+}
+
+// The same over the bricks of several volumes of one shape (a shared cache):
+// request r belongs to volume req_vol[r]; weights are reloaded when a
+// workgroup's volume changes.
+template <class Eng, int kStageFloats>
+__global__ __launch_bounds__(kBlock) void k_decode_staged_multi(const InrDev* vols, const BrickSrc src,
+                                                                const int32_t* req_vol, const BrickDst dst,
+                                                                int32_t parts) {
+    const int64_t items = src.n_requests() * parts;
+    if ((int64_t)blockIdx.x >= items) return;
+    Eng eng;
+    int32_t cur = -1;
+    __shared__ typename Eng::Lds lds;
+    __shared__ float stage[kStageFloats > 0 ? kStageFloats : 1];
+    __shared__ StageLevel sl[kMaxLevels];
+    __shared__ int64_t vol_s[kMaxLevels];
+    __shared__ uint2 ctab[kMaxLevels * 3 * kTabB];
+    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const int64_t r = it / parts;
+        const int32_t v = req_vol[r];
+        const InrDev& m = vols[v < 0 ? 0 : v];
+        if (v != cur) {
+            eng.load_weights(m);
+            cur = v;
+        }
+        decode_item_staged<Eng, kStageFloats>(m, eng, lds, stage, sl, vol_s, ctab, src, dst, r,
+                                              (int32_t)(it - r * parts), parts, v >= 0);
+    }
+}
+
 template <class Eng>
 __global__ __launch_bounds__(kBlock) void k_decode_multi(const InrDev* vols, const BrickSrc src, const int32_t* req_vol,
                                                          const BrickDst dst) {
@@ -298,6 +470,53 @@ static hipError_t launch_all(int what, const InrDev& m, const void* a, hipStream
             hipLaunchKernelGGL((k_decode_multi<Eng>), dim3(blocks), dim3(kBlock), 0, s, vols, *src, req_vol, *dst);
             break;
         }
+        case 5: {
+            // LDS-staged decoding (INR engines only): a[2] = {parts, stage floats}
+            const BrickSrc* src = (const BrickSrc*)((const void* const*)a)[0];
+            const BrickDst* dst = (const BrickDst*)((const void* const*)a)[1];
+            const int32_t* shape = (const int32_t*)((const void* const*)a)[2];
+            if constexpr (std::is_same<Eng, GridEngine>::value) {
+                hipLaunchKernelGGL((k_decode<Eng>), dim3(grid_for((int64_t)src->n_host * src->B3, kMaxInrBlocks)),
+                                   dim3(kBlock), 0, s, m, *src, *dst);
+            } else {
+                const int64_t items = (int64_t)src->n_host * shape[0];
+                const int blocks = (int)(items < kMaxInrBlocks ? (items < 1 ? 1 : items) : kMaxInrBlocks);
+                if (shape[1] <= 0)
+                    hipLaunchKernelGGL((k_decode_staged<Eng, 0>), dim3(blocks), dim3(kBlock), 0, s, m, *src, *dst,
+                                       shape[0]);
+                else if (shape[1] <= 8192)
+                    hipLaunchKernelGGL((k_decode_staged<Eng, 8192>), dim3(blocks), dim3(kBlock), 0, s, m, *src, *dst,
+                                       shape[0]);
+                else
+                    hipLaunchKernelGGL((k_decode_staged<Eng, 16384>), dim3(blocks), dim3(kBlock), 0, s, m, *src,
+                                       *dst, shape[0]);
+            }
+            break;
+        }
+        case 6: {
+            // LDS-staged decoding over several volumes: a[4] = {parts, stage floats}
+            const BrickSrc* src = (const BrickSrc*)((const void* const*)a)[0];
+            const BrickDst* dst = (const BrickDst*)((const void* const*)a)[1];
+            const InrDev* vols = (const InrDev*)((const void* const*)a)[2];
+            const int32_t* req_vol = (const int32_t*)((const void* const*)a)[3];
+            const int32_t* shape = (const int32_t*)((const void* const*)a)[4];
+            if constexpr (std::is_same<Eng, GridEngine>::value) {
+                return hipErrorInvalidValue;
+            } else {
+                const int64_t items = (int64_t)src->n_host * shape[0];
+                const int blocks = (int)(items < kMaxInrBlocks ? (items < 1 ? 1 : items) : kMaxInrBlocks);
+                if (shape[1] <= 0)
+                    hipLaunchKernelGGL((k_decode_staged_multi<Eng, 0>), dim3(blocks), dim3(kBlock), 0, s, vols,
+                                       *src, req_vol, *dst, shape[0]);
+                else if (shape[1] <= 8192)
+                    hipLaunchKernelGGL((k_decode_staged_multi<Eng, 8192>), dim3(blocks), dim3(kBlock), 0, s, vols,
+                                       *src, req_vol, *dst, shape[0]);
+                else
+                    hipLaunchKernelGGL((k_decode_staged_multi<Eng, 16384>), dim3(blocks), dim3(kBlock), 0, s, vols,
+                                       *src, req_vol, *dst, shape[0]);
+            }
+            break;
+        }
         case 3: {
             const MissSrc* src = (const MissSrc*)((const void* const*)a)[0];
             const MissDst* dst = (const MissDst*)((const void* const*)a)[1];
@@ -351,7 +570,7 @@ hipError_t inr_infer_points(const InrDev& m, const float* pos, int64_t n, float*
 
 hipError_t inr_decode_bricks(const InrDev& m, const CacheGeom& g, const int32_t* reqs, const uint32_t* n_dev,
                              const uint32_t* gate, int32_t n_cap, const int32_t* slots, const BrickOut& out,
-                             int prec, hipStream_t s) {
+                             int prec, hipStream_t s, DecodeShape shape) {
     if (n_cap <= 0) return hipSuccess;
     BrickSrc src;
     src.reqs = reqs;
@@ -365,13 +584,19 @@ hipError_t inr_decode_bricks(const InrDev& m, const CacheGeom& g, const int32_t*
         for (int a = 0; a < 3; ++a) src.nb[L][a] = L < g.n_lods ? g.lod[L].nb[a] : 0;
     for (int a = 0; a < 3; ++a) src.dims[a] = m.dims[a];
     BrickDst dst{out.out, out.out16, slots, src.B3, out.split};
+    if (shape.parts > 0 && g.brick <= kTabB && g.brick % shape.parts == 0) {
+        const int32_t sh[2] = {shape.parts, shape.stage_floats};
+        const void* a[3] = {&src, &dst, sh};
+        return dispatch(prec, 5, m, a, s);
+    }
     const void* a[2] = {&src, &dst};
     return dispatch(prec, 1, m, a, s);
 }
 
 hipError_t inr_decode_bricks_multi(const InrDev* d_vols, const InrDev& shape, const CacheGeom& g, const int32_t* reqs,
                                    const int32_t* vols, const uint32_t* n_dev, const uint32_t* gate, int32_t n_cap,
-                                   const int32_t* slots, const BrickOut& out, int prec, hipStream_t s) {
+                                   const int32_t* slots, const BrickOut& out, int prec, hipStream_t s,
+                                   DecodeShape ds) {
     if (n_cap <= 0) return hipSuccess;
     BrickSrc src;
     src.reqs = reqs;
@@ -385,6 +610,11 @@ hipError_t inr_decode_bricks_multi(const InrDev* d_vols, const InrDev& shape, co
         for (int a = 0; a < 3; ++a) src.nb[L][a] = L < g.n_lods ? g.lod[L].nb[a] : 0;
     for (int a = 0; a < 3; ++a) src.dims[a] = shape.dims[a];
     BrickDst dst{out.out, out.out16, slots, src.B3, out.split};
+    if (!shape.grid && ds.parts > 0 && g.brick <= kTabB && g.brick % ds.parts == 0) {
+        const int32_t sh[2] = {ds.parts, ds.stage_floats};
+        const void* a[5] = {&src, &dst, d_vols, vols, sh};
+        return dispatch(prec, 6, shape, a, s);
+    }
     const void* a[4] = {&src, &dst, d_vols, vols};
     return dispatch(prec, 4, shape, a, s);
 }

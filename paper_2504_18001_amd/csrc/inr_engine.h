@@ -90,13 +90,24 @@ __device__ inline void to_unit(const InrDev& m, const double x[3], double u[3]) 
 // Multi-resolution hash encoding (Section 3) of one level: trilinear
 // interpolation of the 8 grid corners around u*N_l.  The level index is
 // wave-uniform, so the dense/hashed branch never diverges.
-template <int F>
-__device__ inline void encode_level(const LevelDev& lv, const float* table, const double u[3], float* out) {
+// Cell c = floor(u N_l) and weights w = u N_l - c (FP64, rounded once).
+__device__ inline void level_cell(const LevelDev& lv, const double u[3], uint32_t c[3], float w[3]) {
     const double N = lv.res;
-    const double s0 = u[0] * N, s1 = u[1] * N, s2 = u[2] * N;
-    const double f0 = floor(s0), f1 = floor(s1), f2 = floor(s2);
-    const float w0 = (float)(s0 - f0), w1 = (float)(s1 - f1), w2 = (float)(s2 - f2);
-    const uint32_t c0 = (uint32_t)f0, c1 = (uint32_t)f1, c2 = (uint32_t)f2;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double sa = u[a] * N;
+        const double fa = floor(sa);
+        w[a] = (float)(sa - fa);
+        c[a] = (uint32_t)fa;
+    }
+}
+
+// The 8 corner entries of cell c from the level's table, interpolated.
+template <int F>
+__device__ inline void gather_level(const LevelDev& lv, const float* table, const uint32_t c[3], const float w[3],
+                                    float* out) {
+    const uint32_t c0 = c[0], c1 = c[1], c2 = c[2];
+    const float w0 = w[0], w1 = w[1], w2 = w[2];
     uint32_t idx[8];
     if (lv.mask == 0u) {
         const uint32_t sd = lv.side, sd2 = lv.side2;
@@ -140,6 +151,85 @@ __device__ inline void encode_level(const LevelDev& lv, const float* table, cons
     }
 }
 
+template <int F>
+__device__ inline void encode_level(const LevelDev& lv, const float* table, const double u[3], float* out) {
+    uint32_t c[3];
+    float w[3];
+    level_cell(lv, u, c, w);
+    gather_level<F>(lv, table, c, w, out);
+}
+
+// LDS staging of the hash-table corners that the lattice points of one brick
+// part touch (brick decoding, Section 4.3.2): per level, the cells of a
+// regular block of lattice points span a box of grid corners; a box that fits
+// is copied into LDS once, and the part's points interpolate from there.
+struct StageLevel {
+    int32_t lo[3];  // first corner of the box
+    int32_t e[3];   // corners per axis
+    int32_t off;    // first float of the box in the stage; -1: read from the table
+};
+
+// gather_level for a staged level: the same cell, weights and accumulation
+// order, the 8 corners read from the level's box in LDS.
+template <int F>
+__device__ inline void gather_level_lds(const StageLevel& sl, const float* stage, const uint32_t c[3],
+                                        const float w[3], float* out) {
+    const float w0 = w[0], w1 = w[1], w2 = w[2];
+    const int32_t ex = sl.e[0], exy = sl.e[0] * sl.e[1];
+    const int32_t b = ((int32_t)c[0] - sl.lo[0]) + ((int32_t)c[1] - sl.lo[1]) * ex + ((int32_t)c[2] - sl.lo[2]) * exy;
+    const int32_t idx[8] = {b, b + 1, b + ex, b + ex + 1, b + exy, b + exy + 1, b + exy + ex, b + exy + ex + 1};
+    const float* sp = stage + sl.off;
+    float e[8][F];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) Entry<F>::load(sp + idx[k] * F, e[k]);
+    const float wx0 = 1.0f - w0, wy0 = 1.0f - w1, wz0 = 1.0f - w2;
+    const float wxy[4] = {wx0 * wy0, w0 * wy0, wx0 * w1, w0 * w1};
+#pragma unroll
+    for (int j = 0; j < F; ++j) out[j] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const float wt = wxy[k & 3] * ((k & 4) ? w2 : wz0);
+#pragma unroll
+        for (int j = 0; j < F; ++j) out[j] = __builtin_fmaf(wt, e[k][j], out[j]);
+    }
+}
+
+// Where a point's per-level cells and weights come from: computed from its
+// normalised coordinate, or (brick lattice points, whose coordinates are
+// separable) read from per-axis tables that hold the same FP64 results:
+// tab[(l * 3 + a) * n + i] = (cell, bits of the weight) of lattice index i
+// along axis a at level l.
+struct CoordU {
+    double u[3];
+    __device__ void cell(const LevelDev& lv, int, uint32_t c[3], float w[3]) const { level_cell(lv, u, c, w); }
+};
+struct CoordTab {
+    const uint2* tab;
+    int32_t n;
+    int32_t i[3];
+    __device__ void cell(const LevelDev&, int l, uint32_t c[3], float w[3]) const {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const uint2 t = tab[(l * 3 + a) * n + i[a]];
+            c[a] = t.x;
+            w[a] = __uint_as_float(t.y);
+        }
+    }
+};
+
+// Level l of a point: from the stage when its box is there, else from the table.
+template <int F, class Coord>
+__device__ inline void encode_level_any(const InrDev& m, int l, const Coord& co, const StageLevel* sl,
+                                        const float* stage, float* out) {
+    uint32_t c[3];
+    float w[3];
+    co.cell(m.lv[l], l, c, w);
+    if (sl && sl[l].off >= 0)
+        gather_level_lds<F>(sl[l], stage, c, w, out);
+    else
+        gather_level<F>(m.lv[l], m.table, c, w, out);
+}
+
 __device__ inline float finish_value(const InrDev& m, float y) {
     float v = __builtin_fmaf(m.value_scale, y, m.value_offset);
     v = v < 0.0f ? 0.0f : v;
@@ -156,7 +246,8 @@ struct GridEngine {
         int unused;
     };
     __device__ void load_weights(const InrDev&) {}
-    __device__ float eval(const InrDev& m, const double x[3], Lds&) const {
+    __device__ float eval(const InrDev& m, const double x[3], Lds&, const StageLevel* = nullptr,
+                          const float* = nullptr) const {
         int32_t j[3];
         float f[3];
 #pragma unroll
@@ -222,16 +313,23 @@ struct InrEngine<Cfg, true> {
         }
     }
 
-    // All 256 lanes of the workgroup must call eval together.
-    __device__ float eval(const InrDev& m, const double x[3], Lds& lds) {
+    // All 256 lanes of the workgroup must call eval together.  sl, stage:
+    // LDS-staged corner boxes of the levels (brick decoding), or null.
+    __device__ float eval(const InrDev& m, const double x[3], Lds& lds, const StageLevel* sl = nullptr,
+                          const float* stage = nullptr) {
+        CoordU co;
+        to_unit(m, x, co.u);
+        return eval_c(m, co, lds, sl, stage);
+    }
+
+    template <class Coord>
+    __device__ float eval_c(const InrDev& m, const Coord& co, Lds& lds, const StageLevel* sl, const float* stage) {
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, row = lane & 15, g = lane >> 4;
-        double u[3];
-        to_unit(m, x, u);
         float* my = lds.f + threadIdx.x * ROW;
 #pragma unroll 2
         for (int l = 0; l < NL; ++l) {
             float f[F];
-            encode_level<F>(m.lv[l], m.table, u, f);
+            encode_level_any<F>(m, l, co, sl, stage, f);
 #pragma unroll
             for (int j = 0; j < F; ++j) my[l * F + j] = f[j];
         }
@@ -337,16 +435,22 @@ struct InrEngine<Cfg, false> {
         }
     }
 
-    __device__ float eval(const InrDev& m, const double x[3], Lds& lds) {
+    __device__ float eval(const InrDev& m, const double x[3], Lds& lds, const StageLevel* sl = nullptr,
+                          const float* stage = nullptr) {
+        CoordU co;
+        to_unit(m, x, co.u);
+        return eval_c(m, co, lds, sl, stage);
+    }
+
+    template <class Coord>
+    __device__ float eval_c(const InrDev& m, const Coord& co, Lds& lds, const StageLevel* sl, const float* stage) {
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, row = lane & 15, g = lane >> 4;
-        double u[3];
-        to_unit(m, x, u);
         T* my = lds.f[0] + threadIdx.x * ROW;
         T* my_lo = lds.f[NP - 1] + threadIdx.x * ROW;
 #pragma unroll 2
         for (int l = 0; l < NL; ++l) {
             float f[F];
-            encode_level<F>(m.lv[l], m.table, u, f);
+            encode_level_any<F>(m, l, co, sl, stage, f);
 #pragma unroll
             for (int j = 0; j < F; ++j) {
                 my[l * F + j] = part_hi(f[j]);

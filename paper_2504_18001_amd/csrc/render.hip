@@ -538,6 +538,12 @@ template <int kPipe, bool kLdsFlags, int kFast, bool kAdapt, int kPool, int kWav
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves, 8))) void k_march(FrameDev f, int32_t it, uint32_t n0) {
     static_assert(!kAdapt || kPipe == 1, "the adaptive sampler decides one sample ahead at most");
     const FrameHot hot = load_hot(f.var);  // before any store of this kernel
+    // a later iteration without rays (one queued before the count was known)
+    // leaves at once; workgroup 0 still clears the next iteration's counters
+    if (it > 0 && f.ctr[it].live == 0u) {
+        if (blockIdx.x == 0 && threadIdx.x < 8) f.claim[(((it + 1) & 1) * 8 + threadIdx.x) * kClaimStride] = 0u;
+        return;
+    }
     // the pre-load frames march every ray to the end of the box (Sec. 4.3.4)
     const bool ert_on = f.ert_on && hot.preload == 0;
     __shared__ float4 tfs[256];
@@ -765,6 +771,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves, 
 }
 
 __global__ __launch_bounds__(kBlock) void k_shade(FrameDev f, int32_t it) {
+    if (f.ctr[it].pending == 0u) return;  // nothing to shade (the same for every workgroup)
     const CamDev cam = f.var->cam;
     __shared__ float4 tfs[256];
     tfs[threadIdx.x] = reinterpret_cast<const float4*>(f.tf)[threadIdx.x];
@@ -918,6 +925,11 @@ __device__ inline float4 pt_pixel_value(const PtLane& s) {
 template <bool kLdsFlags, int kFast, int kPool>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_path(FrameDev f, int32_t it, uint32_t n0) {
     const FrameHot hot = load_hot(f.var);  // before any store of this kernel
+    // as k_march: a later iteration without pixels leaves at once
+    if (it > 0 && f.ctr[it - 1].pending == 0u) {
+        if (blockIdx.x == 0 && threadIdx.x < 8) f.claim[(((it + 1) & 1) * 8 + threadIdx.x) * kClaimStride] = 0u;
+        return;
+    }
     __shared__ float4 tfs[256];
     __shared__ LodGeom lgs[kMaxLods];
     __shared__ uint64_t sflags[kLdsFlags ? kMaxLdsFlagWords : 1];
@@ -1394,10 +1406,11 @@ __global__ void k_pending_gather(PendingSrc src, int32_t n, uint32_t* host_out, 
     __threadfence_system();
 }
 
-hipError_t launch_pending_gather(const FrameDev* const* fs, int n, uint32_t* host_out, uint32_t* gate, hipStream_t s) {
+hipError_t launch_pending_gather(const FrameDev* const* fs, int n, int it, uint32_t* host_out, uint32_t* gate,
+                                 hipStream_t s) {
     if (n < 1 || n > 64) return hipErrorInvalidValue;
     PendingSrc src{};
-    for (int i = 0; i < n; ++i) src.p[i] = &fs[i]->ctr[0].pending;
+    for (int i = 0; i < n; ++i) src.p[i] = &fs[i]->ctr[it].pending;
     hipLaunchKernelGGL(k_pending_gather, dim3(1), dim3(64), 0, s, src, n, host_out, gate);
     return hipGetLastError();
 }

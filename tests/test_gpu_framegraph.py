@@ -46,8 +46,12 @@ def miss_set(cache):
     return g[np.lexsort(g.T[::-1])]
 
 
-@pytest.mark.parametrize("n_views,mixed", [(5, False), (1, False), (5, True)])
-def test_graph_frames_equal_eager_frames_and_oracle(n_views, mixed):
+@pytest.mark.parametrize("n_views,mixed,dev_iters", [(5, False, 0), (1, False, 0), (5, True, 0), (5, False, 3),
+                                                     (1, False, 3)])
+def test_graph_frames_equal_eager_frames_and_oracle(n_views, mixed, dev_iters):
+    """dev_iters: wavefront iterations after the first marches queued in the
+    graph, so that frames of at most dev_iters + 1 iterations need no host
+    round trip before their end."""
     from oracle import oracle as O
     from paper_2504_18001_amd import cinr
     vols = [gpu_volume(s) for s in range(3)]
@@ -62,6 +66,8 @@ def test_graph_frames_equal_eager_frames_and_oracle(n_views, mixed):
     kw = dict(lod_scale=ls, seed=W.seed, samples_per_iter=W.samples_per_iter, pipe_depth=2, xcd_bands=4)
     mv = cinr.MultiViewRenderer(n_views)
     fg = cinr.FrameGraph(gg, [(vols[VOLS[i]], view_cam(i, 0), W.tf(0)) for i in idx], W.step, **kw)
+    fg.set_device_iterations(dev_iters)
+    iters = []  # most iterations of a view, per frame
     for f in range(12):
         print(f"frame {f}, {n_views} views", flush=True)
         eager = mv.render(ge, [(vols[VOLS[i]], view_cam(i, f), W.tf(f)) for i in idx], W.step, frame_index=f, **kw)
@@ -69,6 +75,7 @@ def test_graph_frames_equal_eager_frames_and_oracle(n_views, mixed):
             fg.tfs[i].copy_(torch.as_tensor(np.asarray(W.tf(f), np.float32)))
         imgs = fg.render([view_cam(i, f) for i in idx], f)
         se, sg = mv.last_stats(), fg.last_stats()
+        iters.append(max(sg[i]["iterations"] for i in idx))
         ps = [O.make_params(W.step, ls, seed=W.seed, frame_index=f, samples_per_iter=W.samples_per_iter)
               for _ in idx]
         ref = oc.render_views([(VOLS[i], view_cam(i, f), W.tf(f)) for i in idx], ps)
@@ -87,9 +94,12 @@ def test_graph_frames_equal_eager_frames_and_oracle(n_views, mixed):
         np.testing.assert_array_equal(gg.dump(cinr.DUMP_PAGE_TABLE), oc.page_table())
         np.testing.assert_array_equal(gg.dump(cinr.DUMP_LAST_USED), oc.last_used())
     n_graph, n_eager, n_tail = fg.counts()
-    print("graph frames", n_graph, "eager", n_eager, "with further iterations", n_tail)
+    print("graph frames", n_graph, "eager", n_eager, "with further iterations", n_tail, "iterations", iters)
     assert n_graph == 12 and n_eager == 0
-    assert n_tail >= 1  # the cold start leaves true misses after the first marches
+    # the cold start leaves true misses after the first marches; frames of more
+    # iterations than the graph queues finish with host round trips
+    assert max(iters) > 1
+    assert n_tail == sum(1 for k in iters if k > 1 + dev_iters)
     ev = gg.dump(cinr.DUMP_EVICTION_LOG)
     assert (ev[:, 2] >= 0).any()  # bricks were evicted (LRU pass in the end graph)
     if mixed:  # in both classes

@@ -28,11 +28,15 @@ def view_cam(i, f):
     return c
 
 
-@pytest.mark.parametrize("pool_dtype", ["f32", "f16", "mixed"])
-def test_shared_cache_views_match_oracle(pool_dtype):
+@pytest.mark.parametrize("pool_dtype,staged", [("f32", False), ("f16", False), ("mixed", False), ("f32", True)])
+def test_shared_cache_views_match_oracle(pool_dtype, staged):
+    """staged: the shared cache decodes its bricks of the 3 INRs with
+    LDS-staged corner boxes (4 parts per brick, 32 KiB)."""
     from oracle import oracle as O
     from paper_2504_18001_amd import cinr
     vols = [gpu_volume(s) for s in range(3)]
+    if staged:
+        vols[0].set_decode_shape(4, 32)
     ms = [oracle_inr(W.arch, s) for s in range(3)]
     B, nl, pool, req = 8, 2, 150, 24
     # mixed: LoD 1 in a binary16 class of 75 slots, LoD 0 in 75 binary32 slots,

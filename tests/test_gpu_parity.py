@@ -73,6 +73,49 @@ def test_decode_bricks(name, arch, B, n_lods, dtype):
     assert err.max() <= VTOL[dtype]
 
 
+STAGED = [(1, 0), (1, 64), (2, 32), (4, 0), (4, 64), (8, 32), (16, 0), (16, 64)]
+
+
+@pytest.mark.parametrize("name,arch,B,n_lods", [("small", configs.ARCH_SMALL, 8, 2), ("inr512", configs.ARCH_512, 16, 4),
+                                                ("tera", configs.ARCH_TERA, 16, 6)])
+@pytest.mark.parametrize("dtype", ["f32", "bf16x3"])
+def test_decode_bricks_staged_is_bit_identical(name, arch, B, n_lods, dtype):
+    """Decoding with LDS-staged corner boxes, every launch shape, against the
+    unstaged decode (bit for bit: same cells, weights and order) and the
+    oracle; random requests of every LoD plus the clamped last brick of each
+    LoD, the origin brick and two invalid requests (NaN bricks)."""
+    vol = gpu_volume(arch, 1)
+    m = oracle_inr(arch, 1)
+    nb, _ = vol.geometry(B, n_lods)
+    reqs = synth.random_requests(nb.tolist(), 45, seed=4)
+    extra = [[L, *(nb[L] - 1)] for L in range(n_lods)] + [[0, 0, 0, 0], [0, int(nb[0][0]), 0, 0], [-1, 0, 0, 0]]
+    reqs = torch.from_numpy(np.concatenate([reqs, np.asarray(extra, np.int32)])).cuda()
+    base = vol.decode_bricks_shaped(reqs, B, dtype, parts=0).cpu().numpy()
+    ref = m.decode_bricks(reqs[:-2].cpu().numpy(), B, n_lods)
+    assert np.abs(base[:-2] - ref).max() <= VTOL[dtype]
+    assert np.isnan(base[-2:]).all() and np.isfinite(base[:-2]).all()
+    for parts, kib in STAGED:
+        if B % parts:
+            continue
+        got = vol.decode_bricks_shaped(reqs, B, dtype, parts=parts, stage_kib=kib).cpu().numpy()
+        assert np.array_equal(got, base, equal_nan=True), (parts, kib, np.nanmax(np.abs(got - base)))
+
+
+def test_decode_shape_arguments():
+    from paper_2504_18001_amd import cinr
+    vol = gpu_volume(configs.ARCH_SMALL, 0)
+    reqs = torch.zeros((1, 4), dtype=torch.int32, device="cuda")
+    for parts, kib in ((3, 64), (4, 48), (-1, 64), (2, -32)):
+        with pytest.raises(cinr.CinrError):
+            vol.decode_bricks_shaped(reqs, 8, parts=parts, stage_kib=kib)
+    with pytest.raises(cinr.CinrError, match="multiple"):
+        vol.decode_bricks_shaped(reqs, 8, parts=16, stage_kib=64)
+    vol.set_decode_shape(4, 32)
+    a = vol.decode_bricks(reqs, 8).cpu().numpy()
+    vol.set_decode_shape(0)
+    assert np.array_equal(a, vol.decode_bricks(reqs, 8).cpu().numpy())
+
+
 def test_decode_invalid_request_gives_nan():
     vol = gpu_volume(configs.ARCH_SMALL, 0)
     reqs = torch.tensor([[0, 0, 0, 0], [0, 99, 0, 0], [17, 0, 0, 0]], dtype=torch.int32, device="cuda")

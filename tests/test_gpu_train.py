@@ -68,11 +68,28 @@ def test_gradients_match_oracle(name, arch, dtype):
         assert np.abs(gw - rgw).max() < 1e-4 * np.abs(rgw).max()
         assert np.abs(gt - rgt).max() < 1e-4 * np.abs(rgt).max()
     else:
-        # BF16 operands (8 significant bits) with FP32 accumulation
+        # against the FP64 gradient: BF16 operands (8 significant bits) with FP32 accumulation
         assert el < 2e-2 and ew < 5e-2 and et < 8e-2
         cos_w = float(gw.ravel() @ rgw.ravel() / (np.linalg.norm(gw) * np.linalg.norm(rgw)))
         cos_t = float(gt.ravel() @ rgt.ravel() / (np.linalg.norm(gt) * np.linalg.norm(rgt)))
         assert cos_w > 0.998 and cos_t > 0.998
+        # element by element against the oracle with the same BF16 operands: what
+        # remains is FP32 against FP64 accumulation (about 1e-6 of an element's
+        # terms) and operands whose FP32 and FP64 values round to neighbouring
+        # BF16 values (one BF16 unit, 2^-8, of one term).  Bound per element:
+        # 2^-8 |g| + 2^-11 max|g| of the tensor (weights of each layer, table);
+        # measured: at most 1e-4 max|g| on both shapes.
+        bl, bgt, bgw = O.loss_grad(m, u.astype(np.float64), t.astype(np.float64), bf16_operands=True)
+        assert abs(float(loss.item()) - bl) <= 1e-4 * bl
+        H, IN = arch.widths[1], arch.widths[0]
+        cuts = [0, H * IN, H * IN + H * H, gw.size]
+        for name_, got, ref in [("W%d" % (k + 1), gw[cuts[k]:cuts[k + 1]], bgw[cuts[k]:cuts[k + 1]]) for k in range(3)] + \
+                [("table", gt.ravel(), bgt.ravel())]:
+            d = np.abs(got - ref)
+            bound = 2.0 ** -8 * np.abs(ref) + 2.0 ** -11 * np.abs(ref).max()
+            print(name_, "max |d| / max |g|", d.max() / np.abs(ref).max(), "worst d / bound", (d / bound).max(),
+                  "elements over 1e-4 max|g|", int((d > 1e-4 * np.abs(ref).max()).sum()), "of", d.size)
+            assert (d <= bound).all(), name_
 
 
 def test_gradients_of_no_points_are_zero():

@@ -44,6 +44,51 @@ def test_gradients_match_central_differences():
         assert gt[r, c] == pytest.approx(fd, rel=1e-5, abs=1e-9)
 
 
+def test_round_bf16_closed_forms():
+    """bfloat16 keeps 8 significant bits: 1 + k 2^-7 are neighbours near 1;
+    halfway cases go to the even neighbour."""
+    r = O.round_bf16
+    assert r(1.0) == 1.0 and r(-3.0) == -3.0 and r(0.0) == 0.0
+    assert r(1.0 + 2.0 ** -8) == 1.0                      # tie, to even (k = 0)
+    assert r(1.0 + 3 * 2.0 ** -8) == 1.0 + 2.0 ** -6      # tie, to even (k = 2)
+    assert r(1.0 + 2.0 ** -8 + 2.0 ** -20) == 1.0 + 2.0 ** -7
+    assert r(-(1.0 + 2.0 ** -8 + 2.0 ** -20)) == -(1.0 + 2.0 ** -7)
+    assert r(0.1) == 0.10009765625                        # 0x3DCD
+    assert r(2.0 ** -130) == 2.0 ** -130                  # subnormal of binary32, exact
+    assert r(255.5) == 256.0 and r(254.5) == 254.0        # ties at the top of [128, 256)
+
+
+def test_bf16_operand_gradients_reduce_to_fp64_on_exact_values():
+    """With table entries, weights and points whose every intermediate value
+    has at most 8 significant bits, the BF16-operand mode rounds nothing away
+    and equals the FP64 gradients exactly; with general values it differs."""
+    arch = InrArch(dims=(16, 16, 16), n_levels=1, n_features=2, log2_table=6, n_min=2, growth=1.5,
+                   widths=(2, 2, 2, 1))
+    table, weights = random_inr_params(arch, 1)
+    rng = np.random.default_rng(3)
+    table = rng.choice([0.0, 0.5, -0.5, 1.0], size=table.shape).astype(np.float32)
+    # one weight of +-1 per row: each hidden value is one feature or one activation
+    w = np.zeros_like(weights)
+    w[[0, 3, 4, 7, 8]] = [1.0, -1.0, 1.0, 1.0, 1.0]
+    # u N on multiples of 1/2; 4 points, so that d loss / d y = 2 e / 4 stays dyadic
+    u = np.array([[0.25, 0.5, 0.75], [0.0, 0.25, 0.5], [0.5, 0.5, 0.5], [0.75, 0.0, 0.25]])
+    g = np.array([0.5, 0.25, 1.0, 0.0])
+    m = O.OracleInr(arch, table, w)
+    l0, gt0, gw0 = O.loss_grad(m, u, g)
+    l1, gt1, gw1 = O.loss_grad(m, u, g, bf16_operands=True)
+    assert l1 == l0 and np.array_equal(gw1, gw0) and np.array_equal(gt1, gt0)
+    # general values: the rounding shows
+    table2, weights2 = random_inr_params(TINY, 2)
+    m2 = O.OracleInr(TINY, table2, weights2)
+    u2 = rng.uniform(0, 1, size=(16, 3))
+    g2 = rng.uniform(0, 1, size=16)
+    _, a0, b0 = O.loss_grad(m2, u2, g2)
+    _, a1, b1 = O.loss_grad(m2, u2, g2, bf16_operands=True)
+    assert not np.array_equal(b0, b1)
+    # and stays within a few BF16 roundings of the FP64 gradient
+    assert np.abs(b1 - b0).max() <= 2.0 ** -4 * np.abs(b0).max()
+
+
 def test_adam_matches_torch_optim_adam():
     rng = np.random.default_rng(1)
     n = 50
