@@ -367,8 +367,10 @@ cinr_status cinr_decode_bricks(cinr_volume vol, const int32_t* d_reqs, int32_t n
  * parts_per_brick = 0: one point per lane over the whole request list, every
  * corner read from the hash table (the layout of cinr_infer_points).
  * Otherwise (brick <= 16; a larger brick uses parts_per_brick = 0) a
- * workgroup takes one of parts_per_brick (1, 2, 4, 8 or 16; a divisor of
- * `brick`) slabs of z-slices of a brick.  The lattice coordinates of a brick
+ * workgroup takes one of P slabs of z-slices of a brick, where P is at least
+ * parts_per_brick (1, 2, 4, 8 or 16; a divisor of `brick`) and is doubled on
+ * the device, while it divides the brick and stays <= 16, until the launch's
+ * request count gives every resident workgroup a slab (short request lists).  The lattice coordinates of a brick
  * are separable, so each hash-grid level's cells and weights are computed per
  * axis once per slab.  With stage_kib 32 or 64 (0: none), for each level the
  * box of grid corners that the slab's lattice points touch is also copied

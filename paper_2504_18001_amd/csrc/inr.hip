@@ -269,10 +269,21 @@ __device__ void decode_item_staged(const InrDev& m, Eng& eng, typename Eng::Lds&
     __syncthreads();  // the tables, stage and boxes are refilled for the next item
 }
 
+// Parts per brick of a launch: at least `parts`; doubled (while it divides the
+// brick) until the request count read on the device gives every workgroup of
+// the grid an item, so that a short request list still fills the chip.
+__device__ inline int32_t decode_parts(int64_t n, int32_t parts, int32_t B) {
+    int32_t p = parts;
+    while (2 * p <= kTabB && B % (2 * p) == 0 && n * p < (int64_t)gridDim.x) p *= 2;
+    return p;
+}
+
 template <class Eng, int kStageFloats>
 __global__ __launch_bounds__(kBlock) void k_decode_staged(const InrDev m, const BrickSrc src, const BrickDst dst,
-                                                          int32_t parts) {
-    const int64_t items = src.n_requests() * parts;
+                                                          int32_t min_parts) {
+    const int64_t n = src.n_requests();
+    const int32_t parts = decode_parts(n, min_parts, src.B);
+    const int64_t items = n * parts;
     // sized for the request cap: idle workgroups leave before the weights
     if ((int64_t)blockIdx.x >= items) return;
     Eng eng;
@@ -295,8 +306,10 @@ __global__ __launch_bounds__(kBlock) void k_decode_staged(const InrDev m, const 
 template <class Eng, int kStageFloats>
 __global__ __launch_bounds__(kBlock) void k_decode_staged_multi(const InrDev* vols, const BrickSrc src,
                                                                 const int32_t* req_vol, const BrickDst dst,
-                                                                int32_t parts) {
-    const int64_t items = src.n_requests() * parts;
+                                                                int32_t min_parts) {
+    const int64_t n = src.n_requests();
+    const int32_t parts = decode_parts(n, min_parts, src.B);
+    const int64_t items = n * parts;
     if ((int64_t)blockIdx.x >= items) return;
     Eng eng;
     int32_t cur = -1;
@@ -434,6 +447,33 @@ static int grid_for(int64_t points, int max_blocks) {
 
 constexpr int kMaxInrBlocks = 256 * 8;  // 8 workgroups per CU on 256 CUs
 
+// Workgroups of `kernel` resident on the current device at once (per
+// instantiation and device), at least 1.
+template <class Kernel>
+static int resident_grid(Kernel kernel, int* cache) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return kMaxInrBlocks;
+    if (cache[dev] == 0) {
+        int per_cu = 0, n_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess ||
+            hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return kMaxInrBlocks;
+        cache[dev] = (per_cu > 0 ? per_cu : 1) * (n_cu > 0 ? n_cu : 1);
+    }
+    return cache[dev];
+}
+
+// Grid of a staged decoding launch: one resident wave of workgroups, or fewer
+// when even `parts_max` parts of every request of the cap are fewer items.
+template <class Kernel>
+static int staged_grid(Kernel kernel, int* cache, int64_t n_cap, int32_t parts, int32_t B) {
+    int32_t pmax = parts;
+    while (2 * pmax <= kTabB && B % (2 * pmax) == 0) pmax *= 2;
+    const int64_t items = n_cap * pmax;
+    const int cap = resident_grid(kernel, cache);
+    return (int)(items < cap ? (items < 1 ? 1 : items) : cap);
+}
+
 template <class Eng>
 static hipError_t launch_all(int what, const InrDev& m, const void* a, hipStream_t s) {
     switch (what) {
@@ -479,17 +519,20 @@ static hipError_t launch_all(int what, const InrDev& m, const void* a, hipStream
                 hipLaunchKernelGGL((k_decode<Eng>), dim3(grid_for((int64_t)src->n_host * src->B3, kMaxInrBlocks)),
                                    dim3(kBlock), 0, s, m, *src, *dst);
             } else {
-                const int64_t items = (int64_t)src->n_host * shape[0];
-                const int blocks = (int)(items < kMaxInrBlocks ? (items < 1 ? 1 : items) : kMaxInrBlocks);
+                static int cap0[64], cap1[64], cap2[64];
+                const int64_t n = src->n_host;
                 if (shape[1] <= 0)
-                    hipLaunchKernelGGL((k_decode_staged<Eng, 0>), dim3(blocks), dim3(kBlock), 0, s, m, *src, *dst,
-                                       shape[0]);
+                    hipLaunchKernelGGL((k_decode_staged<Eng, 0>),
+                                       dim3(staged_grid(k_decode_staged<Eng, 0>, cap0, n, shape[0], src->B)),
+                                       dim3(kBlock), 0, s, m, *src, *dst, shape[0]);
                 else if (shape[1] <= 8192)
-                    hipLaunchKernelGGL((k_decode_staged<Eng, 8192>), dim3(blocks), dim3(kBlock), 0, s, m, *src, *dst,
-                                       shape[0]);
+                    hipLaunchKernelGGL((k_decode_staged<Eng, 8192>),
+                                       dim3(staged_grid(k_decode_staged<Eng, 8192>, cap1, n, shape[0], src->B)),
+                                       dim3(kBlock), 0, s, m, *src, *dst, shape[0]);
                 else
-                    hipLaunchKernelGGL((k_decode_staged<Eng, 16384>), dim3(blocks), dim3(kBlock), 0, s, m, *src,
-                                       *dst, shape[0]);
+                    hipLaunchKernelGGL((k_decode_staged<Eng, 16384>),
+                                       dim3(staged_grid(k_decode_staged<Eng, 16384>, cap2, n, shape[0], src->B)),
+                                       dim3(kBlock), 0, s, m, *src, *dst, shape[0]);
             }
             break;
         }
@@ -503,17 +546,20 @@ static hipError_t launch_all(int what, const InrDev& m, const void* a, hipStream
             if constexpr (std::is_same<Eng, GridEngine>::value) {
                 return hipErrorInvalidValue;
             } else {
-                const int64_t items = (int64_t)src->n_host * shape[0];
-                const int blocks = (int)(items < kMaxInrBlocks ? (items < 1 ? 1 : items) : kMaxInrBlocks);
+                static int cap0[64], cap1[64], cap2[64];
+                const int64_t n = src->n_host;
                 if (shape[1] <= 0)
-                    hipLaunchKernelGGL((k_decode_staged_multi<Eng, 0>), dim3(blocks), dim3(kBlock), 0, s, vols,
-                                       *src, req_vol, *dst, shape[0]);
+                    hipLaunchKernelGGL((k_decode_staged_multi<Eng, 0>),
+                                       dim3(staged_grid(k_decode_staged_multi<Eng, 0>, cap0, n, shape[0], src->B)),
+                                       dim3(kBlock), 0, s, vols, *src, req_vol, *dst, shape[0]);
                 else if (shape[1] <= 8192)
-                    hipLaunchKernelGGL((k_decode_staged_multi<Eng, 8192>), dim3(blocks), dim3(kBlock), 0, s, vols,
-                                       *src, req_vol, *dst, shape[0]);
+                    hipLaunchKernelGGL((k_decode_staged_multi<Eng, 8192>),
+                                       dim3(staged_grid(k_decode_staged_multi<Eng, 8192>, cap1, n, shape[0], src->B)),
+                                       dim3(kBlock), 0, s, vols, *src, req_vol, *dst, shape[0]);
                 else
-                    hipLaunchKernelGGL((k_decode_staged_multi<Eng, 16384>), dim3(blocks), dim3(kBlock), 0, s, vols,
-                                       *src, req_vol, *dst, shape[0]);
+                    hipLaunchKernelGGL((k_decode_staged_multi<Eng, 16384>),
+                                       dim3(staged_grid(k_decode_staged_multi<Eng, 16384>, cap2, n, shape[0], src->B)),
+                                       dim3(kBlock), 0, s, vols, *src, req_vol, *dst, shape[0]);
             }
             break;
         }

@@ -99,6 +99,15 @@ def test_decode_bricks_staged_is_bit_identical(name, arch, B, n_lods, dtype):
             continue
         got = vol.decode_bricks_shaped(reqs, B, dtype, parts=parts, stage_kib=kib).cpu().numpy()
         assert np.array_equal(got, base, equal_nan=True), (parts, kib, np.nanmax(np.abs(got - base)))
+    # a short list is split into more parts on the device; a list of 1536
+    # requests (two per resident workgroup) keeps each shape's own parts
+    big = torch.from_numpy(synth.random_requests(nb.tolist(), 1536, seed=5)).cuda()
+    bbase = vol.decode_bricks_shaped(big, B, dtype, parts=0).cpu().numpy()
+    for parts, kib in STAGED:
+        if B % parts:
+            continue
+        got = vol.decode_bricks_shaped(big, B, dtype, parts=parts, stage_kib=kib).cpu().numpy()
+        assert np.array_equal(got, bbase), ("1536 requests", parts, kib)
 
 
 def test_decode_shape_arguments():
