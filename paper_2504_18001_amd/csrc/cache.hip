@@ -231,7 +231,13 @@ __global__ __launch_bounds__(256) void k_topk(TopkArgs a) {
     uint64_t c = a.cap0;
     if (a.count_dev && (uint64_t)*a.count_dev < c) c = *a.count_dev;
     const uint64_t n_touched = c;
-    for (int q = 0; q < a.pass; ++q) c = ((c + kTopkChunk - 1) / kTopkChunk) * (uint64_t)a.k;
+    // every live element in pass 0's first workgroup: it sorts them all and
+    // completes the selection; the later passes have nothing to do
+    const bool one = !a.fused && n_touched <= (uint64_t)kTopkChunk;
+    if (one && a.pass > 0) return;
+    const bool last = one || a.pass == a.last_pass;
+    if (!one)
+        for (int q = 0; q < a.pass; ++q) c = ((c + kTopkChunk - 1) / kTopkChunk) * (uint64_t)a.k;
     const uint64_t base = (uint64_t)blockIdx.x * kTopkChunk;
     if (base >= c && blockIdx.x > 0 && !a.fused) return;
     const uint32_t have = base >= c ? 0u : (uint32_t)(c - base < kTopkChunk ? c - base : kTopkChunk);
@@ -255,8 +261,8 @@ __global__ __launch_bounds__(256) void k_topk(TopkArgs a) {
         }
         __syncthreads();
         sort_desc(s, m);
-        for (int32_t e = threadIdx.x; e < a.k; e += 256)
-            a.out[(uint64_t)blockIdx.x * a.k + e] = (uint32_t)e < m ? s[e] : 0ull;
+        uint64_t* out = (last && !a.fused) ? a.final_out : a.out + (uint64_t)blockIdx.x * a.k;
+        for (int32_t e = threadIdx.x; e < a.k; e += 256) out[e] = (uint32_t)e < m ? s[e] : 0ull;
     }
     if (a.fused) {
         // the last workgroup to finish pass 0 completes the selection
@@ -278,7 +284,7 @@ __global__ __launch_bounds__(256) void k_topk(TopkArgs a) {
         sort_desc(s, m);
         for (int32_t e = threadIdx.x; e < a.k; e += 256) a.final_out[e] = (uint32_t)e < m ? s[e] : 0ull;
     }
-    if (a.sel.ctr) {
+    if (a.sel.ctr && (last || a.fused)) {
         // request list: keys of the non-zero scores, best first
         if (threadIdx.x == 0) nsel = 0u;
         __syncthreads();
@@ -520,7 +526,9 @@ hipError_t launch_topk(const TopkArgs& base, const TopkPlan& plan, uint64_t* buf
         a.in = src;
         const bool last = p + 1 == plan.n_pass;
         a.out = last ? final_out : ((p & 1) ? buf1 : buf0);
-        a.sel = (last && epilogue) ? *epilogue : SelectArgs{};
+        a.final_out = final_out;
+        a.last_pass = plan.n_pass - 1;
+        a.sel = epilogue ? *epilogue : SelectArgs{};
         hipLaunchKernelGGL(k_topk, dim3(plan.blocks[p]), dim3(256), 0, s, a);
         src = a.out;
     }

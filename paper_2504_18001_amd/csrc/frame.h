@@ -295,6 +295,10 @@ struct TopkArgs {
     uint32_t* done;         // count of finished workgroups (reset by the last)
     uint64_t* final_out;
     SelectTail tail;
+    // passes of an unfused selection (the epilogue `sel` runs after the last);
+    // when pass 0's live count fits one workgroup, that workgroup finishes the
+    // selection and the later passes return at once
+    int32_t last_pass;
 };
 
 // render.cpp launchers
