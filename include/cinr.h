@@ -58,8 +58,12 @@ typedef enum {
 typedef enum { CINR_F32 = 0, CINR_BF16 = 1, CINR_F16 = 2, CINR_BF16X3 = 3 } cinr_dtype;
 
 typedef enum {
-    CINR_CACHED = 0,         /* sampler of Algorithm 2 behind the brick cache */
-    CINR_UNCACHED_DIRECT = 1 /* every sample inferred from the INR (the uncached baseline) */
+    CINR_CACHED = 0,          /* sampler of Algorithm 2 behind the brick cache */
+    CINR_UNCACHED_DIRECT = 1, /* every sample inferred from the INR (the uncached baseline) */
+    CINR_UNCACHED_LATTICE = 2 /* every sample the trilinear interpolation of the INR's values at its 8 LoD-0
+                                 lattice points (cell clamped so that its upper corner exists): what a cache
+                                 holding every LoD-0 brick renders, with no bricks.  Ray marching only;
+                                 samples_per_iter >= 8, of which samples_per_iter / 8 samples per step */
 } cinr_mode;
 
 typedef enum {

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libcinr.so")
 
 MAX_LEVELS, MAX_LAYERS, MAX_LODS = 32, 8, 16
 F32, BF16, F16, BF16X3 = 0, 1, 2, 3
-CACHED, UNCACHED_DIRECT = 0, 1
+CACHED, UNCACHED_DIRECT, UNCACHED_LATTICE = 0, 1, 2
 RANK_TIMESTAMP, RANK_PRIORITY = 0, 1
 PERSPECTIVE, ORTHOGRAPHIC = 0, 1
 DUMP_PAGE_TABLE, DUMP_SLOT_OWNER, DUMP_LAST_USED, DUMP_RANK, DUMP_REQ_COUNT = 0, 1, 2, 3, 4

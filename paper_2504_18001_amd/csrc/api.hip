@@ -856,7 +856,8 @@ cinr_status prepare_view(cinr_cache c, cinr_volume v, const cinr_camera* cam, co
     if (!v || !cam || !d_tf || !rp || !d_rgba) return fail(CINR_INVALID_ARG, "null argument");
     cinr_status st = check_camera(cam);
     if (st) return st;
-    if (rp->mode != CINR_CACHED && rp->mode != CINR_UNCACHED_DIRECT) return fail(CINR_INVALID_ARG, "mode = %d", rp->mode);
+    if (rp->mode != CINR_CACHED && rp->mode != CINR_UNCACHED_DIRECT && rp->mode != CINR_UNCACHED_LATTICE)
+        return fail(CINR_INVALID_ARG, "mode = %d", rp->mode);
     if (!(rp->step > 0.0f) || !isfinite(rp->step)) return fail(CINR_INVALID_ARG, "step must be > 0");
     if (!(rp->lod_scale >= 0.0f)) return fail(CINR_INVALID_ARG, "lod_scale must be >= 0");
     if (rp->pipe_depth != 0 && rp->pipe_depth != 1 && rp->pipe_depth != 2 && rp->pipe_depth != 4 && rp->pipe_depth != 8)
@@ -884,7 +885,10 @@ cinr_status prepare_view(cinr_cache c, cinr_volume v, const cinr_camera* cam, co
         if ((int64_t)cam->width * cam->height >= kMaxPathPixels)
             return fail(CINR_INVALID_ARG, "width*height >= 2^27 for the path tracer");
         if (rp->ert_record) return fail(CINR_INVALID_ARG, "ert_record is a ray-marching output");
+        if (rp->mode == CINR_UNCACHED_LATTICE) return fail(CINR_INVALID_ARG, "the lattice mode is ray-marching only");
     }
+    if (rp->mode == CINR_UNCACHED_LATTICE && rp->samples_per_iter < 8)
+        return fail(CINR_INVALID_ARG, "the lattice mode needs samples_per_iter >= 8");
     const bool cached = rp->mode == CINR_CACHED;
     if (cached && !c) return fail(CINR_INVALID_ARG, "the cached mode needs a cache");
     const int vi = cached ? c->index_of(v) : -1;
@@ -904,7 +908,9 @@ cinr_status prepare_view(cinr_cache c, cinr_volume v, const cinr_camera* cam, co
         double diag = 0.0;
         for (int a = 0; a < 3; ++a) diag += (double)(v->desc.dims[a] - 1) * (double)(v->desc.dims[a] - 1);
         const double max_samples = ceil(sqrt(diag) / (double)rp->step) + 2.0;
-        max_iters = (int64_t)ceil(max_samples / S) + 2;
+        // the lattice mode gathers S / 8 samples per step (8 values each)
+        const int32_t Sg = rp->mode == CINR_UNCACHED_LATTICE ? S / 8 : S;
+        max_iters = (int64_t)ceil(max_samples / Sg) + 2;
     }
     if (max_iters > kMaxIters) return fail(CINR_INVALID_ARG, "step too small for samples_per_iter (needs %lld iterations)", (long long)max_iters);
     r.v = v;

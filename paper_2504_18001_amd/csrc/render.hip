@@ -347,13 +347,15 @@ struct Tally {
             skipped += st == S_SKIP;
         }
     }
-    // all 64 lanes of the wave must call this together
-    __device__ void commit(unsigned long long* stats) {
+    // all 64 lanes of the wave must call this together; `lattice`: the
+    // lattice mode's samples (gathered like misses) count as hits
+    __device__ void commit(unsigned long long* stats, bool lattice = false) {
+        const uint32_t m = lattice ? 0u : misses;
         wave_add_u64(&stats[ST_RAYS], rays);
         wave_add_u64(&stats[ST_SAMPLES], samples);
-        wave_add_u64(&stats[ST_HITS], samples - fallbacks - misses - skipped);
+        wave_add_u64(&stats[ST_HITS], samples - fallbacks - m - skipped);
         wave_add_u64(&stats[ST_FALLBACKS], fallbacks);
-        wave_add_u64(&stats[ST_MISSES], misses);
+        wave_add_u64(&stats[ST_MISSES], m);
         wave_add_u64(&stats[ST_SKIPPED], skipped);
     }
 };
@@ -603,6 +605,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves, 
     const uint32_t n = it == 0 ? n0 : f.ctr[it].live;
     UnitQueue q(f.claim + (it & 1) * 8 * kClaimStride, (n + 63u) / 64u, (uint32_t)f.xcd_bands);
     const int32_t S = f.S;
+    const bool lat = f.mode == CINR_UNCACHED_LATTICE;
+    const int32_t Sg = lat ? S / 8 : S;  // samples gathered per pending step
     Tally tally;
     SlotCache sc{&slotc[threadIdx.x]};  // residency is constant within a frame: valid across rays
     for (;;) {
@@ -694,7 +698,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves, 
                 }
             }
         }
-        // a wavefront step of S samples starting at the miss
+        // a wavefront step of S samples starting at the miss (the lattice
+        // mode: S / 8 samples, whose 8 lattice corners each take a value slot)
         if (__ballot(pend) != 0ull) {
             const uint32_t pi = wave_reserve(pend ? 1u : 0u, cold->pending);
             uint64_t mask = 0;
@@ -708,7 +713,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves, 
                 mask = 1;
                 nc = 1;
                 int32_t kg = k + (kAdapt ? (1 << e_miss) : 1);  // grid index of the next sample
-                while (nc < S) {
+                while (nc < Sg) {
                     float qp[3];
                     if (!sample_pos(o, d, ts, te, f.step, kg, f.vm1, qp)) break;
                     const SampleRes sr = sample_cache<kFast, kAdapt, kPool>(f, hot, lgs, fl, qp, sc);
@@ -717,7 +722,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves, 
                     if (sr.status == S_MISS)
                         mask |= 1ull << nc;
                     else
-                        vb[nc] = sr.status == S_SKIP ? -1.0f : sr.value;
+                        vb[lat ? 8 * nc : nc] = sr.status == S_SKIP ? -1.0f : sr.value;
                     if (kAdapt) ve[nc] = (uint8_t)sr.e;
                     kg += kAdapt ? (1 << sr.e) : 1;
                     ++nc;
@@ -728,7 +733,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves, 
                 kn[pix] = k;
             }
             // true-miss records (position, destination slot), reserved per wave
-            uint32_t mb = wave_reserve((uint32_t)__popcll(mask), cold->misses);
+            uint32_t mb = wave_reserve((uint32_t)__popcll(mask) * (lat ? 8u : 1u), cold->misses);
             if (pend) {
                 float4* mr = cold->miss_rec;
                 const uint8_t* ve = f.vexp + (int64_t)pi * S;
@@ -737,7 +742,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves, 
                     if ((mask >> sidx) & 1ull) {
                         float qp[3];
                         sample_pos(o, d, ts, te, f.step, kg, f.vm1, qp);
-                        mr[mb++] = make_float4(qp[0], qp[1], qp[2], __uint_as_float(pi * (uint32_t)S + (uint32_t)sidx));
+                        if (lat) {
+                            // the 8 LoD-0 lattice points around the sample (cell
+                            // clamped so that its upper corner exists)
+                            int32_t j[3];
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) {
+                                j[a] = (int32_t)qp[a];
+                                if (j[a] > f.dims[a] - 2) j[a] = f.dims[a] - 2;
+                            }
+                            for (int32_t n = 0; n < 8; ++n)
+                                mr[mb++] = make_float4((float)(j[0] + (n & 1)), (float)(j[1] + ((n >> 1) & 1)),
+                                                       (float)(j[2] + (n >> 2)),
+                                                       __uint_as_float(pi * (uint32_t)S + (uint32_t)(8 * sidx + n)));
+                        } else {
+                            mr[mb++] = make_float4(qp[0], qp[1], qp[2], __uint_as_float(pi * (uint32_t)S + (uint32_t)sidx));
+                        }
                         log_miss(cold, pix, kg, qp);
                     }
                     kg += kAdapt ? (1 << ve[sidx]) : 1;
@@ -750,7 +770,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves, 
             rgba[pix] = acc;
         }
     }
-    tally.commit(f.stats);
+    tally.commit(f.stats, lat);
     if (it == 0 && f.gather_host) {
         // the frame's pending count once every workgroup has finished: the
         // last one to take a ticket reads it (all reservations precede the
@@ -780,6 +800,7 @@ __global__ __launch_bounds__(kBlock) void k_shade(FrameDev f, int32_t it) {
     int32_t* next = (it & 1) ? f.live0 : f.live1;
     const int32_t S = f.S;
     const bool ert_on = f.ert_on && f.var->preload == 0;  // suspended in the pre-load frames
+    const bool lat = f.mode == CINR_UNCACHED_LATTICE;
     for (uint32_t pi = blockIdx.x * kBlock + threadIdx.x; pi < n; pi += gridDim.x * kBlock) {
         const int32_t pix = f.pend_pix[pi];
         const int32_t nc = f.pend_n[pi];
@@ -789,8 +810,36 @@ __global__ __launch_bounds__(kBlock) void k_shade(FrameDev f, int32_t it) {
         const uint8_t* ve = f.vexp + (int64_t)pi * S;
         bool done = false;
         int32_t kg = k;  // grid index after the composited samples
+        float lo[3] = {0.f, 0.f, 0.f}, ld[3] = {0.f, 0.f, 0.f}, lts = 0.0f, lte = -1.0f;
+        if (lat) ray_setup(cam, f.vm1, pix % f.W, pix / f.W, lo, ld, lts, lte);
         for (int32_t s = 0; s < nc; ++s) {
-            const float v = vb[s];
+            float v;
+            if (lat) {
+                // trilinear of the sample's 8 lattice values (a skipped sample
+                // holds -1 in its first slot)
+                const float* c = vb + 8 * s;
+                v = c[0];
+                if (v >= 0.0f) {
+                    float q[3];
+                    sample_pos(lo, ld, lts, lte, f.step, kg, f.vm1, q);
+                    float fr[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        int32_t j = (int32_t)q[a];
+                        if (j > f.dims[a] - 2) j = f.dims[a] - 2;
+                        fr[a] = q[a] - (float)j;
+                    }
+                    const float x00 = __builtin_fmaf(fr[0], c[1] - c[0], c[0]);
+                    const float x10 = __builtin_fmaf(fr[0], c[3] - c[2], c[2]);
+                    const float x01 = __builtin_fmaf(fr[0], c[5] - c[4], c[4]);
+                    const float x11 = __builtin_fmaf(fr[0], c[7] - c[6], c[6]);
+                    const float y0 = __builtin_fmaf(fr[1], x10 - x00, x00);
+                    const float y1 = __builtin_fmaf(fr[1], x11 - x01, x01);
+                    v = __builtin_fmaf(fr[2], y1 - y0, y0);
+                }
+            } else {
+                v = vb[s];
+            }
             const int32_t e = f.adapt > 0 ? (int32_t)ve[s] : 0;
             if (v >= 0.0f) composite(acc, v, tfs, e ? __builtin_ldexpf(f.step, e) : f.step);
             kg += 1 << e;

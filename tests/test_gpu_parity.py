@@ -171,6 +171,52 @@ def test_uncached_render_small(dtype):
         assert st["rays"] == rst["rays"] and st["samples"] == rst["samples"] and st["misses"] == rst["misses"]
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16x3"])
+def test_uncached_lattice_render_small(dtype):
+    """The lattice mode (each sample interpolated from the INR's values at its
+    8 LoD-0 lattice points) against the oracle's: images within the
+    tolerance, statistics equal.  Then the invariant that a cache holding
+    every LoD-0 brick renders the lattice image bit for bit (the same lattice
+    values, interpolation, compositing and early termination)."""
+    from oracle import oracle as O
+    from paper_2504_18001_amd import cinr
+    w = configs.SMALL
+    vol = gpu_volume(w.arch, 0)
+    m = oracle_inr(w.arch, 0)
+    B = 8
+    nb, off = vol.geometry(B, 1)
+    n0 = int(off[1])
+    cache = cinr.Cache(vol, B, 1, n0, 16)
+    cache.prefill(torch.arange(n0, dtype=torch.int32, device="cuda"), dtype=dtype)
+    for frame in (0, 3):
+        cam = w.camera(frame)
+        cam.width, cam.height = 72, 56  # ragged 8x8 tiles
+        tf = w.tf(frame)
+        img, st = _render_gpu(vol, cam, tf, w, frame, cinr.UNCACHED_LATTICE, dtype, S=32)
+        p = O.make_params(w.step, w.lod_scale, seed=w.seed, frame_index=frame, samples_per_iter=32,
+                          mode=O.UNCACHED_LATTICE)
+        ref, rst = O.render_uncached(m, cam, tf, p)
+        err = np.abs(img - ref).max()
+        print("lattice", dtype, frame, err, st, rst)
+        assert err <= TOL[dtype]
+        for k in ("rays", "samples", "hits", "misses", "skipped"):
+            assert st[k] == rst[k], (k, st[k], rst[k])
+        for ert in (2.0, 0.95):
+            a, _ = _render_gpu(vol, cam, tf, w, frame, cinr.UNCACHED_LATTICE, dtype, S=32, ert=ert)
+            c, cst = _render_gpu(vol, cam, tf, w, frame, cinr.CACHED, dtype, cache=cache, S=32, ert=ert)
+            np.testing.assert_array_equal(c, a, err_msg=f"frame {frame} ert {ert}")
+            assert cst["misses"] == 0 and cst["fallbacks"] == 0
+
+
+def test_uncached_lattice_arguments():
+    from paper_2504_18001_amd import cinr
+    w = configs.SMALL
+    vol = gpu_volume(w.arch, 0)
+    cam = w.camera(0)
+    with pytest.raises(cinr.CinrError, match="samples_per_iter >= 8"):
+        _render_gpu(vol, cam, w.tf(0), w, 0, cinr.UNCACHED_LATTICE, S=4)
+
+
 def _compare_state(gc, oc, frame, check_misses=True):
     from paper_2504_18001_amd import cinr
     np.testing.assert_array_equal(gc.dump(cinr.DUMP_PAGE_TABLE), oc.page_table(), err_msg=f"page table f{frame}")
