@@ -89,7 +89,8 @@ typedef enum { CINR_PERSPECTIVE = 0, CINR_ORTHOGRAPHIC = 1 } cinr_projection;
  *  n_layers, widths  MLP without biases: widths[0] = n_levels*n_features,
  *                widths[n_layers] = 1, ReLU between layers.
  *  value_scale, value_offset  value = clamp(scale*y + offset, 0, 1).
- *  d_table       f32 [sum_l T_l][n_features], level-major.  Borrowed.
+ *  d_table       f32 [sum_l T_l][n_features], level-major, under 4 GiB
+ *                (CINR_INVALID_ARG otherwise).  Borrowed.
  *  d_weights     f32, layer k as [widths[k+1]][widths[k]] row-major,
  *                layers concatenated.  Borrowed.
  *  d_macrocells  optional f32 [ceil(Vz/N)][ceil(Vy/N)][ceil(Vx/N)][2] of

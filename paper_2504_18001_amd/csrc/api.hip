@@ -265,6 +265,11 @@ extern "C" cinr_status cinr_create_volume_inr(const cinr_volume_desc* d, cinr_vo
         }
     }
     v->table_entries = (int64_t)off;
+    // the gathers address the table with 32-bit byte offsets
+    if (off * (uint64_t)d->n_features * sizeof(float) > 0xFFFFFFFFull) {
+        delete v;
+        return fail(CINR_INVALID_ARG, "hash table larger than 4 GiB");
+    }
     m.value_scale = d->value_scale;
     m.value_offset = d->value_offset;
     m.table = d->d_table;

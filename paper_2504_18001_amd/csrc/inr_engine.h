@@ -102,13 +102,9 @@ __device__ inline void level_cell(const LevelDev& lv, const double u[3], uint32_
     }
 }
 
-// The 8 corner entries of cell c from the level's table, interpolated.
-template <int F>
-__device__ inline void gather_level(const LevelDev& lv, const float* table, const uint32_t c[3], const float w[3],
-                                    float* out) {
+// Table entries of the 8 corners of cell c (x fastest, then y, then z).
+__device__ inline void level_corners_idx(const LevelDev& lv, const uint32_t c[3], uint32_t idx[8]) {
     const uint32_t c0 = c[0], c1 = c[1], c2 = c[2];
-    const float w0 = w[0], w1 = w[1], w2 = w[2];
-    uint32_t idx[8];
     if (lv.mask == 0u) {
         const uint32_t sd = lv.side, sd2 = lv.side2;
         const uint32_t b = c0 + c1 * sd + c2 * sd2;
@@ -135,10 +131,25 @@ __device__ inline void gather_level(const LevelDev& lv, const float* table, cons
         idx[6] = (x0 ^ a11) & mk;
         idx[7] = (x1 ^ a11) & mk;
     }
-    const float* tb = table + (size_t)lv.offset * F;
-    float e[8][F];
+}
+
+// The 8 corner entries.  The table is under 4 GiB (checked when the volume
+// is created), so each load takes the table's uniform base and a 32-bit byte
+// offset.
+template <int F>
+__device__ inline void level_corners_load(const LevelDev& lv, const float* table, const uint32_t idx[8],
+                                          float e[8][F]) {
+    const char* t8 = reinterpret_cast<const char*>(table);
+    const uint32_t b8 = lv.offset * (uint32_t)(F * sizeof(float));
 #pragma unroll
-    for (int k = 0; k < 8; ++k) Entry<F>::load(tb + (size_t)idx[k] * F, e[k]);
+    for (int k = 0; k < 8; ++k)
+        Entry<F>::load(reinterpret_cast<const float*>(t8 + (b8 + idx[k] * (uint32_t)(F * sizeof(float)))), e[k]);
+}
+
+// Trilinear interpolation of the 8 corner entries with weights w.
+template <int F>
+__device__ inline void level_interp(const float e[8][F], const float w[3], float* out) {
+    const float w0 = w[0], w1 = w[1], w2 = w[2];
     const float wx0 = 1.0f - w0, wy0 = 1.0f - w1, wz0 = 1.0f - w2;
     const float wxy[4] = {wx0 * wy0, w0 * wy0, wx0 * w1, w0 * w1};
 #pragma unroll
@@ -149,6 +160,17 @@ __device__ inline void gather_level(const LevelDev& lv, const float* table, cons
 #pragma unroll
         for (int j = 0; j < F; ++j) out[j] = __builtin_fmaf(wt, e[k][j], out[j]);
     }
+}
+
+// The 8 corner entries of cell c from the level's table, interpolated.
+template <int F>
+__device__ inline void gather_level(const LevelDev& lv, const float* table, const uint32_t c[3], const float w[3],
+                                    float* out) {
+    uint32_t idx[8];
+    level_corners_idx(lv, c, idx);
+    float e[8][F];
+    level_corners_load<F>(lv, table, idx, e);
+    level_interp<F>(e, w, out);
 }
 
 template <int F>
@@ -326,6 +348,8 @@ struct InrEngine<Cfg, true> {
     __device__ float eval_c(const InrDev& m, const Coord& co, Lds& lds, const StageLevel* sl, const float* stage) {
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, row = lane & 15, g = lane >> 4;
         float* my = lds.f + threadIdx.x * ROW;
+        // one level at a time: the FP32 engine's registers leave no room for
+        // a second level's corners in flight
 #pragma unroll 2
         for (int l = 0; l < NL; ++l) {
             float f[F];
