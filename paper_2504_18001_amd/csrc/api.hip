@@ -1384,7 +1384,7 @@ cinr_status cache_end_frame(cinr_cache c, int32_t prec, bool lru_pass, Timing& t
         ta.tail.stats = 1;
         ta.tail.c = cd;
         ta.tail.g = c->g;
-        uint32_t* fuse = c->plan_sel.n_pass == 2 ? &cd.ctr->select_done : nullptr;
+        uint32_t* fuse = c->plan_sel.n_pass >= 2 ? &cd.ctr->select_done : nullptr;
         HIP_TRY(launch_topk(ta, c->plan_sel, cd.topk[0], cd.topk[1], cd.sel, &sel, fuse, s));
         // LRU victims, only when the pool may be full (the pass is also gated
         // on the device by the number of slots to evict)

@@ -55,24 +55,124 @@ __global__ void k_clear_last_req(CacheDev c, int64_t n_keys) {
         c.last_req[t] = 0u;
 }
 
-// Score of touched brick `idx` after its rank update (first selection pass).
-__device__ inline uint64_t rank_score(const RankArgs& ra, int32_t frame, uint64_t idx) {
-    const int32_t key = ra.touched[idx];
-    const uint32_t cnt = ra.req[key];
-    if (ra.last_req) ra.last_req[key] = cnt;
-    const int64_t old = ra.rank[key];
-    int64_t r = old < 0 ? (int64_t)frame + (int64_t)cnt - 1 : old + (int64_t)cnt;
+// Scores of the touched bricks base + e, e = threadIdx.x + 256 q < have,
+// after their rank update (first selection pass), into s[e]; s[e] = 0 for
+// have <= e < m.  Each thread's keys are read together, then their counts
+// and ranks, so that a thread waits for three round trips in all rather
+// than three per brick (the touched keys are distinct: no two threads write
+// the same entries).
+__device__ inline void rank_scores(const RankArgs& ra, int32_t frame, uint64_t base, uint32_t have, uint32_t m,
+                                   uint64_t* s) {
+    constexpr int kPer = kTopkChunk / 256;
+    int32_t key[kPer];
+    uint32_t cnt[kPer];
+    int64_t old[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const uint32_t e = threadIdx.x + 256u * q;
+        key[q] = e < have ? ra.touched[base + e] : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        cnt[q] = key[q] >= 0 ? ra.req[key[q]] : 0u;
+        old[q] = key[q] >= 0 ? ra.rank[key[q]] : 0;
+    }
     const int64_t cap = (int64_t)frame + ra.window;
-    if (r > cap) r = cap;
-    ra.rank[key] = r;
-    ra.req[key] = 0u;
-    const uint64_t low = 0xFFFFFFFFull - (uint64_t)(uint32_t)key;
-    return ra.ranking ? (((uint64_t)r << 32) | low) : low;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const uint32_t e = threadIdx.x + 256u * q;
+        if (e >= m) continue;
+        if (key[q] < 0) {
+            s[e] = 0ull;
+            continue;
+        }
+        int64_t r = old[q] < 0 ? (int64_t)frame + (int64_t)cnt[q] - 1 : old[q] + (int64_t)cnt[q];
+        if (r > cap) r = cap;
+        if (ra.last_req) ra.last_req[key[q]] = cnt[q];
+        ra.rank[key[q]] = r;
+        ra.req[key[q]] = 0u;
+        const uint64_t low = 0xFFFFFFFFull - (uint64_t)(uint32_t)key[q];
+        s[e] = ra.ranking ? (((uint64_t)r << 32) | low) : low;
+    }
+}
+
+__device__ inline uint64_t shfl_xor_u64(uint64_t v, uint32_t mask) {
+    const uint32_t lo = __shfl_xor((uint32_t)v, (int)mask);
+    const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), (int)mask);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Bitonic sort of s[0, 256 E) in descending order with E elements per thread
+// in registers (thread t holds elements t E .. t E + E - 1): the steps whose
+// partner is in the same thread compare in registers, those whose partner
+// thread is in the same wavefront exchange by shuffles, and only the steps
+// across wavefronts go through LDS.  The same network as sort_desc.
+template <int E>
+__device__ void sort_desc_regs(uint64_t* s) {
+    constexpr uint32_t m = 256u * E;
+    const uint32_t t = threadIdx.x;
+    uint64_t v[E];
+#pragma unroll
+    for (int q = 0; q < E; ++q) v[q] = s[t * E + q];
+    for (uint32_t len = 2; len <= m; len <<= 1) {
+        // partners in other threads: element t E + q pairs with (t ^ pt) E + q
+        for (uint32_t j = len >> 1; j >= (uint32_t)E; j >>= 1) {
+            const uint32_t pt = j / E;
+            uint64_t o[E];
+            if (pt < 64u) {
+#pragma unroll
+                for (int q = 0; q < E; ++q) o[q] = shfl_xor_u64(v[q], pt);
+            } else {
+                __syncthreads();  // the previous exchange's reads are done
+#pragma unroll
+                for (int q = 0; q < E; ++q) s[t * E + q] = v[q];
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < E; ++q) o[q] = s[(t ^ pt) * E + q];
+            }
+            const bool lower = (t & pt) == 0u;
+#pragma unroll
+            for (int q = 0; q < E; ++q) {
+                const bool desc = ((t * E + q) & len) == 0u;
+                const uint64_t hi = v[q] > o[q] ? v[q] : o[q];
+                const uint64_t lo = v[q] > o[q] ? o[q] : v[q];
+                v[q] = (lower == desc) ? hi : lo;
+            }
+        }
+        // partners in the same thread (compile-time indices: registers)
+#pragma unroll
+        for (int jj = E / 2; jj >= 1; jj >>= 1) {
+            if ((uint32_t)jj >= len) continue;
+#pragma unroll
+            for (int q = 0; q < E; ++q) {
+                const int x = q ^ jj;
+                if (x > q) {
+                    const bool desc = ((t * E + q) & len) == 0u;
+                    const uint64_t a = v[q], b = v[x];
+                    if (desc ? (a < b) : (a > b)) {
+                        v[q] = b;
+                        v[x] = a;
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < E; ++q) s[t * E + q] = v[q];
+    __syncthreads();
 }
 
 // Bitonic sort of s[0, m) in descending order (m a power of two, <= 2048),
 // by the 256 threads of the workgroup.
 __device__ void sort_desc(uint64_t* s, uint32_t m) {
+    switch (m) {
+        case 256: sort_desc_regs<1>(s); return;
+        case 512: sort_desc_regs<2>(s); return;
+        case 1024: sort_desc_regs<4>(s); return;
+        case 2048: sort_desc_regs<8>(s); return;
+        default: break;
+    }
     for (uint32_t len = 2; len <= m; len <<= 1) {
         for (uint32_t j = len >> 1; j > 0; j >>= 1) {
             for (uint32_t e = threadIdx.x; e < m; e += 256) {
@@ -233,39 +333,41 @@ __global__ __launch_bounds__(256) void k_topk(TopkArgs a) {
     const uint64_t n_touched = c;
     // every live element in pass 0's first workgroup: it sorts them all and
     // completes the selection; the later passes have nothing to do
-    const bool one = !a.fused && n_touched <= (uint64_t)kTopkChunk;
+    const bool one = n_touched <= (uint64_t)kTopkChunk;
     if (one && a.pass > 0) return;
-    const bool last = one || a.pass == a.last_pass;
+    const bool last = one || (!a.fused && a.pass == a.last_pass);
     if (!one)
         for (int q = 0; q < a.pass; ++q) c = ((c + kTopkChunk - 1) / kTopkChunk) * (uint64_t)a.k;
     const uint64_t base = (uint64_t)blockIdx.x * kTopkChunk;
-    if (base >= c && blockIdx.x > 0 && !a.fused) return;
+    if (base >= c && blockIdx.x > 0 && (one || !a.fused)) return;
     const uint32_t have = base >= c ? 0u : (uint32_t)(c - base < kTopkChunk ? c - base : kTopkChunk);
     uint32_t m = pow2_at_least(have);
     if (have > 0 || blockIdx.x == 0) {
-        const int32_t frame = (a.pass == 0 && a.mode == TOPK_RANK) ? *a.ra.frame : 0;
-        for (uint32_t e = threadIdx.x; e < m; e += 256) {
-            const uint64_t idx = base + e;
-            uint64_t v = 0ull;
-            if (e < have) {
-                if (a.pass == 0 && a.mode == TOPK_LRU) {
-                    const uint64_t slot = idx + (uint64_t)a.lru_base;
-                    v = ~(((uint64_t)(uint32_t)a.lru_last_used[slot] << 32) | slot);
+        if (a.pass == 0 && a.mode == TOPK_RANK) {
+            rank_scores(a.ra, *a.ra.frame, base, have, m, s);
+        } else {
+            for (uint32_t e = threadIdx.x; e < m; e += 256) {
+                const uint64_t idx = base + e;
+                uint64_t v = 0ull;
+                if (e < have) {
+                    if (a.pass == 0 && a.mode == TOPK_LRU) {
+                        const uint64_t slot = idx + (uint64_t)a.lru_base;
+                        v = ~(((uint64_t)(uint32_t)a.lru_last_used[slot] << 32) | slot);
+                    } else {
+                        v = a.in[idx];
+                    }
                 }
-                else if (a.pass == 0 && a.mode == TOPK_RANK)
-                    v = rank_score(a.ra, frame, idx);
-                else
-                    v = a.in[idx];
+                s[e] = v;
             }
-            s[e] = v;
         }
         __syncthreads();
         sort_desc(s, m);
-        uint64_t* out = (last && !a.fused) ? a.final_out : a.out + (uint64_t)blockIdx.x * a.k;
+        uint64_t* out = last ? a.final_out : a.out + (uint64_t)blockIdx.x * a.k;
         for (int32_t e = threadIdx.x; e < a.k; e += 256) out[e] = (uint32_t)e < m ? s[e] : 0ull;
     }
-    if (a.fused) {
-        // the last workgroup to finish pass 0 completes the selection
+    if (a.fused && !one) {
+        // the last workgroup to finish pass 0 runs the later passes, chunk by
+        // chunk, ping-ponging between out and out2, the last into final_out
         __threadfence();
         __syncthreads();
         if (threadIdx.x == 0) ticket = atomicAdd(a.done, 1u);
@@ -273,13 +375,30 @@ __global__ __launch_bounds__(256) void k_topk(TopkArgs a) {
         if (ticket != gridDim.x - 1u) return;
         __threadfence();
         if (threadIdx.x == 0) *a.done = 0u;
-        // pass 1 over pass 0's live output: at most 2048 entries (the host
-        // fuses only selections of two passes)
-        const uint64_t cc = ((c + kTopkChunk - 1) / kTopkChunk) * (uint64_t)a.k;
-        const uint32_t h = (uint32_t)(cc < kTopkChunk ? cc : kTopkChunk);
+        uint64_t cc = ((c + kTopkChunk - 1) / kTopkChunk) * (uint64_t)a.k;  // live elements of pass 1
+        const uint64_t* src = a.out;
+        for (int p = 1; cc > (uint64_t)kTopkChunk; ++p) {
+            uint64_t* dst = (p & 1) ? a.out2 : a.out;
+            const uint64_t nb = (cc + kTopkChunk - 1) / kTopkChunk;
+            for (uint64_t b = 0; b < nb; ++b) {
+                const uint64_t rest = cc - b * kTopkChunk;
+                const uint32_t h = (uint32_t)(rest < kTopkChunk ? rest : kTopkChunk);
+                m = pow2_at_least(h);
+                __syncthreads();
+                for (uint32_t e = threadIdx.x; e < m; e += 256) s[e] = e < h ? src[b * kTopkChunk + e] : 0ull;
+                __syncthreads();
+                sort_desc(s, m);
+                for (int32_t e = threadIdx.x; e < a.k; e += 256) dst[b * a.k + e] = (uint32_t)e < m ? s[e] : 0ull;
+            }
+            __threadfence();
+            __syncthreads();
+            src = dst;
+            cc = nb * (uint64_t)a.k;
+        }
+        const uint32_t h = (uint32_t)cc;
         m = pow2_at_least(h);
         __syncthreads();
-        for (uint32_t e = threadIdx.x; e < m; e += 256) s[e] = e < h ? a.out[e] : 0ull;
+        for (uint32_t e = threadIdx.x; e < m; e += 256) s[e] = e < h ? src[e] : 0ull;
         __syncthreads();
         sort_desc(s, m);
         for (int32_t e = threadIdx.x; e < a.k; e += 256) a.final_out[e] = (uint32_t)e < m ? s[e] : 0ull;
@@ -507,11 +626,12 @@ hipError_t launch_clear_last_req(const CacheDev& c, int64_t n_keys, hipStream_t 
 
 hipError_t launch_topk(const TopkArgs& base, const TopkPlan& plan, uint64_t* buf0, uint64_t* buf1, uint64_t* final_out,
                        const SelectArgs* epilogue, uint32_t* fuse_done, hipStream_t s) {
-    if (fuse_done && plan.n_pass == 2) {
-        // one launch: pass 0, then pass 1 in its last workgroup
+    if (fuse_done && plan.n_pass >= 2) {
+        // one launch: pass 0, then the later passes in its last workgroup
         TopkArgs a = base;
         a.pass = 0;
         a.out = buf0;
+        a.out2 = buf1;
         a.final_out = final_out;
         a.fused = 1;
         a.done = fuse_done;

@@ -289,11 +289,13 @@ struct TopkArgs {
     int32_t lru_base;           // TOPK_LRU: slots [lru_base, lru_base + count)
     RankArgs ra;
     SelectArgs sel;
-    // fused launch of a two-pass selection: the workgroups of pass 0, then
-    // the last of them to finish runs pass 1 alone into final_out
+    // fused launch of a selection of two or more passes: the workgroups of
+    // pass 0, then the last of them to finish runs the later passes alone
+    // (through out and out2) into final_out
     int32_t fused;
     uint32_t* done;         // count of finished workgroups (reset by the last)
     uint64_t* final_out;
+    uint64_t* out2;
     SelectTail tail;
     // passes of an unfused selection (the epilogue `sel` runs after the last);
     // when pass 0's live count fits one workgroup, that workgroup finishes the
