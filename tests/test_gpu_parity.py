@@ -208,6 +208,40 @@ def test_uncached_lattice_render_small(dtype):
             assert cst["misses"] == 0 and cst["fallbacks"] == 0
 
 
+@pytest.mark.parametrize("ranking", [1, 0])
+def test_selection_among_many_candidates(ranking):
+    """Frames requesting far more bricks than one 2048-entry chunk of the
+    selection (the 512^3 architecture with 8^3 bricks: 389,017 keys, a
+    four-pass selection run in one launch): the request list must be the
+    first max_requests requested keys by (rank desc, key asc), or by key for
+    the timestamp variant, recomputed on the host from the dumped counts and
+    ranks.  Two frames, so that the second adds to ranks of the first."""
+    from paper_2504_18001_amd import cinr
+    w = configs.HD512
+    vol = gpu_volume(w.arch, 0)
+    cache = cinr.Cache(vol, 8, 1, 4096, 256, ranking=ranking, keep_request_counts=True)
+    r = cinr.Renderer()
+    for f in range(2):
+        cam = w.camera(f)
+        cam.width, cam.height = 256, 144
+        r.render(vol, cam, w.tf(f), w.step, 0.0, frame_index=f, seed=w.seed, mode=cinr.CACHED, dtype="f32",
+                 cache=cache)
+        req = cache.dump(cinr.DUMP_REQ_COUNT)
+        rank = cache.dump(cinr.DUMP_RANK)
+        got = cache.dump(cinr.DUMP_REQUEST_LIST)
+        touched = np.nonzero(req)[0]
+        print("frame", f, "requested bricks", len(touched), "selected", len(got))
+        assert len(touched) > 4 * 2048
+        if ranking:
+            order = np.lexsort((touched, -rank[touched]))
+            want = touched[order][:256]
+        else:
+            want = np.sort(touched)[:256]
+        np.testing.assert_array_equal(got, want.astype(np.int32), err_msg=f"frame {f}")
+        # ranks of this frame's requests: a new brick f + c - 1, an old one rank + c (clamped)
+        assert (rank[touched] >= f).all()
+
+
 def test_uncached_lattice_arguments():
     from paper_2504_18001_amd import cinr
     w = configs.SMALL
