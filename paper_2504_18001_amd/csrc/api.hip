@@ -102,8 +102,10 @@ struct Timing {
             pool.pop_back();
             return e;
         }
+        // timestamps only: no system-scope fence (it would write back the
+        // L2, full of the march's framebuffer lines, at every record)
         hipEvent_t e = nullptr;
-        (void)hipEventCreate(&e);
+        (void)hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
         return e;
     }
 };
@@ -146,7 +148,8 @@ struct cinr_volume_s {
     int64_t table_entries = 0;  // hash-table entries over all levels
     int32_t* pinned = nullptr;  // readback of the live-ray counts (one per view)
     FrameVar* stage = nullptr;  // per-frame values of the views (pinned host, read by k_frame_begin)
-    hipEvent_t ev = nullptr;
+    hipEvent_t ev = nullptr;     // completion of copies into `pinned` (system-scope fence)
+    hipEvent_t ev_nf = nullptr;  // completion of the first marches, which store `pinned` themselves
     Timing timing;
     std::map<uint64_t, SamplerTuner> tuners;  // by image size
     DecodeShape decode_shape;                 // launch shape of this volume's brick decoding
@@ -320,6 +323,7 @@ extern "C" void cinr_destroy_volume(cinr_volume v) {
     if (v->pinned) (void)hipHostFree(v->pinned);
     if (v->stage) (void)hipHostFree(v->stage);
     if (v->ev) (void)hipEventDestroy(v->ev);
+    if (v->ev_nf) (void)hipEventDestroy(v->ev_nf);
     for (auto& r : v->timing.recs) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -1037,6 +1041,7 @@ cinr_status ensure_readback(cinr_volume v) {
         HIP_TRY(hipHostMalloc((void**)&v->pinned, sizeof(uint32_t) * kMaxViews, hipHostMallocDefault));
         HIP_TRY(hipHostMalloc((void**)&v->stage, sizeof(FrameVar) * kMaxViews, hipHostMallocDefault));
         HIP_TRY(hipEventCreateWithFlags(&v->ev, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&v->ev_nf, hipEventDisableTiming | hipEventDisableSystemFence));
     }
     return CINR_OK;
 }
@@ -1321,19 +1326,19 @@ cinr_status render_frame_views(cinr_cache c, std::vector<ViewRun>& runs, Timing&
     std::vector<const FrameDev*> fs;
     for (const ViewRun& r : runs) fs.push_back(&r.f);
     if (!fused) HIP_TRY(launch_pending_gather(fs.data(), (int)runs.size(), 0, pinned, gate, s));
-    HIP_TRY(hipEventRecord(rv->ev, s));
+    HIP_TRY(hipEventRecord(rv->ev_nf, s));
     const bool lru = c && lru_pass_needed(c);
     st = end_views(c, runs, lru, tm, gate, s);
     if (st) return st;
     bool trial = false;
     for (const ViewRun& r : runs) trial = trial || (r.timing_trial && r.tuner && r.tuner->pending);
     if (!trial) {
-        st = poll_pending(pinned, (int)runs.size(), rv->ev);
+        st = poll_pending(pinned, (int)runs.size(), rv->ev_nf);
         if (st) return st;
     } else {
         // a launch-shape trial's end event must have completed before it is
         // timed
-        HIP_TRY(hipEventSynchronize(rv->ev));
+        HIP_TRY(hipEventSynchronize(rv->ev_nf));
     }
     std::vector<uint32_t> known(runs.size());
     bool tail = false;
@@ -1671,7 +1676,7 @@ extern "C" cinr_status cinr_frame_graph_create(cinr_cache c, int32_t n_views, co
     HIP_TRY(hipHostMalloc((void**)&g->stage, sizeof(FrameVar) * n_views, hipHostMallocDefault));
     HIP_TRY(hipHostMalloc((void**)&g->pending, sizeof(uint32_t) * n_views, hipHostMallocDefault));
     HIP_TRY(hipStreamCreateWithFlags(&g->cs, hipStreamNonBlocking));
-    HIP_TRY(hipEventCreateWithFlags(&g->ev, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&g->ev, hipEventDisableTiming | hipEventDisableSystemFence));
     *out = g.release();
     return CINR_OK;
 }
