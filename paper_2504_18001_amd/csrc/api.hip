@@ -1069,8 +1069,8 @@ cinr_status view_march0(ViewRun& r, hipStream_t s) {
     SamplerTuner* t = r.tuner;
     if (r.timing_trial) {
         if (!t->a) {
-            HIP_TRY(hipEventCreate(&t->a));
-            HIP_TRY(hipEventCreate(&t->b));
+            HIP_TRY(hipEventCreateWithFlags(&t->a, hipEventDisableSystemFence));
+            HIP_TRY(hipEventCreateWithFlags(&t->b, hipEventDisableSystemFence));
         }
         HIP_TRY(hipEventRecord(t->a, s));
     }
