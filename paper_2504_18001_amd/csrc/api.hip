@@ -1718,11 +1718,20 @@ extern "C" cinr_status cinr_frame_graph_render(cinr_frame_graph g, const cinr_ca
     int32_t K = g->dev_iters;
     for (const ViewRun& r : runs) K = (int32_t)std::min<int64_t>(K, r.max_iters - 1);
     if (K < 0) K = 0;
+    // one ray-marched view and no queued iteration: its first march hands
+    // the pending count over itself, as in eager frames
+    const bool fused = n == 1 && K == 0 && !runs[0].f.path.on;
     if (!g->frame[lru]) {
         TimingOff off(runs);
         Timing none;
         st = capture(g, &g->frame[lru], [&](hipStream_t cs) -> cinr_status {
+            if (fused) {
+                runs[0].f.gather_host = g->pending;
+                runs[0].f.gather_gate = runs[0].L.gate;
+                runs[0].f.exit_ticket = runs[0].L.ticket;
+            }
             cinr_status r = start_views(c, runs, side, cs);
+            if (fused) runs[0].f.gather_host = runs[0].f.gather_gate = runs[0].f.exit_ticket = nullptr;
             if (r) return r;
             if (side) {
                 r = join_side_streams(c, cs);
@@ -1733,9 +1742,11 @@ extern "C" cinr_status cinr_frame_graph_render(cinr_frame_graph g, const cinr_ca
                     r = view_device_iteration(v, k, cs);
                     if (r) return r;
                 }
-            std::vector<const FrameDev*> fs;
-            for (const ViewRun& v : runs) fs.push_back(&v.f);
-            HIP_TRY(launch_pending_gather(fs.data(), n, K, g->pending, runs[0].L.gate, cs));
+            if (!fused) {
+                std::vector<const FrameDev*> fs;
+                for (const ViewRun& v : runs) fs.push_back(&v.f);
+                HIP_TRY(launch_pending_gather(fs.data(), n, K, g->pending, runs[0].L.gate, cs));
+            }
             return end_views(c, runs, lru, none, runs[0].L.gate, cs);
         });
         if (st) return st;
