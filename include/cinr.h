@@ -216,8 +216,12 @@ typedef struct {
  *                xcd_bands tunes the launch online, per volume and image
  *                size: frames of that size try pipe depths {1, 2} x bands
  *                {1, 4, 16} x waves {3, 4} twice each (24 trials, the second
- *                round in reverse order), then the fastest first-iteration
- *                march is kept (cinr_tuned_launch reports the choice).  A
+ *                round in reverse order), then the candidate with the
+ *                lowest first-march time per sample is kept
+ *                (cinr_tuned_launch reports the choice); each counted trial
+ *                reads the frame's sample count back, with a synchronisation
+ *                of the view's stream.  Frames under a pre-load LoD floor
+ *                are not counted.  A
  *                frame whose first march leaves rays waiting on true misses
  *                is not counted (its march was cut short) until 96 such
  *                frames have passed.

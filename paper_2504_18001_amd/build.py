@@ -15,6 +15,12 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # -packed-fp32-ops: no packed FP32 instructions.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-I", INCLUDE, "-I", CSRC]
+# Per-source flags.  The sampler's launches are bound by the latency of each
+# lane's chain of dependent steps; the scheduler's ILP strategy orders their
+# instructions for more independent work between a load and its use (the
+# 1080p frames run 1.7 % faster).  Brick decoding is slower with it, so it
+# applies to the sampler's source only.
+SOURCE_FLAGS = {"render.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
 
 
 def build(verbose: bool = False, jobs: int = 4) -> str:
@@ -22,7 +28,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     procs = []
     for src in SOURCES:
         obj = os.path.join(CSRC, src.replace(".hip", ".o"))
-        cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC, *FLAGS, *SOURCE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((subprocess.Popen(cmd, stderr=subprocess.PIPE, text=True), src))

@@ -112,7 +112,7 @@ struct Timing {
 
 // Online tuning of the sampler's launch shape (pipe depth, XCD bands) for one
 // image size: the first frames try every candidate twice (results do not
-// depend on the shape), the fastest first-iteration march is kept.
+// depend on the shape), the lowest first-march time per sample is kept.
 struct SamplerTuner {
     static constexpr int kCand = 12;
     static constexpr int kPipe[kCand] = {1, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 2};
@@ -125,7 +125,7 @@ struct SamplerTuner {
     static constexpr int kMaxWait = 96;
     int trial = 0;           // frames tried so far
     int waited = 0;          // trial frames not counted
-    float ms[kCand] = {};
+    float ms[kCand] = {};     // sums of first-march time per sample (ns per sample)
     int best = -1;
     hipEvent_t a = nullptr, b = nullptr;
     bool pending = false;    // events of the current trial recorded, not yet read
@@ -1130,11 +1130,21 @@ cinr_status tuner_collect(ViewRun& r, uint32_t first_pending) {
     float ms = 0.0f;
     HIP_TRY(hipEventElapsedTime(&ms, t->a, t->b));
     t->pending = false;
+    // frames under a pre-load LoD floor sample coarse, coherent bricks and
+    // cost far less per sample than the frames that follow: not counted
+    if (r.hv.lod_floor > 0) return CINR_OK;
     if (first_pending != 0u && t->waited < SamplerTuner::kMaxWait) {
         t->waited += 1;  // the same candidate is tried again on the next frame
         return CINR_OK;
     }
-    t->ms[SamplerTuner::of_trial(t->trial)] += ms;
+    // time per sample: consecutive frames of an orbit differ in work by more
+    // than the candidates differ in speed.  The first march's samples are
+    // committed before it hands its pending count over, and nothing later in
+    // the frame changes them.
+    unsigned long long n = 0ull;
+    HIP_TRY(hipMemcpyAsync(&n, &r.f.stats[ST_SAMPLES], sizeof n, hipMemcpyDeviceToHost, r.st));
+    HIP_TRY(hipStreamSynchronize(r.st));
+    t->ms[SamplerTuner::of_trial(t->trial)] += n ? ms * 1e6f / (float)n : ms;
     t->trial += 1;
     if (t->trial >= SamplerTuner::kCand * SamplerTuner::kRounds) {
         int best = 0;
