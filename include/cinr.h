@@ -215,8 +215,10 @@ typedef struct {
  *                Results depend on none of them.  0 in pipe_depth or
  *                xcd_bands tunes the launch online, per volume and image
  *                size: frames of that size try pipe depths {1, 2} x bands
- *                {1, 4, 16} x waves {3, 4} twice each (24 trials, the second
- *                round in reverse order), then the candidate with the
+ *                {1, 4, 16} x waves {3, 4} x the two claim directions of the
+ *                image tiles (first tile first, or last tile first) twice
+ *                each (48 trials, the second round in reverse order), then
+ *                the candidate with the
  *                lowest first-march time per sample is kept
  *                (cinr_tuned_launch reports the choice); each counted trial
  *                reads the frame's sample count back, with a synchronisation

@@ -114,10 +114,14 @@ struct Timing {
 // image size: the first frames try every candidate twice (results do not
 // depend on the shape), the lowest first-march time per sample is kept.
 struct SamplerTuner {
-    static constexpr int kCand = 12;
-    static constexpr int kPipe[kCand] = {1, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 2};
-    static constexpr int kBands[kCand] = {1, 1, 4, 4, 16, 16, 1, 1, 4, 4, 16, 16};
-    static constexpr int kWaves[kCand] = {3, 3, 3, 3, 3, 3, 4, 4, 4, 4, 4, 4};
+    static constexpr int kCand = 24;
+    static constexpr int kPipe[kCand] = {1, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 2};
+    static constexpr int kBands[kCand] = {1, 1, 4, 4, 16, 16, 1, 1, 4, 4, 16, 16,
+                                          1, 1, 4, 4, 16, 16, 1, 1, 4, 4, 16, 16};
+    static constexpr int kWaves[kCand] = {3, 3, 3, 3, 3, 3, 4, 4, 4, 4, 4, 4, 3, 3, 3, 3, 3, 3, 4, 4, 4, 4, 4, 4};
+    // claim direction of the tiles: 1 takes the last tile first (which end
+    // holds the tiles of long rays depends on the view)
+    static constexpr int kRev[kCand] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1};
     static constexpr int kRounds = 2;
     // a trial counts when the view's first march left no ray pending (a whole
     // march, as in steady state); after this many frames cut short by true
@@ -965,10 +969,12 @@ cinr_status prepare_view(cinr_cache c, cinr_volume v, const cinr_camera* cam, co
         f.pipe = rp->pipe_depth > 0 ? rp->pipe_depth : SamplerTuner::kPipe[cand];
         f.xcd_bands = rp->xcd_bands > 0 ? rp->xcd_bands : SamplerTuner::kBands[cand];
         f.waves = rp->waves_per_simd > 0 ? rp->waves_per_simd : SamplerTuner::kWaves[cand];
+        f.claim_rev = SamplerTuner::kRev[cand];
     } else {
         f.pipe = rp->pipe_depth;
         f.xcd_bands = rp->xcd_bands;
         f.waves = rp->waves_per_simd > 0 ? rp->waves_per_simd : 3;
+        f.claim_rev = 0;
     }
     f.mc_N = v->desc.macrocell_size;
     f.div_mc = make_fastdiv((uint32_t)(f.mc_N > 0 ? f.mc_N : 1));

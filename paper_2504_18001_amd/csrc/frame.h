@@ -166,6 +166,7 @@ struct FrameDev {
     ViewEnd* view_table;  // nullable: the cache's table of the views' statistics targets
     int32_t mode;
     int32_t xcd_bands;  // image bands per XCD in the march kernel's work split
+    int32_t claim_rev;  // 1: work units are claimed from the last one down
     int32_t pipe;       // samples fetched ahead per ray in the march kernel
     int32_t waves;      // waves per SIMD of the march kernel's register budget (3 or 4)
     int32_t mc_N;

@@ -495,8 +495,9 @@ __global__ __launch_bounds__(kBlock) void k_frame_begin(FrameDev f, int32_t n_ct
 struct UnitQueue {
     uint32_t* ctr;  // 8 counters, kClaimStride words apart
     uint32_t n_units, bsz, per_x, home;
+    bool rev;           // units handed out from the last one down
     uint32_t dead = 0;  // counters known to be exhausted (wave-uniform)
-    __device__ UnitQueue(uint32_t* c, uint32_t n, uint32_t bands) : ctr(c), n_units(n) {
+    __device__ UnitQueue(uint32_t* c, uint32_t n, uint32_t bands, bool reverse) : ctr(c), n_units(n), rev(reverse) {
         const uint32_t nb = 8u * bands;
         bsz = (n + nb - 1u) / nb;
         per_x = bands * bsz;
@@ -519,7 +520,7 @@ struct UnitQueue {
             }
             const uint32_t band = x + 8u * (j / bsz);
             const uint32_t u = band * bsz + j % bsz;
-            if (u < n_units) return (int64_t)u;
+            if (u < n_units) return (int64_t)(rev ? n_units - 1u - u : u);
         }
         return -1;
     }
@@ -603,7 +604,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves, 
     __syncthreads();
     const ColdRef cold = &cold_s;
     const uint32_t n = it == 0 ? n0 : f.ctr[it].live;
-    UnitQueue q(f.claim + (it & 1) * 8 * kClaimStride, (n + 63u) / 64u, (uint32_t)f.xcd_bands);
+    UnitQueue q(f.claim + (it & 1) * 8 * kClaimStride, (n + 63u) / 64u, (uint32_t)f.xcd_bands, f.claim_rev != 0);
     const int32_t S = f.S;
     const bool lat = f.mode == CINR_UNCACHED_LATTICE;
     const int32_t Sg = lat ? S / 8 : S;  // samples gathered per pending step
@@ -1017,7 +1018,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
     const uint32_t n = it == 0 ? n0 : f.ctr[it - 1].pending;
     const int32_t* cur = (it & 1) ? f.live1 : f.live0;
     int32_t* next = (it & 1) ? f.live0 : f.live1;
-    UnitQueue q(f.claim + (it & 1) * 8 * kClaimStride, (n + 63u) / 64u, (uint32_t)f.xcd_bands);
+    UnitQueue q(f.claim + (it & 1) * 8 * kClaimStride, (n + 63u) / 64u, (uint32_t)f.xcd_bands, f.claim_rev != 0);
     const PtDev P = f.path;
     const uint32_t key1 = (uint32_t)hot.frame;
     Tally tally;

@@ -87,8 +87,9 @@ def test_online_launch_tuning_converges_and_changes_nothing():
         cache = cinr.Cache(vol, 16, 4, 400, 20, preload_period=2)
         r = cinr.Renderer()
         out = []
-        # 24 trials, plus up to 96 frames cut short by true misses
-        for f in range(124):
+        # 48 trials, plus up to 96 frames cut short by true misses and the
+        # frames under a pre-load LoD floor, which are not counted
+        for f in range(160):
             kw = dict(pipe_depth=0, xcd_bands=0) if mode == "tuned" else dict(pipe_depth=2, xcd_bands=4)
             img = r.render(vol, w.camera(f, dims), w.tf(f), w.step, w.lod_scale, frame_index=f, seed=w.seed,
                            ert_threshold=w.ert_threshold, samples_per_iter=w.samples_per_iter, mode=cinr.CACHED,
