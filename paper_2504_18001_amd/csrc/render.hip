@@ -490,7 +490,9 @@ __global__ __launch_bounds__(kBlock) void k_frame_begin(FrameDev f, int32_t n_ct
 // the 8 XCDs) claims bands x, x+8, ... in order through its own counter, so
 // that each XCD's L2 sees compact image regions and every XCD gets bands from
 // all over the image.  A wave whose XCD has no unit left claims from the
-// others.
+// others.  With `rev` the same sequence hands out unit n - 1 - u instead of u:
+// a lockstep wave takes as long as its longest ray, and the tuner picks the
+// direction that starts a view's tiles of long rays early rather than last.
 
 struct UnitQueue {
     uint32_t* ctr;  // 8 counters, kClaimStride words apart
